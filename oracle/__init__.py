@@ -1,0 +1,212 @@
+"""FP64 CPU oracle for batched B-spline point projection and inversion.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product library never imports this
+package.  The arithmetic lives in ``mrep_oracle.c`` (plain C, OpenMP over
+queries and curves); this module builds it with gcc and marshals numpy arrays.
+
+Each wrapper names the passage of the paper its C function follows; see the
+header of ``mrep_oracle.c`` for the readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mrep_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
+               "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    lib.orc_basis.argtypes = [C.c_int, C.c_int, dp, C.c_double, dp]
+    lib.orc_eval.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int64, dp, dp, dp, dp]
+    lib.orc_eval_batch.argtypes = [C.c_int, ip, lp, dp, lp, dp, C.c_int64, ip, dp, dp]
+    lib.orc_bezier_spans.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int, dp, dp]
+    lib.orc_bez_split.argtypes = [C.c_int, dp, C.c_double, dp, dp]
+    lib.orc_bez_split.restype = None
+    lib.orc_bez_eval.argtypes = [C.c_int, dp, C.c_double, dp]
+    lib.orc_bez_eval.restype = None
+    lib.orc_g1_reduce.argtypes = [C.c_int, dp, dp, dp]
+    lib.orc_piece_deviation.argtypes = [C.c_int, dp, dp, C.c_int]
+    lib.orc_piece_deviation.restype = C.c_double
+    lib.orc_decompose_batch.argtypes = [C.c_int, ip, lp, dp, lp, dp, dp, C.c_int]
+    lib.orc_decompose_batch.restype = C.c_void_p
+    lib.orc_dec_status.argtypes = [C.c_void_p]
+    lib.orc_dec_counts.argtypes = [C.c_void_p, lp]
+    lib.orc_dec_counts.restype = C.c_int64
+    lib.orc_dec_fetch.argtypes = [C.c_void_p, dp, dp, ip]
+    lib.orc_dec_fetch.restype = None
+    lib.orc_dec_free.argtypes = [C.c_void_p]
+    lib.orc_dec_free.restype = None
+    lib.orc_project_batch.argtypes = [C.c_int, ip, lp, dp, lp, dp, C.c_int64, ip, dp, dp, dp, ip, dp, dp,
+                                      C.c_int]
+    lib.orc_max_threads.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def basis(p: int, U, t: float) -> np.ndarray:
+    """All N_{i,p}(t) by the Cox-de Boor recursion (Sec. 4, eq. bsplinebasis)."""
+    U = _d(U)
+    n = U.shape[0] - p - 1
+    N = np.zeros(n)
+    if _load().orc_basis(p, n, _ptr(U, C.c_double), float(t), _ptr(N, C.c_double)) != 0:
+        raise RuntimeError("orc_basis failed")
+    return N
+
+
+def eval_curve(p: int, P, U, t, derivs: bool = False):
+    """C(t) (and C', C'') by de Boor's algorithm on the B-spline of Sec. 4."""
+    P, U, t = _d(P), _d(U), np.atleast_1d(_d(t))
+    m = t.shape[0]
+    X, D1, D2 = np.zeros((m, 3)), np.zeros((m, 3)), np.zeros((m, 3))
+    rc = _load().orc_eval(p, P.shape[0], _ptr(P, C.c_double), _ptr(U, C.c_double), m, _ptr(t, C.c_double),
+                          _ptr(X, C.c_double), _ptr(D1, C.c_double), _ptr(D2, C.c_double))
+    if rc != 0:
+        raise ValueError("bad curve")
+    return (X, D1, D2) if derivs else X
+
+
+def eval_batch(curves, cid, t) -> np.ndarray:
+    """X[i] = C_{cid[i]}(t[i]) over a CSR curve set (de Boor)."""
+    cid = np.ascontiguousarray(cid, dtype=np.int32)
+    t = _d(t)
+    X = np.zeros((t.shape[0], 3))
+    rc = _load().orc_eval_batch(curves.n, _ptr(curves.degree, C.c_int32), _ptr(curves.cp_off, C.c_int64),
+                                _ptr(_d(curves.cp), C.c_double), _ptr(curves.knot_off, C.c_int64),
+                                _ptr(_d(curves.knots), C.c_double), t.shape[0], _ptr(cid, C.c_int32),
+                                _ptr(t, C.c_double), _ptr(X, C.c_double))
+    if rc != 0:
+        raise ValueError("bad curve id")
+    return X
+
+
+def bezier_spans(p: int, P, U):
+    """Bezier control points of every non-degenerate span by Boehm knot insertion (Sec. 5.2.1)."""
+    P, U = _d(P), _d(U)
+    n = P.shape[0]
+    bz = np.zeros((n, p + 1, 3))
+    tab = np.zeros((n, 2))
+    ns = _load().orc_bezier_spans(p, n, _ptr(P, C.c_double), _ptr(U, C.c_double), n, _ptr(bz, C.c_double),
+                                  _ptr(tab, C.c_double))
+    if ns < 0:
+        raise ValueError("bad curve")
+    return bz[:ns].copy(), tab[:ns].copy()
+
+
+def bez_eval(Q, u) -> np.ndarray:
+    """de Casteljau evaluation of a Bezier piece with control points Q[p+1,3] at each u."""
+    Q = _d(Q)
+    u = np.atleast_1d(_d(u))
+    out = np.zeros((u.shape[0], 3))
+    lib = _load()
+    for i, x in enumerate(u):
+        lib.orc_bez_eval(Q.shape[0] - 1, _ptr(Q, C.c_double), float(x), out[i].ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def bez_split(Q, z: float):
+    """de Casteljau split of a Bezier piece at z (Sec. 5.2.2, eq. submatrix)."""
+    Q = _d(Q)
+    p = Q.shape[0] - 1
+    L, R = np.zeros_like(Q), np.zeros_like(Q)
+    _load().orc_bez_split(p, _ptr(Q, C.c_double), float(z), _ptr(L, C.c_double), _ptr(R, C.c_double))
+    return L, R
+
+
+def g1_reduce(Q):
+    """G1-continuous L2-optimal cubic of a degree-p Bezier piece (Sec. 5.2.2); returns (R[4,3], (d0,d1))."""
+    Q = _d(Q)
+    p = Q.shape[0] - 1
+    R = np.zeros((4, 3))
+    dl = np.zeros(2)
+    if _load().orc_g1_reduce(p, _ptr(Q, C.c_double), _ptr(R, C.c_double), _ptr(dl, C.c_double)) != 0:
+        raise ValueError("bad degree")
+    return R, dl
+
+
+def piece_deviation(Q, R, ns: int = 4097) -> float:
+    """max over ns uniform samples of |Q(u) - R(u)| (same-parameter deviation)."""
+    Q, R = _d(Q), _d(R)
+    return float(_load().orc_piece_deviation(Q.shape[0] - 1, _ptr(Q, C.c_double), _ptr(R, C.c_double), ns))
+
+
+def decompose(curves, tol_abs, nthreads: int = 0):
+    """Cubic pieces of every curve: Boehm spans, elevation / G1-L2 reduction, error-controlled splits.
+
+    Returns dict(counts[n], R[S,4,3], tab[S,2] (t_a, t_b), span[S]).
+    """
+    tol = np.broadcast_to(_d(tol_abs), (curves.n,)).copy()
+    lib = _load()
+    h = lib.orc_decompose_batch(curves.n, _ptr(curves.degree, C.c_int32), _ptr(curves.cp_off, C.c_int64),
+                                _ptr(_d(curves.cp), C.c_double), _ptr(curves.knot_off, C.c_int64),
+                                _ptr(_d(curves.knots), C.c_double), _ptr(tol, C.c_double), int(nthreads))
+    try:
+        if lib.orc_dec_status(h) != 0:
+            raise ValueError("decomposition failed (bad curve or piece cap exceeded)")
+        counts = np.zeros(curves.n, np.int64)
+        tot = lib.orc_dec_counts(h, _ptr(counts, C.c_int64))
+        R = np.zeros((tot, 4, 3))
+        tab = np.zeros((tot, 2))
+        span = np.zeros(tot, np.int32)
+        lib.orc_dec_fetch(h, _ptr(R, C.c_double), _ptr(tab, C.c_double), _ptr(span, C.c_int32))
+    finally:
+        lib.orc_dec_free(h)
+    return {"counts": counts, "R": R, "tab": tab, "span": span}
+
+
+def project(curves, cid, q, nthreads: int = 0):
+    """Global minimiser of |q - C(t)| over each query's own curve (Sec. 4, eq. projections).
+
+    Returns dict(t, dist, span, kappa, runner): runner is the distance of the best other local
+    minimum (inf if none), kappa = f'(t*)/|C'(t*)|^2 at a stationary minimiser (1 at a boundary one).
+    """
+    cid = np.ascontiguousarray(cid, dtype=np.int32)
+    q = _d(q).reshape(-1, 3)
+    m = q.shape[0]
+    t, d, kap, run = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
+    span = np.zeros(m, np.int32)
+    rc = _load().orc_project_batch(curves.n, _ptr(curves.degree, C.c_int32), _ptr(curves.cp_off, C.c_int64),
+                                   _ptr(_d(curves.cp), C.c_double), _ptr(curves.knot_off, C.c_int64),
+                                   _ptr(_d(curves.knots), C.c_double), m, _ptr(cid, C.c_int32),
+                                   _ptr(q, C.c_double), _ptr(t, C.c_double), _ptr(d, C.c_double),
+                                   _ptr(span, C.c_int32), _ptr(kap, C.c_double), _ptr(run, C.c_double),
+                                   int(nthreads))
+    if rc != 0:
+        raise ValueError("bad curve or id")
+    return {"t": t, "dist": d, "span": span, "kappa": kap, "runner": run}
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
