@@ -1,0 +1,223 @@
+/*
+ * mrep.h -- C ABI of libmrep: batched point projection and inversion on
+ * B-spline curves through cubic Bezier matrix representations, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operations follow the problem statement and method of Wu & Zou,
+ * "Matrix representation and GPU-optimized parallel B-spline computing":
+ *   - a degree-p B-spline curve C(t) = sum_i N_{i,p}(t) P_i with a clamped knot
+ *     vector (Sec. 4, curve definition and eq. bsplinebasis);
+ *   - its decomposition into Bezier pieces in matrix form
+ *     Q_q = B_p^{-1} M_{q,p,T} A_{q,p,T} P (Sec. 5.2.1, eqs. bsplinematrix,
+ *     Mqpt, decomposition, decomfinal), followed for p >= 4 by a G1,
+ *     L2-optimal reduction to cubic and error-controlled splitting to a
+ *     tolerance (Sec. 5.2.2), for p <= 2 by degree elevation;
+ *   - projection: for each query q the global minimiser
+ *     t* = argmin_t |q - C(t)| over the whole domain (Sec. 4, eqs. projection
+ *     and projections); inversion is projection of an on-curve point
+ *     (Sec. 4, eq. inversion).
+ *
+ * Conventions
+ *   - Every function returns int32_t status: MREP_OK (0) or a negative MREP_E_*
+ *     code; mrep_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Pointer arguments named dev_* or documented as DEVICE are HIP device
+ *     pointers owned by the caller (e.g. torch tensors); the library never
+ *     allocates device memory visible to the caller and never frees caller
+ *     memory.  HOST pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it and the call returns without waiting;
+ *     outputs are valid once the caller synchronises that stream.
+ *   - Coordinates are xyz interleaved (AoS, 3 doubles per point).
+ *   - Parameters t are in the curve's own knot parameter; the domain of a
+ *     clamped curve with n control points is [U[p], U[n]].
+ *   - Per-query outcomes are flag bits in flags_out, never call failures.
+ */
+#ifndef MREP_H
+#define MREP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MREP_ABI_VERSION 1
+
+/* status codes */
+#define MREP_OK 0
+#define MREP_E_INVALID_ARG (-1) /* null pointer, negative size, bad option struct */
+#define MREP_E_BAD_DEGREE (-2)  /* degree < 1 or > MREP_MAX_DEGREE, or too few control points */
+#define MREP_E_BAD_KNOTS (-3)   /* knot vector not non-decreasing, wrong length, not clamped,
+                                   empty domain, interior multiplicity > p, or non-finite */
+#define MREP_E_TOL (-4)         /* tol_rel <= 0, or a span needed more than MREP_MAX_PIECES_PER_SPAN pieces */
+#define MREP_E_SMALL_BUFFER (-5) /* caller buffer smaller than the size the library reported */
+#define MREP_E_HIP (-6)         /* a HIP runtime call failed (message in mrep_last_error) */
+#define MREP_E_NO_DEVICE (-7)   /* no gfx950 device available to the calling thread */
+
+#define MREP_MAX_DEGREE 15
+#define MREP_MAX_PIECES_PER_SPAN 4096
+
+/* per-query flag bits */
+#define MREP_F_POLISHED 0x1u    /* FP64 Newton on the exact degree-p span decided the answer */
+#define MREP_F_NEAR_TIE 0x2u    /* another local minimum lies within the tie margin */
+#define MREP_F_ILL_COND 0x4u    /* near-tangent: f'/|C'|^2 < 1e-2 at the minimiser */
+#define MREP_F_ENDPOINT 0x8u    /* minimiser at an end of the curve's domain */
+#define MREP_F_OFFCURVE 0x10u   /* invert only: distance above the curve's tolerance */
+#define MREP_F_FULLSCAN 0x20u   /* screen candidate list overflowed; every segment was examined */
+#define MREP_F_BAD_ID 0x40u     /* curve_id out of range: outputs are NaN / -1 */
+
+/* screen precisions (mrep_opts.precision) */
+#define MREP_PREC_FP64 0 /* exhaustive FP64 examination of every segment (no MFMA screen) */
+#define MREP_PREC_BF16 3 /* BF16 MFMA screen, FP32 accumulate, FP32 Newton, FP64 polish */
+
+typedef struct mrep_plan mrep_plan; /* host-side decomposition result, owned by the library */
+typedef struct mrep_geom mrep_geom; /* device view into a caller-owned buffer (non-owning) */
+
+/* Summary of a plan. */
+typedef struct {
+    int64_t n_curves;
+    int64_t n_spans;       /* non-degenerate knot spans over all curves */
+    int64_t n_segments;    /* cubic Bezier pieces over all curves */
+    int64_t device_bytes;  /* size of the device buffer mrep_upload needs */
+    int32_t max_degree;
+    int32_t reserved;
+    double tol_rel;
+} mrep_plan_info_t;
+
+/* Options of a projection call.  Set struct_size = sizeof(mrep_opts) and start
+ * from mrep_opts_default(). */
+typedef struct {
+    int32_t struct_size;
+    int32_t precision;      /* MREP_PREC_* */
+    int32_t max_candidates; /* screen candidates kept per query (1..16); overflow -> full scan */
+    int32_t flags;          /* MREP_OPT_* bits */
+    double tie_rel;         /* near-tie margin relative to the curve's box diagonal (default 2e-6) */
+} mrep_opts;
+
+/* mrep_opts.flags: record HIP events around each stage of the call on its
+ * stream; read them back with mrep_last_stage_times. */
+#define MREP_OPT_TIME_STAGES 0x1
+#define MREP_N_STAGES 3 /* grouping by curve, screen, refine + polish + write */
+
+/* ---------------------------------------------------------------------- */
+/* Decomposition (host, FP64)                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Decompose n_curves clamped B-spline curves into cubic Bezier pieces.
+ *   degree[n_curves]           HOST  degree p of each curve (1..MREP_MAX_DEGREE)
+ *   cp_off[n_curves+1]         HOST  CSR offsets (in points) into cp_xyz
+ *   cp_xyz[3*cp_off[n]]        HOST  control points, xyz interleaved
+ *   knot_off[n_curves+1]       HOST  CSR offsets into knots; curve c has
+ *                                    (#points + p + 1) knots
+ *   knots[knot_off[n]]         HOST
+ *   tol_rel                    tolerance relative to each curve's control-point
+ *                              box diagonal: the same-parameter deviation of
+ *                              every cubic piece from the exact curve is at most
+ *                              tol_rel * diag (Sec. 5.2.2, tolerance alpha)
+ *   n_threads                  host threads to use (<= 0: all available)
+ *   out                        receives a new plan; free with mrep_plan_free.
+ * Each span's exact Bezier form is Q = B_p^{-1} M A P (Sec. 5.2.1); p = 3 keeps
+ * it, p <= 2 elevates it, p >= 4 reduces it with the G1 conditions and the
+ * L2-optimal (delta0, delta1) of Sec. 5.2.2 and splits it at the sample of
+ * largest deviation until the tolerance holds.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_BAD_DEGREE, MREP_E_BAD_KNOTS, MREP_E_TOL. */
+int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
+                              const double* cp_xyz, const int64_t* knot_off, const double* knots,
+                              double tol_rel, int32_t n_threads, mrep_plan** out);
+
+/* Summary of a plan.  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info);
+
+/* Host copies of the decomposition (each output nullable):
+ *   seg_off[n_curves+1]  CSR offsets of each curve's pieces
+ *   seg_t[2*n_segments]  (t_a, t_b) of each piece in the curve's parameter
+ *   seg_cp[12*n_segments] the piece's 4 cubic control points, xyz interleaved
+ *   seg_span[n_segments] index of the knot span the piece lies in (global over the plan)
+ * Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_plan_export(const mrep_plan* plan, int64_t* seg_off, double* seg_t, double* seg_cp,
+                         int32_t* seg_span);
+
+void mrep_plan_free(mrep_plan* plan);
+
+/* Copy a plan's tables into a caller-owned DEVICE buffer of at least
+ * info.device_bytes bytes (256-byte aligned), asynchronously on `stream`.
+ * The returned view stays valid while the buffer lives; release it with
+ * mrep_geom_release (which does not touch the buffer).  The plan may be freed
+ * once the stream has passed the copy.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP, MREP_E_NO_DEVICE. */
+int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* stream, mrep_geom** out);
+
+void mrep_geom_release(mrep_geom* geom);
+
+/* ---------------------------------------------------------------------- */
+/* Batched device operations                                              */
+/* ---------------------------------------------------------------------- */
+
+int32_t mrep_opts_default(mrep_opts* opts);
+
+/* DEVICE workspace size for a projection / inversion of n queries.
+ * Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes);
+
+/* Project n query points, each onto its own curve (curve_id), returning the
+ * global minimiser of eq. projection on the EXACT curve.
+ *   curve_id[n]  DEVICE int32
+ *   q_xyz[3n]    DEVICE double, xyz interleaved
+ *   workspace    DEVICE, >= mrep_workspace_bytes(...) bytes, 256-byte aligned
+ *   t_out[n]     DEVICE double   minimising parameter
+ *   dist_out[n]  DEVICE double   |q - C(t)|
+ *   seg_out[n]   DEVICE int32    0-based index of the cubic piece holding t
+ *                                within the curve's piece list (mrep_plan_export)
+ *   flags_out[n] DEVICE uint32   MREP_F_* bits
+ * Queries may come in any order.  Calls on one stream are ordered; the same
+ * workspace must not be used by two calls that may overlap.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
+                            double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
+
+/* Inversion (Sec. 4, eq. inversion): as mrep_project_curves, and additionally
+ * sets MREP_F_OFFCURVE where the distance exceeds the curve's tolerance
+ * tol_rel * diag (the point is then not on the curve). */
+int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                           const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
+                           double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
+
+/* Evaluate C_{curve_id[i]}(t[i]) on the exact curve (FP64).  t outside the
+ * domain is clamped to it.  curve_id[n], t[n], xyz_out[3n]: DEVICE.
+ * Out-of-range ids give NaN.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
+int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t,
+                         double* xyz_out, void* stream);
+
+/* Durations in milliseconds of the stages of the last call on the calling
+ * thread that set MREP_OPT_TIME_STAGES: ms_out[0] grouping, [1] screen (0 in
+ * FP64 mode), [2] refine/polish/write.  Waits for that call's events.
+ * n = capacity of ms_out (>= MREP_N_STAGES).
+ * Errors: MREP_E_INVALID_ARG (no timed call yet, n too small), MREP_E_HIP. */
+int32_t mrep_last_stage_times(double* ms_out, int32_t n);
+
+/* ---------------------------------------------------------------------- */
+/* Host introspection of the constant matrices (for tests and tools)       */
+/* ---------------------------------------------------------------------- */
+
+/* (p+1)x(p+1) row-major.  inverse = 0: B_p with [1 u .. u^p] B_p = Bernstein
+ * basis row (Sec. 5.2.1, eq. bsplineafter); inverse = 1: B_p^{-1}, the
+ * power-to-Bernstein matrix (Sec. 5.3, the rebasement matrix T). */
+int32_t mrep_bernstein_matrix(int32_t p, int32_t inverse, double* out);
+
+/* 2(p+1)x(p+1) row-major subdivision matrix [S_L(z); S_R(z)] of a degree-p
+ * Bezier piece (Sec. 5.2.2, eqs. submatrix and subLandR, at degree p). */
+int32_t mrep_subdivision_matrix(int32_t p, double z, double* out);
+
+/* (m+1)x(n+1) row-major Gram matrix of Bernstein bases (Sec. 5.2.2, eq. gram). */
+int32_t mrep_gram_matrix(int32_t m, int32_t n, double* out);
+
+const char* mrep_last_error(void);
+int32_t mrep_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MREP_H */

@@ -32,7 +32,9 @@
  *     max_u |Q(u) - R(u)|, accepted when its value on 129 uniform samples plus
  *     a Lipschitz allowance (h/2 * max|Q'-R'|) is <= tol;
  *   - a piece that fails is split at the sample of largest deviation (clamped
- *     to [1/8, 7/8]) on the ORIGINAL degree-p piece, and both halves are
+ *     to [1/8, 7/8]; samples within 1e-6 relative of the largest count as
+ *     tied maxima and the smallest of them is taken) on the ORIGINAL degree-p
+ *     piece, and both halves are
  *     reduced again (this makes the split point lie on the original curve,
  *     the effect of the paper's control-polygon modification);
  *   - a zero end tangent leaves its delta at 1 and the other delta is solved
@@ -463,15 +465,18 @@ int orc_g1_reduce(int p, const double *Q, double *R, double *delta)
  * max |Q' - R'| from the hodograph of Q - R written at degree p. */
 static double or_piece_error(int p, const double *Q, const double *R, int *imax)
 {
-    double best = -1.0;
+    double best = -1.0, ev[129];
     int bi = 64;
     for (int i = 0; i <= 128; ++i) {
         double u = (double)i / 128.0, x[3], y[3];
         or_bez_eval(p, Q, u, x);
         or_bez_eval(3, R, u, y);
-        double e = sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) + (x[2] - y[2]) * (x[2] - y[2]));
-        if (e > best) { best = e; bi = i; }
+        ev[i] = sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) + (x[2] - y[2]) * (x[2] - y[2]));
+        if (ev[i] > best) best = ev[i];
     }
+    /* tied maxima (within 1e-6 relative): the smallest parameter is split */
+    for (int i = 0; i <= 128; ++i)
+        if (ev[i] >= best * (1.0 - 1e-6)) { bi = i; break; }
     /* elevate R to degree p */
     double A[OR_MAXP + 2][3], B[OR_MAXP + 2][3];
     memcpy(A, R, sizeof(double) * 12);

@@ -1,0 +1,1109 @@
+// HIP kernels and C-ABI entry points of libmrep (gfx950 / MI355X).
+//
+// Projection pipeline for n queries, each onto its own curve (Sec. 4, eq.
+// projections), after the curves were decomposed into cubic Bezier pieces in
+// matrix form (Sec. 5.2):
+//   1. group queries by curve (histogram, scan, scatter);
+//   2. screen (BF16 mode): for every (query, piece) the squared distance to the
+//      piece's 32 uniform samples is one MFMA contraction of a per-(query,
+//      sample) monomial row with a per-piece coefficient column; the minimum
+//      over samples gives a certified lower bound of the distance to the EXACT
+//      curve over the piece's parameter range, and every piece whose lower
+//      bound does not exceed the best upper bound is kept as a candidate (the
+//      role the paper's elimination criterion, Sec. 5.3, plays);
+//   3. refine: Newton on the orthogonality condition (C - q).C' = 0 (eqs. Et
+//      and E't) from every local minimum of a rescan of each candidate, in
+//      FP32 in the piece's local frame (FP64 in the FP64 mode, which examines
+//      every piece instead of screening);
+//   4. polish: FP64 Newton on the exact degree-p span (power form of the
+//      decomposed span) wherever the cubic is an approximation (p >= 4), the
+//      minimiser is near-tangent, or two minima are nearly tied;
+//   5. write t (FP64 curve parameter, Sec. 5.4.2 reparameterisation), the
+//      distance, the piece index and flags.
+// The paper's per-query minimum under atomic locks (PCWS, Sec. 5.4.2) becomes a
+// per-query ownership: one thread (refine) or one 16-lane row (screen) owns a
+// query, so no lock or atomic is needed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/mrep.h"
+#include "mrep_internal.h"
+
+using namespace mrep;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+struct mrep_plan {
+    Plan p;
+};
+struct mrep_geom {
+    Geom g;
+};
+
+namespace mrep {
+static thread_local std::string t_err;
+void set_error(const std::string& msg) { t_err = msg; }
+}  // namespace mrep
+
+#define HIP_OK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+            return MREP_E_HIP;                                                               \
+        }                                                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device views
+// ---------------------------------------------------------------------------
+struct DevGeom {
+    const DCurve* curves;
+    const uint16_t* col;
+    const float* aux;
+    const float* lcp;
+    const double* gcp;
+    const double* segt;
+    const int32_t* segspan;
+    const double* spant;
+    const int32_t* span0;
+    const double* coef;
+    int32_t n_curves;
+};
+
+static DevGeom dev_view(const Geom& g)
+{
+    DevGeom d;
+    d.curves = reinterpret_cast<const DCurve*>(g.base + g.L.off_curve);
+    d.col = reinterpret_cast<const uint16_t*>(g.base + g.L.off_col);
+    d.aux = reinterpret_cast<const float*>(g.base + g.L.off_aux);
+    d.lcp = reinterpret_cast<const float*>(g.base + g.L.off_lcp);
+    d.gcp = reinterpret_cast<const double*>(g.base + g.L.off_gcp);
+    d.segt = reinterpret_cast<const double*>(g.base + g.L.off_segt);
+    d.segspan = reinterpret_cast<const int32_t*>(g.base + g.L.off_segspan);
+    d.spant = reinterpret_cast<const double*>(g.base + g.L.off_spant);
+    d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
+    d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
+    d.n_curves = (int32_t)g.L.n_curves;
+    return d;
+}
+
+struct Work {
+    int32_t* hist;     // n_curves
+    int32_t* q_off;    // n_curves + 1
+    int32_t* tile_off; // n_curves + 1
+    int32_t* perm;     // n
+    int32_t* cand;     // n * kc
+    int32_t* cand_n;   // n
+    float* ub;         // n
+};
+
+static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Stage timing: events recorded on the call's stream when asked to.
+struct StageEvents {
+    hipEvent_t ev[MREP_N_STAGES + 1] = {};
+    bool created = false, recorded = false;
+};
+static thread_local StageEvents t_stage;
+
+static int stage_record(int i, hipStream_t st)
+{
+    if (!t_stage.created) {
+        for (int k = 0; k <= MREP_N_STAGES; ++k) HIP_OK(hipEventCreate(&t_stage.ev[k]));
+        t_stage.created = true;
+    }
+    HIP_OK(hipEventRecord(t_stage.ev[i], st));
+    return MREP_OK;
+}
+
+static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work* w)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off = a256(off + bytes);
+        return o;
+    };
+    int64_t o_hist = take(4 * n_curves);
+    int64_t o_qoff = take(4 * (n_curves + 1));
+    int64_t o_toff = take(4 * (n_curves + 1));
+    int64_t o_perm = take(4 * n);
+    int64_t o_cand = take(4 * n * kc);
+    int64_t o_candn = take(4 * n);
+    int64_t o_ub = take(4 * n);
+    if (w) {
+        w->hist = reinterpret_cast<int32_t*>(base + o_hist);
+        w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
+        w->tile_off = reinterpret_cast<int32_t*>(base + o_toff);
+        w->perm = reinterpret_cast<int32_t*>(base + o_perm);
+        w->cand = reinterpret_cast<int32_t*>(base + o_cand);
+        w->cand_n = reinterpret_cast<int32_t*>(base + o_candn);
+        w->ub = reinterpret_cast<float*>(base + o_ub);
+    }
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// 1. grouping queries by curve
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_hist(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves, int32_t* __restrict__ hist,
+                       double* __restrict__ t_out, double* __restrict__ d_out, int32_t* __restrict__ s_out,
+                       uint32_t* __restrict__ f_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cid[i];
+    if (c < 0 || c >= n_curves) {
+        t_out[i] = __builtin_nan("");
+        d_out[i] = __builtin_nan("");
+        s_out[i] = -1;
+        f_out[i] = MREP_F_BAD_ID;
+        return;
+    }
+    atomicAdd(&hist[c], 1);
+}
+
+// One workgroup of 1024 threads: q_off = exclusive scan of hist, tile_off =
+// exclusive scan of ceil(hist / kQueriesPerTile); hist is reset to 0 for use
+// as the scatter cursor.
+__global__ __launch_bounds__(1024) void k_scan(int32_t* __restrict__ hist, int32_t n_curves,
+                                               int32_t* __restrict__ q_off, int32_t* __restrict__ tile_off)
+{
+    __shared__ int32_t s_q[1024], s_t[1024];
+    const int tid = threadIdx.x;
+    const int per = (n_curves + 1023) / 1024;
+    const int lo = min(tid * per, n_curves), hi = min(lo + per, n_curves);
+    int32_t sq = 0, st = 0;
+    for (int c = lo; c < hi; ++c) {
+        int32_t h = hist[c];
+        sq += h;
+        st += (h + kQueriesPerTile - 1) / kQueriesPerTile;
+    }
+    s_q[tid] = sq;
+    s_t[tid] = st;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int32_t aq = tid >= d ? s_q[tid - d] : 0;
+        int32_t at = tid >= d ? s_t[tid - d] : 0;
+        __syncthreads();
+        s_q[tid] += aq;
+        s_t[tid] += at;
+        __syncthreads();
+    }
+    int32_t rq = s_q[tid] - sq, rt = s_t[tid] - st;  // exclusive
+    for (int c = lo; c < hi; ++c) {
+        int32_t h = hist[c];
+        q_off[c] = rq;
+        tile_off[c] = rt;
+        rq += h;
+        rt += (h + kQueriesPerTile - 1) / kQueriesPerTile;
+        hist[c] = 0;
+    }
+    if (tid == 1023) {
+        q_off[n_curves] = s_q[1023];
+        tile_off[n_curves] = s_t[1023];
+    }
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves,
+                          const int32_t* __restrict__ q_off, int32_t* __restrict__ cursor, int32_t* __restrict__ perm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cid[i];
+    if (c < 0 || c >= n_curves) return;
+    int32_t pos = atomicAdd(&cursor[c], 1);
+    perm[q_off[c] + pos] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// 2. BF16 MFMA screen
+// ---------------------------------------------------------------------------
+// Row of a (query, sample u) pair, length 32:
+//   [u^j q'_x, u^j q'_y, u^j q'_z  (j = 0..3) | u^m (m = 0..6) | 0 x 13]
+// Column of a piece C(u) = c + sum_j a_j u^j (centre c relative to the curve
+// origin o, q' = q - o):
+//   [-2 a_j (12) | e_m (7) | 0 x 13],  e(u) = |C - c|^2 + 2 c.(C - c)
+// row . col + |q' - c|^2 = |q - C(u)|^2.
+//
+// v_mfma_f32_16x16x32_bf16 operand layout (wave64): lane l supplies row
+// (l & 15) of A and column (l & 15) of B, each with K entries 8*(l>>4) .. +7;
+// the 16x16 FP32 result gives lane l column (l & 15), rows 4*(l>>4) .. +3.
+// Rows of one MFMA are (query g = row>>2, sample 4i + (row&3)) for i = 0..7,
+// so lane l ends up with 4 samples of query (l>>4) against piece (l&15) per
+// MFMA, and 8 MFMAs cover all 32 samples without any cross-lane reduction.
+
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// Screen bound: |computed - exact| of a squared sample distance.  BF16 rounds
+// each row and column entry by <= 2^-8 relative, products are exact in FP32
+// and the FP32 sum adds <= 32 * 2^-24; 0.0085 covers 2 * 2^-8 + both with margin.
+#define SCREEN_KAPPA 0.0085f
+
+constexpr int kSets = 2;  // query sets of 4 per wave
+
+__global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
+                                                     const int32_t* __restrict__ q_off,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ qxyz, int32_t kc,
+                                                     int32_t* __restrict__ cand, int32_t* __restrict__ cand_n,
+                                                     float* __restrict__ ub_out)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short s_col[kChunk * kScreenK];
+    __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
+
+    const int n_curves = G.n_curves;
+    const int tile = blockIdx.x;
+    if (tile >= tile_off[n_curves]) return;
+    // curve owning this tile: last c with tile_off[c] <= tile
+    int lo = 0, hi = n_curves;  // tile_off[lo] <= tile < tile_off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const int c = lo;
+    const DCurve cv = G.curves[c];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int qbase = q_off[c] + (tile - tile_off[c]) * kQueriesPerTile + wave * (4 * kSets);
+    const int qend = q_off[c + 1];
+
+    // A fragments (rows) for both query sets, built once.
+    const int arow = lane & 15;
+    const int kb = lane >> 4;
+    bf16x8 A[kSets][8];
+    float pq[kSets][4];  // post-process query of this lane: x, y, z, max-norm
+    float eq[kSets];
+    bool pvalid[kSets];
+    for (int s = 0; s < kSets; ++s) {
+        int ja = qbase + 4 * s + (arow >> 2);
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        if (ja < qend) {
+            const double* q = qxyz + 3 * (int64_t)perm[ja];
+            qx = (float)(q[0] - cv.origin[0]);
+            qy = (float)(q[1] - cv.origin[1]);
+            qz = (float)(q[2] - cv.origin[2]);
+        }
+        for (int i = 0; i < 8; ++i) {
+            float u = (float)(4 * i + (arow & 3)) / (float)(kSamples - 1);
+            float u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
+            float v[8];
+            if (kb == 0) {
+                v[0] = qx; v[1] = qy; v[2] = qz; v[3] = u * qx; v[4] = u * qy; v[5] = u * qz; v[6] = u2 * qx; v[7] = u2 * qy;
+            } else if (kb == 1) {
+                v[0] = u2 * qz; v[1] = u3 * qx; v[2] = u3 * qy; v[3] = u3 * qz; v[4] = 1.f; v[5] = u; v[6] = u2; v[7] = u3;
+            } else if (kb == 2) {
+                v[0] = u4; v[1] = u5; v[2] = u6; v[3] = 0.f; v[4] = 0.f; v[5] = 0.f; v[6] = 0.f; v[7] = 0.f;
+            } else {
+                for (int k = 0; k < 8; ++k) v[k] = 0.f;
+            }
+            u16x8 bits;
+            for (int k = 0; k < 8; ++k) bits[k] = bf16_bits(v[k]);
+            A[s][i] = __builtin_bit_cast(bf16x8, bits);
+        }
+        int jp = qbase + 4 * s + (lane >> 4);
+        pvalid[s] = jp < qend;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        double nq = 0.0;
+        if (pvalid[s]) {
+            const double* q = qxyz + 3 * (int64_t)perm[jp];
+            px = (float)(q[0] - cv.origin[0]);
+            py = (float)(q[1] - cv.origin[1]);
+            pz = (float)(q[2] - cv.origin[2]);
+            nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        }
+        pq[s][0] = px; pq[s][1] = py; pq[s][2] = pz;
+        pq[s][3] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
+        // rounding of q - o to FP32 moves the query by <= 2^-24 |q - o| per axis,
+        // the origin itself is exact; 2^-22 |q| bounds the distance change
+        eq[s] = (float)(nq * 2.4e-7) + 1e-30f;
+    }
+
+    float ubsq[kSets], lb1[kSets], lb2[kSets], disc[kSets];
+    int s1[kSets], s2[kSets];
+    for (int s = 0; s < kSets; ++s) {
+        ubsq[s] = INFINITY; lb1[s] = INFINITY; lb2[s] = INFINITY; disc[s] = INFINITY; s1[s] = -1; s2[s] = -1;
+    }
+
+    const int nseg = cv.n_seg;
+    for (int base = 0; base < nseg; base += kChunk) {
+        const int cn = min(kChunk, nseg - base);
+        const int cn16 = (cn + 15) & ~15;
+        __syncthreads();
+        // stage columns (64 B each) and aux (32 B each); zero the ragged tail
+        {
+            const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
+            uint4* sc = reinterpret_cast<uint4*>(s_col);
+            for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
+            const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
+            float4* sa = reinterpret_cast<float4*>(s_aux);
+            for (int i = threadIdx.x; i < cn16 * 2; i += 256) sa[i] = (i < cn * 2) ? ga[i] : make_float4(0, 0, 0, 0);
+        }
+        __syncthreads();
+        for (int tb = 0; tb < cn16; tb += 16) {
+            const int sl = tb + (lane & 15);
+            const bf16x8 B = *reinterpret_cast<const bf16x8*>(&s_col[sl * kScreenK + kb * 8]);
+            const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);
+            const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);
+            const bool svalid = sl < cn;
+            const int gseg = (int)(cv.seg_off + base + sl);
+            for (int s = 0; s < kSets; ++s) {
+                float acc = INFINITY;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                    floatx4 r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][i], B, z, 0, 0, 0);
+                    acc = fminf(acc, fminf(r[0], r[1]));
+                    acc = fminf(acc, fminf(r[2], r[3]));
+                }
+                // post-process (query lane>>4 of set s, piece sl)
+                const float dx = pq[s][0] - x0.x, dy = pq[s][1] - x0.y, dz = pq[s][2] - x0.z;
+                const float d2c = dx * dx + dy * dy + dz * dz;
+                const float D = acc + d2c;
+                const float delta = SCREEN_KAPPA * (pq[s][3] * x0.w + x1.x) + 1e-6f * (d2c + fabsf(acc));
+                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - x1.y - eq[s];
+                if (svalid) {
+                    ubsq[s] = fminf(ubsq[s], D + delta);
+                    // keep the two smallest lower bounds; remember the smallest discarded one
+                    if (lb < lb2[s]) {
+                        disc[s] = fminf(disc[s], lb2[s]);
+                        if (lb < lb1[s]) {
+                            lb2[s] = lb1[s]; s2[s] = s1[s]; lb1[s] = lb; s1[s] = gseg;
+                        } else {
+                            lb2[s] = lb; s2[s] = gseg;
+                        }
+                    } else {
+                        disc[s] = fminf(disc[s], lb);
+                    }
+                }
+            }
+        }
+    }
+    // per query (16 lanes): upper bound, candidate list
+    for (int s = 0; s < kSets; ++s) {
+        float u = ubsq[s];
+        for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
+        const float UB = sqrtf(u) + (float)cv.tol_eff + eq[s];
+        const bool c1 = lb1[s] <= UB, c2 = lb2[s] <= UB, ov = disc[s] <= UB;
+        const uint64_t m1 = __ballot(c1), m2 = __ballot(c2), mo = __ballot(ov);
+        const int g = lane >> 4;
+        const uint64_t gm = 0xFFFFull << (16 * g);
+        const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+        const int tot = __popcll(m1 & gm) + __popcll(m2 & gm);
+        const int pos = __popcll(m1 & gm & below) + __popcll(m2 & gm & below);
+        const bool overflow = tot > kc || (mo & gm) != 0ull;
+        const int jp = qbase + 4 * s + g;
+        if (pvalid[s]) {
+            if (c1 && pos < kc) cand[(int64_t)jp * kc + pos] = s1[s];
+            if (c2 && pos + 1 < kc) cand[(int64_t)jp * kc + pos + 1] = s2[s];
+            if ((lane & 15) == 0) {
+                cand_n[jp] = overflow ? -1 : tot;
+                ub_out[jp] = UB;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3-5. refine, polish, write
+// ---------------------------------------------------------------------------
+template <typename T>
+struct V3 {
+    T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ T dot(const V3<T>& a, const V3<T>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// Cubic piece in its local frame: C(u) = a0 + a1 u + a2 u^2 + a3 u^3 (relative
+// to the query), i.e. r(u) = C(u) - q.
+template <typename T>
+struct Cubic {
+    V3<T> a0, a1, a2, a3;
+    __device__ void eval(T u, V3<T>& r, V3<T>& d1, V3<T>& d2) const
+    {
+        r.x = a0.x + u * (a1.x + u * (a2.x + u * a3.x));
+        r.y = a0.y + u * (a1.y + u * (a2.y + u * a3.y));
+        r.z = a0.z + u * (a1.z + u * (a2.z + u * a3.z));
+        d1.x = a1.x + u * ((T)2 * a2.x + u * (T)3 * a3.x);
+        d1.y = a1.y + u * ((T)2 * a2.y + u * (T)3 * a3.y);
+        d1.z = a1.z + u * ((T)2 * a2.z + u * (T)3 * a3.z);
+        d2.x = (T)2 * a2.x + u * (T)6 * a3.x;
+        d2.y = (T)2 * a2.y + u * (T)6 * a3.y;
+        d2.z = (T)2 * a2.z + u * (T)6 * a3.z;
+    }
+    __device__ T dist2(T u) const
+    {
+        T x = a0.x + u * (a1.x + u * (a2.x + u * a3.x));
+        T y = a0.y + u * (a1.y + u * (a2.y + u * a3.y));
+        T z = a0.z + u * (a1.z + u * (a2.z + u * a3.z));
+        return x * x + y * y + z * z;
+    }
+};
+
+// Load piece s as a cubic relative to q.  FP32: local control points minus the
+// local query (q - c computed in FP64).  FP64: global control points minus q.
+__device__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<float>& C)
+{
+    const float* lp = G.lcp + s * 12;
+    const float* ax = G.aux + s * 8;
+    const double cx = cv.origin[0] + (double)ax[AUX_CX];
+    const double cy = cv.origin[1] + (double)ax[AUX_CY];
+    const double cz = cv.origin[2] + (double)ax[AUX_CZ];
+    const float qx = (float)(q[0] - cx), qy = (float)(q[1] - cy), qz = (float)(q[2] - cz);
+    float P[12];
+    for (int i = 0; i < 12; ++i) P[i] = lp[i];
+    C.a0 = {P[0] - qx, P[1] - qy, P[2] - qz};
+    C.a1 = {3.f * (P[3] - P[0]), 3.f * (P[4] - P[1]), 3.f * (P[5] - P[2])};
+    C.a2 = {3.f * (P[6] - 2.f * P[3] + P[0]), 3.f * (P[7] - 2.f * P[4] + P[1]), 3.f * (P[8] - 2.f * P[5] + P[2])};
+    C.a3 = {P[9] - 3.f * P[6] + 3.f * P[3] - P[0], P[10] - 3.f * P[7] + 3.f * P[4] - P[1],
+            P[11] - 3.f * P[8] + 3.f * P[5] - P[2]};
+}
+
+__device__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<double>& C)
+{
+    const double* P = G.gcp + s * 12;
+    double R[12];
+    for (int i = 0; i < 12; ++i) R[i] = P[i];
+    C.a0 = {R[0] - q[0], R[1] - q[1], R[2] - q[2]};
+    C.a1 = {3.0 * (R[3] - R[0]), 3.0 * (R[4] - R[1]), 3.0 * (R[5] - R[2])};
+    C.a2 = {3.0 * (R[6] - 2.0 * R[3] + R[0]), 3.0 * (R[7] - 2.0 * R[4] + R[1]), 3.0 * (R[8] - 2.0 * R[5] + R[2])};
+    C.a3 = {R[9] - 3.0 * R[6] + 3.0 * R[3] - R[0], R[10] - 3.0 * R[7] + 3.0 * R[4] - R[1],
+            R[11] - 3.0 * R[8] + 3.0 * R[5] - R[2]};
+}
+
+template <typename T>
+struct Newt {
+    static constexpr int iters = 8;
+    static constexpr T eps = (T)1e-6;
+};
+template <>
+struct Newt<double> {
+    static constexpr int iters = 40;
+    static constexpr double eps = 1e-15;
+};
+
+// Minimum of |C(u) - q|^2 on [lo, hi] near the sample u0: safeguarded Newton on
+// f = r.C' when f changes sign on the bracket; otherwise the better bracket end.
+template <typename T>
+__device__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_best, T& kappa)
+{
+    V3<T> r, d1, d2;
+    C.eval(lo, r, d1, d2);
+    T flo = dot(r, d1), dlo = dot(r, r);
+    C.eval(hi, r, d1, d2);
+    T fhi = dot(r, d1), dhi = dot(r, r);
+    T u = u0;
+    kappa = (T)1;
+    if (flo < (T)0 && fhi > (T)0) {
+        T a = lo, b = hi;
+        for (int it = 0; it < Newt<T>::iters; ++it) {
+            C.eval(u, r, d1, d2);
+            T f = dot(r, d1);
+            T fp = dot(d1, d1) + dot(r, d2);
+            if (f < (T)0) a = u; else if (f > (T)0) b = u; else break;
+            T un = fp > (T)0 ? u - f / fp : (T)0.5 * (a + b);
+            if (!(un > a && un < b)) un = (T)0.5 * (a + b);
+            T du = un - u;
+            u = un;
+            if (fabs(du) <= Newt<T>::eps * ((T)1 + fabs(u))) break;
+        }
+        C.eval(u, r, d1, d2);
+        T sp = dot(d1, d1);
+        T fp = sp + dot(r, d2);
+        kappa = sp > (T)0 ? fp / sp : (T)1;
+        T d = dot(r, r);
+        u_best = u;
+        d_best = d;
+        if (dlo < d_best) { u_best = lo; d_best = dlo; kappa = (T)1; }
+        if (dhi < d_best) { u_best = hi; d_best = dhi; kappa = (T)1; }
+        return;
+    }
+    u_best = dlo <= dhi ? lo : hi;
+    d_best = dlo <= dhi ? dlo : dhi;
+    T d0 = C.dist2(u0);
+    if (d0 < d_best) { u_best = u0; d_best = d0; }
+}
+
+// Sample k of a piece's local parameter: k / (S-1), the last one exactly 1.
+template <typename T>
+__device__ __forceinline__ T sample_u(int k)
+{
+    return k == kSamples - 1 ? (T)1 : (T)k / (T)(kSamples - 1);
+}
+
+// Best local minimum of one piece: rescan S samples, Newton from each local
+// minimum of the samples.  Returns squared distance, u, kappa.
+template <typename T>
+__device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
+{
+    T dm = C.dist2((T)0), d0 = dm;
+    T d1 = C.dist2(sample_u<T>(1));
+    u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
+    for (int k = 0; k < kSamples; ++k) {
+        // here dm = D(k-1), d0 = D(k), d1 = D(k+1)
+        bool lm = (k == 0 || d0 <= dm) && (k == kSamples - 1 || d0 <= d1);
+        if (lm) {
+            T lo = sample_u<T>(k > 0 ? k - 1 : 0);
+            T hi = sample_u<T>(k < kSamples - 1 ? k + 1 : kSamples - 1);
+            T ub, db, kb;
+            newton_min(C, lo, hi, sample_u<T>(k), ub, db, kb);
+            if (db < d_out) { d_out = db; u_out = ub; k_out = kb; }
+        }
+        dm = d0;
+        d0 = d1;
+        if (k + 2 <= kSamples - 1) d1 = C.dist2(sample_u<T>(k + 2));
+    }
+}
+
+// Exact degree-p span in local power form: C(v) = sum_j c_j v^j, v in [0,1].
+__device__ void span_eval(const double* cf, int p, double v, const double* q, double* r, double* d1, double* d2)
+{
+    double x[3], y[3], z[3];
+    for (int c = 0; c < 3; ++c) { x[c] = cf[3 * p + c]; y[c] = 0.0; z[c] = 0.0; }
+    for (int j = p - 1; j >= 0; --j)
+        for (int c = 0; c < 3; ++c) {
+            z[c] = z[c] * v + 2.0 * y[c];
+            y[c] = y[c] * v + x[c];
+            x[c] = x[c] * v + cf[3 * j + c];
+        }
+    for (int c = 0; c < 3; ++c) { r[c] = x[c] - q[c]; d1[c] = y[c]; d2[c] = z[c]; }
+}
+
+// FP64 Newton on the exact span from global parameter t0; returns (t, dist, kappa).
+__device__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q, double& t_out,
+                       double& d_out, double& k_out)
+{
+    const int p = cv.degree;
+    const double tq = G.spant[2 * span], tq1 = G.spant[2 * span + 1];
+    const double h = tq1 - tq;
+    const double* cf = G.coef + cv.coef_off + (int64_t)(span - cv.span_off) * 3 * (p + 1);
+    double v = (t0 - tq) / h;
+    v = fmin(fmax(v, 0.0), 1.0);
+    double r[3], d1[3], d2[3];
+    span_eval(cf, p, v, q, r, d1, d2);
+    double best_v = v, best_d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    for (int it = 0; it < 12; ++it) {
+        double f = r[0] * d1[0] + r[1] * d1[1] + r[2] * d1[2];
+        double fp = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2] + r[0] * d2[0] + r[1] * d2[1] + r[2] * d2[2];
+        if (!(fp > 0.0)) break;
+        double vn = fmin(fmax(v - f / fp, 0.0), 1.0);
+        double dv = vn - v;
+        v = vn;
+        span_eval(cf, p, v, q, r, d1, d2);
+        double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (d <= best_d) { best_d = d; best_v = v; }
+        if (fabs(dv) <= 1e-15) break;
+    }
+    span_eval(cf, p, best_v, q, r, d1, d2);
+    double sp = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+    double fp = sp + r[0] * d2[0] + r[1] * d2[1] + r[2] * d2[2];
+    k_out = sp > 0.0 ? fp / sp : 1.0;
+    t_out = (best_v == 1.0) ? tq1 : tq + best_v * h;
+    d_out = sqrt(best_d);
+}
+
+struct Cand {
+    double t, d2;   // FP64 global parameter, squared distance (refine precision)
+    double kappa;
+    int32_t seg;
+};
+
+template <typename T>
+__device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cand& b1, Cand& b2)
+{
+    Cubic<T> C;
+    load_cubic(G, cv, s, q, C);
+    T u, d, k;
+    piece_min(C, u, d, k);
+    const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
+    Cand x;
+    x.t = (u == (T)1) ? tb : ta + (double)u * (tb - ta);
+    x.d2 = (double)d;
+    x.kappa = (double)k;
+    x.seg = (int32_t)s;
+    if (x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t)) { b2 = b1; b1 = x; }
+    else if (x.d2 < b2.d2) b2 = x;
+}
+
+// Minimum sampled squared distance of a piece (the full-scan prune).
+template <typename T>
+__device__ T piece_sample_min(const DevGeom& G, const DCurve& cv, int64_t s, const double* q)
+{
+    Cubic<T> C;
+    load_cubic(G, cv, s, q, C);
+    T m = C.dist2((T)0);
+    for (int k = 1; k < kSamples; ++k) m = fmin(m, C.dist2(sample_u<T>(k)));
+    return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __restrict__ cid,
+                                                const double* __restrict__ qxyz,
+                                                const int32_t* __restrict__ q_off,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
+                                                const int32_t* __restrict__ cand_n, int32_t kc, int32_t use_list,
+                                                double tie_rel, int32_t invert, double* __restrict__ t_out,
+                                                double* __restrict__ d_out, int32_t* __restrict__ s_out,
+                                                uint32_t* __restrict__ f_out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[G.n_curves]) return;
+    const int32_t qi = perm[j];
+    const int32_t c = cid[qi];
+    const DCurve cv = G.curves[c];
+    double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    uint32_t flags = 0;
+    Cand b1, b2;
+    b1.d2 = INFINITY; b1.t = 0.0; b1.seg = (int32_t)cv.seg_off; b1.kappa = 1.0;
+    b2 = b1;
+    int n_list = use_list ? cand_n[j] : -1;
+    if (n_list == 0) n_list = -1;  // cannot happen for finite inputs: examine everything
+    // Sampling error of the refine precision on a squared distance (relative).
+    const double rel = sizeof(T) == 4 ? 4e-6 : 1e-14;
+    if (n_list >= 0) {
+        for (int i = 0; i < n_list; ++i) consider<T>(G, cv, cand[j * kc + i], q, b1, b2);
+    } else {
+        if (use_list) flags |= MREP_F_FULLSCAN;
+        // pass 1: best upper bound from the samples of every piece
+        double ub = INFINITY;
+        for (int64_t s = cv.seg_off; s < cv.seg_off + cv.n_seg; ++s) {
+            double m = (double)piece_sample_min<T>(G, cv, s, q);
+            ub = fmin(ub, sqrt(m * (1.0 + rel)) + cv.tol_eff);
+        }
+        // pass 2: refine every piece whose lower bound reaches it
+        for (int64_t s = cv.seg_off; s < cv.seg_off + cv.n_seg; ++s) {
+            double m = (double)piece_sample_min<T>(G, cv, s, q);
+            const float* ax = G.aux + s * 8;
+            double lb = sqrt(fmax(m * (1.0 - rel), 0.0)) - (double)ax[AUX_ES] * 1.001;
+            if (lb <= ub) consider<T>(G, cv, s, q, b1, b2);
+        }
+    }
+    // decide in FP64 on the exact span where the cubic is approximate, the
+    // minimiser is near-tangent, or the runner-up is within the tie margin
+    const double d1 = sqrt(b1.d2), d2 = sqrt(b2.d2);
+    const double margin = 2.0 * cv.tol_eff + (sizeof(T) == 4 ? 2e-6 : 1e-12) * (d1 + cv.diag) + tie_rel * cv.diag;
+    const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
+    const bool approx = cv.degree >= 4;
+    const bool illc = b1.kappa < 1e-2;
+    double t, dist, kap = b1.kappa;
+    int32_t seg = b1.seg;
+    if (approx || tie || illc) {
+        flags |= MREP_F_POLISHED;
+        polish(G, cv, G.segspan[b1.seg], b1.t, q, t, dist, kap);
+        if (tie) {
+            double tt, dd, kk;
+            polish(G, cv, G.segspan[b2.seg], b2.t, q, tt, dd, kk);
+            if (dd < dist || (dd == dist && tt < t)) { t = tt; dist = dd; kap = kk; seg = b2.seg; }
+            if (fabs(dd - dist) <= tie_rel * cv.diag && fabs(tt - t) > 1e-6) flags |= MREP_F_NEAR_TIE;
+        }
+    } else {
+        // exact cubic (p <= 3): FP64 distance at the refined parameter
+        Cubic<double> C;
+        load_cubic(G, cv, seg, q, C);
+        const double ta = G.segt[2 * seg], tb = G.segt[2 * seg + 1];
+        double u = (b1.t - ta) / (tb - ta);
+        u = fmin(fmax(u, 0.0), 1.0);
+        t = b1.t;
+        dist = sqrt(C.dist2(u));
+    }
+    if (kap < 1e-2) flags |= MREP_F_ILL_COND;
+    // piece holding t: [t_a, t_b), the last piece closed
+    {
+        const int64_t s0 = cv.seg_off, s1 = cv.seg_off + cv.n_seg - 1;
+        int64_t s = seg;
+        while (s > s0 && t < G.segt[2 * s]) --s;
+        while (s < s1 && t >= G.segt[2 * s + 1]) ++s;
+        seg = (int32_t)s;
+    }
+    const double dom0 = G.spant[2 * cv.span_off], dom1 = G.spant[2 * (cv.span_off + cv.n_span - 1) + 1];
+    if (t <= dom0 || t >= dom1) flags |= MREP_F_ENDPOINT;
+    if (invert && dist > cv.tol_user) flags |= MREP_F_OFFCURVE;
+    t_out[qi] = t;
+    d_out[qi] = dist;
+    s_out[qi] = (int32_t)(seg - cv.seg_off);
+    f_out[qi] = flags;
+}
+
+__global__ void k_eval(DevGeom G, int64_t n, const int32_t* __restrict__ cid, const double* __restrict__ t,
+                       double* __restrict__ xyz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = cid[i];
+    if (c < 0 || c >= G.n_curves) {
+        xyz[3 * i] = xyz[3 * i + 1] = xyz[3 * i + 2] = __builtin_nan("");
+        return;
+    }
+    const DCurve cv = G.curves[c];
+    const double dom0 = G.spant[2 * cv.span_off], dom1 = G.spant[2 * (cv.span_off + cv.n_span - 1) + 1];
+    double tt = fmin(fmax(t[i], dom0), dom1);
+    int lo = 0, hi = cv.n_span;  // spant[lo].t0 <= tt
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (G.spant[2 * (cv.span_off + mid)] <= tt) lo = mid; else hi = mid;
+    }
+    const int64_t sp = cv.span_off + lo;
+    const double tq = G.spant[2 * sp], tq1 = G.spant[2 * sp + 1];
+    const double v = (tt - tq) / (tq1 - tq);
+    const double* cf = G.coef + cv.coef_off + (int64_t)lo * 3 * (cv.degree + 1);
+    const double z[3] = {0, 0, 0};
+    double r[3], d1[3], d2[3];
+    span_eval(cf, cv.degree, v, z, r, d1, d2);
+    xyz[3 * i] = r[0];
+    xyz[3 * i + 1] = r[1];
+    xyz[3 * i + 2] = r[2];
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+static int check_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("no HIP device");
+        return MREP_E_NO_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        set_error("hipGetDeviceProperties failed");
+        return MREP_E_NO_DEVICE;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error(std::string("libmrep is built for gfx950, device is ") + prop.gcnArchName);
+        return MREP_E_NO_DEVICE;
+    }
+    return MREP_OK;
+}
+
+extern "C" {
+
+int32_t mrep_abi_version(void) { return MREP_ABI_VERSION; }
+
+const char* mrep_last_error(void) { return t_err.c_str(); }
+
+int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
+                              const int64_t* knot_off, const double* knots, double tol_rel, int32_t n_threads,
+                              mrep_plan** out)
+{
+    if (!out || n_curves < 0 || (n_curves > 0 && (!degree || !cp_off || !cp_xyz || !knot_off || !knots))) {
+        set_error("mrep_decompose_curves: null pointer or negative count");
+        return MREP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!(tol_rel > 0.0) || !std::isfinite(tol_rel)) {
+        set_error("mrep_decompose_curves: tol_rel must be positive");
+        return MREP_E_TOL;
+    }
+    mrep_plan* p = new mrep_plan();
+    std::string err;
+    int rc = build_plan(n_curves, degree, cp_off, cp_xyz, knot_off, knots, tol_rel, n_threads, p->p, err);
+    if (rc != MREP_OK) {
+        delete p;
+        set_error("mrep_decompose_curves: " + err);
+        return rc;
+    }
+    *out = p;
+    return MREP_OK;
+}
+
+int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info)
+{
+    if (!plan || !info) {
+        set_error("mrep_plan_info: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    info->n_curves = plan->p.n_curves;
+    info->n_spans = plan->p.layout.n_span;
+    info->n_segments = plan->p.layout.n_seg;
+    info->device_bytes = plan->p.layout.total;
+    info->max_degree = plan->p.max_degree;
+    info->reserved = 0;
+    info->tol_rel = plan->p.tol_rel;
+    return MREP_OK;
+}
+
+int32_t mrep_plan_export(const mrep_plan* plan, int64_t* seg_off, double* seg_t, double* seg_cp, int32_t* seg_span)
+{
+    if (!plan) {
+        set_error("mrep_plan_export: null plan");
+        return MREP_E_INVALID_ARG;
+    }
+    const Plan& P = plan->p;
+    if (seg_off) {
+        for (int64_t c = 0; c < P.n_curves; ++c) seg_off[c] = P.curves[(size_t)c].seg_off;
+        seg_off[P.n_curves] = P.layout.n_seg;
+    }
+    if (seg_t) memcpy(seg_t, P.seg_t.data(), sizeof(double) * P.seg_t.size());
+    if (seg_cp) memcpy(seg_cp, P.seg_cp.data(), sizeof(double) * P.seg_cp.size());
+    if (seg_span) memcpy(seg_span, P.seg_span.data(), sizeof(int32_t) * P.seg_span.size());
+    return MREP_OK;
+}
+
+void mrep_plan_free(mrep_plan* plan) { delete plan; }
+
+int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* stream, mrep_geom** out)
+{
+    if (!plan || !dev_buf || !out) {
+        set_error("mrep_upload: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    const Plan& P = plan->p;
+    if (bytes < P.layout.total) {
+        set_error("mrep_upload: buffer smaller than device_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)dev_buf & 255) != 0) {
+        set_error("mrep_upload: buffer not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char* b = (char*)dev_buf;
+    const GeomLayout& L = P.layout;
+    auto cp = [&](int64_t off, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(b + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    HIP_OK(cp(L.off_curve, P.curves.data(), sizeof(DCurve) * P.curves.size()));
+    HIP_OK(cp(L.off_col, P.col.data(), sizeof(uint16_t) * P.col.size()));
+    HIP_OK(cp(L.off_aux, P.aux.data(), sizeof(float) * P.aux.size()));
+    HIP_OK(cp(L.off_lcp, P.lcp.data(), sizeof(float) * P.lcp.size()));
+    HIP_OK(cp(L.off_gcp, P.seg_cp.data(), sizeof(double) * P.seg_cp.size()));
+    HIP_OK(cp(L.off_segt, P.seg_t.data(), sizeof(double) * P.seg_t.size()));
+    HIP_OK(cp(L.off_segspan, P.seg_span.data(), sizeof(int32_t) * P.seg_span.size()));
+    HIP_OK(cp(L.off_spant, P.span_t.data(), sizeof(double) * P.span_t.size()));
+    HIP_OK(cp(L.off_span0, P.span0.data(), sizeof(int32_t) * P.span0.size()));
+    HIP_OK(cp(L.off_coef, P.coef.data(), sizeof(double) * P.coef.size()));
+    // the plan's host vectors are pageable: finish the copies before returning
+    HIP_OK(hipStreamSynchronize(st));
+    mrep_geom* g = new mrep_geom();
+    g->g.L = L;
+    g->g.base = b;
+    HIP_OK(hipGetDevice(&g->g.device));
+    *out = g;
+    return MREP_OK;
+}
+
+void mrep_geom_release(mrep_geom* geom) { delete geom; }
+
+int32_t mrep_opts_default(mrep_opts* o)
+{
+    if (!o) {
+        set_error("mrep_opts_default: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    o->struct_size = (int32_t)sizeof(mrep_opts);
+    o->precision = MREP_PREC_BF16;
+    o->max_candidates = 8;
+    o->flags = 0;
+    o->tie_rel = 2e-6;
+    return MREP_OK;
+}
+
+static int check_opts(const mrep_opts* o)
+{
+    if (!o || o->struct_size != (int32_t)sizeof(mrep_opts)) {
+        set_error("mrep_opts: null or struct_size mismatch");
+        return MREP_E_INVALID_ARG;
+    }
+    if (o->precision != MREP_PREC_FP64 && o->precision != MREP_PREC_BF16) {
+        set_error("mrep_opts: unsupported precision");
+        return MREP_E_INVALID_ARG;
+    }
+    if (o->max_candidates < 1 || o->max_candidates > kMaxCand) {
+        set_error("mrep_opts: max_candidates out of range 1..16");
+        return MREP_E_INVALID_ARG;
+    }
+    if (!(o->tie_rel >= 0.0)) {
+        set_error("mrep_opts: tie_rel must be >= 0");
+        return MREP_E_INVALID_ARG;
+    }
+    return MREP_OK;
+}
+
+int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
+{
+    if (!geom || !bytes || n < 0) {
+        set_error("mrep_workspace_bytes: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    *bytes = work_layout(geom->g.L.n_curves, n, opts->max_candidates, nullptr, nullptr);
+    return MREP_OK;
+}
+
+static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                           const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
+                           int32_t* seg_out, uint32_t* flags_out, void* stream, int invert)
+{
+    if (!geom || n < 0) {
+        set_error("mrep_project_curves: null geometry or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (n == 0) return MREP_OK;
+    if (n >= ((int64_t)1 << 31) - 1024) {
+        set_error("mrep_project_curves: n must be < 2^31");
+        return MREP_E_INVALID_ARG;
+    }
+    if (!curve_id || !q_xyz || !workspace || !t_out || !dist_out || !seg_out || !flags_out) {
+        set_error("mrep_project_curves: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    const int64_t nc = geom->g.L.n_curves;
+    const int kc = opts->max_candidates;
+    Work w;
+    int64_t need = work_layout(nc, n, kc, (char*)workspace, &w);
+    if (ws_bytes < need) {
+        set_error("mrep_project_curves: workspace smaller than mrep_workspace_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("mrep_project_curves: workspace not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    if (nc == 0) {
+        set_error("mrep_project_curves: geometry has no curves");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    DevGeom G = dev_view(geom->g);
+    const int T = 256;
+    const bool timed = (opts->flags & MREP_OPT_TIME_STAGES) != 0;
+    if (timed) {
+        t_stage.recorded = false;
+        if ((rc = stage_record(0, st))) return rc;
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + T - 1) / T)), dim3(T), 0, st, w.hist, nc, 0);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, st, curve_id, n, (int32_t)nc, w.hist,
+                       t_out, dist_out, seg_out, flags_out);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w.hist, (int32_t)nc, w.q_off, w.tile_off);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, st, curve_id, n, (int32_t)nc,
+                       w.q_off, w.hist, w.perm);
+    if (timed && (rc = stage_record(1, st))) return rc;
+    int use_list = 0;
+    if (opts->precision == MREP_PREC_BF16) {
+        const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile;
+        hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)tiles), dim3(256), 0, st, G, w.tile_off, w.q_off, w.perm,
+                           q_xyz, (int32_t)kc, w.cand, w.cand_n, w.ub);
+        use_list = 1;
+    }
+    if (timed && (rc = stage_record(2, st))) return rc;
+    const int RT = 128;
+    if (opts->precision == MREP_PREC_BF16) {
+        hipLaunchKernelGGL(k_refine<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
+                           w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, use_list, opts->tie_rel, invert, t_out,
+                           dist_out, seg_out, flags_out);
+    } else {
+        hipLaunchKernelGGL(k_refine<double>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
+                           q_xyz, w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, 0, opts->tie_rel, invert, t_out,
+                           dist_out, seg_out, flags_out);
+    }
+    HIP_OK(hipGetLastError());
+    if (timed) {
+        if ((rc = stage_record(3, st))) return rc;
+        t_stage.recorded = true;
+    }
+    return MREP_OK;
+}
+
+int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
+                            int32_t* seg_out, uint32_t* flags_out, void* stream)
+{
+    return run_project(geom, opts, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
+                       stream, 0);
+}
+
+int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                           const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
+                           int32_t* seg_out, uint32_t* flags_out, void* stream)
+{
+    return run_project(geom, opts, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
+                       stream, 1);
+}
+
+int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t, double* xyz_out,
+                         void* stream)
+{
+    if (!geom || n < 0 || (n > 0 && (!curve_id || !t || !xyz_out))) {
+        set_error("mrep_eval_curves: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    DevGeom G = dev_view(geom->g);
+    hipLaunchKernelGGL(k_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, G, n, curve_id, t,
+                       xyz_out);
+    HIP_OK(hipGetLastError());
+    return MREP_OK;
+}
+
+int32_t mrep_last_stage_times(double* ms_out, int32_t n)
+{
+    if (!ms_out || n < MREP_N_STAGES || !t_stage.recorded) {
+        set_error("mrep_last_stage_times: no timed call on this thread, or n too small");
+        return MREP_E_INVALID_ARG;
+    }
+    HIP_OK(hipEventSynchronize(t_stage.ev[MREP_N_STAGES]));
+    for (int k = 0; k < MREP_N_STAGES; ++k) {
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, t_stage.ev[k], t_stage.ev[k + 1]));
+        ms_out[k] = (double)ms;
+    }
+    return MREP_OK;
+}
+
+int32_t mrep_bernstein_matrix(int32_t p, int32_t inverse, double* out)
+{
+    if (p < 1 || p > MREP_MAX_DEGREE || !out) {
+        set_error("mrep_bernstein_matrix: bad degree or null");
+        return MREP_E_INVALID_ARG;
+    }
+    if (inverse) bernstein_inverse(p, out); else bernstein_matrix(p, out);
+    return MREP_OK;
+}
+
+int32_t mrep_subdivision_matrix(int32_t p, double z, double* out)
+{
+    if (p < 1 || p > MREP_MAX_DEGREE || !out) {
+        set_error("mrep_subdivision_matrix: bad degree or null");
+        return MREP_E_INVALID_ARG;
+    }
+    subdivision_matrix(p, z, out);
+    return MREP_OK;
+}
+
+int32_t mrep_gram_matrix(int32_t m, int32_t n, double* out)
+{
+    if (m < 0 || n < 0 || m > 2 * MREP_MAX_DEGREE || n > 2 * MREP_MAX_DEGREE || !out) {
+        set_error("mrep_gram_matrix: bad degree or null");
+        return MREP_E_INVALID_ARG;
+    }
+    gram_matrix(m, n, out);
+    return MREP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,643 @@
+// Host-side M-rep decomposition of clamped B-spline curves (FP64).
+//
+// Each non-degenerate knot span q is converted to its exact Bezier form in the
+// matrix form of Sec. 5.2.1:  Q_q = B_p^{-1} M_{q,p,T} A_{q,p,T} [P_{q-p} .. P_q]
+// (eqs. bsplinematrix, Mqpt, decomposition, decomfinal).  A_{q,p,T} holds the
+// power coefficients of the p+1 basis functions that live on the span; they are
+// produced by running the Cox-de Boor recursion (eq. bsplinebasis) on
+// polynomials.  We expand them in the span-local shifted variable s = t - t_q,
+// which turns M_{q,p,T} into diag(h^j), h = t_{q+1} - t_q: the binomial terms
+// t_q^{i-j} of the paper's M only move the origin of the power basis, and an
+// origin at t = 0 would cost ~(t_q/h)^p of FP64 precision for short spans far
+// from the origin.
+//
+// Cubic conversion (Sec. 5.2.2): p = 3 keeps Q, p <= 2 elevates it, p >= 4
+// takes the G1-continuous cubic R (eq. G1-condition) whose (delta0, delta1)
+// minimise the L2 deviation (eq. epsl), from the 2x2 system obtained by setting
+// the derivatives of eqs. differentiatedelta0/1 to zero with the Gram matrices
+// of eq. gram.  A cubic whose deviation bound exceeds the tolerance is replaced
+// by splitting the ORIGINAL degree-p piece with the degree-p form of the
+// subdivision matrix S(z) (eqs. submatrix, subLandR) at the sample of largest
+// deviation and reducing both halves again, so that the split point lies on
+// the original curve (the effect of the paper's control-polygon modification).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <thread>
+
+#include "../../include/mrep.h"
+#include "mrep_internal.h"
+
+namespace mrep {
+
+namespace {
+
+constexpr int kMaxP = MREP_MAX_DEGREE;
+constexpr int kErrSamples = 129;  // u_i = i / 128
+
+double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return std::round(r);
+}
+
+double ipow(double x, int k)
+{
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r *= x;
+    return r;
+}
+
+// Constant tables per degree: Bernstein inverse, Gram rows, error-sample bases,
+// elevation-to-p of a cubic.
+struct DegreeTables {
+    int p = 0;
+    double Bi[(kMaxP + 1) * (kMaxP + 1)];                 // power -> Bernstein
+    double Bq[kErrSamples * (kMaxP + 1)];                 // B_{k,p}(u_i)
+    double B3[kErrSamples * 4];                           // B_{k,3}(u_i)
+    double E3p[(kMaxP + 1) * 4];                          // cubic written at degree p
+    double G3p[4 * (kMaxP + 1)];                          // Gram G_{3,p}
+    double G33[16];
+};
+
+DegreeTables g_tab[kMaxP + 1];
+std::atomic<int> g_tab_ready{0};
+
+void elevation_matrix(int p, double* E)  // (p+2) x (p+1): degree p -> p+1
+{
+    for (int i = 0; i <= p + 1; ++i)
+        for (int j = 0; j <= p; ++j) {
+            double a = (double)i / (double)(p + 1);
+            double v = 0.0;
+            if (j == i - 1) v += a;
+            if (j == i) v += 1.0 - a;
+            E[i * (p + 1) + j] = v;
+        }
+}
+
+void init_tables()
+{
+    if (g_tab_ready.load(std::memory_order_acquire)) return;
+    static std::atomic<int> once{0};
+    int expected = 0;
+    if (!once.compare_exchange_strong(expected, 1)) {
+        while (!g_tab_ready.load(std::memory_order_acquire)) std::this_thread::yield();
+        return;
+    }
+    for (int p = 1; p <= kMaxP; ++p) {
+        DegreeTables& T = g_tab[p];
+        T.p = p;
+        bernstein_inverse(p, T.Bi);
+        for (int i = 0; i < kErrSamples; ++i) {
+            double u = (double)i / (double)(kErrSamples - 1);
+            for (int k = 0; k <= p; ++k) T.Bq[i * (p + 1) + k] = binom(p, k) * ipow(u, k) * ipow(1.0 - u, p - k);
+            for (int k = 0; k <= 3; ++k) T.B3[i * 4 + k] = binom(3, k) * ipow(u, k) * ipow(1.0 - u, 3 - k);
+        }
+        // E3p = E_{p-1} ... E_3 (identity for p <= 3)
+        double cur[(kMaxP + 1) * 4], nxt[(kMaxP + 1) * 4], E[(kMaxP + 2) * (kMaxP + 1)];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) cur[i * 4 + j] = (i == j) ? 1.0 : 0.0;
+        for (int d = 3; d < p; ++d) {
+            elevation_matrix(d, E);
+            for (int i = 0; i <= d + 1; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k <= d; ++k) s += E[i * (d + 1) + k] * cur[k * 4 + j];
+                    nxt[i * 4 + j] = s;
+                }
+            memcpy(cur, nxt, sizeof(double) * 4 * (size_t)(d + 2));
+        }
+        if (p >= 3) memcpy(T.E3p, cur, sizeof(double) * 4 * (size_t)(p + 1));
+        gram_matrix(3, p, T.G3p);
+        gram_matrix(3, 3, T.G33);
+    }
+    g_tab_ready.store(1, std::memory_order_release);
+}
+
+struct Piece {
+    double R[12];
+    double ta, tb;
+    int32_t span;
+};
+
+struct CurveOut {
+    std::vector<Piece> pieces;
+    std::vector<double> span_t;
+    std::vector<double> coef;   // (p+1)*3 per span
+    std::vector<int32_t> span_first;  // first piece (local) of each span
+    int rc = 0;
+    std::string err;
+    double diag = 0.0, tol_abs = 0.0;
+};
+
+// Power coefficients (in s = t - t_q) of N_{q-p+r, p} for r = 0..p on span q:
+// A[j*(p+1) + r] = coefficient of s^j.  Cox-de Boor on polynomials.
+void span_basis_poly(int p, const double* U, int q, double* A)
+{
+    double N[kMaxP + 2][kMaxP + 2];  // N[r][j], r = i - (q - p)
+    for (int r = 0; r <= p + 1; ++r)
+        for (int j = 0; j <= p + 1; ++j) N[r][j] = 0.0;
+    N[p][0] = 1.0;  // N_{q,0} = 1 on [t_q, t_q+1)
+    const double tq = U[q];
+    for (int k = 1; k <= p; ++k) {
+        double M[kMaxP + 2][kMaxP + 2];
+        for (int r = 0; r <= p + 1; ++r)
+            for (int j = 0; j <= p + 1; ++j) M[r][j] = 0.0;
+        for (int i = q - k; i <= q; ++i) {
+            int r = i - (q - p);
+            // (s + tq - U_i)/(U_{i+k} - U_i) * N_{i,k-1}
+            double d1 = U[i + k] - U[i];
+            if (d1 != 0.0) {
+                double c0 = (tq - U[i]) / d1, c1 = 1.0 / d1;
+                for (int j = 0; j < k; ++j) {
+                    M[r][j] += c0 * N[r][j];
+                    M[r][j + 1] += c1 * N[r][j];
+                }
+            }
+            // (U_{i+k+1} - tq - s)/(U_{i+k+1} - U_{i+1}) * N_{i+1,k-1}
+            double d2 = U[i + k + 1] - U[i + 1];
+            if (d2 != 0.0 && r + 1 <= p) {
+                double c0 = (U[i + k + 1] - tq) / d2, c1 = -1.0 / d2;
+                for (int j = 0; j < k; ++j) {
+                    M[r][j] += c0 * N[r + 1][j];
+                    M[r][j + 1] += c1 * N[r + 1][j];
+                }
+            }
+        }
+        memcpy(N, M, sizeof(N));
+    }
+    for (int j = 0; j <= p; ++j)
+        for (int r = 0; r <= p; ++r) A[j * (p + 1) + r] = N[r][j];
+}
+
+// G1 L2-optimal cubic of a degree-p piece (p >= 4).
+void g1_reduce(int p, const DegreeTables& T, const double* Q, double* R)
+{
+    const double* Q0 = Q;
+    const double* Qp = Q + 3 * p;
+    double a[3], b[3], V1[3], V2[3];
+    const double* g = T.G33;
+    for (int c = 0; c < 3; ++c) {
+        a[c] = (double)p / 3.0 * (Q[3 + c] - Q[c]);
+        b[c] = (double)p / 3.0 * (Q[3 * p + c] - Q[3 * (p - 1) + c]);
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k <= p; ++k) {
+            s1 += T.G3p[1 * (p + 1) + k] * Q[3 * k + c];
+            s2 += T.G3p[2 * (p + 1) + k] * Q[3 * k + c];
+        }
+        V1[c] = s1 - (g[4 + 0] + g[4 + 1]) * Q0[c] - (g[4 + 2] + g[4 + 3]) * Qp[c];
+        V2[c] = s2 - (g[8 + 0] + g[8 + 1]) * Q0[c] - (g[8 + 2] + g[8 + 3]) * Qp[c];
+    }
+    double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double V1a = V1[0] * a[0] + V1[1] * a[1] + V1[2] * a[2];
+    double V2b = V2[0] * b[0] + V2[1] * b[1] + V2[2] * b[2];
+    double g11 = g[5], g12 = g[6], g21 = g[9], g22 = g[10];
+    // g11 aa d0 - g12 ab d1 = V1a ;  g21 ab d0 - g22 bb d1 = V2b
+    double d0 = 1.0, d1 = 1.0;
+    if (aa > 0.0 && bb > 0.0) {
+        double m11 = g11 * aa, m12 = -g12 * ab, m21 = g21 * ab, m22 = -g22 * bb;
+        double det = m11 * m22 - m12 * m21;
+        d0 = (V1a * m22 - m12 * V2b) / det;
+        d1 = (m11 * V2b - m21 * V1a) / det;
+    } else if (aa > 0.0) {
+        d0 = (V1a + g12 * ab * d1) / (g11 * aa);
+    } else if (bb > 0.0) {
+        d1 = (g21 * ab * d0 - V2b) / (g22 * bb);
+    }
+    for (int c = 0; c < 3; ++c) {
+        R[c] = Q0[c];
+        R[3 + c] = Q0[c] + a[c] * d0;
+        R[6 + c] = Qp[c] - b[c] * d1;
+        R[9 + c] = Qp[c];
+    }
+}
+
+// Deviation bound of R from Q: max over the error samples plus (1/256) times a
+// bound on |Q' - R'| from the hodograph of Q - E3p R.
+double deviation_bound(int p, const DegreeTables& T, const double* Q, const double* R, int* imax)
+{
+    double best = -1.0, ev[kErrSamples];
+    int bi = 64;
+    for (int i = 0; i < kErrSamples; ++i) {
+        double x[3] = {0, 0, 0}, y[3] = {0, 0, 0};
+        for (int k = 0; k <= p; ++k)
+            for (int c = 0; c < 3; ++c) x[c] += T.Bq[i * (p + 1) + k] * Q[3 * k + c];
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) y[c] += T.B3[i * 4 + k] * R[3 * k + c];
+        ev[i] = sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) + (x[2] - y[2]) * (x[2] - y[2]));
+        best = std::max(best, ev[i]);
+    }
+    // The deviation can peak at several parameters at once (the paper splits
+    // all of them); samples within 1e-6 relative of the maximum count as tied
+    // and the smallest parameter among them is split first, so that rounding
+    // differences cannot move the split point.
+    for (int i = 0; i < kErrSamples; ++i)
+        if (ev[i] >= best * (1.0 - 1e-6)) { bi = i; break; }
+    double D[(kMaxP + 1) * 3];
+    for (int i = 0; i <= p; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += T.E3p[i * 4 + k] * R[3 * k + c];
+            D[3 * i + c] = Q[3 * i + c] - s;
+        }
+    double L = 0.0;
+    for (int i = 0; i < p; ++i) {
+        double v2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double d = D[3 * (i + 1) + c] - D[3 * i + c];
+            v2 += d * d;
+        }
+        double v = (double)p * sqrt(v2);
+        if (v > L) L = v;
+    }
+    *imax = bi;
+    return best + L / 256.0;
+}
+
+void split_piece(int p, const double* Q, double z, double* L, double* R)
+{
+    double S[2 * (kMaxP + 1) * (kMaxP + 1)];
+    subdivision_matrix(p, z, S);
+    for (int i = 0; i <= p; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double l = 0.0, r = 0.0;
+            for (int k = 0; k <= p; ++k) {
+                l += S[i * (p + 1) + k] * Q[3 * k + c];
+                r += S[(p + 1 + i) * (p + 1) + k] * Q[3 * k + c];
+            }
+            L[3 * i + c] = l;
+            R[3 * i + c] = r;
+        }
+}
+
+bool reduce_span(int p, const DegreeTables& T, const double* Q, double ta, double tb, double tol, int32_t span,
+                 std::vector<Piece>& out)
+{
+    struct Item { double Q[3 * (kMaxP + 1)]; double ta, tb; };
+    std::vector<Item> stack;
+    stack.reserve(64);
+    Item first;
+    memcpy(first.Q, Q, sizeof(double) * 3 * (size_t)(p + 1));
+    first.ta = ta; first.tb = tb;
+    stack.push_back(first);
+    int splits = 0;
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        Piece pc;
+        g1_reduce(p, T, it.Q, pc.R);
+        int imax = 64;
+        double e = deviation_bound(p, T, it.Q, pc.R, &imax);
+        if (e <= tol) {
+            pc.ta = it.ta; pc.tb = it.tb; pc.span = span;
+            out.push_back(pc);
+            continue;
+        }
+        if (++splits >= MREP_MAX_PIECES_PER_SPAN) return false;
+        int iz = std::min(std::max(imax, 16), 112);
+        double z = (double)iz / 128.0;
+        Item l, r;
+        split_piece(p, it.Q, z, l.Q, r.Q);
+        double tm = it.ta + z * (it.tb - it.ta);
+        l.ta = it.ta; l.tb = tm;
+        r.ta = tm; r.tb = it.tb;
+        stack.push_back(r);  // left is processed first: pieces come out in order
+        stack.push_back(l);
+    }
+    return true;
+}
+
+bool validate_curve(int p, int n, const double* P, const double* U, std::string& err, int& code)
+{
+    if (p < 1 || p > kMaxP) { code = MREP_E_BAD_DEGREE; err = "degree out of range"; return false; }
+    if (n < p + 1) { code = MREP_E_BAD_DEGREE; err = "fewer than p+1 control points"; return false; }
+    int m = n + p + 1;
+    for (int i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(P[i])) { code = MREP_E_INVALID_ARG; err = "non-finite control point"; return false; }
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(U[i])) { code = MREP_E_BAD_KNOTS; err = "non-finite knot"; return false; }
+    for (int i = 0; i + 1 < m; ++i)
+        if (U[i + 1] < U[i]) { code = MREP_E_BAD_KNOTS; err = "knots not non-decreasing"; return false; }
+    for (int i = 0; i < p; ++i)
+        if (U[i] != U[p] || U[m - 1 - i] != U[n]) { code = MREP_E_BAD_KNOTS; err = "knot vector not clamped"; return false; }
+    if (!(U[p] < U[n])) { code = MREP_E_BAD_KNOTS; err = "empty parameter domain"; return false; }
+    // interior multiplicity (indices p+1 .. n-1) at most p
+    int run = 1;
+    for (int i = p + 2; i <= n - 1; ++i) {
+        run = (U[i] == U[i - 1]) ? run + 1 : 1;
+        if (run > p) { code = MREP_E_BAD_KNOTS; err = "interior knot multiplicity > degree"; return false; }
+    }
+    if (n - 1 >= p + 1 && U[p + 1] == U[p]) {
+        // an interior knot equal to the clamped start would make multiplicity > p+1 at the end
+        code = MREP_E_BAD_KNOTS; err = "knot vector not clamped (multiplicity > p+1 at an end)"; return false;
+    }
+    if (n - 1 >= p + 1 && U[n - 1] == U[n]) {
+        code = MREP_E_BAD_KNOTS; err = "knot vector not clamped (multiplicity > p+1 at an end)"; return false;
+    }
+    return true;
+}
+
+void decompose_curve(int p, int n, const double* P, const double* U, double tol_rel, CurveOut& out)
+{
+    std::string err;
+    int code = 0;
+    if (!validate_curve(p, n, P, U, err, code)) { out.rc = code; out.err = err; return; }
+    const DegreeTables& T = g_tab[p];
+    double lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], P[3 * i + c]); hi[c] = std::max(hi[c], P[3 * i + c]); }
+    out.diag = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) + (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    out.tol_abs = tol_rel * out.diag;
+    double A[(kMaxP + 1) * (kMaxP + 1)], D[(kMaxP + 1) * 3], Q[(kMaxP + 1) * 3];
+    int32_t span_local = 0;
+    for (int q = p; q <= n - 1; ++q) {
+        if (!(U[q] < U[q + 1])) continue;
+        double h = U[q + 1] - U[q];
+        span_basis_poly(p, U, q, A);
+        // D = diag(h^j) A P_{q-p..q}: power coefficients of the span in local u
+        double hj = 1.0;
+        for (int j = 0; j <= p; ++j) {
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int r = 0; r <= p; ++r) s += A[j * (p + 1) + r] * P[3 * (q - p + r) + c];
+                D[3 * j + c] = hj * s;
+            }
+            hj *= h;
+        }
+        // Q = B_p^{-1} D
+        for (int i = 0; i <= p; ++i)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int j = 0; j <= i; ++j) s += T.Bi[i * (p + 1) + j] * D[3 * j + c];
+                Q[3 * i + c] = s;
+            }
+        out.span_t.push_back(U[q]);
+        out.span_t.push_back(U[q + 1]);
+        out.coef.insert(out.coef.end(), D, D + 3 * (p + 1));
+        out.span_first.push_back((int32_t)out.pieces.size());
+        if (p <= 3) {
+            double Acur[3 * 4], Bn[3 * 4], E[5 * 4];
+            memcpy(Acur, Q, sizeof(double) * 3 * (size_t)(p + 1));
+            for (int d = p; d < 3; ++d) {
+                elevation_matrix(d, E);
+                for (int i = 0; i <= d + 1; ++i)
+                    for (int c = 0; c < 3; ++c) {
+                        double s = 0.0;
+                        for (int k = 0; k <= d; ++k) s += E[i * (d + 1) + k] * Acur[3 * k + c];
+                        Bn[3 * i + c] = s;
+                    }
+                memcpy(Acur, Bn, sizeof(double) * 3 * (size_t)(d + 2));
+            }
+            Piece pc;
+            memcpy(pc.R, Acur, sizeof(pc.R));
+            pc.ta = U[q]; pc.tb = U[q + 1]; pc.span = span_local;
+            out.pieces.push_back(pc);
+        } else {
+            if (!reduce_span(p, T, Q, U[q], U[q + 1], out.tol_abs, span_local, out.pieces)) {
+                out.rc = MREP_E_TOL;
+                out.err = "a span needed more than MREP_MAX_PIECES_PER_SPAN pieces";
+                return;
+            }
+        }
+        span_local++;
+    }
+    if (p <= 3) out.tol_abs = 0.0;
+}
+
+inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Screen and refine tables of one piece.  The centre c = o + c_rel with c_rel
+// rounded to FP32, o the curve origin, so that c is exact in FP64.
+void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* col, float* aux, float* lcp)
+{
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(std::min(R[c], R[3 + c]), std::min(R[6 + c], R[9 + c]));
+        hi[c] = std::max(std::max(R[c], R[3 + c]), std::max(R[6 + c], R[9 + c]));
+    }
+    float cf[3];
+    double cd[3];
+    for (int c = 0; c < 3; ++c) {
+        cf[c] = (float)(0.5 * (lo[c] + hi[c]) - o[c]);
+        cd[c] = o[c] + (double)cf[c];
+    }
+    double crel[3] = {(double)cf[0], (double)cf[1], (double)cf[2]};
+    double a[4][3];
+    for (int c = 0; c < 3; ++c) {
+        a[0][c] = R[c] - cd[c];
+        a[1][c] = 3.0 * (R[3 + c] - R[c]);
+        a[2][c] = 3.0 * (R[6 + c] - 2.0 * R[3 + c] + R[c]);
+        a[3][c] = R[9 + c] - 3.0 * R[6 + c] + 3.0 * R[3 + c] - R[c];
+    }
+    double e[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k) e[j + k] += dot3(a[j], a[k]);
+    for (int m = 0; m < 4; ++m) e[m] += 2.0 * dot3(crel, a[m]);
+    double colv[kScreenK];
+    for (int i = 0; i < kScreenK; ++i) colv[i] = 0.0;
+    for (int j = 0; j < 4; ++j)
+        for (int c = 0; c < 3; ++c) colv[3 * j + c] = -2.0 * a[j][c];
+    for (int m = 0; m < 7; ++m) colv[12 + m] = e[m];
+    double As = 0.0, Es = 0.0;
+    for (int i = 0; i < 12; ++i) As += fabs(colv[i]);
+    for (int m = 0; m < 7; ++m) Es += fabs(e[m]);
+    for (int i = 0; i < kScreenK; ++i) col[i] = f32_to_bf16_rne((float)colv[i]);
+    double L = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double d[3] = {R[3 * (i + 1)] - R[3 * i], R[3 * (i + 1) + 1] - R[3 * i + 1], R[3 * (i + 1) + 2] - R[3 * i + 2]};
+        L = std::max(L, 3.0 * sqrt(dot3(d, d)));
+    }
+    aux[AUX_CX] = cf[0];
+    aux[AUX_CY] = cf[1];
+    aux[AUX_CZ] = cf[2];
+    aux[AUX_A] = (float)(As * 1.01);
+    aux[AUX_E] = (float)(Es * 1.01);
+    aux[AUX_ES] = (float)((L / (2.0 * (kSamples - 1)) + tol_eff) * 1.0001);
+    aux[AUX_L] = (float)L;
+    aux[AUX_TOL] = (float)tol_eff;
+    for (int i = 0; i < 4; ++i)
+        for (int c = 0; c < 3; ++c) lcp[3 * i + c] = (float)(R[3 * i + c] - cd[c]);
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+}  // namespace
+
+uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    uint32_t r = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + r) >> 16);
+}
+
+void bernstein_matrix(int p, double* B)
+{
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i <= p; ++i) B[j * (p + 1) + i] = 0.0;
+    for (int i = 0; i <= p; ++i)
+        for (int k = 0; k <= p - i; ++k)
+            B[(i + k) * (p + 1) + i] = binom(p, i) * binom(p - i, k) * ((k & 1) ? -1.0 : 1.0);
+}
+
+void bernstein_inverse(int p, double* Bi)
+{
+    for (int i = 0; i <= p; ++i)
+        for (int j = 0; j <= p; ++j) Bi[i * (p + 1) + j] = (j <= i) ? binom(i, j) / binom(p, j) : 0.0;
+}
+
+void subdivision_matrix(int p, double z, double* S)
+{
+    int n = p + 1;
+    for (int i = 0; i < 2 * n * n; ++i) S[i] = 0.0;
+    for (int i = 0; i <= p; ++i)
+        for (int j = 0; j <= i; ++j) S[i * n + j] = binom(i, j) * ipow(z, j) * ipow(1.0 - z, i - j);
+    for (int i = 0; i <= p; ++i)
+        for (int j = i; j <= p; ++j) S[(n + i) * n + j] = binom(p - i, j - i) * ipow(z, j - i) * ipow(1.0 - z, p - j);
+}
+
+void gram_matrix(int m, int n, double* G)
+{
+    for (int i = 0; i <= m; ++i)
+        for (int j = 0; j <= n; ++j)
+            G[i * (n + 1) + j] = binom(m, i) * binom(n, j) / ((double)(m + n + 1) * binom(m + n, i + j));
+}
+
+int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
+               const int64_t* knot_off, const double* knots, double tol_rel, int n_threads, Plan& plan,
+               std::string& err)
+{
+    init_tables();
+    std::vector<CurveOut> outs((size_t)n_curves);
+    for (int32_t c = 0; c < n_curves; ++c) {
+        int64_t n = cp_off[c + 1] - cp_off[c];
+        int64_t nk = knot_off[c + 1] - knot_off[c];
+        if (n < 0 || nk < 0) { err = "negative CSR extent"; return MREP_E_INVALID_ARG; }
+        if (degree[c] < 1 || degree[c] > kMaxP) { err = "curve " + std::to_string(c) + ": degree out of range"; return MREP_E_BAD_DEGREE; }
+        if (nk != n + degree[c] + 1) { err = "curve " + std::to_string(c) + ": knot count != points + p + 1"; return MREP_E_BAD_KNOTS; }
+        if (n > (int64_t)1 << 24) { err = "curve too long"; return MREP_E_INVALID_ARG; }
+    }
+    int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::min<int>(nt, std::max<int32_t>(1, n_curves));
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            int32_t c = next.fetch_add(1);
+            if (c >= n_curves) break;
+            decompose_curve(degree[c], (int)(cp_off[c + 1] - cp_off[c]), cp_xyz + 3 * cp_off[c], knots + knot_off[c],
+                            tol_rel, outs[(size_t)c]);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; ++i) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+    for (int32_t c = 0; c < n_curves; ++c)
+        if (outs[(size_t)c].rc) {
+            err = "curve " + std::to_string(c) + ": " + outs[(size_t)c].err;
+            return outs[(size_t)c].rc;
+        }
+    // concatenate
+    plan.n_curves = n_curves;
+    plan.tol_rel = tol_rel;
+    plan.max_degree = 0;
+    plan.curves.resize((size_t)n_curves);
+    int64_t nseg = 0, nspan = 0, ncoef = 0;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const CurveOut& o = outs[(size_t)c];
+        DCurve& d = plan.curves[(size_t)c];
+        d.seg_off = nseg;
+        d.span_off = nspan;
+        d.coef_off = ncoef;
+        d.n_seg = (int32_t)o.pieces.size();
+        d.n_span = (int32_t)(o.span_t.size() / 2);
+        d.degree = degree[c];
+        d.pad = 0;
+        d.tol_eff = degree[c] >= 4 ? o.tol_abs : 1e-13 * o.diag;
+        d.tol_user = tol_rel * o.diag;
+        d.diag = o.diag;
+        {
+            const double* P = cp_xyz + 3 * cp_off[c];
+            int64_t n = cp_off[c + 1] - cp_off[c];
+            for (int k = 0; k < 3; ++k) {
+                double lo = P[k], hi = P[k];
+                for (int64_t i = 0; i < n; ++i) { lo = std::min(lo, P[3 * i + k]); hi = std::max(hi, P[3 * i + k]); }
+                d.origin[k] = (double)(float)(0.5 * (lo + hi));
+            }
+        }
+        nseg += d.n_seg;
+        nspan += d.n_span;
+        ncoef += (int64_t)o.coef.size();
+        plan.max_degree = std::max(plan.max_degree, degree[c]);
+    }
+    if (nseg >= ((int64_t)1 << 31)) { err = "more than 2^31 pieces"; return MREP_E_INVALID_ARG; }
+    plan.seg_cp.resize((size_t)nseg * 12);
+    plan.seg_t.resize((size_t)nseg * 2);
+    plan.seg_span.resize((size_t)nseg);
+    plan.span_t.resize((size_t)nspan * 2);
+    plan.span0.resize((size_t)nspan + 1);
+    plan.coef.resize((size_t)ncoef);
+    plan.col.resize((size_t)nseg * kScreenK);
+    plan.aux.resize((size_t)nseg * 8);
+    plan.lcp.resize((size_t)nseg * 12);
+    std::atomic<int32_t> next2{0};
+    auto worker2 = [&]() {
+        for (;;) {
+            int32_t c = next2.fetch_add(1);
+            if (c >= n_curves) break;
+            const CurveOut& o = outs[(size_t)c];
+            const DCurve& d = plan.curves[(size_t)c];
+            double tol_eff = d.tol_eff;
+            for (int32_t s = 0; s < d.n_seg; ++s) {
+                const Piece& pc = o.pieces[(size_t)s];
+                int64_t g = d.seg_off + s;
+                memcpy(&plan.seg_cp[(size_t)g * 12], pc.R, sizeof(double) * 12);
+                plan.seg_t[(size_t)g * 2] = pc.ta;
+                plan.seg_t[(size_t)g * 2 + 1] = pc.tb;
+                plan.seg_span[(size_t)g] = (int32_t)(d.span_off + pc.span);
+                piece_tables(pc.R, d.origin, tol_eff, &plan.col[(size_t)g * kScreenK], &plan.aux[(size_t)g * 8],
+                             &plan.lcp[(size_t)g * 12]);
+            }
+            for (int32_t j = 0; j < d.n_span; ++j) {
+                plan.span_t[(size_t)(d.span_off + j) * 2] = o.span_t[(size_t)j * 2];
+                plan.span_t[(size_t)(d.span_off + j) * 2 + 1] = o.span_t[(size_t)j * 2 + 1];
+                plan.span0[(size_t)(d.span_off + j)] = (int32_t)(d.seg_off + o.span_first[(size_t)j]);
+            }
+            memcpy(&plan.coef[(size_t)d.coef_off], o.coef.data(), sizeof(double) * o.coef.size());
+        }
+    };
+    th.clear();
+    next2 = 0;
+    for (int i = 1; i < nt; ++i) th.emplace_back(worker2);
+    worker2();
+    for (auto& t : th) t.join();
+    plan.span0[(size_t)nspan] = (int32_t)nseg;
+
+    GeomLayout& L = plan.layout;
+    L.n_curves = n_curves;
+    L.n_seg = nseg;
+    L.n_span = nspan;
+    L.n_coef = ncoef;
+    int64_t off = 0;
+    L.off_curve = off; off = align256(off + (int64_t)sizeof(DCurve) * n_curves);
+    L.off_col = off; off = align256(off + 2 * kScreenK * nseg);
+    L.off_aux = off; off = align256(off + 4 * 8 * nseg);
+    L.off_lcp = off; off = align256(off + 4 * 12 * nseg);
+    L.off_gcp = off; off = align256(off + 8 * 12 * nseg);
+    L.off_segt = off; off = align256(off + 8 * 2 * nseg);
+    L.off_segspan = off; off = align256(off + 4 * nseg);
+    L.off_spant = off; off = align256(off + 8 * 2 * nspan);
+    L.off_span0 = off; off = align256(off + 4 * (nspan + 1));
+    L.off_coef = off; off = align256(off + 8 * ncoef);
+    L.total = off;
+    return MREP_OK;
+}
+
+}  // namespace mrep

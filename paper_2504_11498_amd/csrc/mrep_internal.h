@@ -1,0 +1,99 @@
+// Internal layout shared by the host decomposition and the HIP kernels of
+// libmrep.  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace mrep {
+
+// Samples per cubic piece in the screen and in the per-candidate rescan: the
+// local parameter u_k = k / (kSamples - 1), both ends included.
+constexpr int kSamples = 32;
+// Queries per screen workgroup (4 waves x 8 queries).
+constexpr int kQueriesPerTile = 32;
+// Segments staged in LDS per chunk by the screen.
+constexpr int kChunk = 256;
+// Length of a screen row / column (MFMA K dimension, 19 entries used).
+constexpr int kScreenK = 32;
+constexpr int kMaxCand = 16;
+
+// Per-curve record in device memory.
+struct DCurve {
+    int64_t seg_off;     // first piece (global index)
+    int64_t span_off;    // first span (global index)
+    int64_t coef_off;    // first double of this curve's exact-span power coefficients
+    int32_t n_seg;
+    int32_t n_span;
+    int32_t degree;
+    int32_t pad;
+    double tol_eff;      // same-parameter deviation bound of the pieces (rounding level for p <= 3)
+    double tol_user;     // tol_rel * diag: the caller's tolerance (inversion's on-curve test)
+    double diag;         // control-point box diagonal
+    double origin[3];    // FP32-representable box centre: screen coordinates are relative to it
+};
+static_assert(sizeof(DCurve) == 88, "DCurve layout");
+
+// Offsets (bytes) of each table inside the device buffer.
+struct GeomLayout {
+    int64_t n_curves = 0, n_seg = 0, n_span = 0, n_coef = 0;
+    int64_t off_curve = 0;   // DCurve[n_curves]
+    int64_t off_col = 0;     // uint16 (bf16 bits)[n_seg][32]   screen column
+    int64_t off_aux = 0;     // float[n_seg][8]                 centre, bound terms
+    int64_t off_lcp = 0;     // float[n_seg][12]                control points minus centre
+    int64_t off_gcp = 0;     // double[n_seg][12]               control points (global)
+    int64_t off_segt = 0;    // double[n_seg][2]                (t_a, t_b)
+    int64_t off_segspan = 0; // int32[n_seg]                    span index (global)
+    int64_t off_spant = 0;   // double[n_span][2]               (t_q, t_q+1)
+    int64_t off_span0 = 0;   // int32[n_span + 1]               first piece of each span (global)
+    int64_t off_coef = 0;    // double[n_coef]                  exact span power coefficients in local u
+    int64_t total = 0;
+};
+
+// aux[8] per segment: cx, cy, cz (FP32 centre relative to the curve origin),
+// A (sum |2 a_j|_1), E (sum |e_m|), e (L/(2(S-1)) + tol), L (speed bound in u), tol.
+enum { AUX_CX = 0, AUX_CY, AUX_CZ, AUX_A, AUX_E, AUX_ES, AUX_L, AUX_TOL };
+
+struct Plan {
+    int64_t n_curves = 0;
+    double tol_rel = 0;
+    int32_t max_degree = 0;
+    std::vector<DCurve> curves;
+    // pieces
+    std::vector<double> seg_cp;   // 12 per piece (global FP64)
+    std::vector<double> seg_t;    // 2 per piece
+    std::vector<int32_t> seg_span;
+    // spans
+    std::vector<double> span_t;   // 2 per span
+    std::vector<int32_t> span0;   // n_span + 1
+    std::vector<double> coef;     // exact span power coefficients
+    // derived screen tables
+    std::vector<uint16_t> col;    // 32 per piece
+    std::vector<float> aux;       // 8 per piece
+    std::vector<float> lcp;       // 12 per piece
+    GeomLayout layout;
+};
+
+struct Geom {
+    GeomLayout L;
+    char* base = nullptr;
+    int device = 0;
+    const DCurve* curves() const { return reinterpret_cast<const DCurve*>(base + L.off_curve); }
+};
+
+// host decomposition (mrep_host.cpp)
+int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
+               const int64_t* knot_off, const double* knots, double tol_rel, int n_threads, Plan& plan,
+               std::string& err);
+void bernstein_matrix(int p, double* B);      // (p+1)^2, power coeffs of each Bernstein function
+void bernstein_inverse(int p, double* Bi);    // power -> Bernstein
+void subdivision_matrix(int p, double z, double* S);
+void gram_matrix(int m, int n, double* G);
+uint16_t f32_to_bf16_rne(float x);
+
+void set_error(const std::string& msg);
+
+}  // namespace mrep

@@ -1,0 +1,197 @@
+"""GPU parity: libmrep through its C ABI against the FP64 oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_11498_amd import gen
+from parity import compare, oracle_pieces
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mrep():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_11498_amd import mrep as m
+
+    return m
+
+
+def _run(geom, q, cid, precision, invert=False, max_candidates=8):
+    m = sys.modules["paper_2504_11498_amd.mrep"]
+    opts = m.default_opts(precision, max_candidates=max_candidates)
+    qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    ct = torch.from_numpy(np.ascontiguousarray(cid, dtype=np.int32)).cuda()
+    t, d, s, f = geom.project(qt, ct, opts, invert=invert)
+    torch.cuda.synchronize()
+    return {"t": t.cpu().numpy(), "dist": d.cpu().numpy(), "seg": s.cpu().numpy(), "flags": f.cpu().numpy().view(np.uint32)}
+
+
+@pytest.fixture(scope="module")
+def single(mrep):
+    curves, qs = gen.curve_single(1)
+    plan = mrep.decompose_curves(curves, 1e-6)
+    geom = plan.upload()
+    ref = oracle.project(curves, qs.curve_id, qs.point)
+    return curves, qs, geom, ref, oracle_pieces(curves, 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_single_cubic_all_queries(single, precision):
+    curves, qs, geom, ref, dec = single
+    _say(f"[case] single cubic, 10000 box queries, {precision}")
+    out = _run(geom, qs.point, qs.curve_id, precision)
+    st = compare(curves, qs.curve_id, qs.point, out, ref, dec, label=f"single/{precision}")
+    _say(f"[ok] {st}")
+
+
+@pytest.fixture(scope="module")
+def batched(mrep):
+    curves, qs = gen.curves_batched(2)
+    q = qs.materialise(lambda cid, t: oracle.eval_batch(curves, cid, t))
+    _say("[setup] batched curves: decomposing 4096 curves on the host")
+    plan = mrep.decompose_curves(curves, 1e-6)
+    geom = plan.upload()
+    rng = np.random.default_rng(7)
+    sub = np.sort(rng.choice(qs.n, 20_000, replace=False))
+    ref = oracle.project(curves, qs.curve_id[sub], q[sub])
+    dec = oracle_pieces(curves, 1e-6)
+    return curves, qs, q, plan, geom, sub, ref, dec
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp64"])
+def test_batched_subset(batched, precision):
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say(f"[case] batched curves, 20000-query subset, {precision}")
+    out = _run(geom, q[sub], qs.curve_id[sub], precision)
+    st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label=f"batched/{precision}")
+    _say(f"[ok] {st} fullscan={np.mean((out['flags'] & 0x20) != 0):.4f}")
+
+
+def test_batched_full_size_sampled(batched):
+    """All 1,048,576 queries in the bench launch configuration; 2000 sampled outputs checked."""
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] batched curves, full 1M queries, bf16")
+    out = _run(geom, q, qs.curve_id, "bf16")
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["seg"] >= 0)
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(qs.n, 2000, replace=False))
+    r = oracle.project(curves, qs.curve_id[pick], q[pick])
+    sample = {k: v[pick] for k, v in out.items()}
+    st = compare(curves, qs.curve_id[pick], q[pick], sample, r, dec, label="batched/full")
+    # the subset run and the full run agree bitwise on shared queries (per-query determinism)
+    out_sub = _run(geom, q[sub], qs.curve_id[sub], "bf16")
+    for k in ("t", "dist", "seg"):
+        np.testing.assert_array_equal(out_sub[k], out[k][sub])
+    _say(f"[ok] {st}")
+
+
+def test_repeat_is_bitwise_deterministic(batched):
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] determinism, 20000-query subset x2, bf16")
+    a = _run(geom, q[sub], qs.curve_id[sub], "bf16")
+    b = _run(geom, q[sub[::-1]], qs.curve_id[sub[::-1]], "bf16")
+    for k in ("t", "dist", "seg", "flags"):
+        np.testing.assert_array_equal(a[k], b[k][::-1])
+
+
+def test_candidate_overflow_falls_back_correctly(batched):
+    """max_candidates = 1 forces the full-scan path for many queries; results must not change."""
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] max_candidates=1 (forced full scans), bf16")
+    small = sub[:3000]
+    out = _run(geom, q[small], qs.curve_id[small], "bf16", max_candidates=1)
+    assert np.mean((out["flags"] & 0x20) != 0) > 0.05
+    r = {k: v[:3000] for k, v in ref.items()}
+    compare(curves, qs.curve_id[small], q[small], out, r, dec, label="overflow")
+
+
+def test_inversion_of_on_curve_points(batched):
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] inversion of on-curve points, bf16")
+    rng = np.random.default_rng(3)
+    cid = rng.integers(0, curves.n, 5000).astype(np.int32)
+    t0 = rng.uniform(0, 1, 5000)
+    pts = oracle.eval_batch(curves, cid, t0)
+    out = _run(geom, pts, cid, "bf16", invert=True)
+    diag = curves.bbox_diag()[cid]
+    assert np.all(out["dist"] <= 1e-6 * diag)
+    assert not np.any(out["flags"] & 0x10)
+    r = oracle.project(curves, cid, pts)
+    ok = (r["runner"] - r["dist"]) > 2e-6 * diag
+    assert np.all(np.abs(out["t"][ok] - t0[ok]) <= 1e-7)
+    # offset points are reported off-curve
+    off = pts + rng.normal(size=pts.shape) * (0.01 * diag)[:, None]
+    out2 = _run(geom, off, cid, "bf16", invert=True)
+    assert np.all(((out2["flags"] & 0x10) != 0) == (out2["dist"] > 1e-6 * diag))
+
+
+def test_eval_matches_oracle(batched):
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] eval")
+    rng = np.random.default_rng(5)
+    cid = rng.integers(0, curves.n, 20000).astype(np.int32)
+    t = np.concatenate([rng.uniform(0, 1, 19998), [0.0, 1.0]])
+    xyz = geom.eval(torch.from_numpy(cid).cuda(), torch.from_numpy(t).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(xyz.cpu().numpy(), oracle.eval_batch(curves, cid, t), atol=1e-12)
+
+
+def test_edge_cases(mrep):
+    _say("[case] edge cases: empty, single query, bad ids, endpoints, tiny curves")
+    rng = np.random.default_rng(12)
+    degs, cps, kts = [], [], []
+    for p in [1, 2, 3, 5, 7]:
+        n_cp = p + 1  # a single Bezier span
+        degs.append(p), cps.append(rng.uniform(0, 1, (n_cp, 3))), kts.append(np.r_[np.zeros(p + 1), np.ones(p + 1)])
+    # a straight cubic with equally spaced control points (closed form)
+    A, B = rng.uniform(0, 1, 3), rng.uniform(0, 1, 3)
+    degs.append(3), cps.append(A + np.linspace(0, 1, 4)[:, None] * (B - A)), kts.append(np.r_[np.zeros(4), np.ones(4)])
+    curves = gen._pack(degs, cps, kts)
+    geom = mrep.decompose_curves(curves, 1e-6).upload()
+    # empty call
+    opts = mrep.default_opts("bf16")
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    geom.project(e, torch.empty(0, dtype=torch.int32, device="cuda"), opts)
+    # queries: random, exact endpoints, far away, with bad ids mixed in
+    cid = np.repeat(np.arange(curves.n, dtype=np.int32), 200)
+    q = rng.uniform(-0.5, 1.5, (cid.shape[0], 3))
+    for c in range(curves.n):
+        p, P, U = curves.curve(c)
+        q[c * 200] = P[0]
+        q[c * 200 + 1] = P[-1]
+        q[c * 200 + 2] = P[0] + 100.0
+    for prec in ["fp64", "bf16"]:
+        out = _run(geom, q, cid, prec)
+        ref = oracle.project(curves, cid, q)
+        compare(curves, cid, q, out, ref, oracle_pieces(curves, 1e-6), label=f"edge/{prec}")
+        # endpoints invert to the domain ends
+        for c in range(curves.n):
+            assert out["t"][c * 200] == 0.0 and out["t"][c * 200 + 1] == 1.0
+            assert out["flags"][c * 200] & 0x8 and out["flags"][c * 200 + 1] & 0x8
+        # straight line: closed form
+        sl = cid == curves.n - 1
+        d = B - A
+        ts = np.clip((q[sl] - A) @ d / (d @ d), 0, 1)
+        np.testing.assert_allclose(out["dist"][sl], np.linalg.norm(q[sl] - (A + ts[:, None] * d), axis=1), atol=1e-12)
+        # one query alone
+        one = _run(geom, q[5:6], cid[5:6], prec)
+        assert one["t"][0] == out["t"][5] and one["dist"][0] == out["dist"][5]
+    bad = cid.copy()
+    bad[::7] = curves.n + 3
+    bad[3] = -1
+    out = _run(geom, q, bad, "bf16")
+    isbad = (bad < 0) | (bad >= curves.n)
+    assert np.all((out["flags"][isbad] & 0x40) != 0) and np.all(np.isnan(out["dist"][isbad]))
+    assert np.all(out["seg"][isbad] == -1)
+    assert np.all(np.isfinite(out["dist"][~isbad]))

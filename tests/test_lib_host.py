@@ -1,0 +1,173 @@
+"""CPU tests of libmrep's host side: exported symbols, constant matrices against
+the paper's printed values, the FP64 M-rep decomposition against the oracle's
+independent Boehm-based decomposition, and every host-forceable error code."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import ROOT, load_golden
+from paper_2504_11498_amd import gen
+
+mrep = pytest.importorskip("paper_2504_11498_amd.mrep", reason="libmrep.so not built")
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "mrep.h")).read()
+    declared = set(re.findall(r"\b(mrep_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(mrep.EXPORTS)
+    lib = C.CDLL(mrep.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert mrep.abi_version() == 1
+
+
+def test_rebasement_matrix_matches_printed_T5():
+    T = np.array([[float(v) for v in r.split()] for r in load_golden("power_to_bernstein_deg5.txt")])
+    np.testing.assert_allclose(mrep.bernstein_matrix(5, inverse=True), T, atol=1e-15)
+    for p in range(1, 10):
+        B, Bi = mrep.bernstein_matrix(p), mrep.bernstein_matrix(p, inverse=True)
+        np.testing.assert_allclose(B @ Bi, np.eye(p + 1), atol=1e-12)
+
+
+def test_bernstein_matrix_reproduces_bernstein_basis():
+    from math import comb
+
+    u = np.linspace(0, 1, 11)
+    for p in [2, 3, 6]:
+        U = np.vander(u, p + 1, increasing=True)
+        ref = np.stack([comb(p, i) * u**i * (1 - u) ** (p - i) for i in range(p + 1)], -1)
+        np.testing.assert_allclose(U @ mrep.bernstein_matrix(p), ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("z", [0.2, 0.5, 0.9])
+def test_subdivision_matrix_matches_printed_Sz(z):
+    rows = load_golden("subdivision_matrix_Sz.txt")
+    env = {"__builtins__": {}, "z": z}
+    S = np.array([[eval(e, env) for e in r.split(";")] for r in rows])  # noqa: S307
+    np.testing.assert_allclose(mrep.subdivision_matrix(3, z), S, atol=1e-15)
+
+
+def test_degree_p_subdivision_agrees_with_oracle_de_casteljau():
+    rng = np.random.default_rng(4)
+    for p in [4, 7]:
+        Q = rng.uniform(0, 1, (p + 1, 3))
+        S = mrep.subdivision_matrix(p, 0.3)
+        L, R = oracle.bez_split(Q, 0.3)
+        np.testing.assert_allclose(S[: p + 1] @ Q, L, atol=1e-14)
+        np.testing.assert_allclose(S[p + 1 :] @ Q, R, atol=1e-14)
+
+
+def test_gram_matrix_closed_form():
+    x, w = np.polynomial.legendre.leggauss(30)
+    u, w = 0.5 * (x + 1), 0.5 * w
+    from math import comb
+
+    for m, n in [(3, 3), (3, 6)]:
+        G = mrep.gram_matrix(m, n)
+        for i in range(m + 1):
+            for j in range(n + 1):
+                bi = comb(m, i) * u**i * (1 - u) ** (m - i)
+                bj = comb(n, j) * u**j * (1 - u) ** (n - j)
+                assert abs(G[i, j] - np.sum(w * bi * bj)) < 4e-15
+        np.testing.assert_allclose(G.sum(1), 1.0 / (m + 1), atol=1e-15)  # rows sum to 1/(m+1)
+
+
+def _compare_with_oracle(curves, tol_rel):
+    plan = mrep.decompose_curves(curves, tol_rel)
+    ex = plan.export()
+    diag = curves.bbox_diag()
+    ref = oracle.decompose(curves, tol_rel * diag)
+    counts = np.diff(ex["seg_off"])
+    mismatch = np.nonzero(counts != ref["counts"])[0]
+    return plan, ex, ref, counts, mismatch, diag
+
+
+def test_decomposition_low_degree_matches_boehm():
+    curves, _ = gen.curve_single(1)
+    plan, ex, ref, counts, mismatch, diag = _compare_with_oracle(curves, 1e-6)
+    assert plan.n_segments == 13 and mismatch.size == 0
+    np.testing.assert_array_equal(ex["seg_t"], ref["tab"])
+    assert np.abs(ex["seg_cp"] - ref["R"]).max() <= 1e-13 * diag[0]
+    # p = 2 (elevated) and doubled knots
+    c2 = gen.curves_batched_geometry(seed=8, n_curves=30, deg_lo=2, deg_hi=3, cp_lo=8, cp_hi=60)
+    plan, ex, ref, counts, mismatch, diag = _compare_with_oracle(c2, 1e-6)
+    assert mismatch.size == 0
+    np.testing.assert_array_equal(ex["seg_t"], ref["tab"])
+    assert np.abs(ex["seg_cp"] - ref["R"]).max() <= 1e-12
+
+
+def test_decomposition_high_degree_matches_oracle_breakpoints():
+    curves = gen.curves_batched_geometry(seed=9, n_curves=48, deg_lo=4, deg_hi=7, cp_lo=8, cp_hi=120)
+    plan, ex, ref, counts, mismatch, diag = _compare_with_oracle(curves, 1e-6)
+    assert mismatch.size == 0, mismatch
+    np.testing.assert_allclose(ex["seg_t"], ref["tab"], atol=1e-14)
+    # the G1/L2-optimal cubic is unique: both derivations agree to rounding
+    assert np.abs(ex["seg_cp"] - ref["R"]).max() <= 1e-10
+    # every piece within tolerance of the exact curve (oracle's dense check)
+    worst = 0.0
+    for c in range(curves.n):
+        p, P, U = curves.curve(c)
+        bz, tab = oracle.bezier_spans(p, P, U)
+        for s in range(ex["seg_off"][c], ex["seg_off"][c + 1]):
+            ta, tb = ex["seg_t"][s]
+            k = int(np.searchsorted(tab[:, 0], ta, side="right") - 1)
+            h = tab[k, 1] - tab[k, 0]
+            # exact piece: split the span's Bezier at the piece's local range
+            a, b = (ta - tab[k, 0]) / h, (tb - tab[k, 0]) / h
+            _, right = oracle.bez_split(bz[k], a)
+            piece, _ = oracle.bez_split(right, (b - a) / (1 - a) if a < 1 else 1.0)
+            worst = max(worst, oracle.piece_deviation(piece, ex["seg_cp"][s], 2049) / (1e-6 * diag[c]))
+    assert worst <= 1.0
+
+
+def _curveset(p, P, U):
+    return gen._pack([p], [np.asarray(P, float)], [np.asarray(U, float)])
+
+
+def test_error_codes():
+    P = np.random.default_rng(0).uniform(0, 1, (6, 3))
+    U = np.array([0, 0, 0, 0, 0.4, 0.6, 1, 1, 1, 1.0])
+    mrep.decompose_curves(_curveset(3, P, U), 1e-6)  # valid
+    cases = [
+        (_curveset(0, P, np.concatenate([[0], U[3:7], [1, 1]])), 1e-6, mrep.E_BAD_DEGREE),
+        (_curveset(16, np.zeros((20, 3)), np.linspace(0, 1, 37)), 1e-6, mrep.E_BAD_DEGREE),
+        (_curveset(3, P, U[::-1]), 1e-6, mrep.E_BAD_KNOTS),
+        (_curveset(3, P, np.array([0, 0, 0, 0.1, 0.4, 0.6, 1, 1, 1, 1.0])), 1e-6, mrep.E_BAD_KNOTS),
+        (_curveset(3, P, np.array([0, 0, 0, 0, 0.5, 0.5, 0.5, 0.5, 1, 1, 1, 1.0])[:10]), 1e-6, mrep.E_BAD_KNOTS),
+        (_curveset(3, P, U[:-1]), 1e-6, mrep.E_BAD_KNOTS),
+        (_curveset(3, P, np.where(U == 0.4, np.nan, U)), 1e-6, mrep.E_BAD_KNOTS),
+        (_curveset(3, P, U), 0.0, mrep.E_TOL),
+        (_curveset(3, P, U), -1.0, mrep.E_TOL),
+        (_curveset(2, P[:3], np.array([0, 0, 0, 1, 1, 1.0])), float("nan"), mrep.E_TOL),
+    ]
+    for curves, tol, code in cases:
+        with pytest.raises(mrep.MrepError) as ei:
+            mrep.decompose_curves(curves, tol)
+        assert ei.value.code == code, (ei.value, code)
+    # interior multiplicity p+1
+    U2 = np.array([0, 0, 0, 0, 0.5, 0.5, 0.5, 0.5, 1, 1, 1, 1.0])
+    with pytest.raises(mrep.MrepError) as ei:
+        mrep.decompose_curves(_curveset(3, np.zeros((8, 3)), U2), 1e-6)
+    assert ei.value.code == mrep.E_BAD_KNOTS
+    # null pointers and bad option structs at the C level
+    assert mrep._decompose(1, None, None, None, None, None, 1e-6, 0, None) == mrep.E_INVALID_ARG
+    o = mrep.default_opts()
+    o.struct_size = 3
+    b = C.c_int64()
+    assert mrep._ws_bytes(None, 10, C.byref(o), C.byref(b)) == mrep.E_INVALID_ARG
+    assert mrep._project(None, C.byref(o), 10, None, None, None, 0, None, None, None, None, None) == mrep.E_INVALID_ARG
+    assert mrep._upload(None, None, 0, None, None) == mrep.E_INVALID_ARG
+
+
+def test_piece_cap_is_reported():
+    # an absurd tolerance forces more than the per-span piece cap
+    rng = np.random.default_rng(1)
+    P = rng.uniform(0, 1, (8, 3))
+    U = np.concatenate([np.zeros(8), np.ones(8)])
+    with pytest.raises(mrep.MrepError) as ei:
+        mrep.decompose_curves(_curveset(7, P, U), 1e-17)
+    assert ei.value.code == mrep.E_TOL
