@@ -232,12 +232,15 @@ __global__ void k_scatter(const int32_t* __restrict__ cid, int64_t n, int32_t n_
 // ---------------------------------------------------------------------------
 // 2. BF16 MFMA screen
 // ---------------------------------------------------------------------------
-// Row of a (query, sample u) pair, length 32:
-//   [u^j q'_x, u^j q'_y, u^j q'_z  (j = 0..3) | u^m (m = 0..6) | 0 x 13]
-// Column of a piece C(u) = c + sum_j a_j u^j (centre c relative to the curve
+// Row of a (query, sample) pair, length 32, in the centred sample parameter
+// v = 2u - 1 in [-1, 1]:
+//   [v^j q'_x, v^j q'_y, v^j q'_z  (j = 0..3) | v^m (m = 0..6) | 0 x 13]
+// Column of a piece C = c + sum_j b_j v^j (centre c relative to the curve
 // origin o, q' = q - o):
-//   [-2 a_j (12) | e_m (7) | 0 x 13],  e(u) = |C - c|^2 + 2 c.(C - c)
-// row . col + |q' - c|^2 = |q - C(u)|^2.
+//   [-2 b_j (12) | e_m (7) | 0 x 13],  e(v) = |C - c|^2 + 2 c.(C - c)
+// row . col + |q' - c|^2 = |q - C|^2.  The centred basis keeps |b_j| near the
+// piece's half-chord and curvature terms (the u-basis coefficients are several
+// times the chord), which is what the BF16 rounding bound scales with.
 //
 // v_mfma_f32_16x16x32_bf16 operand layout (wave64): lane l supplies row
 // (l & 15) of A and column (l & 15) of B, each with K entries 8*(l>>4) .. +7;
@@ -303,7 +306,8 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
             qz = (float)(q[2] - cv.origin[2]);
         }
         for (int i = 0; i < 8; ++i) {
-            float u = (float)(4 * i + (arow & 3)) / (float)(kSamples - 1);
+            // centred sample parameter v = 2u - 1 in [-1, 1]
+            float u = -1.0f + 2.0f * (float)(4 * i + (arow & 3)) / (float)(kSamples - 1);
             float u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
             float v[8];
             if (kb == 0) {
@@ -332,9 +336,10 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         }
         pq[s][0] = px; pq[s][1] = py; pq[s][2] = pz;
         pq[s][3] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
-        // rounding of q - o to FP32 moves the query by <= 2^-24 |q - o| per axis,
-        // the origin itself is exact; 2^-22 |q| bounds the distance change
-        eq[s] = (float)(nq * 2.4e-7) + 1e-30f;
+        // rounding q - o to FP32 moves the query by <= 2^-24 |q - o| per axis
+        // (the origin is exact in FP32): 2.4e-7 |q'| bounds the distance change
+        eq[s] = sqrtf(px * px + py * py + pz * pz) * 2.4e-7f + 1e-30f;
+        (void)nq;
     }
 
     float ubsq[kSets], lb1[kSets], lb2[kSets], disc[kSets];
@@ -520,7 +525,9 @@ __device__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_
             T fp = dot(d1, d1) + dot(r, d2);
             if (f < (T)0) a = u; else if (f > (T)0) b = u; else break;
             T un = fp > (T)0 ? u - f / fp : (T)0.5 * (a + b);
-            if (!(un > a && un < b)) un = (T)0.5 * (a + b);
+            // closed bracket: a converged step that rounds onto u (= a or b)
+            // must end the iteration, not trigger a bisection
+            if (!(un >= a && un <= b)) un = (T)0.5 * (a + b);
             T du = un - u;
             u = un;
             if (fabs(du) <= Newt<T>::eps * ((T)1 + fabs(u))) break;
@@ -623,7 +630,19 @@ __device__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double 
 struct Cand {
     double t, d2;   // FP64 global parameter, squared distance (refine precision)
     double kappa;
+    double t_err;   // bound on the parameter error left by the refine precision
     int32_t seg;
+};
+
+template <typename T>
+struct Eps;
+template <>
+struct Eps<float> {
+    static constexpr double v = 5.97e-8;  // 2^-24
+};
+template <>
+struct Eps<double> {
+    static constexpr double v = 1.12e-16;  // 2^-53
 };
 
 template <typename T>
@@ -639,6 +658,17 @@ __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const do
     x.d2 = (double)d;
     x.kappa = (double)k;
     x.seg = (int32_t)s;
+    // Rounding of the terms of f = r.C' (magnitude <= scale * |C'|) moves the
+    // root by about 8 eps scale / (|C'| kappa) in u.
+    {
+        V3<T> r, d1, d2;
+        C.eval(u, r, d1, d2);
+        const double sp = sqrt((double)dot(d1, d1));
+        const double scale = sqrt((double)dot(C.a0, C.a0)) + sqrt((double)dot(C.a1, C.a1)) +
+                             sqrt((double)dot(C.a2, C.a2)) + sqrt((double)dot(C.a3, C.a3));
+        const double kap = fabs((double)k);
+        x.t_err = (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
+    }
     if (x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t)) { b2 = b1; b1 = x; }
     else if (x.d2 < b2.d2) b2 = x;
 }
@@ -672,7 +702,7 @@ __global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __rest
     double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
     uint32_t flags = 0;
     Cand b1, b2;
-    b1.d2 = INFINITY; b1.t = 0.0; b1.seg = (int32_t)cv.seg_off; b1.kappa = 1.0;
+    b1.d2 = INFINITY; b1.t = 0.0; b1.seg = (int32_t)cv.seg_off; b1.kappa = 1.0; b1.t_err = 0.0;
     b2 = b1;
     int n_list = use_list ? cand_n[j] : -1;
     if (n_list == 0) n_list = -1;  // cannot happen for finite inputs: examine everything
@@ -703,9 +733,11 @@ __global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __rest
     const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
     const bool approx = cv.degree >= 4;
     const bool illc = b1.kappa < 1e-2;
+    // FP64 where the refine precision cannot certify the parameter to 1e-8
+    const bool coarse = b1.t_err > 1e-8;
     double t, dist, kap = b1.kappa;
     int32_t seg = b1.seg;
-    if (approx || tie || illc) {
+    if (approx || tie || illc || coarse) {
         flags |= MREP_F_POLISHED;
         polish(G, cv, G.segspan[b1.seg], b1.t, q, t, dist, kap);
         if (tie) {

@@ -435,14 +435,22 @@ void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* co
         a[2][c] = 3.0 * (R[6 + c] - 2.0 * R[3 + c] + R[c]);
         a[3][c] = R[9 + c] - 3.0 * R[6 + c] + 3.0 * R[3 + c] - R[c];
     }
+    // the screen works in the centred parameter v = 2u - 1: b_m = sum_j a_j C(j,m) 2^-j
+    double b[4][3];
+    for (int m = 0; m < 4; ++m)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int j = m; j < 4; ++j) s += a[j][c] * binom(j, m) * ipow(0.5, j);
+            b[m][c] = s;
+        }
     double e[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int j = 0; j < 4; ++j)
-        for (int k = 0; k < 4; ++k) e[j + k] += dot3(a[j], a[k]);
-    for (int m = 0; m < 4; ++m) e[m] += 2.0 * dot3(crel, a[m]);
+        for (int k = 0; k < 4; ++k) e[j + k] += dot3(b[j], b[k]);
+    for (int m = 0; m < 4; ++m) e[m] += 2.0 * dot3(crel, b[m]);
     double colv[kScreenK];
     for (int i = 0; i < kScreenK; ++i) colv[i] = 0.0;
     for (int j = 0; j < 4; ++j)
-        for (int c = 0; c < 3; ++c) colv[3 * j + c] = -2.0 * a[j][c];
+        for (int c = 0; c < 3; ++c) colv[3 * j + c] = -2.0 * b[j][c];
     for (int m = 0; m < 7; ++m) colv[12 + m] = e[m];
     double As = 0.0, Es = 0.0;
     for (int i = 0; i < 12; ++i) As += fabs(colv[i]);
