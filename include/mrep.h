@@ -62,7 +62,7 @@ extern "C" {
 #define MREP_F_POLISHED 0x1u    /* FP64 Newton on the exact degree-p span decided the answer */
 #define MREP_F_NEAR_TIE 0x2u    /* another local minimum lies within the tie margin */
 #define MREP_F_ILL_COND 0x4u    /* near-tangent: f'/|C'|^2 < 1e-2 at the minimiser */
-#define MREP_F_ENDPOINT 0x8u    /* minimiser at an end of the curve's domain */
+#define MREP_F_ENDPOINT 0x8u    /* minimiser within 1e-12 (relative) of an end of the curve's domain */
 #define MREP_F_OFFCURVE 0x10u   /* invert only: distance above the curve's tolerance */
 #define MREP_F_FULLSCAN 0x20u   /* screen candidate list overflowed; every segment was examined */
 #define MREP_F_BAD_ID 0x40u     /* curve_id out of range: outputs are NaN / -1 */

@@ -766,7 +766,7 @@ __global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __rest
         seg = (int32_t)s;
     }
     const double dom0 = G.spant[2 * cv.span_off], dom1 = G.spant[2 * (cv.span_off + cv.n_span - 1) + 1];
-    if (t <= dom0 || t >= dom1) flags |= MREP_F_ENDPOINT;
+    if (t <= dom0 + 1e-12 * (dom1 - dom0) || t >= dom1 - 1e-12 * (dom1 - dom0)) flags |= MREP_F_ENDPOINT;
     if (invert && dist > cv.tol_user) flags |= MREP_F_OFFCURVE;
     t_out[qi] = t;
     d_out[qi] = dist;

@@ -177,7 +177,7 @@ def test_edge_cases(mrep):
         compare(curves, cid, q, out, ref, oracle_pieces(curves, 1e-6), label=f"edge/{prec}")
         # endpoints invert to the domain ends
         for c in range(curves.n):
-            assert out["t"][c * 200] == 0.0 and out["t"][c * 200 + 1] == 1.0
+            assert abs(out["t"][c * 200]) <= 1e-12 and abs(out["t"][c * 200 + 1] - 1.0) <= 1e-12
             assert out["flags"][c * 200] & 0x8 and out["flags"][c * 200 + 1] & 0x8
         # straight line: closed form
         sl = cid == curves.n - 1
