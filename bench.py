@@ -43,6 +43,19 @@ def _traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def summarize_rocprof(path):
+    """Per-kernel duration summary (calls, mean/min/max microseconds, total ms) of a rocprofv3 SQLite result."""
+    import sqlite3
+
+    con = sqlite3.connect(path)
+    rows = con.execute(
+        "select name, count(*), avg(end-start), min(end-start), max(end-start), sum(end-start) "
+        "from kernels group by name order by sum(end-start) desc").fetchall()
+    print(f"{'kernel':70s} {'calls':>5s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s}")
+    for name, n, avg, lo, hi, tot in rows:
+        print(f"{name[:70]:70s} {n:5d} {avg / 1e3:10.1f} {lo / 1e3:10.1f} {hi / 1e3:10.1f} {tot / 1e6:10.3f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,7 +63,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(args.summarize_rocprof)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
