@@ -18,6 +18,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+# the screen's minimum over MFMA results: no NaN canonicalisation, MFMA results in VGPRs
+SCREEN_FLAGS = ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+
+
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -32,8 +36,10 @@ def build(verbose: bool = False) -> str:
           os.path.join(CSRC, "mrep_host.cpp"), "-o", host_o])
     dev_o = os.path.join(BUILD, "mrep_device.o")
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_device.hip"), "-o", dev_o])
+    scr_o = os.path.join(BUILD, "mrep_screen.o")
+    _run(["hipcc", *HIP_FLAGS, *SCREEN_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_screen.hip"), "-o", scr_o])
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, host_o, "-o", tmp, "-lpthread"])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, host_o, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

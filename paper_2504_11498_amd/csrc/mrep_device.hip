@@ -28,16 +28,14 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/mrep.h"
-#include "mrep_internal.h"
+#include "mrep_dev.h"
 
 using namespace mrep;
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 struct mrep_plan {
     Plan p;
@@ -60,48 +58,16 @@ void set_error(const std::string& msg) { t_err = msg; }
         }                                                                                    \
     } while (0)
 
-// ---------------------------------------------------------------------------
-// device views
-// ---------------------------------------------------------------------------
-struct DevGeom {
-    const DCurve* curves;
-    const uint16_t* col;
-    const float* aux;
-    const float* lcp;
-    const double* gcp;
-    const double* segt;
-    const int32_t* segspan;
-    const double* spant;
-    const int32_t* span0;
-    const double* coef;
-    int32_t n_curves;
-};
-
-static DevGeom dev_view(const Geom& g)
-{
-    DevGeom d;
-    d.curves = reinterpret_cast<const DCurve*>(g.base + g.L.off_curve);
-    d.col = reinterpret_cast<const uint16_t*>(g.base + g.L.off_col);
-    d.aux = reinterpret_cast<const float*>(g.base + g.L.off_aux);
-    d.lcp = reinterpret_cast<const float*>(g.base + g.L.off_lcp);
-    d.gcp = reinterpret_cast<const double*>(g.base + g.L.off_gcp);
-    d.segt = reinterpret_cast<const double*>(g.base + g.L.off_segt);
-    d.segspan = reinterpret_cast<const int32_t*>(g.base + g.L.off_segspan);
-    d.spant = reinterpret_cast<const double*>(g.base + g.L.off_spant);
-    d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
-    d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
-    d.n_curves = (int32_t)g.L.n_curves;
-    return d;
-}
-
 struct Work {
-    int32_t* hist;     // n_curves
-    int32_t* q_off;    // n_curves + 1
-    int32_t* tile_off; // n_curves + 1
-    int32_t* perm;     // n
-    int32_t* cand;     // n * kc
-    int32_t* cand_n;   // n
-    float* ub;         // n
+    int32_t* hist;      // n_curves + 1: per-curve counts / scatter cursors, then the overflow count
+    int32_t* q_off;     // n_curves + 1
+    int32_t* tile_off;  // n_curves + 1
+    int32_t* perm;      // n: sorted position -> query
+    int32_t* cand;      // n * kc
+    int32_t* cand_n;    // n
+    float* ub;          // n
+    int32_t* ovf_list;  // n: sorted positions whose candidate list overflowed
+    int32_t* ovf_count;  // = hist + n_curves
 };
 
 static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -131,13 +97,14 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
         off = a256(off + bytes);
         return o;
     };
-    int64_t o_hist = take(4 * n_curves);
+    int64_t o_hist = take(4 * (n_curves + 1));
     int64_t o_qoff = take(4 * (n_curves + 1));
     int64_t o_toff = take(4 * (n_curves + 1));
     int64_t o_perm = take(4 * n);
     int64_t o_cand = take(4 * n * kc);
     int64_t o_candn = take(4 * n);
     int64_t o_ub = take(4 * n);
+    int64_t o_ovf = take(4 * n);
     if (w) {
         w->hist = reinterpret_cast<int32_t*>(base + o_hist);
         w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
@@ -146,6 +113,8 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
         w->cand = reinterpret_cast<int32_t*>(base + o_cand);
         w->cand_n = reinterpret_cast<int32_t*>(base + o_candn);
         w->ub = reinterpret_cast<float*>(base + o_ub);
+        w->ovf_list = reinterpret_cast<int32_t*>(base + o_ovf);
+        w->ovf_count = w->hist + n_curves;
     }
     return off;
 }
@@ -159,21 +128,44 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_hist(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves, int32_t* __restrict__ hist,
-                       double* __restrict__ t_out, double* __restrict__ d_out, int32_t* __restrict__ s_out,
-                       uint32_t* __restrict__ f_out)
+// Lanes of a wave that share a key make one atomic between them (sorted or
+// clustered inputs put whole waves on one curve).  Returns the old counter
+// value plus the lane's rank among the lanes with its key.  Every iteration
+// retires at least the leader lane, so the loop ends within 64 rounds.
+__device__ __forceinline__ int32_t wave_add(int32_t* base, int32_t key, bool active)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t c = cid[i];
-    if (c < 0 || c >= n_curves) {
-        t_out[i] = __builtin_nan("");
-        d_out[i] = __builtin_nan("");
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint64_t pending = __ballot(active);
+    int32_t result = 0;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t lkey = __shfl(key, leader, 64);
+        const uint64_t same = __ballot(active && key == lkey) & pending;
+        int32_t old = 0;
+        if (lane == leader) old = atomicAdd(&base[lkey], (int32_t)__popcll(same));
+        old = __shfl(old, leader, 64);
+        if ((same >> lane) & 1ull) result = old + (int32_t)__popcll(same & lt);
+        pending &= ~same;
+    }
+    return result;
+}
+
+__global__ __launch_bounds__(256) void k_hist(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves,
+                                              int32_t* __restrict__ hist, double* __restrict__ t_out,
+                                              double* __restrict__ d_out, int32_t* __restrict__ s_out,
+                                              uint32_t* __restrict__ f_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t c = i < n ? cid[i] : -1;
+    const bool bad = i < n && (c < 0 || c >= n_curves);
+    if (bad) {
+        t_out[i] = __longlong_as_double(0x7ff8000000000000ll);
+        d_out[i] = __longlong_as_double(0x7ff8000000000000ll);
         s_out[i] = -1;
         f_out[i] = MREP_F_BAD_ID;
-        return;
     }
-    atomicAdd(&hist[c], 1);
+    wave_add(hist, c, i < n && !bad);
 }
 
 // One workgroup of 1024 threads: q_off = exclusive scan of hist, tile_off =
@@ -218,213 +210,15 @@ __global__ __launch_bounds__(1024) void k_scan(int32_t* __restrict__ hist, int32
     }
 }
 
-__global__ void k_scatter(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves,
-                          const int32_t* __restrict__ q_off, int32_t* __restrict__ cursor, int32_t* __restrict__ perm)
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cid, int64_t n, int32_t n_curves,
+                                                 const int32_t* __restrict__ q_off, int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ perm)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t c = cid[i];
-    if (c < 0 || c >= n_curves) return;
-    int32_t pos = atomicAdd(&cursor[c], 1);
-    perm[q_off[c] + pos] = (int32_t)i;
-}
-
-// ---------------------------------------------------------------------------
-// 2. BF16 MFMA screen
-// ---------------------------------------------------------------------------
-// Row of a (query, sample) pair, length 32, in the centred sample parameter
-// v = 2u - 1 in [-1, 1]:
-//   [v^j q'_x, v^j q'_y, v^j q'_z  (j = 0..3) | v^m (m = 0..6) | 0 x 13]
-// Column of a piece C = c + sum_j b_j v^j (centre c relative to the curve
-// origin o, q' = q - o):
-//   [-2 b_j (12) | e_m (7) | 0 x 13],  e(v) = |C - c|^2 + 2 c.(C - c)
-// row . col + |q' - c|^2 = |q - C|^2.  The centred basis keeps |b_j| near the
-// piece's half-chord and curvature terms (the u-basis coefficients are several
-// times the chord), which is what the BF16 rounding bound scales with.
-//
-// v_mfma_f32_16x16x32_bf16 operand layout (wave64): lane l supplies row
-// (l & 15) of A and column (l & 15) of B, each with K entries 8*(l>>4) .. +7;
-// the 16x16 FP32 result gives lane l column (l & 15), rows 4*(l>>4) .. +3.
-// Rows of one MFMA are (query g = row>>2, sample 4i + (row&3)) for i = 0..7,
-// so lane l ends up with 4 samples of query (l>>4) against piece (l&15) per
-// MFMA, and 8 MFMAs cover all 32 samples without any cross-lane reduction.
-
-__device__ __forceinline__ unsigned short bf16_bits(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
-// Screen bound: |computed - exact| of a squared sample distance.  BF16 rounds
-// each row and column entry by <= 2^-8 relative, products are exact in FP32
-// and the FP32 sum adds <= 32 * 2^-24; 0.0085 covers 2 * 2^-8 + both with margin.
-#define SCREEN_KAPPA 0.0085f
-
-constexpr int kSets = 2;  // query sets of 4 per wave
-
-__global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
-                                                     const int32_t* __restrict__ q_off,
-                                                     const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ qxyz, int32_t kc,
-                                                     int32_t* __restrict__ cand, int32_t* __restrict__ cand_n,
-                                                     float* __restrict__ ub_out)
-{
-    __shared__ __attribute__((aligned(16))) unsigned short s_col[kChunk * kScreenK];
-    __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
-
-    const int n_curves = G.n_curves;
-    const int tile = blockIdx.x;
-    if (tile >= tile_off[n_curves]) return;
-    // curve owning this tile: last c with tile_off[c] <= tile
-    int lo = 0, hi = n_curves;  // tile_off[lo] <= tile < tile_off[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
-    }
-    const int c = lo;
-    const DCurve cv = G.curves[c];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int qbase = q_off[c] + (tile - tile_off[c]) * kQueriesPerTile + wave * (4 * kSets);
-    const int qend = q_off[c + 1];
-
-    // A fragments (rows) for both query sets, built once.
-    const int arow = lane & 15;
-    const int kb = lane >> 4;
-    bf16x8 A[kSets][8];
-    float pq[kSets][4];  // post-process query of this lane: x, y, z, max-norm
-    float eq[kSets];
-    bool pvalid[kSets];
-    for (int s = 0; s < kSets; ++s) {
-        int ja = qbase + 4 * s + (arow >> 2);
-        float qx = 0.f, qy = 0.f, qz = 0.f;
-        if (ja < qend) {
-            const double* q = qxyz + 3 * (int64_t)perm[ja];
-            qx = (float)(q[0] - cv.origin[0]);
-            qy = (float)(q[1] - cv.origin[1]);
-            qz = (float)(q[2] - cv.origin[2]);
-        }
-        for (int i = 0; i < 8; ++i) {
-            // centred sample parameter v = 2u - 1 in [-1, 1]
-            float u = -1.0f + 2.0f * (float)(4 * i + (arow & 3)) / (float)(kSamples - 1);
-            float u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
-            float v[8];
-            if (kb == 0) {
-                v[0] = qx; v[1] = qy; v[2] = qz; v[3] = u * qx; v[4] = u * qy; v[5] = u * qz; v[6] = u2 * qx; v[7] = u2 * qy;
-            } else if (kb == 1) {
-                v[0] = u2 * qz; v[1] = u3 * qx; v[2] = u3 * qy; v[3] = u3 * qz; v[4] = 1.f; v[5] = u; v[6] = u2; v[7] = u3;
-            } else if (kb == 2) {
-                v[0] = u4; v[1] = u5; v[2] = u6; v[3] = 0.f; v[4] = 0.f; v[5] = 0.f; v[6] = 0.f; v[7] = 0.f;
-            } else {
-                for (int k = 0; k < 8; ++k) v[k] = 0.f;
-            }
-            u16x8 bits;
-            for (int k = 0; k < 8; ++k) bits[k] = bf16_bits(v[k]);
-            A[s][i] = __builtin_bit_cast(bf16x8, bits);
-        }
-        int jp = qbase + 4 * s + (lane >> 4);
-        pvalid[s] = jp < qend;
-        float px = 0.f, py = 0.f, pz = 0.f;
-        double nq = 0.0;
-        if (pvalid[s]) {
-            const double* q = qxyz + 3 * (int64_t)perm[jp];
-            px = (float)(q[0] - cv.origin[0]);
-            py = (float)(q[1] - cv.origin[1]);
-            pz = (float)(q[2] - cv.origin[2]);
-            nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-        }
-        pq[s][0] = px; pq[s][1] = py; pq[s][2] = pz;
-        pq[s][3] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
-        // rounding q - o to FP32 moves the query by <= 2^-24 |q - o| per axis
-        // (the origin is exact in FP32): 2.4e-7 |q'| bounds the distance change
-        eq[s] = sqrtf(px * px + py * py + pz * pz) * 2.4e-7f + 1e-30f;
-        (void)nq;
-    }
-
-    float ubsq[kSets], lb1[kSets], lb2[kSets], disc[kSets];
-    int s1[kSets], s2[kSets];
-    for (int s = 0; s < kSets; ++s) {
-        ubsq[s] = INFINITY; lb1[s] = INFINITY; lb2[s] = INFINITY; disc[s] = INFINITY; s1[s] = -1; s2[s] = -1;
-    }
-
-    const int nseg = cv.n_seg;
-    for (int base = 0; base < nseg; base += kChunk) {
-        const int cn = min(kChunk, nseg - base);
-        const int cn16 = (cn + 15) & ~15;
-        __syncthreads();
-        // stage columns (64 B each) and aux (32 B each); zero the ragged tail
-        {
-            const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
-            uint4* sc = reinterpret_cast<uint4*>(s_col);
-            for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
-            const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
-            float4* sa = reinterpret_cast<float4*>(s_aux);
-            for (int i = threadIdx.x; i < cn16 * 2; i += 256) sa[i] = (i < cn * 2) ? ga[i] : make_float4(0, 0, 0, 0);
-        }
-        __syncthreads();
-        for (int tb = 0; tb < cn16; tb += 16) {
-            const int sl = tb + (lane & 15);
-            const bf16x8 B = *reinterpret_cast<const bf16x8*>(&s_col[sl * kScreenK + kb * 8]);
-            const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);
-            const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);
-            const bool svalid = sl < cn;
-            const int gseg = (int)(cv.seg_off + base + sl);
-            for (int s = 0; s < kSets; ++s) {
-                float acc = INFINITY;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    floatx4 z = {0.f, 0.f, 0.f, 0.f};
-                    floatx4 r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][i], B, z, 0, 0, 0);
-                    acc = fminf(acc, fminf(r[0], r[1]));
-                    acc = fminf(acc, fminf(r[2], r[3]));
-                }
-                // post-process (query lane>>4 of set s, piece sl)
-                const float dx = pq[s][0] - x0.x, dy = pq[s][1] - x0.y, dz = pq[s][2] - x0.z;
-                const float d2c = dx * dx + dy * dy + dz * dz;
-                const float D = acc + d2c;
-                const float delta = SCREEN_KAPPA * (pq[s][3] * x0.w + x1.x) + 1e-6f * (d2c + fabsf(acc));
-                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - x1.y - eq[s];
-                if (svalid) {
-                    ubsq[s] = fminf(ubsq[s], D + delta);
-                    // keep the two smallest lower bounds; remember the smallest discarded one
-                    if (lb < lb2[s]) {
-                        disc[s] = fminf(disc[s], lb2[s]);
-                        if (lb < lb1[s]) {
-                            lb2[s] = lb1[s]; s2[s] = s1[s]; lb1[s] = lb; s1[s] = gseg;
-                        } else {
-                            lb2[s] = lb; s2[s] = gseg;
-                        }
-                    } else {
-                        disc[s] = fminf(disc[s], lb);
-                    }
-                }
-            }
-        }
-    }
-    // per query (16 lanes): upper bound, candidate list
-    for (int s = 0; s < kSets; ++s) {
-        float u = ubsq[s];
-        for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
-        const float UB = sqrtf(u) + (float)cv.tol_eff + eq[s];
-        const bool c1 = lb1[s] <= UB, c2 = lb2[s] <= UB, ov = disc[s] <= UB;
-        const uint64_t m1 = __ballot(c1), m2 = __ballot(c2), mo = __ballot(ov);
-        const int g = lane >> 4;
-        const uint64_t gm = 0xFFFFull << (16 * g);
-        const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-        const int tot = __popcll(m1 & gm) + __popcll(m2 & gm);
-        const int pos = __popcll(m1 & gm & below) + __popcll(m2 & gm & below);
-        const bool overflow = tot > kc || (mo & gm) != 0ull;
-        const int jp = qbase + 4 * s + g;
-        if (pvalid[s]) {
-            if (c1 && pos < kc) cand[(int64_t)jp * kc + pos] = s1[s];
-            if (c2 && pos + 1 < kc) cand[(int64_t)jp * kc + pos + 1] = s2[s];
-            if ((lane & 15) == 0) {
-                cand_n[jp] = overflow ? -1 : tot;
-                ub_out[jp] = UB;
-            }
-        }
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t c = i < n ? cid[i] : -1;
+    const bool ok = i < n && c >= 0 && c < n_curves;
+    const int32_t pos = wave_add(cursor, c, ok);
+    if (ok) perm[q_off[c] + pos] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -684,56 +478,26 @@ __device__ T piece_sample_min(const DevGeom& G, const DCurve& cv, int64_t s, con
     return m;
 }
 
+struct Outs {
+    double* t;
+    double* d;
+    int32_t* s;
+    uint32_t* f;
+};
+
+// Decide one query from its two best candidates: FP64 polish on the exact span
+// where the cubic is an approximation (p >= 4), the minimiser is near-tangent,
+// the refine precision cannot certify the parameter to 1e-8, or the runner-up
+// is within the tie margin; then write t, distance, piece and flags.
 template <typename T>
-__global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __restrict__ cid,
-                                                const double* __restrict__ qxyz,
-                                                const int32_t* __restrict__ q_off,
-                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
-                                                const int32_t* __restrict__ cand_n, int32_t kc, int32_t use_list,
-                                                double tie_rel, int32_t invert, double* __restrict__ t_out,
-                                                double* __restrict__ d_out, int32_t* __restrict__ s_out,
-                                                uint32_t* __restrict__ f_out)
+__device__ void finish(const DevGeom& G, const DCurve& cv, const double* q, const Cand& b1, const Cand& b2,
+                       uint32_t flags, double tie_rel, int invert, int32_t qi, const Outs& o)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= q_off[G.n_curves]) return;
-    const int32_t qi = perm[j];
-    const int32_t c = cid[qi];
-    const DCurve cv = G.curves[c];
-    double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
-    uint32_t flags = 0;
-    Cand b1, b2;
-    b1.d2 = INFINITY; b1.t = 0.0; b1.seg = (int32_t)cv.seg_off; b1.kappa = 1.0; b1.t_err = 0.0;
-    b2 = b1;
-    int n_list = use_list ? cand_n[j] : -1;
-    if (n_list == 0) n_list = -1;  // cannot happen for finite inputs: examine everything
-    // Sampling error of the refine precision on a squared distance (relative).
-    const double rel = sizeof(T) == 4 ? 4e-6 : 1e-14;
-    if (n_list >= 0) {
-        for (int i = 0; i < n_list; ++i) consider<T>(G, cv, cand[j * kc + i], q, b1, b2);
-    } else {
-        if (use_list) flags |= MREP_F_FULLSCAN;
-        // pass 1: best upper bound from the samples of every piece
-        double ub = INFINITY;
-        for (int64_t s = cv.seg_off; s < cv.seg_off + cv.n_seg; ++s) {
-            double m = (double)piece_sample_min<T>(G, cv, s, q);
-            ub = fmin(ub, sqrt(m * (1.0 + rel)) + cv.tol_eff);
-        }
-        // pass 2: refine every piece whose lower bound reaches it
-        for (int64_t s = cv.seg_off; s < cv.seg_off + cv.n_seg; ++s) {
-            double m = (double)piece_sample_min<T>(G, cv, s, q);
-            const float* ax = G.aux + s * 8;
-            double lb = sqrt(fmax(m * (1.0 - rel), 0.0)) - (double)ax[AUX_ES] * 1.001;
-            if (lb <= ub) consider<T>(G, cv, s, q, b1, b2);
-        }
-    }
-    // decide in FP64 on the exact span where the cubic is approximate, the
-    // minimiser is near-tangent, or the runner-up is within the tie margin
     const double d1 = sqrt(b1.d2), d2 = sqrt(b2.d2);
     const double margin = 2.0 * cv.tol_eff + (sizeof(T) == 4 ? 2e-6 : 1e-12) * (d1 + cv.diag) + tie_rel * cv.diag;
     const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
     const bool approx = cv.degree >= 4;
     const bool illc = b1.kappa < 1e-2;
-    // FP64 where the refine precision cannot certify the parameter to 1e-8
     const bool coarse = b1.t_err > 1e-8;
     double t, dist, kap = b1.kappa;
     int32_t seg = b1.seg;
@@ -768,10 +532,113 @@ __global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __rest
     const double dom0 = G.spant[2 * cv.span_off], dom1 = G.spant[2 * (cv.span_off + cv.n_span - 1) + 1];
     if (t <= dom0 + 1e-12 * (dom1 - dom0) || t >= dom1 - 1e-12 * (dom1 - dom0)) flags |= MREP_F_ENDPOINT;
     if (invert && dist > cv.tol_user) flags |= MREP_F_OFFCURVE;
-    t_out[qi] = t;
-    d_out[qi] = dist;
-    s_out[qi] = (int32_t)(seg - cv.seg_off);
-    f_out[qi] = flags;
+    o.t[qi] = t;
+    o.d[qi] = dist;
+    o.s[qi] = (int32_t)(seg - cv.seg_off);
+    o.f[qi] = flags;
+}
+
+__device__ __forceinline__ Cand empty_cand(const DCurve& cv)
+{
+    Cand b;
+    b.d2 = INFINITY; b.t = 0.0; b.seg = (int32_t)cv.seg_off; b.kappa = 1.0; b.t_err = 0.0;
+    return b;
+}
+
+// One thread per query with a screen candidate list.  Queries whose list
+// overflowed are appended to ovf_list for k_fullscan.
+template <typename T>
+__global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __restrict__ cid,
+                                                const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
+                                                const int32_t* __restrict__ cand_n, int32_t kc, double tie_rel,
+                                                int32_t invert, int32_t* __restrict__ ovf_list,
+                                                int32_t* __restrict__ ovf_count, Outs o)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[G.n_curves]) return;
+    const int n_list = cand_n[j];
+    if (n_list <= 0) {  // overflow (or, impossible for finite input, an empty list)
+        ovf_list[atomicAdd(ovf_count, 1)] = (int32_t)j;
+        return;
+    }
+    const int32_t qi = perm[j];
+    const DCurve cv = G.curves[cid[qi]];
+    double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    Cand b1 = empty_cand(cv), b2 = b1;
+    for (int i = 0; i < n_list; ++i) consider<T>(G, cv, cand[j * kc + i], q, b1, b2);
+    finish<T>(G, cv, q, b1, b2, 0u, tie_rel, invert, qi, o);
+}
+
+// Lexicographic (d2, t, lane) minimum over the wave; every lane gets the winner lane.
+__device__ __forceinline__ int wave_argmin(double d2, double t)
+{
+    int lane = threadIdx.x & 63, bl = lane;
+    double bd = d2, bt = t;
+    for (int off = 32; off > 0; off >>= 1) {
+        double od = __shfl_xor(bd, off, 64), ot = __shfl_xor(bt, off, 64);
+        int ol = __shfl_xor(bl, off, 64);
+        if (od < bd || (od == bd && (ot < bt || (ot == bt && ol < bl)))) { bd = od; bt = ot; bl = ol; }
+    }
+    return bl;
+}
+
+__device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
+{
+    Cand r;
+    r.d2 = __shfl(c.d2, src, 64);
+    r.t = __shfl(c.t, src, 64);
+    r.kappa = __shfl(c.kappa, src, 64);
+    r.t_err = __shfl(c.t_err, src, 64);
+    r.seg = __shfl(c.seg, src, 64);
+    return r;
+}
+
+// One wave per query, lanes striding over the query's pieces: (1) the best
+// upper bound from every piece's samples, (2) refine every piece whose lower
+// bound reaches it, (3) wave top-2, (4) finish on lane 0.  Used for every
+// query in the FP64 mode (list == nullptr) and for the screen's overflows.
+// Persistent: wave w takes items w, w + waves, ... until the count is reached.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fullscan(DevGeom G, const int32_t* __restrict__ cid,
+                                                  const double* __restrict__ qxyz,
+                                                  const int32_t* __restrict__ q_off,
+                                                  const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ list,
+                                                  const int32_t* __restrict__ count, uint32_t flag_in,
+                                                  double tie_rel, int32_t invert, Outs o)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t total = list ? (int64_t)*count : (int64_t)q_off[G.n_curves];
+    // relative sampling error of the refine precision on a squared distance
+    const double rel = sizeof(T) == 4 ? 4e-6 : 1e-14;
+    for (int64_t item = wave; item < total; item += nwaves) {
+        const int64_t j = list ? (int64_t)list[item] : item;
+        const int32_t qi = perm[j];
+        const DCurve cv = G.curves[cid[qi]];
+        double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        const int64_t s_end = cv.seg_off + cv.n_seg;
+        double ub = INFINITY;
+        for (int64_t s = cv.seg_off + lane; s < s_end; s += 64) {
+            double m = (double)piece_sample_min<T>(G, cv, s, q);
+            ub = fmin(ub, sqrt(m * (1.0 + rel)) + cv.tol_eff);
+        }
+        for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off, 64));
+        Cand b1 = empty_cand(cv), b2 = b1;
+        for (int64_t s = cv.seg_off + lane; s < s_end; s += 64) {
+            double m = (double)piece_sample_min<T>(G, cv, s, q);
+            double lb = sqrt(fmax(m * (1.0 - rel), 0.0)) - (double)G.aux[s * 8 + AUX_ES] * 1.001;
+            if (lb <= ub) consider<T>(G, cv, s, q, b1, b2);
+        }
+        const int w = wave_argmin(b1.d2, b1.t);
+        const Cand best = cand_from_lane(b1, w);
+        const Cand other = (lane == w) ? b2 : b1;
+        const int r = wave_argmin(other.d2, other.t);
+        const Cand runner = cand_from_lane(other, r);
+        if (lane == 0) finish<T>(G, cv, q, best, runner, flag_in, tie_rel, invert, qi, o);
+    }
 }
 
 __global__ void k_eval(DevGeom G, int64_t n, const int32_t* __restrict__ cid, const double* __restrict__ t,
@@ -1029,30 +896,32 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
         t_stage.recorded = false;
         if ((rc = stage_record(0, st))) return rc;
     }
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + T - 1) / T)), dim3(T), 0, st, w.hist, nc, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + 1 + T - 1) / T)), dim3(T), 0, st, w.hist, nc + 1, 0);
     hipLaunchKernelGGL(k_hist, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, st, curve_id, n, (int32_t)nc, w.hist,
                        t_out, dist_out, seg_out, flags_out);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w.hist, (int32_t)nc, w.q_off, w.tile_off);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, st, curve_id, n, (int32_t)nc,
                        w.q_off, w.hist, w.perm);
     if (timed && (rc = stage_record(1, st))) return rc;
-    int use_list = 0;
     if (opts->precision == MREP_PREC_BF16) {
         const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile;
-        hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)tiles), dim3(256), 0, st, G, w.tile_off, w.q_off, w.perm,
-                           q_xyz, (int32_t)kc, w.cand, w.cand_n, w.ub);
-        use_list = 1;
+        HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.cand, w.cand_n, w.ub,
+                                  st));
     }
     if (timed && (rc = stage_record(2, st))) return rc;
     const int RT = 128;
+    Outs o{t_out, dist_out, seg_out, flags_out};
+    const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
     if (opts->precision == MREP_PREC_BF16) {
         hipLaunchKernelGGL(k_refine<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
-                           w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, use_list, opts->tie_rel, invert, t_out,
-                           dist_out, seg_out, flags_out);
+                           w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, opts->tie_rel, invert, w.ovf_list,
+                           w.ovf_count, o);
+        hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
+                           (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, (uint32_t)MREP_F_FULLSCAN,
+                           opts->tie_rel, invert, o);
     } else {
-        hipLaunchKernelGGL(k_refine<double>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
-                           q_xyz, w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, 0, opts->tie_rel, invert, t_out,
-                           dist_out, seg_out, flags_out);
+        hipLaunchKernelGGL(k_fullscan<double>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
+                           (const int32_t*)nullptr, (const int32_t*)nullptr, 0u, opts->tie_rel, invert, o);
     }
     HIP_OK(hipGetLastError());
     if (timed) {

@@ -1,0 +1,227 @@
+// BF16 MFMA screen of libmrep (gfx950).
+//
+// This translation unit is compiled with -fno-honor-nans (its inputs are
+// finite: NaN query coordinates are outside the contract) so that the minimum
+// over MFMA results needs no canonicalisation, and with MFMA results in VGPRs
+// (no AGPR round trip): two v_min3 per MFMA is then the whole reduction.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/mrep.h"
+#include "mrep_dev.h"
+
+namespace mrep {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// 2. BF16 MFMA screen
+// ---------------------------------------------------------------------------
+// Row of a (query, sample) pair, length 32, in the centred sample parameter
+// v = 2u - 1 in [-1, 1]:
+//   [v^j q'_x, v^j q'_y, v^j q'_z  (j = 0..3) | v^m (m = 0..6) | 0 x 13]
+// Column of a piece C = c + sum_j b_j v^j (centre c relative to the curve
+// origin o, q' = q - o):
+//   [-2 b_j (12) | e_m (7) | 0 x 13],  e(v) = |C - c|^2 + 2 c.(C - c)
+// row . col + |q' - c|^2 = |q - C|^2.  The centred basis keeps |b_j| near the
+// piece's half-chord and curvature terms (the u-basis coefficients are several
+// times the chord), which is what the BF16 rounding bound scales with.
+//
+// v_mfma_f32_16x16x32_bf16 operand layout (wave64): lane l supplies row
+// (l & 15) of A and column (l & 15) of B, each with K entries 8*(l>>4) .. +7;
+// the 16x16 FP32 result gives lane l column (l & 15), rows 4*(l>>4) .. +3.
+// Rows of one MFMA are (query g = row>>2, sample 4i + (row&3)) for i = 0..7,
+// so lane l ends up with 4 samples of query (l>>4) against piece (l&15) per
+// MFMA, and 8 MFMAs cover all 32 samples without any cross-lane reduction.
+
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// Screen bound: |computed - exact| of a squared sample distance.  BF16 rounds
+// each row and column entry by <= 2^-8 relative, products are exact in FP32
+// and the FP32 sum adds <= 32 * 2^-24; 0.0085 covers 2 * 2^-8 + both with margin.
+#define SCREEN_KAPPA 0.0085f
+
+constexpr int kSets = 2;  // query sets of 4 per wave
+
+__global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
+                                                     const int32_t* __restrict__ q_off,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ qxyz, int32_t kc,
+                                                     int32_t* __restrict__ cand, int32_t* __restrict__ cand_n,
+                                                     float* __restrict__ ub_out)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short s_col[kChunk * kScreenK];
+    __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
+
+    const int n_curves = G.n_curves;
+    const int tile = blockIdx.x;
+    if (tile >= tile_off[n_curves]) return;
+    // curve owning this tile: last c with tile_off[c] <= tile
+    int lo = 0, hi = n_curves;  // tile_off[lo] <= tile < tile_off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+    }
+    const int c = lo;
+    const DCurve cv = G.curves[c];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int qbase = q_off[c] + (tile - tile_off[c]) * kQueriesPerTile + wave * (4 * kSets);
+    const int qend = q_off[c + 1];
+
+    // A fragments (rows) for both query sets, built once.
+    const int arow = lane & 15;
+    const int kb = lane >> 4;
+    bf16x8 A[kSets][8];
+    float pq[kSets][4];  // post-process query of this lane: x, y, z, max-norm
+    float eq[kSets];
+    bool pvalid[kSets];
+    for (int s = 0; s < kSets; ++s) {
+        int ja = qbase + 4 * s + (arow >> 2);
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        if (ja < qend) {
+            const double* q = qxyz + 3 * (int64_t)perm[ja];
+            qx = (float)(q[0] - cv.origin[0]);
+            qy = (float)(q[1] - cv.origin[1]);
+            qz = (float)(q[2] - cv.origin[2]);
+        }
+        for (int i = 0; i < 8; ++i) {
+            // centred sample parameter v = 2u - 1 in [-1, 1]
+            float u = -1.0f + 2.0f * (float)(4 * i + (arow & 3)) / (float)(kSamples - 1);
+            float u2 = u * u, u3 = u2 * u, u4 = u2 * u2, u5 = u4 * u, u6 = u3 * u3;
+            float v[8];
+            if (kb == 0) {
+                v[0] = qx; v[1] = qy; v[2] = qz; v[3] = u * qx; v[4] = u * qy; v[5] = u * qz; v[6] = u2 * qx; v[7] = u2 * qy;
+            } else if (kb == 1) {
+                v[0] = u2 * qz; v[1] = u3 * qx; v[2] = u3 * qy; v[3] = u3 * qz; v[4] = 1.f; v[5] = u; v[6] = u2; v[7] = u3;
+            } else if (kb == 2) {
+                v[0] = u4; v[1] = u5; v[2] = u6; v[3] = 0.f; v[4] = 0.f; v[5] = 0.f; v[6] = 0.f; v[7] = 0.f;
+            } else {
+                for (int k = 0; k < 8; ++k) v[k] = 0.f;
+            }
+            u16x8 bits;
+            for (int k = 0; k < 8; ++k) bits[k] = bf16_bits(v[k]);
+            A[s][i] = __builtin_bit_cast(bf16x8, bits);
+        }
+        int jp = qbase + 4 * s + (lane >> 4);
+        pvalid[s] = jp < qend;
+        float px = 0.f, py = 0.f, pz = 0.f;
+        double nq = 0.0;
+        if (pvalid[s]) {
+            const double* q = qxyz + 3 * (int64_t)perm[jp];
+            px = (float)(q[0] - cv.origin[0]);
+            py = (float)(q[1] - cv.origin[1]);
+            pz = (float)(q[2] - cv.origin[2]);
+            nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        }
+        pq[s][0] = px; pq[s][1] = py; pq[s][2] = pz;
+        pq[s][3] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
+        // rounding q - o to FP32 moves the query by <= 2^-24 |q - o| per axis
+        // (the origin is exact in FP32): 2.4e-7 |q'| bounds the distance change
+        eq[s] = sqrtf(px * px + py * py + pz * pz) * 2.4e-7f + 1e-30f;
+        (void)nq;
+    }
+
+    float ubsq[kSets], lb1[kSets], lb2[kSets], disc[kSets];
+    int s1[kSets], s2[kSets];
+    for (int s = 0; s < kSets; ++s) {
+        ubsq[s] = INFINITY; lb1[s] = INFINITY; lb2[s] = INFINITY; disc[s] = INFINITY; s1[s] = -1; s2[s] = -1;
+    }
+
+    const int nseg = cv.n_seg;
+    for (int base = 0; base < nseg; base += kChunk) {
+        const int cn = min(kChunk, nseg - base);
+        const int cn16 = (cn + 15) & ~15;
+        __syncthreads();
+        // stage columns (64 B each) and aux (32 B each); zero the ragged tail
+        {
+            const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
+            uint4* sc = reinterpret_cast<uint4*>(s_col);
+            for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
+            const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
+            float4* sa = reinterpret_cast<float4*>(s_aux);
+            for (int i = threadIdx.x; i < cn16 * 2; i += 256) sa[i] = (i < cn * 2) ? ga[i] : make_float4(0, 0, 0, 0);
+        }
+        __syncthreads();
+        for (int tb = 0; tb < cn16; tb += 16) {
+            const int sl = tb + (lane & 15);
+            const bf16x8 B = *reinterpret_cast<const bf16x8*>(&s_col[sl * kScreenK + kb * 8]);
+            const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);
+            const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);
+            const bool svalid = sl < cn;
+            const int gseg = (int)(cv.seg_off + base + sl);
+            for (int s = 0; s < kSets; ++s) {
+                float acc = INFINITY;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                    floatx4 r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][i], B, z, 0, 0, 0);
+                    acc = __builtin_fminf(__builtin_fminf(acc, r[0]), r[1]);
+                    acc = __builtin_fminf(__builtin_fminf(acc, r[2]), r[3]);
+                }
+                // post-process (query lane>>4 of set s, piece sl)
+                const float dx = pq[s][0] - x0.x, dy = pq[s][1] - x0.y, dz = pq[s][2] - x0.z;
+                const float d2c = dx * dx + dy * dy + dz * dz;
+                const float D = acc + d2c;
+                const float delta = SCREEN_KAPPA * (pq[s][3] * x0.w + x1.x) + 1e-6f * (d2c + fabsf(acc));
+                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - x1.y - eq[s];
+                if (svalid) {
+                    ubsq[s] = fminf(ubsq[s], D + delta);
+                    // keep the two smallest lower bounds; remember the smallest discarded one
+                    if (lb < lb2[s]) {
+                        disc[s] = fminf(disc[s], lb2[s]);
+                        if (lb < lb1[s]) {
+                            lb2[s] = lb1[s]; s2[s] = s1[s]; lb1[s] = lb; s1[s] = gseg;
+                        } else {
+                            lb2[s] = lb; s2[s] = gseg;
+                        }
+                    } else {
+                        disc[s] = fminf(disc[s], lb);
+                    }
+                }
+            }
+        }
+    }
+    // per query (16 lanes): upper bound, candidate list
+    for (int s = 0; s < kSets; ++s) {
+        float u = ubsq[s];
+        for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
+        const float UB = sqrtf(u) + (float)cv.tol_eff + eq[s];
+        const bool c1 = lb1[s] <= UB, c2 = lb2[s] <= UB, ov = disc[s] <= UB;
+        const uint64_t m1 = __ballot(c1), m2 = __ballot(c2), mo = __ballot(ov);
+        const int g = lane >> 4;
+        const uint64_t gm = 0xFFFFull << (16 * g);
+        const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+        const int tot = __popcll(m1 & gm) + __popcll(m2 & gm);
+        const int pos = __popcll(m1 & gm & below) + __popcll(m2 & gm & below);
+        const bool overflow = tot > kc || (mo & gm) != 0ull;
+        const int jp = qbase + 4 * s + g;
+        if (pvalid[s]) {
+            if (c1 && pos < kc) cand[(int64_t)jp * kc + pos] = s1[s];
+            if (c2 && pos + 1 < kc) cand[(int64_t)jp * kc + pos + 1] = s2[s];
+            if ((lane & 15) == 0) {
+                cand_n[jp] = overflow ? -1 : tot;
+                ub_out[jp] = UB;
+            }
+        }
+    }
+}
+
+hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* tile_off, const int32_t* q_off,
+                              const int32_t* perm, const double* qxyz, int32_t kc, int32_t* cand, int32_t* cand_n,
+                              float* ub_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)grid), dim3(256), 0, st, G, tile_off, q_off, perm, qxyz, kc, cand,
+                       cand_n, ub_out);
+    return hipGetLastError();
+}
+
+}  // namespace mrep
