@@ -43,10 +43,22 @@ inline DevGeom dev_view(const Geom& g)
 }
 
 
+// Outputs of the screen, per sorted query position j and per reserved
+// (query, piece) pair p.  A workgroup reserves one contiguous block of pairs.
+struct ScreenOut {
+    int32_t* cand_n;      // [n] candidates of query j, or -1 when the list overflowed
+    int32_t* pair_off;    // [n] first pair of query j
+    int32_t* pair_seg;    // [cap] global piece index of pair p
+    int32_t* pair_j;      // [cap] sorted query position of pair p
+    int32_t* pair_count;  // pairs reserved so far (zero before the screen)
+    int64_t pair_cap;     // capacity of the pair arrays; beyond it a query overflows
+    float* ub;            // [n] the certified upper bound of query j (diagnostic)
+};
+
 // Launch the BF16 MFMA screen (mrep_screen.hip): one workgroup per tile of
 // kQueriesPerTile queries of one curve; grid = n_curves + ceil(n / tile).
 hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* tile_off, const int32_t* q_off,
-                              const int32_t* perm, const double* qxyz, int32_t kc, int32_t* cand, int32_t* cand_n,
-                              float* ub_out, hipStream_t st);
+                              const int32_t* perm, const double* qxyz, int32_t kc, const ScreenOut& out,
+                              hipStream_t st);
 
 }  // namespace mrep

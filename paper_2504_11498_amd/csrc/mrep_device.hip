@@ -59,17 +59,19 @@ void set_error(const std::string& msg) { t_err = msg; }
     } while (0)
 
 struct Work {
-    int32_t* hist;      // n_curves + 1: per-curve counts / scatter cursors, then the overflow count
-    int32_t* q_off;     // n_curves + 1
-    int32_t* tile_off;  // n_curves + 1
-    int32_t* perm;      // n: sorted position -> query
-    int32_t* cand;      // n * kc
-    int32_t* cand_n;    // n
-    float* ub;          // n
-    int32_t* ovf_list;  // n: sorted positions whose candidate list overflowed
-    int32_t* ovf_count;  // = hist + n_curves
+    int32_t* hist;        // n_curves + 1: per-curve counts / scatter cursors, then the overflow count
+    int32_t* q_off;       // n_curves + 1
+    int32_t* tile_off;    // n_curves + 1
+    int32_t* perm;        // n: sorted position -> query
+    int32_t* ovf_list;    // n: sorted positions whose candidate list overflowed
+    int32_t* ovf_count;   // = hist + n_curves
+    int32_t* pair_count;  // = hist + n_curves + 1
+    ScreenOut so;         // candidate lists as (query, piece) pairs
+    float4* pair_res;     // [cap] u, squared distance, kappa, parameter error bound of each pair
 };
 
+// pairs reserved per query on average before queries overflow to the full scan
+constexpr int64_t kPairsPerQuery = 4;
 static int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 // Stage timing: events recorded on the call's stream when asked to.
@@ -91,30 +93,41 @@ static int stage_record(int i, hipStream_t st)
 
 static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work* w)
 {
+    (void)kc;
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
         int64_t o = off;
         off = a256(off + bytes);
         return o;
     };
-    int64_t o_hist = take(4 * (n_curves + 1));
+    const int64_t cap = std::min<int64_t>(kPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
+    int64_t o_hist = take(4 * (n_curves + 2));
     int64_t o_qoff = take(4 * (n_curves + 1));
     int64_t o_toff = take(4 * (n_curves + 1));
     int64_t o_perm = take(4 * n);
-    int64_t o_cand = take(4 * n * kc);
-    int64_t o_candn = take(4 * n);
-    int64_t o_ub = take(4 * n);
     int64_t o_ovf = take(4 * n);
+    int64_t o_candn = take(4 * n);
+    int64_t o_poff = take(4 * n);
+    int64_t o_ub = take(4 * n);
+    int64_t o_pseg = take(4 * cap);
+    int64_t o_pj = take(4 * cap);
+    int64_t o_pres = take(16 * cap);
     if (w) {
         w->hist = reinterpret_cast<int32_t*>(base + o_hist);
         w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
         w->tile_off = reinterpret_cast<int32_t*>(base + o_toff);
         w->perm = reinterpret_cast<int32_t*>(base + o_perm);
-        w->cand = reinterpret_cast<int32_t*>(base + o_cand);
-        w->cand_n = reinterpret_cast<int32_t*>(base + o_candn);
-        w->ub = reinterpret_cast<float*>(base + o_ub);
         w->ovf_list = reinterpret_cast<int32_t*>(base + o_ovf);
         w->ovf_count = w->hist + n_curves;
+        w->pair_count = w->hist + n_curves + 1;
+        w->so.cand_n = reinterpret_cast<int32_t*>(base + o_candn);
+        w->so.pair_off = reinterpret_cast<int32_t*>(base + o_poff);
+        w->so.pair_seg = reinterpret_cast<int32_t*>(base + o_pseg);
+        w->so.pair_j = reinterpret_cast<int32_t*>(base + o_pj);
+        w->so.pair_count = w->pair_count;
+        w->so.pair_cap = cap;
+        w->so.ub = reinterpret_cast<float*>(base + o_ub);
+        w->pair_res = reinterpret_cast<float4*>(base + o_pres);
     }
     return off;
 }
@@ -350,27 +363,66 @@ __device__ __forceinline__ T sample_u(int k)
     return k == kSamples - 1 ? (T)1 : (T)k / (T)(kSamples - 1);
 }
 
-// Best local minimum of one piece: rescan S samples, Newton from each local
-// minimum of the samples.  Returns squared distance, u, kappa.
+template <typename T>
+__device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
+
+// Minimum of one piece.  Rescan S samples; Newton from every local minimum of
+// the samples; then every sample interval not covered by those brackets whose
+// second-order lower bound  min(D_k, D_k+1) - M h^2 / 8  still reaches below
+// the best value gets a Newton solve of its own (M >= |D''| = 2(|C'|^2 +
+// r.C'') from the hodograph control polygons), so the minimum over the piece
+// is certified, not only the sampled one.  Returns squared distance, u, kappa.
+// One unrolled pass produces bit masks; the Newton solves run in compact loops
+// over the set bits, which keeps the kernels small.
 template <typename T>
 __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
 {
-    T dm = C.dist2((T)0), d0 = dm;
-    T d1 = C.dist2(sample_u<T>(1));
-    u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
+    // C' has Bezier control points a1, a1 + a2, a1 + 2 a2 + 3 a3; C'' has 2 a2, 2 a2 + 6 a3
+    const V3<T> h1 = {C.a1.x + C.a2.x, C.a1.y + C.a2.y, C.a1.z + C.a2.z};
+    const V3<T> h2 = {C.a1.x + (T)2 * C.a2.x + (T)3 * C.a3.x, C.a1.y + (T)2 * C.a2.y + (T)3 * C.a3.y,
+                      C.a1.z + (T)2 * C.a2.z + (T)3 * C.a3.z};
+    const V3<T> g0 = {(T)2 * C.a2.x, (T)2 * C.a2.y, (T)2 * C.a2.z};
+    const V3<T> g1 = {g0.x + (T)6 * C.a3.x, g0.y + (T)6 * C.a3.y, g0.z + (T)6 * C.a3.z};
+    const T L1 = fmax(norm3(C.a1), fmax(norm3(h1), norm3(h2)));
+    const T L2 = fmax(norm3(g0), norm3(g1));
+    const T h = (T)1 / (T)(kSamples - 1);
+
+    T D[kSamples];
+    T dmax = (T)0, dmin = (T)INFINITY;
+#pragma unroll
     for (int k = 0; k < kSamples; ++k) {
-        // here dm = D(k-1), d0 = D(k), d1 = D(k+1)
-        bool lm = (k == 0 || d0 <= dm) && (k == kSamples - 1 || d0 <= d1);
-        if (lm) {
-            T lo = sample_u<T>(k > 0 ? k - 1 : 0);
-            T hi = sample_u<T>(k < kSamples - 1 ? k + 1 : kSamples - 1);
+        D[k] = C.dist2(sample_u<T>(k));
+        dmax = fmax(dmax, D[k]);
+        dmin = fmin(dmin, D[k]);
+    }
+    const T rmax = sqrt(dmax) + L1 * h;
+    const T gap = (T)2 * (L1 * L1 + rmax * L2) * h * h * (T)0.125;
+    uint32_t lm = 0, chk = 0;  // local minima of the samples; intervals whose bound reaches the sampled minimum
+#pragma unroll
+    for (int k = 0; k < kSamples; ++k) {
+        const bool m = (k == 0 || D[k] <= D[k - 1]) && (k == kSamples - 1 || D[k] <= D[k + 1]);
+        lm |= (uint32_t)m << k;
+        if (k < kSamples - 1) chk |= (uint32_t)(fmin(D[k], D[k + 1]) - gap < dmin) << k;
+    }
+    u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
+    uint32_t covered = 0;  // bit k: interval (k, k+1) lies inside a refined bracket
+    for (uint32_t bits = lm; bits; bits &= bits - 1) {
+        const int k = __builtin_ctz(bits);
+        const int a = k > 0 ? k - 1 : 0, b = k < kSamples - 1 ? k + 1 : kSamples - 1;
+        T ub, db, kb;
+        newton_min(C, sample_u<T>(a), sample_u<T>(b), sample_u<T>(k), ub, db, kb);
+        if (db < d_out) { d_out = db; u_out = ub; k_out = kb; }
+        covered |= ((1u << b) - 1u) & ~((1u << a) - 1u);
+    }
+    const T best = d_out * ((T)1 - (T)(sizeof(T) == 4 ? 8e-6 : 2e-14));
+    for (uint32_t bits = chk & ~covered; bits; bits &= bits - 1) {
+        const int k = __builtin_ctz(bits);
+        const T ua = sample_u<T>(k), ub_ = sample_u<T>(k + 1);
+        if (fmin(C.dist2(ua), C.dist2(ub_)) - gap < best) {
             T ub, db, kb;
-            newton_min(C, lo, hi, sample_u<T>(k), ub, db, kb);
+            newton_min(C, ua, ub_, (T)0.5 * (ua + ub_), ub, db, kb);
             if (db < d_out) { d_out = db; u_out = ub; k_out = kb; }
         }
-        dm = d0;
-        d0 = d1;
-        if (k + 2 <= kSamples - 1) d1 = C.dist2(sample_u<T>(k + 2));
     }
 }
 
@@ -439,6 +491,40 @@ struct Eps<double> {
     static constexpr double v = 1.12e-16;  // 2^-53
 };
 
+// Bound on the parameter error the refine precision leaves at u: rounding of
+// the terms of f = r.C' (magnitude <= scale * |C'|) moves the root by about
+// 8 eps scale / (|C'| kappa) in u.
+template <typename T>
+__device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
+{
+    V3<T> r, d1, d2;
+    C.eval(u, r, d1, d2);
+    const double sp = sqrt((double)dot(d1, d1));
+    const double scale = sqrt((double)dot(C.a0, C.a0)) + sqrt((double)dot(C.a1, C.a1)) +
+                         sqrt((double)dot(C.a2, C.a2)) + sqrt((double)dot(C.a3, C.a3));
+    const double kap = fabs((double)k);
+    return (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
+}
+
+// Keep the two best candidates (squared distance, then parameter).
+__device__ __forceinline__ void top2(const Cand& x, Cand& b1, Cand& b2)
+{
+    if (x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t)) { b2 = b1; b1 = x; }
+    else if (x.d2 < b2.d2) b2 = x;
+}
+
+__device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u, double d2, double kappa, double t_err)
+{
+    const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
+    Cand x;
+    x.t = (u == 1.0) ? tb : ta + u * (tb - ta);
+    x.d2 = d2;
+    x.kappa = kappa;
+    x.t_err = t_err;
+    x.seg = (int32_t)s;
+    return x;
+}
+
 template <typename T>
 __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cand& b1, Cand& b2)
 {
@@ -447,24 +533,7 @@ __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const do
     T u, d, k;
     piece_min(C, u, d, k);
     const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
-    Cand x;
-    x.t = (u == (T)1) ? tb : ta + (double)u * (tb - ta);
-    x.d2 = (double)d;
-    x.kappa = (double)k;
-    x.seg = (int32_t)s;
-    // Rounding of the terms of f = r.C' (magnitude <= scale * |C'|) moves the
-    // root by about 8 eps scale / (|C'| kappa) in u.
-    {
-        V3<T> r, d1, d2;
-        C.eval(u, r, d1, d2);
-        const double sp = sqrt((double)dot(d1, d1));
-        const double scale = sqrt((double)dot(C.a0, C.a0)) + sqrt((double)dot(C.a1, C.a1)) +
-                             sqrt((double)dot(C.a2, C.a2)) + sqrt((double)dot(C.a3, C.a3));
-        const double kap = fabs((double)k);
-        x.t_err = (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
-    }
-    if (x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t)) { b2 = b1; b1 = x; }
-    else if (x.d2 < b2.d2) b2 = x;
+    top2(make_cand(G, s, (double)u, (double)d, (double)k, param_error(C, u, k, ta, tb)), b1, b2);
 }
 
 // Minimum sampled squared distance of a piece (the full-scan prune).
@@ -545,28 +614,60 @@ __device__ __forceinline__ Cand empty_cand(const DCurve& cv)
     return b;
 }
 
-// One thread per query with a screen candidate list.  Queries whose list
-// overflowed are appended to ovf_list for k_fullscan.
+// One thread per (query, candidate piece) pair reserved by the screen: the
+// certified minimum over the piece in the refine precision.  Persistent grid.
 template <typename T>
-__global__ __launch_bounds__(128) void k_refine(DevGeom G, const int32_t* __restrict__ cid,
+__global__ __launch_bounds__(256) void k_pairs(DevGeom G, const int32_t* __restrict__ cid,
+                                               const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ pair_seg,
+                                               const int32_t* __restrict__ pair_j,
+                                               const int32_t* __restrict__ pair_count, int64_t pair_cap,
+                                               float4* __restrict__ pair_res)
+{
+    const int64_t total = min((int64_t)*pair_count, pair_cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t jj = pair_j[p];
+        if (jj < 0) continue;  // reserved by a query that then overflowed the capacity
+        const int64_t s = pair_seg[p];
+        const int32_t qi = perm[jj];
+        const DCurve cv = G.curves[cid[qi]];
+        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        Cubic<T> C;
+        load_cubic(G, cv, s, q, C);
+        T u, d, k;
+        piece_min(C, u, d, k);
+        const double err = param_error(C, u, k, G.segt[2 * s], G.segt[2 * s + 1]);
+        pair_res[p] = make_float4((float)u, (float)d, (float)k, (float)err);
+    }
+}
+
+// One thread per query: the two best of its pairs, then finish.  Queries whose
+// list overflowed are appended to ovf_list for k_fullscan.
+template <typename T>
+__global__ __launch_bounds__(128) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
-                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
-                                                const int32_t* __restrict__ cand_n, int32_t kc, double tie_rel,
-                                                int32_t invert, int32_t* __restrict__ ovf_list,
-                                                int32_t* __restrict__ ovf_count, Outs o)
+                                                const int32_t* __restrict__ perm, ScreenOut so,
+                                                const float4* __restrict__ pair_res, double tie_rel, int32_t invert,
+                                                int32_t* __restrict__ ovf_list, int32_t* __restrict__ ovf_count,
+                                                Outs o)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q_off[G.n_curves]) return;
-    const int n_list = cand_n[j];
+    const int n_list = so.cand_n[j];
     if (n_list <= 0) {  // overflow (or, impossible for finite input, an empty list)
         ovf_list[atomicAdd(ovf_count, 1)] = (int32_t)j;
         return;
     }
     const int32_t qi = perm[j];
     const DCurve cv = G.curves[cid[qi]];
-    double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
     Cand b1 = empty_cand(cv), b2 = b1;
-    for (int i = 0; i < n_list; ++i) consider<T>(G, cv, cand[j * kc + i], q, b1, b2);
+    const int64_t p0 = so.pair_off[j];
+    for (int i = 0; i < n_list; ++i) {
+        const float4 r = pair_res[p0 + i];
+        top2(make_cand(G, so.pair_seg[p0 + i], (double)r.x, (double)r.y, (double)r.z, (double)r.w), b1, b2);
+    }
     finish<T>(G, cv, q, b1, b2, 0u, tie_rel, invert, qi, o);
 }
 
@@ -814,7 +915,7 @@ int32_t mrep_opts_default(mrep_opts* o)
     }
     o->struct_size = (int32_t)sizeof(mrep_opts);
     o->precision = MREP_PREC_BF16;
-    o->max_candidates = 8;
+    o->max_candidates = 16;
     o->flags = 0;
     o->tie_rel = 2e-6;
     return MREP_OK;
@@ -864,8 +965,9 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
     int rc = check_opts(opts);
     if (rc) return rc;
     if (n == 0) return MREP_OK;
-    if (n >= ((int64_t)1 << 31) - 1024) {
-        set_error("mrep_project_curves: n must be < 2^31");
+    // the screen's pair counter is 32-bit: n * max_candidates must stay below 2^31
+    if (n * (int64_t)opts->max_candidates >= (int64_t)INT32_MAX) {
+        set_error("mrep_project_curves: n * max_candidates must be < 2^31");
         return MREP_E_INVALID_ARG;
     }
     if (!curve_id || !q_xyz || !workspace || !t_out || !dist_out || !seg_out || !flags_out) {
@@ -896,7 +998,7 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
         t_stage.recorded = false;
         if ((rc = stage_record(0, st))) return rc;
     }
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + 1 + T - 1) / T)), dim3(T), 0, st, w.hist, nc + 1, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nc + 2 + T - 1) / T)), dim3(T), 0, st, w.hist, nc + 2, 0);
     hipLaunchKernelGGL(k_hist, dim3((unsigned)((n + T - 1) / T)), dim3(T), 0, st, curve_id, n, (int32_t)nc, w.hist,
                        t_out, dist_out, seg_out, flags_out);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w.hist, (int32_t)nc, w.q_off, w.tile_off);
@@ -905,16 +1007,19 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
     if (timed && (rc = stage_record(1, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
         const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile;
-        HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.cand, w.cand_n, w.ub,
-                                  st));
+        HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.so, st));
     }
     if (timed && (rc = stage_record(2, st))) return rc;
     const int RT = 128;
     Outs o{t_out, dist_out, seg_out, flags_out};
     const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
     if (opts->precision == MREP_PREC_BF16) {
-        hipLaunchKernelGGL(k_refine<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
-                           w.q_off, w.perm, w.cand, w.cand_n, (int32_t)kc, opts->tie_rel, invert, w.ovf_list,
+        const unsigned pr_blocks = (unsigned)std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.perm,
+                           (const int32_t*)w.so.pair_seg, (const int32_t*)w.so.pair_j, (const int32_t*)w.pair_count,
+                           w.so.pair_cap, w.pair_res);
+        hipLaunchKernelGGL(k_finish<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
+                           w.q_off, w.perm, w.so, (const float4*)w.pair_res, opts->tie_rel, invert, w.ovf_list,
                            w.ovf_count, o);
         hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
                            (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, (uint32_t)MREP_F_FULLSCAN,

@@ -49,14 +49,14 @@ __device__ __forceinline__ unsigned short bf16_bits(float x)
 // and the FP32 sum adds <= 32 * 2^-24; 0.0085 covers 2 * 2^-8 + both with margin.
 #define SCREEN_KAPPA 0.0085f
 
-constexpr int kSets = 2;  // query sets of 4 per wave
+constexpr int kSets = 2;   // query sets of 4 per wave
+constexpr int kDepth = 3;  // lower bounds kept per lane and query
 
 __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
                                                      const int32_t* __restrict__ q_off,
                                                      const int32_t* __restrict__ perm,
                                                      const double* __restrict__ qxyz, int32_t kc,
-                                                     int32_t* __restrict__ cand, int32_t* __restrict__ cand_n,
-                                                     float* __restrict__ ub_out)
+                                                     ScreenOut out)
 {
     __shared__ __attribute__((aligned(16))) unsigned short s_col[kChunk * kScreenK];
     __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
@@ -130,10 +130,14 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         (void)nq;
     }
 
-    float ubsq[kSets], lb1[kSets], lb2[kSets], disc[kSets];
-    int s1[kSets], s2[kSets];
+    // per lane and query set: running upper bound (squared), the kDepth smallest
+    // lower bounds with their pieces (sorted), the smallest discarded bound
+    float ubsq[kSets], lbk[kSets][kDepth], disc[kSets];
+    int sk[kSets][kDepth];
     for (int s = 0; s < kSets; ++s) {
-        ubsq[s] = INFINITY; lb1[s] = INFINITY; lb2[s] = INFINITY; disc[s] = INFINITY; s1[s] = -1; s2[s] = -1;
+        ubsq[s] = INFINITY;
+        disc[s] = INFINITY;
+        for (int k = 0; k < kDepth; ++k) { lbk[s][k] = INFINITY; sk[s][k] = -1; }
     }
 
     const int nseg = cv.n_seg;
@@ -141,14 +145,17 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         const int cn = min(kChunk, nseg - base);
         const int cn16 = (cn + 15) & ~15;
         __syncthreads();
-        // stage columns (64 B each) and aux (32 B each); zero the ragged tail
+        // stage columns (64 B each) and aux (32 B each).  The ragged tail gets
+        // zero columns and aux that force an infinite lower and upper bound.
         {
             const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
             uint4* sc = reinterpret_cast<uint4*>(s_col);
             for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
             const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
             float4* sa = reinterpret_cast<float4*>(s_aux);
-            for (int i = threadIdx.x; i < cn16 * 2; i += 256) sa[i] = (i < cn * 2) ? ga[i] : make_float4(0, 0, 0, 0);
+            for (int i = threadIdx.x; i < cn16 * 2; i += 256)
+                sa[i] = (i < cn * 2) ? ga[i] : ((i & 1) ? make_float4(INFINITY, -INFINITY, 0.f, 0.f)
+                                                        : make_float4(0.f, 0.f, 0.f, 0.f));
         }
         __syncthreads();
         for (int tb = 0; tb < cn16; tb += 16) {
@@ -156,7 +163,6 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
             const bf16x8 B = *reinterpret_cast<const bf16x8*>(&s_col[sl * kScreenK + kb * 8]);
             const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);
             const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);
-            const bool svalid = sl < cn;
             const int gseg = (int)(cv.seg_off + base + sl);
             for (int s = 0; s < kSets; ++s) {
                 float acc = INFINITY;
@@ -167,60 +173,102 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
                     acc = __builtin_fminf(__builtin_fminf(acc, r[0]), r[1]);
                     acc = __builtin_fminf(__builtin_fminf(acc, r[2]), r[3]);
                 }
-                // post-process (query lane>>4 of set s, piece sl)
+                // epilogue for (query lane>>4 of set s, piece sl)
                 const float dx = pq[s][0] - x0.x, dy = pq[s][1] - x0.y, dz = pq[s][2] - x0.z;
                 const float d2c = dx * dx + dy * dy + dz * dz;
                 const float D = acc + d2c;
-                const float delta = SCREEN_KAPPA * (pq[s][3] * x0.w + x1.x) + 1e-6f * (d2c + fabsf(acc));
-                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - x1.y - eq[s];
-                if (svalid) {
-                    ubsq[s] = fminf(ubsq[s], D + delta);
-                    // keep the two smallest lower bounds; remember the smallest discarded one
-                    if (lb < lb2[s]) {
-                        disc[s] = fminf(disc[s], lb2[s]);
-                        if (lb < lb1[s]) {
-                            lb2[s] = lb1[s]; s2[s] = s1[s]; lb1[s] = lb; s1[s] = gseg;
-                        } else {
-                            lb2[s] = lb; s2[s] = gseg;
-                        }
-                    } else {
-                        disc[s] = fminf(disc[s], lb);
+                const float delta = SCREEN_KAPPA * fmaf(pq[s][3], x0.w, x1.x) + 1e-6f * (d2c + fabsf(acc));
+                ubsq[s] = fminf(ubsq[s], D + delta);
+                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - (x1.y + eq[s]);
+                float out = lb;
+                if (lb < lbk[s][kDepth - 1]) {  // rare: insert into the sorted list
+                    out = lbk[s][kDepth - 1];
+                    float v = lb;
+                    int g = gseg;
+#pragma unroll
+                    for (int k = 0; k < kDepth; ++k) {
+                        const bool sw = v < lbk[s][k];
+                        const float tv = sw ? lbk[s][k] : v;
+                        const int tg = sw ? sk[s][k] : g;
+                        lbk[s][k] = sw ? v : lbk[s][k];
+                        sk[s][k] = sw ? g : sk[s][k];
+                        v = tv;
+                        g = tg;
                     }
                 }
+                disc[s] = fminf(disc[s], out);
             }
         }
     }
-    // per query (16 lanes): upper bound, candidate list
+    // per query (16 lanes): upper bound and candidate count; then one atomic
+    // per workgroup reserves the pairs of all its queries
+    __shared__ int32_t s_off[4 * kSets * 4];
+    __shared__ int32_t s_base;
+    const int g = lane >> 4;
+    const uint64_t gm = 0xFFFFull << (16 * g);
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int tot[kSets], pos[kSets];
+    bool ovf[kSets];
+    float UBv[kSets];
+    bool ck[kSets][kDepth];
     for (int s = 0; s < kSets; ++s) {
         float u = ubsq[s];
         for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
-        const float UB = sqrtf(u) + (float)cv.tol_eff + eq[s];
-        const bool c1 = lb1[s] <= UB, c2 = lb2[s] <= UB, ov = disc[s] <= UB;
-        const uint64_t m1 = __ballot(c1), m2 = __ballot(c2), mo = __ballot(ov);
-        const int g = lane >> 4;
-        const uint64_t gm = 0xFFFFull << (16 * g);
-        const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-        const int tot = __popcll(m1 & gm) + __popcll(m2 & gm);
-        const int pos = __popcll(m1 & gm & below) + __popcll(m2 & gm & below);
-        const bool overflow = tot > kc || (mo & gm) != 0ull;
+        UBv[s] = sqrtf(u) + (float)cv.tol_eff + eq[s];
+        tot[s] = 0;
+        pos[s] = 0;
+#pragma unroll
+        for (int k = 0; k < kDepth; ++k) {
+            ck[s][k] = lbk[s][k] <= UBv[s];
+            const uint64_t m = __ballot(ck[s][k]);
+            tot[s] += __popcll(m & gm);
+            pos[s] += __popcll(m & gm & below);
+        }
+        ovf[s] = tot[s] > kc || (__ballot(disc[s] <= UBv[s]) & gm) != 0ull || !pvalid[s];
+        if ((lane & 15) == 0) s_off[(wave * kSets + s) * 4 + g] = ovf[s] ? 0 : tot[s];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int i = 0; i < 4 * kSets * 4; ++i) {
+            const int v = s_off[i];
+            s_off[i] = sum;
+            sum += v;
+        }
+        s_base = sum > 0 ? atomicAdd(out.pair_count, sum) : 0;
+    }
+    __syncthreads();
+    for (int s = 0; s < kSets; ++s) {
+        if (!pvalid[s]) continue;
         const int jp = qbase + 4 * s + g;
-        if (pvalid[s]) {
-            if (c1 && pos < kc) cand[(int64_t)jp * kc + pos] = s1[s];
-            if (c2 && pos + 1 < kc) cand[(int64_t)jp * kc + pos + 1] = s2[s];
-            if ((lane & 15) == 0) {
-                cand_n[jp] = overflow ? -1 : tot;
-                ub_out[jp] = UB;
-            }
+        const int64_t first = (int64_t)s_base + s_off[(wave * kSets + s) * 4 + g];
+        const bool over = ovf[s] || first + tot[s] > out.pair_cap;
+        if (!ovf[s]) {
+            // every reserved slot below the capacity is written; a query cut by
+            // the capacity marks its slots unused (-1) and takes the full scan
+#pragma unroll
+            for (int k = 0; k < kDepth; ++k)
+                if (ck[s][k]) {
+                    const int64_t p = first + pos[s] + k;
+                    if (p < out.pair_cap) {
+                        out.pair_seg[p] = sk[s][k];
+                        out.pair_j[p] = over ? -1 : jp;
+                    }
+                }
+        }
+        if ((lane & 15) == 0) {
+            out.cand_n[jp] = over ? -1 : tot[s];
+            out.pair_off[jp] = (int32_t)(over ? 0 : first);
+            out.ub[jp] = UBv[s];
         }
     }
 }
 
 hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* tile_off, const int32_t* q_off,
-                              const int32_t* perm, const double* qxyz, int32_t kc, int32_t* cand, int32_t* cand_n,
-                              float* ub_out, hipStream_t st)
+                              const int32_t* perm, const double* qxyz, int32_t kc, const ScreenOut& out,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)grid), dim3(256), 0, st, G, tile_off, q_off, perm, qxyz, kc, cand,
-                       cand_n, ub_out);
+    hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)grid), dim3(256), 0, st, G, tile_off, q_off, perm, qxyz, kc, out);
     return hipGetLastError();
 }
 

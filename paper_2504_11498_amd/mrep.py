@@ -173,7 +173,7 @@ def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:
     return Plan(h.value)
 
 
-def default_opts(precision: str | int = "bf16", max_candidates: int = 8, tie_rel: float = 2e-6,
+def default_opts(precision: str | int = "bf16", max_candidates: int = 16, tie_rel: float = 2e-6,
                  time_stages: bool = False) -> Opts:
     o = Opts()
     _check(_opts_default(C.byref(o)), "mrep_opts_default")

@@ -27,7 +27,7 @@ def mrep():
     return m
 
 
-def _run(geom, q, cid, precision, invert=False, max_candidates=8):
+def _run(geom, q, cid, precision, invert=False, max_candidates=16):
     m = sys.modules["paper_2504_11498_amd.mrep"]
     opts = m.default_opts(precision, max_candidates=max_candidates)
     qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
