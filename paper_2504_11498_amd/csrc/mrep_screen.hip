@@ -51,6 +51,11 @@ __device__ __forceinline__ unsigned short bf16_bits(float x)
 
 constexpr int kSets = 2;   // query sets of 4 per wave
 constexpr int kDepth = 3;  // lower bounds kept per lane and query
+// margins that make the raw hardware square root (<= 1 ulp) safe for the
+// certified bounds, with room for the FP32 rounding of the epilogue
+static_assert(kChunk == 256 && kQueriesPerTile == 32, "the staging and tile code assume 256 threads, 256 pieces, 32 queries");
+constexpr float kSqrtLo = 1.0f - 0x1p-20f;
+constexpr float kSqrtHi = 1.0f + 0x1p-20f;
 
 __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
                                                      const int32_t* __restrict__ q_off,
@@ -150,12 +155,24 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         {
             const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
             uint4* sc = reinterpret_cast<uint4*>(s_col);
-            for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
             const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
             float4* sa = reinterpret_cast<float4*>(s_aux);
-            for (int i = threadIdx.x; i < cn16 * 2; i += 256)
-                sa[i] = (i < cn * 2) ? ga[i] : ((i & 1) ? make_float4(INFINITY, -INFINITY, 0.f, 0.f)
-                                                        : make_float4(0.f, 0.f, 0.f, 0.f));
+            if (cn == kChunk) {  // full chunk: 4 column and 2 aux vectors per thread, unconditional
+                uint4 c0 = gc[threadIdx.x], c1 = gc[threadIdx.x + 256], c2 = gc[threadIdx.x + 512],
+                      c3 = gc[threadIdx.x + 768];
+                float4 a0 = ga[threadIdx.x], a1 = ga[threadIdx.x + 256];
+                sc[threadIdx.x] = c0;
+                sc[threadIdx.x + 256] = c1;
+                sc[threadIdx.x + 512] = c2;
+                sc[threadIdx.x + 768] = c3;
+                sa[threadIdx.x] = a0;
+                sa[threadIdx.x + 256] = a1;
+            } else {
+                for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
+                for (int i = threadIdx.x; i < cn16 * 2; i += 256)
+                    sa[i] = (i < cn * 2) ? ga[i] : ((i & 1) ? make_float4(INFINITY, -INFINITY, 0.f, 0.f)
+                                                            : make_float4(0.f, 0.f, 0.f, 0.f));
+            }
         }
         __syncthreads();
         for (int tb = 0; tb < cn16; tb += 16) {
@@ -179,7 +196,8 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
                 const float D = acc + d2c;
                 const float delta = SCREEN_KAPPA * fmaf(pq[s][3], x0.w, x1.x) + 1e-6f * (d2c + fabsf(acc));
                 ubsq[s] = fminf(ubsq[s], D + delta);
-                const float lb = sqrtf(fmaxf(D - delta, 0.f)) - (x1.y + eq[s]);
+                // raw v_sqrt_f32 (<= 1 ulp): the lower bound is shrunk by 2^-20 relative
+                const float lb = __builtin_amdgcn_sqrtf(fmaxf(D - delta, 0.f)) * kSqrtLo - (x1.y + eq[s]);
                 float out = lb;
                 if (lb < lbk[s][kDepth - 1]) {  // rare: insert into the sorted list
                     out = lbk[s][kDepth - 1];
@@ -214,7 +232,7 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
     for (int s = 0; s < kSets; ++s) {
         float u = ubsq[s];
         for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
-        UBv[s] = sqrtf(u) + (float)cv.tol_eff + eq[s];
+        UBv[s] = __builtin_amdgcn_sqrtf(u) * kSqrtHi + (float)cv.tol_eff + eq[s];
         tot[s] = 0;
         pos[s] = 0;
 #pragma unroll
