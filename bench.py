@@ -27,7 +27,7 @@ FLOPS_PER_SAMPLE = 2 * 32  # one 16x16x32 MFMA output element per (query, piece,
 
 
 def _kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2504_11498_amd", "csrc", "mrep_device.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2504_11498_amd", "csrc", "mrep_screen.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 

@@ -272,7 +272,7 @@ struct Cubic {
 
 // Load piece s as a cubic relative to q.  FP32: local control points minus the
 // local query (q - c computed in FP64).  FP64: global control points minus q.
-__device__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<float>& C)
+__device__ __forceinline__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<float>& C)
 {
     const float* lp = G.lcp + s * 12;
     const float* ax = G.aux + s * 8;
@@ -289,7 +289,7 @@ __device__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const 
             P[11] - 3.f * P[8] + 3.f * P[5] - P[2]};
 }
 
-__device__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<double>& C)
+__device__ __forceinline__ void load_cubic(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cubic<double>& C)
 {
     const double* P = G.gcp + s * 12;
     double R[12];
@@ -315,7 +315,7 @@ struct Newt<double> {
 // Minimum of |C(u) - q|^2 on [lo, hi] near the sample u0: safeguarded Newton on
 // f = r.C' when f changes sign on the bracket; otherwise the better bracket end.
 template <typename T>
-__device__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_best, T& kappa)
+__device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_best, T& kappa)
 {
     V3<T> r, d1, d2;
     C.eval(lo, r, d1, d2);
@@ -427,7 +427,7 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
 }
 
 // Exact degree-p span in local power form: C(v) = sum_j c_j v^j, v in [0,1].
-__device__ void span_eval(const double* cf, int p, double v, const double* q, double* r, double* d1, double* d2)
+__device__ __forceinline__ void span_eval(const double* cf, int p, double v, const double* q, double* r, double* d1, double* d2)
 {
     double x[3], y[3], z[3];
     for (int c = 0; c < 3; ++c) { x[c] = cf[3 * p + c]; y[c] = 0.0; z[c] = 0.0; }
@@ -441,7 +441,7 @@ __device__ void span_eval(const double* cf, int p, double v, const double* q, do
 }
 
 // FP64 Newton on the exact span from global parameter t0; returns (t, dist, kappa).
-__device__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q, double& t_out,
+__device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q, double& t_out,
                        double& d_out, double& k_out)
 {
     const int p = cv.degree;
@@ -506,11 +506,24 @@ __device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
     return (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
 }
 
-// Keep the two best candidates (squared distance, then parameter).
+__device__ __forceinline__ void cand_select(bool c, const Cand& a, Cand& dst)
+{
+    dst.t = c ? a.t : dst.t;
+    dst.d2 = c ? a.d2 : dst.d2;
+    dst.kappa = c ? a.kappa : dst.kappa;
+    dst.t_err = c ? a.t_err : dst.t_err;
+    dst.seg = c ? a.seg : dst.seg;
+}
+
+// Keep the two best candidates (squared distance, then parameter); field-wise
+// selects keep the candidates in registers.
 __device__ __forceinline__ void top2(const Cand& x, Cand& b1, Cand& b2)
 {
-    if (x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t)) { b2 = b1; b1 = x; }
-    else if (x.d2 < b2.d2) b2 = x;
+    const bool first = x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t);
+    const bool second = !first && x.d2 < b2.d2;
+    cand_select(first, b1, b2);
+    cand_select(second, x, b2);
+    cand_select(first, x, b1);
 }
 
 __device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u, double d2, double kappa, double t_err)
@@ -559,7 +572,7 @@ struct Outs {
 // the refine precision cannot certify the parameter to 1e-8, or the runner-up
 // is within the tie margin; then write t, distance, piece and flags.
 template <typename T>
-__device__ void finish(const DevGeom& G, const DCurve& cv, const double* q, const Cand& b1, const Cand& b2,
+__device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const double* q, const Cand& b1, const Cand& b2,
                        uint32_t flags, double tie_rel, int invert, int32_t qi, const Outs& o)
 {
     const double d1 = sqrt(b1.d2), d2 = sqrt(b2.d2);
@@ -1006,7 +1019,8 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
                        w.q_off, w.hist, w.perm);
     if (timed && (rc = stage_record(1, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
-        const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile;
+        // upper bound of the tile count, plus room for the per-XCD rounding
+        const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + 8;
         HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.so, st));
     }
     if (timed && (rc = stage_record(2, st))) return rc;

@@ -51,6 +51,7 @@ __device__ __forceinline__ unsigned short bf16_bits(float x)
 
 constexpr int kSets = 2;   // query sets of 4 per wave
 constexpr int kDepth = 3;  // lower bounds kept per lane and query
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
 // margins that make the raw hardware square root (<= 1 ulp) safe for the
 // certified bounds, with room for the FP32 rounding of the epilogue
 static_assert(kChunk == 256 && kQueriesPerTile == 32, "the staging and tile code assume 256 threads, 256 pieces, 32 queries");
@@ -67,8 +68,14 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
     __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
 
     const int n_curves = G.n_curves;
-    const int tile = blockIdx.x;
-    if (tile >= tile_off[n_curves]) return;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
+    // (blockIdx % 8), so XCD x takes the contiguous tile range [x*per, (x+1)*per)
+    // and the tiles of one curve share that XCD's L2 for the curve's pieces.
+    const int n_tiles = tile_off[n_curves];
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    const int slot = (int)(blockIdx.x / kXcds);
+    const int tile = (int)(blockIdx.x % kXcds) * per + slot;
+    if (slot >= per || tile >= n_tiles) return;
     // curve owning this tile: last c with tile_off[c] <= tile
     int lo = 0, hi = n_curves;  // tile_off[lo] <= tile < tile_off[hi]
     while (hi - lo > 1) {
