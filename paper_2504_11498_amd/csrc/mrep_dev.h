@@ -23,6 +23,7 @@ struct DevGeom {
     const int32_t* span0;
     const double* coef;
     int32_t n_curves;
+    int64_t n_seg;
 };
 
 inline DevGeom dev_view(const Geom& g)
@@ -39,6 +40,7 @@ inline DevGeom dev_view(const Geom& g)
     d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
     d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
     d.n_curves = (int32_t)g.L.n_curves;
+    d.n_seg = g.L.n_seg;
     return d;
 }
 

@@ -643,6 +643,7 @@ __global__ __launch_bounds__(256) void k_pairs(DevGeom G, const int32_t* __restr
         const int32_t jj = pair_j[p];
         if (jj < 0) continue;  // reserved by a query that then overflowed the capacity
         const int64_t s = pair_seg[p];
+        if (s < 0 || s >= G.n_seg) continue;  // never written by the screen (defensive)
         const int32_t qi = perm[jj];
         const DCurve cv = G.curves[cid[qi]];
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};

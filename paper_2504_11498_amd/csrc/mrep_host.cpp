@@ -464,11 +464,11 @@ void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* co
     aux[AUX_CX] = cf[0];
     aux[AUX_CY] = cf[1];
     aux[AUX_CZ] = cf[2];
-    aux[AUX_A] = (float)(As * 1.01);
-    aux[AUX_E] = (float)(Es * 1.01);
+    aux[AUX_CC] = (float)dot3(crel, crel);
+    aux[AUX_KA] = (float)(kScreenKappaBf16 * As * 1.01);
+    aux[AUX_KE] = (float)(kScreenKappaBf16 * Es * 1.01);
     aux[AUX_ES] = (float)((L / (2.0 * (kSamples - 1)) + tol_eff) * 1.0001);
     aux[AUX_L] = (float)L;
-    aux[AUX_TOL] = (float)tol_eff;
     for (int i = 0; i < 4; ++i)
         for (int c = 0; c < 3; ++c) lcp[3 * i + c] = (float)(R[3 * i + c] - cd[c]);
 }

@@ -13,8 +13,11 @@ namespace mrep {
 // Samples per cubic piece in the screen and in the per-candidate rescan: the
 // local parameter u_k = k / (kSamples - 1), both ends included.
 constexpr int kSamples = 32;
-// Queries per screen workgroup (4 waves x 8 queries).
-constexpr int kQueriesPerTile = 32;
+// Queries per screen workgroup tile.
+#ifndef MREP_TILE_QUERIES
+#define MREP_TILE_QUERIES 32
+#endif
+constexpr int kQueriesPerTile = MREP_TILE_QUERIES;
 // Segments staged in LDS per chunk by the screen.
 constexpr int kChunk = 256;
 // Length of a screen row / column (MFMA K dimension, 19 entries used).
@@ -53,9 +56,16 @@ struct GeomLayout {
     int64_t total = 0;
 };
 
-// aux[8] per segment: cx, cy, cz (FP32 centre relative to the curve origin),
-// A (sum |2 a_j|_1), E (sum |e_m|), e (L/(2(S-1)) + tol), L (speed bound in u), tol.
-enum { AUX_CX = 0, AUX_CY, AUX_CZ, AUX_A, AUX_E, AUX_ES, AUX_L, AUX_TOL };
+// aux[8] per piece: cx, cy, cz (FP32 centre relative to the curve origin),
+// |c|^2, kappa A and kappa E (the screen's rounding-bound terms: A = sum |2 b_j|_1,
+// E = sum |e_m|, kappa = kScreenKappaBf16), e = L/(2(S-1)) + tol, L (speed bound in u).
+enum { AUX_CX = 0, AUX_CY, AUX_CZ, AUX_CC, AUX_KA, AUX_KE, AUX_ES, AUX_L };
+
+// BF16 screen: |computed - exact| of a sample's squared distance is at most
+// kappa * (max|q'_i| A + E).  BF16 rounds each row and column entry by <= 2^-8
+// relative and the MFMA sums exact products in FP32 (<= 32 * 2^-24), so
+// 2 * 2^-8 + 2^-16 + 32 * 2^-24 = 0.00783 is the bound; 0.0085 leaves margin.
+constexpr double kScreenKappaBf16 = 0.0085;
 
 struct Plan {
     int64_t n_curves = 0;

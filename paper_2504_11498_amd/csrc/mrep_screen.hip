@@ -37,35 +37,41 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 // so lane l ends up with 4 samples of query (l>>4) against piece (l&15) per
 // MFMA, and 8 MFMAs cover all 32 samples without any cross-lane reduction.
 
-__device__ __forceinline__ unsigned short bf16_bits(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
 
 // Screen bound: |computed - exact| of a squared sample distance.  BF16 rounds
 // each row and column entry by <= 2^-8 relative, products are exact in FP32
-// and the FP32 sum adds <= 32 * 2^-24; 0.0085 covers 2 * 2^-8 + both with margin.
-#define SCREEN_KAPPA 0.0085f
+// and the FP32 sum adds <= 32 * 2^-24; kScreenKappaBf16 (folded into the
+// stored bound terms A and E) covers 2 * 2^-8 + both with margin.  The
+// epilogue's FP32 terms add <= 1e-6 (|q'|^2 + |c|^2 + |acc|).
 
-constexpr int kSets = 2;   // query sets of 4 per wave
-constexpr int kDepth = 3;  // lower bounds kept per lane and query
-constexpr int kXcds = 8;   // accelerator complex dies of an MI355X, each with its own L2
+#ifndef MREP_SCREEN_WAVES
+#define MREP_SCREEN_WAVES 4
+#endif
+#ifndef MREP_SCREEN_SETS
+#define MREP_SCREEN_SETS 2
+#endif
+constexpr int kWaves = MREP_SCREEN_WAVES;  // waves per workgroup
+constexpr int kSets = MREP_SCREEN_SETS;    // query sets of 4 per wave
+constexpr int kThreads = 64 * kWaves;
+constexpr int kDepth = 3;   // lower bounds kept per lane and query
+constexpr int kXcds = 8;    // accelerator complex dies of an MI355X, each with its own L2
+static_assert(4 * kSets * kWaves == kQueriesPerTile, "tile = waves x sets x 4 queries");
+static_assert(kChunk * 4 % kThreads == 0 && kChunk * 2 % kThreads == 0, "full-chunk staging");
 // margins that make the raw hardware square root (<= 1 ulp) safe for the
 // certified bounds, with room for the FP32 rounding of the epilogue
-static_assert(kChunk == 256 && kQueriesPerTile == 32, "the staging and tile code assume 256 threads, 256 pieces, 32 queries");
 constexpr float kSqrtLo = 1.0f - 0x1p-20f;
 constexpr float kSqrtHi = 1.0f + 0x1p-20f;
 
-__global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
-                                                     const int32_t* __restrict__ q_off,
-                                                     const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ qxyz, int32_t kc,
-                                                     ScreenOut out)
+__global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
+                                                          const int32_t* __restrict__ q_off,
+                                                          const int32_t* __restrict__ perm,
+                                                          const double* __restrict__ qxyz, int32_t kc,
+                                                          ScreenOut out)
 {
     __shared__ __attribute__((aligned(16))) unsigned short s_col[kChunk * kScreenK];
     __shared__ __attribute__((aligned(16))) float s_aux[kChunk * 8];
+    __shared__ int32_t s_off[kWaves * kSets * 4];
+    __shared__ int32_t s_base;
 
     const int n_curves = G.n_curves;
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
@@ -89,12 +95,12 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
     const int qbase = q_off[c] + (tile - tile_off[c]) * kQueriesPerTile + wave * (4 * kSets);
     const int qend = q_off[c + 1];
 
-    // A fragments (rows) for both query sets, built once.
+    // A fragments (rows), built once per query set.
     const int arow = lane & 15;
     const int kb = lane >> 4;
     bf16x8 A[kSets][8];
-    float pq[kSets][4];  // post-process query of this lane: x, y, z, max-norm
-    float eq[kSets];
+    // epilogue query of this lane (query lane>>4 of each set): -2 q', |q'|^2, max |q'_i|
+    float m2q[kSets][3], qq[kSets], qmax[kSets], eq[kSets];
     bool pvalid[kSets];
     for (int s = 0; s < kSets; ++s) {
         int ja = qbase + 4 * s + (arow >> 2);
@@ -119,31 +125,31 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
             } else {
                 for (int k = 0; k < 8; ++k) v[k] = 0.f;
             }
-            u16x8 bits;
-            for (int k = 0; k < 8; ++k) bits[k] = bf16_bits(v[k]);
-            A[s][i] = __builtin_bit_cast(bf16x8, bits);
+            bf16x8 a;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] = (__bf16)v[k];  // v_cvt_pk_bf16_f32, round to nearest even
+            A[s][i] = a;
         }
-        int jp = qbase + 4 * s + (lane >> 4);
+        const int jp = qbase + 4 * s + (lane >> 4);
         pvalid[s] = jp < qend;
         float px = 0.f, py = 0.f, pz = 0.f;
-        double nq = 0.0;
         if (pvalid[s]) {
             const double* q = qxyz + 3 * (int64_t)perm[jp];
             px = (float)(q[0] - cv.origin[0]);
             py = (float)(q[1] - cv.origin[1]);
             pz = (float)(q[2] - cv.origin[2]);
-            nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
         }
-        pq[s][0] = px; pq[s][1] = py; pq[s][2] = pz;
-        pq[s][3] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
+        m2q[s][0] = -2.f * px; m2q[s][1] = -2.f * py; m2q[s][2] = -2.f * pz;
+        qq[s] = px * px + py * py + pz * pz;
+        qmax[s] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
         // rounding q - o to FP32 moves the query by <= 2^-24 |q - o| per axis
         // (the origin is exact in FP32): 2.4e-7 |q'| bounds the distance change
-        eq[s] = sqrtf(px * px + py * py + pz * pz) * 2.4e-7f + 1e-30f;
-        (void)nq;
+        eq[s] = __builtin_amdgcn_sqrtf(qq[s]) * 2.4e-7f + 1e-30f;
     }
 
     // per lane and query set: running upper bound (squared), the kDepth smallest
-    // lower bounds with their pieces (sorted), the smallest discarded bound
+    // lower bounds (sorted) with their pieces, the smallest discarded bound.
+    // Lower bounds here leave out the per-query term eq, added at the end.
     float ubsq[kSets], lbk[kSets][kDepth], disc[kSets];
     int sk[kSets][kDepth];
     for (int s = 0; s < kSets; ++s) {
@@ -164,20 +170,21 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
             uint4* sc = reinterpret_cast<uint4*>(s_col);
             const float4* ga = reinterpret_cast<const float4*>(G.aux + (cv.seg_off + base) * 8);
             float4* sa = reinterpret_cast<float4*>(s_aux);
-            if (cn == kChunk) {  // full chunk: 4 column and 2 aux vectors per thread, unconditional
-                uint4 c0 = gc[threadIdx.x], c1 = gc[threadIdx.x + 256], c2 = gc[threadIdx.x + 512],
-                      c3 = gc[threadIdx.x + 768];
-                float4 a0 = ga[threadIdx.x], a1 = ga[threadIdx.x + 256];
-                sc[threadIdx.x] = c0;
-                sc[threadIdx.x + 256] = c1;
-                sc[threadIdx.x + 512] = c2;
-                sc[threadIdx.x + 768] = c3;
-                sa[threadIdx.x] = a0;
-                sa[threadIdx.x + 256] = a1;
+            if (cn == kChunk) {
+                uint4 cr[kChunk * 4 / kThreads];
+                float4 ar[kChunk * 2 / kThreads];
+#pragma unroll
+                for (int k = 0; k < kChunk * 4 / kThreads; ++k) cr[k] = gc[threadIdx.x + k * kThreads];
+#pragma unroll
+                for (int k = 0; k < kChunk * 2 / kThreads; ++k) ar[k] = ga[threadIdx.x + k * kThreads];
+#pragma unroll
+                for (int k = 0; k < kChunk * 4 / kThreads; ++k) sc[threadIdx.x + k * kThreads] = cr[k];
+#pragma unroll
+                for (int k = 0; k < kChunk * 2 / kThreads; ++k) sa[threadIdx.x + k * kThreads] = ar[k];
             } else {
-                for (int i = threadIdx.x; i < cn16 * 4; i += 256) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
-                for (int i = threadIdx.x; i < cn16 * 2; i += 256)
-                    sa[i] = (i < cn * 2) ? ga[i] : ((i & 1) ? make_float4(INFINITY, -INFINITY, 0.f, 0.f)
+                for (int i = threadIdx.x; i < cn16 * 4; i += kThreads) sc[i] = (i < cn * 4) ? gc[i] : make_uint4(0, 0, 0, 0);
+                for (int i = threadIdx.x; i < cn16 * 2; i += kThreads)
+                    sa[i] = (i < cn * 2) ? ga[i] : ((i & 1) ? make_float4(0.f, INFINITY, -INFINITY, 0.f)
                                                             : make_float4(0.f, 0.f, 0.f, 0.f));
             }
         }
@@ -185,8 +192,8 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         for (int tb = 0; tb < cn16; tb += 16) {
             const int sl = tb + (lane & 15);
             const bf16x8 B = *reinterpret_cast<const bf16x8*>(&s_col[sl * kScreenK + kb * 8]);
-            const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);
-            const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);
+            const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);      // c, |c|^2
+            const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);  // kappa A, kappa E, e
             const int gseg = (int)(cv.seg_off + base + sl);
             for (int s = 0; s < kSets; ++s) {
                 float acc = INFINITY;
@@ -198,16 +205,16 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
                     acc = __builtin_fminf(__builtin_fminf(acc, r[2]), r[3]);
                 }
                 // epilogue for (query lane>>4 of set s, piece sl)
-                const float dx = pq[s][0] - x0.x, dy = pq[s][1] - x0.y, dz = pq[s][2] - x0.z;
-                const float d2c = dx * dx + dy * dy + dz * dz;
+                const float qqcc = qq[s] + x0.w;
+                const float d2c = fmaf(m2q[s][0], x0.x, fmaf(m2q[s][1], x0.y, fmaf(m2q[s][2], x0.z, qqcc)));
                 const float D = acc + d2c;
-                const float delta = SCREEN_KAPPA * fmaf(pq[s][3], x0.w, x1.x) + 1e-6f * (d2c + fabsf(acc));
+                const float delta = fmaf(qmax[s], x1.x, x1.y) + 1e-6f * (qqcc + fabsf(acc));
                 ubsq[s] = fminf(ubsq[s], D + delta);
                 // raw v_sqrt_f32 (<= 1 ulp): the lower bound is shrunk by 2^-20 relative
-                const float lb = __builtin_amdgcn_sqrtf(fmaxf(D - delta, 0.f)) * kSqrtLo - (x1.y + eq[s]);
-                float out = lb;
-                if (lb < lbk[s][kDepth - 1]) {  // rare: insert into the sorted list
-                    out = lbk[s][kDepth - 1];
+                const float lb = fmaf(__builtin_amdgcn_sqrtf(fmaxf(D - delta, 0.f)), kSqrtLo, -x1.z);
+                const float l3 = lbk[s][kDepth - 1];
+                disc[s] = fminf(disc[s], fmaxf(lb, l3));  // the value that leaves the list
+                if (lb < l3) {  // rare: insert into the sorted list
                     float v = lb;
                     int g = gseg;
 #pragma unroll
@@ -221,14 +228,11 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
                         g = tg;
                     }
                 }
-                disc[s] = fminf(disc[s], out);
             }
         }
     }
     // per query (16 lanes): upper bound and candidate count; then one atomic
     // per workgroup reserves the pairs of all its queries
-    __shared__ int32_t s_off[4 * kSets * 4];
-    __shared__ int32_t s_base;
     const int g = lane >> 4;
     const uint64_t gm = 0xFFFFull << (16 * g);
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -240,22 +244,24 @@ __global__ __launch_bounds__(256) void k_screen_bf16(DevGeom G, const int32_t* _
         float u = ubsq[s];
         for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
         UBv[s] = __builtin_amdgcn_sqrtf(u) * kSqrtHi + (float)cv.tol_eff + eq[s];
+        // lower bounds carry eq only here: lb - eq <= UB  <=>  lb <= UB + eq
+        const float cmp = UBv[s] + eq[s];
         tot[s] = 0;
         pos[s] = 0;
 #pragma unroll
         for (int k = 0; k < kDepth; ++k) {
-            ck[s][k] = lbk[s][k] <= UBv[s];
+            ck[s][k] = sk[s][k] >= 0 && lbk[s][k] <= cmp;  // an unfilled slot is never a candidate
             const uint64_t m = __ballot(ck[s][k]);
             tot[s] += __popcll(m & gm);
             pos[s] += __popcll(m & gm & below);
         }
-        ovf[s] = tot[s] > kc || (__ballot(disc[s] <= UBv[s]) & gm) != 0ull || !pvalid[s];
+        ovf[s] = tot[s] > kc || (__ballot(disc[s] <= cmp) & gm) != 0ull || !pvalid[s];
         if ((lane & 15) == 0) s_off[(wave * kSets + s) * 4 + g] = ovf[s] ? 0 : tot[s];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int sum = 0;
-        for (int i = 0; i < 4 * kSets * 4; ++i) {
+        for (int i = 0; i < kWaves * kSets * 4; ++i) {
             const int v = s_off[i];
             s_off[i] = sum;
             sum += v;
@@ -293,7 +299,8 @@ hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* til
                               const int32_t* perm, const double* qxyz, int32_t kc, const ScreenOut& out,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)grid), dim3(256), 0, st, G, tile_off, q_off, perm, qxyz, kc, out);
+    hipLaunchKernelGGL(k_screen_bf16, dim3((unsigned)grid), dim3(kThreads), 0, st, G, tile_off, q_off, perm, qxyz, kc,
+                       out);
     return hipGetLastError();
 }
 

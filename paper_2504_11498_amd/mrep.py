@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmrep.so")
+# MREP_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MREP_LIBRARY") or os.path.join(_HERE, "libmrep.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libmrep.so not built ({LIB_PATH}); run paper_2504_11498_amd/build.py or __graft_entry__.build()")
