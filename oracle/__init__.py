@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrep_oracle.c")
+_SRC_MLP = os.path.join(_HERE, "mlp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -27,7 +28,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
-               "-shared", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-o", tmp, _SRC, _SRC_MLP, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -37,7 +38,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_MLP)):
         build(force=True)
     lib = C.CDLL(_LIB)
     dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -64,6 +65,8 @@ def _load():
     lib.orc_project_batch.argtypes = [C.c_int, ip, lp, dp, lp, dp, C.c_int64, ip, dp, dp, dp, ip, dp, dp,
                                       C.c_int]
     lib.orc_max_threads.restype = C.c_int
+    lib.orc_mlp_loss.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int64, dp, dp, dp, dp, dp]
+    lib.orc_mlp_loss.restype = C.c_double
     _lib = lib
     return lib
 
@@ -210,3 +213,25 @@ def project(curves, cid, q, nthreads: int = 0):
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def mlp_loss(params, x, u_star=None, accept=None, n_in=15, hidden=128, n_out=2, grad=False):
+    """FP64 seeding-network forward (and backward) on a batch (see mlp_oracle.c).
+
+    Returns (loss, y[B, n_out], grad or None)."""
+    params = _d(params)
+    x = _d(x).reshape(-1, n_in)
+    B = x.shape[0]
+    y = np.zeros((B, n_out))
+    g = np.zeros_like(params) if grad else None
+    us = _d(u_star) if u_star is not None else None
+    ac = _d(accept) if accept is not None else None
+    loss = _load().orc_mlp_loss(n_in, hidden, n_out, _ptr(params, C.c_double), B, _ptr(x, C.c_double),
+                                _ptr(us, C.c_double) if us is not None else None,
+                                _ptr(ac, C.c_double) if ac is not None else None, _ptr(y, C.c_double),
+                                _ptr(g, C.c_double) if g is not None else None)
+    return float(loss), y, g
+
+
+def mlp_param_count(n_in=15, hidden=128, n_out=2):
+    return hidden * n_in + hidden + hidden * hidden + hidden + n_out * hidden + n_out

@@ -340,3 +340,98 @@ def test_projection_never_worse_than_dense_sampling():
     # where the minimum is unique the dense argmin agrees in t to the sampling step
     u = r["runner"] > r["dist"] + 1e-3
     assert np.all(np.abs(tt[ii[u]] - r["t"][u]) <= 2e-5)
+
+
+# --------------------------------------------------------------------------- seeding network (MLP)
+from scipy.special import ndtr  # noqa: E402  standard normal CDF: GELU(z) = z * Phi(z)
+
+NIN, NH, NOUT = 15, 128, 2
+
+
+def _blocks(params):
+    o = 0
+    out = []
+    for shape in [(NH, NIN), (NH,), (NH, NH), (NH,), (NOUT, NH), (NOUT,)]:
+        n = int(np.prod(shape))
+        out.append(params[o : o + n].reshape(shape))
+        o += n
+    return out
+
+
+def test_mlp_param_count():
+    assert oracle.mlp_param_count() == 18818
+
+
+def test_mlp_linear_network_via_gelu_odd_part():
+    """GELU(z) - GELU(-z) = z exactly, so a network whose hidden units come in
+    (+z, -z) pairs and whose next layer takes their difference is linear:
+    y = w . x + c in closed form.  A transposed weight layout or a wrong
+    activation fails this."""
+    rng = np.random.default_rng(7)
+    p = np.zeros(oracle.mlp_param_count())
+    W1, b1, W2, b2, W3, b3 = _blocks(p)
+    for k in range(NIN):
+        W1[2 * k, k] = 1.0
+        W1[2 * k + 1, k] = -1.0
+        W2[2 * k, 2 * k], W2[2 * k, 2 * k + 1] = 1.0, -1.0
+        W2[2 * k + 1, 2 * k], W2[2 * k + 1, 2 * k + 1] = -1.0, 1.0
+    w0, w1 = rng.normal(size=NIN), rng.normal(size=NIN)
+    for k in range(NIN):
+        W3[0, 2 * k], W3[0, 2 * k + 1] = w0[k], -w0[k]
+        W3[1, 2 * k], W3[1, 2 * k + 1] = w1[k], -w1[k]
+    b3[:] = [0.25, -0.5]
+    x = rng.normal(size=(33, NIN))
+    _, y, _ = oracle.mlp_loss(p, x)
+    np.testing.assert_allclose(y[:, 0], x @ w0 + 0.25, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(y[:, 1], x @ w1 - 0.5, rtol=0, atol=1e-12)
+
+
+def test_mlp_single_path_matches_normal_cdf():
+    """One active unit per layer: y0 = g(a * g(x_3 + 0.5) - 0.2) + 0.1 with
+    g(z) = z * Phi(z), Phi from scipy's ndtr."""
+    p = np.zeros(oracle.mlp_param_count())
+    W1, b1, W2, b2, W3, b3 = _blocks(p)
+    W1[5, 3], b1[5] = 1.0, 0.5
+    W2[9, 5], b2[9] = 1.7, -0.2
+    W3[0, 9], b3[0] = 1.0, 0.1
+    x = np.linspace(-3, 3, 13)[:, None] * np.eye(NIN)[3][None, :]
+    _, y, _ = oracle.mlp_loss(p, x)
+    g = lambda z: z * ndtr(z)  # noqa: E731
+    want = g(1.7 * g(x[:, 3] + 0.5) - 0.2) + 0.1
+    np.testing.assert_allclose(y[:, 0], want, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(y[:, 1], 0.0, atol=0)
+
+
+def test_mlp_loss_terms():
+    """Loss with a zero network (outputs = biases): MSE masked by accept plus
+    binary cross-entropy log(1 + exp(-z)) for a = 1 and log(1 + exp(z)) for a = 0."""
+    p = np.zeros(oracle.mlp_param_count())
+    b3 = _blocks(p)[5]
+    b3[:] = [0.3, 1.25]
+    us = np.array([0.1, 0.9, 0.5, 0.0])
+    ac = np.array([1.0, 0.0, 1.0, 0.0])
+    loss, _, _ = oracle.mlp_loss(p, np.zeros((4, NIN)), us, ac)
+    z = 1.25
+    terms = ac * (0.3 - us) ** 2 + np.where(ac > 0, np.logaddexp(0, -z), np.logaddexp(0, z))
+    assert loss == pytest.approx(terms.mean(), rel=0, abs=1e-15)
+
+
+def test_mlp_gradient_central_differences():
+    """Backward pass against central differences of the loss, on entries of
+    every parameter block."""
+    rng = np.random.default_rng(11)
+    npar = oracle.mlp_param_count()
+    p = rng.normal(0, 0.3, npar)
+    x = rng.normal(size=(24, NIN))
+    us = rng.uniform(0, 1, 24)
+    ac = (rng.uniform(size=24) < 0.5).astype(float)
+    loss, _, g = oracle.mlp_loss(p, x, us, ac, grad=True)
+    offs = np.cumsum([0, NH * NIN, NH, NH * NH, NH, NOUT * NH, NOUT])
+    idx = np.concatenate([rng.integers(offs[b], offs[b + 1], 6) for b in range(6)])
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        num = (oracle.mlp_loss(pp, x, us, ac)[0] - oracle.mlp_loss(pm, x, us, ac)[0]) / (2 * h)
+        assert abs(num - g[i]) <= 1e-7 * max(1.0, abs(num)), (i, num, g[i])
