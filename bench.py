@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
@@ -104,7 +105,7 @@ def main():
         geom.project(q, cid, opts, workspace=ws, out=outs)
         mrep.last_stage_times()
     torch.cuda.synchronize()
-    stage_ms = np.zeros(mrep.N_STAGES)
+    stage_ms = np.zeros(3)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     e0.record()
@@ -163,9 +164,84 @@ def main():
             "per_unit": "64 flop per screened (query, piece, sample): one 16x16x32 BF16 MFMA output element",
         },
     }
+    if not args.no_seeded:
+        result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(curves, qs, outs, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def _timed(fn, steps):
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    stage = None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+        st = mrep.last_stage_times()
+        stage = st if stage is None else stage + st
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, stage / steps
+
+
+def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):
+    """Learned seeding: train on held-out curves, then time the seeded and the sphere-pruned projection
+    of the same queries; both are compared with the plain method's answers."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep, seeding
+
+    dev = q.device
+    t0 = time.perf_counter()
+    tr_curves = gen.curves_batched_geometry(12, n_curves=1024)
+    tr_qs = gen.offset_queries(112, tr_curves, per_curve=1000)
+    tr_plan = mrep.decompose_curves(tr_curves, 1e-6)
+    tr_geom = tr_plan.upload(dev)
+    tr_cid = torch.from_numpy(tr_qs.curve_id).to(dev)
+    tr_q = (tr_geom.eval(tr_cid, torch.from_numpy(tr_qs.t0).to(dev)) + torch.from_numpy(tr_qs.offset).to(dev)).contiguous()
+    x, u, a, stats = seeding.training_pairs(tr_plan, tr_geom, tr_q, tr_cid, seed=0)
+    prep_s = time.perf_counter() - t0
+    net = mrep.Network(dev, seed=7)
+    t0 = time.perf_counter()
+    losses = seeding.train(net, x, u, a, epochs=10, batch=4096, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t0
+    del x, u, a, tr_geom
+
+    n = q.shape[0]
+    opts = mrep.default_opts("bf16", time_stages=True)
+    outs = tuple(torch.empty_like(o) for o in plain_outs)
+    ws = torch.empty(geom.seeded_workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
+    res = {}
+    for name, nn in (("nn", net), ("sphere_pruned", None)):
+        def step():
+            geom.project_seeded(q, cid, nn, opts, workspace=ws, out=outs)
+
+        for _ in range(args.warmup):
+            step()
+        ms, stage = _timed(step, args.steps)
+        flags = outs[3].cpu().numpy().view(np.uint32)
+        diag = torch.from_numpy(curves.bbox_diag()).to(dev)[cid.long()]
+        dd = ((outs[1] - plain_outs[1]).abs() / diag).max().item()
+        dt = (outs[0] - plain_outs[0]).abs()
+        res[name] = {
+            "value": n / (ms / 1e3),
+            "ms_per_step": ms,
+            "speedup_vs_plain": (n / (ms / 1e3)) / plain_value,
+            "stage_ms": {"group_candidates": float(stage[0]), "network": float(stage[1]),
+                         "seed_certify": float(stage[2]), "fallback": float(stage[3])},
+            "fallback_frac": float(np.mean((flags & mrep.F_NN_FALLBACK) != 0)),
+            "vs_plain_max_dist_rel": dd,
+            "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
+        }
+    res["training"] = {"geometry": "1024 held-out curves (seed 12), 1000 offset queries each (seed 112)",
+                       **stats, "epochs": 10, "batch": 4096, "lr": 1e-3, "steps": int(len(losses)),
+                       "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
+                       "prep_s": prep_s, "train_s": train_s}
+    return res
 
 
 def cpu_baseline(curves, qs, outs, seconds):

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 1
+#define MREP_ABI_VERSION 2
 
 /* status codes */
 #define MREP_OK 0
@@ -66,6 +66,7 @@ extern "C" {
 #define MREP_F_OFFCURVE 0x10u   /* invert only: distance above the curve's tolerance */
 #define MREP_F_FULLSCAN 0x20u   /* screen candidate list overflowed; every segment was examined */
 #define MREP_F_BAD_ID 0x40u     /* curve_id out of range: outputs are NaN / -1 */
+#define MREP_F_NN_FALLBACK 0x80u /* seeded call: the certificate failed and the screened pipeline decided */
 
 /* screen precisions (mrep_opts.precision) */
 #define MREP_PREC_FP64 0 /* exhaustive FP64 examination of every segment (no MFMA screen) */
@@ -98,7 +99,7 @@ typedef struct {
 /* mrep_opts.flags: record HIP events around each stage of the call on its
  * stream; read them back with mrep_last_stage_times. */
 #define MREP_OPT_TIME_STAGES 0x1
-#define MREP_N_STAGES 3 /* grouping by curve, screen, refine + polish + write */
+#define MREP_N_STAGES 4 /* most stages any call records (see mrep_last_stage_times) */
 
 /* ---------------------------------------------------------------------- */
 /* Decomposition (host, FP64)                                              */
@@ -172,6 +173,8 @@ int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* 
  *   flags_out[n] DEVICE uint32   MREP_F_* bits
  * Queries may come in any order.  Calls on one stream are ordered; the same
  * workspace must not be used by two calls that may overlap.
+ * Limits: n * opts->max_candidates < 2^31 (the candidate-pair counter is
+ * 32-bit); larger batches are split by the caller.
  * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
 int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
                             const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
@@ -191,11 +194,112 @@ int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_
                          double* xyz_out, void* stream);
 
 /* Durations in milliseconds of the stages of the last call on the calling
- * thread that set MREP_OPT_TIME_STAGES: ms_out[0] grouping, [1] screen (0 in
- * FP64 mode), [2] refine/polish/write.  Waits for that call's events.
- * n = capacity of ms_out (>= MREP_N_STAGES).
+ * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 3
+ * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine/polish/write.
+ * mrep_project_curves_seeded: 4 stages, [0] grouping + sphere candidates,
+ * [1] network scoring (0 without a network), [2] seed + certificate (or the
+ * sphere-pruned refine), [3] fallback through the screened pipeline.  Waits for
+ * that call's events.  n = capacity of ms_out (>= MREP_N_STAGES is always
+ * enough).  Returns the number of stages written (> 0).
  * Errors: MREP_E_INVALID_ARG (no timed call yet, n too small), MREP_E_HIP. */
 int32_t mrep_last_stage_times(double* ms_out, int32_t n);
+
+/* ---------------------------------------------------------------------- */
+/* Learned seeding (an extension; the paper has no learned part)           */
+/* ---------------------------------------------------------------------- */
+/* A multilayer perceptron scores, for a query and one of its curve's cubic
+ * pieces (Sec. 5.2 matrix representation), the local parameter u of the
+ * closest point on the piece and the logit that the projection lies on it:
+ *   x (MREP_NN_IN = 15: the piece's 4 control points and the query, minus the
+ *   control points' centroid, divided by their box diagonal)
+ *   -> Linear(15, 128) -> GELU (erf form) -> Linear(128, 128) -> GELU
+ *   -> Linear(128, 2) = (u, logit).
+ * Parameters: FP32, row-major W[out][in], in the order W1 b1 W2 b2 W3 b3
+ * (mrep_nn_param_count() = 18818).  Products run as BF16 MFMA with FP32
+ * accumulation; master weights and Adam state stay FP32.
+ * Loss of a batch of B rows with targets (u*, a), a in {0, 1}:
+ *   (1/B) sum [ a (u - u*)^2 + max(z, 0) - z a + log(1 + exp(-|z|)) ],
+ * z = logit. */
+#define MREP_NN_IN 15
+#define MREP_NN_HIDDEN 128
+#define MREP_NN_OUT 2
+#define MREP_NN_K 4 /* candidate pieces scored per query */
+
+typedef struct mrep_nn mrep_nn; /* device view of a caller-owned state buffer (non-owning) */
+
+int32_t mrep_nn_param_count(void);
+
+/* Sizes: *state_bytes of the network state buffer (parameters, Adam moments,
+ * gradient, packed BF16 weight image), *work_bytes of the work buffer of
+ * mrep_nn_forward / mrep_nn_train_step for `batch` rows.  Either output may be
+ * NULL (not both).  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_nn_bytes(int64_t batch, int64_t* state_bytes, int64_t* work_bytes);
+
+/* Bind a DEVICE buffer of >= state_bytes (256-byte aligned, caller-owned,
+ * must outlive the handle) as network state.  Its contents are undefined until
+ * mrep_nn_init or mrep_nn_set_params.  Release the handle with
+ * mrep_nn_release (the buffer stays the caller's).
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_NO_DEVICE. */
+int32_t mrep_nn_bind(void* dev_state, int64_t bytes, mrep_nn** out);
+void mrep_nn_release(mrep_nn* nn);
+
+/* Weights uniform in +-1/sqrt(fan_in) from splitmix64(seed), biases 0, Adam
+ * state and step count reset.  Synchronous on `stream`. */
+int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream);
+/* host[n] (HOST, n = mrep_nn_param_count()) -> parameters; resets Adam.
+ * Synchronous on `stream`.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
+int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stream);
+/* parameters -> host[n] (HOST).  Synchronous on `stream`. */
+int32_t mrep_nn_get_params(const mrep_nn* nn, float* host, int64_t n, void* stream);
+
+/* Outputs y[n][2] for inputs x[n][15] (both DEVICE, FP32).
+ * mrep_nn_forward: the training kernels (layer by layer through `work`, of
+ * mrep_nn_bytes(n) work bytes); mrep_nn_infer: the fused inference kernel
+ * (weights in LDS, no work buffer).  Asynchronous on `stream`.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, void* work, int64_t work_bytes,
+                        void* stream);
+int32_t mrep_nn_infer(const mrep_nn* nn, int64_t n, const float* x, float* y, void* stream);
+
+/* One training step on `batch` rows: forward, the loss above, backward, and
+ * (lr > 0) one Adam step (beta = 0.9, 0.999; eps 1e-8; bias-corrected).
+ * x[n_rows][15], u_star[n_rows], accept[n_rows]: DEVICE FP32 training set.
+ * rows[batch] (DEVICE int32, nullable) selects the rows of this batch; an entry
+ * outside [0, n_rows) contributes an all-zero row.  rows == NULL: the first
+ * `batch` rows (batch <= n_rows).  loss_out (DEVICE float, nullable): the
+ * batch loss before the step.  grad_out (DEVICE float[param_count], nullable):
+ * the gradient.  work: DEVICE, mrep_nn_bytes(batch) work bytes.  Asynchronous
+ * on `stream`.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* u_star, const float* accept,
+                           int64_t batch, const int32_t* rows, float lr, float* loss_out, float* grad_out,
+                           void* work, int64_t work_bytes, void* stream);
+
+/* Workspace of mrep_project_curves_seeded and mrep_nn_features for n queries
+ * (DEVICE, 256-byte aligned).  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes);
+
+/* Training-data export: for every query its MREP_NN_K candidate pieces (the
+ * pieces whose bounding spheres come closest, nearest first) as curve-local
+ * indices seg_out[n][4] (-1: the curve has fewer pieces, or a bad id) and
+ * their network inputs x_out[n][4][15].  All arrays DEVICE.  Asynchronous.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz,
+                         int32_t* seg_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream);
+
+/* Seeded projection: same contract and outputs as mrep_project_curves (BF16
+ * mode only).  The network picks one of each query's 4 candidate pieces and
+ * seeds Newton there; the answer is kept only when a certificate proves it is
+ * the global minimum (every other piece is farther by its bounding sphere, by
+ * its endpoint distances where (C - q).C' keeps one sign on it, read off its
+ * Bernstein coefficients, or by its certified piece minimum); every other query goes through the screened pipeline and is
+ * flagged MREP_F_NN_FALLBACK.  nn == NULL: sphere-pruned projection, every
+ * piece whose sphere lower bound reaches the best sphere upper bound is
+ * refined (no fallback).  ws: mrep_seeded_workspace_bytes(n).
+ * Errors: as mrep_project_curves. */
+int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                                   const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
+                                   double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out,
+                                   void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Host introspection of the constant matrices (for tests and tools)       */

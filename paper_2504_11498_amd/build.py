@@ -38,8 +38,11 @@ def build(verbose: bool = False) -> str:
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_device.hip"), "-o", dev_o])
     scr_o = os.path.join(BUILD, "mrep_screen.o")
     _run(["hipcc", *HIP_FLAGS, *SCREEN_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_screen.hip"), "-o", scr_o])
+    nn_o = os.path.join(BUILD, "mrep_nn.o")
+    _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_nn.hip"), "-o", nn_o])
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, host_o, "-o", tmp, "-lpthread"])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, nn_o, host_o, "-o", tmp,
+          "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mrep.h"
 #include "mrep_internal.h"
 
 namespace mrep {
@@ -63,4 +64,44 @@ hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* til
                               const int32_t* perm, const double* qxyz, int32_t kc, const ScreenOut& out,
                               hipStream_t st);
 
+// Output arrays of a projection call (indexed by the caller's query index).
+struct Outs {
+    double* t;
+    double* d;
+    int32_t* s;
+    uint32_t* f;
+};
+
+// Shared host helpers (mrep_device.hip).
+int check_device();
+int check_opts(const mrep_opts* o);
+// Stage timing of the calling thread: stage_begin records event 0, stage_mark(i)
+// event i, stage_end(count) publishes the call's stage count.
+int stage_begin(hipStream_t st);
+int stage_mark(int i, hipStream_t st);
+void stage_end(int count);
+
+// Group n queries by curve (n_dev, nullable: actual count on the device):
+// hist[n_curves + 2] zeroed and counted, q_off / tile_off exclusive scans,
+// perm[sorted position] = query index.  Invalid ids get NaN / -1 /
+// MREP_F_BAD_ID outputs when o.t is not null.
+hipError_t launch_grouping(int64_t n_curves, int64_t n, const int32_t* n_dev, const int32_t* curve_id,
+                           int32_t* hist, int32_t* q_off, int32_t* tile_off, int32_t* perm, const Outs& o,
+                           hipStream_t st);
+
+// The screened projection pipeline (grouping, screen, refine, finish) on a
+// workspace of project_ws_bytes(n_curves, n, kc) bytes.  n bounds the query
+// count; n_dev (nullable) holds the actual count on the device.  With timed,
+// stage marks stage0 + 1 .. stage0 + 3 are recorded after grouping, screen and
+// refine.
+int64_t project_ws_bytes(int64_t n_curves, int64_t n, int kc);
+int project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const int32_t* n_dev, const int32_t* curve_id,
+                 const double* q_xyz, void* workspace, const Outs& o, hipStream_t st, int invert, bool timed,
+                 int stage0);
+
 }  // namespace mrep
+
+// Device geometry handle of the C ABI: a non-owning view of the caller's buffer.
+struct mrep_geom {
+    mrep::Geom g;
+};

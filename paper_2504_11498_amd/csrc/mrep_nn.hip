@@ -1,0 +1,1319 @@
+// Learned seeding for curve projection: a small MLP proposes, for a (query,
+// candidate piece) pair, the local parameter of the closest point and a logit
+// that the projection lies on that piece; a certificate then decides whether
+// the seeded answer is the global minimum, and the screened pipeline takes
+// every query whose certificate fails.  (The paper has no learned part; this is
+// an extension built around its piecewise-cubic matrix representation,
+// Sec. 5.2, and its Newton step on (C - q).C' = 0, eqs. Et and E't.)
+//
+// Network (exact-erf GELU, FP32 master weights, BF16 MFMA products with FP32
+// accumulation):
+//   x (15: a piece's 4 control points and the query, translated by the control
+//   points' centroid and scaled by 1 / their box diagonal)
+//     -> Linear(15, 128) -> GELU -> Linear(128, 128) -> GELU -> Linear(128, 2)
+//   outputs: y0 = predicted local parameter u in the piece, y1 = logit.
+// Parameter layout (FP32, row-major W[out][in]): W1 | b1 | W2 | b2 | W3 | b3.
+//
+// Seeded projection of one query:
+//   1. candidates: every piece of the query's curve is bounded by a sphere
+//      around its control points; the K pieces with the smallest sphere lower
+//      bound, the smallest sphere upper bound UB, and the index range [lo, hi]
+//      of pieces whose lower bound reaches UB plus the tie margin;
+//   2. the MLP scores the K candidates;
+//   3. Newton from the predicted u on the best-scored piece, after walking to a
+//      neighbour while the piece is monotone in the distance (at most 4 hops).
+//      The piece minimum is certified by the Bernstein coefficients of
+//      f(u) = (C(u) - q).C'(u): one sign change means exactly one critical
+//      point;
+//   4. certificate over [lo, hi]: every other piece has a sphere lower bound
+//      above d* + margin, or a minimum above it: an endpoint distance where f
+//      keeps one sign on the piece (again read off its Bernstein coefficients),
+//      else the piece's certified minimum;
+//   5. certified queries finish as in the screened pipeline (FP64 polish rules,
+//      reparameterisation, flags); the others are compacted and projected by
+//      the screened pipeline, flagged MREP_F_NN_FALLBACK.
+// Without a network the same kernels give a sphere-pruned projection: every
+// piece in [lo, hi] whose lower bound reaches UB + margin is refined.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mrep.h"
+#include "mrep_dev.h"
+#include "mrep_refine.h"
+
+using namespace mrep;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kIn = MREP_NN_IN, kH = MREP_NN_HIDDEN, kOut = MREP_NN_OUT, kK = MREP_NN_K;
+static_assert(kIn == 15 && kH == 128 && kOut == 2 && kK == 4, "kernel tiling assumes 15-128-128-2, 4 candidates");
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kH * kIn;
+constexpr int64_t kOffW2 = kOffB1 + kH;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kH * kH;
+constexpr int64_t kOffW3 = kOffB2 + kH;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kOut * kH;
+constexpr int64_t kNParams = kOffB3 + kOut;
+
+// BF16 weight image copied into LDS by the inference kernel.  Rows are padded
+// by 16 bytes so that the 16 rows one MFMA operand load touches start in
+// different banks.  Layer 2 and 3 columns are stored in the order in which the
+// previous layer's MFMA output already sits in the lanes (see k_mlp).
+constexpr int kRowW1 = 80;                       // 32 bf16 (15 used) + pad
+constexpr int kRowW2 = 272;                      // 128 bf16 + pad
+constexpr int kImgW1 = 0;
+constexpr int kImgW2 = kImgW1 + kH * kRowW1;     // 10240
+constexpr int kImgW3 = kImgW2 + kH * kRowW2;     // 45056
+constexpr int kImgB1 = kImgW3 + 16 * kRowW2;     // 49408
+constexpr int kImgB2 = kImgB1 + 4 * kH;
+constexpr int kImgB3 = kImgB2 + 4 * kH;
+constexpr int kImgBytes = kImgB3 + 4 * 16;       // 50496
+static_assert(kImgBytes % 16 == 0, "image copied in 16-byte units");
+
+int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+constexpr int64_t kParamBytes = ((4 * kNParams + 255) / 256) * 256;
+// state: params | Adam m | Adam v | grad | LDS image
+constexpr int64_t kStateBytes = 4 * kParamBytes + ((kImgBytes + 255) / 256) * 256;
+
+#define NN_HIP(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));        \
+            return MREP_E_HIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Training-form kernels: a strided BF16 MFMA GEMM and elementwise passes.
+// ---------------------------------------------------------------------------
+// C[M x N] = sum_k A(m, k) B(k, n) with A, B FP32 in memory (any strides),
+// rounded to BF16 in registers; v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+// One wave per 16x16 tile of C; out-of-range rows, columns and k read as zero.
+struct GemmArgs {
+    int M, N, K;
+    const float* A;
+    int64_t sam, sak;
+    const float* B;
+    int64_t sbk, sbn;
+    float* C;
+    int64_t scm, scn;
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int tiles_n = (g.N + 15) / 16;
+    const int64_t tiles = (int64_t)((g.M + 15) / 16) * tiles_n;
+    if (tile >= tiles) return;
+    const int m0 = (int)(tile / tiles_n) * 16, n0 = (int)(tile % tiles_n) * 16;
+    const int r = lane & 15, kb = lane >> 4;
+    const int am = m0 + r, bn = n0 + r;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + kb * 8 + j;
+            const bool kin = k < g.K;
+            a[j] = (__bf16)((kin && am < g.M) ? g.A[am * g.sam + k * g.sak] : 0.f);
+            b[j] = (__bf16)((kin && bn < g.N) ? g.B[k * g.sbk + bn * g.sbn] : 0.f);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int cn = n0 + r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int cm = m0 + 4 * kb + i;
+        if (cm < g.M && cn < g.N) g.C[cm * g.scm + cn * g.scn] = acc[i];
+    }
+}
+
+hipError_t gemm(const GemmArgs& a, hipStream_t st)
+{
+    const int64_t tiles = (int64_t)((a.M + 15) / 16) * ((a.N + 15) / 16);
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float dgelu(float z)
+{
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Z += b (per column); H = GELU(Z) when H is not null
+__global__ void k_bias_act(int64_t M, int N, float* __restrict__ Z, const float* __restrict__ b, float* __restrict__ H)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * N) return;
+    const float z = Z[i] + b[i % N];
+    Z[i] = z;
+    if (H) H[i] = gelu(z);
+}
+
+// dZ = dH * GELU'(Z)
+__global__ void k_gelu_back(int64_t n, const float* __restrict__ dH, const float* __restrict__ Z, float* __restrict__ dZ)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dZ[i] = dH[i] * dgelu(Z[i]);
+}
+
+// out[n] = sum_m X[m][n]: one block per column, fixed-order tree (deterministic)
+__global__ __launch_bounds__(256) void k_colsum(int64_t M, int N, const float* __restrict__ X, float* __restrict__ out)
+{
+    __shared__ float s[256];
+    const int n = blockIdx.x;
+    float a = 0.f;
+    for (int64_t m = threadIdx.x; m < M; m += 256) a += X[m * N + n];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = s[0];
+}
+
+// Loss a (y0 - u*)^2 + BCE(y1, a) per row and dL/dY of the batch mean.
+__global__ void k_loss_grad(int64_t B, const float* __restrict__ Y, const float* __restrict__ us,
+                            const float* __restrict__ acc, float* __restrict__ dY, float* __restrict__ row_loss)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const float a = acc[i], du = Y[2 * i] - us[i], z = Y[2 * i + 1];
+    row_loss[i] = a * du * du + fmaxf(z, 0.f) - z * a + log1pf(expf(-fabsf(z)));
+    dY[2 * i] = 2.f * a * du / (float)B;
+    dY[2 * i + 1] = (1.f / (1.f + expf(-z)) - a) / (float)B;
+}
+
+// mean of x[0..n) into *out (one block, fixed order)
+__global__ __launch_bounds__(256) void k_mean(int64_t n, const float* __restrict__ x, float* __restrict__ out)
+{
+    __shared__ float s[256];
+    float a = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 256) a += x[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0] / (float)(n > 0 ? n : 1);
+}
+
+// Minibatch gather: rows[i] selects the training row of batch row i; a row
+// outside [0, n_rows) becomes an all-zero row.
+__global__ void k_gather(int64_t B, const int32_t* __restrict__ rows, int64_t n_rows, const float* __restrict__ x,
+                         const float* __restrict__ us, const float* __restrict__ acc, float* __restrict__ xb,
+                         float* __restrict__ usb, float* __restrict__ accb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const int64_t r = rows[i];
+    const bool ok = r >= 0 && r < n_rows;
+    for (int k = 0; k < kIn; ++k) xb[i * kIn + k] = ok ? x[r * kIn + k] : 0.f;
+    usb[i] = ok ? us[r] : 0.f;
+    accb[i] = ok ? acc[r] : 0.f;
+}
+
+// Adam with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t on FP32 master weights.
+__global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP32 master weights -> BF16 LDS image (one thread per 2-byte slot; the FP32
+// bias slots are written by the thread of their first half).
+__global__ void k_pack(const float* __restrict__ P, uint8_t* __restrict__ img)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kImgBytes / 2) return;
+    const int off = 2 * i;
+    if (off >= kImgB1) {
+        if (off & 2) return;
+        float v = 0.f;
+        if (off < kImgB2) v = P[kOffB1 + (off - kImgB1) / 4];
+        else if (off < kImgB3) v = P[kOffB2 + (off - kImgB2) / 4];
+        else if ((off - kImgB3) / 4 < kOut) v = P[kOffB3 + (off - kImgB3) / 4];
+        *reinterpret_cast<float*>(img + off) = v;
+        return;
+    }
+    float v = 0.f;
+    if (off < kImgW2) {
+        const int h = off / kRowW1, k = (off % kRowW1) / 2;
+        if (k < kIn) v = P[kOffW1 + h * kIn + k];
+    } else {
+        const bool l3 = off >= kImgW3;
+        const int base = l3 ? kImgW3 : kImgW2;
+        const int h = (off - base) / kRowW2, p = ((off - base) % kRowW2) / 2;
+        if (p < kH && (!l3 || h < kOut)) {
+            // K position p = (kb, g, j) holds hidden unit 32 kb + 16 (j >> 2) + 4 g + (j & 3)
+            const int kb = p >> 5, g = (p >> 3) & 3, j = p & 7;
+            const int src = 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3);
+            v = l3 ? P[kOffW3 + h * kH + src] : P[kOffW2 + h * kH + src];
+        }
+    }
+    *reinterpret_cast<__bf16*>(img + off) = (__bf16)v;
+}
+
+struct TrainWork {
+    float *Xb, *Usb, *Ab, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH, *dZ, *rowl;
+};
+
+int64_t train_layout(int64_t B, char* base, TrainWork* w)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off = a256(off + bytes);
+        return o;
+    };
+    int64_t oXb = take(4 * B * kIn), oUs = take(4 * B), oA = take(4 * B);
+    int64_t oZ1 = take(4 * B * kH), oH1 = take(4 * B * kH), oZ2 = take(4 * B * kH), oH2 = take(4 * B * kH);
+    int64_t oY = take(4 * B * kOut), odY = take(4 * B * kOut), odH = take(4 * B * kH), odZ = take(4 * B * kH);
+    int64_t orl = take(4 * B);
+    if (w) {
+        w->Xb = (float*)(base + oXb); w->Usb = (float*)(base + oUs); w->Ab = (float*)(base + oA);
+        w->Z1 = (float*)(base + oZ1); w->H1 = (float*)(base + oH1); w->Z2 = (float*)(base + oZ2);
+        w->H2 = (float*)(base + oH2); w->Y = (float*)(base + oY); w->dY = (float*)(base + odY);
+        w->dH = (float*)(base + odH); w->dZ = (float*)(base + odZ); w->rowl = (float*)(base + orl);
+    }
+    return off;
+}
+
+int forward(const float* P, int64_t B, const float* X, const TrainWork& w, hipStream_t st)
+{
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kIn, X, kIn, 1, P + kOffW1, 1, kIn, w.Z1, kH, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z1, P + kOffB1, w.H1);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.H1, kH, 1, P + kOffW2, 1, kH, w.Z2, kH, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z2, P + kOffB2, w.H2);
+    NN_HIP(gemm(GemmArgs{(int)B, kOut, kH, w.H2, kH, 1, P + kOffW3, 1, kH, w.Y, kOut, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kOut)), dim3(256), 0, st, B, kOut, w.Y, P + kOffB3,
+                       (float*)nullptr);
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+int backward(const float* P, int64_t B, const float* X, const float* us, const float* acc, const TrainWork& w,
+             float* G, float* loss_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_loss_grad, dim3(blocks_for(B)), dim3(256), 0, st, B, w.Y, us, acc, w.dY, w.rowl);
+    if (loss_out) hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, B, w.rowl, loss_out);
+    // layer 3: dW3 = dY^T H2, db3 = colsum dY, dH2 = dY W3
+    NN_HIP(gemm(GemmArgs{kOut, kH, (int)B, w.dY, 1, kOut, w.H2, kH, 1, G + kOffW3, kH, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, st, B, kOut, w.dY, G + kOffB3);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kOut, w.dY, kOut, 1, P + kOffW3, kH, 1, w.dH, kH, 1}, st));
+    hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z2, w.dZ);
+    // layer 2: dW2 = dZ2^T H1, db2, dH1 = dZ2 W2
+    NN_HIP(gemm(GemmArgs{kH, kH, (int)B, w.dZ, 1, kH, w.H1, kH, 1, G + kOffW2, kH, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + kOffB2);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.dZ, kH, 1, P + kOffW2, kH, 1, w.dH, kH, 1}, st));
+    hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z1, w.dZ);
+    // layer 1: dW1 = dZ1^T X, db1
+    NN_HIP(gemm(GemmArgs{kH, kIn, (int)B, w.dZ, 1, kH, X, kIn, 1, G + kOffW1, kIn, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + kOffB1);
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood, 2014): the initialisation generator
+uint64_t splitmix64(uint64_t& s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Features of a (query, piece) pair, shared by training-data export and the
+// fused inference kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_features(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, float* x)
+{
+    const float* lp = G.lcp + s * 12;
+    const float* ax = G.aux + s * 8;
+    float P[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) P[i] = lp[i];
+    const float ql[3] = {(float)(q[0] - (cv.origin[0] + (double)ax[AUX_CX])),
+                         (float)(q[1] - (cv.origin[1] + (double)ax[AUX_CY])),
+                         (float)(q[2] - (cv.origin[2] + (double)ax[AUX_CZ]))};
+    float m[3], ext2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        m[c] = 0.25f * (P[c] + P[3 + c] + P[6 + c] + P[9 + c]);
+        const float lo = fminf(fminf(P[c], P[3 + c]), fminf(P[6 + c], P[9 + c]));
+        const float hi = fmaxf(fmaxf(P[c], P[3 + c]), fmaxf(P[6 + c], P[9 + c]));
+        ext2 += (hi - lo) * (hi - lo);
+    }
+    const float inv = ext2 > 0.f ? 1.f / sqrtf(ext2) : 1.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[3 * i + c] = (P[3 * i + c] - m[c]) * inv;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[12 + c] = (ql[c] - m[c]) * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: one wave runs 16 rows through the three layers with the
+// weights' BF16 image in LDS.  The products are computed transposed
+// (Z^T = W X^T): weights are the MFMA A operand, rows the B operand, so each
+// layer's output already sits in the lanes as the next layer's B operand (lane
+// (g, r) holds units 16 t + 4 g + i of row r); the image stores layer 2 and 3
+// weight columns in that order.  Persistent grid; 4 waves per block.
+// ---------------------------------------------------------------------------
+struct RowsFromMemory {
+    int64_t n;
+    const float* x;
+    float* y;
+    __device__ int64_t count() const { return n; }
+    __device__ bool features(int64_t row, float* f) const
+    {
+        if (row >= n) return false;
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) f[k] = x[row * kIn + k];
+        return true;
+    }
+    __device__ void write(int64_t row, float y0, float y1) const
+    {
+        if (row < n) { y[2 * row] = y0; y[2 * row + 1] = y1; }
+    }
+};
+
+struct RowsFromCandidates {
+    DevGeom G;
+    const int32_t* cid;
+    const double* qxyz;
+    const int32_t* q_off;
+    const int32_t* perm;
+    const int32_t* cand;  // [n][kK] global piece index or -1
+    float2* out;          // [n][kK] (u, logit)
+    __device__ int64_t count() const { return (int64_t)q_off[G.n_curves] * kK; }
+    __device__ bool features(int64_t row, float* f) const
+    {
+        if (row >= count()) return false;
+        const int32_t s = cand[row];
+        if (s < 0) return false;
+        const int32_t qi = perm[row / kK];
+        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        pair_features(G, G.curves[cid[qi]], s, q, f);
+        return true;
+    }
+    __device__ void write(int64_t row, float y0, float y1) const
+    {
+        if (row < count()) out[row] = make_float2(y0, cand[row] >= 0 ? y1 : -INFINITY);
+    }
+};
+
+__device__ __forceinline__ bf16x8 pack8(const floatx4& a, const floatx4& b)
+{
+    bf16x8 r;
+    r[0] = (__bf16)a[0]; r[1] = (__bf16)a[1]; r[2] = (__bf16)a[2]; r[3] = (__bf16)a[3];
+    r[4] = (__bf16)b[0]; r[5] = (__bf16)b[1]; r[6] = (__bf16)b[2]; r[7] = (__bf16)b[3];
+    return r;
+}
+
+__device__ __forceinline__ floatx4 gelu4(floatx4 z)
+{
+    floatx4 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[i] = gelu(z[i]);
+    return h;
+}
+
+template <typename Rows>
+__global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restrict__ img)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t s_img[kImgBytes];
+    for (int i = threadIdx.x; i < kImgBytes / 16; i += 256)
+        reinterpret_cast<uint4*>(s_img)[i] = reinterpret_cast<const uint4*>(img)[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int64_t n_tiles = (rows.count() + 15) / 16;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += nwaves) {
+        const int64_t row = tile * 16 + r;
+        float f[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) f[k] = 0.f;
+        const bool ok = rows.features(row, f);
+        bf16x8 xb;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = g == 0 ? f[j] : (g == 1 && j < 7 ? f[8 + j] : 0.f);
+            xb[j] = (__bf16)(ok ? v : 0.f);
+        }
+        // layer 1
+        floatx4 h[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB1 + 4 * (16 * t + 4 * g));
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + kImgW1 + (16 * t + r) * kRowW1 + 16 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb, acc, 0, 0, 0);
+            h[t] = gelu4(acc);
+        }
+        // layer 2
+        bf16x8 hb[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) hb[kb] = pack8(h[2 * kb], h[2 * kb + 1]);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB2 + 4 * (16 * t + 4 * g));
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8*>(s_img + kImgW2 + (16 * t + r) * kRowW2 + 64 * kb + 16 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
+            }
+            h[t] = gelu4(acc);
+        }
+        // layer 3 (rows 0, 1 of the 16-row weight tile are the outputs)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) hb[kb] = pack8(h[2 * kb], h[2 * kb + 1]);
+        floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB3 + 16 * g);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + kImgW3 + r * kRowW2 + 64 * kb + 16 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
+        }
+        if (g == 0) rows.write(row, acc[0], acc[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Candidates by sphere bounds.  Piece s lies in the sphere of radius r_s
+// (largest control-point distance from its box centre c_s, plus the piece's
+// deviation bound tol_eff) around c_s, so for the query q
+//     |q - c_s| - r_s  <=  dist(q, piece s)  <=  |q - c_s| + r_s.
+// One workgroup per tile of kQueriesPerTile queries of one curve, 8 lanes per
+// query striding over the curve's pieces staged in LDS.  Pass 1: the K
+// smallest lower bounds (ties to the lower index) and UB = min upper bound;
+// pass 2: [lo, hi] = index range of the pieces whose lower bound is at most
+// UB + margin(UB).  Bounds carry a rounding allowance of 1e-6 (|q'| + diag).
+// ---------------------------------------------------------------------------
+constexpr int kBoxSub = 8;
+constexpr int kBoxThreads = kQueriesPerTile * kBoxSub;
+constexpr int kBoxChunk = 1024;
+constexpr int kXcds = 8;
+static_assert(kBoxThreads == 256, "box kernel: 32 queries x 8 lanes");
+
+struct BoxOut {
+    int32_t* cand;  // [n][kK] global piece index (-1: fewer pieces)
+    int32_t* lohi;  // [n][2]
+    float* ub;      // [n]
+};
+
+// float -> uint32 with the same order (negative values included)
+__device__ __forceinline__ uint32_t ord_key(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord_val(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+__device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b)
+{
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+__device__ __forceinline__ float tie_margin(float d, const DCurve& cv, float tie_rel)
+{
+    return 2.f * (float)cv.tol_eff + 4e-6f * (d + (float)cv.diag) + tie_rel * (float)cv.diag;
+}
+
+__global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* __restrict__ tile_off,
+                                                     const int32_t* __restrict__ q_off,
+                                                     const int32_t* __restrict__ perm, const double* __restrict__ qxyz,
+                                                     float tie_rel, BoxOut out)
+{
+    __shared__ float4 s_sph[kBoxChunk];
+    const int n_tiles = tile_off[G.n_curves];
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    const int slot = (int)(blockIdx.x / kXcds);
+    const int tile = (int)(blockIdx.x % kXcds) * per + slot;
+    if (slot >= per || tile >= n_tiles) return;
+    int lo_c = 0, hi_c = G.n_curves;  // tile_off[lo_c] <= tile < tile_off[hi_c]
+    while (hi_c - lo_c > 1) {
+        const int mid = (lo_c + hi_c) >> 1;
+        if (tile_off[mid] <= tile) lo_c = mid; else hi_c = mid;
+    }
+    const int c = lo_c;
+    const DCurve cv = G.curves[c];
+    const int qs = threadIdx.x / kBoxSub, sub = threadIdx.x % kBoxSub;
+    const int64_t j = (int64_t)q_off[c] + (int64_t)(tile - tile_off[c]) * kQueriesPerTile + qs;
+    const bool active = j < q_off[c + 1];
+    float ql[3] = {0.f, 0.f, 0.f};
+    if (active) {
+        const int32_t qi = perm[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - cv.origin[k]);
+    }
+    const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)cv.diag);
+    const float tol = (float)(cv.tol_eff * 1.000001);
+    uint64_t key[kK];
+#pragma unroll
+    for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+    float ub = INFINITY, thr = 0.f;
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int c0 = 0; c0 < cv.n_seg; c0 += kBoxChunk) {
+            const int cn = min(kBoxChunk, cv.n_seg - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < cn; i += kBoxThreads) {
+                const int64_t s = cv.seg_off + c0 + i;
+                const float* lp = G.lcp + s * 12;
+                const float* ax = G.aux + s * 8;
+                float r2 = 0.f;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    r2 = fmaxf(r2, lp[3 * p] * lp[3 * p] + lp[3 * p + 1] * lp[3 * p + 1] + lp[3 * p + 2] * lp[3 * p + 2]);
+                s_sph[i] = make_float4(ax[AUX_CX], ax[AUX_CY], ax[AUX_CZ], sqrtf(r2) * 1.000002f + tol);
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int i = sub; i < cn; i += kBoxSub) {
+                const float4 p = s_sph[i];
+                const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                const float re = p.w + eps;
+                if (pass == 0) {
+                    const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
+                    const float tu = ub - re;
+                    const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
+                    const bool cu = tu > 0.f && d2 < tu * tu;
+                    if (c4 || cu) {
+                        const float d = sqrtf(d2);
+                        ub = fminf(ub, d + re);
+                        uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
+#pragma unroll
+                        for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
+                    }
+                } else {
+                    const float tt = thr + re;
+                    if (tt >= 0.f && d2 <= tt * tt) {
+                        lo = min(lo, c0 + i);
+                        hi = max(hi, c0 + i);
+                    }
+                }
+            }
+        }
+        if (pass == 0) {
+            // merge the 8 lanes' sorted lists: exchange, keep the smaller half (bitonic)
+#pragma unroll
+            for (int off = 1; off < kBoxSub; off <<= 1) {
+                uint64_t o[kK];
+#pragma unroll
+                for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
+#pragma unroll
+                for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
+                cswap(key[0], key[2]);
+                cswap(key[1], key[3]);
+                cswap(key[0], key[1]);
+                cswap(key[2], key[3]);
+                ub = fminf(ub, __shfl_xor(ub, off, 64));
+            }
+            thr = ub + tie_margin(ub, cv, tie_rel);
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kBoxSub; off <<= 1) {
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    if (active && sub == 0) {
+#pragma unroll
+        for (int k = 0; k < kK; ++k)
+            out.cand[j * kK + k] = key[k] == ~0ull ? -1 : (int32_t)(cv.seg_off + (uint32_t)key[k]);
+        out.lohi[2 * j] = (int32_t)cv.seg_off + (hi >= 0 ? lo : 0);
+        out.lohi[2 * j + 1] = (int32_t)cv.seg_off + (hi >= 0 ? hi : cv.n_seg - 1);
+        out.ub[j] = ub;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Certificate helpers
+// ---------------------------------------------------------------------------
+// Piece s relative to the query in its local frame: R_i = P_i - q (Bernstein
+// control points of C - q), D_j = 3 (P_{j+1} - P_j) (of C').
+struct BezQ {
+    float R[4][3];
+    float D[3][3];
+    float qn;   // |q - c_s|
+    float rad;  // max |P_i - c_s|
+};
+
+__device__ __forceinline__ void load_bezq(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, BezQ& b)
+{
+    const float* lp = G.lcp + s * 12;
+    const float* ax = G.aux + s * 8;
+    const float ql[3] = {(float)(q[0] - (cv.origin[0] + (double)ax[AUX_CX])),
+                         (float)(q[1] - (cv.origin[1] + (double)ax[AUX_CY])),
+                         (float)(q[2] - (cv.origin[2] + (double)ax[AUX_CZ]))};
+    float P[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) P[i] = lp[i];
+    float r2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r2 = fmaxf(r2, P[3 * i] * P[3 * i] + P[3 * i + 1] * P[3 * i + 1] + P[3 * i + 2] * P[3 * i + 2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.R[i][c] = P[3 * i + c] - ql[c];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b.D[i][c] = 3.f * (P[3 * (i + 1) + c] - P[3 * i + c]);
+    b.qn = sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]);
+    b.rad = sqrtf(r2);
+}
+
+// Sphere lower bound of the distance from q to the exact curve over piece s.
+__device__ __forceinline__ float sphere_lb(const BezQ& b, const DCurve& cv)
+{
+    return b.qn * (1.f - 1e-6f) - b.rad * (1.f + 1e-6f) - (float)(cv.tol_eff * 1.000001);
+}
+
+__device__ __forceinline__ float dot3f(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ __forceinline__ float norm3f(const float* a) { return sqrtf(dot3f(a, a)); }
+
+// Bernstein coefficients beta_k (k = 0..5) of f(u) = (C(u) - q).C'(u) and a
+// bound e_k on their rounding: B^3_i B^2_j = C(3,i) C(2,j) / C(5,i+j) B^5_{i+j}.
+// Returns the sign class: +1 every beta_k > e_k, -1 every beta_k < -e_k,
+// 2 one sign change from clearly negative to clearly positive, 0 otherwise.
+// relax0 / relax5 let beta_0 / beta_5 sit within its rounding band (a piece
+// adjacent to the chosen one shares that endpoint with it).
+__device__ __forceinline__ int fprime_class(const BezQ& b, bool relax0, bool relax5)
+{
+    float dd[4][3], aa[4][3];
+    float nR[4], nD[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nR[i] = norm3f(b.R[i]) + b.qn;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) nD[j] = norm3f(b.D[j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            dd[i][j] = dot3f(b.R[i], b.D[j]);
+            aa[i][j] = nR[i] * nD[j];
+        }
+    float be[6], er[6];
+    be[0] = dd[0][0];
+    be[1] = 0.6f * dd[1][0] + 0.4f * dd[0][1];
+    be[2] = 0.3f * dd[2][0] + 0.6f * dd[1][1] + 0.1f * dd[0][2];
+    be[3] = 0.1f * dd[3][0] + 0.6f * dd[2][1] + 0.3f * dd[1][2];
+    be[4] = 0.4f * dd[3][1] + 0.6f * dd[2][2];
+    be[5] = dd[3][2];
+    er[0] = aa[0][0];
+    er[1] = 0.6f * aa[1][0] + 0.4f * aa[0][1];
+    er[2] = 0.3f * aa[2][0] + 0.6f * aa[1][1] + 0.1f * aa[0][2];
+    er[3] = 0.1f * aa[3][0] + 0.6f * aa[2][1] + 0.3f * aa[1][2];
+    er[4] = 0.4f * aa[3][1] + 0.6f * aa[2][2];
+    er[5] = aa[3][2];
+    bool pos = true, neg = true, amb = false;
+    int changes = 0, prev = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float e = 1e-6f * er[k];
+        const bool relaxed = (k == 0 && relax0) || (k == 5 && relax5);
+        const int sg = be[k] > e ? 1 : (be[k] < -e ? -1 : 0);
+        pos = pos && (sg > 0 || (relaxed && be[k] >= -e));
+        neg = neg && (sg < 0 || (relaxed && be[k] <= e));
+        if (sg == 0) amb = true;
+        if (sg != 0) {
+            if (prev != 0 && sg != prev) ++changes;
+            prev = sg;
+        }
+    }
+    if (pos) return 1;
+    if (neg) return -1;
+    if (!amb && changes == 1 && be[0] < 0.f) return 2;
+    return 0;
+}
+
+__device__ __forceinline__ float end_dist(const BezQ& b, int i) { return norm3f(b.R[i]); }
+
+// ---------------------------------------------------------------------------
+// Seed + certificate (Seeded) or sphere-pruned refine (!Seeded): one thread per
+// sorted query position.
+// ---------------------------------------------------------------------------
+template <bool Seeded>
+__global__ __launch_bounds__(128) void k_decide(DevGeom G, const int32_t* __restrict__ cid,
+                                                const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
+                                                const int32_t* __restrict__ perm, BoxOut box,
+                                                const float2* __restrict__ scores, float tie_rel, int32_t invert,
+                                                int32_t* __restrict__ fb_list, int32_t* __restrict__ fb_count, Outs o)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[G.n_curves]) return;
+    const int32_t qi = perm[j];
+    const DCurve cv = G.curves[cid[qi]];
+    const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    const int64_t lo = box.lohi[2 * j], hi = box.lohi[2 * j + 1];
+    const float ubx = box.ub[j];
+    const int64_t s_first = cv.seg_off, s_last = cv.seg_off + cv.n_seg - 1;
+    Cand b1 = empty_cand(cv), b2 = b1;
+    if (!Seeded) {
+        const float thr = ubx + tie_margin(ubx, cv, tie_rel);
+        for (int64_t s = lo; s <= hi; ++s) {
+            BezQ b;
+            load_bezq(G, cv, s, q, b);
+            if (sphere_lb(b, cv) <= thr) consider<float>(G, cv, s, q, b1, b2);
+        }
+        finish<float>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
+        return;
+    }
+    // 1. best-scored candidate
+    int64_t s = -1;
+    float best = -INFINITY, u0 = 0.5f;
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+        const int32_t sk = box.cand[j * kK + k];
+        const float2 y = scores[j * kK + k];
+        if (sk >= 0 && (s < 0 || y.y > best)) { s = sk; best = y.y; u0 = y.x; }
+    }
+    bool ok = s >= 0;
+    u0 = fminf(fmaxf(u0, 0.f), 1.f);
+    // 2. walk to the piece holding the minimum, then its certified minimum
+    BezQ b;
+    int cls = 0;
+    for (int hop = 0; ok; ++hop) {
+        load_bezq(G, cv, s, q, b);
+        cls = fprime_class(b, false, false);
+        if (cls == 1 && s > s_first) {
+            if (hop == 4) ok = false;
+            else { --s; u0 = 1.f; }
+        } else if (cls == -1 && s < s_last) {
+            if (hop == 4) ok = false;
+            else { ++s; u0 = 0.f; }
+        } else {
+            break;
+        }
+    }
+    float u = 0.f, d2 = INFINITY, kap = 1.f;
+    Cubic<float> C;
+    if (ok) {
+        load_cubic(G, cv, s, q, C);
+        if (cls == 1) { u = 0.f; d2 = C.dist2(0.f); }
+        else if (cls == -1) { u = 1.f; d2 = C.dist2(1.f); }
+        else {
+            if (cls == 2) {
+                newton_min(C, 0.f, 1.f, u0, u, d2, kap);
+                // orthogonality residual of the Newton point: cosine <= 1e-4, or coincidence
+                V3<float> r, d1, dd2;
+                C.eval(u, r, d1, dd2);
+                const float rn = sqrtf(dot(r, r)), sp = sqrtf(dot(d1, d1));
+                const bool conv = u > 0.f && u < 1.f &&
+                                  (fabsf(dot(r, d1)) <= 1e-4f * rn * sp || rn <= 1e-7f * (float)cv.diag);
+                if (!conv) cls = 0;
+            }
+            if (cls == 0) piece_min(C, u, d2, kap);
+        }
+    }
+    const float ds = sqrtf(d2);
+    if (ok && !(ds <= ubx)) ok = false;  // a piece's sphere holds a closer point
+    // 3. certificate over [lo, hi]: every other piece whose sphere reaches lim has a
+    // certified minimum above lim; a monotone piece's minimum is an endpoint
+    // distance, any other piece's is its certified piece minimum.  The
+    // neighbour whose minimum is the endpoint it shares with the chosen piece is
+    // kept as the runner-up for the tie test instead.
+    const float lim = ds + tie_margin(ds, cv, tie_rel);
+    for (int64_t s2 = lo; ok && s2 <= hi; ++s2) {
+        if (s2 == s) continue;
+        BezQ n;
+        load_bezq(G, cv, s2, q, n);
+        if (sphere_lb(n, cv) > lim) continue;
+        const bool adj_r = s2 == s + 1, adj_l = s2 == s - 1;
+        const int c2 = fprime_class(n, adj_r, adj_l);
+        float mn;
+        int end = -1;
+        if (c2 == 1) { mn = end_dist(n, 0); end = 0; }
+        else if (c2 == -1) { mn = end_dist(n, 3); end = 3; }
+        else {
+            Cubic<float> C2;
+            load_cubic(G, cv, s2, q, C2);
+            float uu, dd, kk;
+            piece_min(C2, uu, dd, kk);
+            mn = sqrtf(dd) * (1.f - 8e-6f);
+        }
+        if (mn > lim) continue;
+        if ((adj_r && end == 0) || (adj_l && end == 3)) {
+            const Cand e = make_cand(G, s2, end == 0 ? 0.0 : 1.0, (double)mn * mn, 1.0, 0.0);
+            if (e.d2 < b2.d2) b2 = e;
+            continue;
+        }
+        ok = false;
+    }
+    if (!ok) {
+        fb_list[atomicAdd(fb_count, 1)] = qi;
+        return;
+    }
+    const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
+    b1 = make_cand(G, s, (double)u, (double)d2, (double)kap, param_error(C, u, kap, ta, tb));
+    finish<float>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
+}
+
+// Fallback plumbing: gather the failed queries, scatter their answers back.
+__global__ void k_fb_gather(const int32_t* __restrict__ count, int64_t n, const int32_t* __restrict__ list,
+                            const int32_t* __restrict__ cid, const double* __restrict__ q, int32_t* __restrict__ cid_c,
+                            double* __restrict__ q_c)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= min(n, (int64_t)*count)) return;
+    const int32_t qi = list[i];
+    cid_c[i] = cid[qi];
+    q_c[3 * i] = q[3 * (int64_t)qi];
+    q_c[3 * i + 1] = q[3 * (int64_t)qi + 1];
+    q_c[3 * i + 2] = q[3 * (int64_t)qi + 2];
+}
+
+__global__ void k_fb_scatter(const int32_t* __restrict__ count, int64_t n, const int32_t* __restrict__ list, Outs c,
+                             Outs o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= min(n, (int64_t)*count)) return;
+    const int32_t qi = list[i];
+    o.t[qi] = c.t[i];
+    o.d[qi] = c.d[i];
+    o.s[qi] = c.s[i];
+    o.f[qi] = c.f[i] | MREP_F_NN_FALLBACK;
+}
+
+// Training-data export: candidates and features in the caller's query order.
+__global__ void k_feat_write(DevGeom G, const int32_t* __restrict__ cid, const double* __restrict__ qxyz,
+                             const int32_t* __restrict__ q_off, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ cand, int32_t* __restrict__ seg_out, float* __restrict__ x_out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[G.n_curves]) return;
+    const int32_t qi = perm[j];
+    const DCurve cv = G.curves[cid[qi]];
+    const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    for (int k = 0; k < kK; ++k) {
+        const int32_t s = cand[j * kK + k];
+        float f[kIn];
+        for (int i = 0; i < kIn; ++i) f[i] = 0.f;
+        if (s >= 0) pair_features(G, cv, s, q, f);
+        seg_out[(int64_t)qi * kK + k] = s >= 0 ? (int32_t)(s - cv.seg_off) : -1;
+        for (int i = 0; i < kIn; ++i) x_out[((int64_t)qi * kK + k) * kIn + i] = f[i];
+    }
+}
+
+__global__ void k_fill_feat(int64_t n, int32_t* __restrict__ seg_out, float* __restrict__ x_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kK) return;
+    seg_out[i] = -1;
+    for (int k = 0; k < kIn; ++k) x_out[i * kIn + k] = 0.f;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Workspace of the seeded call.
+struct SeedWork {
+    int32_t *hist, *q_off, *tile_off, *perm;
+    BoxOut box;
+    float2* scores;
+    int32_t *fb_list, *fb_count;
+    int32_t* cid_c;
+    double* q_c;
+    Outs oc;
+    void* core;
+};
+
+int64_t seed_layout(int64_t nc, int64_t n, int kc, char* base, SeedWork* w)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off = a256(off + bytes);
+        return o;
+    };
+    const int64_t oh = take(4 * (nc + 2)), oq = take(4 * (nc + 1)), ot = take(4 * (nc + 1)), op = take(4 * n);
+    const int64_t oc = take(4 * n * kK), olh = take(8 * n), oub = take(4 * n), osc = take(8 * n * kK);
+    const int64_t ofl = take(4 * n), ofc = take(4), ocid = take(4 * n), oqc = take(24 * n);
+    const int64_t ott = take(8 * n), odd = take(8 * n), oss = take(4 * n), off_ = take(4 * n);
+    const int64_t ocore = take(project_ws_bytes(nc, n, kc));
+    if (w) {
+        w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
+        w->perm = (int32_t*)(base + op);
+        w->box.cand = (int32_t*)(base + oc); w->box.lohi = (int32_t*)(base + olh); w->box.ub = (float*)(base + oub);
+        w->scores = (float2*)(base + osc);
+        w->fb_list = (int32_t*)(base + ofl); w->fb_count = (int32_t*)(base + ofc);
+        w->cid_c = (int32_t*)(base + ocid); w->q_c = (double*)(base + oqc);
+        w->oc = Outs{(double*)(base + ott), (double*)(base + odd), (int32_t*)(base + oss), (uint32_t*)(base + off_)};
+        w->core = base + ocore;
+    }
+    return off;
+}
+
+}  // namespace
+
+struct mrep_nn {
+    uint8_t* base = nullptr;  // device: params | m | v | grad | image
+    int64_t step = 0;
+    float* params() const { return (float*)base; }
+    float* m() const { return (float*)(base + kParamBytes); }
+    float* v() const { return (float*)(base + 2 * kParamBytes); }
+    float* grad() const { return (float*)(base + 3 * kParamBytes); }
+    uint8_t* img() const { return base + 4 * kParamBytes; }
+};
+
+static int pack_image(const mrep_nn* nn, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(kImgBytes / 2)), dim3(256), 0, st, (const float*)nn->params(), nn->img());
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+// grouping + sphere candidates shared by the seeded call and the feature export
+static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz, float tie_rel,
+                      SeedWork& w, const Outs& o, hipStream_t st)
+{
+    const int64_t nc = geom->g.L.n_curves;
+    NN_HIP(launch_grouping(nc, n, nullptr, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
+    const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
+    hipLaunchKernelGGL(k_box, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
+                       (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
+                       w.box);
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+extern "C" {
+
+int32_t mrep_nn_param_count(void) { return (int32_t)kNParams; }
+
+int32_t mrep_nn_bytes(int64_t batch, int64_t* state_bytes, int64_t* work_bytes)
+{
+    if (batch < 0 || (!state_bytes && !work_bytes)) {
+        set_error("mrep_nn_bytes: negative batch or no output");
+        return MREP_E_INVALID_ARG;
+    }
+    if (state_bytes) *state_bytes = kStateBytes;
+    if (work_bytes) *work_bytes = train_layout(batch, nullptr, nullptr);
+    return MREP_OK;
+}
+
+int32_t mrep_nn_bind(void* dev_state, int64_t bytes, mrep_nn** out)
+{
+    if (!dev_state || !out) {
+        set_error("mrep_nn_bind: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (bytes < kStateBytes) {
+        set_error("mrep_nn_bind: buffer smaller than mrep_nn_bytes' state size");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)dev_state & 255) != 0) {
+        set_error("mrep_nn_bind: buffer not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    mrep_nn* n = new mrep_nn();
+    n->base = (uint8_t*)dev_state;
+    *out = n;
+    return MREP_OK;
+}
+
+void mrep_nn_release(mrep_nn* nn) { delete nn; }
+
+int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stream)
+{
+    if (!nn || !host || n != kNParams) {
+        set_error("mrep_nn_set_params: null pointer or wrong parameter count");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> zero((size_t)kNParams, 0.f);
+    NN_HIP(hipMemcpyAsync(nn->params(), host, 4 * kNParams, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->m(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->v(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->grad(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
+    // pageable host sources: complete before returning
+    NN_HIP(hipStreamSynchronize(st));
+    nn->step = 0;
+    return MREP_OK;
+}
+
+int32_t mrep_nn_get_params(const mrep_nn* nn, float* host, int64_t n, void* stream)
+{
+    if (!nn || !host || n != kNParams) {
+        set_error("mrep_nn_get_params: null pointer or wrong parameter count");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    NN_HIP(hipMemcpyAsync(host, nn->params(), 4 * kNParams, hipMemcpyDeviceToHost, st));
+    NN_HIP(hipStreamSynchronize(st));
+    return MREP_OK;
+}
+
+int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream)
+{
+    if (!nn) {
+        set_error("mrep_nn_init: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    // weights uniform in +-1/sqrt(fan_in), biases zero
+    std::vector<float> p((size_t)kNParams, 0.f);
+    uint64_t s = seed;
+    auto fill = [&](int64_t off, int64_t count, int fan_in) {
+        const double a = 1.0 / sqrt((double)fan_in);
+        for (int64_t i = 0; i < count; ++i) {
+            const double u = (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0);
+            p[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
+        }
+    };
+    fill(kOffW1, (int64_t)kH * kIn, kIn);
+    fill(kOffW2, (int64_t)kH * kH, kH);
+    fill(kOffW3, (int64_t)kOut * kH, kH);
+    return mrep_nn_set_params(nn, p.data(), kNParams, stream);
+}
+
+int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, void* work, int64_t work_bytes,
+                        void* stream)
+{
+    if (!nn || n < 0 || (n > 0 && (!x || !y || !work))) {
+        set_error("mrep_nn_forward: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    if (n > INT32_MAX / kH) {
+        set_error("mrep_nn_forward: n too large for one call");
+        return MREP_E_INVALID_ARG;
+    }
+    TrainWork w;
+    if (work_bytes < train_layout(n, (char*)work, &w)) {
+        set_error("mrep_nn_forward: work buffer smaller than mrep_nn_bytes(n)");
+        return MREP_E_SMALL_BUFFER;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = forward(nn->params(), n, x, w, st);
+    if (rc) return rc;
+    NN_HIP(hipMemcpyAsync(y, w.Y, 4 * n * kOut, hipMemcpyDeviceToDevice, st));
+    return MREP_OK;
+}
+
+int32_t mrep_nn_infer(const mrep_nn* nn, int64_t n, const float* x, float* y, void* stream)
+{
+    if (!nn || n < 0 || (n > 0 && (!x || !y))) {
+        set_error("mrep_nn_infer: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = pack_image(nn, st);
+    if (rc) return rc;
+    RowsFromMemory rows{n, x, y};
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 63) / 64, 2048);
+    hipLaunchKernelGGL(k_mlp<RowsFromMemory>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* u_star, const float* accept,
+                           int64_t batch, const int32_t* rows, float lr, float* loss_out, float* grad_out,
+                           void* work, int64_t work_bytes, void* stream)
+{
+    if (!nn || batch <= 0 || !x || !u_star || !accept || !work || (!rows && n_rows < batch)) {
+        set_error("mrep_nn_train_step: null pointer or empty batch");
+        return MREP_E_INVALID_ARG;
+    }
+    if (batch > INT32_MAX / kH || !(lr >= 0.f)) {
+        set_error("mrep_nn_train_step: batch too large or negative learning rate");
+        return MREP_E_INVALID_ARG;
+    }
+    TrainWork w;
+    if (work_bytes < train_layout(batch, (char*)work, &w)) {
+        set_error("mrep_nn_train_step: work buffer smaller than mrep_nn_bytes(batch)");
+        return MREP_E_SMALL_BUFFER;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const float *X = x, *Us = u_star, *A = accept;
+    if (rows) {
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(batch)), dim3(256), 0, st, batch, rows, n_rows, x, u_star,
+                           accept, w.Xb, w.Usb, w.Ab);
+        X = w.Xb; Us = w.Usb; A = w.Ab;
+    }
+    int rc = forward(nn->params(), batch, X, w, st);
+    if (rc) return rc;
+    rc = backward(nn->params(), batch, X, Us, A, w, nn->grad(), loss_out, st);
+    if (rc) return rc;
+    if (grad_out) NN_HIP(hipMemcpyAsync(grad_out, nn->grad(), 4 * kNParams, hipMemcpyDeviceToDevice, st));
+    if (lr > 0.f) {
+        nn->step += 1;
+        const float c1 = (float)(1.0 - pow(0.9, (double)nn->step)), c2 = (float)(1.0 - pow(0.999, (double)nn->step));
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNParams)), dim3(256), 0, st, kNParams, nn->params(), nn->m(),
+                           nn->v(), (const float*)nn->grad(), lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+        NN_HIP(hipGetLastError());
+    }
+    return MREP_OK;
+}
+
+int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
+{
+    if (!geom || !bytes || n < 0) {
+        set_error("mrep_seeded_workspace_bytes: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    *bytes = seed_layout(geom->g.L.n_curves, n, opts->max_candidates, nullptr, nullptr);
+    return MREP_OK;
+}
+
+int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz,
+                         int32_t* seg_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream)
+{
+    if (!geom || n < 0) {
+        set_error("mrep_nn_features: null geometry or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    if (!curve_id || !q_xyz || !seg_out || !x_out || !workspace) {
+        set_error("mrep_nn_features: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n * kK >= (int64_t)INT32_MAX || geom->g.L.n_curves == 0) {
+        set_error("mrep_nn_features: n * 4 must be < 2^31 and the geometry non-empty");
+        return MREP_E_INVALID_ARG;
+    }
+    const int64_t nc = geom->g.L.n_curves;
+    SeedWork w;
+    if (ws_bytes < seed_layout(nc, n, 1, (char*)workspace, &w)) {
+        set_error("mrep_nn_features: workspace smaller than mrep_seeded_workspace_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("mrep_nn_features: workspace not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_fill_feat, dim3(blocks_for(n * kK)), dim3(256), 0, st, n, seg_out, x_out);
+    // grouping writes nothing for invalid ids when the outputs are null
+    const Outs none{nullptr, nullptr, nullptr, nullptr};
+    int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_feat_write, dim3(blocks_for(n, 128)), dim3(128), 0, st, dev_view(geom->g), curve_id, q_xyz,
+                       (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.box.cand, seg_out, x_out);
+    NN_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                                   const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
+                                   double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream)
+{
+    if (!geom || n < 0) {
+        set_error("mrep_project_curves_seeded: null geometry or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (opts->precision != MREP_PREC_BF16) {
+        set_error("mrep_project_curves_seeded: the seeded path runs in the BF16 mode (FP32 refine)");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    if (n * (int64_t)std::max(opts->max_candidates, kK) >= (int64_t)INT32_MAX) {
+        set_error("mrep_project_curves_seeded: n * max(max_candidates, 4) must be < 2^31");
+        return MREP_E_INVALID_ARG;
+    }
+    if (!curve_id || !q_xyz || !workspace || !t_out || !dist_out || !seg_out || !flags_out) {
+        set_error("mrep_project_curves_seeded: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    const int64_t nc = geom->g.L.n_curves;
+    if (nc == 0) {
+        set_error("mrep_project_curves_seeded: geometry has no curves");
+        return MREP_E_INVALID_ARG;
+    }
+    SeedWork w;
+    if (ws_bytes < seed_layout(nc, n, opts->max_candidates, (char*)workspace, &w)) {
+        set_error("mrep_project_curves_seeded: workspace smaller than mrep_seeded_workspace_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("mrep_project_curves_seeded: workspace not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const bool timed = (opts->flags & MREP_OPT_TIME_STAGES) != 0;
+    if (timed && (rc = stage_begin(st))) return rc;
+    const Outs o{t_out, dist_out, seg_out, flags_out};
+    const DevGeom G = dev_view(geom->g);
+    const float tie = (float)opts->tie_rel;
+    rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, w.fb_count, 1);
+    if (timed && (rc = stage_mark(1, st))) return rc;
+    if (nn) {
+        rc = pack_image(nn, st);
+        if (rc) return rc;
+        RowsFromCandidates rows{G, curve_id, q_xyz, w.q_off, w.perm, w.box.cand, w.scores};
+        const unsigned nb = (unsigned)std::min<int64_t>((n * kK + 63) / 64, 2048);
+        hipLaunchKernelGGL(k_mlp<RowsFromCandidates>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
+        NN_HIP(hipGetLastError());
+    }
+    if (timed && (rc = stage_mark(2, st))) return rc;
+    if (nn)
+        hipLaunchKernelGGL(k_decide<true>, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
+                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
+                           (int32_t)0, w.fb_list, w.fb_count, o);
+    else
+        hipLaunchKernelGGL(k_decide<false>, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
+                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
+                           (int32_t)0, w.fb_list, w.fb_count, o);
+    NN_HIP(hipGetLastError());
+    if (timed && (rc = stage_mark(3, st))) return rc;
+    if (nn) {
+        hipLaunchKernelGGL(k_fb_gather, dim3(blocks_for(n)), dim3(256), 0, st, (const int32_t*)w.fb_count, n,
+                           (const int32_t*)w.fb_list, curve_id, q_xyz, w.cid_c, w.q_c);
+        rc = project_core(geom->g, opts, n, w.fb_count, w.cid_c, w.q_c, w.core, w.oc, st, 0, false, 0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_fb_scatter, dim3(blocks_for(n)), dim3(256), 0, st, (const int32_t*)w.fb_count, n,
+                           (const int32_t*)w.fb_list, w.oc, o);
+        NN_HIP(hipGetLastError());
+    }
+    if (timed) {
+        if ((rc = stage_mark(4, st))) return rc;
+        stage_end(4);
+    }
+    return MREP_OK;
+}
+
+}  // extern "C"

@@ -25,10 +25,12 @@ _lib = C.CDLL(LIB_PATH)
 # status codes and flags (mirror include/mrep.h)
 OK, E_INVALID_ARG, E_BAD_DEGREE, E_BAD_KNOTS, E_TOL, E_SMALL_BUFFER, E_HIP, E_NO_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 F_POLISHED, F_NEAR_TIE, F_ILL_COND, F_ENDPOINT, F_OFFCURVE, F_FULLSCAN, F_BAD_ID = 1, 2, 4, 8, 16, 32, 64
+F_NN_FALLBACK = 128
 PREC_FP64, PREC_BF16 = 0, 3
 OPT_TIME_STAGES = 1
-N_STAGES = 3
+N_STAGES = 4
 MAX_DEGREE = 15
+NN_IN, NN_HIDDEN, NN_OUT, NN_K = 15, 128, 2, 4
 
 _vp, _i32, _i64, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _pi32, _pi64, _pd = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
@@ -67,6 +69,21 @@ _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
 _subdiv = _sig("mrep_subdivision_matrix", _i32, _i32, _dbl, _pd)
 _gram = _sig("mrep_gram_matrix", _i32, _i32, _i32, _pd)
 _stage_times = _sig("mrep_last_stage_times", _i32, _pd, _i32)
+_nn_param_count = _sig("mrep_nn_param_count", _i32)
+_nn_bytes = _sig("mrep_nn_bytes", _i32, _i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64))
+_nn_bind = _sig("mrep_nn_bind", _i32, _vp, _i64, C.POINTER(_vp))
+_nn_release = _sig("mrep_nn_release", None, _vp)
+_nn_init = _sig("mrep_nn_init", _i32, _vp, C.c_uint64, _vp)
+_nn_set = _sig("mrep_nn_set_params", _i32, _vp, C.POINTER(C.c_float), _i64, _vp)
+_nn_get = _sig("mrep_nn_get_params", _i32, _vp, C.POINTER(C.c_float), _i64, _vp)
+_nn_forward = _sig("mrep_nn_forward", _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp)
+_nn_infer = _sig("mrep_nn_infer", _i32, _vp, _i64, _vp, _vp, _vp)
+_nn_train = _sig("mrep_nn_train_step", _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp, C.c_float, _vp, _vp, _vp, _i64,
+                 _vp)
+_seed_ws = _sig("mrep_seeded_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POINTER(C.c_int64))
+_nn_features = _sig("mrep_nn_features", _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp)
+_project_seeded = _sig("mrep_project_curves_seeded", _i32, _vp, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp,
+                       _vp, _vp, _vp, _vp)
 _last_error = _sig("mrep_last_error", C.c_char_p)
 _abi = _sig("mrep_abi_version", _i32)
 
@@ -74,7 +91,10 @@ _abi = _sig("mrep_abi_version", _i32)
 EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_plan_free", "mrep_upload",
            "mrep_geom_release", "mrep_opts_default", "mrep_workspace_bytes", "mrep_project_curves",
            "mrep_invert_curves", "mrep_eval_curves", "mrep_bernstein_matrix", "mrep_subdivision_matrix",
-           "mrep_gram_matrix", "mrep_last_stage_times", "mrep_last_error", "mrep_abi_version"]
+           "mrep_gram_matrix", "mrep_last_stage_times", "mrep_last_error", "mrep_abi_version",
+           "mrep_nn_param_count", "mrep_nn_bytes", "mrep_nn_bind", "mrep_nn_release", "mrep_nn_init",
+           "mrep_nn_set_params", "mrep_nn_get_params", "mrep_nn_forward", "mrep_nn_infer", "mrep_nn_train_step",
+           "mrep_seeded_workspace_bytes", "mrep_nn_features", "mrep_project_curves_seeded"]
 
 
 class MrepError(RuntimeError):
@@ -188,10 +208,15 @@ def default_opts(precision: str | int = "bf16", max_candidates: int = 16, tie_re
 
 
 def last_stage_times():
-    """[grouping, screen, refine] milliseconds of the last call made with time_stages=True on this thread."""
+    """Stage milliseconds of the last call made with time_stages=True on this thread.
+
+    mrep_project_curves: [grouping, screen, refine]; seeded call: [grouping + sphere candidates, network,
+    seed + certificate, fallback]."""
     out = np.zeros(N_STAGES)
-    _check(_stage_times(_p(out, C.c_double), N_STAGES), "mrep_last_stage_times")
-    return out
+    rc = _stage_times(_p(out, C.c_double), N_STAGES)
+    if rc <= 0:
+        raise MrepError(rc, "mrep_last_stage_times")
+    return out[:rc]
 
 
 def bernstein_matrix(p: int, inverse: bool = False) -> np.ndarray:
@@ -265,6 +290,61 @@ class Geometry:
                   _vp(stream)), "mrep_invert_curves" if invert else "mrep_project_curves")
         return t, d, s, f
 
+    def seeded_workspace_bytes(self, n: int, opts: Opts) -> int:
+        b = C.c_int64()
+        _check(_seed_ws(self._h, int(n), C.byref(opts), C.byref(b)), "mrep_seeded_workspace_bytes")
+        return int(b.value)
+
+    def _seed_workspace(self, n, opts, workspace):
+        import torch
+
+        need = self.seeded_workspace_bytes(n, opts)
+        if workspace is not None:
+            return workspace
+        if getattr(self, "_sws", None) is None or self._sws.numel() < need:
+            self._sws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.buf.device)
+        return self._sws
+
+    def project_seeded(self, q, curve_id, nn: "Network | None" = None, opts: Opts | None = None, workspace=None,
+                       out=None):
+        """Seeded projection (nn given) or sphere-pruned projection (nn None); same outputs as project()."""
+        import torch
+
+        if opts is None:
+            opts = default_opts()
+        assert q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and q.dim() == 2 and q.shape[1] == 3
+        assert curve_id.is_cuda and curve_id.dtype == torch.int32 and curve_id.is_contiguous()
+        n = q.shape[0]
+        assert curve_id.shape[0] == n
+        ws = self._seed_workspace(n, opts, workspace)
+        if out is None:
+            t = torch.empty(n, dtype=torch.float64, device=q.device)
+            d = torch.empty(n, dtype=torch.float64, device=q.device)
+            s = torch.empty(n, dtype=torch.int32, device=q.device)
+            f = torch.empty(n, dtype=torch.int32, device=q.device)
+        else:
+            t, d, s, f = out
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_project_seeded(self._h, nn._h if nn is not None else None, C.byref(opts), int(n),
+                               _vp(curve_id.data_ptr()), _vp(q.data_ptr()), _vp(ws.data_ptr()), int(ws.numel()),
+                               _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
+                               _vp(stream)), "mrep_project_curves_seeded")
+        return t, d, s, f
+
+    def features(self, q, curve_id, workspace=None):
+        """The network's candidate pieces seg[n, 4] (curve-local, -1 none) and inputs x[n, 4, 15]."""
+        import torch
+
+        n = q.shape[0]
+        opts = default_opts()
+        ws = self._seed_workspace(n, opts, workspace)
+        seg = torch.empty((n, NN_K), dtype=torch.int32, device=q.device)
+        x = torch.empty((n, NN_K, NN_IN), dtype=torch.float32, device=q.device)
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_nn_features(self._h, int(n), _vp(curve_id.data_ptr()), _vp(q.data_ptr()), _vp(seg.data_ptr()),
+                            _vp(x.data_ptr()), _vp(ws.data_ptr()), int(ws.numel()), _vp(stream)), "mrep_nn_features")
+        return seg, x
+
     def eval(self, curve_id, t):
         """C_{curve_id[i]}(t[i]) on the exact curve, FP64, device tensors in and out."""
         import torch
@@ -279,6 +359,99 @@ class Geometry:
     def close(self):
         if self._h:
             _geom_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------- learned seeding
+def nn_param_count() -> int:
+    return int(_nn_param_count())
+
+
+class Network:
+    """The seeding MLP's device state (parameters, Adam moments, gradient, weight image) in a torch buffer."""
+
+    def __init__(self, device=None, seed: int | None = 0):
+        import torch
+
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        sb = C.c_int64()
+        _check(_nn_bytes(0, C.byref(sb), None), "mrep_nn_bytes")
+        self.state = torch.empty(int(sb.value), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_nn_bind(_vp(self.state.data_ptr()), self.state.numel(), C.byref(h)), "mrep_nn_bind")
+        self._h = h
+        self._work = None
+        if seed is not None:
+            self.init(seed)
+
+    def _stream(self):
+        import torch
+
+        return _vp(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def init(self, seed: int):
+        _check(_nn_init(self._h, C.c_uint64(int(seed)), self._stream()), "mrep_nn_init")
+
+    def set_params(self, p):
+        p = _host(p, np.float32)
+        _check(_nn_set(self._h, _p(p, C.c_float), int(p.shape[0]), self._stream()), "mrep_nn_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(nn_param_count(), np.float32)
+        _check(_nn_get(self._h, _p(p, C.c_float), int(p.shape[0]), self._stream()), "mrep_nn_get_params")
+        return p
+
+    def _work_for(self, rows):
+        import torch
+
+        wb = C.c_int64()
+        _check(_nn_bytes(int(rows), None, C.byref(wb)), "mrep_nn_bytes")
+        if self._work is None or self._work.numel() < wb.value:
+            self._work = torch.empty(max(int(wb.value), 256), dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def forward(self, x):
+        """Training-form forward: y[n, 2] for x[n, 15] (float32, device)."""
+        import torch
+
+        n = x.shape[0]
+        y = torch.empty((n, NN_OUT), dtype=torch.float32, device=x.device)
+        w = self._work_for(n)
+        _check(_nn_forward(self._h, int(n), _vp(x.data_ptr()), _vp(y.data_ptr()), _vp(w.data_ptr()), int(w.numel()),
+                           self._stream()), "mrep_nn_forward")
+        return y
+
+    def infer(self, x):
+        """Fused-kernel forward: y[n, 2] for x[n, 15] (float32, device)."""
+        import torch
+
+        n = x.shape[0]
+        y = torch.empty((n, NN_OUT), dtype=torch.float32, device=x.device)
+        _check(_nn_infer(self._h, int(n), _vp(x.data_ptr()), _vp(y.data_ptr()), self._stream()), "mrep_nn_infer")
+        return y
+
+    def train_step(self, x, u_star, accept, rows=None, batch=None, lr: float = 1e-3, loss=None, grad=None):
+        """One step on the rows `rows` (int32 device, or the first `batch` rows); returns nothing (async).
+
+        loss: optional 1-element float32 device tensor receiving the batch loss; grad: optional device tensor of
+        nn_param_count() floats receiving the gradient."""
+        b = int(rows.shape[0]) if rows is not None else int(batch if batch is not None else x.shape[0])
+        w = self._work_for(b)
+        _check(_nn_train(self._h, int(x.shape[0]), _vp(x.data_ptr()), _vp(u_star.data_ptr()), _vp(accept.data_ptr()),
+                         b, _vp(rows.data_ptr()) if rows is not None else None, float(lr),
+                         _vp(loss.data_ptr()) if loss is not None else None,
+                         _vp(grad.data_ptr()) if grad is not None else None, _vp(w.data_ptr()), int(w.numel()),
+                         self._stream()), "mrep_nn_train_step")
+
+    def close(self):
+        if self._h:
+            _nn_release(self._h)
             self._h = None
 
     def __del__(self):

@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 1
+    assert mrep.abi_version() == 2
 
 
 def test_rebasement_matrix_matches_printed_T5():
@@ -171,3 +171,23 @@ def test_piece_cap_is_reported():
     with pytest.raises(mrep.MrepError) as ei:
         mrep.decompose_curves(_curveset(7, P, U), 1e-17)
     assert ei.value.code == mrep.E_TOL
+
+
+def test_seeding_network_sizes_and_host_errors():
+    """Parameter count equals the oracle network's; sizes and argument errors need no device."""
+    assert mrep.nn_param_count() == oracle.mlp_param_count() == 18818
+    sb, wb = C.c_int64(), C.c_int64()
+    assert mrep._nn_bytes(4096, C.byref(sb), C.byref(wb)) == mrep.OK
+    assert sb.value >= 4 * 4 * 18818 and sb.value % 256 == 0
+    assert wb.value >= 4096 * (4 * 128 + 15) * 4
+    assert mrep._nn_bytes(-1, C.byref(sb), None) == mrep.E_INVALID_ARG
+    assert mrep._nn_bytes(1, None, None) == mrep.E_INVALID_ARG
+    h = mrep._vp()
+    assert mrep._nn_bind(None, sb.value, C.byref(h)) == mrep.E_INVALID_ARG
+    assert mrep._nn_bind(mrep._vp(256), 16, C.byref(h)) == mrep.E_SMALL_BUFFER
+    assert mrep._nn_bind(mrep._vp(257), sb.value, C.byref(h)) == mrep.E_INVALID_ARG
+    assert mrep._nn_train(None, 10, None, None, None, 10, None, 1e-3, None, None, None, 0, None) == mrep.E_INVALID_ARG
+    assert mrep._nn_forward(None, 10, None, None, None, 0, None) == mrep.E_INVALID_ARG
+    assert mrep._nn_infer(None, 10, None, None, None) == mrep.E_INVALID_ARG
+    assert mrep._project_seeded(None, None, None, 10, None, None, None, 0, None, None, None, None,
+                                None) == mrep.E_INVALID_ARG
