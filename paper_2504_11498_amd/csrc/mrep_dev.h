@@ -89,6 +89,15 @@ hipError_t launch_grouping(int64_t n_curves, int64_t n, const int32_t* n_dev, co
                            int32_t* hist, int32_t* q_off, int32_t* tile_off, int32_t* perm, const Outs& o,
                            hipStream_t st);
 
+// Refine, finish and full-scan fallback over candidate pairs in ScreenOut form
+// (k_pairs, k_finish, k_fullscan in FP32).  n bounds the sorted query count;
+// done (nullable) skips decided queries; flag_in is ORed into every flag word
+// written; the overflow counter *ovf_count must be zero on entry.
+hipError_t launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
+                         const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
+                         const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
+                         int32_t* ovf_count, const Outs& o, hipStream_t st);
+
 // The screened projection pipeline (grouping, screen, refine, finish) on a
 // workspace of project_ws_bytes(n_curves, n, kc) bytes.  n bounds the query
 // count; n_dev (nullable) holds the actual count on the device.  With timed,

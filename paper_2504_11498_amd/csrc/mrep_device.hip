@@ -247,19 +247,21 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cid
 
 // One thread per (query, candidate piece) pair reserved by the screen: the
 // certified minimum over the piece in the refine precision.  Persistent grid.
+// done (nullable): per sorted query, nonzero when the query is already decided.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pairs(DevGeom G, const int32_t* __restrict__ cid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ pair_seg,
                                                const int32_t* __restrict__ pair_j,
                                                const int32_t* __restrict__ pair_count, int64_t pair_cap,
-                                               float4* __restrict__ pair_res)
+                                               const uint8_t* __restrict__ done, float4* __restrict__ pair_res)
 {
     const int64_t total = min((int64_t)*pair_count, pair_cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t jj = pair_j[p];
         if (jj < 0) continue;  // reserved by a query that then overflowed the capacity
+        if (done && done[jj]) continue;
         const int64_t s = pair_seg[p];
         if (s < 0 || s >= G.n_seg) continue;  // never written by the screen (defensive)
         const int32_t qi = perm[jj];
@@ -280,12 +282,14 @@ template <typename T>
 __global__ __launch_bounds__(128) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, ScreenOut so,
-                                                const float4* __restrict__ pair_res, double tie_rel, int32_t invert,
+                                                const float4* __restrict__ pair_res, const uint8_t* __restrict__ done,
+                                                uint32_t flag_in, double tie_rel, int32_t invert,
                                                 int32_t* __restrict__ ovf_list, int32_t* __restrict__ ovf_count,
                                                 Outs o)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q_off[G.n_curves]) return;
+    if (done && done[j]) return;
     const int n_list = so.cand_n[j];
     if (n_list <= 0) {  // overflow (or, impossible for finite input, an empty list)
         ovf_list[atomicAdd(ovf_count, 1)] = (int32_t)j;
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(128) void k_finish(DevGeom G, const int32_t* __rest
         const float4 r = pair_res[p0 + i];
         top2(make_cand(G, so.pair_seg[p0 + i], (double)r.x, (double)r.y, (double)r.z, (double)r.w), b1, b2);
     }
-    finish<T>(G, cv, q, b1, b2, 0u, tie_rel, invert, qi, o);
+    finish<T>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
 }
 
 // Lexicographic (d2, t, lane) minimum over the wave; every lane gets the winner lane.
@@ -624,26 +628,37 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
         HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.so, st));
     }
     if (timed && (rc = stage_mark(stage0 + 2, st))) return rc;
-    const int RT = 128;
-    const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
     if (opts->precision == MREP_PREC_BF16) {
-        const unsigned pr_blocks = (unsigned)std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.perm,
-                           (const int32_t*)w.so.pair_seg, (const int32_t*)w.so.pair_j, (const int32_t*)w.pair_count,
-                           w.so.pair_cap, w.pair_res);
-        hipLaunchKernelGGL(k_finish<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
-                           w.q_off, w.perm, w.so, (const float4*)w.pair_res, opts->tie_rel, invert, w.ovf_list,
-                           w.ovf_count, o);
-        hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
-                           (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, (uint32_t)MREP_F_FULLSCAN,
-                           opts->tie_rel, invert, o);
+        HIP_OK(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.so, w.pair_res, nullptr, 0u, opts->tie_rel,
+                             invert, w.ovf_list, w.ovf_count, o, st));
     } else {
+        const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
         hipLaunchKernelGGL(k_fullscan<double>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
                            (const int32_t*)nullptr, (const int32_t*)nullptr, 0u, opts->tie_rel, invert, o);
     }
     HIP_OK(hipGetLastError());
     if (timed && (rc = stage_mark(stage0 + 3, st))) return rc;
     return MREP_OK;
+}
+
+hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
+                               const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
+                               const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
+                               int32_t* ovf_count, const Outs& o, hipStream_t st)
+{
+    const int RT = 128;
+    const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
+    const unsigned pr_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((so.pair_cap + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, perm,
+                       (const int32_t*)so.pair_seg, (const int32_t*)so.pair_j, (const int32_t*)so.pair_count,
+                       so.pair_cap, done, pair_res);
+    hipLaunchKernelGGL(k_finish<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
+                       q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list, ovf_count,
+                       o);
+    hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off, perm,
+                       (const int32_t*)ovf_list, (const int32_t*)ovf_count, (uint32_t)MREP_F_FULLSCAN | flag_in,
+                       tie_rel, invert, o);
+    return hipGetLastError();
 }
 
 int64_t mrep::project_ws_bytes(int64_t n_curves, int64_t n, int kc) { return work_layout(n_curves, n, kc, nullptr, nullptr); }

@@ -391,12 +391,18 @@ struct RowsFromMemory {
     const float* x;
     float* y;
     __device__ int64_t count() const { return n; }
-    __device__ bool features(int64_t row, float* f) const
+    // B operand of layer 1: lane group g holds inputs 8 g .. 8 g + 7 of the row
+    __device__ bf16x8 operand(int64_t row, int g) const
     {
-        if (row >= n) return false;
+        bf16x8 v;
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) f[k] = x[row * kIn + k];
-        return true;
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        if (row < n && g < 2) {
+            const float* r = x + row * kIn + 8 * g;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)((8 * g + j < kIn) ? r[j] : 0.f);
+        }
+        return v;
     }
     __device__ void write(int64_t row, float y0, float y1) const
     {
@@ -404,24 +410,21 @@ struct RowsFromMemory {
     }
 };
 
+// Rows = (sorted query, candidate) pairs; inputs prepared by k_box as BF16 rows of 16.
 struct RowsFromCandidates {
-    DevGeom G;
-    const int32_t* cid;
-    const double* qxyz;
     const int32_t* q_off;
-    const int32_t* perm;
+    int32_t n_curves;
     const int32_t* cand;  // [n][kK] global piece index or -1
+    const uint16_t* xb;   // [n][kK][16] BF16 inputs
     float2* out;          // [n][kK] (u, logit)
-    __device__ int64_t count() const { return (int64_t)q_off[G.n_curves] * kK; }
-    __device__ bool features(int64_t row, float* f) const
+    __device__ int64_t count() const { return (int64_t)q_off[n_curves] * kK; }
+    __device__ bf16x8 operand(int64_t row, int g) const
     {
-        if (row >= count()) return false;
-        const int32_t s = cand[row];
-        if (s < 0) return false;
-        const int32_t qi = perm[row / kK];
-        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
-        pair_features(G, G.curves[cid[qi]], s, q, f);
-        return true;
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        if (g < 2 && row < count() && cand[row] >= 0) v = *reinterpret_cast<const bf16x8*>(xb + row * 16 + 8 * g);
+        return v;
     }
     __device__ void write(int64_t row, float y0, float y1) const
     {
@@ -457,16 +460,7 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += nwaves) {
         const int64_t row = tile * 16 + r;
-        float f[kIn];
-#pragma unroll
-        for (int k = 0; k < kIn; ++k) f[k] = 0.f;
-        const bool ok = rows.features(row, f);
-        bf16x8 xb;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float v = g == 0 ? f[j] : (g == 1 && j < 7 ? f[8 + j] : 0.f);
-            xb[j] = (__bf16)(ok ? v : 0.f);
-        }
+        const bf16x8 xb = rows.operand(row, g);
         // layer 1
         floatx4 h[8];
 #pragma unroll
@@ -518,13 +512,14 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
 constexpr int kBoxSub = 8;
 constexpr int kBoxThreads = kQueriesPerTile * kBoxSub;
 constexpr int kBoxChunk = 1024;
+constexpr int kBoxCap = 64;  // listed pieces per query; more: the query goes to the full scan
 constexpr int kXcds = 8;
 static_assert(kBoxThreads == 256, "box kernel: 32 queries x 8 lanes");
 
 struct BoxOut {
     int32_t* cand;  // [n][kK] global piece index (-1: fewer pieces)
-    int32_t* lohi;  // [n][2]
-    float* ub;      // [n]
+    uint16_t* xb;   // [n][kK][16] BF16 network inputs of the candidates (null: not written)
+    ScreenOut so;   // per query: the pieces whose lower bound reaches UB + margin; so.ub = UB
 };
 
 // float -> uint32 with the same order (negative values included)
@@ -555,6 +550,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                                                      float tie_rel, BoxOut out)
 {
     __shared__ float4 s_sph[kBoxChunk];
+    __shared__ int32_t s_list[kQueriesPerTile][kBoxCap];
+    __shared__ int32_t s_base[kQueriesPerTile];
     const int n_tiles = tile_off[G.n_curves];
     const int per = (n_tiles + kXcds - 1) / kXcds;
     const int slot = (int)(blockIdx.x / kXcds);
@@ -567,12 +564,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
     }
     const int c = lo_c;
     const DCurve cv = G.curves[c];
+    const int lane = threadIdx.x & 63;
     const int qs = threadIdx.x / kBoxSub, sub = threadIdx.x % kBoxSub;
     const int64_t j = (int64_t)q_off[c] + (int64_t)(tile - tile_off[c]) * kQueriesPerTile + qs;
     const bool active = j < q_off[c + 1];
+    const int32_t qi = active ? perm[j] : 0;
     float ql[3] = {0.f, 0.f, 0.f};
     if (active) {
-        const int32_t qi = perm[j];
 #pragma unroll
         for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - cv.origin[k]);
     }
@@ -582,15 +580,15 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
 #pragma unroll
     for (int k = 0; k < kK; ++k) key[k] = ~0ull;
     float ub = INFINITY, thr = 0.f;
-    int32_t lo = INT32_MAX, hi = -1;
+    int cnt = 0;  // pieces listed so far (same value in the query's 8 lanes)
     for (int pass = 0; pass < 2; ++pass) {
         for (int c0 = 0; c0 < cv.n_seg; c0 += kBoxChunk) {
             const int cn = min(kBoxChunk, cv.n_seg - c0);
             __syncthreads();
             for (int i = threadIdx.x; i < cn; i += kBoxThreads) {
-                const int64_t s = cv.seg_off + c0 + i;
-                const float* lp = G.lcp + s * 12;
-                const float* ax = G.aux + s * 8;
+                const int64_t sg = cv.seg_off + c0 + i;
+                const float* lp = G.lcp + sg * 12;
+                const float* ax = G.aux + sg * 8;
                 float r2 = 0.f;
 #pragma unroll
                 for (int p = 0; p < 4; ++p)
@@ -599,12 +597,12 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
             }
             __syncthreads();
             if (!active) continue;
-            for (int i = sub; i < cn; i += kBoxSub) {
-                const float4 p = s_sph[i];
-                const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                const float d2 = dx * dx + dy * dy + dz * dz;
-                const float re = p.w + eps;
-                if (pass == 0) {
+            if (pass == 0) {
+                for (int i = sub; i < cn; i += kBoxSub) {
+                    const float4 p = s_sph[i];
+                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    const float re = p.w + eps;
                     const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
                     const float tu = ub - re;
                     const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
@@ -616,12 +614,22 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
 #pragma unroll
                         for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
                     }
-                } else {
-                    const float tt = thr + re;
-                    if (tt >= 0.f && d2 <= tt * tt) {
-                        lo = min(lo, c0 + i);
-                        hi = max(hi, c0 + i);
+                }
+            } else {
+                // the 8 lanes of a query run the same trip count: the ballot below sees all of them
+                for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
+                    const int i = i0 + sub;
+                    bool hit = false;
+                    if (i < cn) {
+                        const float4 p = s_sph[i];
+                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                        const float tt = thr + p.w + eps;
+                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
                     }
+                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                    if (hit && pos < kBoxCap) s_list[qs][pos] = c0 + i;
+                    cnt += __popc(grp);
                 }
             }
         }
@@ -643,18 +651,58 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
             thr = ub + tie_margin(ub, cv, tie_rel);
         }
     }
-#pragma unroll
-    for (int off = 1; off < kBoxSub; off <<= 1) {
-        lo = min(lo, __shfl_xor(lo, off, 64));
-        hi = max(hi, __shfl_xor(hi, off, 64));
+    // reserve the workgroup's pairs with one atomic
+    const bool listed = active && cnt <= kBoxCap;
+    if (sub == 0) s_base[qs] = listed ? cnt : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) {
+            const int v = s_base[k];
+            s_base[k] = tot;
+            tot += v;
+        }
+        const int base = tot > 0 ? atomicAdd(out.so.pair_count, tot) : 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) s_base[k] += base;
     }
-    if (active && sub == 0) {
+    __syncthreads();
+    if (!active) return;
+    const int64_t b = s_base[qs];
+    const bool fits = listed && b + cnt <= out.so.pair_cap;
+    if (sub == 0) {
+        out.so.cand_n[j] = fits ? cnt : -1;
+        out.so.pair_off[j] = (int32_t)b;
+        out.so.ub[j] = ub;
 #pragma unroll
         for (int k = 0; k < kK; ++k)
             out.cand[j * kK + k] = key[k] == ~0ull ? -1 : (int32_t)(cv.seg_off + (uint32_t)key[k]);
-        out.lohi[2 * j] = (int32_t)cv.seg_off + (hi >= 0 ? lo : 0);
-        out.lohi[2 * j + 1] = (int32_t)cv.seg_off + (hi >= 0 ? hi : cv.n_seg - 1);
-        out.ub[j] = ub;
+    }
+    if (listed) {
+        for (int k = sub; k < cnt; k += kBoxSub) {
+            if (b + k >= out.so.pair_cap) break;
+            out.so.pair_seg[b + k] = fits ? (int32_t)(cv.seg_off + s_list[qs][k]) : 0;
+            out.so.pair_j[b + k] = fits ? (int32_t)j : -1;  // a slot past the capacity stays unused
+        }
+    }
+    if (out.xb && sub < kK) {
+        const uint64_t kk = sub == 0 ? key[0] : (sub == 1 ? key[1] : (sub == 2 ? key[2] : key[3]));
+        float f[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) f[k] = 0.f;
+        if (kk != ~0ull) {
+            const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+            pair_features(G, cv, cv.seg_off + (uint32_t)kk, q, f);
+        }
+        uint32_t w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint16_t lo = __builtin_bit_cast(uint16_t, (__bf16)f[2 * k]);
+            const uint16_t hi = 2 * k + 1 < kIn ? __builtin_bit_cast(uint16_t, (__bf16)f[2 * k + 1]) : (uint16_t)0;
+            w[k] = (uint32_t)lo | ((uint32_t)hi << 16);
+        }
+        uint4* dst = reinterpret_cast<uint4*>(out.xb + (j * kK + sub) * 16);
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
 }
 
@@ -762,35 +810,28 @@ __device__ __forceinline__ int fprime_class(const BezQ& b, bool relax0, bool rel
 __device__ __forceinline__ float end_dist(const BezQ& b, int i) { return norm3f(b.R[i]); }
 
 // ---------------------------------------------------------------------------
-// Seed + certificate (Seeded) or sphere-pruned refine (!Seeded): one thread per
-// sorted query position.
+// Seed + certificate: one thread per sorted query position.  Certified queries
+// are finished and marked done; the others are left to the refine over their
+// sphere lists (k_pairs / k_finish), which also covers list overflows.
 // ---------------------------------------------------------------------------
-template <bool Seeded>
 __global__ __launch_bounds__(128) void k_decide(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, BoxOut box,
                                                 const float2* __restrict__ scores, float tie_rel, int32_t invert,
-                                                int32_t* __restrict__ fb_list, int32_t* __restrict__ fb_count, Outs o)
+                                                uint8_t* __restrict__ done, Outs o)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q_off[G.n_curves]) return;
+    const int n_list = box.so.cand_n[j];
+    if (n_list <= 0) {
+        done[j] = 0;
+        return;
+    }
     const int32_t qi = perm[j];
     const DCurve cv = G.curves[cid[qi]];
     const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
-    const int64_t lo = box.lohi[2 * j], hi = box.lohi[2 * j + 1];
-    const float ubx = box.ub[j];
+    const int64_t p0 = box.so.pair_off[j];
     const int64_t s_first = cv.seg_off, s_last = cv.seg_off + cv.n_seg - 1;
-    Cand b1 = empty_cand(cv), b2 = b1;
-    if (!Seeded) {
-        const float thr = ubx + tie_margin(ubx, cv, tie_rel);
-        for (int64_t s = lo; s <= hi; ++s) {
-            BezQ b;
-            load_bezq(G, cv, s, q, b);
-            if (sphere_lb(b, cv) <= thr) consider<float>(G, cv, s, q, b1, b2);
-        }
-        finish<float>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
-        return;
-    }
     // 1. best-scored candidate
     int64_t s = -1;
     float best = -INFINITY, u0 = 0.5f;
@@ -800,28 +841,32 @@ __global__ __launch_bounds__(128) void k_decide(DevGeom G, const int32_t* __rest
         const float2 y = scores[j * kK + k];
         if (sk >= 0 && (s < 0 || y.y > best)) { s = sk; best = y.y; u0 = y.x; }
     }
-    bool ok = s >= 0;
-    u0 = fminf(fmaxf(u0, 0.f), 1.f);
-    // 2. walk to the piece holding the minimum, then its certified minimum
-    BezQ b;
-    int cls = 0;
-    for (int hop = 0; ok; ++hop) {
-        load_bezq(G, cv, s, q, b);
-        cls = fprime_class(b, false, false);
-        if (cls == 1 && s > s_first) {
-            if (hop == 4) ok = false;
-            else { --s; u0 = 1.f; }
-        } else if (cls == -1 && s < s_last) {
-            if (hop == 4) ok = false;
-            else { ++s; u0 = 0.f; }
-        } else {
-            break;
-        }
-    }
+    bool ok = s >= 0, certified = false;
     float u = 0.f, d2 = INFINITY, kap = 1.f;
     Cubic<float> C;
-    if (ok) {
+    Cand b2 = empty_cand(cv);
+    // at most 3 attempts: a failed certificate that found a strictly closer piece restarts there
+    for (int attempt = 0; ok && !certified && attempt < 3; ++attempt) {
+        u0 = fminf(fmaxf(u0, 0.f), 1.f);
+        // 2. walk to the piece holding the minimum, then its certified minimum
+        int cls = 0;
+        for (int hop = 0; ok; ++hop) {
+            BezQ bq;
+            load_bezq(G, cv, s, q, bq);
+            cls = fprime_class(bq, false, false);
+            if (cls == 1 && s > s_first) {
+                if (hop == 4) ok = false;
+                else { --s; u0 = 1.f; }
+            } else if (cls == -1 && s < s_last) {
+                if (hop == 4) ok = false;
+                else { ++s; u0 = 0.f; }
+            } else {
+                break;
+            }
+        }
+        if (!ok) break;
         load_cubic(G, cv, s, q, C);
+        kap = 1.f;
         if (cls == 1) { u = 0.f; d2 = C.dist2(0.f); }
         else if (cls == -1) { u = 1.f; d2 = C.dist2(1.f); }
         else {
@@ -837,74 +882,58 @@ __global__ __launch_bounds__(128) void k_decide(DevGeom G, const int32_t* __rest
             }
             if (cls == 0) piece_min(C, u, d2, kap);
         }
-    }
-    const float ds = sqrtf(d2);
-    if (ok && !(ds <= ubx)) ok = false;  // a piece's sphere holds a closer point
-    // 3. certificate over [lo, hi]: every other piece whose sphere reaches lim has a
-    // certified minimum above lim; a monotone piece's minimum is an endpoint
-    // distance, any other piece's is its certified piece minimum.  The
-    // neighbour whose minimum is the endpoint it shares with the chosen piece is
-    // kept as the runner-up for the tie test instead.
-    const float lim = ds + tie_margin(ds, cv, tie_rel);
-    for (int64_t s2 = lo; ok && s2 <= hi; ++s2) {
-        if (s2 == s) continue;
-        BezQ n;
-        load_bezq(G, cv, s2, q, n);
-        if (sphere_lb(n, cv) > lim) continue;
-        const bool adj_r = s2 == s + 1, adj_l = s2 == s - 1;
-        const int c2 = fprime_class(n, adj_r, adj_l);
-        float mn;
-        int end = -1;
-        if (c2 == 1) { mn = end_dist(n, 0); end = 0; }
-        else if (c2 == -1) { mn = end_dist(n, 3); end = 3; }
-        else {
-            Cubic<float> C2;
-            load_cubic(G, cv, s2, q, C2);
-            float uu, dd, kk;
-            piece_min(C2, uu, dd, kk);
-            mn = sqrtf(dd) * (1.f - 8e-6f);
+        const float ds = sqrtf(d2);
+        // 3. certificate over the listed pieces (an unlisted piece's sphere lower bound
+        // exceeds UB + margin >= d* + margin): each other piece whose sphere reaches
+        // lim must have a certified minimum above lim.  A monotone piece's minimum is
+        // an endpoint distance, any other piece's is its certified piece minimum.  The
+        // neighbour whose minimum is the endpoint it shares with the chosen piece is
+        // kept as the runner-up for the tie test instead.
+        const float lim = ds + tie_margin(ds, cv, tie_rel);
+        b2 = empty_cand(cv);
+        bool fail = false;
+        int64_t better = -1;
+        float better_d = ds * (1.f - 1e-5f), better_u = 0.5f;
+        for (int i = 0; i < n_list; ++i) {
+            const int64_t s2 = box.so.pair_seg[p0 + i];
+            if (s2 == s) continue;
+            BezQ n;
+            load_bezq(G, cv, s2, q, n);
+            if (sphere_lb(n, cv) > lim) continue;
+            const bool adj_r = s2 == s + 1, adj_l = s2 == s - 1;
+            const int c2 = fprime_class(n, adj_r, adj_l);
+            float mn, um;
+            int end = -1;
+            if (c2 == 1) { mn = end_dist(n, 0); end = 0; um = 0.f; }
+            else if (c2 == -1) { mn = end_dist(n, 3); end = 3; um = 1.f; }
+            else {
+                Cubic<float> C2;
+                load_cubic(G, cv, s2, q, C2);
+                float dd, kk;
+                piece_min(C2, um, dd, kk);
+                mn = sqrtf(dd) * (1.f - 8e-6f);
+            }
+            if (mn > lim) continue;
+            if ((adj_r && end == 0) || (adj_l && end == 3)) {
+                const Cand e = make_cand(G, s2, end == 0 ? 0.0 : 1.0, (double)mn * mn, 1.0, 0.0);
+                if (e.d2 < b2.d2) b2 = e;
+                continue;
+            }
+            fail = true;
+            if (mn < better_d) { better_d = mn; better = s2; better_u = um; }
         }
-        if (mn > lim) continue;
-        if ((adj_r && end == 0) || (adj_l && end == 3)) {
-            const Cand e = make_cand(G, s2, end == 0 ? 0.0 : 1.0, (double)mn * mn, 1.0, 0.0);
-            if (e.d2 < b2.d2) b2 = e;
-            continue;
-        }
-        ok = false;
+        if (!fail) { certified = true; break; }
+        if (better < 0) ok = false;
+        else { s = better; u0 = better_u; }
     }
-    if (!ok) {
-        fb_list[atomicAdd(fb_count, 1)] = qi;
+    if (!certified) {
+        done[j] = 0;
         return;
     }
+    done[j] = 1;
     const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
-    b1 = make_cand(G, s, (double)u, (double)d2, (double)kap, param_error(C, u, kap, ta, tb));
+    const Cand b1 = make_cand(G, s, (double)u, (double)d2, (double)kap, param_error(C, u, kap, ta, tb));
     finish<float>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
-}
-
-// Fallback plumbing: gather the failed queries, scatter their answers back.
-__global__ void k_fb_gather(const int32_t* __restrict__ count, int64_t n, const int32_t* __restrict__ list,
-                            const int32_t* __restrict__ cid, const double* __restrict__ q, int32_t* __restrict__ cid_c,
-                            double* __restrict__ q_c)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= min(n, (int64_t)*count)) return;
-    const int32_t qi = list[i];
-    cid_c[i] = cid[qi];
-    q_c[3 * i] = q[3 * (int64_t)qi];
-    q_c[3 * i + 1] = q[3 * (int64_t)qi + 1];
-    q_c[3 * i + 2] = q[3 * (int64_t)qi + 2];
-}
-
-__global__ void k_fb_scatter(const int32_t* __restrict__ count, int64_t n, const int32_t* __restrict__ list, Outs c,
-                             Outs o)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= min(n, (int64_t)*count)) return;
-    const int32_t qi = list[i];
-    o.t[qi] = c.t[i];
-    o.d[qi] = c.d[i];
-    o.s[qi] = c.s[i];
-    o.f[qi] = c.f[i] | MREP_F_NN_FALLBACK;
 }
 
 // Training-data export: candidates and features in the caller's query order.
@@ -935,25 +964,18 @@ __global__ void k_fill_feat(int64_t n, int32_t* __restrict__ seg_out, float* __r
     for (int k = 0; k < kIn; ++k) x_out[i * kIn + k] = 0.f;
 }
 
-__global__ void k_zero_i32(int32_t* p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
 
 // Workspace of the seeded call.
+constexpr int64_t kSpherePairsPerQuery = 24;  // average listed pieces per query the pair arrays hold
 struct SeedWork {
-    int32_t *hist, *q_off, *tile_off, *perm;
+    int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
     BoxOut box;
+    float4* pair_res;
     float2* scores;
-    int32_t *fb_list, *fb_count;
-    int32_t* cid_c;
-    double* q_c;
-    Outs oc;
-    void* core;
+    uint8_t* done;
 };
 
-int64_t seed_layout(int64_t nc, int64_t n, int kc, char* base, SeedWork* w)
+int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
 {
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -961,20 +983,27 @@ int64_t seed_layout(int64_t nc, int64_t n, int kc, char* base, SeedWork* w)
         off = a256(off + bytes);
         return o;
     };
+    const int64_t cap = std::min<int64_t>(kSpherePairsPerQuery * n + 1024, (int64_t)INT32_MAX);
     const int64_t oh = take(4 * (nc + 2)), oq = take(4 * (nc + 1)), ot = take(4 * (nc + 1)), op = take(4 * n);
-    const int64_t oc = take(4 * n * kK), olh = take(8 * n), oub = take(4 * n), osc = take(8 * n * kK);
-    const int64_t ofl = take(4 * n), ofc = take(4), ocid = take(4 * n), oqc = take(24 * n);
-    const int64_t ott = take(8 * n), odd = take(8 * n), oss = take(4 * n), off_ = take(4 * n);
-    const int64_t ocore = take(project_ws_bytes(nc, n, kc));
+    const int64_t oov = take(4 * n), oc = take(4 * n * kK), oxb = take(32 * n * kK), ocn = take(4 * n);
+    const int64_t opo = take(4 * n), oub = take(4 * n), ops = take(4 * cap), opj = take(4 * cap);
+    const int64_t opr = take(16 * cap), osc = take(8 * n * kK), odn = take(n);
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
-        w->perm = (int32_t*)(base + op);
-        w->box.cand = (int32_t*)(base + oc); w->box.lohi = (int32_t*)(base + olh); w->box.ub = (float*)(base + oub);
+        w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
+        w->ovf_count = w->hist + nc;  // zeroed by the grouping, like the pair counter after it
+        w->box.cand = (int32_t*)(base + oc);
+        w->box.xb = (uint16_t*)(base + oxb);
+        w->box.so.cand_n = (int32_t*)(base + ocn);
+        w->box.so.pair_off = (int32_t*)(base + opo);
+        w->box.so.ub = (float*)(base + oub);
+        w->box.so.pair_seg = (int32_t*)(base + ops);
+        w->box.so.pair_j = (int32_t*)(base + opj);
+        w->box.so.pair_count = w->hist + nc + 1;
+        w->box.so.pair_cap = cap;
+        w->pair_res = (float4*)(base + opr);
         w->scores = (float2*)(base + osc);
-        w->fb_list = (int32_t*)(base + ofl); w->fb_count = (int32_t*)(base + ofc);
-        w->cid_c = (int32_t*)(base + ocid); w->q_c = (double*)(base + oqc);
-        w->oc = Outs{(double*)(base + ott), (double*)(base + odd), (int32_t*)(base + oss), (uint32_t*)(base + off_)};
-        w->core = base + ocore;
+        w->done = (uint8_t*)(base + odn);
     }
     return off;
 }
@@ -1192,7 +1221,7 @@ int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep
     }
     int rc = check_opts(opts);
     if (rc) return rc;
-    *bytes = seed_layout(geom->g.L.n_curves, n, opts->max_candidates, nullptr, nullptr);
+    *bytes = seed_layout(geom->g.L.n_curves, n, nullptr, nullptr);
     return MREP_OK;
 }
 
@@ -1214,7 +1243,7 @@ int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_
     }
     const int64_t nc = geom->g.L.n_curves;
     SeedWork w;
-    if (ws_bytes < seed_layout(nc, n, 1, (char*)workspace, &w)) {
+    if (ws_bytes < seed_layout(nc, n, (char*)workspace, &w)) {
         set_error("mrep_nn_features: workspace smaller than mrep_seeded_workspace_bytes");
         return MREP_E_SMALL_BUFFER;
     }
@@ -1226,6 +1255,7 @@ int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_
     hipLaunchKernelGGL(k_fill_feat, dim3(blocks_for(n * kK)), dim3(256), 0, st, n, seg_out, x_out);
     // grouping writes nothing for invalid ids when the outputs are null
     const Outs none{nullptr, nullptr, nullptr, nullptr};
+    w.box.xb = nullptr;
     int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_feat_write, dim3(blocks_for(n, 128)), dim3(128), 0, st, dev_view(geom->g), curve_id, q_xyz,
@@ -1263,7 +1293,7 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
         return MREP_E_INVALID_ARG;
     }
     SeedWork w;
-    if (ws_bytes < seed_layout(nc, n, opts->max_candidates, (char*)workspace, &w)) {
+    if (ws_bytes < seed_layout(nc, n, (char*)workspace, &w)) {
         set_error("mrep_project_curves_seeded: workspace smaller than mrep_seeded_workspace_bytes");
         return MREP_E_SMALL_BUFFER;
     }
@@ -1277,38 +1307,28 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
     const Outs o{t_out, dist_out, seg_out, flags_out};
     const DevGeom G = dev_view(geom->g);
     const float tie = (float)opts->tie_rel;
+    if (!nn) w.box.xb = nullptr;
     rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, w.fb_count, 1);
     if (timed && (rc = stage_mark(1, st))) return rc;
     if (nn) {
         rc = pack_image(nn, st);
         if (rc) return rc;
-        RowsFromCandidates rows{G, curve_id, q_xyz, w.q_off, w.perm, w.box.cand, w.scores};
+        RowsFromCandidates rows{w.q_off, (int32_t)nc, w.box.cand, w.box.xb, w.scores};
         const unsigned nb = (unsigned)std::min<int64_t>((n * kK + 63) / 64, 2048);
         hipLaunchKernelGGL(k_mlp<RowsFromCandidates>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
         NN_HIP(hipGetLastError());
     }
     if (timed && (rc = stage_mark(2, st))) return rc;
-    if (nn)
-        hipLaunchKernelGGL(k_decide<true>, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
-                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
-                           (int32_t)0, w.fb_list, w.fb_count, o);
-    else
-        hipLaunchKernelGGL(k_decide<false>, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
-                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
-                           (int32_t)0, w.fb_list, w.fb_count, o);
-    NN_HIP(hipGetLastError());
-    if (timed && (rc = stage_mark(3, st))) return rc;
     if (nn) {
-        hipLaunchKernelGGL(k_fb_gather, dim3(blocks_for(n)), dim3(256), 0, st, (const int32_t*)w.fb_count, n,
-                           (const int32_t*)w.fb_list, curve_id, q_xyz, w.cid_c, w.q_c);
-        rc = project_core(geom->g, opts, n, w.fb_count, w.cid_c, w.q_c, w.core, w.oc, st, 0, false, 0);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_fb_scatter, dim3(blocks_for(n)), dim3(256), 0, st, (const int32_t*)w.fb_count, n,
-                           (const int32_t*)w.fb_list, w.oc, o);
+        hipLaunchKernelGGL(k_decide, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
+                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
+                           (int32_t)0, w.done, o);
         NN_HIP(hipGetLastError());
     }
+    if (timed && (rc = stage_mark(3, st))) return rc;
+    NN_HIP(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.box.so, w.pair_res, nn ? w.done : nullptr,
+                         nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, 0, w.ovf_list, w.ovf_count, o, st));
     if (timed) {
         if ((rc = stage_mark(4, st))) return rc;
         stage_end(4);
