@@ -19,6 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrep_oracle.c")
 _SRC_MLP = os.path.join(_HERE, "mlp_oracle.c")
+_SRC_SURF = os.path.join(_HERE, "surf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -28,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
-               "-shared", "-o", tmp, _SRC, _SRC_MLP, "-lm"]
+               "-shared", "-o", tmp, _SRC, _SRC_MLP, _SRC_SURF, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -38,7 +39,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_MLP)):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC_MLP, _SRC_SURF)):
         build(force=True)
     lib = C.CDLL(_LIB)
     dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -67,6 +68,12 @@ def _load():
     lib.orc_max_threads.restype = C.c_int
     lib.orc_mlp_loss.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int64, dp, dp, dp, dp, dp]
     lib.orc_mlp_loss.restype = C.c_double
+    sargs = [C.c_int, ip, ip, ip, ip, lp, dp, lp, dp, lp, dp]
+    lib.orc_surf_eval_batch.argtypes = sargs + [C.c_int64, ip, dp, dp]
+    lib.orc_surf_project_batch.argtypes = sargs + [C.c_int64, ip, dp, dp, dp, dp, dp, C.c_int]
+    lib.orc_surf_patches.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, dp]
+    lib.orc_surf_patch_deviation.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_int]
+    lib.orc_surf_patch_deviation.restype = C.c_double
     _lib = lib
     return lib
 
@@ -235,3 +242,76 @@ def mlp_loss(params, x, u_star=None, accept=None, n_in=15, hidden=128, n_out=2, 
 
 def mlp_param_count(n_in=15, hidden=128, n_out=2):
     return hidden * n_in + hidden + hidden * hidden + hidden + n_out * hidden + n_out
+
+
+# --------------------------------------------------------------------------- surfaces (surf_oracle.c)
+def _surf_args(S):
+    i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)  # noqa: E731
+    i64 = lambda a: np.ascontiguousarray(a, dtype=np.int64)  # noqa: E731
+    keep = [i32(S.deg_u), i32(S.deg_v), i32(S.n_u), i32(S.n_v), i64(S.cp_off), _d(S.cp), i64(S.ku_off), _d(S.ku),
+            i64(S.kv_off), _d(S.kv)]
+    ptrs = [_ptr(keep[0], C.c_int32), _ptr(keep[1], C.c_int32), _ptr(keep[2], C.c_int32), _ptr(keep[3], C.c_int32),
+            _ptr(keep[4], C.c_int64), _ptr(keep[5], C.c_double), _ptr(keep[6], C.c_int64), _ptr(keep[7], C.c_double),
+            _ptr(keep[8], C.c_int64), _ptr(keep[9], C.c_double)]
+    return keep, [int(S.n)] + ptrs
+
+
+def surf_eval(S, sid, uv):
+    """S_{sid[k]}(u_k, v_k) by tensor-product de Boor (FP64)."""
+    sid = np.ascontiguousarray(sid, dtype=np.int32)
+    uv = _d(uv).reshape(-1, 2)
+    out = np.zeros((sid.shape[0], 3))
+    keep, args = _surf_args(S)
+    _load().orc_surf_eval_batch(*args, sid.shape[0], _ptr(sid, C.c_int32), _ptr(uv, C.c_double), _ptr(out, C.c_double))
+    return out
+
+
+def surf_surface(S, k):
+    """(p, q, nu, nv, P[nu*nv,3], U, V) of surface k."""
+    return (int(S.deg_u[k]), int(S.deg_v[k]), int(S.n_u[k]), int(S.n_v[k]),
+            np.ascontiguousarray(S.cp[S.cp_off[k]:S.cp_off[k + 1]], dtype=np.float64),
+            np.ascontiguousarray(S.ku[S.ku_off[k]:S.ku_off[k + 1]], dtype=np.float64),
+            np.ascontiguousarray(S.kv[S.kv_off[k]:S.kv_off[k + 1]], dtype=np.float64))
+
+
+def surf_patches(S, k):
+    """Exact Bezier patches of surface k by Boehm insertion: nets[np, p+1, q+1, 3], rects[np, 4]."""
+    p, q, nu, nv, P, U, V = surf_surface(S, k)
+    cap = nu * nv
+    nets = np.zeros((cap, p + 1, q + 1, 3))
+    rects = np.zeros((cap, 4))
+    n = _load().orc_surf_patches(p, q, nu, nv, _ptr(P, C.c_double), _ptr(U, C.c_double), _ptr(V, C.c_double), cap,
+                                 _ptr(nets, C.c_double), _ptr(rects, C.c_double))
+    if n < 0:
+        raise ValueError("orc_surf_patches failed")
+    return nets[:n], rects[:n]
+
+
+def surf_patch_deviation(S, k, R, rect, ns=33):
+    """Largest |R(s,t) - S(u,v)| of a bicubic patch R[4,4,3] on rect over an ns x ns grid."""
+    p, q, nu, nv, P, U, V = surf_surface(S, k)
+    R = _d(R).reshape(4, 4, 3)
+    rect = _d(rect)
+    return float(_load().orc_surf_patch_deviation(p, q, nu, nv, _ptr(P, C.c_double), _ptr(U, C.c_double),
+                                                  _ptr(V, C.c_double), _ptr(R, C.c_double), _ptr(rect, C.c_double),
+                                                  int(ns)))
+
+
+def surf_project(S, sid, q, nthreads: int = 0):
+    """Global minimiser (u, v) of |q - S(u, v)| over each query's own surface.
+
+    Returns dict(uv[n,2], dist, runner, kappa): runner = distance of the best other local minimum farther than
+    1e-6 in parameter (inf if none within 3e-6 * diag), kappa = smallest eigenvalue of the distance Hessian
+    relative to the first fundamental form at an interior minimiser (1 on the boundary)."""
+    sid = np.ascontiguousarray(sid, dtype=np.int32)
+    q = _d(q).reshape(-1, 3)
+    n = sid.shape[0]
+    uv = np.zeros((n, 2))
+    dist, runner, kappa = np.zeros(n), np.zeros(n), np.zeros(n)
+    keep, args = _surf_args(S)
+    rc = _load().orc_surf_project_batch(*args, n, _ptr(sid, C.c_int32), _ptr(q, C.c_double), _ptr(uv, C.c_double),
+                                        _ptr(dist, C.c_double), _ptr(runner, C.c_double), _ptr(kappa, C.c_double),
+                                        int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_surf_project_batch failed")
+    return {"uv": uv, "dist": dist, "runner": runner, "kappa": kappa}

@@ -435,3 +435,116 @@ def test_mlp_gradient_central_differences():
         pm[i] -= h
         num = (oracle.mlp_loss(pp, x, us, ac)[0] - oracle.mlp_loss(pm, x, us, ac)[0]) / (2 * h)
         assert abs(num - g[i]) <= 1e-7 * max(1.0, abs(num)), (i, num, g[i])
+
+
+# --------------------------------------------------------------------------- surfaces (tensor product)
+from scipy.interpolate import NdBSpline  # noqa: E402
+from scipy.optimize import minimize  # noqa: E402
+
+
+def _one_surface(p, q, nu, nv, rng, height=True):
+    x = np.linspace(0, 1, nu)
+    y = np.linspace(0, 1, nv)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    Z = rng.uniform(-0.3, 0.3, X.shape) if height else rng.uniform(0, 1, X.shape)
+    P = np.stack([X, Y, Z], -1).reshape(-1, 3)
+    U = np.r_[np.zeros(p + 1), np.sort(rng.uniform(0.05, 0.95, nu - p - 1)), np.ones(p + 1)]
+    V = np.r_[np.zeros(q + 1), np.sort(rng.uniform(0.05, 0.95, nv - q - 1)), np.ones(q + 1)]
+    return gen.SurfaceSet(np.array([p], np.int32), np.array([q], np.int32), np.array([nu], np.int32),
+                          np.array([nv], np.int32), np.array([0, nu * nv], np.int64), P, np.array([0, len(U)], np.int64),
+                          U, np.array([0, len(V)], np.int64), V)
+
+
+def _ndb(S):
+    p, q, nu, nv, P, U, V = oracle.surf_surface(S, 0)
+    return NdBSpline((U, V), P.reshape(nu, nv, 3), (p, q))
+
+
+@pytest.mark.parametrize("p,q", [(3, 3), (5, 5), (2, 4), (1, 3)])
+def test_surface_eval_matches_scipy(p, q):
+    rng = np.random.default_rng(100 + 10 * p + q)
+    S = _one_surface(p, q, p + 6, q + 5, rng, height=False)
+    uv = np.concatenate([rng.uniform(0, 1, (300, 2)), [[0, 0], [1, 1], [0, 1], [1, 0]]])
+    got = oracle.surf_eval(S, np.zeros(len(uv), np.int32), uv)
+    np.testing.assert_allclose(got, _ndb(S)(uv), atol=1e-14)
+
+
+@pytest.mark.parametrize("p,q", [(3, 3), (5, 5), (2, 3)])
+def test_surface_bezier_patches_reproduce_surface(p, q):
+    """Boehm patches: each patch net evaluated by Bernstein sums equals the surface on its rectangle."""
+    from math import comb
+
+    rng = np.random.default_rng(7 + p + q)
+    S = _one_surface(p, q, p + 5, q + 4, rng)
+    nets, rects = oracle.surf_patches(S, 0)
+    assert len(nets) == (p + 5 - p) * (q + 4 - q)
+    spl = _ndb(S)
+    st = rng.uniform(0, 1, (40, 2))
+    for net, rc in zip(nets, rects):
+        Bu = np.array([[comb(p, i) * s ** i * (1 - s) ** (p - i) for i in range(p + 1)] for s in st[:, 0]])
+        Bv = np.array([[comb(q, j) * t ** j * (1 - t) ** (q - j) for j in range(q + 1)] for t in st[:, 1]])
+        val = np.einsum("ni,nj,ijc->nc", Bu, Bv, net)
+        uv = np.stack([rc[0] + st[:, 0] * (rc[1] - rc[0]), rc[2] + st[:, 1] * (rc[3] - rc[2])], 1)
+        np.testing.assert_allclose(val, spl(uv), atol=1e-13)
+    # exact bicubic patches have zero deviation; a shifted net deviates by the shift
+    if p == 3 and q == 3:
+        assert oracle.surf_patch_deviation(S, 0, nets[5], rects[5]) <= 1e-14
+        assert abs(oracle.surf_patch_deviation(S, 0, nets[5] + [0, 0, 1e-3], rects[5]) - 1e-3) <= 1e-14
+
+
+def test_surface_projection_plane_closed_form():
+    """Control points at the Greville abscissae reproduce S(u, v) = (u, v, 0) (linear precision), so the
+    projection of (x, y, z) is (clamp(x), clamp(y)) with the matching distance."""
+    rng = np.random.default_rng(3)
+    p = q = 3
+    n = 9
+    U = np.r_[np.zeros(p + 1), np.sort(rng.uniform(0.1, 0.9, n - p - 1)), np.ones(p + 1)]
+    V = np.r_[np.zeros(q + 1), np.sort(rng.uniform(0.1, 0.9, n - q - 1)), np.ones(q + 1)]
+    gu = np.array([U[i + 1:i + p + 1].mean() for i in range(n)])
+    gv = np.array([V[j + 1:j + q + 1].mean() for j in range(n)])
+    X, Y = np.meshgrid(gu, gv, indexing="ij")
+    P = np.stack([X, Y, np.zeros_like(X)], -1).reshape(-1, 3)
+    S = gen.SurfaceSet(np.array([p], np.int32), np.array([q], np.int32), np.array([n], np.int32),
+                       np.array([n], np.int32), np.array([0, n * n], np.int64), P, np.array([0, len(U)], np.int64),
+                       U, np.array([0, len(V)], np.int64), V)
+    x = rng.uniform(-0.4, 1.4, (200, 3))
+    r = oracle.surf_project(S, np.zeros(200, np.int32), x)
+    cu, cv = np.clip(x[:, 0], 0, 1), np.clip(x[:, 1], 0, 1)
+    np.testing.assert_allclose(r["uv"][:, 0], cu, atol=1e-9)
+    np.testing.assert_allclose(r["uv"][:, 1], cv, atol=1e-9)
+    np.testing.assert_allclose(r["dist"], np.linalg.norm(x - np.stack([cu, cv, 0 * cu], 1), axis=1), atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [3, 5])
+def test_surface_inversion_of_on_surface_points(p):
+    """Height fields over a monotone grid: a point on the surface has a unique foot point, its own (u0, v0)."""
+    rng = np.random.default_rng(50 + p)
+    S = _one_surface(p, p, 12, 11, rng)
+    uv0 = rng.uniform(0, 1, (300, 2))
+    x = oracle.surf_eval(S, np.zeros(300, np.int32), uv0)
+    r = oracle.surf_project(S, np.zeros(300, np.int32), x)
+    assert r["dist"].max() <= 1e-12
+    np.testing.assert_allclose(r["uv"], uv0, atol=1e-9)
+
+
+def test_surface_projection_brute_force():
+    """Dense 401 x 401 sampling of scipy's surface, then a bounded quasi-Newton polish from the 5 best
+    samples: the oracle is never worse and agrees to 1e-9."""
+    rng = np.random.default_rng(77)
+    S = _one_surface(3, 3, 7, 6, rng)
+    spl = _ndb(S)
+    g = np.linspace(0, 1, 401)
+    G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    pts = spl(G)
+    x = rng.uniform(-0.2, 1.2, (40, 3))
+    x[:, 2] = rng.uniform(-0.6, 0.6, 40)
+    r = oracle.surf_project(S, np.zeros(40, np.int32), x)
+    for k in range(40):
+        d = np.linalg.norm(pts - x[k], axis=1)
+        best = np.inf
+        for i in np.argsort(d)[:5]:
+            res = minimize(lambda w: float(np.sum((spl(w[None])[0] - x[k]) ** 2)), G[i], method="L-BFGS-B",
+                           bounds=[(0, 1), (0, 1)], options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 500})
+            best = min(best, np.sqrt(res.fun), d[i])
+        assert r["dist"][k] <= best + 1e-12
+        assert abs(r["dist"][k] - best) <= 1e-9
