@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 2
+#define MREP_ABI_VERSION 3
 
 /* status codes */
 #define MREP_OK 0
@@ -203,6 +203,76 @@ int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_
  * enough).  Returns the number of stages written (> 0).
  * Errors: MREP_E_INVALID_ARG (no timed call yet, n too small), MREP_E_HIP. */
 int32_t mrep_last_stage_times(double* ms_out, int32_t n);
+
+/* ---------------------------------------------------------------------- */
+/* Surfaces (tensor-product B-splines; the paper's matrix form applied in  */
+/* u and in v, Sec. 5.2.1, with the curve reduction of Sec. 5.2.2 applied  */
+/* to rows, then columns)                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Decompose n_surf clamped tensor-product B-spline surfaces into bicubic
+ * Bezier patches.  Per surface s:
+ *   deg_u[s], deg_v[s]          HOST  degrees (1..MREP_MAX_DEGREE)
+ *   n_u[s], n_v[s]              HOST  control-net size
+ *   cp_off[n_surf+1]            HOST  CSR offsets (in points) into cp_xyz; net u-major: P[i * n_v + j]
+ *   cp_xyz                      HOST  double xyz
+ *   ku_off / ku, kv_off / kv    HOST  CSR knot vectors (n_u + p + 1 and n_v + q + 1 values, clamped)
+ *   tol_rel                     tolerance relative to the net's box diagonal
+ * Each non-degenerate span patch becomes B_p^-1 D_u P D_v^T B_q^-T exactly
+ * (degrees <= 3 elevated to cubic); a direction of degree >= 4 is reduced to
+ * cubic with the G1 L2 curve reduction (rows in u, then columns in v), and a
+ * patch whose error bound on a 32 x 32 grid exceeds tol_rel * diag is split
+ * (on the exact net) in the direction of larger error at the worst grid line.
+ * Errors: as mrep_decompose_curves. */
+int32_t mrep_decompose_surfaces(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u,
+                                const int32_t* n_v, const int64_t* cp_off, const double* cp_xyz,
+                                const int64_t* ku_off, const double* ku, const int64_t* kv_off, const double* kv,
+                                double tol_rel, int32_t n_threads, mrep_plan** out);
+
+/* HOST copies of a surface plan (any output may be NULL):
+ *   patch_off[n_surf+1]   first patch of each surface
+ *   patch_uv[P][4]        (u_a, u_b, v_a, v_b) of each patch
+ *   patch_cp[P][4][4][3]  bicubic Bezier net (u-major)
+ *   patch_span[P]         index of the exact span patch within its surface (u-span major)
+ * mrep_plan_info on a surface plan reports surfaces in n_curves, patches in
+ * n_segments, span patches in n_spans and reserved = 1.
+ * Errors: MREP_E_INVALID_ARG (null or curve plan). */
+int32_t mrep_plan_export_surfaces(const mrep_plan* plan, int64_t* patch_off, double* patch_uv, double* patch_cp,
+                                  int32_t* patch_span);
+
+/* DEVICE workspace size for a surface projection of n queries.
+ * Errors: MREP_E_INVALID_ARG (also for a curve geometry). */
+int32_t mrep_surface_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes);
+
+/* Project n query points, each onto its own surface, returning the global
+ * minimiser of |q - S(u, v)| over the whole domain of the EXACT surface.
+ *   surface_id[n] DEVICE int32;  q_xyz[3n] DEVICE double
+ *   uv_out[2n]    DEVICE double  (u, v) of the minimiser
+ *   dist_out[n]   DEVICE double  |q - S(u, v)|
+ *   patch_out[n]  DEVICE int32   index of the bicubic patch holding (u, v) within the surface
+ *                                (half-open rectangles, closed at the domain's far sides)
+ *   flags_out[n]  DEVICE uint32  MREP_F_POLISHED (always: FP64 Newton on the exact span
+ *                                patch decides), MREP_F_NEAR_TIE, MREP_F_ILL_COND (smallest
+ *                                relative curvature of the distance < 1e-2),
+ *                                MREP_F_ENDPOINT (on the boundary of the domain),
+ *                                MREP_F_FULLSCAN, MREP_F_BAD_ID
+ * opts->precision and max_candidates are ignored (candidates come from patch
+ * bounding spheres; patches are minimised in FP32 and the answer in FP64).
+ * Limits: n < 2^31 / 24.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_project_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
+                              const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out,
+                              double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream);
+
+/* Inversion: as mrep_project_surfaces, and MREP_F_OFFCURVE where the distance
+ * exceeds the surface's tolerance tol_rel * diag. */
+int32_t mrep_invert_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
+                             const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out,
+                             double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream);
+
+/* S_{surface_id[i]}(uv[2i], uv[2i+1]) on the exact surface (FP64), clamped to
+ * the domain; DEVICE arrays.  Bad ids give NaN. */
+int32_t mrep_eval_surfaces(const mrep_geom* geom, int64_t n, const int32_t* surface_id, const double* uv,
+                           double* xyz_out, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Learned seeding (an extension; the paper has no learned part)           */

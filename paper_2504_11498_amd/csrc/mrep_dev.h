@@ -110,7 +110,16 @@ int project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const int32
 
 }  // namespace mrep
 
-// Device geometry handle of the C ABI: a non-owning view of the caller's buffer.
+// Handles of the C ABI.  A plan (host) and a geometry (non-owning device view
+// of the caller's buffer) hold either curves or surfaces.
+enum { MREP_GEOM_CURVES = 0, MREP_GEOM_SURFACES = 1 };
+struct mrep_plan {
+    int kind = MREP_GEOM_CURVES;
+    mrep::Plan p;
+    mrep::SurfPlan sp;
+};
 struct mrep_geom {
+    int kind = MREP_GEOM_CURVES;
     mrep::Geom g;
+    mrep::SurfGeom sg;
 };

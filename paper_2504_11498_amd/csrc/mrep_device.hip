@@ -38,9 +38,6 @@
 using namespace mrep;
 
 
-struct mrep_plan {
-    Plan p;
-};
 
 namespace mrep {
 static thread_local std::string t_err;
@@ -467,6 +464,17 @@ int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info)
         set_error("mrep_plan_info: null pointer");
         return MREP_E_INVALID_ARG;
     }
+    if (plan->kind == MREP_GEOM_SURFACES) {
+        const SurfPlan& S = plan->sp;
+        info->n_curves = S.n_surf;
+        info->n_spans = S.layout.n_span;
+        info->n_segments = S.layout.n_patch;
+        info->device_bytes = S.layout.total;
+        info->max_degree = S.max_degree;
+        info->reserved = 1;
+        info->tol_rel = S.tol_rel;
+        return MREP_OK;
+    }
     info->n_curves = plan->p.n_curves;
     info->n_spans = plan->p.layout.n_span;
     info->n_segments = plan->p.layout.n_seg;
@@ -477,10 +485,63 @@ int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info)
     return MREP_OK;
 }
 
+int32_t mrep_decompose_surfaces(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u,
+                                const int32_t* n_v, const int64_t* cp_off, const double* cp_xyz,
+                                const int64_t* ku_off, const double* ku, const int64_t* kv_off, const double* kv,
+                                double tol_rel, int32_t n_threads, mrep_plan** out)
+{
+    if (!out || n_surf < 0 ||
+        (n_surf > 0 && (!deg_u || !deg_v || !n_u || !n_v || !cp_off || !cp_xyz || !ku_off || !ku || !kv_off || !kv))) {
+        set_error("mrep_decompose_surfaces: null pointer or negative count");
+        return MREP_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!(tol_rel > 0.0) || !std::isfinite(tol_rel)) {
+        set_error("mrep_decompose_surfaces: tol_rel must be positive");
+        return MREP_E_TOL;
+    }
+    mrep_plan* p = new mrep_plan();
+    p->kind = MREP_GEOM_SURFACES;
+    std::string err;
+    int rc = build_surf_plan(n_surf, deg_u, deg_v, n_u, n_v, cp_off, cp_xyz, ku_off, ku, kv_off, kv, tol_rel,
+                             n_threads, p->sp, err);
+    if (rc != MREP_OK) {
+        delete p;
+        set_error("mrep_decompose_surfaces: " + err);
+        return rc;
+    }
+    *out = p;
+    return MREP_OK;
+}
+
+int32_t mrep_plan_export_surfaces(const mrep_plan* plan, int64_t* patch_off, double* patch_uv, double* patch_cp,
+                                  int32_t* patch_span)
+{
+    if (!plan || plan->kind != MREP_GEOM_SURFACES) {
+        set_error("mrep_plan_export_surfaces: null plan or a curve plan");
+        return MREP_E_INVALID_ARG;
+    }
+    const SurfPlan& S = plan->sp;
+    if (patch_off) {
+        for (int64_t c = 0; c < S.n_surf; ++c) patch_off[c] = S.surfs[(size_t)c].patch_off;
+        patch_off[S.n_surf] = S.layout.n_patch;
+    }
+    if (patch_uv) memcpy(patch_uv, S.uv.data(), sizeof(double) * S.uv.size());
+    if (patch_cp) memcpy(patch_cp, S.gcp.data(), sizeof(double) * S.gcp.size());
+    if (patch_span) {
+        for (int64_t c = 0; c < S.n_surf; ++c) {
+            const DSurf& d = S.surfs[(size_t)c];
+            for (int32_t k = 0; k < d.n_patch; ++k)
+                patch_span[d.patch_off + k] = (int32_t)(S.pspan[(size_t)(d.patch_off + k)] - d.span_off);
+        }
+    }
+    return MREP_OK;
+}
+
 int32_t mrep_plan_export(const mrep_plan* plan, int64_t* seg_off, double* seg_t, double* seg_cp, int32_t* seg_span)
 {
-    if (!plan) {
-        set_error("mrep_plan_export: null plan");
+    if (!plan || plan->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_plan_export: null plan or a surface plan");
         return MREP_E_INVALID_ARG;
     }
     const Plan& P = plan->p;
@@ -496,6 +557,8 @@ int32_t mrep_plan_export(const mrep_plan* plan, int64_t* seg_off, double* seg_t,
 
 void mrep_plan_free(mrep_plan* plan) { delete plan; }
 
+static int32_t upload_surfaces(const SurfPlan& P, void* dev_buf, int64_t bytes, void* stream, mrep_geom** out);
+
 int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* stream, mrep_geom** out)
 {
     if (!plan || !dev_buf || !out) {
@@ -503,6 +566,7 @@ int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* s
         return MREP_E_INVALID_ARG;
     }
     *out = nullptr;
+    if (plan->kind == MREP_GEOM_SURFACES) return upload_surfaces(plan->sp, dev_buf, bytes, stream, out);
     const Plan& P = plan->p;
     if (bytes < P.layout.total) {
         set_error("mrep_upload: buffer smaller than device_bytes");
@@ -542,6 +606,45 @@ int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* s
 }
 
 void mrep_geom_release(mrep_geom* geom) { delete geom; }
+
+static int32_t upload_surfaces(const SurfPlan& P, void* dev_buf, int64_t bytes, void* stream, mrep_geom** out)
+{
+    if (bytes < P.layout.total) {
+        set_error("mrep_upload: buffer smaller than device_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)dev_buf & 255) != 0) {
+        set_error("mrep_upload: buffer not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char* b = (char*)dev_buf;
+    const SurfLayout& L = P.layout;
+    auto cp = [&](int64_t off, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(b + off, src, n, hipMemcpyHostToDevice, st);
+    };
+    HIP_OK(cp(L.off_surf, P.surfs.data(), sizeof(DSurf) * P.surfs.size()));
+    HIP_OK(cp(L.off_sph, P.sph.data(), sizeof(float) * P.sph.size()));
+    HIP_OK(cp(L.off_lcp, P.lcp.data(), sizeof(float) * P.lcp.size()));
+    HIP_OK(cp(L.off_gcp, P.gcp.data(), sizeof(double) * P.gcp.size()));
+    HIP_OK(cp(L.off_uv, P.uv.data(), sizeof(double) * P.uv.size()));
+    HIP_OK(cp(L.off_pspan, P.pspan.data(), sizeof(int32_t) * P.pspan.size()));
+    HIP_OK(cp(L.off_span0, P.span0.data(), sizeof(int32_t) * P.span0.size()));
+    HIP_OK(cp(L.off_brk, P.brk.data(), sizeof(double) * P.brk.size()));
+    HIP_OK(cp(L.off_coef, P.coef.data(), sizeof(double) * P.coef.size()));
+    // the plan's host vectors are pageable: finish the copies before returning
+    HIP_OK(hipStreamSynchronize(st));
+    mrep_geom* g = new mrep_geom();
+    g->kind = MREP_GEOM_SURFACES;
+    g->sg.L = L;
+    g->sg.base = b;
+    HIP_OK(hipGetDevice(&g->sg.device));
+    *out = g;
+    return MREP_OK;
+}
 
 int32_t mrep_opts_default(mrep_opts* o)
 {
@@ -584,8 +687,8 @@ extern "C" {
 
 int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
 {
-    if (!geom || !bytes || n < 0) {
-        set_error("mrep_workspace_bytes: null pointer or negative n");
+    if (!geom || !bytes || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_workspace_bytes: null pointer, surface geometry or negative n");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
@@ -667,8 +770,8 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
                            int32_t* seg_out, uint32_t* flags_out, void* stream, int invert)
 {
-    if (!geom || n < 0) {
-        set_error("mrep_project_curves: null geometry or negative n");
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_project_curves: null or surface geometry, or negative n");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
@@ -727,8 +830,8 @@ int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t
 int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t, double* xyz_out,
                          void* stream)
 {
-    if (!geom || n < 0 || (n > 0 && (!curve_id || !t || !xyz_out))) {
-        set_error("mrep_eval_curves: null pointer or negative n");
+    if (!geom || n < 0 || (n > 0 && (!curve_id || !t || !xyz_out)) || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_eval_curves: null pointer, surface geometry or negative n");
         return MREP_E_INVALID_ARG;
     }
     if (n == 0) return MREP_OK;

@@ -649,3 +649,502 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
 }
 
 }  // namespace mrep
+
+// ---------------------------------------------------------------------------
+// Surfaces.  A tensor-product span patch (span q_u in u, q_v in v) is the
+// matrix form of Sec. 5.2.1 applied in both directions: power coefficients
+// C = D_u P D_v^T (D = diag(h^j) A of the span, eq. Mqpt) and Bezier net
+// N = B_p^{-1} D_u P D_v^T B_q^{-T}.  Degrees <= 3 are elevated to cubic
+// exactly; a degree >= 4 direction is reduced with the curve's G1 L2 cubic
+// (Sec. 5.2.2), rows in u first, then columns in v, and a patch whose error
+// bound on a 32 x 32 grid exceeds the tolerance is split (on the exact net) in
+// the direction whose hodograph bound of the error is larger, at the worst
+// grid line clamped to [4/31, 27/31].
+// ---------------------------------------------------------------------------
+namespace mrep {
+namespace {
+
+constexpr int kSurfGrid = 32;
+
+struct SPiece {
+    double R[48];
+    double ua, ub, va, vb;
+    int32_t span;
+};
+
+struct SurfOut {
+    std::vector<SPiece> pieces;
+    std::vector<double> brk, coef;
+    std::vector<int32_t> span_first;
+    int n_su = 0, n_sv = 0;
+    int rc = 0;
+    std::string err;
+    double diag = 0.0, tol_abs = 0.0;
+};
+
+// degree-d curve (d+1 points) -> cubic (4 points)
+void curve_to_cubic(int d, const double* Q, double* R4)
+{
+    if (d == 3) { memcpy(R4, Q, sizeof(double) * 12); return; }
+    if (d > 3) { g1_reduce(d, g_tab[d], Q, R4); return; }
+    double A[12], B[12], E[5 * 4];
+    memcpy(A, Q, sizeof(double) * 3 * (size_t)(d + 1));
+    for (int e = d; e < 3; ++e) {
+        elevation_matrix(e, E);
+        for (int i = 0; i <= e + 1; ++i)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int k = 0; k <= e; ++k) s += E[i * (e + 1) + k] * A[3 * k + c];
+                B[3 * i + c] = s;
+            }
+        memcpy(A, B, sizeof(double) * 3 * (size_t)(e + 2));
+    }
+    memcpy(R4, A, sizeof(double) * 12);
+}
+
+// (p+1) x (q+1) net (u-major) -> bicubic 4 x 4: rows in u, then columns in v
+void net_to_bicubic(int p, int q, const double* N, double* R)
+{
+    double T[4 * (kMaxP + 1) * 3], col[(kMaxP + 1) * 3], r4[12];
+    for (int j = 0; j <= q; ++j) {
+        for (int i = 0; i <= p; ++i)
+            for (int c = 0; c < 3; ++c) col[3 * i + c] = N[3 * (i * (q + 1) + j) + c];
+        curve_to_cubic(p, col, r4);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) T[3 * (k * (q + 1) + j) + c] = r4[3 * k + c];
+    }
+    for (int k = 0; k < 4; ++k) {
+        curve_to_cubic(q, &T[3 * (k * (q + 1))], r4);
+        for (int l = 0; l < 4; ++l)
+            for (int c = 0; c < 3; ++c) R[3 * (k * 4 + l) + c] = r4[3 * l + c];
+    }
+}
+
+void bern_row(int d, double s, double* b)
+{
+    for (int i = 0; i <= d; ++i) b[i] = binom(d, i) * ipow(s, i) * ipow(1.0 - s, d - i);
+}
+
+// net of degree (a, b) written at degree (A, B) >= (a, b)
+void elevate_net(int a, int b, const double* N, int A, int B, double* out)
+{
+    double cur[(kMaxP + 1) * (kMaxP + 1) * 3], nxt[(kMaxP + 1) * (kMaxP + 1) * 3], E[(kMaxP + 2) * (kMaxP + 1)];
+    memcpy(cur, N, sizeof(double) * 3 * (size_t)(a + 1) * (b + 1));
+    int ca = a, cb = b;
+    while (ca < A) {
+        elevation_matrix(ca, E);
+        for (int i = 0; i <= ca + 1; ++i)
+            for (int j = 0; j <= cb; ++j)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int k = 0; k <= ca; ++k) s += E[i * (ca + 1) + k] * cur[3 * (k * (cb + 1) + j) + c];
+                    nxt[3 * (i * (cb + 1) + j) + c] = s;
+                }
+        ++ca;
+        memcpy(cur, nxt, sizeof(double) * 3 * (size_t)(ca + 1) * (cb + 1));
+    }
+    while (cb < B) {
+        elevation_matrix(cb, E);
+        for (int i = 0; i <= ca; ++i)
+            for (int j = 0; j <= cb + 1; ++j)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int k = 0; k <= cb; ++k) s += E[j * (cb + 1) + k] * cur[3 * (i * (cb + 1) + k) + c];
+                    nxt[3 * (i * (cb + 2) + j) + c] = s;
+                }
+        ++cb;
+        memcpy(cur, nxt, sizeof(double) * 3 * (size_t)(ca + 1) * (cb + 1));
+    }
+    memcpy(out, cur, sizeof(double) * 3 * (size_t)(A + 1) * (B + 1));
+}
+
+// Error bound of the bicubic R against the exact net N: the largest deviation
+// on the 32 x 32 grid plus half a grid step times the hodograph bounds Ls, Lt
+// of their difference.  (ki, kj): the first grid point (row-major) within
+// 1e-6 relative of the largest deviation.
+double bicubic_error(int p, int q, const double* N, const double* R, int* ki, int* kj, double* Ls, double* Lt)
+{
+    double bp[kSurfGrid][kMaxP + 1], bq[kSurfGrid][kMaxP + 1], b3[kSurfGrid][4];
+    for (int k = 0; k < kSurfGrid; ++k) {
+        const double s = (double)k / (kSurfGrid - 1);
+        bern_row(p, s, bp[k]);
+        bern_row(q, s, bq[k]);
+        bern_row(3, s, b3[k]);
+    }
+    static thread_local std::vector<double> ev;
+    ev.assign((size_t)kSurfGrid * kSurfGrid, 0.0);
+    double best = 0.0;
+    for (int k = 0; k < kSurfGrid; ++k) {
+        // rows of N and R collapsed in u at s_k
+        double nu[(kMaxP + 1) * 3], ru[4 * 3];
+        for (int j = 0; j <= q; ++j)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int i = 0; i <= p; ++i) s += bp[k][i] * N[3 * (i * (q + 1) + j) + c];
+                nu[3 * j + c] = s;
+            }
+        for (int l = 0; l < 4; ++l)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int i = 0; i < 4; ++i) s += b3[k][i] * R[3 * (i * 4 + l) + c];
+                ru[3 * l + c] = s;
+            }
+        for (int l = 0; l < kSurfGrid; ++l) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double x = 0.0, y = 0.0;
+                for (int j = 0; j <= q; ++j) x += bq[l][j] * nu[3 * j + c];
+                for (int j = 0; j < 4; ++j) y += b3[l][j] * ru[3 * j + c];
+                d2 += (x - y) * (x - y);
+            }
+            const double e = sqrt(d2);
+            ev[(size_t)k * kSurfGrid + l] = e;
+            best = std::max(best, e);
+        }
+    }
+    *ki = 0; *kj = 0;
+    for (int k = 0, found = 0; k < kSurfGrid && !found; ++k)
+        for (int l = 0; l < kSurfGrid; ++l)
+            if (ev[(size_t)k * kSurfGrid + l] >= best * (1.0 - 1e-6)) { *ki = k; *kj = l; found = 1; break; }
+    const int A = std::max(p, 3), B = std::max(q, 3);
+    double Ne[(kMaxP + 1) * (kMaxP + 1) * 3], Re[(kMaxP + 1) * (kMaxP + 1) * 3];
+    elevate_net(p, q, N, A, B, Ne);
+    elevate_net(3, 3, R, A, B, Re);
+    double ls = 0.0, lt = 0.0;
+    for (int i = 0; i <= A; ++i)
+        for (int j = 0; j <= B; ++j) {
+            double du2 = 0.0, dv2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double d00 = Ne[3 * (i * (B + 1) + j) + c] - Re[3 * (i * (B + 1) + j) + c];
+                if (i < A) {
+                    const double d10 = Ne[3 * ((i + 1) * (B + 1) + j) + c] - Re[3 * ((i + 1) * (B + 1) + j) + c];
+                    du2 += (d10 - d00) * (d10 - d00);
+                }
+                if (j < B) {
+                    const double d01 = Ne[3 * (i * (B + 1) + j + 1) + c] - Re[3 * (i * (B + 1) + j + 1) + c];
+                    dv2 += (d01 - d00) * (d01 - d00);
+                }
+            }
+            ls = std::max(ls, (double)A * sqrt(du2));
+            lt = std::max(lt, (double)B * sqrt(dv2));
+        }
+    *Ls = ls;
+    *Lt = lt;
+    return best + (ls + lt) / (2.0 * (kSurfGrid - 1));
+}
+
+// split an exact net at z in u (dir 0: every column curve) or v (dir 1: every row curve)
+void split_net(int p, int q, const double* N, int dir, double z, double* A, double* B)
+{
+    double c[(kMaxP + 1) * 3], l[(kMaxP + 1) * 3], r[(kMaxP + 1) * 3];
+    if (dir == 0) {
+        for (int j = 0; j <= q; ++j) {
+            for (int i = 0; i <= p; ++i)
+                for (int k = 0; k < 3; ++k) c[3 * i + k] = N[3 * (i * (q + 1) + j) + k];
+            split_piece(p, c, z, l, r);
+            for (int i = 0; i <= p; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    A[3 * (i * (q + 1) + j) + k] = l[3 * i + k];
+                    B[3 * (i * (q + 1) + j) + k] = r[3 * i + k];
+                }
+        }
+    } else {
+        for (int i = 0; i <= p; ++i) {
+            split_piece(q, &N[3 * (i * (q + 1))], z, l, r);
+            memcpy(&A[3 * (i * (q + 1))], l, sizeof(double) * 3 * (size_t)(q + 1));
+            memcpy(&B[3 * (i * (q + 1))], r, sizeof(double) * 3 * (size_t)(q + 1));
+        }
+    }
+}
+
+bool reduce_patch(int p, int q, const double* N0, double ua, double ub, double va, double vb, double tol, int32_t span,
+                  std::vector<SPiece>& out)
+{
+    struct Item {
+        double N[(kMaxP + 1) * (kMaxP + 1) * 3];
+        double ua, ub, va, vb;
+    };
+    std::vector<Item> stack;
+    Item first;
+    memcpy(first.N, N0, sizeof(double) * 3 * (size_t)(p + 1) * (q + 1));
+    first.ua = ua; first.ub = ub; first.va = va; first.vb = vb;
+    stack.push_back(first);
+    int splits = 0;
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        SPiece pc;
+        net_to_bicubic(p, q, it.N, pc.R);
+        pc.ua = it.ua; pc.ub = it.ub; pc.va = it.va; pc.vb = it.vb; pc.span = span;
+        if (p <= 3 && q <= 3) { out.push_back(pc); continue; }
+        int ki = 0, kj = 0;
+        double Ls = 0.0, Lt = 0.0;
+        const double e = bicubic_error(p, q, it.N, pc.R, &ki, &kj, &Ls, &Lt);
+        if (e <= tol) { out.push_back(pc); continue; }
+        if (++splits >= MREP_MAX_PIECES_PER_SPAN) return false;
+        const int dir = (p >= 4 && (q <= 3 || Ls >= Lt)) ? 0 : 1;
+        const int k = std::min(std::max(dir == 0 ? ki : kj, 4), kSurfGrid - 1 - 4);
+        const double z = (double)k / (kSurfGrid - 1);
+        Item a, b;
+        a.ua = b.ua = it.ua; a.ub = b.ub = it.ub; a.va = b.va = it.va; a.vb = b.vb = it.vb;
+        split_net(p, q, it.N, dir, z, a.N, b.N);
+        if (dir == 0) {
+            const double um = it.ua + z * (it.ub - it.ua);
+            a.ub = um; b.ua = um;
+        } else {
+            const double vm = it.va + z * (it.vb - it.va);
+            a.vb = vm; b.va = vm;
+        }
+        stack.push_back(b);
+        stack.push_back(a);
+    }
+    return true;
+}
+
+void decompose_surface(int p, int q, int nu, int nv, const double* P, const double* U, const double* V, double tol_rel,
+                       SurfOut& out)
+{
+    std::string err;
+    int code = 0;
+    std::vector<double> zeros((size_t)3 * std::max(nu, nv), 0.0);
+    if (!validate_curve(p, nu, zeros.data(), U, err, code) || !validate_curve(q, nv, zeros.data(), V, err, code)) {
+        out.rc = code;
+        out.err = err;
+        return;
+    }
+    for (int64_t i = 0; i < (int64_t)3 * nu * nv; ++i)
+        if (!std::isfinite(P[i])) { out.rc = MREP_E_INVALID_ARG; out.err = "non-finite control point"; return; }
+    double lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
+    for (int i = 0; i < nu * nv; ++i)
+        for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], P[3 * i + c]); hi[c] = std::max(hi[c], P[3 * i + c]); }
+    out.diag = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) + (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    out.tol_abs = tol_rel * out.diag;
+    std::vector<int> su, sv;
+    for (int k = p; k <= nu - 1; ++k) if (U[k] < U[k + 1]) su.push_back(k);
+    for (int k = q; k <= nv - 1; ++k) if (V[k] < V[k + 1]) sv.push_back(k);
+    out.n_su = (int)su.size();
+    out.n_sv = (int)sv.size();
+    for (int k : su) out.brk.push_back(U[k]);
+    out.brk.push_back(U[su.back() + 1]);
+    for (int k : sv) out.brk.push_back(V[k]);
+    out.brk.push_back(V[sv.back() + 1]);
+    const DegreeTables& Tp = g_tab[p];
+    const DegreeTables& Tq = g_tab[q];
+    double Au[(kMaxP + 1) * (kMaxP + 1)], Av[(kMaxP + 1) * (kMaxP + 1)];
+    double Du[(kMaxP + 1) * (kMaxP + 1)], Dv[(kMaxP + 1) * (kMaxP + 1)];
+    double Mu[(kMaxP + 1) * (kMaxP + 1)], Mv[(kMaxP + 1) * (kMaxP + 1)];
+    std::vector<double> Cf((size_t)(p + 1) * (q + 1) * 3), Nz((size_t)(p + 1) * (q + 1) * 3);
+    int32_t span = 0;
+    for (int a = 0; a < out.n_su; ++a) {
+        const int qu = su[(size_t)a];
+        const double hu = U[qu + 1] - U[qu];
+        span_basis_poly(p, U, qu, Au);
+        double hj = 1.0;
+        for (int j = 0; j <= p; ++j, hj *= hu)
+            for (int r = 0; r <= p; ++r) Du[j * (p + 1) + r] = hj * Au[j * (p + 1) + r];
+        for (int i = 0; i <= p; ++i)
+            for (int r = 0; r <= p; ++r) {
+                double s = 0.0;
+                for (int j = 0; j <= i; ++j) s += Tp.Bi[i * (p + 1) + j] * Du[j * (p + 1) + r];
+                Mu[i * (p + 1) + r] = s;
+            }
+        for (int b = 0; b < out.n_sv; ++b) {
+            const int qv = sv[(size_t)b];
+            const double hv = V[qv + 1] - V[qv];
+            span_basis_poly(q, V, qv, Av);
+            double hk = 1.0;
+            for (int j = 0; j <= q; ++j, hk *= hv)
+                for (int r = 0; r <= q; ++r) Dv[j * (q + 1) + r] = hk * Av[j * (q + 1) + r];
+            for (int i = 0; i <= q; ++i)
+                for (int r = 0; r <= q; ++r) {
+                    double s = 0.0;
+                    for (int j = 0; j <= i; ++j) s += Tq.Bi[i * (q + 1) + j] * Dv[j * (q + 1) + r];
+                    Mv[i * (q + 1) + r] = s;
+                }
+            // C = Du P Dv^T and N = Mu P Mv^T over the span's control points
+            for (int x = 0; x <= p; ++x)
+                for (int y = 0; y <= q; ++y)
+                    for (int c = 0; c < 3; ++c) {
+                        double sc = 0.0, sn = 0.0;
+                        for (int r = 0; r <= p; ++r)
+                            for (int t = 0; t <= q; ++t) {
+                                const double pv = P[3 * ((size_t)(qu - p + r) * nv + (qv - q + t)) + c];
+                                sc += Du[x * (p + 1) + r] * Dv[y * (q + 1) + t] * pv;
+                                sn += Mu[x * (p + 1) + r] * Mv[y * (q + 1) + t] * pv;
+                            }
+                        Cf[3 * (x * (q + 1) + y) + c] = sc;
+                        Nz[3 * (x * (q + 1) + y) + c] = sn;
+                    }
+            out.coef.insert(out.coef.end(), Cf.begin(), Cf.end());
+            out.span_first.push_back((int32_t)out.pieces.size());
+            if (!reduce_patch(p, q, Nz.data(), U[qu], U[qu + 1], V[qv], V[qv + 1], out.tol_abs, span, out.pieces)) {
+                out.rc = MREP_E_TOL;
+                out.err = "a span patch needed more than MREP_MAX_PIECES_PER_SPAN pieces";
+                return;
+            }
+            ++span;
+        }
+    }
+    if (p <= 3 && q <= 3) out.tol_abs = 0.0;
+}
+
+// tables of one bicubic patch: FP32 centre relative to the origin (exact in
+// FP64), radius bound, FP32 net relative to the centre
+void patch_tables(const double* R, const double* o, double tol_eff, float* sph, float* lcp)
+{
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = hi[c] = R[c];
+        for (int i = 1; i < 16; ++i) { lo[c] = std::min(lo[c], R[3 * i + c]); hi[c] = std::max(hi[c], R[3 * i + c]); }
+    }
+    float cf[3];
+    double cd[3];
+    for (int c = 0; c < 3; ++c) {
+        cf[c] = (float)(0.5 * (lo[c] + hi[c]) - o[c]);
+        cd[c] = o[c] + (double)cf[c];
+    }
+    double r = 0.0;
+    for (int i = 0; i < 16; ++i) {
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) d2 += (R[3 * i + c] - cd[c]) * (R[3 * i + c] - cd[c]);
+        r = std::max(r, sqrt(d2));
+        for (int c = 0; c < 3; ++c) lcp[3 * i + c] = (float)(R[3 * i + c] - cd[c]);
+    }
+    sph[0] = cf[0];
+    sph[1] = cf[1];
+    sph[2] = cf[2];
+    sph[3] = nextafterf((float)(r * (1.0 + 1e-6) + tol_eff * (1.0 + 1e-6)), INFINITY);
+}
+
+}  // namespace
+
+int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u, const int32_t* n_v,
+                    const int64_t* cp_off, const double* cp_xyz, const int64_t* ku_off, const double* ku,
+                    const int64_t* kv_off, const double* kv, double tol_rel, int n_threads, SurfPlan& plan,
+                    std::string& err)
+{
+    init_tables();
+    for (int32_t s = 0; s < n_surf; ++s) {
+        const std::string who = "surface " + std::to_string(s) + ": ";
+        if (deg_u[s] < 1 || deg_u[s] > kMaxP || deg_v[s] < 1 || deg_v[s] > kMaxP) { err = who + "degree out of range"; return MREP_E_BAD_DEGREE; }
+        if (n_u[s] < deg_u[s] + 1 || n_v[s] < deg_v[s] + 1) { err = who + "too few control points"; return MREP_E_BAD_DEGREE; }
+        if (cp_off[s + 1] - cp_off[s] != (int64_t)n_u[s] * n_v[s]) { err = who + "net size != n_u * n_v"; return MREP_E_INVALID_ARG; }
+        if (ku_off[s + 1] - ku_off[s] != n_u[s] + deg_u[s] + 1 || kv_off[s + 1] - kv_off[s] != n_v[s] + deg_v[s] + 1) {
+            err = who + "knot count != points + degree + 1";
+            return MREP_E_BAD_KNOTS;
+        }
+        if ((int64_t)n_u[s] * n_v[s] > ((int64_t)1 << 24)) { err = who + "net too large"; return MREP_E_INVALID_ARG; }
+    }
+    std::vector<SurfOut> outs((size_t)n_surf);
+    int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::min<int>(nt, std::max<int32_t>(1, n_surf));
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const int32_t s = next.fetch_add(1);
+            if (s >= n_surf) break;
+            decompose_surface(deg_u[s], deg_v[s], n_u[s], n_v[s], cp_xyz + 3 * cp_off[s], ku + ku_off[s],
+                              kv + kv_off[s], tol_rel, outs[(size_t)s]);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; ++i) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+    for (int32_t s = 0; s < n_surf; ++s)
+        if (outs[(size_t)s].rc) {
+            err = "surface " + std::to_string(s) + ": " + outs[(size_t)s].err;
+            return outs[(size_t)s].rc;
+        }
+    plan.n_surf = n_surf;
+    plan.tol_rel = tol_rel;
+    plan.surfs.resize((size_t)n_surf);
+    int64_t npatch = 0, nspan = 0, ncoef = 0, nbrk = 0;
+    for (int32_t s = 0; s < n_surf; ++s) {
+        const SurfOut& o = outs[(size_t)s];
+        DSurf& d = plan.surfs[(size_t)s];
+        d.patch_off = npatch;
+        d.span_off = nspan;
+        d.coef_off = ncoef;
+        d.brk_off = nbrk;
+        d.n_patch = (int32_t)o.pieces.size();
+        d.n_su = o.n_su;
+        d.n_sv = o.n_sv;
+        d.deg_u = deg_u[s];
+        d.deg_v = deg_v[s];
+        d.pad = 0;
+        d.tol_eff = (deg_u[s] >= 4 || deg_v[s] >= 4) ? o.tol_abs : 1e-13 * o.diag;
+        d.tol_user = tol_rel * o.diag;
+        d.diag = o.diag;
+        const double* P = cp_xyz + 3 * cp_off[s];
+        const int64_t n = (int64_t)n_u[s] * n_v[s];
+        for (int k = 0; k < 3; ++k) {
+            double lo = P[k], hi = P[k];
+            for (int64_t i = 0; i < n; ++i) { lo = std::min(lo, P[3 * i + k]); hi = std::max(hi, P[3 * i + k]); }
+            d.origin[k] = (double)(float)(0.5 * (lo + hi));
+        }
+        npatch += d.n_patch;
+        nspan += (int64_t)o.n_su * o.n_sv;
+        ncoef += (int64_t)o.coef.size();
+        nbrk += (int64_t)o.brk.size();
+        plan.max_degree = std::max(plan.max_degree, std::max(deg_u[s], deg_v[s]));
+    }
+    if (npatch >= ((int64_t)1 << 31)) { err = "more than 2^31 patches"; return MREP_E_INVALID_ARG; }
+    plan.gcp.resize((size_t)npatch * 48);
+    plan.uv.resize((size_t)npatch * 4);
+    plan.pspan.resize((size_t)npatch);
+    plan.span0.resize((size_t)nspan + 1);
+    plan.brk.resize((size_t)nbrk);
+    plan.coef.resize((size_t)ncoef);
+    plan.sph.resize((size_t)npatch * 4);
+    plan.lcp.resize((size_t)npatch * 48);
+    std::atomic<int32_t> next2{0};
+    auto worker2 = [&]() {
+        for (;;) {
+            const int32_t s = next2.fetch_add(1);
+            if (s >= n_surf) break;
+            const SurfOut& o = outs[(size_t)s];
+            const DSurf& d = plan.surfs[(size_t)s];
+            for (int32_t k = 0; k < d.n_patch; ++k) {
+                const SPiece& pc = o.pieces[(size_t)k];
+                const int64_t g = d.patch_off + k;
+                memcpy(&plan.gcp[(size_t)g * 48], pc.R, sizeof(double) * 48);
+                plan.uv[(size_t)g * 4] = pc.ua;
+                plan.uv[(size_t)g * 4 + 1] = pc.ub;
+                plan.uv[(size_t)g * 4 + 2] = pc.va;
+                plan.uv[(size_t)g * 4 + 3] = pc.vb;
+                plan.pspan[(size_t)g] = (int32_t)(d.span_off + pc.span);
+                patch_tables(pc.R, d.origin, d.tol_eff, &plan.sph[(size_t)g * 4], &plan.lcp[(size_t)g * 48]);
+            }
+            for (int64_t j = 0; j < (int64_t)o.n_su * o.n_sv; ++j)
+                plan.span0[(size_t)(d.span_off + j)] = (int32_t)(d.patch_off + o.span_first[(size_t)j]);
+            memcpy(&plan.brk[(size_t)d.brk_off], o.brk.data(), sizeof(double) * o.brk.size());
+            memcpy(&plan.coef[(size_t)d.coef_off], o.coef.data(), sizeof(double) * o.coef.size());
+        }
+    };
+    th.clear();
+    for (int i = 1; i < nt; ++i) th.emplace_back(worker2);
+    worker2();
+    for (auto& t : th) t.join();
+    plan.span0[(size_t)nspan] = (int32_t)npatch;
+    SurfLayout& L = plan.layout;
+    L.n_surf = n_surf;
+    L.n_patch = npatch;
+    L.n_span = nspan;
+    L.n_coef = ncoef;
+    L.n_brk = nbrk;
+    int64_t off = 0;
+    L.off_surf = off; off = align256(off + (int64_t)sizeof(DSurf) * n_surf);
+    L.off_sph = off; off = align256(off + 16 * npatch);
+    L.off_lcp = off; off = align256(off + 4 * 48 * npatch);
+    L.off_gcp = off; off = align256(off + 8 * 48 * npatch);
+    L.off_uv = off; off = align256(off + 8 * 4 * npatch);
+    L.off_pspan = off; off = align256(off + 4 * npatch);
+    L.off_span0 = off; off = align256(off + 4 * (nspan + 1));
+    L.off_brk = off; off = align256(off + 8 * nbrk);
+    L.off_coef = off; off = align256(off + 8 * ncoef);
+    L.total = off;
+    return MREP_OK;
+}
+
+}  // namespace mrep

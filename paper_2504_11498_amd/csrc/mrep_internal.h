@@ -94,10 +94,65 @@ struct Geom {
     const DCurve* curves() const { return reinterpret_cast<const DCurve*>(base + L.off_curve); }
 };
 
+// ---------------------------------------------------------------------------
+// Surfaces: bicubic patches of tensor-product B-spline surfaces
+// ---------------------------------------------------------------------------
+// Per-surface record in device memory.
+struct DSurf {
+    int64_t patch_off;   // first bicubic patch (global)
+    int64_t span_off;    // first exact span patch (global); u-span major, n_su x n_sv
+    int64_t coef_off;    // first double of the exact span patches' power coefficients
+    int64_t brk_off;     // first double of the breakpoints: n_su + 1 in u, then n_sv + 1 in v
+    int32_t n_patch;
+    int32_t n_su, n_sv;  // exact span grid
+    int32_t deg_u, deg_v;
+    int32_t pad;
+    double tol_eff;      // deviation bound of the patches from the exact surface
+    double tol_user;     // tol_rel * diag
+    double diag;         // control-net box diagonal
+    double origin[3];    // FP32-representable box centre
+};
+static_assert(sizeof(DSurf) == 104, "DSurf layout");
+
+struct SurfLayout {
+    int64_t n_surf = 0, n_patch = 0, n_span = 0, n_coef = 0, n_brk = 0;
+    int64_t off_surf = 0;   // DSurf[n_surf]
+    int64_t off_sph = 0;    // float4[n_patch]      centre (relative to the surface origin), radius
+    int64_t off_lcp = 0;    // float[n_patch][48]  control net minus centre (u-major, 4 x 4 x xyz)
+    int64_t off_gcp = 0;    // double[n_patch][48] control net (global)
+    int64_t off_uv = 0;     // double[n_patch][4]  (u_a, u_b, v_a, v_b)
+    int64_t off_pspan = 0;  // int32[n_patch]      exact span patch (global)
+    int64_t off_span0 = 0;  // int32[n_span + 1]   first patch of each exact span patch (global)
+    int64_t off_brk = 0;    // double[n_brk]
+    int64_t off_coef = 0;   // double[n_coef]      exact span patches: power coefficients in local (s, t)
+    int64_t total = 0;
+};
+
+struct SurfPlan {
+    int64_t n_surf = 0;
+    double tol_rel = 0;
+    int32_t max_degree = 0;
+    std::vector<DSurf> surfs;
+    std::vector<double> gcp, uv, brk, coef;
+    std::vector<int32_t> pspan, span0;
+    std::vector<float> sph, lcp;
+    SurfLayout layout;
+};
+
+struct SurfGeom {
+    SurfLayout L;
+    char* base = nullptr;
+    int device = 0;
+};
+
 // host decomposition (mrep_host.cpp)
 int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
                const int64_t* knot_off, const double* knots, double tol_rel, int n_threads, Plan& plan,
                std::string& err);
+int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u,
+                    const int32_t* n_v, const int64_t* cp_off, const double* cp_xyz, const int64_t* ku_off,
+                    const double* ku, const int64_t* kv_off, const double* kv, double tol_rel, int n_threads,
+                    SurfPlan& plan, std::string& err);
 void bernstein_matrix(int p, double* B);      // (p+1)^2, power coeffs of each Bernstein function
 void bernstein_inverse(int p, double* Bi);    // power -> Bernstein
 void subdivision_matrix(int p, double z, double* S);

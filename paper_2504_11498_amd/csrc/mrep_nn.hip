@@ -1215,8 +1215,8 @@ int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const fl
 
 int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
 {
-    if (!geom || !bytes || n < 0) {
-        set_error("mrep_seeded_workspace_bytes: null pointer or negative n");
+    if (!geom || !bytes || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_seeded_workspace_bytes: null pointer, surface geometry or negative n");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
@@ -1228,8 +1228,8 @@ int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep
 int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz,
                          int32_t* seg_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream)
 {
-    if (!geom || n < 0) {
-        set_error("mrep_nn_features: null geometry or negative n");
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_nn_features: null or surface geometry, or negative n");
         return MREP_E_INVALID_ARG;
     }
     if (n == 0) return MREP_OK;
@@ -1268,8 +1268,8 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
                                    const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
                                    double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream)
 {
-    if (!geom || n < 0) {
-        set_error("mrep_project_curves_seeded: null geometry or negative n");
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_project_curves_seeded: null or surface geometry, or negative n");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);

@@ -1,0 +1,1036 @@
+// Surface projection and inversion on gfx950: tensor-product B-spline surfaces
+// decomposed (host, FP64) into bicubic Bezier patches, the surface case of the
+// paper's matrix representation (Sec. 5.2.1 applied in u and in v).
+//
+// Pipeline for n queries, each onto its own surface:
+//   1. group queries by surface (counting sort, shared with the curve path);
+//   2. sphere candidates: every patch lies in a sphere (centre, radius bound
+//      incl. its deviation from the exact surface); per query, the pieces
+//      whose lower bound |q - c| - r reaches the best upper bound |q - c| + r
+//      plus the tie margin are listed as (query, patch) pairs;
+//   3. per pair, the certified minimum of |S(s,t) - q|^2 over the patch in
+//      FP32: a 7 x 7 sample grid, box-constrained Newton on the stationarity
+//      conditions (S - q).S_s = (S - q).S_t = 0 from its local minima, the four
+//      edge curves by the curve path's certified 1D minimum, and a Newton solve
+//      in every grid cell whose second-order lower bound
+//      min(corner f) - (M_ss h^2 + M_tt h^2) / 8 still beats the best;
+//   4. per query, the two best pairs; FP64 box-constrained Newton on the EXACT
+//      span patch (power form of degree (p, q)) from the best, continuing into
+//      a neighbouring span patch when the minimiser sits on a shared edge with
+//      the gradient pointing across, and from the runner-up when it is within
+//      the tie margin; write (u, v), distance, patch index and flags.
+// Queries whose list overflows take a wave-per-query scan of all their patches.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/mrep.h"
+#include "mrep_dev.h"
+#include "mrep_refine.h"
+
+using namespace mrep;
+
+namespace {
+
+constexpr int kSphSub = 8;
+constexpr int kSphThreads = kQueriesPerTile * kSphSub;
+constexpr int kSphChunk = 1024;
+constexpr int kSphCap = 64;
+constexpr int kXcds = 8;
+constexpr int64_t kSurfPairsPerQuery = 24;
+constexpr int kGrid = 7;  // samples per direction in a patch
+static_assert(kSphThreads == 256, "sphere kernel: 32 queries x 8 lanes");
+
+struct DevSurf {
+    const DSurf* surfs;
+    const float4* sph;
+    const float* lcp;
+    const double* gcp;
+    const double* uv;
+    const int32_t* pspan;
+    const int32_t* span0;
+    const double* brk;
+    const double* coef;
+    int32_t n_surf;
+    int64_t n_patch;
+};
+
+DevSurf surf_view(const SurfGeom& g)
+{
+    DevSurf d;
+    d.surfs = reinterpret_cast<const DSurf*>(g.base + g.L.off_surf);
+    d.sph = reinterpret_cast<const float4*>(g.base + g.L.off_sph);
+    d.lcp = reinterpret_cast<const float*>(g.base + g.L.off_lcp);
+    d.gcp = reinterpret_cast<const double*>(g.base + g.L.off_gcp);
+    d.uv = reinterpret_cast<const double*>(g.base + g.L.off_uv);
+    d.pspan = reinterpret_cast<const int32_t*>(g.base + g.L.off_pspan);
+    d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
+    d.brk = reinterpret_cast<const double*>(g.base + g.L.off_brk);
+    d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
+    d.n_surf = (int32_t)g.L.n_surf;
+    d.n_patch = g.L.n_patch;
+    return d;
+}
+
+__device__ __forceinline__ float s_margin(float d, const DSurf& sf, float tie_rel)
+{
+    return 2.f * (float)sf.tol_eff + 4e-6f * (d + (float)sf.diag) + tie_rel * (float)sf.diag;
+}
+
+// ---------------------------------------------------------------------------
+// 2. sphere candidate lists
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* __restrict__ tile_off,
+                                                      const int32_t* __restrict__ q_off,
+                                                      const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ qxyz, float tie_rel, ScreenOut so)
+{
+    __shared__ float4 s_sph[kSphChunk];
+    __shared__ int32_t s_list[kQueriesPerTile][kSphCap];
+    __shared__ int32_t s_base[kQueriesPerTile];
+    const int n_tiles = tile_off[D.n_surf];
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    const int slot = (int)(blockIdx.x / kXcds);
+    const int tile = (int)(blockIdx.x % kXcds) * per + slot;
+    if (slot >= per || tile >= n_tiles) return;
+    int lo_c = 0, hi_c = D.n_surf;
+    while (hi_c - lo_c > 1) {
+        const int mid = (lo_c + hi_c) >> 1;
+        if (tile_off[mid] <= tile) lo_c = mid; else hi_c = mid;
+    }
+    const DSurf sf = D.surfs[lo_c];
+    const int lane = threadIdx.x & 63;
+    const int qs = threadIdx.x / kSphSub, sub = threadIdx.x % kSphSub;
+    const int64_t j = (int64_t)q_off[lo_c] + (int64_t)(tile - tile_off[lo_c]) * kQueriesPerTile + qs;
+    const bool active = j < q_off[lo_c + 1];
+    float ql[3] = {0.f, 0.f, 0.f};
+    if (active) {
+        const int32_t qi = perm[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - sf.origin[k]);
+    }
+    const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
+    float ub = INFINITY, thr = 0.f;
+    int cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int c0 = 0; c0 < sf.n_patch; c0 += kSphChunk) {
+            const int cn = min(kSphChunk, sf.n_patch - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < cn; i += kSphThreads) s_sph[i] = D.sph[sf.patch_off + c0 + i];
+            __syncthreads();
+            if (!active) continue;
+            if (pass == 0) {
+                for (int i = sub; i < cn; i += kSphSub) {
+                    const float4 p = s_sph[i];
+                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                    const float tu = ub - p.w - eps;
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    if (!(tu > 0.f) || d2 < tu * tu) ub = fminf(ub, sqrtf(d2) + p.w + eps);
+                }
+            } else {
+                for (int i0 = 0; i0 < cn; i0 += kSphSub) {
+                    const int i = i0 + sub;
+                    bool hit = false;
+                    if (i < cn) {
+                        const float4 p = s_sph[i];
+                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                        const float tt = thr + p.w + eps;
+                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                    }
+                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                    if (hit && pos < kSphCap) s_list[qs][pos] = c0 + i;
+                    cnt += __popc(grp);
+                }
+            }
+        }
+        if (pass == 0) {
+#pragma unroll
+            for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
+            thr = ub + s_margin(ub, sf, tie_rel);
+        }
+    }
+    const bool listed = active && cnt <= kSphCap;
+    if (sub == 0) s_base[qs] = listed ? cnt : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) {
+            const int v = s_base[k];
+            s_base[k] = tot;
+            tot += v;
+        }
+        const int base = tot > 0 ? atomicAdd(so.pair_count, tot) : 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) s_base[k] += base;
+    }
+    __syncthreads();
+    if (!active) return;
+    const int64_t b = s_base[qs];
+    const bool fits = listed && b + cnt <= so.pair_cap;
+    if (sub == 0) {
+        so.cand_n[j] = fits ? cnt : -1;
+        so.pair_off[j] = (int32_t)b;
+        so.ub[j] = ub;
+    }
+    if (listed) {
+        for (int k = sub; k < cnt; k += kSphSub) {
+            if (b + k >= so.pair_cap) break;
+            so.pair_seg[b + k] = fits ? (int32_t)(sf.patch_off + s_list[qs][k]) : 0;
+            so.pair_j[b + k] = fits ? (int32_t)j : -1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. certified minimum of one bicubic patch (FP32, local frame)
+// ---------------------------------------------------------------------------
+// Power form relative to the query: S(s,t) - q = sum_{a,b} C[a][b] s^a t^b.
+struct Bicubic {
+    float C[4][4][3];
+    float Ls, Lt, Lss, Ltt, far;  // |S_s|, |S_t|, |S_ss|, |S_tt| bounds; max |P - q|
+};
+
+__device__ __forceinline__ void load_bicubic(const DevSurf& D, const DSurf& sf, int64_t k, const double* q, Bicubic& B)
+{
+    const float* lp = D.lcp + k * 48;
+    const float4 c = D.sph[k];
+    const float ql[3] = {(float)(q[0] - (sf.origin[0] + (double)c.x)), (float)(q[1] - (sf.origin[1] + (double)c.y)),
+                         (float)(q[2] - (sf.origin[2] + (double)c.z))};
+    float P[4][4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) P[i][j][x] = lp[3 * (4 * i + j) + x] - ql[x];
+    // hodograph bounds
+    float ls = 0.f, lt = 0.f, lss = 0.f, ltt = 0.f, far = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            far = fmaxf(far, P[i][j][0] * P[i][j][0] + P[i][j][1] * P[i][j][1] + P[i][j][2] * P[i][j][2]);
+            if (i < 3) {
+                const float a = P[i + 1][j][0] - P[i][j][0], b = P[i + 1][j][1] - P[i][j][1], e = P[i + 1][j][2] - P[i][j][2];
+                ls = fmaxf(ls, a * a + b * b + e * e);
+            }
+            if (j < 3) {
+                const float a = P[i][j + 1][0] - P[i][j][0], b = P[i][j + 1][1] - P[i][j][1], e = P[i][j + 1][2] - P[i][j][2];
+                lt = fmaxf(lt, a * a + b * b + e * e);
+            }
+            if (i < 2) {
+                const float a = P[i + 2][j][0] - 2.f * P[i + 1][j][0] + P[i][j][0];
+                const float b = P[i + 2][j][1] - 2.f * P[i + 1][j][1] + P[i][j][1];
+                const float e = P[i + 2][j][2] - 2.f * P[i + 1][j][2] + P[i][j][2];
+                lss = fmaxf(lss, a * a + b * b + e * e);
+            }
+            if (j < 2) {
+                const float a = P[i][j + 2][0] - 2.f * P[i][j + 1][0] + P[i][j][0];
+                const float b = P[i][j + 2][1] - 2.f * P[i][j + 1][1] + P[i][j][1];
+                const float e = P[i][j + 2][2] - 2.f * P[i][j + 1][2] + P[i][j][2];
+                ltt = fmaxf(ltt, a * a + b * b + e * e);
+            }
+        }
+    B.Ls = 3.f * sqrtf(ls);
+    B.Lt = 3.f * sqrtf(lt);
+    B.Lss = 6.f * sqrtf(lss);
+    B.Ltt = 6.f * sqrtf(ltt);
+    B.far = sqrtf(far);
+    // Bernstein -> power in each direction: rows of M are (1,0,0,0) (-3,3,0,0) (3,-6,3,0) (-1,3,-3,1)
+    const float M[4][4] = {{1.f, 0.f, 0.f, 0.f}, {-3.f, 3.f, 0.f, 0.f}, {3.f, -6.f, 3.f, 0.f}, {-1.f, 3.f, -3.f, 1.f}};
+    float T[4][4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                float s = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s += M[a][i] * P[i][j][x];
+                T[a][j][x] = s;
+            }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s += M[b][j] * T[a][j][x];
+                B.C[a][b][x] = s;
+            }
+}
+
+__device__ __forceinline__ float bc_f(const Bicubic& B, float s, float t)
+{
+    float r = 0.f;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 3; a >= 0; --a) {
+            const float d = B.C[a][0][x] + t * (B.C[a][1][x] + t * (B.C[a][2][x] + t * B.C[a][3][x]));
+            acc = acc * s + d;
+        }
+        r += acc * acc;
+    }
+    return r;
+}
+
+// value, gradient of f/2 = (S-q).S_s, (S-q).S_t, Hessian of f/2, metric
+struct BcEval {
+    float f, gs, gt, h11, h12, h22, g11, g12, g22;
+};
+
+__device__ __forceinline__ BcEval bc_eval(const Bicubic& B, float s, float t)
+{
+    float r[3], Ss[3], St[3], Sss[3], Sst[3], Stt[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        float D[4], D1[4], D2[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            D[a] = B.C[a][0][x] + t * (B.C[a][1][x] + t * (B.C[a][2][x] + t * B.C[a][3][x]));
+            D1[a] = B.C[a][1][x] + t * (2.f * B.C[a][2][x] + t * 3.f * B.C[a][3][x]);
+            D2[a] = 2.f * B.C[a][2][x] + t * 6.f * B.C[a][3][x];
+        }
+        r[x] = D[0] + s * (D[1] + s * (D[2] + s * D[3]));
+        Ss[x] = D[1] + s * (2.f * D[2] + s * 3.f * D[3]);
+        Sss[x] = 2.f * D[2] + s * 6.f * D[3];
+        St[x] = D1[0] + s * (D1[1] + s * (D1[2] + s * D1[3]));
+        Sst[x] = D1[1] + s * (2.f * D1[2] + s * 3.f * D1[3]);
+        Stt[x] = D2[0] + s * (D2[1] + s * (D2[2] + s * D2[3]));
+    }
+    BcEval e;
+    e.f = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    e.gs = r[0] * Ss[0] + r[1] * Ss[1] + r[2] * Ss[2];
+    e.gt = r[0] * St[0] + r[1] * St[1] + r[2] * St[2];
+    e.g11 = Ss[0] * Ss[0] + Ss[1] * Ss[1] + Ss[2] * Ss[2];
+    e.g12 = Ss[0] * St[0] + Ss[1] * St[1] + Ss[2] * St[2];
+    e.g22 = St[0] * St[0] + St[1] * St[1] + St[2] * St[2];
+    e.h11 = e.g11 + r[0] * Sss[0] + r[1] * Sss[1] + r[2] * Sss[2];
+    e.h12 = e.g12 + r[0] * Sst[0] + r[1] * Sst[1] + r[2] * Sst[2];
+    e.h22 = e.g22 + r[0] * Stt[0] + r[1] * Stt[1] + r[2] * Stt[2];
+    return e;
+}
+
+// smallest eigenvalue of the Hessian of f/2 relative to the metric (1 if degenerate)
+template <typename T>
+__device__ __forceinline__ T rel_curv(T h11, T h12, T h22, T g11, T g12, T g22)
+{
+    const T dg = g11 * g22 - g12 * g12;
+    if (!(dg > (T)0)) return (T)1;
+    const T tr = (g22 * h11 - (T)2 * g12 * h12 + g11 * h22) / dg;
+    const T dt = (h11 * h22 - h12 * h12) / dg;
+    const T disc = tr * tr - (T)4 * dt;
+    return (T)0.5 * (tr - sqrt(disc > (T)0 ? disc : (T)0));
+}
+
+struct PatchMin {
+    float s, t, f, kappa;
+};
+
+__device__ __forceinline__ void pm_take(PatchMin& best, float s, float t, float f, float k)
+{
+    if (f < best.f) { best.s = s; best.t = t; best.f = f; best.kappa = k; }
+}
+
+// Box-constrained Newton on [lo_s, hi_s] x [lo_t, hi_t] from (s, t): a
+// coordinate on a side with the gradient pointing outward is held there.
+__device__ void bc_newton(const Bicubic& B, float s, float t, float lo_s, float hi_s, float lo_t, float hi_t,
+                          PatchMin& best)
+{
+    BcEval e = bc_eval(B, s, t);
+    for (int it = 0; it < 16; ++it) {
+        // active set: a coordinate on a side whose gradient points outward stays there
+        const bool fs = (s == lo_s && e.gs > 0.f) || (s == hi_s && e.gs < 0.f);
+        const bool ft = (t == lo_t && e.gt > 0.f) || (t == hi_t && e.gt < 0.f);
+        if (fs && ft) break;
+        float ds = 0.f, dt = 0.f;
+        if (!fs && !ft) {
+            // where the distance is not convex, shift the Hessian by a multiple of the
+            // metric (Levenberg-Marquardt) so that its smallest relative curvature is 1e-3
+            float h11 = e.h11, h12 = e.h12, h22 = e.h22;
+            const float lam = rel_curv(h11, h12, h22, e.g11, e.g12, e.g22);
+            if (lam < 1e-3f) {
+                const float mu = 1e-3f - lam;
+                h11 += mu * e.g11; h12 += mu * e.g12; h22 += mu * e.g22;
+            }
+            const float det = h11 * h22 - h12 * h12;
+            if (det > 0.f && h11 > 0.f) {
+                ds = -(h22 * e.gs - h12 * e.gt) / det;
+                dt = -(h11 * e.gt - h12 * e.gs) / det;
+            } else {
+                ds = -e.gs / (e.g11 + 1e-30f);
+                dt = -e.gt / (e.g22 + 1e-30f);
+            }
+        } else if (!fs) {
+            ds = -e.gs / fmaxf(e.h11, 1e-3f * e.g11 + 1e-30f);
+        } else {
+            dt = -e.gt / fmaxf(e.h22, 1e-3f * e.g22 + 1e-30f);
+        }
+        const float lim = 0.25f;
+        const float m = fmaxf(fabsf(ds), fabsf(dt));
+        if (m > lim) { ds *= lim / m; dt *= lim / m; }
+        float sn = fminf(fmaxf(s + ds, lo_s), hi_s), tn = fminf(fmaxf(t + dt, lo_t), hi_t);
+        BcEval en = bc_eval(B, sn, tn);
+        for (int bt = 0; bt < 4 && en.f > e.f; ++bt) {
+            ds *= 0.5f;
+            dt *= 0.5f;
+            sn = fminf(fmaxf(s + ds, lo_s), hi_s);
+            tn = fminf(fmaxf(t + dt, lo_t), hi_t);
+            en = bc_eval(B, sn, tn);
+        }
+        if (en.f > e.f) break;
+        const float step = fabsf(sn - s) + fabsf(tn - t);
+        s = sn;
+        t = tn;
+        e = en;
+        if (step <= 1e-7f) break;
+    }
+    const bool interior = s > 0.f && s < 1.f && t > 0.f && t < 1.f;
+    pm_take(best, s, t, e.f, interior ? rel_curv(e.h11, e.h12, e.h22, e.g11, e.g12, e.g22) : 1.f);
+}
+
+// one edge of the patch as a cubic curve relative to the query
+__device__ __forceinline__ void bc_edge(const Bicubic& B, int which, Cubic<float>& E)
+{
+    float c[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            float v = 0.f;
+            if (which == 0) v = B.C[0][k][x];                                                       // s = 0, along t
+            else if (which == 1) v = B.C[0][k][x] + B.C[1][k][x] + B.C[2][k][x] + B.C[3][k][x];     // s = 1
+            else if (which == 2) v = B.C[k][0][x];                                                  // t = 0, along s
+            else v = B.C[k][0][x] + B.C[k][1][x] + B.C[k][2][x] + B.C[k][3][x];                     // t = 1
+            c[k][x] = v;
+        }
+    E.a0 = {c[0][0], c[0][1], c[0][2]};
+    E.a1 = {c[1][0], c[1][1], c[1][2]};
+    E.a2 = {c[2][0], c[2][1], c[2][2]};
+    E.a3 = {c[3][0], c[3][1], c[3][2]};
+}
+
+__device__ PatchMin patch_min(const Bicubic& B)
+{
+    PatchMin best{0.f, 0.f, INFINITY, 1.f};
+    // edges: certified 1D minima of the four boundary curves
+    for (int w = 0; w < 4; ++w) {
+        Cubic<float> E;
+        bc_edge(B, w, E);
+        float u, d, k;
+        piece_min(E, u, d, k);
+        const float s = w == 0 ? 0.f : (w == 1 ? 1.f : u);
+        const float t = w == 2 ? 0.f : (w == 3 ? 1.f : u);
+        pm_take(best, s, t, d, 1.f);
+    }
+    const float h = 1.f / (kGrid - 1);
+    float F[kGrid][kGrid];
+#pragma unroll
+    for (int i = 0; i < kGrid; ++i)
+#pragma unroll
+        for (int j = 0; j < kGrid; ++j) F[i][j] = bc_f(B, i * h, j * h);
+    // Newton from the interior local minima of the samples; the four cells
+    // around such a sample count as covered
+    uint64_t covered = 0;  // bit i*(kGrid-1)+j: cell (i, j)
+    for (int i = 1; i < kGrid - 1; ++i)
+        for (int j = 1; j < kGrid - 1; ++j) {
+            const float v = F[i][j];
+            bool m = true;
+#pragma unroll
+            for (int a = -1; a <= 1; ++a)
+#pragma unroll
+                for (int b = -1; b <= 1; ++b)
+                    if ((a || b) && F[i + a][j + b] < v) m = false;
+            if (!m) continue;
+            bc_newton(B, i * h, j * h, 0.f, 1.f, 0.f, 1.f, best);
+            covered |= 1ull << ((i - 1) * (kGrid - 1) + (j - 1));
+            covered |= 1ull << ((i - 1) * (kGrid - 1) + j);
+            covered |= 1ull << (i * (kGrid - 1) + (j - 1));
+            covered |= 1ull << (i * (kGrid - 1) + j);
+        }
+    // second-order bound of each cell: f >= min(corners) - (M_ss + M_tt) h^2 / 8
+    const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
+    const float gap = (Mss + Mtt) * h * h * 0.125f;
+    for (int i = 0; i < kGrid - 1; ++i)
+        for (int j = 0; j < kGrid - 1; ++j) {
+            if ((covered >> (i * (kGrid - 1) + j)) & 1ull) continue;
+            const float mn = fminf(fminf(F[i][j], F[i + 1][j]), fminf(F[i][j + 1], F[i + 1][j + 1]));
+            if (mn - gap < best.f * (1.f - 8e-6f))
+                bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
+        }
+    return best;
+}
+
+// One thread per (query, patch) pair.
+__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
+                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
+                                                ScreenOut so, float4* __restrict__ res)
+{
+    const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t jj = so.pair_j[p];
+        if (jj < 0) continue;
+        const int64_t k = so.pair_seg[p];
+        if (k < 0 || k >= D.n_patch) continue;
+        const int32_t qi = perm[jj];
+        const DSurf sf = D.surfs[sid[qi]];
+        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        Bicubic B;
+        load_bicubic(D, sf, k, q, B);
+        const PatchMin m = patch_min(B);
+        res[p] = make_float4(m.s, m.t, m.f, m.kappa);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. FP64 polish on the exact span patch, finish
+// ---------------------------------------------------------------------------
+struct SCand {
+    double u, v, d2, kappa;
+    int64_t patch;
+};
+
+__device__ __forceinline__ bool s_better(const SCand& a, const SCand& b)
+{
+    return a.d2 < b.d2 || (a.d2 == b.d2 && (a.u < b.u || (a.u == b.u && a.v < b.v)));
+}
+
+__device__ __forceinline__ void s_sel(bool c, const SCand& a, SCand& d)
+{
+    d.u = c ? a.u : d.u;
+    d.v = c ? a.v : d.v;
+    d.d2 = c ? a.d2 : d.d2;
+    d.kappa = c ? a.kappa : d.kappa;
+    d.patch = c ? a.patch : d.patch;
+}
+
+__device__ __forceinline__ void s_top2(const SCand& x, SCand& b1, SCand& b2)
+{
+    const bool first = s_better(x, b1);
+    const bool second = !first && s_better(x, b2);
+    s_sel(first, b1, b2);
+    s_sel(second, x, b2);
+    s_sel(first, x, b1);
+}
+
+__device__ __forceinline__ SCand s_empty()
+{
+    SCand c;
+    c.u = c.v = 0.0;
+    c.d2 = INFINITY;
+    c.kappa = 1.0;
+    c.patch = -1;
+    return c;
+}
+
+__device__ __forceinline__ SCand s_make(const DevSurf& D, int64_t k, float s, float t, float f, float kap)
+{
+    const double* r = D.uv + 4 * k;
+    SCand c;
+    c.u = s == 1.f ? r[1] : r[0] + (double)s * (r[1] - r[0]);
+    c.v = t == 1.f ? r[3] : r[2] + (double)t * (r[3] - r[2]);
+    c.d2 = (double)f;
+    c.kappa = (double)kap;
+    c.patch = k;
+    return c;
+}
+
+// Exact span patch (degree p x q, power form in local (s, t)) minus the query.
+struct ExactEval {
+    double f, gs, gt, h11, h12, h22, g11, g12, g22;
+};
+
+__device__ ExactEval exact_eval(const double* cf, int p, int q, const double* x, double s, double t)
+{
+    double r[3], Ss[3], St[3], Sss[3], Sst[3], Stt[3];
+    for (int c = 0; c < 3; ++c) {
+        // Horner in s of D_a(t), D_a'(t), D_a''(t)
+        double v = 0, vs = 0, vss = 0, vt = 0, vst = 0, vtt = 0;
+        for (int a = p; a >= 0; --a) {
+            double d = 0, d1 = 0, d2 = 0;
+            for (int b = q; b >= 0; --b) {
+                const double cc = cf[3 * (a * (q + 1) + b) + c];
+                d2 = d2 * t + 2.0 * d1;
+                d1 = d1 * t + d;
+                d = d * t + cc;
+            }
+            vss = vss * s + 2.0 * vs;
+            vs = vs * s + v;
+            v = v * s + d;
+            vst = vst * s + vt;
+            vt = vt * s + d1;
+            vtt = vtt * s + d2;
+        }
+        r[c] = v - x[c];
+        Ss[c] = vs;
+        Sss[c] = vss;
+        St[c] = vt;
+        Sst[c] = vst;
+        Stt[c] = vtt;
+    }
+    ExactEval e;
+    e.f = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    e.gs = r[0] * Ss[0] + r[1] * Ss[1] + r[2] * Ss[2];
+    e.gt = r[0] * St[0] + r[1] * St[1] + r[2] * St[2];
+    e.g11 = Ss[0] * Ss[0] + Ss[1] * Ss[1] + Ss[2] * Ss[2];
+    e.g12 = Ss[0] * St[0] + Ss[1] * St[1] + Ss[2] * St[2];
+    e.g22 = St[0] * St[0] + St[1] * St[1] + St[2] * St[2];
+    e.h11 = e.g11 + r[0] * Sss[0] + r[1] * Sss[1] + r[2] * Sss[2];
+    e.h12 = e.g12 + r[0] * Sst[0] + r[1] * Sst[1] + r[2] * Sst[2];
+    e.h22 = e.g22 + r[0] * Stt[0] + r[1] * Stt[1] + r[2] * Stt[2];
+    return e;
+}
+
+// span index of parameter w among n spans with breakpoints b[0..n]
+__device__ __forceinline__ int span_of(const double* b, int n, double w)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b[mid] <= w) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+struct Polished {
+    double u, v, dist, kappa;
+};
+
+// FP64 box-constrained Newton on the exact span patch holding (u, v); moves to
+// the neighbouring span patch (at most 4 times) when it stops on a shared edge
+// with the gradient pointing across it.
+__device__ Polished s_polish(const DevSurf& D, const DSurf& sf, double u, double v, const double* x)
+{
+    const double* bu = D.brk + sf.brk_off;
+    const double* bv = bu + sf.n_su + 1;
+    int iu = span_of(bu, sf.n_su, u), iv = span_of(bv, sf.n_sv, v);
+    const int p = sf.deg_u, q = sf.deg_v;
+    double s = 0, t = 0;
+    ExactEval e;
+    for (int hop = 0; hop < 5; ++hop) {
+        const double ua = bu[iu], ub = bu[iu + 1], va = bv[iv], vb = bv[iv + 1];
+        const double* cf = D.coef + sf.coef_off + (int64_t)(iu * sf.n_sv + iv) * 3 * (p + 1) * (q + 1);
+        s = fmin(fmax((u - ua) / (ub - ua), 0.0), 1.0);
+        t = fmin(fmax((v - va) / (vb - va), 0.0), 1.0);
+        e = exact_eval(cf, p, q, x, s, t);
+        for (int it = 0; it < 60; ++it) {
+            // active set: a coordinate on a side whose gradient points outward stays there
+            const bool fs = (s == 0.0 && e.gs > 0.0) || (s == 1.0 && e.gs < 0.0);
+            const bool ft = (t == 0.0 && e.gt > 0.0) || (t == 1.0 && e.gt < 0.0);
+            if (fs && ft) break;
+            double ds = 0, dt = 0;
+            if (!fs && !ft) {
+                double h11 = e.h11, h12 = e.h12, h22 = e.h22;
+                const double lam = rel_curv(h11, h12, h22, e.g11, e.g12, e.g22);
+                if (lam < 1e-3) {  // Levenberg-Marquardt shift where the distance is not convex
+                    const double mu = 1e-3 - lam;
+                    h11 += mu * e.g11; h12 += mu * e.g12; h22 += mu * e.g22;
+                }
+                const double det = h11 * h22 - h12 * h12;
+                if (det > 0.0 && h11 > 0.0) {
+                    ds = -(h22 * e.gs - h12 * e.gt) / det;
+                    dt = -(h11 * e.gt - h12 * e.gs) / det;
+                } else {
+                    ds = -e.gs / (e.g11 + 1e-300);
+                    dt = -e.gt / (e.g22 + 1e-300);
+                }
+            } else if (!fs) {
+                ds = -e.gs / fmax(e.h11, 1e-3 * e.g11 + 1e-300);
+            } else {
+                dt = -e.gt / fmax(e.h22, 1e-3 * e.g22 + 1e-300);
+            }
+            const double m = fmax(fabs(ds), fabs(dt));
+            if (m > 0.25) { ds *= 0.25 / m; dt *= 0.25 / m; }
+            double sn = fmin(fmax(s + ds, 0.0), 1.0), tn = fmin(fmax(t + dt, 0.0), 1.0);
+            ExactEval en = exact_eval(cf, p, q, x, sn, tn);
+            for (int bt = 0; bt < 30 && en.f > e.f; ++bt) {
+                ds *= 0.5;
+                dt *= 0.5;
+                sn = fmin(fmax(s + ds, 0.0), 1.0);
+                tn = fmin(fmax(t + dt, 0.0), 1.0);
+                en = exact_eval(cf, p, q, x, sn, tn);
+            }
+            if (en.f > e.f) break;
+            const double step = fabs(sn - s) + fabs(tn - t);
+            s = sn;
+            t = tn;
+            e = en;
+            if (step <= 1e-15) break;
+        }
+        u = s == 1.0 ? ub : ua + s * (ub - ua);
+        v = t == 1.0 ? vb : va + t * (vb - va);
+        // continue across a shared edge when the gradient points across it
+        int niu = iu, niv = iv;
+        if (s == 0.0 && e.gs > 0.0 && iu > 0) niu = iu - 1;
+        else if (s == 1.0 && e.gs < 0.0 && iu < sf.n_su - 1) niu = iu + 1;
+        if (t == 0.0 && e.gt > 0.0 && iv > 0) niv = iv - 1;
+        else if (t == 1.0 && e.gt < 0.0 && iv < sf.n_sv - 1) niv = iv + 1;
+        if (niu == iu && niv == iv) break;
+        iu = niu;
+        iv = niv;
+    }
+    Polished r;
+    r.u = u;
+    r.v = v;
+    r.dist = sqrt(e.f);
+    const bool interior = s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0;
+    r.kappa = interior ? rel_curv(e.h11, e.h12, e.h22, e.g11, e.g12, e.g22) : 1.0;
+    return r;
+}
+
+struct SOuts {
+    double* uv;
+    double* d;
+    int32_t* patch;
+    uint32_t* f;
+};
+
+__device__ void s_finish(const DevSurf& D, const DSurf& sf, const double* x, const SCand& b1, const SCand& b2,
+                         uint32_t flags, double tie_rel, int invert, int32_t qi, const SOuts& o)
+{
+    const double d1 = sqrt(b1.d2), d2 = sqrt(b2.d2);
+    const double margin = 2.0 * sf.tol_eff + 2e-6 * (d1 + sf.diag) + tie_rel * sf.diag;
+    const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
+    flags |= MREP_F_POLISHED;
+    Polished r = s_polish(D, sf, b1.u, b1.v, x);
+    if (tie) {
+        const Polished r2 = s_polish(D, sf, b2.u, b2.v, x);
+        const bool take = r2.dist < r.dist || (r2.dist == r.dist && (r2.u < r.u || (r2.u == r.u && r2.v < r.v)));
+        const double sep = fabs(r2.u - r.u) + fabs(r2.v - r.v);
+        if (fabs(r2.dist - r.dist) <= tie_rel * sf.diag && sep > 1e-6) flags |= MREP_F_NEAR_TIE;
+        if (take) r = r2;
+    }
+    if (r.kappa < 1e-2) flags |= MREP_F_ILL_COND;
+    // patch holding (u, v): among the pieces of its exact span patch, half-open
+    // rectangles closed at the surface's far sides
+    const double* bu = D.brk + sf.brk_off;
+    const double* bv = bu + sf.n_su + 1;
+    const int iu = span_of(bu, sf.n_su, r.u), iv = span_of(bv, sf.n_sv, r.v);
+    const int64_t sp = sf.span_off + (int64_t)iu * sf.n_sv + iv;
+    int64_t patch = D.span0[sp];
+    for (int64_t k = D.span0[sp]; k < D.span0[sp + 1]; ++k) {
+        const double* rc = D.uv + 4 * k;
+        const bool in_u = r.u >= rc[0] && (r.u < rc[1] || (rc[1] == bu[sf.n_su] && r.u <= rc[1]));
+        const bool in_v = r.v >= rc[2] && (r.v < rc[3] || (rc[3] == bv[sf.n_sv] && r.v <= rc[3]));
+        if (in_u && in_v) { patch = k; break; }
+    }
+    const double u0 = bu[0], u1 = bu[sf.n_su], v0 = bv[0], v1 = bv[sf.n_sv];
+    if (r.u <= u0 + 1e-12 * (u1 - u0) || r.u >= u1 - 1e-12 * (u1 - u0) || r.v <= v0 + 1e-12 * (v1 - v0) ||
+        r.v >= v1 - 1e-12 * (v1 - v0))
+        flags |= MREP_F_ENDPOINT;
+    if (invert && r.dist > sf.tol_user) flags |= MREP_F_OFFCURVE;
+    o.uv[2 * (int64_t)qi] = r.u;
+    o.uv[2 * (int64_t)qi + 1] = r.v;
+    o.d[qi] = r.dist;
+    o.patch[qi] = (int32_t)(patch - sf.patch_off);
+    o.f[qi] = flags;
+}
+
+__global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __restrict__ sid,
+                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
+                                                 const int32_t* __restrict__ perm, ScreenOut so,
+                                                 const float4* __restrict__ res, double tie_rel, int32_t invert,
+                                                 int32_t* __restrict__ ovf_list, int32_t* __restrict__ ovf_count,
+                                                 SOuts o)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[D.n_surf]) return;
+    const int n_list = so.cand_n[j];
+    if (n_list <= 0) {
+        ovf_list[atomicAdd(ovf_count, 1)] = (int32_t)j;
+        return;
+    }
+    const int32_t qi = perm[j];
+    const DSurf sf = D.surfs[sid[qi]];
+    const double x[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    SCand b1 = s_empty(), b2 = b1;
+    const int64_t p0 = so.pair_off[j];
+    for (int i = 0; i < n_list; ++i) {
+        const float4 r = res[p0 + i];
+        s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
+    }
+    s_finish(D, sf, x, b1, b2, 0u, tie_rel, invert, qi, o);
+}
+
+// Overflowed lists: one wave per query over all its patches (sphere bound
+// against the wave's best sphere upper bound, then the patch minimum).
+__global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restrict__ sid,
+                                               const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ list, const int32_t* __restrict__ count,
+                                               double tie_rel, int32_t invert, SOuts o)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t total = *count;
+    for (int64_t item = wave; item < total; item += nwaves) {
+        const int32_t qi = perm[list[item]];
+        const DSurf sf = D.surfs[sid[qi]];
+        const double x[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        const float ql[3] = {(float)(x[0] - sf.origin[0]), (float)(x[1] - sf.origin[1]), (float)(x[2] - sf.origin[2])};
+        const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
+        float ub = INFINITY;
+        for (int64_t k = lane; k < sf.n_patch; k += 64) {
+            const float4 c = D.sph[sf.patch_off + k];
+            const float dx = ql[0] - c.x, dy = ql[1] - c.y, dz = ql[2] - c.z;
+            ub = fminf(ub, sqrtf(dx * dx + dy * dy + dz * dz) + c.w + eps);
+        }
+        for (int off = 32; off > 0; off >>= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
+        const float thr = ub + s_margin(ub, sf, (float)tie_rel);
+        SCand b1 = s_empty(), b2 = b1;
+        for (int64_t k = lane; k < sf.n_patch; k += 64) {
+            const int64_t g = sf.patch_off + k;
+            const float4 c = D.sph[g];
+            const float dx = ql[0] - c.x, dy = ql[1] - c.y, dz = ql[2] - c.z;
+            if (sqrtf(dx * dx + dy * dy + dz * dz) - c.w - eps > thr) continue;
+            Bicubic B;
+            load_bicubic(D, sf, g, x, B);
+            const PatchMin m = patch_min(B);
+            s_top2(s_make(D, g, m.s, m.t, m.f, m.kappa), b1, b2);
+        }
+        // wave top-2
+        for (int off = 32; off > 0; off >>= 1) {
+            SCand o1, o2;
+            o1.u = __shfl_xor(b1.u, off, 64); o1.v = __shfl_xor(b1.v, off, 64); o1.d2 = __shfl_xor(b1.d2, off, 64);
+            o1.kappa = __shfl_xor(b1.kappa, off, 64); o1.patch = __shfl_xor(b1.patch, off, 64);
+            o2.u = __shfl_xor(b2.u, off, 64); o2.v = __shfl_xor(b2.v, off, 64); o2.d2 = __shfl_xor(b2.d2, off, 64);
+            o2.kappa = __shfl_xor(b2.kappa, off, 64); o2.patch = __shfl_xor(b2.patch, off, 64);
+            s_top2(o1, b1, b2);
+            s_top2(o2, b1, b2);
+        }
+        if (lane == 0) s_finish(D, sf, x, b1, b2, (uint32_t)MREP_F_FULLSCAN, tie_rel, invert, qi, o);
+    }
+}
+
+__global__ void k_seval(DevSurf D, int64_t n, const int32_t* __restrict__ sid, const double* __restrict__ uv,
+                        double* __restrict__ xyz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = sid[i];
+    if (c < 0 || c >= D.n_surf) {
+        xyz[3 * i] = xyz[3 * i + 1] = xyz[3 * i + 2] = __builtin_nan("");
+        return;
+    }
+    const DSurf sf = D.surfs[c];
+    const double* bu = D.brk + sf.brk_off;
+    const double* bv = bu + sf.n_su + 1;
+    const double u = fmin(fmax(uv[2 * i], bu[0]), bu[sf.n_su]);
+    const double v = fmin(fmax(uv[2 * i + 1], bv[0]), bv[sf.n_sv]);
+    const int iu = span_of(bu, sf.n_su, u), iv = span_of(bv, sf.n_sv, v);
+    const int p = sf.deg_u, q = sf.deg_v;
+    const double* cf = D.coef + sf.coef_off + (int64_t)(iu * sf.n_sv + iv) * 3 * (p + 1) * (q + 1);
+    const double s = (u - bu[iu]) / (bu[iu + 1] - bu[iu]), t = (v - bv[iv]) / (bv[iv + 1] - bv[iv]);
+    for (int x = 0; x < 3; ++x) {
+        double acc = 0.0;
+        for (int a = p; a >= 0; --a) {
+            double d = 0.0;
+            for (int b = q; b >= 0; --b) d = d * t + cf[3 * (a * (q + 1) + b) + x];
+            acc = acc * s + d;
+        }
+        xyz[3 * i + x] = acc;
+    }
+}
+
+struct SWork {
+    int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
+    ScreenOut so;
+    float4* res;
+};
+
+int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = (off + bytes + 255) & ~(int64_t)255;
+        return o;
+    };
+    const int64_t cap = std::min<int64_t>(kSurfPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
+    const int64_t oh = take(4 * (ns + 2)), oq = take(4 * (ns + 1)), ot = take(4 * (ns + 1)), op = take(4 * n);
+    const int64_t oov = take(4 * n), ocn = take(4 * n), opo = take(4 * n), oub = take(4 * n);
+    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap);
+    if (w) {
+        w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
+        w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
+        w->ovf_count = w->hist + ns;
+        w->so.cand_n = (int32_t*)(base + ocn);
+        w->so.pair_off = (int32_t*)(base + opo);
+        w->so.ub = (float*)(base + oub);
+        w->so.pair_seg = (int32_t*)(base + ops);
+        w->so.pair_j = (int32_t*)(base + opj);
+        w->so.pair_count = w->hist + ns + 1;
+        w->so.pair_cap = cap;
+        w->res = (float4*)(base + ors);
+    }
+    return off;
+}
+
+#define S_HIP(expr)                                                               \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));        \
+            return MREP_E_HIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+int32_t run_surf(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* sid, const double* q,
+                 void* ws, int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out, uint32_t* flags_out,
+                 void* stream, int invert)
+{
+    if (!geom || n < 0) {
+        set_error("mrep_project_surfaces: null geometry or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (geom->kind != MREP_GEOM_SURFACES) {
+        set_error("mrep_project_surfaces: the geometry holds curves");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (n == 0) return MREP_OK;
+    if (n * kSurfPairsPerQuery >= (int64_t)INT32_MAX) {
+        set_error("mrep_project_surfaces: n must be < 2^31 / 24");
+        return MREP_E_INVALID_ARG;
+    }
+    if (!sid || !q || !ws || !uv_out || !dist_out || !patch_out || !flags_out) {
+        set_error("mrep_project_surfaces: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    const int64_t ns = geom->sg.L.n_surf;
+    if (ns == 0) {
+        set_error("mrep_project_surfaces: geometry has no surfaces");
+        return MREP_E_INVALID_ARG;
+    }
+    SWork w;
+    if (ws_bytes < s_layout(ns, n, (char*)ws, &w)) {
+        set_error("mrep_project_surfaces: workspace smaller than mrep_surface_workspace_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)ws & 255) != 0) {
+        set_error("mrep_project_surfaces: workspace not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const bool timed = (opts->flags & MREP_OPT_TIME_STAGES) != 0;
+    if (timed && (rc = stage_begin(st))) return rc;
+    const DevSurf D = surf_view(geom->sg);
+    // invalid surface ids are skipped by the grouping and written by k_sbad
+    S_HIP(launch_grouping(ns, n, nullptr, sid, w.hist, w.q_off, w.tile_off, w.perm,
+                          Outs{nullptr, nullptr, nullptr, nullptr}, st));
+    const int64_t tiles = ns + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
+    hipLaunchKernelGGL(k_ssph, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, (const int32_t*)w.tile_off,
+                       (const int32_t*)w.q_off, (const int32_t*)w.perm, q, (float)opts->tie_rel, w.so);
+    S_HIP(hipGetLastError());
+    if (timed && (rc = stage_mark(1, st))) return rc;
+    const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, w.res);
+    S_HIP(hipGetLastError());
+    if (timed && (rc = stage_mark(2, st))) return rc;
+    SOuts o{uv_out, dist_out, patch_out, flags_out};
+    hipLaunchKernelGGL(k_sfinish, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, D, sid, q,
+                       (const int32_t*)w.q_off, (const int32_t*)w.perm, w.so, (const float4*)w.res, opts->tie_rel,
+                       invert, w.ovf_list, w.ovf_count, o);
+    const unsigned fb = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);
+    hipLaunchKernelGGL(k_sfull, dim3(fb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm,
+                       (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, opts->tie_rel, invert, o);
+    S_HIP(hipGetLastError());
+    if (timed) {
+        if ((rc = stage_mark(3, st))) return rc;
+        stage_end(3);
+    }
+    return MREP_OK;
+}
+
+}  // namespace
+
+// invalid surface ids: written before grouping (grouping skips them)
+__global__ void k_sbad(int64_t n, int32_t n_surf, const int32_t* __restrict__ sid, double* __restrict__ uv,
+                       double* __restrict__ d, int32_t* __restrict__ patch, uint32_t* __restrict__ f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = sid[i];
+    if (c >= 0 && c < n_surf) return;
+    const double nan = __builtin_nan("");
+    uv[2 * i] = uv[2 * i + 1] = nan;
+    d[i] = nan;
+    patch[i] = -1;
+    f[i] = MREP_F_BAD_ID;
+}
+
+extern "C" {
+
+int32_t mrep_surface_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
+{
+    if (!geom || !bytes || n < 0) {
+        set_error("mrep_surface_workspace_bytes: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (geom->kind != MREP_GEOM_SURFACES) {
+        set_error("mrep_surface_workspace_bytes: the geometry holds curves");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    *bytes = s_layout(geom->sg.L.n_surf, n, nullptr, nullptr);
+    return MREP_OK;
+}
+
+static int32_t surf_entry(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* sid, const double* q,
+                          void* ws, int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out,
+                          uint32_t* flags_out, void* stream, int invert)
+{
+    int rc = run_surf(geom, opts, n, sid, q, ws, ws_bytes, uv_out, dist_out, patch_out, flags_out, stream, invert);
+    if (rc || n == 0) return rc;
+    hipLaunchKernelGGL(k_sbad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n,
+                       (int32_t)geom->sg.L.n_surf, sid, uv_out, dist_out, patch_out, flags_out);
+    S_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+int32_t mrep_project_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
+                              const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out,
+                              double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream)
+{
+    return surf_entry(geom, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out, dist_out, patch_out, flags_out,
+                      stream, 0);
+}
+
+int32_t mrep_invert_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
+                             const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out, double* dist_out,
+                             int32_t* patch_out, uint32_t* flags_out, void* stream)
+{
+    return surf_entry(geom, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out, dist_out, patch_out, flags_out,
+                      stream, 1);
+}
+
+int32_t mrep_eval_surfaces(const mrep_geom* geom, int64_t n, const int32_t* surface_id, const double* uv,
+                           double* xyz_out, void* stream)
+{
+    if (!geom || n < 0 || (n > 0 && (!surface_id || !uv || !xyz_out))) {
+        set_error("mrep_eval_surfaces: null pointer or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (geom->kind != MREP_GEOM_SURFACES) {
+        set_error("mrep_eval_surfaces: the geometry holds curves");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    hipLaunchKernelGGL(k_seval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       surf_view(geom->sg), n, surface_id, uv, xyz_out);
+    S_HIP(hipGetLastError());
+    return MREP_OK;
+}
+
+}  // extern "C"

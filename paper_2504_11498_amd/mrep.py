@@ -84,6 +84,15 @@ _seed_ws = _sig("mrep_seeded_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts),
 _nn_features = _sig("mrep_nn_features", _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp)
 _project_seeded = _sig("mrep_project_curves_seeded", _i32, _vp, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp,
                        _vp, _vp, _vp, _vp)
+_decompose_s = _sig("mrep_decompose_surfaces", _i32, _i32, _pi32, _pi32, _pi32, _pi32, _pi64, _pd, _pi64, _pd, _pi64,
+                    _pd, _dbl, _i32, C.POINTER(_vp))
+_plan_export_s = _sig("mrep_plan_export_surfaces", _i32, _vp, _pi64, _pd, _pd, _pi32)
+_surf_ws = _sig("mrep_surface_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POINTER(C.c_int64))
+_project_s = _sig("mrep_project_surfaces", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                  _vp)
+_invert_s = _sig("mrep_invert_surfaces", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                 _vp)
+_eval_s = _sig("mrep_eval_surfaces", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
 _last_error = _sig("mrep_last_error", C.c_char_p)
 _abi = _sig("mrep_abi_version", _i32)
 
@@ -94,7 +103,9 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_gram_matrix", "mrep_last_stage_times", "mrep_last_error", "mrep_abi_version",
            "mrep_nn_param_count", "mrep_nn_bytes", "mrep_nn_bind", "mrep_nn_release", "mrep_nn_init",
            "mrep_nn_set_params", "mrep_nn_get_params", "mrep_nn_forward", "mrep_nn_infer", "mrep_nn_train_step",
-           "mrep_seeded_workspace_bytes", "mrep_nn_features", "mrep_project_curves_seeded"]
+           "mrep_seeded_workspace_bytes", "mrep_nn_features", "mrep_project_curves_seeded",
+           "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
+           "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces"]
 
 
 class MrepError(RuntimeError):
@@ -157,6 +168,20 @@ class Plan:
                             _p(seg_span, C.c_int32)), "mrep_plan_export")
         return {"seg_off": seg_off, "seg_t": seg_t, "seg_cp": seg_cp, "seg_span": seg_span}
 
+    @property
+    def is_surfaces(self):
+        return int(self.info.reserved) == 1
+
+    def export_surfaces(self):
+        n, s = self.n_curves, self.n_segments
+        patch_off = np.zeros(n + 1, np.int64)
+        patch_uv = np.zeros((s, 4))
+        patch_cp = np.zeros((s, 4, 4, 3))
+        patch_span = np.zeros(s, np.int32)
+        _check(_plan_export_s(self._h, _p(patch_off, C.c_int64), _p(patch_uv, C.c_double), _p(patch_cp, C.c_double),
+                              _p(patch_span, C.c_int32)), "mrep_plan_export_surfaces")
+        return {"patch_off": patch_off, "patch_uv": patch_uv, "patch_cp": patch_cp, "patch_span": patch_span}
+
     def upload(self, device=None):
         """Copy the tables to a new device buffer (a torch tensor) and return a Geometry."""
         import torch
@@ -191,6 +216,21 @@ def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:
     _check(_decompose(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(cp, C.c_double),
                       _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel), int(n_threads), C.byref(h)),
            "mrep_decompose_curves")
+    return Plan(h.value)
+
+
+def decompose_surfaces(surfs, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:
+    """mrep_decompose_surfaces on a SurfaceSet-like object (deg_u, deg_v, n_u, n_v, cp_off, cp, ku_off, ku, kv_off,
+    kv)."""
+    a = [_host(surfs.deg_u, np.int32), _host(surfs.deg_v, np.int32), _host(surfs.n_u, np.int32),
+         _host(surfs.n_v, np.int32), _host(surfs.cp_off, np.int64), _host(surfs.cp, np.float64),
+         _host(surfs.ku_off, np.int64), _host(surfs.ku, np.float64), _host(surfs.kv_off, np.int64),
+         _host(surfs.kv, np.float64)]
+    h = _vp()
+    _check(_decompose_s(int(a[0].shape[0]), _p(a[0], C.c_int32), _p(a[1], C.c_int32), _p(a[2], C.c_int32),
+                        _p(a[3], C.c_int32), _p(a[4], C.c_int64), _p(a[5], C.c_double), _p(a[6], C.c_int64),
+                        _p(a[7], C.c_double), _p(a[8], C.c_int64), _p(a[9], C.c_double), float(tol_rel),
+                        int(n_threads), C.byref(h)), "mrep_decompose_surfaces")
     return Plan(h.value)
 
 
@@ -344,6 +384,55 @@ class Geometry:
         _check(_nn_features(self._h, int(n), _vp(curve_id.data_ptr()), _vp(q.data_ptr()), _vp(seg.data_ptr()),
                             _vp(x.data_ptr()), _vp(ws.data_ptr()), int(ws.numel()), _vp(stream)), "mrep_nn_features")
         return seg, x
+
+    def surface_workspace_bytes(self, n: int, opts: Opts) -> int:
+        b = C.c_int64()
+        _check(_surf_ws(self._h, int(n), C.byref(opts), C.byref(b)), "mrep_surface_workspace_bytes")
+        return int(b.value)
+
+    def project_surfaces(self, q, surface_id, opts: Opts | None = None, invert: bool = False, workspace=None,
+                         out=None):
+        """Project q[n,3] (float64, device) onto surfaces surface_id[n] (int32, device).
+
+        Returns (uv[n,2], dist, patch, flags) device tensors; enqueued on the current stream."""
+        import torch
+
+        if opts is None:
+            opts = default_opts()
+        assert q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and q.dim() == 2 and q.shape[1] == 3
+        assert surface_id.is_cuda and surface_id.dtype == torch.int32 and surface_id.is_contiguous()
+        n = q.shape[0]
+        assert surface_id.shape[0] == n
+        if workspace is None:
+            need = self.surface_workspace_bytes(n, opts)
+            if getattr(self, "_sws2", None) is None or self._sws2.numel() < need:
+                self._sws2 = torch.empty(max(need, 256), dtype=torch.uint8, device=self.buf.device)
+            workspace = self._sws2
+        if out is None:
+            uv = torch.empty((n, 2), dtype=torch.float64, device=q.device)
+            d = torch.empty(n, dtype=torch.float64, device=q.device)
+            s = torch.empty(n, dtype=torch.int32, device=q.device)
+            f = torch.empty(n, dtype=torch.int32, device=q.device)
+        else:
+            uv, d, s, f = out
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        fn = _invert_s if invert else _project_s
+        _check(fn(self._h, C.byref(opts), int(n), _vp(surface_id.data_ptr()), _vp(q.data_ptr()),
+                  _vp(workspace.data_ptr()), int(workspace.numel()), _vp(uv.data_ptr()), _vp(d.data_ptr()),
+                  _vp(s.data_ptr()), _vp(f.data_ptr()), _vp(stream)),
+               "mrep_invert_surfaces" if invert else "mrep_project_surfaces")
+        return uv, d, s, f
+
+    def eval_surfaces(self, surface_id, uv):
+        """S_{surface_id[i]}(u_i, v_i) on the exact surface, FP64, device tensors in and out."""
+        import torch
+
+        n = uv.shape[0]
+        xyz = torch.empty((n, 3), dtype=torch.float64, device=uv.device)
+        stream = torch.cuda.current_stream(uv.device).cuda_stream
+        _check(_eval_s(self._h, int(n), _vp(surface_id.data_ptr()), _vp(uv.data_ptr()), _vp(xyz.data_ptr()),
+                       _vp(stream)), "mrep_eval_surfaces")
+        return xyz
 
     def eval(self, curve_id, t):
         """C_{curve_id[i]}(t[i]) on the exact curve, FP64, device tensors in and out."""

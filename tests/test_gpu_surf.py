@@ -1,0 +1,155 @@
+"""GPU parity of surface projection / inversion / evaluation against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_11498_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DIST_REL, UV_ABS, UNIQUE_REL, KAPPA_MIN = 1e-6, 1e-7, 2e-6, 1e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mrep():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_11498_amd import mrep as m
+
+    return m
+
+
+def _diag(S):
+    return np.array([np.linalg.norm(S.cp[S.cp_off[k]:S.cp_off[k + 1]].max(0) - S.cp[S.cp_off[k]:S.cp_off[k + 1]].min(0))
+                     for k in range(S.n)])
+
+
+def _run(geom, q, sid, invert=False):
+    m = sys.modules["paper_2504_11498_amd.mrep"]
+    qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(sid, dtype=np.int32)).cuda()
+    uv, d, p, f = geom.project_surfaces(qt, st, m.default_opts(), invert=invert)
+    torch.cuda.synchronize()
+    return {"uv": uv.cpu().numpy(), "dist": d.cpu().numpy(), "patch": p.cpu().numpy(),
+            "flags": f.cpu().numpy().view(np.uint32)}
+
+
+def compare_surf(S, sid, q, out, ref, ex=None, label=""):
+    """Parity bar: distance within 1e-6 * diag and never below the oracle; (u, v) within 1e-7 where the
+    oracle's minimum is unique and well conditioned; the patch index equals the exported patch holding the
+    oracle's (u, v) where unique and not within 1e-7 of a patch side."""
+    diag = _diag(S)[sid]
+    err = np.abs(out["dist"] - ref["dist"]) / diag
+    below = (ref["dist"] - out["dist"]) / diag
+    unique = (ref["runner"] - ref["dist"]) > UNIQUE_REL * diag
+    wc = unique & (ref["kappa"] >= KAPPA_MIN)
+    duv = np.abs(out["uv"] - ref["uv"]).max(1)
+    st = {"n": int(len(sid)), "max_dist_rel": float(err.max()), "max_uv_err_wc": float(duv[wc].max()) if wc.any() else 0.0,
+          "wc_frac": float(wc.mean())}
+    bad = np.nonzero(err > DIST_REL)[0]
+    assert bad.size == 0, f"{label}: {bad.size} distances off, worst {err.max():.3e} at {bad[:5]}"
+    assert below.max() <= 1e-12, f"{label}: below the oracle by {below.max():.3e}"
+    bad = np.nonzero(wc & (duv > UV_ABS))[0]
+    if bad.size:
+        for i in bad[:6]:
+            print(f"  q{i} gpu uv={out['uv'][i]} d={out['dist'][i]:.15g} f={out['flags'][i]:#x} | oracle uv={ref['uv'][i]} "
+                  f"d={ref['dist'][i]:.15g} kappa={ref['kappa'][i]:.3g} runner={ref['runner'][i]:.6g}", flush=True)
+    assert bad.size == 0, f"{label}: {bad.size} (u,v) off, worst {duv[wc].max():.3e} at {bad[:5]}"
+    if ex is not None:
+        checked = 0
+        for i in np.nonzero(unique)[0]:
+            o0, o1 = ex["patch_off"][sid[i]], ex["patch_off"][sid[i] + 1]
+            r = ex["patch_uv"][o0:o1]
+            u, v = ref["uv"][i]
+            inside = (r[:, 0] <= u) & (u <= r[:, 1]) & (r[:, 2] <= v) & (v <= r[:, 3])
+            near = np.min(np.abs(np.concatenate([r[inside, 0] - u, r[inside, 1] - u, r[inside, 2] - v,
+                                                 r[inside, 3] - v]))) if inside.any() else 0.0
+            if near <= 1e-7:
+                continue
+            k = int(np.nonzero(inside)[0][0])
+            assert out["patch"][i] == k, f"{label}: query {i} patch {out['patch'][i]} != {k}"
+            checked += 1
+        st["patch_checked"] = checked
+    return st
+
+
+@pytest.fixture(scope="module")
+def c3small(mrep):
+    S, Q = gen.surfaces(3, n_surf=8, per_surface=600)
+    sid = Q["surface_id"]
+    q = oracle.surf_eval(S, sid, Q["uv0"]) + Q["offset"]
+    _say("[setup] 8 surfaces (4 bicubic, 4 quintic), 4800 queries: decompose, upload, oracle")
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    geom = plan.upload()
+    ref = oracle.surf_project(S, sid, q)
+    return S, Q, sid, q, plan, geom, ref
+
+
+def test_surface_projection_parity(c3small):
+    S, Q, sid, q, plan, geom, ref = c3small
+    _say("[case] surface projection, 4800 queries (half on the surface)")
+    out = _run(geom, q, sid)
+    st = compare_surf(S, sid, q, out, ref, plan.export_surfaces(), label="surf")
+    _say(f"[ok] {st} fullscan={np.mean((out['flags'] & 0x20) != 0):.4f}")
+
+
+def test_surface_inversion(c3small):
+    S, Q, sid, q, plan, geom, ref = c3small
+    on = Q["on_surface"]
+    _say("[case] surface inversion of on-surface points")
+    x = oracle.surf_eval(S, sid[on], Q["uv0"][on])
+    out = _run(geom, x, sid[on], invert=True)
+    diag = _diag(S)[sid[on]]
+    assert np.all(out["dist"] <= 1e-6 * diag)
+    assert not np.any(out["flags"] & 0x10)
+    np.testing.assert_allclose(out["uv"], Q["uv0"][on], atol=UV_ABS)
+    off = x + np.random.default_rng(1).normal(size=x.shape) * (0.01 * diag)[:, None]
+    out2 = _run(geom, off, sid[on], invert=True)
+    assert np.all(((out2["flags"] & 0x10) != 0) == (out2["dist"] > 1e-6 * diag))
+
+
+def test_surface_eval(c3small, mrep):
+    S, Q, sid, q, plan, geom, ref = c3small
+    rng = np.random.default_rng(4)
+    s = rng.integers(0, S.n, 5000).astype(np.int32)
+    uv = np.concatenate([rng.uniform(0, 1, (4996, 2)), [[0, 0], [1, 1], [0, 1], [1, 0]]])
+    xyz = geom.eval_surfaces(torch.from_numpy(s).cuda(), torch.from_numpy(uv).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(xyz.cpu().numpy(), oracle.surf_eval(S, s, uv), atol=1e-12)
+
+
+def test_surface_edge_cases(c3small, mrep):
+    S, Q, sid, q, plan, geom, ref = c3small
+    _say("[case] surfaces: empty, single query, bad ids, far points, deterministic order")
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    geom.project_surfaces(e, torch.empty(0, dtype=torch.int32, device="cuda"))
+    out = _run(geom, q, sid)
+    one = _run(geom, q[7:8], sid[7:8])
+    assert one["dist"][0] == out["dist"][7] and np.all(one["uv"][0] == out["uv"][7])
+    rev = _run(geom, q[::-1], sid[::-1])
+    np.testing.assert_array_equal(rev["uv"][::-1], out["uv"])
+    np.testing.assert_array_equal(rev["dist"][::-1], out["dist"])
+    bad = sid.copy()
+    bad[::5] = S.n + 2
+    bad[1] = -1
+    ob = _run(geom, q, bad)
+    isbad = (bad < 0) | (bad >= S.n)
+    assert np.all(ob["flags"][isbad] & 0x40) and np.all(np.isnan(ob["dist"][isbad]))
+    assert np.all(ob["patch"][isbad] == -1)
+    np.testing.assert_array_equal(ob["dist"][~isbad], out["dist"][~isbad])
+    # far points: projections land on the boundary or a corner, flagged
+    far = np.tile(np.array([[5.0, 5.0, 0.0], [-5.0, 0.5, 0.0]]), (S.n, 1))
+    fs = np.repeat(np.arange(S.n, dtype=np.int32), 2)
+    of = _run(geom, far, fs)
+    rf = oracle.surf_project(S, fs, far)
+    compare_surf(S, fs, far, of, rf, label="far")
+    assert np.all(of["flags"] & 0x8)

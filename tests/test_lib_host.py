@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 2
+    assert mrep.abi_version() == 3
 
 
 def test_rebasement_matrix_matches_printed_T5():
@@ -191,3 +191,98 @@ def test_seeding_network_sizes_and_host_errors():
     assert mrep._nn_infer(None, 10, None, None, None) == mrep.E_INVALID_ARG
     assert mrep._project_seeded(None, None, None, 10, None, None, None, 0, None, None, None, None,
                                 None) == mrep.E_INVALID_ARG
+
+
+# --------------------------------------------------------------------------- surfaces
+def _surf(p, q, nu, nv, seed, height=True):
+    rng = np.random.default_rng(seed)
+    x, y = np.linspace(0, 1, nu), np.linspace(0, 1, nv)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    Z = 0.1 * np.sin(4 * X + 3 * Y) + rng.normal(0, 0.02, X.shape) if height else rng.uniform(0, 1, X.shape)
+    P = np.stack([X, Y, Z], -1).reshape(-1, 3)
+    iu = np.cumsum(rng.exponential(1, nu - p))
+    iv = np.cumsum(rng.exponential(1, nv - q))
+    U = np.r_[np.zeros(p + 1), iu[:-1] / iu[-1], np.ones(p + 1)]
+    V = np.r_[np.zeros(q + 1), iv[:-1] / iv[-1], np.ones(q + 1)]
+    return gen.SurfaceSet(np.array([p], np.int32), np.array([q], np.int32), np.array([nu], np.int32),
+                          np.array([nv], np.int32), np.array([0, nu * nv], np.int64), P, np.array([0, len(U)], np.int64),
+                          U, np.array([0, len(V)], np.int64), V)
+
+
+def test_surface_bicubic_patches_equal_boehm():
+    S = _surf(3, 3, 9, 8, 1)
+    ex = mrep.decompose_surfaces(S, 1e-6).export_surfaces()
+    nets, rects = oracle.surf_patches(S, 0)
+    assert ex["patch_cp"].shape[0] == len(nets) == 6 * 5
+    np.testing.assert_allclose(ex["patch_cp"], nets, atol=1e-13)
+    np.testing.assert_allclose(ex["patch_uv"], rects, atol=0)
+    np.testing.assert_array_equal(ex["patch_span"], np.arange(30))
+
+
+@pytest.mark.parametrize("p,q", [(5, 5), (4, 3), (2, 5)])
+def test_surface_reduced_patches_within_tolerance(p, q):
+    S = _surf(p, q, 12, 11, 2 + p + q)
+    tol_rel = 1e-6
+    ex = mrep.decompose_surfaces(S, tol_rel).export_surfaces()
+    diag = np.linalg.norm(S.cp.max(0) - S.cp.min(0))
+    nets, rects = oracle.surf_patches(S, 0)
+    # the pieces of every span patch tile its rectangle
+    for sp, rc in enumerate(rects):
+        mine = ex["patch_uv"][ex["patch_span"] == sp]
+        area = np.sum((mine[:, 1] - mine[:, 0]) * (mine[:, 3] - mine[:, 2]))
+        assert abs(area - (rc[1] - rc[0]) * (rc[3] - rc[2])) <= 1e-12
+        assert np.all(mine[:, 0] >= rc[0]) and np.all(mine[:, 1] <= rc[1])
+        assert np.all(mine[:, 2] >= rc[2]) and np.all(mine[:, 3] <= rc[3])
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(ex["patch_uv"]), min(60, len(ex["patch_uv"])), replace=False)
+    for k in pick:
+        dev = oracle.surf_patch_deviation(S, 0, ex["patch_cp"][k], ex["patch_uv"][k], ns=33)
+        assert dev <= tol_rel * diag * (1 + 1e-9), (k, dev / diag)
+
+
+def test_surface_elevated_bicubic_recovered_exactly():
+    """A single bicubic Bezier patch written at degree (5, 4) reduces back to itself with no split."""
+    rng = np.random.default_rng(9)
+    R = rng.uniform(0, 1, (4, 4, 3))
+
+    def elev(n, d):  # (d+1) x (n+1) matrix writing degree n at degree d
+        M = np.eye(n + 1)
+        for e in range(n, d):
+            E = np.zeros((e + 2, e + 1))
+            for i in range(e + 2):
+                if i > 0:
+                    E[i, i - 1] = i / (e + 1)
+                if i <= e:
+                    E[i, i] = 1 - i / (e + 1)
+            M = E @ M
+        return M
+
+    N = np.einsum("ia,abc,jb->ijc", elev(3, 5), R, elev(3, 4))
+    S = gen.SurfaceSet(np.array([5], np.int32), np.array([4], np.int32), np.array([6], np.int32),
+                       np.array([5], np.int32), np.array([0, 30], np.int64), N.reshape(-1, 3),
+                       np.array([0, 12], np.int64), np.r_[np.zeros(6), np.ones(6)], np.array([0, 10], np.int64),
+                       np.r_[np.zeros(5), np.ones(5)])
+    ex = mrep.decompose_surfaces(S, 1e-9).export_surfaces()
+    assert ex["patch_cp"].shape[0] == 1
+    np.testing.assert_allclose(ex["patch_cp"][0], R, atol=1e-12)
+
+
+def test_surface_decomposition_errors():
+    S = _surf(3, 3, 6, 6, 4)
+    bad = gen.SurfaceSet(S.deg_u, S.deg_v, S.n_u, S.n_v, S.cp_off, S.cp, S.ku_off, S.ku.copy(), S.kv_off, S.kv)
+    bad.ku[1] = 0.5  # not clamped / decreasing
+    with pytest.raises(mrep.MrepError) as e:
+        mrep.decompose_surfaces(bad, 1e-6)
+    assert e.value.code == mrep.E_BAD_KNOTS
+    bad2 = gen.SurfaceSet(np.array([9], np.int32), S.deg_v, S.n_u, S.n_v, S.cp_off, S.cp, S.ku_off, S.ku, S.kv_off,
+                          S.kv)
+    with pytest.raises(mrep.MrepError) as e:
+        mrep.decompose_surfaces(bad2, 1e-6)
+    assert e.value.code == mrep.E_BAD_DEGREE
+    with pytest.raises(mrep.MrepError) as e:
+        mrep.decompose_surfaces(S, -1.0)
+    assert e.value.code == mrep.E_TOL
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    assert plan.is_surfaces and plan.n_segments == 9
+    with pytest.raises(mrep.MrepError):
+        plan.export()
