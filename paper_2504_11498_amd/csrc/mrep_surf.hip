@@ -39,9 +39,9 @@ namespace {
 constexpr int kSphSub = 8;
 constexpr int kSphThreads = kQueriesPerTile * kSphSub;
 constexpr int kSphChunk = 1024;
-constexpr int kSphCap = 64;
+constexpr int kSphCap = 128;
 constexpr int kXcds = 8;
-constexpr int64_t kSurfPairsPerQuery = 24;
+constexpr int64_t kSurfPairsPerQuery = 64;
 constexpr int kGrid = 7;  // samples per direction in a patch
 static_assert(kSphThreads == 256, "sphere kernel: 32 queries x 8 lanes");
 
@@ -900,7 +900,7 @@ int32_t run_surf(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const 
     if (rc) return rc;
     if (n == 0) return MREP_OK;
     if (n * kSurfPairsPerQuery >= (int64_t)INT32_MAX) {
-        set_error("mrep_project_surfaces: n must be < 2^31 / 24");
+        set_error("mrep_project_surfaces: n must be < 2^31 / 64");
         return MREP_E_INVALID_ARG;
     }
     if (!sid || !q || !ws || !uv_out || !dist_out || !patch_out || !flags_out) {

@@ -153,3 +153,26 @@ def test_surface_edge_cases(c3small, mrep):
     rf = oracle.surf_project(S, fs, far)
     compare_surf(S, fs, far, of, rf, label="far")
     assert np.all(of["flags"] & 0x8)
+
+
+def test_batched_surfaces_full_size_sampled(mrep):
+    """All 256 surfaces and 4,194,304 queries in the launch configuration the benchmark times; 800 sampled
+    outputs checked against the oracle."""
+    S, Q = gen.surfaces(3)
+    _say("[setup] batched surfaces: decomposing 256 surfaces on the host")
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    geom = plan.upload()
+    sid = Q["surface_id"]
+    st = torch.from_numpy(sid).cuda()
+    q = (geom.eval_surfaces(st, torch.from_numpy(Q["uv0"]).cuda()) + torch.from_numpy(Q["offset"]).cuda()).contiguous()
+    _say("[case] batched surfaces, 4,194,304 queries")
+    uv, d, p, f = geom.project_surfaces(q, st, mrep.default_opts())
+    torch.cuda.synchronize()
+    out = {"uv": uv.cpu().numpy(), "dist": d.cpu().numpy(), "patch": p.cpu().numpy(), "flags": f.cpu().numpy().view(np.uint32)}
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["patch"] >= 0)
+    rng = np.random.default_rng(21)
+    pick = np.sort(rng.choice(len(sid), 800, replace=False))
+    qn = q.cpu().numpy()[pick]
+    ref = oracle.surf_project(S, sid[pick], qn)
+    st_ = compare_surf(S, sid[pick], qn, {k: v[pick] for k, v in out.items()}, ref, plan.export_surfaces(), label="c3")
+    _say(f"[ok] {st_}")
