@@ -258,7 +258,7 @@ int32_t mrep_surface_workspace_bytes(const mrep_geom* geom, int64_t n, const mre
  *                                MREP_F_FULLSCAN, MREP_F_BAD_ID
  * opts->precision and max_candidates are ignored (candidates come from patch
  * bounding spheres; patches are minimised in FP32 and the answer in FP64).
- * Limits: n < 2^31 / 64.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+ * Limits: n < 2^31 / 96.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
 int32_t mrep_project_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
                               const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out,
                               double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream);

@@ -39,9 +39,9 @@ namespace {
 constexpr int kSphSub = 8;
 constexpr int kSphThreads = kQueriesPerTile * kSphSub;
 constexpr int kSphChunk = 1024;
-constexpr int kSphCap = 128;
+constexpr int kSphCap = 256;
 constexpr int kXcds = 8;
-constexpr int64_t kSurfPairsPerQuery = 64;
+constexpr int64_t kSurfPairsPerQuery = 96;
 constexpr int kGrid = 7;  // samples per direction in a patch
 static_assert(kSphThreads == 256, "sphere kernel: 32 queries x 8 lanes");
 
@@ -470,10 +470,14 @@ __device__ PatchMin patch_min(const Bicubic& B)
     return best;
 }
 
-// One thread per (query, patch) pair.
-__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
+// Per pair: a 4 x 4 sample bound of the patch.  lb = min(samples) - (M_ss +
+// M_tt) h^2 / 8 with h = 1/3 (second-order bound of f = |S - q|^2) and the
+// best sample value, atomically minimised per query (non-negative float bits
+// order like integers).
+__global__ __launch_bounds__(256) void k_sbound(DevSurf D, const int32_t* __restrict__ sid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
-                                                ScreenOut so, float4* __restrict__ res)
+                                                ScreenOut so, float* __restrict__ lb,
+                                                uint32_t* __restrict__ fub)
 {
     const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
@@ -486,9 +490,75 @@ __global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __rest
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         Bicubic B;
         load_bicubic(D, sf, k, q, B);
+        float mn = INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mn = fminf(mn, bc_f(B, i * (1.f / 3.f), j * (1.f / 3.f)));
+        const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
+        lb[p] = mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f;
+        atomicMin(&fub[jj], __float_as_uint(mn * (1.f + 4e-6f)));
+    }
+}
+
+// Pairs whose lower bound reaches the query's best sample plus the tie margin
+// go to a dense list (one atomic per wave); the others get +inf.
+__global__ __launch_bounds__(256) void k_sgate(DevSurf D, const int32_t* __restrict__ sid,
+                                               const int32_t* __restrict__ perm, ScreenOut so,
+                                               const float* __restrict__ lb, const uint32_t* __restrict__ fub,
+                                               float tie_rel, int32_t* __restrict__ live, int32_t* __restrict__ n_live,
+                                               float4* __restrict__ res)
+{
+    const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        bool keep = false;
+        if (p < total) {
+            const int32_t jj = so.pair_j[p];
+            const int64_t k = so.pair_seg[p];
+            if (jj >= 0 && k >= 0 && k < D.n_patch) {
+                const DSurf& sf = D.surfs[sid[perm[jj]]];
+                const float ub = sqrtf(__uint_as_float(fub[jj]));
+                const float thr = ub + s_margin(ub, sf, tie_rel);
+                keep = lb[p] <= thr * thr;
+                if (!keep) res[p] = make_float4(0.f, 0.f, INFINITY, 1.f);
+            }
+        }
+        const uint64_t m = __ballot(keep);
+        int32_t first = 0;
+        if (lane == 0 && m) first = atomicAdd(n_live, (int32_t)__popcll(m));
+        first = __shfl(first, 0, 64);
+        if (keep) live[first + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)p;
+    }
+}
+
+// One thread per live pair: the certified patch minimum.
+__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
+                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
+                                                ScreenOut so, const int32_t* __restrict__ live,
+                                                const int32_t* __restrict__ n_live, float4* __restrict__ res)
+{
+    const int64_t total = *n_live;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = live[i];
+        const int32_t jj = so.pair_j[p];
+        const int64_t k = so.pair_seg[p];
+        const int32_t qi = perm[jj];
+        const DSurf sf = D.surfs[sid[qi]];
+        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        Bicubic B;
+        load_bicubic(D, sf, k, q, B);
         const PatchMin m = patch_min(B);
         res[p] = make_float4(m.s, m.t, m.f, m.kappa);
     }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -845,6 +915,10 @@ struct SWork {
     int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
     ScreenOut so;
     float4* res;
+    float* lb;       // [cap] sampled lower bound of each pair
+    uint32_t* fub;  // [n] best sample value of each query (float bits)
+    int32_t* live;   // [cap] pairs that need the patch minimum
+    int32_t* n_live; // their count
 };
 
 int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
@@ -858,7 +932,8 @@ int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
     const int64_t cap = std::min<int64_t>(kSurfPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
     const int64_t oh = take(4 * (ns + 2)), oq = take(4 * (ns + 1)), ot = take(4 * (ns + 1)), op = take(4 * n);
     const int64_t oov = take(4 * n), ocn = take(4 * n), opo = take(4 * n), oub = take(4 * n);
-    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap);
+    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap), olb = take(4 * cap);
+    const int64_t ofu = take(4 * n), olv = take(4 * cap), onl = take(4);
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
@@ -871,6 +946,10 @@ int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
         w->so.pair_count = w->hist + ns + 1;
         w->so.pair_cap = cap;
         w->res = (float4*)(base + ors);
+        w->lb = (float*)(base + olb);
+        w->fub = (uint32_t*)(base + ofu);
+        w->live = (int32_t*)(base + olv);
+        w->n_live = (int32_t*)(base + onl);
     }
     return off;
 }
@@ -900,7 +979,7 @@ int32_t run_surf(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const 
     if (rc) return rc;
     if (n == 0) return MREP_OK;
     if (n * kSurfPairsPerQuery >= (int64_t)INT32_MAX) {
-        set_error("mrep_project_surfaces: n must be < 2^31 / 64");
+        set_error("mrep_project_surfaces: n must be < 2^31 / 96");
         return MREP_E_INVALID_ARG;
     }
     if (!sid || !q || !ws || !uv_out || !dist_out || !patch_out || !flags_out) {
@@ -934,7 +1013,13 @@ int32_t run_surf(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const 
     S_HIP(hipGetLastError());
     if (timed && (rc = stage_mark(1, st))) return rc;
     const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, w.res);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.fub, n, 0x7f800000u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)w.n_live, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_sbound, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, w.lb, w.fub);
+    hipLaunchKernelGGL(k_sgate, dim3(pb), dim3(256), 0, st, D, sid, (const int32_t*)w.perm, w.so, (const float*)w.lb,
+                       (const uint32_t*)w.fub, (float)opts->tie_rel, w.live, w.n_live, w.res);
+    hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so,
+                       (const int32_t*)w.live, (const int32_t*)w.n_live, w.res);
     S_HIP(hipGetLastError());
     if (timed && (rc = stage_mark(2, st))) return rc;
     SOuts o{uv_out, dist_out, patch_out, flags_out};
