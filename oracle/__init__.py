@@ -225,13 +225,13 @@ def max_threads() -> int:
 def mlp_loss(params, x, u_star=None, accept=None, n_in=15, hidden=128, n_out=2, grad=False):
     """FP64 seeding-network forward (and backward) on a batch (see mlp_oracle.c).
 
-    Returns (loss, y[B, n_out], grad or None)."""
+    u_star: targets [B, n_out - 1] (or [B] for n_out = 2).  Returns (loss, y[B, n_out], grad or None)."""
     params = _d(params)
     x = _d(x).reshape(-1, n_in)
     B = x.shape[0]
     y = np.zeros((B, n_out))
     g = np.zeros_like(params) if grad else None
-    us = _d(u_star) if u_star is not None else None
+    us = _d(u_star).reshape(B, n_out - 1) if u_star is not None else None
     ac = _d(accept) if accept is not None else None
     loss = _load().orc_mlp_loss(n_in, hidden, n_out, _ptr(params, C.c_double), B, _ptr(x, C.c_double),
                                 _ptr(us, C.c_double) if us is not None else None,

@@ -6,11 +6,12 @@
  * Linear(H, n_out).  GELU is the exact form 0.5 z (1 + erf(z / sqrt 2)).
  * Weights are row-major W[out][in]; biases b[out].
  *
- * Loss over a batch of B rows with targets (u*, a) and a in {0, 1}:
- *   L = (1/B) sum_i [ a_i (y_i0 - u*_i)^2 + BCE(y_i1, a_i) ],
+ * Loss over a batch of B rows with targets t_i (n_out - 1 values) and a in {0, 1}:
+ *   L = (1/B) sum_i [ a_i sum_{o < n_out-1} (y_io - t_io)^2 + BCE(y_i,n_out-1, a_i) ],
  *   BCE(z, a) = max(z, 0) - z a + log(1 + exp(-|z|)).
- * The first output is the predicted local parameter, the second the logit of
- * "the projection lies on this piece".
+ * The first outputs are the predicted local parameters (u for a curve piece,
+ * (u, v) for a surface patch), the last one the logit of "the projection lies
+ * on this piece"; the parameter loss is masked by a (MSE * accept + BCE).
  */
 #include <math.h>
 #include <stdint.h>
@@ -26,9 +27,10 @@ static double ml_dgelu(double z)
 /* Forward and (optionally) backward for one batch.  params holds W1 (H x n_in),
  * b1 (H), W2 (H x H), b2 (H), W3 (n_out x H), b3 (n_out) back to back; grad
  * (nullable) receives dL/dparams in the same layout; y (nullable) receives the
- * outputs [B x n_out].  Returns the loss. */
+ * outputs [B x n_out]; target [B x (n_out - 1)] and accept [B] (nullable
+ * together: forward only).  Returns the loss. */
 double orc_mlp_loss(int n_in, int H, int n_out, const double *params, int64_t B, const double *x,
-                    const double *u_star, const double *accept, double *y, double *grad)
+                    const double *target, const double *accept, double *y, double *grad)
 {
     const double *W1 = params, *b1 = W1 + (size_t)H * n_in, *W2 = b1 + H, *b2 = W2 + (size_t)H * H,
                  *W3 = b2 + H, *b3 = W3 + (size_t)n_out * H;
@@ -62,15 +64,18 @@ double orc_mlp_loss(int n_in, int H, int n_out, const double *params, int64_t B,
             out[o] = s;
             if (y) y[(size_t)r * n_out + o] = s;
         }
-        if (!u_star) continue;
+        if (!target) continue;
         const double a = accept[r];
-        const double du = out[0] - u_star[r];
-        const double z = out[1];
-        loss += a * du * du + (z > 0 ? z : 0.0) - z * a + log1p(exp(-fabs(z)));
+        const double z = out[n_out - 1];
+        double mse = 0.0;
+        for (int o = 0; o < n_out - 1; ++o) {
+            const double du = out[o] - target[(size_t)r * (n_out - 1) + o];
+            mse += du * du;
+            dout[o] = 2.0 * a * du / (double)B;
+        }
+        loss += a * mse + (z > 0 ? z : 0.0) - z * a + log1p(exp(-fabs(z)));
         if (!grad) continue;
-        for (int o = 0; o < n_out; ++o) dout[o] = 0.0;
-        dout[0] = 2.0 * a * du / (double)B;
-        dout[1] = (1.0 / (1.0 + exp(-z)) - a) / (double)B;
+        dout[n_out - 1] = (1.0 / (1.0 + exp(-z)) - a) / (double)B;
         for (int o = 0; o < n_out; ++o) {
             gb3[o] += dout[o];
             for (int k = 0; k < H; ++k) gW3[(size_t)o * H + k] += dout[o] * h2[k];

@@ -548,3 +548,33 @@ def test_surface_projection_brute_force():
             best = min(best, np.sqrt(res.fun), d[i])
         assert r["dist"][k] <= best + 1e-12
         assert abs(r["dist"][k] - best) <= 1e-9
+
+
+def test_mlp_surface_variant_loss_and_gradient():
+    """The patch variant (51 inputs, outputs u, v, logit): loss terms with a zero network and central
+    differences of the gradient."""
+    nin, nout = 51, 3
+    npar = oracle.mlp_param_count(n_in=nin, n_out=nout)
+    assert npar == 23555
+    p = np.zeros(npar)
+    p[-3:] = [0.2, 0.7, -0.4]
+    tgt = np.array([[0.1, 0.5], [0.9, 0.3], [0.6, 0.6]])
+    ac = np.array([1.0, 0.0, 1.0])
+    loss, y, _ = oracle.mlp_loss(p, np.zeros((3, nin)), tgt, ac, n_in=nin, n_out=nout)
+    terms = ac * ((0.2 - tgt[:, 0]) ** 2 + (0.7 - tgt[:, 1]) ** 2) + np.where(ac > 0, np.logaddexp(0, 0.4),
+                                                                              np.logaddexp(0, -0.4))
+    assert loss == pytest.approx(terms.mean(), rel=0, abs=1e-15)
+    rng = np.random.default_rng(12)
+    p = rng.normal(0, 0.2, npar)
+    x = rng.normal(size=(16, nin))
+    tgt = rng.uniform(0, 1, (16, 2))
+    ac = (rng.uniform(size=16) < 0.5).astype(float)
+    _, _, g = oracle.mlp_loss(p, x, tgt, ac, n_in=nin, n_out=nout, grad=True)
+    h = 1e-6
+    for i in rng.choice(npar, 24, replace=False):
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        num = (oracle.mlp_loss(pp, x, tgt, ac, n_in=nin, n_out=nout)[0] -
+               oracle.mlp_loss(pm, x, tgt, ac, n_in=nin, n_out=nout)[0]) / (2 * h)
+        assert abs(num - g[i]) <= 1e-7 * max(1.0, abs(num)), (i, num, g[i])
