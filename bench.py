@@ -292,6 +292,44 @@ def surfaces_bench(args, dev):
                      "polish_write": float(stage[2])},
         "fullscan_frac": float(np.mean((flags & mrep.F_FULLSCAN) != 0)),
     }
+    seeded_outs = None
+    if not args.no_seeded:
+        from paper_2504_11498_amd import seeding
+
+        # the surface network, trained on 32 held-out surfaces (other seeds) outside the timed region
+        S2, Q2 = gen.surfaces(31, n_surf=32, per_surface=1500)
+        plan2 = mrep.decompose_surfaces(S2, 1e-6)
+        geom2 = plan2.upload(dev)
+        sid2 = torch.from_numpy(Q2["surface_id"]).to(dev)
+        q2 = (geom2.eval_surfaces(sid2, torch.from_numpy(Q2["uv0"]).to(dev))
+              + torch.from_numpy(Q2["offset"]).to(dev)).contiguous()
+        t0 = time.perf_counter()
+        x, tgt, acc, tstats = seeding.surface_training_pairs(plan2, geom2, q2, sid2, seed=0)
+        net = mrep.Network(dev, seed=7, kind=mrep.NN_SURFACE)
+        losses = seeding.train(net, x, tgt, acc, epochs=16, batch=1024, lr=1e-3, seed=0)
+        train_s = time.perf_counter() - t0
+        seeded_outs = tuple(torch.empty_like(o) for o in outs)
+        ws2 = torch.empty(geom.surface_seeded_workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
+
+        def sstep():
+            geom.project_surfaces_seeded(q, sid, net, opts, workspace=ws2, out=seeded_outs)
+
+        for _ in range(max(1, args.warmup)):
+            sstep()
+        ms2, stage2 = _timed(sstep, steps)
+        f2 = seeded_outs[3].cpu().numpy().view(np.uint32)
+        res["seeded"] = {
+            "value": n / (ms2 / 1e3),
+            "unit": "projections/s",
+            "ms_per_step": ms2,
+            "stage_ms": {"group_spheres_candidates": float(stage2[0]), "network": float(stage2[1]),
+                         "seed_patch_minima": float(stage2[2]), "polish_write": float(stage2[3])},
+            "nn_fallback_frac": float(np.mean((f2 & mrep.F_NN_FALLBACK) != 0)),
+            "fullscan_frac": float(np.mean((f2 & mrep.F_FULLSCAN) != 0)),
+            "training": {"surfaces": 32, "queries": int(q2.shape[0]), **tstats, "steps": int(len(losses)),
+                         "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean()),
+                         "seconds": train_s},
+        }
     if not args.no_cpu_baseline:
         sys.path.insert(0, ROOT)
         import oracle
@@ -313,6 +351,12 @@ def surfaces_bench(args, dev):
                                "kind": "oracle", "sample": "2000 random queries of the same workload"}
         res["parity_on_sample"] = {"max_dist_rel": float(np.max(np.abs(d_g - r["dist"]) / diag)),
                                    "max_uv_err_unique": float(np.max(np.abs(uv_g - r["uv"]).max(1)[wc])) if wc.any() else 0.0}
+        if seeded_outs is not None:
+            d2 = seeded_outs[1].cpu().numpy()[pick]
+            uv2 = seeded_outs[0].cpu().numpy()[pick]
+            res["seeded"]["parity_on_sample"] = {
+                "max_dist_rel": float(np.max(np.abs(d2 - r["dist"]) / diag)),
+                "max_uv_err_unique": float(np.max(np.abs(uv2 - r["uv"]).max(1)[wc])) if wc.any() else 0.0}
     return res
 
 

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 3
+#define MREP_ABI_VERSION 4
 
 /* status codes */
 #define MREP_OK 0
@@ -66,7 +66,7 @@ extern "C" {
 #define MREP_F_OFFCURVE 0x10u   /* invert only: distance above the curve's tolerance */
 #define MREP_F_FULLSCAN 0x20u   /* screen candidate list overflowed; every segment was examined */
 #define MREP_F_BAD_ID 0x40u     /* curve_id out of range: outputs are NaN / -1 */
-#define MREP_F_NN_FALLBACK 0x80u /* seeded call: the certificate failed and the screened pipeline decided */
+#define MREP_F_NN_FALLBACK 0x80u /* seeded call: curves: the certificate failed and the screened pipeline decided; surfaces: the minimum is not on the seeded patch */
 
 /* screen precisions (mrep_opts.precision) */
 #define MREP_PREC_FP64 0 /* exhaustive FP64 examination of every segment (no MFMA screen) */
@@ -198,7 +198,12 @@ int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_
  * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine/polish/write.
  * mrep_project_curves_seeded: 4 stages, [0] grouping + sphere candidates,
  * [1] network scoring (0 without a network), [2] seed + certificate (or the
- * sphere-pruned refine), [3] fallback through the screened pipeline.  Waits for
+ * sphere-pruned refine), [3] fallback through the screened pipeline.
+ * mrep_project_surfaces / invert: 3 stages, [0] grouping + sphere lists,
+ * [1] sampled bounds + gate + patch minima, [2] top-2 + FP64 polish + write.
+ * mrep_project_surfaces_seeded: 4 stages, [0] grouping + sphere lists +
+ * candidates, [1] network scoring, [2] seeded Newton + bounds + gate + patch
+ * minima, [3] top-2 + FP64 polish + write.  Waits for
  * that call's events.  n = capacity of ms_out (>= MREP_N_STAGES is always
  * enough).  Returns the number of stages written (> 0).
  * Errors: MREP_E_INVALID_ARG (no timed call yet, n too small), MREP_E_HIP. */
@@ -277,70 +282,80 @@ int32_t mrep_eval_surfaces(const mrep_geom* geom, int64_t n, const int32_t* surf
 /* ---------------------------------------------------------------------- */
 /* Learned seeding (an extension; the paper has no learned part)           */
 /* ---------------------------------------------------------------------- */
-/* A multilayer perceptron scores, for a query and one of its curve's cubic
- * pieces (Sec. 5.2 matrix representation), the local parameter u of the
- * closest point on the piece and the logit that the projection lies on it:
- *   x (MREP_NN_IN = 15: the piece's 4 control points and the query, minus the
- *   control points' centroid, divided by their box diagonal)
- *   -> Linear(15, 128) -> GELU (erf form) -> Linear(128, 128) -> GELU
- *   -> Linear(128, 2) = (u, logit).
- * Parameters: FP32, row-major W[out][in], in the order W1 b1 W2 b2 W3 b3
- * (mrep_nn_param_count() = 18818).  Products run as BF16 MFMA with FP32
- * accumulation; master weights and Adam state stay FP32.
- * Loss of a batch of B rows with targets (u*, a), a in {0, 1}:
- *   (1/B) sum [ a (u - u*)^2 + max(z, 0) - z a + log(1 + exp(-|z|)) ],
- * z = logit. */
-#define MREP_NN_IN 15
+/* A multilayer perceptron scores a query against one candidate piece of its
+ * geometry (a cubic piece of a curve or a bicubic patch of a surface, the
+ * Sec. 5.2 matrix representation): the local parameter(s) of the closest point
+ * on the piece and the logit that the projection lies on it.  Two kinds:
+ *   MREP_NN_CURVE:   x (15: the piece's 4 control points and the query)
+ *                    -> 128 -> 128 -> 2 = (u, logit);          18818 parameters
+ *   MREP_NN_SURFACE: x (51: the patch's 16 control points, row-major in
+ *                    (i along u, j along v), and the query)
+ *                    -> 128 -> 128 -> 3 = (s, t, logit);       23555 parameters
+ * Inputs are translated by the control points' centroid and divided by the
+ * diagonal of their axis-aligned box.  Hidden layers: Linear then GELU (erf
+ * form).  Parameters: FP32, row-major W[out][in], in the order W1 b1 W2 b2 W3
+ * b3.  Products run as BF16 MFMA with FP32 accumulation; master weights and
+ * Adam state stay FP32.
+ * Loss of a batch of B rows, outputs y[0..m-1] with m = MREP_NN_*_OUT, targets
+ * t[0..m-2] and a in {0, 1}, z = y[m-1]:
+ *   (1/B) sum [ a |y[0..m-2] - t|^2 + max(z, 0) - z a + log(1 + exp(-|z|)) ]. */
+#define MREP_NN_CURVE 0
+#define MREP_NN_SURFACE 1
+#define MREP_NN_CURVE_IN 15
+#define MREP_NN_CURVE_OUT 2
+#define MREP_NN_SURFACE_IN 51
+#define MREP_NN_SURFACE_OUT 3
 #define MREP_NN_HIDDEN 128
-#define MREP_NN_OUT 2
 #define MREP_NN_K 4 /* candidate pieces scored per query */
 
 typedef struct mrep_nn mrep_nn; /* device view of a caller-owned state buffer (non-owning) */
 
-int32_t mrep_nn_param_count(void);
+/* Parameter count of a kind; -1 for an unknown kind. */
+int32_t mrep_nn_param_count(int32_t kind);
 
-/* Sizes: *state_bytes of the network state buffer (parameters, Adam moments,
- * gradient, packed BF16 weight image), *work_bytes of the work buffer of
- * mrep_nn_forward / mrep_nn_train_step for `batch` rows.  Either output may be
- * NULL (not both).  Errors: MREP_E_INVALID_ARG. */
-int32_t mrep_nn_bytes(int64_t batch, int64_t* state_bytes, int64_t* work_bytes);
+/* Sizes for a kind: *state_bytes of the network state buffer (parameters,
+ * Adam moments, gradient, packed BF16 weight image), *work_bytes of the work
+ * buffer of mrep_nn_forward / mrep_nn_train_step for `batch` rows.  Either
+ * output may be NULL (not both).  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_nn_bytes(int32_t kind, int64_t batch, int64_t* state_bytes, int64_t* work_bytes);
 
 /* Bind a DEVICE buffer of >= state_bytes (256-byte aligned, caller-owned,
- * must outlive the handle) as network state.  Its contents are undefined until
- * mrep_nn_init or mrep_nn_set_params.  Release the handle with
- * mrep_nn_release (the buffer stays the caller's).
+ * must outlive the handle) as the state of a network of `kind`.  Its contents
+ * are undefined until mrep_nn_init or mrep_nn_set_params.  Release the handle
+ * with mrep_nn_release (the buffer stays the caller's).
  * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_NO_DEVICE. */
-int32_t mrep_nn_bind(void* dev_state, int64_t bytes, mrep_nn** out);
+int32_t mrep_nn_bind(int32_t kind, void* dev_state, int64_t bytes, mrep_nn** out);
 void mrep_nn_release(mrep_nn* nn);
 
 /* Weights uniform in +-1/sqrt(fan_in) from splitmix64(seed), biases 0, Adam
  * state and step count reset.  Synchronous on `stream`. */
 int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream);
-/* host[n] (HOST, n = mrep_nn_param_count()) -> parameters; resets Adam.
+/* host[n] (HOST, n = mrep_nn_param_count(kind)) -> parameters; resets Adam.
  * Synchronous on `stream`.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
 int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stream);
 /* parameters -> host[n] (HOST).  Synchronous on `stream`. */
 int32_t mrep_nn_get_params(const mrep_nn* nn, float* host, int64_t n, void* stream);
 
-/* Outputs y[n][2] for inputs x[n][15] (both DEVICE, FP32).
- * mrep_nn_forward: the training kernels (layer by layer through `work`, of
- * mrep_nn_bytes(n) work bytes); mrep_nn_infer: the fused inference kernel
- * (weights in LDS, no work buffer).  Asynchronous on `stream`.
- * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+/* Outputs y[n][out] for inputs x[n][in] (both DEVICE, FP32; in, out of the
+ * network's kind).  mrep_nn_forward: the training kernels (layer by layer
+ * through `work`, of mrep_nn_bytes(kind, n) work bytes); mrep_nn_infer: the
+ * fused inference kernel (weights in LDS, no work buffer).  Asynchronous on
+ * `stream`.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
 int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, void* work, int64_t work_bytes,
                         void* stream);
 int32_t mrep_nn_infer(const mrep_nn* nn, int64_t n, const float* x, float* y, void* stream);
 
 /* One training step on `batch` rows: forward, the loss above, backward, and
  * (lr > 0) one Adam step (beta = 0.9, 0.999; eps 1e-8; bias-corrected).
- * x[n_rows][15], u_star[n_rows], accept[n_rows]: DEVICE FP32 training set.
- * rows[batch] (DEVICE int32, nullable) selects the rows of this batch; an entry
- * outside [0, n_rows) contributes an all-zero row.  rows == NULL: the first
- * `batch` rows (batch <= n_rows).  loss_out (DEVICE float, nullable): the
- * batch loss before the step.  grad_out (DEVICE float[param_count], nullable):
- * the gradient.  work: DEVICE, mrep_nn_bytes(batch) work bytes.  Asynchronous
- * on `stream`.  Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
-int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* u_star, const float* accept,
+ * x[n_rows][in], target[n_rows][out - 1], accept[n_rows]: DEVICE FP32
+ * training set.  rows[batch] (DEVICE int32, nullable) selects the rows of this
+ * batch; an entry outside [0, n_rows) contributes an all-zero row.  rows ==
+ * NULL: the first `batch` rows (batch <= n_rows).  loss_out (DEVICE float,
+ * nullable): the batch loss before the step.  grad_out (DEVICE
+ * float[param_count], nullable): the gradient.  work: DEVICE,
+ * mrep_nn_bytes(kind, batch) work bytes.  Asynchronous on `stream`.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* target, const float* accept,
                            int64_t batch, const int32_t* rows, float lr, float* loss_out, float* grad_out,
                            void* work, int64_t work_bytes, void* stream);
 
@@ -351,7 +366,7 @@ int32_t mrep_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep
 /* Training-data export: for every query its MREP_NN_K candidate pieces (the
  * pieces whose bounding spheres come closest, nearest first) as curve-local
  * indices seg_out[n][4] (-1: the curve has fewer pieces, or a bad id) and
- * their network inputs x_out[n][4][15].  All arrays DEVICE.  Asynchronous.
+ * their MREP_NN_CURVE network inputs x_out[n][4][15].  All arrays DEVICE.  Asynchronous.
  * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
 int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz,
                          int32_t* seg_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream);
@@ -370,6 +385,36 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
                                    const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
                                    double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out,
                                    void* stream);
+
+/* Workspace of mrep_project_surfaces_seeded and mrep_nn_surface_features for
+ * n queries (DEVICE, 256-byte aligned).  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_surface_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts,
+                                            int64_t* bytes);
+
+/* Training-data export for surfaces: for every query its MREP_NN_K candidate
+ * patches (the smallest bounding-sphere lower bounds, nearest first) as
+ * surface-local indices patch_out[n][4] (-1: the surface has fewer patches,
+ * or a bad id) and their MREP_NN_SURFACE network inputs x_out[n][4][51].
+ * All arrays DEVICE.  Asynchronous.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_SMALL_BUFFER, MREP_E_HIP. */
+int32_t mrep_nn_surface_features(const mrep_geom* geom, int64_t n, const int32_t* surface_id, const double* q_xyz,
+                                 int32_t* patch_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream);
+
+/* Seeded surface projection: same contract and outputs as
+ * mrep_project_surfaces.  The network (kind MREP_NN_SURFACE, required) scores
+ * each query's 4 candidate patches; Newton from the predicted (s, t) on the
+ * best-scored patch attains a distance d_seed.  A listed patch whose sphere
+ * lower bound or sampled second-order lower bound exceeds d_seed plus the tie
+ * margin is dropped; the others get the certified patch minimum as in
+ * mrep_project_surfaces, so the answer is the same global minimum.
+ * MREP_F_NN_FALLBACK marks the queries whose minimum does not lie on the
+ * seeded patch, or that took the full scan.
+ * ws: mrep_surface_seeded_workspace_bytes(n).
+ * Errors: as mrep_project_surfaces. */
+int32_t mrep_project_surfaces_seeded(const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                                     const int32_t* surface_id, const double* q_xyz, void* workspace,
+                                     int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out,
+                                     uint32_t* flags_out, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Host introspection of the constant matrices (for tests and tools)       */

@@ -108,6 +108,13 @@ int project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const int32
                  const double* q_xyz, void* workspace, const Outs& o, hipStream_t st, int invert, bool timed,
                  int stage0);
 
+// Network kind of a handle (-1 for NULL), and the fused inference kernel over
+// the (sorted query, candidate patch) rows of a surface call: xb[n][4][64] BF16
+// inputs, cand[n][4] global patch (or -1), out[n][4] = (s, t, logit, 0).
+int nn_kind(const mrep_nn* nn);
+int nn_score_surface_pairs(const mrep_nn* nn, const int32_t* q_off, int32_t n_surf, const int32_t* cand,
+                           const uint16_t* xb, float4* out, int64_t n_rows, hipStream_t st);
+
 }  // namespace mrep
 
 // Handles of the C ABI.  A plan (host) and a geometry (non-owning device view

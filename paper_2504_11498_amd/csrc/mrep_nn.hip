@@ -1,20 +1,25 @@
-// Learned seeding for curve projection: a small MLP proposes, for a (query,
-// candidate piece) pair, the local parameter of the closest point and a logit
-// that the projection lies on that piece; a certificate then decides whether
-// the seeded answer is the global minimum, and the screened pipeline takes
-// every query whose certificate fails.  (The paper has no learned part; this is
-// an extension built around its piecewise-cubic matrix representation,
-// Sec. 5.2, and its Newton step on (C - q).C' = 0, eqs. Et and E't.)
+// Learned seeding: a small MLP proposes, for a (query, candidate piece) pair,
+// the local parameter(s) of the closest point on the piece and a logit that
+// the projection lies on that piece; a certificate then decides whether the
+// seeded answer is the global minimum, and the screened pipeline takes every
+// query whose certificate fails.  (The paper has no learned part; this is an
+// extension built around its piecewise-cubic matrix representation, Sec. 5.2,
+// and its Newton step on (C - q).C' = 0, eqs. Et and E't.)
 //
-// Network (exact-erf GELU, FP32 master weights, BF16 MFMA products with FP32
-// accumulation):
-//   x (15: a piece's 4 control points and the query, translated by the control
-//   points' centroid and scaled by 1 / their box diagonal)
-//     -> Linear(15, 128) -> GELU -> Linear(128, 128) -> GELU -> Linear(128, 2)
-//   outputs: y0 = predicted local parameter u in the piece, y1 = logit.
+// Networks (exact-erf GELU, FP32 master weights, BF16 MFMA products with FP32
+// accumulation), inputs translated by the control points' centroid and scaled
+// by 1 / their box diagonal:
+//   curve kind:   x (15: a piece's 4 control points and the query)
+//                 -> Linear(15, 128) -> GELU -> Linear(128, 128) -> GELU
+//                 -> Linear(128, 2) = (u, logit);
+//   surface kind: x (51: a bicubic patch's 16 control points and the query)
+//                 -> Linear(51, 128) -> GELU -> Linear(128, 128) -> GELU
+//                 -> Linear(128, 3) = (s, t, logit).
 // Parameter layout (FP32, row-major W[out][in]): W1 | b1 | W2 | b2 | W3 | b3.
+// This file holds both kinds' training and inference kernels and the curve
+// path; the surface path lives with the other surface kernels.
 //
-// Seeded projection of one query:
+// Seeded projection of one query onto a curve:
 //   1. candidates: every piece of the query's curve is bounded by a sphere
 //      around its control points; the K pieces with the smallest sphere lower
 //      bound, the smallest sphere upper bound UB, and the index range [lo, hi]
@@ -54,35 +59,64 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kIn = MREP_NN_IN, kH = MREP_NN_HIDDEN, kOut = MREP_NN_OUT, kK = MREP_NN_K;
-static_assert(kIn == 15 && kH == 128 && kOut == 2 && kK == 4, "kernel tiling assumes 15-128-128-2, 4 candidates");
-constexpr int64_t kOffW1 = 0;
-constexpr int64_t kOffB1 = kOffW1 + (int64_t)kH * kIn;
-constexpr int64_t kOffW2 = kOffB1 + kH;
-constexpr int64_t kOffB2 = kOffW2 + (int64_t)kH * kH;
-constexpr int64_t kOffW3 = kOffB2 + kH;
-constexpr int64_t kOffB3 = kOffW3 + (int64_t)kOut * kH;
-constexpr int64_t kNParams = kOffB3 + kOut;
-
-// BF16 weight image copied into LDS by the inference kernel.  Rows are padded
-// by 16 bytes so that the 16 rows one MFMA operand load touches start in
-// different banks.  Layer 2 and 3 columns are stored in the order in which the
-// previous layer's MFMA output already sits in the lanes (see k_mlp).
-constexpr int kRowW1 = 80;                       // 32 bf16 (15 used) + pad
-constexpr int kRowW2 = 272;                      // 128 bf16 + pad
-constexpr int kImgW1 = 0;
-constexpr int kImgW2 = kImgW1 + kH * kRowW1;     // 10240
-constexpr int kImgW3 = kImgW2 + kH * kRowW2;     // 45056
-constexpr int kImgB1 = kImgW3 + 16 * kRowW2;     // 49408
-constexpr int kImgB2 = kImgB1 + 4 * kH;
-constexpr int kImgB3 = kImgB2 + 4 * kH;
-constexpr int kImgBytes = kImgB3 + 4 * 16;       // 50496
-static_assert(kImgBytes % 16 == 0, "image copied in 16-byte units");
+constexpr int kH = MREP_NN_HIDDEN, kK = MREP_NN_K;
+constexpr int kRowW2 = 272;  // 128 bf16 + 16 bytes pad
+constexpr int kCurveIn = MREP_NN_CURVE_IN;
+static_assert(kH == 128 && kK == 4, "kernel tiling assumes 128 hidden units and 4 candidates");
 
 int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
-constexpr int64_t kParamBytes = ((4 * kNParams + 255) / 256) * 256;
-// state: params | Adam m | Adam v | grad | LDS image
-constexpr int64_t kStateBytes = 4 * kParamBytes + ((kImgBytes + 255) / 256) * 256;
+
+// Sizes of one network kind.  BF16 weight image copied into LDS by the
+// inference kernel: W1 rows of k1 (inputs padded to a multiple of 32) bf16 plus
+// 16 bytes, so that the 16 rows one MFMA operand load touches start in
+// different banks; W2 rows of 128 and W3 rows of 128 (16 rows, out used) with
+// their columns stored in the order in which the previous layer's MFMA output
+// already sits in the lanes (see k_mlp); FP32 biases.
+template <int KB1>
+struct Img {
+    static constexpr int row1 = 64 * KB1 + 16;
+    static constexpr int w2 = kH * row1;
+    static constexpr int w3 = w2 + kH * kRowW2;
+    static constexpr int b1 = w3 + 16 * kRowW2;
+    static constexpr int b2 = b1 + 4 * kH;
+    static constexpr int b3 = b2 + 4 * kH;
+    static constexpr int bytes = b3 + 64;
+    static_assert(bytes % 16 == 0, "image copied in 16-byte units");
+};
+static_assert(Img<1>::bytes == 50496 && Img<2>::bytes == 58688, "image sizes");
+
+struct NetDims {
+    int in, out, k1;
+    int64_t oW1, oB1, oW2, oB2, oW3, oB3, n;
+    int row1, img_w2, img_w3, img_b1, img_b2, img_b3, img_bytes;
+    int64_t param_bytes, state_bytes;
+};
+
+NetDims net_dims(int kind)
+{
+    NetDims d;
+    d.in = kind == MREP_NN_SURFACE ? MREP_NN_SURFACE_IN : MREP_NN_CURVE_IN;
+    d.out = kind == MREP_NN_SURFACE ? MREP_NN_SURFACE_OUT : MREP_NN_CURVE_OUT;
+    d.k1 = ((d.in + 31) / 32) * 32;
+    d.oW1 = 0;
+    d.oB1 = d.oW1 + (int64_t)kH * d.in;
+    d.oW2 = d.oB1 + kH;
+    d.oB2 = d.oW2 + (int64_t)kH * kH;
+    d.oW3 = d.oB2 + kH;
+    d.oB3 = d.oW3 + (int64_t)d.out * kH;
+    d.n = d.oB3 + d.out;
+    const bool two = d.k1 == 64;
+    d.row1 = two ? Img<2>::row1 : Img<1>::row1;
+    d.img_w2 = two ? Img<2>::w2 : Img<1>::w2;
+    d.img_w3 = two ? Img<2>::w3 : Img<1>::w3;
+    d.img_b1 = two ? Img<2>::b1 : Img<1>::b1;
+    d.img_b2 = two ? Img<2>::b2 : Img<1>::b2;
+    d.img_b3 = two ? Img<2>::b3 : Img<1>::b3;
+    d.img_bytes = two ? Img<2>::bytes : Img<1>::bytes;
+    d.param_bytes = a256(4 * d.n);
+    d.state_bytes = 4 * d.param_bytes + a256(d.img_bytes);
+    return d;
+}
 
 #define NN_HIP(expr)                                                              \
     do {                                                                          \
@@ -188,16 +222,22 @@ __global__ __launch_bounds__(256) void k_colsum(int64_t M, int N, const float* _
     if (threadIdx.x == 0) out[n] = s[0];
 }
 
-// Loss a (y0 - u*)^2 + BCE(y1, a) per row and dL/dY of the batch mean.
-__global__ void k_loss_grad(int64_t B, const float* __restrict__ Y, const float* __restrict__ us,
+// Loss a |y_param - t|^2 + BCE(y_logit, a) per row (outputs: out - 1 parameters, then the logit)
+// and dL/dY of the batch mean.
+__global__ void k_loss_grad(int64_t B, int out, const float* __restrict__ Y, const float* __restrict__ T,
                             const float* __restrict__ acc, float* __restrict__ dY, float* __restrict__ row_loss)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B) return;
-    const float a = acc[i], du = Y[2 * i] - us[i], z = Y[2 * i + 1];
-    row_loss[i] = a * du * du + fmaxf(z, 0.f) - z * a + log1pf(expf(-fabsf(z)));
-    dY[2 * i] = 2.f * a * du / (float)B;
-    dY[2 * i + 1] = (1.f / (1.f + expf(-z)) - a) / (float)B;
+    const float a = acc[i], z = Y[i * out + out - 1];
+    float mse = 0.f;
+    for (int o = 0; o < out - 1; ++o) {
+        const float du = Y[i * out + o] - T[i * (out - 1) + o];
+        mse += du * du;
+        dY[i * out + o] = 2.f * a * du / (float)B;
+    }
+    row_loss[i] = a * mse + fmaxf(z, 0.f) - z * a + log1pf(expf(-fabsf(z)));
+    dY[i * out + out - 1] = (1.f / (1.f + expf(-z)) - a) / (float)B;
 }
 
 // mean of x[0..n) into *out (one block, fixed order)
@@ -217,16 +257,16 @@ __global__ __launch_bounds__(256) void k_mean(int64_t n, const float* __restrict
 
 // Minibatch gather: rows[i] selects the training row of batch row i; a row
 // outside [0, n_rows) becomes an all-zero row.
-__global__ void k_gather(int64_t B, const int32_t* __restrict__ rows, int64_t n_rows, const float* __restrict__ x,
-                         const float* __restrict__ us, const float* __restrict__ acc, float* __restrict__ xb,
-                         float* __restrict__ usb, float* __restrict__ accb)
+__global__ void k_gather(int64_t B, const int32_t* __restrict__ rows, int64_t n_rows, int in, int nt,
+                         const float* __restrict__ x, const float* __restrict__ t, const float* __restrict__ acc,
+                         float* __restrict__ xb, float* __restrict__ tb, float* __restrict__ accb)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B) return;
     const int64_t r = rows[i];
     const bool ok = r >= 0 && r < n_rows;
-    for (int k = 0; k < kIn; ++k) xb[i * kIn + k] = ok ? x[r * kIn + k] : 0.f;
-    usb[i] = ok ? us[r] : 0.f;
+    for (int k = 0; k < in; ++k) xb[i * in + k] = ok ? x[r * in + k] : 0.f;
+    for (int k = 0; k < nt; ++k) tb[i * nt + k] = ok ? t[r * nt + k] : 0.f;
     accb[i] = ok ? acc[r] : 0.f;
 }
 
@@ -246,43 +286,43 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, 
 
 // FP32 master weights -> BF16 LDS image (one thread per 2-byte slot; the FP32
 // bias slots are written by the thread of their first half).
-__global__ void k_pack(const float* __restrict__ P, uint8_t* __restrict__ img)
+__global__ void k_pack(NetDims d, const float* __restrict__ P, uint8_t* __restrict__ img)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kImgBytes / 2) return;
+    if (i >= d.img_bytes / 2) return;
     const int off = 2 * i;
-    if (off >= kImgB1) {
+    if (off >= d.img_b1) {
         if (off & 2) return;
         float v = 0.f;
-        if (off < kImgB2) v = P[kOffB1 + (off - kImgB1) / 4];
-        else if (off < kImgB3) v = P[kOffB2 + (off - kImgB2) / 4];
-        else if ((off - kImgB3) / 4 < kOut) v = P[kOffB3 + (off - kImgB3) / 4];
+        if (off < d.img_b2) v = P[d.oB1 + (off - d.img_b1) / 4];
+        else if (off < d.img_b3) v = P[d.oB2 + (off - d.img_b2) / 4];
+        else if ((off - d.img_b3) / 4 < d.out) v = P[d.oB3 + (off - d.img_b3) / 4];
         *reinterpret_cast<float*>(img + off) = v;
         return;
     }
     float v = 0.f;
-    if (off < kImgW2) {
-        const int h = off / kRowW1, k = (off % kRowW1) / 2;
-        if (k < kIn) v = P[kOffW1 + h * kIn + k];
+    if (off < d.img_w2) {
+        const int h = off / d.row1, k = (off % d.row1) / 2;
+        if (k < d.in) v = P[d.oW1 + h * d.in + k];
     } else {
-        const bool l3 = off >= kImgW3;
-        const int base = l3 ? kImgW3 : kImgW2;
+        const bool l3 = off >= d.img_w3;
+        const int base = l3 ? d.img_w3 : d.img_w2;
         const int h = (off - base) / kRowW2, p = ((off - base) % kRowW2) / 2;
-        if (p < kH && (!l3 || h < kOut)) {
+        if (p < kH && (!l3 || h < d.out)) {
             // K position p = (kb, g, j) holds hidden unit 32 kb + 16 (j >> 2) + 4 g + (j & 3)
             const int kb = p >> 5, g = (p >> 3) & 3, j = p & 7;
             const int src = 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3);
-            v = l3 ? P[kOffW3 + h * kH + src] : P[kOffW2 + h * kH + src];
+            v = l3 ? P[d.oW3 + h * kH + src] : P[d.oW2 + h * kH + src];
         }
     }
     *reinterpret_cast<__bf16*>(img + off) = (__bf16)v;
 }
 
 struct TrainWork {
-    float *Xb, *Usb, *Ab, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH, *dZ, *rowl;
+    float *Xb, *Tb, *Ab, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH, *dZ, *rowl;
 };
 
-int64_t train_layout(int64_t B, char* base, TrainWork* w)
+int64_t train_layout(const NetDims& d, int64_t B, char* base, TrainWork* w)
 {
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -290,12 +330,12 @@ int64_t train_layout(int64_t B, char* base, TrainWork* w)
         off = a256(off + bytes);
         return o;
     };
-    int64_t oXb = take(4 * B * kIn), oUs = take(4 * B), oA = take(4 * B);
+    int64_t oXb = take(4 * B * d.in), oT = take(4 * B * (d.out - 1)), oA = take(4 * B);
     int64_t oZ1 = take(4 * B * kH), oH1 = take(4 * B * kH), oZ2 = take(4 * B * kH), oH2 = take(4 * B * kH);
-    int64_t oY = take(4 * B * kOut), odY = take(4 * B * kOut), odH = take(4 * B * kH), odZ = take(4 * B * kH);
+    int64_t oY = take(4 * B * d.out), odY = take(4 * B * d.out), odH = take(4 * B * kH), odZ = take(4 * B * kH);
     int64_t orl = take(4 * B);
     if (w) {
-        w->Xb = (float*)(base + oXb); w->Usb = (float*)(base + oUs); w->Ab = (float*)(base + oA);
+        w->Xb = (float*)(base + oXb); w->Tb = (float*)(base + oT); w->Ab = (float*)(base + oA);
         w->Z1 = (float*)(base + oZ1); w->H1 = (float*)(base + oH1); w->Z2 = (float*)(base + oZ2);
         w->H2 = (float*)(base + oH2); w->Y = (float*)(base + oY); w->dY = (float*)(base + odY);
         w->dH = (float*)(base + odH); w->dZ = (float*)(base + odZ); w->rowl = (float*)(base + orl);
@@ -303,37 +343,37 @@ int64_t train_layout(int64_t B, char* base, TrainWork* w)
     return off;
 }
 
-int forward(const float* P, int64_t B, const float* X, const TrainWork& w, hipStream_t st)
+int forward(const NetDims& d, const float* P, int64_t B, const float* X, const TrainWork& w, hipStream_t st)
 {
-    NN_HIP(gemm(GemmArgs{(int)B, kH, kIn, X, kIn, 1, P + kOffW1, 1, kIn, w.Z1, kH, 1}, st));
-    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z1, P + kOffB1, w.H1);
-    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.H1, kH, 1, P + kOffW2, 1, kH, w.Z2, kH, 1}, st));
-    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z2, P + kOffB2, w.H2);
-    NN_HIP(gemm(GemmArgs{(int)B, kOut, kH, w.H2, kH, 1, P + kOffW3, 1, kH, w.Y, kOut, 1}, st));
-    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kOut)), dim3(256), 0, st, B, kOut, w.Y, P + kOffB3,
+    NN_HIP(gemm(GemmArgs{(int)B, kH, d.in, X, d.in, 1, P + d.oW1, 1, d.in, w.Z1, kH, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z1, P + d.oB1, w.H1);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.H1, kH, 1, P + d.oW2, 1, kH, w.Z2, kH, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * kH)), dim3(256), 0, st, B, kH, w.Z2, P + d.oB2, w.H2);
+    NN_HIP(gemm(GemmArgs{(int)B, d.out, kH, w.H2, kH, 1, P + d.oW3, 1, kH, w.Y, d.out, 1}, st));
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(B * d.out)), dim3(256), 0, st, B, d.out, w.Y, P + d.oB3,
                        (float*)nullptr);
     NN_HIP(hipGetLastError());
     return MREP_OK;
 }
 
-int backward(const float* P, int64_t B, const float* X, const float* us, const float* acc, const TrainWork& w,
-             float* G, float* loss_out, hipStream_t st)
+int backward(const NetDims& d, const float* P, int64_t B, const float* X, const float* T, const float* acc,
+             const TrainWork& w, float* G, float* loss_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_loss_grad, dim3(blocks_for(B)), dim3(256), 0, st, B, w.Y, us, acc, w.dY, w.rowl);
+    hipLaunchKernelGGL(k_loss_grad, dim3(blocks_for(B)), dim3(256), 0, st, B, d.out, w.Y, T, acc, w.dY, w.rowl);
     if (loss_out) hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, B, w.rowl, loss_out);
     // layer 3: dW3 = dY^T H2, db3 = colsum dY, dH2 = dY W3
-    NN_HIP(gemm(GemmArgs{kOut, kH, (int)B, w.dY, 1, kOut, w.H2, kH, 1, G + kOffW3, kH, 1}, st));
-    hipLaunchKernelGGL(k_colsum, dim3(kOut), dim3(256), 0, st, B, kOut, w.dY, G + kOffB3);
-    NN_HIP(gemm(GemmArgs{(int)B, kH, kOut, w.dY, kOut, 1, P + kOffW3, kH, 1, w.dH, kH, 1}, st));
+    NN_HIP(gemm(GemmArgs{d.out, kH, (int)B, w.dY, 1, d.out, w.H2, kH, 1, G + d.oW3, kH, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(d.out), dim3(256), 0, st, B, d.out, w.dY, G + d.oB3);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, d.out, w.dY, d.out, 1, P + d.oW3, kH, 1, w.dH, kH, 1}, st));
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z2, w.dZ);
     // layer 2: dW2 = dZ2^T H1, db2, dH1 = dZ2 W2
-    NN_HIP(gemm(GemmArgs{kH, kH, (int)B, w.dZ, 1, kH, w.H1, kH, 1, G + kOffW2, kH, 1}, st));
-    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + kOffB2);
-    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.dZ, kH, 1, P + kOffW2, kH, 1, w.dH, kH, 1}, st));
+    NN_HIP(gemm(GemmArgs{kH, kH, (int)B, w.dZ, 1, kH, w.H1, kH, 1, G + d.oW2, kH, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + d.oB2);
+    NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.dZ, kH, 1, P + d.oW2, kH, 1, w.dH, kH, 1}, st));
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z1, w.dZ);
     // layer 1: dW1 = dZ1^T X, db1
-    NN_HIP(gemm(GemmArgs{kH, kIn, (int)B, w.dZ, 1, kH, X, kIn, 1, G + kOffW1, kIn, 1}, st));
-    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + kOffB1);
+    NN_HIP(gemm(GemmArgs{kH, d.in, (int)B, w.dZ, 1, kH, X, d.in, 1, G + d.oW1, d.in, 1}, st));
+    hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + d.oB1);
     NN_HIP(hipGetLastError());
     return MREP_OK;
 }
@@ -348,8 +388,8 @@ uint64_t splitmix64(uint64_t& s)
 }
 
 // ---------------------------------------------------------------------------
-// Features of a (query, piece) pair, shared by training-data export and the
-// fused inference kernel.
+// Features of a (query, piece) pair of a curve, shared by training-data export
+// and the fused inference kernel.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void pair_features(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, float* x)
 {
@@ -384,41 +424,51 @@ __device__ __forceinline__ void pair_features(const DevGeom& G, const DCurve& cv
 // (Z^T = W X^T): weights are the MFMA A operand, rows the B operand, so each
 // layer's output already sits in the lanes as the next layer's B operand (lane
 // (g, r) holds units 16 t + 4 g + i of row r); the image stores layer 2 and 3
-// weight columns in that order.  Persistent grid; 4 waves per block.
+// weight columns in that order.  Layer 1 takes KB1 K-blocks of 32 inputs.
+// Persistent grid; 4 waves per block.
+// Rows interface: KB1, count(), operand(row, g, kb) = inputs 32 kb + 8 g ..
+// + 7 of the row as BF16, write(row, acc) with acc[o] = output o.
 // ---------------------------------------------------------------------------
+template <int IN, int OUT>
 struct RowsFromMemory {
+    static constexpr int KB1 = (IN + 31) / 32;
     int64_t n;
     const float* x;
     float* y;
     __device__ int64_t count() const { return n; }
-    // B operand of layer 1: lane group g holds inputs 8 g .. 8 g + 7 of the row
-    __device__ bf16x8 operand(int64_t row, int g) const
+    __device__ bf16x8 operand(int64_t row, int g, int kb) const
     {
         bf16x8 v;
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
-        if (row < n && g < 2) {
-            const float* r = x + row * kIn + 8 * g;
+        const int k0 = 32 * kb + 8 * g;
+        if (row < n && k0 < IN) {
+            const float* r = x + row * IN + k0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = (__bf16)((8 * g + j < kIn) ? r[j] : 0.f);
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)((k0 + j < IN) ? r[j] : 0.f);
         }
         return v;
     }
-    __device__ void write(int64_t row, float y0, float y1) const
+    __device__ void write(int64_t row, const floatx4& acc) const
     {
-        if (row < n) { y[2 * row] = y0; y[2 * row + 1] = y1; }
+        if (row < n) {
+#pragma unroll
+            for (int o = 0; o < OUT; ++o) y[OUT * row + o] = acc[o];
+        }
     }
 };
 
-// Rows = (sorted query, candidate) pairs; inputs prepared by k_box as BF16 rows of 16.
+// Rows = (sorted query, candidate piece) pairs of curves; inputs prepared by
+// k_box as BF16 rows of 16.
 struct RowsFromCandidates {
+    static constexpr int KB1 = 1;
     const int32_t* q_off;
     int32_t n_curves;
     const int32_t* cand;  // [n][kK] global piece index or -1
     const uint16_t* xb;   // [n][kK][16] BF16 inputs
     float2* out;          // [n][kK] (u, logit)
     __device__ int64_t count() const { return (int64_t)q_off[n_curves] * kK; }
-    __device__ bf16x8 operand(int64_t row, int g) const
+    __device__ bf16x8 operand(int64_t row, int g, int) const
     {
         bf16x8 v;
 #pragma unroll
@@ -426,9 +476,33 @@ struct RowsFromCandidates {
         if (g < 2 && row < count() && cand[row] >= 0) v = *reinterpret_cast<const bf16x8*>(xb + row * 16 + 8 * g);
         return v;
     }
-    __device__ void write(int64_t row, float y0, float y1) const
+    __device__ void write(int64_t row, const floatx4& acc) const
     {
-        if (row < count()) out[row] = make_float2(y0, cand[row] >= 0 ? y1 : -INFINITY);
+        if (row < count()) out[row] = make_float2(acc[0], cand[row] >= 0 ? acc[1] : -INFINITY);
+    }
+};
+
+// Rows = (sorted query, candidate patch) pairs of surfaces; BF16 rows of 64
+// (51 inputs, zero padded).
+struct RowsFromSurfCandidates {
+    static constexpr int KB1 = 2;
+    const int32_t* q_off;
+    int32_t n_surf;
+    const int32_t* cand;  // [n][kK] global patch index or -1
+    const uint16_t* xb;   // [n][kK][64] BF16 inputs
+    float4* out;          // [n][kK] (s, t, logit, 0)
+    __device__ int64_t count() const { return (int64_t)q_off[n_surf] * kK; }
+    __device__ bf16x8 operand(int64_t row, int g, int kb) const
+    {
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        if (row < count() && cand[row] >= 0) v = *reinterpret_cast<const bf16x8*>(xb + row * 64 + 32 * kb + 8 * g);
+        return v;
+    }
+    __device__ void write(int64_t row, const floatx4& acc) const
+    {
+        if (row < count()) out[row] = make_float4(acc[0], acc[1], cand[row] >= 0 ? acc[2] : -INFINITY, 0.f);
     }
 };
 
@@ -451,8 +525,10 @@ __device__ __forceinline__ floatx4 gelu4(floatx4 z)
 template <typename Rows>
 __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restrict__ img)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t s_img[kImgBytes];
-    for (int i = threadIdx.x; i < kImgBytes / 16; i += 256)
+    constexpr int KB1 = Rows::KB1;
+    using I = Img<KB1>;
+    __shared__ __attribute__((aligned(16))) uint8_t s_img[I::bytes];
+    for (int i = threadIdx.x; i < I::bytes / 16; i += 256)
         reinterpret_cast<uint4*>(s_img)[i] = reinterpret_cast<const uint4*>(img)[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -460,14 +536,19 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += nwaves) {
         const int64_t row = tile * 16 + r;
-        const bf16x8 xb = rows.operand(row, g);
+        bf16x8 xb[KB1];
+#pragma unroll
+        for (int kb = 0; kb < KB1; ++kb) xb[kb] = rows.operand(row, g, kb);
         // layer 1
         floatx4 h[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB1 + 4 * (16 * t + 4 * g));
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + kImgW1 + (16 * t + r) * kRowW1 + 16 * g);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb, acc, 0, 0, 0);
+            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + I::b1 + 4 * (16 * t + 4 * g));
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + (16 * t + r) * I::row1 + 64 * kb + 16 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xb[kb], acc, 0, 0, 0);
+            }
             h[t] = gelu4(acc);
         }
         // layer 2
@@ -476,25 +557,25 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
         for (int kb = 0; kb < 4; ++kb) hb[kb] = pack8(h[2 * kb], h[2 * kb + 1]);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB2 + 4 * (16 * t + 4 * g));
+            floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + I::b2 + 4 * (16 * t + 4 * g));
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
                 const bf16x8 a =
-                    *reinterpret_cast<const bf16x8*>(s_img + kImgW2 + (16 * t + r) * kRowW2 + 64 * kb + 16 * g);
+                    *reinterpret_cast<const bf16x8*>(s_img + I::w2 + (16 * t + r) * kRowW2 + 64 * kb + 16 * g);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
             }
             h[t] = gelu4(acc);
         }
-        // layer 3 (rows 0, 1 of the 16-row weight tile are the outputs)
+        // layer 3 (the first rows of the 16-row weight tile are the outputs)
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) hb[kb] = pack8(h[2 * kb], h[2 * kb + 1]);
-        floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + kImgB3 + 16 * g);
+        floatx4 acc = *reinterpret_cast<const floatx4*>(s_img + I::b3 + 16 * g);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + kImgW3 + r * kRowW2 + 64 * kb + 16 * g);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(s_img + I::w3 + r * kRowW2 + 64 * kb + 16 * g);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
         }
-        if (g == 0) rows.write(row, acc[0], acc[1]);
+        if (g == 0) rows.write(row, acc);
     }
 }
 
@@ -686,9 +767,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
     }
     if (out.xb && sub < kK) {
         const uint64_t kk = sub == 0 ? key[0] : (sub == 1 ? key[1] : (sub == 2 ? key[2] : key[3]));
-        float f[kIn];
+        float f[kCurveIn];
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) f[k] = 0.f;
+        for (int k = 0; k < kCurveIn; ++k) f[k] = 0.f;
         if (kk != ~0ull) {
             const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
             pair_features(G, cv, cv.seg_off + (uint32_t)kk, q, f);
@@ -697,7 +778,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint16_t lo = __builtin_bit_cast(uint16_t, (__bf16)f[2 * k]);
-            const uint16_t hi = 2 * k + 1 < kIn ? __builtin_bit_cast(uint16_t, (__bf16)f[2 * k + 1]) : (uint16_t)0;
+            const uint16_t hi = 2 * k + 1 < kCurveIn ? __builtin_bit_cast(uint16_t, (__bf16)f[2 * k + 1]) : (uint16_t)0;
             w[k] = (uint32_t)lo | ((uint32_t)hi << 16);
         }
         uint4* dst = reinterpret_cast<uint4*>(out.xb + (j * kK + sub) * 16);
@@ -948,11 +1029,11 @@ __global__ void k_feat_write(DevGeom G, const int32_t* __restrict__ cid, const d
     const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
     for (int k = 0; k < kK; ++k) {
         const int32_t s = cand[j * kK + k];
-        float f[kIn];
-        for (int i = 0; i < kIn; ++i) f[i] = 0.f;
+        float f[kCurveIn];
+        for (int i = 0; i < kCurveIn; ++i) f[i] = 0.f;
         if (s >= 0) pair_features(G, cv, s, q, f);
         seg_out[(int64_t)qi * kK + k] = s >= 0 ? (int32_t)(s - cv.seg_off) : -1;
-        for (int i = 0; i < kIn; ++i) x_out[((int64_t)qi * kK + k) * kIn + i] = f[i];
+        for (int i = 0; i < kCurveIn; ++i) x_out[((int64_t)qi * kK + k) * kCurveIn + i] = f[i];
     }
 }
 
@@ -961,7 +1042,7 @@ __global__ void k_fill_feat(int64_t n, int32_t* __restrict__ seg_out, float* __r
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * kK) return;
     seg_out[i] = -1;
-    for (int k = 0; k < kIn; ++k) x_out[i * kIn + k] = 0.f;
+    for (int k = 0; k < kCurveIn; ++k) x_out[i * kCurveIn + k] = 0.f;
 }
 
 
@@ -1013,16 +1094,21 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
 struct mrep_nn {
     uint8_t* base = nullptr;  // device: params | m | v | grad | image
     int64_t step = 0;
+    int kind = MREP_NN_CURVE;
+    NetDims d;
     float* params() const { return (float*)base; }
-    float* m() const { return (float*)(base + kParamBytes); }
-    float* v() const { return (float*)(base + 2 * kParamBytes); }
-    float* grad() const { return (float*)(base + 3 * kParamBytes); }
-    uint8_t* img() const { return base + 4 * kParamBytes; }
+    float* m() const { return (float*)(base + d.param_bytes); }
+    float* v() const { return (float*)(base + 2 * d.param_bytes); }
+    float* grad() const { return (float*)(base + 3 * d.param_bytes); }
+    uint8_t* img() const { return base + 4 * d.param_bytes; }
 };
+
+static bool known_kind(int32_t kind) { return kind == MREP_NN_CURVE || kind == MREP_NN_SURFACE; }
 
 static int pack_image(const mrep_nn* nn, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack, dim3(blocks_for(kImgBytes / 2)), dim3(256), 0, st, (const float*)nn->params(), nn->img());
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(nn->d.img_bytes / 2)), dim3(256), 0, st, nn->d,
+                       (const float*)nn->params(), nn->img());
     NN_HIP(hipGetLastError());
     return MREP_OK;
 }
@@ -1041,29 +1127,49 @@ static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id,
     return MREP_OK;
 }
 
-extern "C" {
+namespace mrep {
 
-int32_t mrep_nn_param_count(void) { return (int32_t)kNParams; }
+int nn_kind(const mrep_nn* nn) { return nn ? nn->kind : -1; }
 
-int32_t mrep_nn_bytes(int64_t batch, int64_t* state_bytes, int64_t* work_bytes)
+int nn_score_surface_pairs(const mrep_nn* nn, const int32_t* q_off, int32_t n_surf, const int32_t* cand,
+                           const uint16_t* xb, float4* out, int64_t n_rows, hipStream_t st)
 {
-    if (batch < 0 || (!state_bytes && !work_bytes)) {
-        set_error("mrep_nn_bytes: negative batch or no output");
-        return MREP_E_INVALID_ARG;
-    }
-    if (state_bytes) *state_bytes = kStateBytes;
-    if (work_bytes) *work_bytes = train_layout(batch, nullptr, nullptr);
+    int rc = pack_image(nn, st);
+    if (rc) return rc;
+    RowsFromSurfCandidates rows{q_off, n_surf, cand, xb, out};
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_rows + 63) / 64, 2048));
+    hipLaunchKernelGGL(k_mlp<RowsFromSurfCandidates>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
+    NN_HIP(hipGetLastError());
     return MREP_OK;
 }
 
-int32_t mrep_nn_bind(void* dev_state, int64_t bytes, mrep_nn** out)
+}  // namespace mrep
+
+extern "C" {
+
+int32_t mrep_nn_param_count(int32_t kind) { return known_kind(kind) ? (int32_t)net_dims(kind).n : -1; }
+
+int32_t mrep_nn_bytes(int32_t kind, int64_t batch, int64_t* state_bytes, int64_t* work_bytes)
 {
-    if (!dev_state || !out) {
-        set_error("mrep_nn_bind: null pointer");
+    if (!known_kind(kind) || batch < 0 || (!state_bytes && !work_bytes)) {
+        set_error("mrep_nn_bytes: unknown kind, negative batch or no output");
+        return MREP_E_INVALID_ARG;
+    }
+    const NetDims d = net_dims(kind);
+    if (state_bytes) *state_bytes = d.state_bytes;
+    if (work_bytes) *work_bytes = train_layout(d, batch, nullptr, nullptr);
+    return MREP_OK;
+}
+
+int32_t mrep_nn_bind(int32_t kind, void* dev_state, int64_t bytes, mrep_nn** out)
+{
+    if (!dev_state || !out || !known_kind(kind)) {
+        set_error("mrep_nn_bind: null pointer or unknown kind");
         return MREP_E_INVALID_ARG;
     }
     *out = nullptr;
-    if (bytes < kStateBytes) {
+    const NetDims d = net_dims(kind);
+    if (bytes < d.state_bytes) {
         set_error("mrep_nn_bind: buffer smaller than mrep_nn_bytes' state size");
         return MREP_E_SMALL_BUFFER;
     }
@@ -1075,6 +1181,8 @@ int32_t mrep_nn_bind(void* dev_state, int64_t bytes, mrep_nn** out)
     if (rc) return rc;
     mrep_nn* n = new mrep_nn();
     n->base = (uint8_t*)dev_state;
+    n->kind = kind;
+    n->d = d;
     *out = n;
     return MREP_OK;
 }
@@ -1083,16 +1191,17 @@ void mrep_nn_release(mrep_nn* nn) { delete nn; }
 
 int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stream)
 {
-    if (!nn || !host || n != kNParams) {
+    if (!nn || !host || n != nn->d.n) {
         set_error("mrep_nn_set_params: null pointer or wrong parameter count");
         return MREP_E_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    std::vector<float> zero((size_t)kNParams, 0.f);
-    NN_HIP(hipMemcpyAsync(nn->params(), host, 4 * kNParams, hipMemcpyHostToDevice, st));
-    NN_HIP(hipMemcpyAsync(nn->m(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
-    NN_HIP(hipMemcpyAsync(nn->v(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
-    NN_HIP(hipMemcpyAsync(nn->grad(), zero.data(), 4 * kNParams, hipMemcpyHostToDevice, st));
+    const int64_t np = nn->d.n;
+    std::vector<float> zero((size_t)np, 0.f);
+    NN_HIP(hipMemcpyAsync(nn->params(), host, 4 * np, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->m(), zero.data(), 4 * np, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->v(), zero.data(), 4 * np, hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemcpyAsync(nn->grad(), zero.data(), 4 * np, hipMemcpyHostToDevice, st));
     // pageable host sources: complete before returning
     NN_HIP(hipStreamSynchronize(st));
     nn->step = 0;
@@ -1101,12 +1210,12 @@ int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stre
 
 int32_t mrep_nn_get_params(const mrep_nn* nn, float* host, int64_t n, void* stream)
 {
-    if (!nn || !host || n != kNParams) {
+    if (!nn || !host || n != nn->d.n) {
         set_error("mrep_nn_get_params: null pointer or wrong parameter count");
         return MREP_E_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    NN_HIP(hipMemcpyAsync(host, nn->params(), 4 * kNParams, hipMemcpyDeviceToHost, st));
+    NN_HIP(hipMemcpyAsync(host, nn->params(), 4 * nn->d.n, hipMemcpyDeviceToHost, st));
     NN_HIP(hipStreamSynchronize(st));
     return MREP_OK;
 }
@@ -1118,7 +1227,8 @@ int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream)
         return MREP_E_INVALID_ARG;
     }
     // weights uniform in +-1/sqrt(fan_in), biases zero
-    std::vector<float> p((size_t)kNParams, 0.f);
+    const NetDims& d = nn->d;
+    std::vector<float> p((size_t)d.n, 0.f);
     uint64_t s = seed;
     auto fill = [&](int64_t off, int64_t count, int fan_in) {
         const double a = 1.0 / sqrt((double)fan_in);
@@ -1127,10 +1237,10 @@ int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream)
             p[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
         }
     };
-    fill(kOffW1, (int64_t)kH * kIn, kIn);
-    fill(kOffW2, (int64_t)kH * kH, kH);
-    fill(kOffW3, (int64_t)kOut * kH, kH);
-    return mrep_nn_set_params(nn, p.data(), kNParams, stream);
+    fill(d.oW1, (int64_t)kH * d.in, d.in);
+    fill(d.oW2, (int64_t)kH * kH, kH);
+    fill(d.oW3, (int64_t)d.out * kH, kH);
+    return mrep_nn_set_params(nn, p.data(), d.n, stream);
 }
 
 int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, void* work, int64_t work_bytes,
@@ -1146,14 +1256,14 @@ int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, 
         return MREP_E_INVALID_ARG;
     }
     TrainWork w;
-    if (work_bytes < train_layout(n, (char*)work, &w)) {
-        set_error("mrep_nn_forward: work buffer smaller than mrep_nn_bytes(n)");
+    if (work_bytes < train_layout(nn->d, n, (char*)work, &w)) {
+        set_error("mrep_nn_forward: work buffer smaller than mrep_nn_bytes(kind, n)");
         return MREP_E_SMALL_BUFFER;
     }
     hipStream_t st = (hipStream_t)stream;
-    int rc = forward(nn->params(), n, x, w, st);
+    int rc = forward(nn->d, nn->params(), n, x, w, st);
     if (rc) return rc;
-    NN_HIP(hipMemcpyAsync(y, w.Y, 4 * n * kOut, hipMemcpyDeviceToDevice, st));
+    NN_HIP(hipMemcpyAsync(y, w.Y, 4 * n * nn->d.out, hipMemcpyDeviceToDevice, st));
     return MREP_OK;
 }
 
@@ -1167,18 +1277,23 @@ int32_t mrep_nn_infer(const mrep_nn* nn, int64_t n, const float* x, float* y, vo
     hipStream_t st = (hipStream_t)stream;
     int rc = pack_image(nn, st);
     if (rc) return rc;
-    RowsFromMemory rows{n, x, y};
     const unsigned nb = (unsigned)std::min<int64_t>((n + 63) / 64, 2048);
-    hipLaunchKernelGGL(k_mlp<RowsFromMemory>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
+    if (nn->kind == MREP_NN_SURFACE) {
+        using R = RowsFromMemory<MREP_NN_SURFACE_IN, MREP_NN_SURFACE_OUT>;
+        hipLaunchKernelGGL(k_mlp<R>, dim3(nb), dim3(256), 0, st, R{n, x, y}, (const uint8_t*)nn->img());
+    } else {
+        using R = RowsFromMemory<MREP_NN_CURVE_IN, MREP_NN_CURVE_OUT>;
+        hipLaunchKernelGGL(k_mlp<R>, dim3(nb), dim3(256), 0, st, R{n, x, y}, (const uint8_t*)nn->img());
+    }
     NN_HIP(hipGetLastError());
     return MREP_OK;
 }
 
-int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* u_star, const float* accept,
+int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const float* target, const float* accept,
                            int64_t batch, const int32_t* rows, float lr, float* loss_out, float* grad_out,
                            void* work, int64_t work_bytes, void* stream)
 {
-    if (!nn || batch <= 0 || !x || !u_star || !accept || !work || (!rows && n_rows < batch)) {
+    if (!nn || batch <= 0 || !x || !target || !accept || !work || (!rows && n_rows < batch)) {
         set_error("mrep_nn_train_step: null pointer or empty batch");
         return MREP_E_INVALID_ARG;
     }
@@ -1186,28 +1301,29 @@ int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const fl
         set_error("mrep_nn_train_step: batch too large or negative learning rate");
         return MREP_E_INVALID_ARG;
     }
+    const NetDims& d = nn->d;
     TrainWork w;
-    if (work_bytes < train_layout(batch, (char*)work, &w)) {
-        set_error("mrep_nn_train_step: work buffer smaller than mrep_nn_bytes(batch)");
+    if (work_bytes < train_layout(d, batch, (char*)work, &w)) {
+        set_error("mrep_nn_train_step: work buffer smaller than mrep_nn_bytes(kind, batch)");
         return MREP_E_SMALL_BUFFER;
     }
     hipStream_t st = (hipStream_t)stream;
-    const float *X = x, *Us = u_star, *A = accept;
+    const float *X = x, *T = target, *A = accept;
     if (rows) {
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(batch)), dim3(256), 0, st, batch, rows, n_rows, x, u_star,
-                           accept, w.Xb, w.Usb, w.Ab);
-        X = w.Xb; Us = w.Usb; A = w.Ab;
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(batch)), dim3(256), 0, st, batch, rows, n_rows, d.in, d.out - 1,
+                           x, target, accept, w.Xb, w.Tb, w.Ab);
+        X = w.Xb; T = w.Tb; A = w.Ab;
     }
-    int rc = forward(nn->params(), batch, X, w, st);
+    int rc = forward(d, nn->params(), batch, X, w, st);
     if (rc) return rc;
-    rc = backward(nn->params(), batch, X, Us, A, w, nn->grad(), loss_out, st);
+    rc = backward(d, nn->params(), batch, X, T, A, w, nn->grad(), loss_out, st);
     if (rc) return rc;
-    if (grad_out) NN_HIP(hipMemcpyAsync(grad_out, nn->grad(), 4 * kNParams, hipMemcpyDeviceToDevice, st));
+    if (grad_out) NN_HIP(hipMemcpyAsync(grad_out, nn->grad(), 4 * d.n, hipMemcpyDeviceToDevice, st));
     if (lr > 0.f) {
         nn->step += 1;
         const float c1 = (float)(1.0 - pow(0.9, (double)nn->step)), c2 = (float)(1.0 - pow(0.999, (double)nn->step));
-        hipLaunchKernelGGL(k_adam, dim3(blocks_for(kNParams)), dim3(256), 0, st, kNParams, nn->params(), nn->m(),
-                           nn->v(), (const float*)nn->grad(), lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for(d.n)), dim3(256), 0, st, d.n, nn->params(), nn->m(), nn->v(),
+                           (const float*)nn->grad(), lr, 0.9f, 0.999f, 1e-8f, c1, c2);
         NN_HIP(hipGetLastError());
     }
     return MREP_OK;
@@ -1272,6 +1388,10 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
         set_error("mrep_project_curves_seeded: null or surface geometry, or negative n");
         return MREP_E_INVALID_ARG;
     }
+    if (nn && nn->kind != MREP_NN_CURVE) {
+        set_error("mrep_project_curves_seeded: the network is not of kind MREP_NN_CURVE");
+        return MREP_E_INVALID_ARG;
+    }
     int rc = check_opts(opts);
     if (rc) return rc;
     if (opts->precision != MREP_PREC_BF16) {
@@ -1314,7 +1434,7 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
     if (nn) {
         rc = pack_image(nn, st);
         if (rc) return rc;
-        RowsFromCandidates rows{w.q_off, (int32_t)nc, w.box.cand, w.box.xb, w.scores};
+        const RowsFromCandidates rows{w.q_off, (int32_t)nc, w.box.cand, w.box.xb, w.scores};
         const unsigned nb = (unsigned)std::min<int64_t>((n * kK + 63) / 64, 2048);
         hipLaunchKernelGGL(k_mlp<RowsFromCandidates>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
         NN_HIP(hipGetLastError());

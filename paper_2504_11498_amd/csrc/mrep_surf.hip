@@ -20,6 +20,14 @@
 //      the gradient pointing across, and from the runner-up when it is within
 //      the tie margin; write (u, v), distance, patch index and flags.
 // Queries whose list overflows take a wave-per-query scan of all their patches.
+//
+// Seeded calls (learned seeding, an extension): step 2 also keeps each
+// query's 4 patches with the smallest sphere lower bounds and writes their
+// network inputs; the surface network scores them; Newton from the predicted
+// (s, t) on the best-scored patch attains a first upper bound.  A pair whose
+// sphere lower bound already exceeds the best bound so far is dropped before
+// its sampled bound is computed; the rest of the pipeline is unchanged, so the
+// answer is the certified global minimum whatever the network predicts.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -43,6 +51,8 @@ constexpr int kSphCap = 256;
 constexpr int kXcds = 8;
 constexpr int64_t kSurfPairsPerQuery = 96;
 constexpr int kGrid = 7;  // samples per direction in a patch
+constexpr int kK = MREP_NN_K;  // candidate patches scored per query (seeded calls)
+constexpr int kFeat = MREP_NN_SURFACE_IN;
 static_assert(kSphThreads == 256, "sphere kernel: 32 queries x 8 lanes");
 
 struct DevSurf {
@@ -84,10 +94,69 @@ __device__ __forceinline__ float s_margin(float d, const DSurf& sf, float tie_re
 // ---------------------------------------------------------------------------
 // 2. sphere candidate lists
 // ---------------------------------------------------------------------------
+// Seeded calls also keep, per query, the kK patches with the smallest lower
+// bounds (ties to the lower index) and write their network inputs.
+struct SphTop {
+    int32_t* cand;  // [n][kK] global patch index (-1: fewer patches)
+    uint16_t* xb;   // [n][kK][64] BF16 network inputs (null: not written)
+};
+
+// float -> uint32 with the same order (negative values included)
+__device__ __forceinline__ uint32_t ord_key(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord_val(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+__device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b)
+{
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// Network inputs of a (query, patch) pair: the 16 control points (row-major,
+// i along u) and the query, minus the control points' centroid, over the
+// diagonal of their box.
+__device__ __forceinline__ void patch_features(const DevSurf& D, const DSurf& sf, int64_t k, const double* q,
+                                               float* x)
+{
+    const float* lp = D.lcp + k * 48;
+    const float4 c = D.sph[k];
+    const float ql[3] = {(float)(q[0] - (sf.origin[0] + (double)c.x)), (float)(q[1] - (sf.origin[1] + (double)c.y)),
+                         (float)(q[2] - (sf.origin[2] + (double)c.z))};
+    float m[3], ext2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float sum = 0.f, lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float v = lp[3 * i + a];
+            sum += v;
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        m[a] = sum * (1.f / 16.f);
+        ext2 += (hi - lo) * (hi - lo);
+    }
+    const float inv = ext2 > 0.f ? 1.f / sqrtf(ext2) : 1.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[3 * i + a] = (lp[3 * i + a] - m[a]) * inv;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[48 + a] = (ql[a] - m[a]) * inv;
+}
+
+template <bool kTop>
 __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* __restrict__ tile_off,
                                                       const int32_t* __restrict__ q_off,
                                                       const int32_t* __restrict__ perm,
-                                                      const double* __restrict__ qxyz, float tie_rel, ScreenOut so)
+                                                      const double* __restrict__ qxyz, float tie_rel, ScreenOut so,
+                                                      SphTop top)
 {
     __shared__ float4 s_sph[kSphChunk];
     __shared__ int32_t s_list[kQueriesPerTile][kSphCap];
@@ -116,6 +185,9 @@ __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* 
     const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
     float ub = INFINITY, thr = 0.f;
     int cnt = 0;
+    uint64_t key[kK];
+#pragma unroll
+    for (int k = 0; k < kK; ++k) key[k] = ~0ull;
     for (int pass = 0; pass < 2; ++pass) {
         for (int c0 = 0; c0 < sf.n_patch; c0 += kSphChunk) {
             const int cn = min(kSphChunk, sf.n_patch - c0);
@@ -123,13 +195,31 @@ __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* 
             for (int i = threadIdx.x; i < cn; i += kSphThreads) s_sph[i] = D.sph[sf.patch_off + c0 + i];
             __syncthreads();
             if (!active) continue;
-            if (pass == 0) {
+            if (pass == 0 && !kTop) {
                 for (int i = sub; i < cn; i += kSphSub) {
                     const float4 p = s_sph[i];
                     const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
                     const float tu = ub - p.w - eps;
                     const float d2 = dx * dx + dy * dy + dz * dz;
                     if (!(tu > 0.f) || d2 < tu * tu) ub = fminf(ub, sqrtf(d2) + p.w + eps);
+                }
+            } else if (pass == 0) {
+                for (int i = sub; i < cn; i += kSphSub) {
+                    const float4 p = s_sph[i];
+                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    const float re = p.w + eps;
+                    const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
+                    const float tu = ub - re;
+                    const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
+                    const bool cu = !(tu > 0.f) || d2 < tu * tu;
+                    if (c4 || cu) {
+                        const float d = sqrtf(d2);
+                        ub = fminf(ub, d + re);
+                        uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
+#pragma unroll
+                        for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
+                    }
                 }
             } else {
                 for (int i0 = 0; i0 < cn; i0 += kSphSub) {
@@ -150,7 +240,21 @@ __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* 
         }
         if (pass == 0) {
 #pragma unroll
-            for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
+            for (int off = 1; off < kSphSub; off <<= 1) {
+                ub = fminf(ub, __shfl_xor(ub, off, 64));
+                if (kTop) {
+                    // merge the lanes' sorted lists: exchange, keep the smaller half (bitonic)
+                    uint64_t o[kK];
+#pragma unroll
+                    for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
+#pragma unroll
+                    for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
+                    cswap(key[0], key[2]);
+                    cswap(key[1], key[3]);
+                    cswap(key[0], key[1]);
+                    cswap(key[2], key[3]);
+                }
+            }
             thr = ub + s_margin(ub, sf, tie_rel);
         }
     }
@@ -181,6 +285,34 @@ __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* 
             if (b + k >= so.pair_cap) break;
             so.pair_seg[b + k] = fits ? (int32_t)(sf.patch_off + s_list[qs][k]) : 0;
             so.pair_j[b + k] = fits ? (int32_t)j : -1;
+        }
+    }
+    if (kTop && sub < kK) {
+        const uint64_t kk = sub == 0 ? key[0] : (sub == 1 ? key[1] : (sub == 2 ? key[2] : key[3]));
+        const int64_t g = kk == ~0ull ? -1 : sf.patch_off + (int64_t)(uint32_t)kk;
+        top.cand[j * kK + sub] = (int32_t)g;
+        if (top.xb) {
+            float f[kFeat];
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) f[k] = 0.f;
+            if (g >= 0) {
+                const int32_t qi = perm[j];
+                const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+                patch_features(D, sf, g, q, f);
+            }
+            uint4* dst = reinterpret_cast<uint4*>(top.xb + (j * kK + sub) * 64);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k0 = 8 * c + 2 * e;
+                    const uint16_t lo = k0 < kFeat ? __builtin_bit_cast(uint16_t, (__bf16)f[k0]) : (uint16_t)0;
+                    const uint16_t hi = k0 + 1 < kFeat ? __builtin_bit_cast(uint16_t, (__bf16)f[k0 + 1]) : (uint16_t)0;
+                    w[e] = (uint32_t)lo | ((uint32_t)hi << 16);
+                }
+                dst[c] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
         }
     }
 }
@@ -419,32 +551,29 @@ __device__ __forceinline__ void bc_edge(const Bicubic& B, int which, Cubic<float
     E.a3 = {c[3][0], c[3][1], c[3][2]};
 }
 
-__device__ PatchMin patch_min(const Bicubic& B)
+// Minimum of f = |S - q|^2 over the patch, or f = +inf when the patch holds no
+// value below `cap` (a value known to be attained elsewhere, plus the tie
+// margin; +inf: no cap).  The 7 x 7 samples give second-order bounds
+// min(corner f) - M h^2 / 8 on every cell and along every edge; an edge or a
+// cell whose bound reaches the best value so far is skipped.
+__device__ PatchMin patch_min(const Bicubic& B, float cap)
 {
-    PatchMin best{0.f, 0.f, INFINITY, 1.f};
-    // edges: certified 1D minima of the four boundary curves
-    for (int w = 0; w < 4; ++w) {
-        Cubic<float> E;
-        bc_edge(B, w, E);
-        float u, d, k;
-        piece_min(E, u, d, k);
-        const float s = w == 0 ? 0.f : (w == 1 ? 1.f : u);
-        const float t = w == 2 ? 0.f : (w == 3 ? 1.f : u);
-        pm_take(best, s, t, d, 1.f);
-    }
+    PatchMin best{0.f, 0.f, cap, 1.f};
     const float h = 1.f / (kGrid - 1);
     float F[kGrid][kGrid];
 #pragma unroll
     for (int i = 0; i < kGrid; ++i)
 #pragma unroll
         for (int j = 0; j < kGrid; ++j) F[i][j] = bc_f(B, i * h, j * h);
-    // Newton from the interior local minima of the samples; the four cells
-    // around such a sample count as covered
+    const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
+    const float gap = (Mss + Mtt) * h * h * 0.125f;
+    // Newton from the interior local minima of the samples below the best; the
+    // four cells around such a sample count as covered
     uint64_t covered = 0;  // bit i*(kGrid-1)+j: cell (i, j)
     for (int i = 1; i < kGrid - 1; ++i)
         for (int j = 1; j < kGrid - 1; ++j) {
             const float v = F[i][j];
-            bool m = true;
+            bool m = v < best.f;
 #pragma unroll
             for (int a = -1; a <= 1; ++a)
 #pragma unroll
@@ -457,9 +586,26 @@ __device__ PatchMin patch_min(const Bicubic& B)
             covered |= 1ull << (i * (kGrid - 1) + (j - 1));
             covered |= 1ull << (i * (kGrid - 1) + j);
         }
+    // edges: certified 1D minima of the boundary curves whose sampled bound
+    // (second-order along the edge) reaches below the best
+    for (int w = 0; w < 4; ++w) {
+        float mn = INFINITY;
+#pragma unroll
+        for (int k = 0; k < kGrid; ++k) {
+            const float v = w == 0 ? F[0][k] : (w == 1 ? F[kGrid - 1][k] : (w == 2 ? F[k][0] : F[k][kGrid - 1]));
+            mn = fminf(mn, v);
+        }
+        const float g1 = (w < 2 ? Mtt : Mss) * h * h * 0.125f;
+        if (!(mn - g1 < best.f * (1.f + 8e-6f))) continue;
+        Cubic<float> E;
+        bc_edge(B, w, E);
+        float u, d, k;
+        piece_min(E, u, d, k);
+        const float s = w == 0 ? 0.f : (w == 1 ? 1.f : u);
+        const float t = w == 2 ? 0.f : (w == 3 ? 1.f : u);
+        pm_take(best, s, t, d, 1.f);
+    }
     // second-order bound of each cell: f >= min(corners) - (M_ss + M_tt) h^2 / 8
-    const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
-    const float gap = (Mss + Mtt) * h * h * 0.125f;
     for (int i = 0; i < kGrid - 1; ++i)
         for (int j = 0; j < kGrid - 1; ++j) {
             if ((covered >> (i * (kGrid - 1) + j)) & 1ull) continue;
@@ -467,6 +613,7 @@ __device__ PatchMin patch_min(const Bicubic& B)
             if (mn - gap < best.f * (1.f - 8e-6f))
                 bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
         }
+    if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f};
     return best;
 }
 
@@ -476,7 +623,7 @@ __device__ PatchMin patch_min(const Bicubic& B)
 // order like integers).
 __global__ __launch_bounds__(256) void k_sbound(DevSurf D, const int32_t* __restrict__ sid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
-                                                ScreenOut so, float* __restrict__ lb,
+                                                ScreenOut so, float tie_rel, float* __restrict__ lb,
                                                 uint32_t* __restrict__ fub)
 {
     const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
@@ -488,6 +635,21 @@ __global__ __launch_bounds__(256) void k_sbound(DevSurf D, const int32_t* __rest
         const int32_t qi = perm[jj];
         const DSurf sf = D.surfs[sid[qi]];
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+        {
+            // sphere bound against the query's best value so far (any value
+            // fub has held is attained, so the test only drops patches that
+            // cannot hold the minimum)
+            const float4 c = D.sph[k];
+            const float dx = (float)(q[0] - sf.origin[0]) - c.x, dy = (float)(q[1] - sf.origin[1]) - c.y,
+                        dz = (float)(q[2] - sf.origin[2]) - c.z;
+            const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float eps = 1e-6f * (d + sqrtf(c.x * c.x + c.y * c.y + c.z * c.z) + (float)sf.diag);
+            const float ub = sqrtf(__uint_as_float(fub[jj]));
+            if (d - c.w - eps > ub + s_margin(ub, sf, tie_rel)) {
+                lb[p] = INFINITY;
+                continue;
+            }
+        }
         Bicubic B;
         load_bicubic(D, sf, k, q, B);
         float mn = INFINITY;
@@ -538,7 +700,9 @@ __global__ __launch_bounds__(256) void k_sgate(DevSurf D, const int32_t* __restr
 __global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                 ScreenOut so, const int32_t* __restrict__ live,
-                                                const int32_t* __restrict__ n_live, float4* __restrict__ res)
+                                                const int32_t* __restrict__ n_live,
+                                                const uint32_t* __restrict__ fub, float tie_rel,
+                                                float4* __restrict__ res)
 {
     const int64_t total = *n_live;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -550,9 +714,50 @@ __global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __rest
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         Bicubic B;
         load_bicubic(D, sf, k, q, B);
-        const PatchMin m = patch_min(B);
+        const float ub = sqrtf(__uint_as_float(fub[jj]));
+        const float thr = ub + s_margin(ub, sf, tie_rel);
+        const PatchMin m = patch_min(B, thr * thr * (1.f + 1e-5f));
         res[p] = make_float4(m.s, m.t, m.f, m.kappa);
     }
+}
+
+// Seeded calls, one thread per query: Newton from the network's (s, t) on the
+// best-scored candidate patch; the attained value (with the same rounding
+// allowance as a sample) is the query's first upper bound.
+__global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restrict__ sid,
+                                               const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
+                                               const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
+                                               const float4* __restrict__ score, uint32_t* __restrict__ fub,
+                                               int32_t* __restrict__ seed_patch)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[D.n_surf]) return;
+    int best = -1;
+    float z = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kK; ++k) {
+        const float zk = score[j * kK + k].z;
+        if (cand[j * kK + k] >= 0 && (best < 0 || zk > z)) { best = k; z = zk; }
+    }
+    if (best < 0) {
+        fub[j] = 0x7f800000u;
+        seed_patch[j] = -1;
+        return;
+    }
+    const int64_t k = cand[j * kK + best];
+    const float4 sc = score[j * kK + best];
+    const int32_t qi = perm[j];
+    const DSurf sf = D.surfs[sid[qi]];
+    const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    Bicubic B;
+    load_bicubic(D, sf, k, q, B);
+    // a prediction that is not a number starts from the patch centre
+    const float s0 = sc.x == sc.x ? fminf(fmaxf(sc.x, 0.f), 1.f) : 0.5f;
+    const float t0 = sc.y == sc.y ? fminf(fmaxf(sc.y, 0.f), 1.f) : 0.5f;
+    PatchMin m{0.f, 0.f, INFINITY, 1.f};
+    bc_newton(B, s0, t0, 0.f, 1.f, 0.f, 1.f, m);
+    fub[j] = __float_as_uint(m.f * (1.f + 4e-6f));
+    seed_patch[j] = (int32_t)k;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
@@ -810,7 +1015,7 @@ __global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __res
                                                  const int32_t* __restrict__ perm, ScreenOut so,
                                                  const float4* __restrict__ res, double tie_rel, int32_t invert,
                                                  int32_t* __restrict__ ovf_list, int32_t* __restrict__ ovf_count,
-                                                 SOuts o)
+                                                 const int32_t* __restrict__ seed_patch, SOuts o)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q_off[D.n_surf]) return;
@@ -828,7 +1033,14 @@ __global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __res
         const float4 r = res[p0 + i];
         s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
     }
-    s_finish(D, sf, x, b1, b2, 0u, tie_rel, invert, qi, o);
+    if (!(b1.d2 < INFINITY)) {
+        // no pair reached below its cap (FP32 rounding at the threshold): full scan
+        ovf_list[atomicAdd(ovf_count, 1)] = (int32_t)j;
+        return;
+    }
+    // seeded calls: the network's patch did not hold the minimum
+    const bool missed = seed_patch && b1.patch != seed_patch[j];
+    s_finish(D, sf, x, b1, b2, missed ? (uint32_t)MREP_F_NN_FALLBACK : 0u, tie_rel, invert, qi, o);
 }
 
 // Overflowed lists: one wave per query over all its patches (sphere bound
@@ -836,7 +1048,7 @@ __global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __res
 __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restrict__ sid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ list, const int32_t* __restrict__ count,
-                                               double tie_rel, int32_t invert, SOuts o)
+                                               double tie_rel, int32_t invert, uint32_t extra, SOuts o)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -864,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restr
             if (sqrtf(dx * dx + dy * dy + dz * dz) - c.w - eps > thr) continue;
             Bicubic B;
             load_bicubic(D, sf, g, x, B);
-            const PatchMin m = patch_min(B);
+            const PatchMin m = patch_min(B, thr * thr * (1.f + 1e-5f));
             s_top2(s_make(D, g, m.s, m.t, m.f, m.kappa), b1, b2);
         }
         // wave top-2
@@ -877,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restr
             s_top2(o1, b1, b2);
             s_top2(o2, b1, b2);
         }
-        if (lane == 0) s_finish(D, sf, x, b1, b2, (uint32_t)MREP_F_FULLSCAN, tie_rel, invert, qi, o);
+        if (lane == 0) s_finish(D, sf, x, b1, b2, (uint32_t)MREP_F_FULLSCAN | extra, tie_rel, invert, qi, o);
     }
 }
 
@@ -911,6 +1123,35 @@ __global__ void k_seval(DevSurf D, int64_t n, const int32_t* __restrict__ sid, c
     }
 }
 
+// Training-data export: the candidates and their FP32 inputs, by query
+__global__ void k_sfeat_write(DevSurf D, const int32_t* __restrict__ sid, const double* __restrict__ qxyz,
+                              const int32_t* __restrict__ q_off, const int32_t* __restrict__ perm,
+                              const int32_t* __restrict__ cand, int32_t* __restrict__ patch_out,
+                              float* __restrict__ x_out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q_off[D.n_surf]) return;
+    const int32_t qi = perm[j];
+    const DSurf sf = D.surfs[sid[qi]];
+    const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
+    for (int k = 0; k < kK; ++k) {
+        const int64_t g = cand[j * kK + k];
+        float f[kFeat];
+        for (int i = 0; i < kFeat; ++i) f[i] = 0.f;
+        if (g >= 0) patch_features(D, sf, g, q, f);
+        patch_out[(int64_t)qi * kK + k] = g >= 0 ? (int32_t)(g - sf.patch_off) : -1;
+        for (int i = 0; i < kFeat; ++i) x_out[((int64_t)qi * kK + k) * kFeat + i] = f[i];
+    }
+}
+
+__global__ void k_sfeat_fill(int64_t n, int32_t* __restrict__ patch_out, float* __restrict__ x_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kK) return;
+    patch_out[i] = -1;
+    for (int k = 0; k < kFeat; ++k) x_out[i * kFeat + k] = 0.f;
+}
+
 struct SWork {
     int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
     ScreenOut so;
@@ -919,9 +1160,13 @@ struct SWork {
     uint32_t* fub;  // [n] best sample value of each query (float bits)
     int32_t* live;   // [cap] pairs that need the patch minimum
     int32_t* n_live; // their count
+    // seeded calls
+    SphTop top;          // [n][kK] candidates, [n][kK][64] BF16 inputs
+    float4* score;       // [n][kK] network outputs
+    int32_t* seed_patch; // [n] seeded patch (global) or -1
 };
 
-int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
+int64_t s_layout(int64_t ns, int64_t n, bool seeded, char* base, SWork* w)
 {
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -934,7 +1179,13 @@ int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
     const int64_t oov = take(4 * n), ocn = take(4 * n), opo = take(4 * n), oub = take(4 * n);
     const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap), olb = take(4 * cap);
     const int64_t ofu = take(4 * n), olv = take(4 * cap), onl = take(4);
+    const int64_t m = seeded ? n : 0;
+    const int64_t oca = take(4 * kK * m), oxb = take(128 * kK * m), osc = take(16 * kK * m), osp = take(4 * m);
     if (w) {
+        w->top.cand = seeded ? (int32_t*)(base + oca) : nullptr;
+        w->top.xb = seeded ? (uint16_t*)(base + oxb) : nullptr;
+        w->score = seeded ? (float4*)(base + osc) : nullptr;
+        w->seed_patch = seeded ? (int32_t*)(base + osp) : nullptr;
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
         w->ovf_count = w->hist + ns;
@@ -963,76 +1214,98 @@ int64_t s_layout(int64_t ns, int64_t n, char* base, SWork* w)
         }                                                                         \
     } while (0)
 
-int32_t run_surf(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* sid, const double* q,
-                 void* ws, int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out, uint32_t* flags_out,
-                 void* stream, int invert)
+int32_t run_surf(const char* fn, const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                 const int32_t* sid, const double* q, void* ws, int64_t ws_bytes, double* uv_out, double* dist_out,
+                 int32_t* patch_out, uint32_t* flags_out, void* stream, int invert)
 {
+    const std::string f(fn);
     if (!geom || n < 0) {
-        set_error("mrep_project_surfaces: null geometry or negative n");
+        set_error(f + ": null geometry or negative n");
         return MREP_E_INVALID_ARG;
     }
     if (geom->kind != MREP_GEOM_SURFACES) {
-        set_error("mrep_project_surfaces: the geometry holds curves");
+        set_error(f + ": the geometry holds curves");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
     if (rc) return rc;
     if (n == 0) return MREP_OK;
     if (n * kSurfPairsPerQuery >= (int64_t)INT32_MAX) {
-        set_error("mrep_project_surfaces: n must be < 2^31 / 96");
+        set_error(f + ": n must be < 2^31 / 96");
         return MREP_E_INVALID_ARG;
     }
     if (!sid || !q || !ws || !uv_out || !dist_out || !patch_out || !flags_out) {
-        set_error("mrep_project_surfaces: null pointer");
+        set_error(f + ": null pointer");
         return MREP_E_INVALID_ARG;
     }
     const int64_t ns = geom->sg.L.n_surf;
     if (ns == 0) {
-        set_error("mrep_project_surfaces: geometry has no surfaces");
+        set_error(f + ": geometry has no surfaces");
         return MREP_E_INVALID_ARG;
     }
+    const bool seeded = nn != nullptr;
     SWork w;
-    if (ws_bytes < s_layout(ns, n, (char*)ws, &w)) {
-        set_error("mrep_project_surfaces: workspace smaller than mrep_surface_workspace_bytes");
+    if (ws_bytes < s_layout(ns, n, seeded, (char*)ws, &w)) {
+        set_error(f + (seeded ? ": workspace smaller than mrep_surface_seeded_workspace_bytes"
+                              : ": workspace smaller than mrep_surface_workspace_bytes"));
         return MREP_E_SMALL_BUFFER;
     }
     if (((uintptr_t)ws & 255) != 0) {
-        set_error("mrep_project_surfaces: workspace not 256-byte aligned");
+        set_error(f + ": workspace not 256-byte aligned");
         return MREP_E_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
     const bool timed = (opts->flags & MREP_OPT_TIME_STAGES) != 0;
     if (timed && (rc = stage_begin(st))) return rc;
+    int stage = 0;
     const DevSurf D = surf_view(geom->sg);
+    const float tie = (float)opts->tie_rel;
     // invalid surface ids are skipped by the grouping and written by k_sbad
     S_HIP(launch_grouping(ns, n, nullptr, sid, w.hist, w.q_off, w.tile_off, w.perm,
                           Outs{nullptr, nullptr, nullptr, nullptr}, st));
     const int64_t tiles = ns + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
-    hipLaunchKernelGGL(k_ssph, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, (const int32_t*)w.tile_off,
-                       (const int32_t*)w.q_off, (const int32_t*)w.perm, q, (float)opts->tie_rel, w.so);
-    S_HIP(hipGetLastError());
-    if (timed && (rc = stage_mark(1, st))) return rc;
+    if (seeded) {
+        hipLaunchKernelGGL(k_ssph<true>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D,
+                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q, tie, w.so,
+                           w.top);
+        S_HIP(hipGetLastError());
+        if (timed && (rc = stage_mark(++stage, st))) return rc;
+        if ((rc = nn_score_surface_pairs(nn, w.q_off, (int32_t)ns, w.top.cand, w.top.xb, w.score, n * kK, st)))
+            return rc;
+        if (timed && (rc = stage_mark(++stage, st))) return rc;
+        hipLaunchKernelGGL(k_sseed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, sid, q,
+                           (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.top.cand,
+                           (const float4*)w.score, w.fub, w.seed_patch);
+    } else {
+        hipLaunchKernelGGL(k_ssph<false>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D,
+                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q, tie, w.so,
+                           SphTop{nullptr, nullptr});
+        S_HIP(hipGetLastError());
+        if (timed && (rc = stage_mark(++stage, st))) return rc;
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.fub, n, 0x7f800000u);
+    }
     const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.fub, n, 0x7f800000u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)w.n_live, (int64_t)1, 0u);
-    hipLaunchKernelGGL(k_sbound, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, w.lb, w.fub);
+    hipLaunchKernelGGL(k_sbound, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, tie, w.lb,
+                       w.fub);
     hipLaunchKernelGGL(k_sgate, dim3(pb), dim3(256), 0, st, D, sid, (const int32_t*)w.perm, w.so, (const float*)w.lb,
-                       (const uint32_t*)w.fub, (float)opts->tie_rel, w.live, w.n_live, w.res);
+                       (const uint32_t*)w.fub, tie, w.live, w.n_live, w.res);
     hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so,
-                       (const int32_t*)w.live, (const int32_t*)w.n_live, w.res);
+                       (const int32_t*)w.live, (const int32_t*)w.n_live, (const uint32_t*)w.fub, tie, w.res);
     S_HIP(hipGetLastError());
-    if (timed && (rc = stage_mark(2, st))) return rc;
+    if (timed && (rc = stage_mark(++stage, st))) return rc;
     SOuts o{uv_out, dist_out, patch_out, flags_out};
     hipLaunchKernelGGL(k_sfinish, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, D, sid, q,
                        (const int32_t*)w.q_off, (const int32_t*)w.perm, w.so, (const float4*)w.res, opts->tie_rel,
-                       invert, w.ovf_list, w.ovf_count, o);
+                       invert, w.ovf_list, w.ovf_count, (const int32_t*)w.seed_patch, o);
     const unsigned fb = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);
     hipLaunchKernelGGL(k_sfull, dim3(fb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm,
-                       (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, opts->tie_rel, invert, o);
+                       (const int32_t*)w.ovf_list, (const int32_t*)w.ovf_count, opts->tie_rel, invert,
+                       seeded ? (uint32_t)MREP_F_NN_FALLBACK : 0u, o);
     S_HIP(hipGetLastError());
     if (timed) {
-        if ((rc = stage_mark(3, st))) return rc;
-        stage_end(3);
+        if ((rc = stage_mark(++stage, st))) return rc;
+        stage_end(stage);
     }
     return MREP_OK;
 }
@@ -1056,27 +1329,39 @@ __global__ void k_sbad(int64_t n, int32_t n_surf, const int32_t* __restrict__ si
 
 extern "C" {
 
-int32_t mrep_surface_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
+static int32_t surf_ws_bytes(const char* fn, const mrep_geom* geom, int64_t n, const mrep_opts* opts,
+                             bool seeded, int64_t* bytes)
 {
     if (!geom || !bytes || n < 0) {
-        set_error("mrep_surface_workspace_bytes: null pointer or negative n");
+        set_error(std::string(fn) + ": null pointer or negative n");
         return MREP_E_INVALID_ARG;
     }
     if (geom->kind != MREP_GEOM_SURFACES) {
-        set_error("mrep_surface_workspace_bytes: the geometry holds curves");
+        set_error(std::string(fn) + ": the geometry holds curves");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
     if (rc) return rc;
-    *bytes = s_layout(geom->sg.L.n_surf, n, nullptr, nullptr);
+    *bytes = s_layout(geom->sg.L.n_surf, n, seeded, nullptr, nullptr);
     return MREP_OK;
 }
 
-static int32_t surf_entry(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* sid, const double* q,
-                          void* ws, int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out,
-                          uint32_t* flags_out, void* stream, int invert)
+int32_t mrep_surface_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
 {
-    int rc = run_surf(geom, opts, n, sid, q, ws, ws_bytes, uv_out, dist_out, patch_out, flags_out, stream, invert);
+    return surf_ws_bytes("mrep_surface_workspace_bytes", geom, n, opts, false, bytes);
+}
+
+int32_t mrep_surface_seeded_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* opts, int64_t* bytes)
+{
+    return surf_ws_bytes("mrep_surface_seeded_workspace_bytes", geom, n, opts, true, bytes);
+}
+
+static int32_t surf_entry(const char* fn, const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                          const int32_t* sid, const double* q, void* ws, int64_t ws_bytes, double* uv_out,
+                          double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream, int invert)
+{
+    int rc = run_surf(fn, geom, nn, opts, n, sid, q, ws, ws_bytes, uv_out, dist_out, patch_out, flags_out, stream,
+                      invert);
     if (rc || n == 0) return rc;
     hipLaunchKernelGGL(k_sbad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n,
                        (int32_t)geom->sg.L.n_surf, sid, uv_out, dist_out, patch_out, flags_out);
@@ -1088,16 +1373,70 @@ int32_t mrep_project_surfaces(const mrep_geom* geom, const mrep_opts* opts, int6
                               const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out,
                               double* dist_out, int32_t* patch_out, uint32_t* flags_out, void* stream)
 {
-    return surf_entry(geom, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out, dist_out, patch_out, flags_out,
-                      stream, 0);
+    return surf_entry("mrep_project_surfaces", geom, nullptr, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out,
+                      dist_out, patch_out, flags_out, stream, 0);
 }
 
 int32_t mrep_invert_surfaces(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* surface_id,
                              const double* q_xyz, void* workspace, int64_t ws_bytes, double* uv_out, double* dist_out,
                              int32_t* patch_out, uint32_t* flags_out, void* stream)
 {
-    return surf_entry(geom, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out, dist_out, patch_out, flags_out,
-                      stream, 1);
+    return surf_entry("mrep_invert_surfaces", geom, nullptr, opts, n, surface_id, q_xyz, workspace, ws_bytes, uv_out,
+                      dist_out, patch_out, flags_out, stream, 1);
+}
+
+int32_t mrep_project_surfaces_seeded(const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                                     const int32_t* surface_id, const double* q_xyz, void* workspace,
+                                     int64_t ws_bytes, double* uv_out, double* dist_out, int32_t* patch_out,
+                                     uint32_t* flags_out, void* stream)
+{
+    if (nn_kind(nn) != MREP_NN_SURFACE) {
+        set_error("mrep_project_surfaces_seeded: the network is missing or not of kind MREP_NN_SURFACE");
+        return MREP_E_INVALID_ARG;
+    }
+    return surf_entry("mrep_project_surfaces_seeded", geom, nn, opts, n, surface_id, q_xyz, workspace, ws_bytes,
+                      uv_out, dist_out, patch_out, flags_out, stream, 0);
+}
+
+int32_t mrep_nn_surface_features(const mrep_geom* geom, int64_t n, const int32_t* surface_id, const double* q_xyz,
+                                 int32_t* patch_out, float* x_out, void* workspace, int64_t ws_bytes, void* stream)
+{
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_SURFACES) {
+        set_error("mrep_nn_surface_features: null or curve geometry, or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    if (!surface_id || !q_xyz || !patch_out || !x_out || !workspace) {
+        set_error("mrep_nn_surface_features: null pointer");
+        return MREP_E_INVALID_ARG;
+    }
+    const int64_t ns = geom->sg.L.n_surf;
+    if (n * kSurfPairsPerQuery >= (int64_t)INT32_MAX || ns == 0) {
+        set_error("mrep_nn_surface_features: n must be < 2^31 / 96 and the geometry non-empty");
+        return MREP_E_INVALID_ARG;
+    }
+    SWork w;
+    if (ws_bytes < s_layout(ns, n, true, (char*)workspace, &w)) {
+        set_error("mrep_nn_surface_features: workspace smaller than mrep_surface_seeded_workspace_bytes");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (((uintptr_t)workspace & 255) != 0) {
+        set_error("mrep_nn_surface_features: workspace not 256-byte aligned");
+        return MREP_E_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const DevSurf D = surf_view(geom->sg);
+    hipLaunchKernelGGL(k_sfeat_fill, dim3((unsigned)((n * kK + 255) / 256)), dim3(256), 0, st, n, patch_out, x_out);
+    S_HIP(launch_grouping(ns, n, nullptr, surface_id, w.hist, w.q_off, w.tile_off, w.perm,
+                          Outs{nullptr, nullptr, nullptr, nullptr}, st));
+    const int64_t tiles = ns + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
+    hipLaunchKernelGGL(k_ssph<true>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, (const int32_t*)w.tile_off,
+                       (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, 2e-6f, w.so,
+                       SphTop{w.top.cand, nullptr});
+    hipLaunchKernelGGL(k_sfeat_write, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, D, surface_id, q_xyz,
+                       (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.top.cand, patch_out, x_out);
+    S_HIP(hipGetLastError());
+    return MREP_OK;
 }
 
 int32_t mrep_eval_surfaces(const mrep_geom* geom, int64_t n, const int32_t* surface_id, const double* uv,

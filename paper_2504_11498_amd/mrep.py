@@ -30,7 +30,10 @@ PREC_FP64, PREC_BF16 = 0, 3
 OPT_TIME_STAGES = 1
 N_STAGES = 4
 MAX_DEGREE = 15
-NN_IN, NN_HIDDEN, NN_OUT, NN_K = 15, 128, 2, 4
+NN_CURVE, NN_SURFACE = 0, 1
+NN_HIDDEN, NN_K = 128, 4
+NN_DIMS = {NN_CURVE: (15, 2), NN_SURFACE: (51, 3)}  # kind -> (inputs, outputs)
+NN_IN, NN_OUT = NN_DIMS[NN_CURVE]
 
 _vp, _i32, _i64, _dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _pi32, _pi64, _pd = C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)
@@ -69,9 +72,9 @@ _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
 _subdiv = _sig("mrep_subdivision_matrix", _i32, _i32, _dbl, _pd)
 _gram = _sig("mrep_gram_matrix", _i32, _i32, _i32, _pd)
 _stage_times = _sig("mrep_last_stage_times", _i32, _pd, _i32)
-_nn_param_count = _sig("mrep_nn_param_count", _i32)
-_nn_bytes = _sig("mrep_nn_bytes", _i32, _i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64))
-_nn_bind = _sig("mrep_nn_bind", _i32, _vp, _i64, C.POINTER(_vp))
+_nn_param_count = _sig("mrep_nn_param_count", _i32, _i32)
+_nn_bytes = _sig("mrep_nn_bytes", _i32, _i32, _i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64))
+_nn_bind = _sig("mrep_nn_bind", _i32, _i32, _vp, _i64, C.POINTER(_vp))
 _nn_release = _sig("mrep_nn_release", None, _vp)
 _nn_init = _sig("mrep_nn_init", _i32, _vp, C.c_uint64, _vp)
 _nn_set = _sig("mrep_nn_set_params", _i32, _vp, C.POINTER(C.c_float), _i64, _vp)
@@ -93,6 +96,10 @@ _project_s = _sig("mrep_project_surfaces", _i32, _vp, C.POINTER(Opts), _i64, _vp
 _invert_s = _sig("mrep_invert_surfaces", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                  _vp)
 _eval_s = _sig("mrep_eval_surfaces", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
+_surf_seed_ws = _sig("mrep_surface_seeded_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POINTER(C.c_int64))
+_nn_surf_features = _sig("mrep_nn_surface_features", _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp)
+_project_s_seeded = _sig("mrep_project_surfaces_seeded", _i32, _vp, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64,
+                         _vp, _vp, _vp, _vp, _vp)
 _last_error = _sig("mrep_last_error", C.c_char_p)
 _abi = _sig("mrep_abi_version", _i32)
 
@@ -105,7 +112,8 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_nn_set_params", "mrep_nn_get_params", "mrep_nn_forward", "mrep_nn_infer", "mrep_nn_train_step",
            "mrep_seeded_workspace_bytes", "mrep_nn_features", "mrep_project_curves_seeded",
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
-           "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces"]
+           "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
+           "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded"]
 
 
 class MrepError(RuntimeError):
@@ -423,6 +431,61 @@ class Geometry:
                "mrep_invert_surfaces" if invert else "mrep_project_surfaces")
         return uv, d, s, f
 
+    def surface_seeded_workspace_bytes(self, n: int, opts: Opts) -> int:
+        b = C.c_int64()
+        _check(_surf_seed_ws(self._h, int(n), C.byref(opts), C.byref(b)), "mrep_surface_seeded_workspace_bytes")
+        return int(b.value)
+
+    def _surf_seed_workspace(self, n, opts, workspace):
+        import torch
+
+        if workspace is not None:
+            return workspace
+        need = self.surface_seeded_workspace_bytes(n, opts)
+        if getattr(self, "_sws3", None) is None or self._sws3.numel() < need:
+            self._sws3 = torch.empty(max(need, 256), dtype=torch.uint8, device=self.buf.device)
+        return self._sws3
+
+    def project_surfaces_seeded(self, q, surface_id, nn: "Network", opts: Opts | None = None, workspace=None,
+                                out=None):
+        """Seeded surface projection (nn of kind NN_SURFACE); same outputs as project_surfaces()."""
+        import torch
+
+        if opts is None:
+            opts = default_opts()
+        assert q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and q.dim() == 2 and q.shape[1] == 3
+        assert surface_id.is_cuda and surface_id.dtype == torch.int32 and surface_id.is_contiguous()
+        n = q.shape[0]
+        assert surface_id.shape[0] == n
+        ws = self._surf_seed_workspace(n, opts, workspace)
+        if out is None:
+            uv = torch.empty((n, 2), dtype=torch.float64, device=q.device)
+            d = torch.empty(n, dtype=torch.float64, device=q.device)
+            s = torch.empty(n, dtype=torch.int32, device=q.device)
+            f = torch.empty(n, dtype=torch.int32, device=q.device)
+        else:
+            uv, d, s, f = out
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_project_s_seeded(self._h, nn._h if nn is not None else None, C.byref(opts), int(n),
+                                 _vp(surface_id.data_ptr()), _vp(q.data_ptr()), _vp(ws.data_ptr()), int(ws.numel()),
+                                 _vp(uv.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
+                                 _vp(stream)), "mrep_project_surfaces_seeded")
+        return uv, d, s, f
+
+    def surface_features(self, q, surface_id, workspace=None):
+        """The surface network's candidate patches patch[n, 4] (surface-local, -1 none) and inputs x[n, 4, 51]."""
+        import torch
+
+        n = q.shape[0]
+        ws = self._surf_seed_workspace(n, default_opts(), workspace)
+        patch = torch.empty((n, NN_K), dtype=torch.int32, device=q.device)
+        x = torch.empty((n, NN_K, NN_DIMS[NN_SURFACE][0]), dtype=torch.float32, device=q.device)
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_nn_surf_features(self._h, int(n), _vp(surface_id.data_ptr()), _vp(q.data_ptr()),
+                                 _vp(patch.data_ptr()), _vp(x.data_ptr()), _vp(ws.data_ptr()), int(ws.numel()),
+                                 _vp(stream)), "mrep_nn_surface_features")
+        return patch, x
+
     def eval_surfaces(self, surface_id, uv):
         """S_{surface_id[i]}(u_i, v_i) on the exact surface, FP64, device tensors in and out."""
         import torch
@@ -458,22 +521,26 @@ class Geometry:
 
 
 # ---------------------------------------------------------------------------- learned seeding
-def nn_param_count() -> int:
-    return int(_nn_param_count())
+def nn_param_count(kind: int = NN_CURVE) -> int:
+    return int(_nn_param_count(int(kind)))
 
 
 class Network:
-    """The seeding MLP's device state (parameters, Adam moments, gradient, weight image) in a torch buffer."""
+    """The seeding MLP's device state (parameters, Adam moments, gradient, weight image) in a torch buffer.
 
-    def __init__(self, device=None, seed: int | None = 0):
+    kind: NN_CURVE (15 -> 128 -> 128 -> 2) or NN_SURFACE (51 -> 128 -> 128 -> 3)."""
+
+    def __init__(self, device=None, seed: int | None = 0, kind: int = NN_CURVE):
         import torch
 
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.kind = int(kind)
+        self.n_in, self.n_out = NN_DIMS[self.kind]
         sb = C.c_int64()
-        _check(_nn_bytes(0, C.byref(sb), None), "mrep_nn_bytes")
+        _check(_nn_bytes(self.kind, 0, C.byref(sb), None), "mrep_nn_bytes")
         self.state = torch.empty(int(sb.value), dtype=torch.uint8, device=self.device)
         h = _vp()
-        _check(_nn_bind(_vp(self.state.data_ptr()), self.state.numel(), C.byref(h)), "mrep_nn_bind")
+        _check(_nn_bind(self.kind, _vp(self.state.data_ptr()), self.state.numel(), C.byref(h)), "mrep_nn_bind")
         self._h = h
         self._work = None
         if seed is not None:
@@ -492,7 +559,7 @@ class Network:
         _check(_nn_set(self._h, _p(p, C.c_float), int(p.shape[0]), self._stream()), "mrep_nn_set_params")
 
     def get_params(self) -> np.ndarray:
-        p = np.zeros(nn_param_count(), np.float32)
+        p = np.zeros(nn_param_count(self.kind), np.float32)
         _check(_nn_get(self._h, _p(p, C.c_float), int(p.shape[0]), self._stream()), "mrep_nn_get_params")
         return p
 
@@ -500,39 +567,43 @@ class Network:
         import torch
 
         wb = C.c_int64()
-        _check(_nn_bytes(int(rows), None, C.byref(wb)), "mrep_nn_bytes")
+        _check(_nn_bytes(self.kind, int(rows), None, C.byref(wb)), "mrep_nn_bytes")
         if self._work is None or self._work.numel() < wb.value:
             self._work = torch.empty(max(int(wb.value), 256), dtype=torch.uint8, device=self.device)
         return self._work
 
     def forward(self, x):
-        """Training-form forward: y[n, 2] for x[n, 15] (float32, device)."""
+        """Training-form forward: y[n, out] for x[n, in] (float32, device)."""
         import torch
 
         n = x.shape[0]
-        y = torch.empty((n, NN_OUT), dtype=torch.float32, device=x.device)
+        assert x.shape[-1] == self.n_in
+        y = torch.empty((n, self.n_out), dtype=torch.float32, device=x.device)
         w = self._work_for(n)
         _check(_nn_forward(self._h, int(n), _vp(x.data_ptr()), _vp(y.data_ptr()), _vp(w.data_ptr()), int(w.numel()),
                            self._stream()), "mrep_nn_forward")
         return y
 
     def infer(self, x):
-        """Fused-kernel forward: y[n, 2] for x[n, 15] (float32, device)."""
+        """Fused-kernel forward: y[n, out] for x[n, in] (float32, device)."""
         import torch
 
         n = x.shape[0]
-        y = torch.empty((n, NN_OUT), dtype=torch.float32, device=x.device)
+        assert x.shape[-1] == self.n_in
+        y = torch.empty((n, self.n_out), dtype=torch.float32, device=x.device)
         _check(_nn_infer(self._h, int(n), _vp(x.data_ptr()), _vp(y.data_ptr()), self._stream()), "mrep_nn_infer")
         return y
 
-    def train_step(self, x, u_star, accept, rows=None, batch=None, lr: float = 1e-3, loss=None, grad=None):
+    def train_step(self, x, target, accept, rows=None, batch=None, lr: float = 1e-3, loss=None, grad=None):
         """One step on the rows `rows` (int32 device, or the first `batch` rows); returns nothing (async).
 
-        loss: optional 1-element float32 device tensor receiving the batch loss; grad: optional device tensor of
-        nn_param_count() floats receiving the gradient."""
+        x[n, in], target[n, out - 1] (or [n] for curves), accept[n]: float32 device tensors.  loss: optional
+        1-element float32 device tensor receiving the batch loss; grad: optional device tensor of
+        nn_param_count(kind) floats receiving the gradient."""
         b = int(rows.shape[0]) if rows is not None else int(batch if batch is not None else x.shape[0])
         w = self._work_for(b)
-        _check(_nn_train(self._h, int(x.shape[0]), _vp(x.data_ptr()), _vp(u_star.data_ptr()), _vp(accept.data_ptr()),
+        assert x.shape[-1] == self.n_in and target.numel() == x.shape[0] * (self.n_out - 1)
+        _check(_nn_train(self._h, int(x.shape[0]), _vp(x.data_ptr()), _vp(target.data_ptr()), _vp(accept.data_ptr()),
                          b, _vp(rows.data_ptr()) if rows is not None else None, float(lr),
                          _vp(loss.data_ptr()) if loss is not None else None,
                          _vp(grad.data_ptr()) if grad is not None else None, _vp(w.data_ptr()), int(w.numel()),

@@ -6,13 +6,11 @@ import pytest
 
 import oracle
 from paper_2504_11498_amd import gen
+from parity import T_ABS as UV_ABS, compare_surf, surf_diag as _diag
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-DIST_REL, UV_ABS, UNIQUE_REL, KAPPA_MIN = 1e-6, 1e-7, 2e-6, 1e-3
-
 
 def _say(msg):
     print(msg, flush=True)
@@ -28,11 +26,6 @@ def mrep():
     return m
 
 
-def _diag(S):
-    return np.array([np.linalg.norm(S.cp[S.cp_off[k]:S.cp_off[k + 1]].max(0) - S.cp[S.cp_off[k]:S.cp_off[k + 1]].min(0))
-                     for k in range(S.n)])
-
-
 def _run(geom, q, sid, invert=False):
     m = sys.modules["paper_2504_11498_amd.mrep"]
     qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
@@ -41,45 +34,6 @@ def _run(geom, q, sid, invert=False):
     torch.cuda.synchronize()
     return {"uv": uv.cpu().numpy(), "dist": d.cpu().numpy(), "patch": p.cpu().numpy(),
             "flags": f.cpu().numpy().view(np.uint32)}
-
-
-def compare_surf(S, sid, q, out, ref, ex=None, label=""):
-    """Parity bar: distance within 1e-6 * diag and never below the oracle; (u, v) within 1e-7 where the
-    oracle's minimum is unique and well conditioned; the patch index equals the exported patch holding the
-    oracle's (u, v) where unique and not within 1e-7 of a patch side."""
-    diag = _diag(S)[sid]
-    err = np.abs(out["dist"] - ref["dist"]) / diag
-    below = (ref["dist"] - out["dist"]) / diag
-    unique = (ref["runner"] - ref["dist"]) > UNIQUE_REL * diag
-    wc = unique & (ref["kappa"] >= KAPPA_MIN)
-    duv = np.abs(out["uv"] - ref["uv"]).max(1)
-    st = {"n": int(len(sid)), "max_dist_rel": float(err.max()), "max_uv_err_wc": float(duv[wc].max()) if wc.any() else 0.0,
-          "wc_frac": float(wc.mean())}
-    bad = np.nonzero(err > DIST_REL)[0]
-    assert bad.size == 0, f"{label}: {bad.size} distances off, worst {err.max():.3e} at {bad[:5]}"
-    assert below.max() <= 1e-12, f"{label}: below the oracle by {below.max():.3e}"
-    bad = np.nonzero(wc & (duv > UV_ABS))[0]
-    if bad.size:
-        for i in bad[:6]:
-            print(f"  q{i} gpu uv={out['uv'][i]} d={out['dist'][i]:.15g} f={out['flags'][i]:#x} | oracle uv={ref['uv'][i]} "
-                  f"d={ref['dist'][i]:.15g} kappa={ref['kappa'][i]:.3g} runner={ref['runner'][i]:.6g}", flush=True)
-    assert bad.size == 0, f"{label}: {bad.size} (u,v) off, worst {duv[wc].max():.3e} at {bad[:5]}"
-    if ex is not None:
-        checked = 0
-        for i in np.nonzero(unique)[0]:
-            o0, o1 = ex["patch_off"][sid[i]], ex["patch_off"][sid[i] + 1]
-            r = ex["patch_uv"][o0:o1]
-            u, v = ref["uv"][i]
-            inside = (r[:, 0] <= u) & (u <= r[:, 1]) & (r[:, 2] <= v) & (v <= r[:, 3])
-            near = np.min(np.abs(np.concatenate([r[inside, 0] - u, r[inside, 1] - u, r[inside, 2] - v,
-                                                 r[inside, 3] - v]))) if inside.any() else 0.0
-            if near <= 1e-7:
-                continue
-            k = int(np.nonzero(inside)[0][0])
-            assert out["patch"][i] == k, f"{label}: query {i} patch {out['patch'][i]} != {k}"
-            checked += 1
-        st["patch_checked"] = checked
-    return st
 
 
 @pytest.fixture(scope="module")

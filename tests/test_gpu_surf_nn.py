@@ -1,0 +1,241 @@
+"""GPU tests of the surface seeding network (51 -> 128 -> 128 -> 3: forward, backward, training) and of the
+seeded surface projection, against the FP64 oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_11498_amd import gen
+from parity import compare_surf, surf_diag
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NIN, NH, NOUT = 51, 128, 3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mrep():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_11498_amd import mrep as m
+
+    return m
+
+
+def _params(seed):
+    """Seeded parameters (numpy): weights uniform in +-1/sqrt(fan_in), biases uniform in +-0.1."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in [(NH, NIN), (NH, NH), (NOUT, NH)]:
+        a = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-a, a, fan_out * fan_in))
+        parts.append(rng.uniform(-0.1, 0.1, fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _blocks(v):
+    offs = np.cumsum([0, NH * NIN, NH, NH * NH, NH, NOUT * NH, NOUT])
+    return [v[offs[i]:offs[i + 1]] for i in range(6)]
+
+
+def test_surface_network_forward_matches_oracle(mrep):
+    _say("[case] surface network forward: training kernels and fused kernel vs oracle, 1000 rows")
+    p = _params(11)
+    rng = np.random.default_rng(12)
+    x = (rng.normal(size=(1000, NIN)) * 0.7).astype(np.float32)
+    net = mrep.Network(seed=None, kind=mrep.NN_SURFACE)
+    assert mrep.nn_param_count(mrep.NN_SURFACE) == p.shape[0] == 23555
+    net.set_params(p)
+    xt = torch.from_numpy(x).cuda()
+    y_f = net.forward(xt).cpu().numpy()
+    y_i = net.infer(xt).cpu().numpy()
+    _, y_ref, _ = oracle.mlp_loss(p.astype(np.float64), x.astype(np.float64), n_in=NIN, n_out=NOUT)
+    for k in range(NOUT):
+        assert _rel(y_f[:, k], y_ref[:, k]) <= 2e-2, ("forward", k, _rel(y_f[:, k], y_ref[:, k]))
+        assert _rel(y_i[:, k], y_ref[:, k]) <= 2e-2, ("infer", k, _rel(y_i[:, k], y_ref[:, k]))
+    assert _rel(y_i, y_f) <= 2e-3
+    assert net.infer(xt[:0]).shape == (0, 3)
+    one = net.infer(xt[999:1000].contiguous()).cpu().numpy()
+    np.testing.assert_allclose(one[0], y_i[999], rtol=0, atol=1e-6)
+
+
+def test_surface_network_gradient_matches_oracle(mrep):
+    _say("[case] surface network loss and gradient vs oracle, 901 rows")
+    p = _params(13)
+    rng = np.random.default_rng(14)
+    B = 901
+    x = rng.normal(size=(B, NIN)).astype(np.float32)
+    st = rng.uniform(0, 1, (B, 2)).astype(np.float32)
+    ac = (rng.uniform(size=B) < 0.5).astype(np.float32)
+    net = mrep.Network(seed=None, kind=mrep.NN_SURFACE)
+    net.set_params(p)
+    loss = torch.zeros(1, device="cuda")
+    grad = torch.zeros(mrep.nn_param_count(mrep.NN_SURFACE), device="cuda")
+    xt, tt, at = (torch.from_numpy(v).cuda() for v in (x, st, ac))
+    net.train_step(xt, tt, at, lr=0.0, loss=loss, grad=grad)
+    torch.cuda.synchronize()
+    l_ref, _, g_ref = oracle.mlp_loss(p.astype(np.float64), x.astype(np.float64), st.astype(np.float64),
+                                      ac.astype(np.float64), n_in=NIN, n_out=NOUT, grad=True)
+    assert abs(float(loss.item()) - l_ref) <= 1e-2 * abs(l_ref)
+    g = grad.cpu().numpy()
+    for i, (a, b) in enumerate(zip(_blocks(g), _blocks(g_ref))):
+        assert _rel(a, b) <= 3e-2, (i, _rel(a, b))
+    np.testing.assert_array_equal(net.get_params(), p)
+    # a curve-kind network refuses surface-sized parameters
+    with pytest.raises(mrep.MrepError):
+        mrep.Network(seed=None).set_params(p)
+
+
+# --------------------------------------------------------------------------- seeded surface projection
+@pytest.fixture(scope="module")
+def strained(mrep):
+    """A surface network trained on held-out surfaces (other seeds than the evaluation set)."""
+    from paper_2504_11498_amd import seeding
+
+    _say("[setup] surface training set: 32 held-out surfaces x 1500 queries")
+    S, Q = gen.surfaces(31, n_surf=32, per_surface=1500)
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    geom = plan.upload()
+    sid = torch.from_numpy(Q["surface_id"]).cuda()
+    q = (geom.eval_surfaces(sid, torch.from_numpy(Q["uv0"]).cuda()) + torch.from_numpy(Q["offset"]).cuda()).contiguous()
+    x, t, a, stats = seeding.surface_training_pairs(plan, geom, q, sid, seed=0)
+    _say(f"[setup] {stats}")
+    net = mrep.Network(seed=7, kind=mrep.NN_SURFACE)
+    losses = seeding.train(net, x, t, a, epochs=16, batch=1024, lr=1e-3, seed=0)
+    _say(f"[setup] loss first {losses[:20].mean():.4f} last {losses[-20:].mean():.4f} ({len(losses)} steps)")
+    return net, losses, stats
+
+
+def test_surface_training_reduces_loss(strained):
+    net, losses, stats = strained
+    assert stats["label_in_candidates"] > 0.5
+    assert losses[-20:].mean() < 0.7 * losses[:20].mean()
+
+
+@pytest.fixture(scope="module")
+def sevalset(mrep):
+    S, Q = gen.surfaces(3, n_surf=8, per_surface=600)
+    sid = Q["surface_id"]
+    q = oracle.surf_eval(S, sid, Q["uv0"]) + Q["offset"]
+    _say("[setup] surface evaluation set: 8 surfaces x 600 queries, oracle projection")
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    geom = plan.upload()
+    ref = oracle.surf_project(S, sid, q)
+    return S, Q, sid, q, plan, geom, ref
+
+
+def _seeded(geom, q, sid, net):
+    qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(sid, dtype=np.int32)).cuda()
+    uv, d, p, f = geom.project_surfaces_seeded(qt, st, net)
+    torch.cuda.synchronize()
+    return {"uv": uv.cpu().numpy(), "dist": d.cpu().numpy(), "patch": p.cpu().numpy(),
+            "flags": f.cpu().numpy().view(np.uint32)}
+
+
+@pytest.mark.parametrize("which", ["trained", "untrained"])
+def test_surface_seeded_projection_parity(mrep, strained, sevalset, which):
+    S, Q, sid, q, plan, geom, ref = sevalset
+    net = strained[0] if which == "trained" else mrep.Network(seed=99, kind=mrep.NN_SURFACE)
+    _say(f"[case] seeded surface projection ({which}), {sid.shape[0]} queries")
+    out = _seeded(geom, q, sid, net)
+    st = compare_surf(S, sid, q, out, ref, plan.export_surfaces(), label=f"surf-seeded/{which}")
+    fb = float(np.mean((out["flags"] & mrep.F_NN_FALLBACK) != 0))
+    _say(f"[ok] {st} fallback={fb:.4f}")
+    if which == "trained":
+        # the network's patch holds the minimum for most queries
+        assert fb < 0.5
+
+
+def test_surface_features(mrep, sevalset):
+    """Candidates are valid, distinct surface-local patches; the inputs equal the normalised control points and
+    query computed in FP64 from the exported patches."""
+    S, Q, sid, q, plan, geom, ref = sevalset
+    qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(sid, dtype=np.int32)).cuda()
+    patch, x = geom.surface_features(qt, st)
+    torch.cuda.synchronize()
+    patch, x = patch.cpu().numpy(), x.cpu().numpy()
+    ex = plan.export_surfaces()
+    n_patch = np.diff(ex["patch_off"])[sid]
+    assert np.all(((patch >= 0) & (patch < n_patch[:, None])) | (patch == -1))
+    assert np.all(patch[:, 0] >= 0)
+    srt = np.sort(patch, axis=1)
+    assert not np.any((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] >= 0))
+    g = ex["patch_off"][sid][:, None] + np.maximum(patch, 0)
+    P = ex["patch_cp"][g].reshape(len(sid), 4, 16, 3)
+    m = P.mean(axis=2, keepdims=True)
+    ext = np.linalg.norm(P.max(axis=2) - P.min(axis=2), axis=-1)[..., None, None]
+    want = np.concatenate([((P - m) / ext).reshape(len(sid), 4, 48),
+                           ((q[:, None, None, :] - m) / ext).reshape(len(sid), 4, 3)], axis=-1)
+    ok = patch >= 0
+    err = np.abs(x[ok] - want[ok]) / np.maximum(1.0, np.abs(want[ok]))
+    assert err.max() <= 1e-4, err.max()
+    # the first candidate has the smallest sphere lower bound: it is usually the label patch
+    uv = ref["uv"]
+    r = ex["patch_uv"][ex["patch_off"][sid][:, None] + np.maximum(patch, 0)]
+    inside = ok & (r[..., 0] <= uv[:, :1]) & (uv[:, :1] <= r[..., 1]) & (r[..., 2] <= uv[:, 1:]) & (uv[:, 1:] <= r[..., 3])
+    assert inside.any(axis=1).mean() > 0.5
+
+
+def test_surface_seeded_edge_cases(mrep, strained, sevalset):
+    _say("[case] seeded surface edge cases: empty, single query, bad ids, wrong network kind")
+    S, Q, sid, q, plan, geom, ref = sevalset
+    net = strained[0]
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    geom.project_surfaces_seeded(e, torch.empty(0, dtype=torch.int32, device="cuda"), net)
+    out = _seeded(geom, q, sid, net)
+    one = _seeded(geom, q[5:6], sid[5:6], net)
+    assert one["dist"][0] == out["dist"][5] and np.array_equal(one["uv"][0], out["uv"][5])
+    bad = sid.copy()
+    bad[::7] = S.n + 3
+    bad[3] = -1
+    outb = _seeded(geom, q, bad, net)
+    isbad = (bad < 0) | (bad >= S.n)
+    assert np.all((outb["flags"][isbad] & mrep.F_BAD_ID) != 0) and np.all(np.isnan(outb["dist"][isbad]))
+    good = ~isbad
+    diag = surf_diag(S)[sid[good]]
+    assert np.max(np.abs(outb["dist"][good] - out["dist"][good]) / diag) <= 1e-9
+    qt = torch.from_numpy(np.ascontiguousarray(q[:10])).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(sid[:10], dtype=np.int32)).cuda()
+    with pytest.raises(mrep.MrepError):
+        geom.project_surfaces_seeded(qt, st, mrep.Network(seed=1))
+    with pytest.raises(mrep.MrepError):
+        geom.project_surfaces_seeded(qt, st, None)
+
+
+def test_batched_surfaces_seeded_full_size_sampled(mrep, strained):
+    """All 256 surfaces and 4,194,304 queries, seeded, in the launch configuration the benchmark times; 800
+    sampled outputs checked against the oracle."""
+    S, Q = gen.surfaces(3)
+    _say("[setup] batched surfaces (seeded): decomposing 256 surfaces on the host")
+    plan = mrep.decompose_surfaces(S, 1e-6)
+    geom = plan.upload()
+    sid = Q["surface_id"]
+    st = torch.from_numpy(sid).cuda()
+    q = (geom.eval_surfaces(st, torch.from_numpy(Q["uv0"]).cuda()) + torch.from_numpy(Q["offset"]).cuda()).contiguous()
+    _say("[case] batched surfaces seeded, 4,194,304 queries")
+    uv, d, p, f = geom.project_surfaces_seeded(q, st, strained[0], mrep.default_opts())
+    torch.cuda.synchronize()
+    out = {"uv": uv.cpu().numpy(), "dist": d.cpu().numpy(), "patch": p.cpu().numpy(), "flags": f.cpu().numpy().view(np.uint32)}
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["patch"] >= 0)
+    _say(f"[info] fallback fraction {np.mean((out['flags'] & mrep.F_NN_FALLBACK) != 0):.4f}")
+    rng = np.random.default_rng(22)
+    pick = np.sort(rng.choice(len(sid), 800, replace=False))
+    qn = q.cpu().numpy()[pick]
+    ref = oracle.surf_project(S, sid[pick], qn)
+    st_ = compare_surf(S, sid[pick], qn, {k: v[pick] for k, v in out.items()}, ref, plan.export_surfaces(),
+                       label="c3-seeded")
+    _say(f"[ok] {st_}")

@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 3
+    assert mrep.abi_version() == 4
 
 
 def test_rebasement_matrix_matches_printed_T5():
@@ -174,23 +174,32 @@ def test_piece_cap_is_reported():
 
 
 def test_seeding_network_sizes_and_host_errors():
-    """Parameter count equals the oracle network's; sizes and argument errors need no device."""
-    assert mrep.nn_param_count() == oracle.mlp_param_count() == 18818
-    sb, wb = C.c_int64(), C.c_int64()
-    assert mrep._nn_bytes(4096, C.byref(sb), C.byref(wb)) == mrep.OK
-    assert sb.value >= 4 * 4 * 18818 and sb.value % 256 == 0
-    assert wb.value >= 4096 * (4 * 128 + 15) * 4
-    assert mrep._nn_bytes(-1, C.byref(sb), None) == mrep.E_INVALID_ARG
-    assert mrep._nn_bytes(1, None, None) == mrep.E_INVALID_ARG
-    h = mrep._vp()
-    assert mrep._nn_bind(None, sb.value, C.byref(h)) == mrep.E_INVALID_ARG
-    assert mrep._nn_bind(mrep._vp(256), 16, C.byref(h)) == mrep.E_SMALL_BUFFER
-    assert mrep._nn_bind(mrep._vp(257), sb.value, C.byref(h)) == mrep.E_INVALID_ARG
+    """Parameter counts equal the oracle networks'; sizes and argument errors need no device."""
+    assert mrep.nn_param_count() == mrep.nn_param_count(mrep.NN_CURVE) == oracle.mlp_param_count() == 18818
+    assert mrep.nn_param_count(mrep.NN_SURFACE) == oracle.mlp_param_count(51, 128, 3) == 23555
+    assert mrep._nn_param_count(7) == -1
+    for kind, n_in, n_out in ((mrep.NN_CURVE, 15, 2), (mrep.NN_SURFACE, 51, 3)):
+        sb, wb = C.c_int64(), C.c_int64()
+        assert mrep._nn_bytes(kind, 4096, C.byref(sb), C.byref(wb)) == mrep.OK
+        assert sb.value >= 4 * 4 * mrep.nn_param_count(kind) and sb.value % 256 == 0
+        assert wb.value >= 4096 * (4 * 128 + n_in + 2 * n_out) * 4
+        assert mrep._nn_bytes(kind, -1, C.byref(sb), None) == mrep.E_INVALID_ARG
+        assert mrep._nn_bytes(kind, 1, None, None) == mrep.E_INVALID_ARG
+        h = mrep._vp()
+        assert mrep._nn_bind(kind, None, sb.value, C.byref(h)) == mrep.E_INVALID_ARG
+        assert mrep._nn_bind(kind, mrep._vp(256), 16, C.byref(h)) == mrep.E_SMALL_BUFFER
+        assert mrep._nn_bind(kind, mrep._vp(257), sb.value, C.byref(h)) == mrep.E_INVALID_ARG
+    sb = C.c_int64()
+    assert mrep._nn_bytes(2, 1, C.byref(sb), None) == mrep.E_INVALID_ARG
+    assert mrep._nn_bind(2, mrep._vp(256), 1 << 20, C.byref(mrep._vp())) == mrep.E_INVALID_ARG
     assert mrep._nn_train(None, 10, None, None, None, 10, None, 1e-3, None, None, None, 0, None) == mrep.E_INVALID_ARG
     assert mrep._nn_forward(None, 10, None, None, None, 0, None) == mrep.E_INVALID_ARG
     assert mrep._nn_infer(None, 10, None, None, None) == mrep.E_INVALID_ARG
     assert mrep._project_seeded(None, None, None, 10, None, None, None, 0, None, None, None, None,
                                 None) == mrep.E_INVALID_ARG
+    assert mrep._project_s_seeded(None, None, None, 10, None, None, None, 0, None, None, None, None,
+                                  None) == mrep.E_INVALID_ARG
+    assert mrep._nn_surf_features(None, 10, None, None, None, None, None, 0, None) == mrep.E_INVALID_ARG
 
 
 # --------------------------------------------------------------------------- surfaces
