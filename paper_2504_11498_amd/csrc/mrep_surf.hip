@@ -558,45 +558,66 @@ __device__ __forceinline__ void bc_edge(const Bicubic& B, int which, Cubic<float
 // cell whose bound reaches the best value so far is skipped.
 __device__ PatchMin patch_min(const Bicubic& B, float cap)
 {
-    PatchMin best{0.f, 0.f, cap, 1.f};
-    const float h = 1.f / (kGrid - 1);
-    float F[kGrid][kGrid];
-#pragma unroll
-    for (int i = 0; i < kGrid; ++i)
-#pragma unroll
-        for (int j = 0; j < kGrid; ++j) F[i][j] = bc_f(B, i * h, j * h);
+    constexpr int kC = kGrid - 1;  // cells per direction
+    static_assert(kC * kC <= 64 && (kGrid - 2) * (kGrid - 2) <= 32, "cell and sample masks fit their words");
+    const float h = 1.f / kC;
     const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
     const float gap = (Mss + Mtt) * h * h * 0.125f;
-    // Newton from the interior local minima of the samples below the best; the
-    // four cells around such a sample count as covered
-    uint64_t covered = 0;  // bit i*(kGrid-1)+j: cell (i, j)
-    for (int i = 1; i < kGrid - 1; ++i)
-        for (int j = 1; j < kGrid - 1; ++j) {
-            const float v = F[i][j];
-            bool m = v < best.f;
+    // Phase 1, on the samples (all loops unrolled, so they stay in registers
+    // and are dead afterwards): interior local minima below the cap, each
+    // edge's smallest sample, and the cells whose bound is below the cap.
+    uint32_t lmin = 0;   // bit (i-1)*(kGrid-2)+(j-1)
+    uint64_t cells = 0;  // bit i*kC+j: cell (i, j)
+    float emn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    {
+        float F[kGrid][kGrid];
 #pragma unroll
-            for (int a = -1; a <= 1; ++a)
+        for (int i = 0; i < kGrid; ++i)
 #pragma unroll
-                for (int b = -1; b <= 1; ++b)
-                    if ((a || b) && F[i + a][j + b] < v) m = false;
-            if (!m) continue;
-            bc_newton(B, i * h, j * h, 0.f, 1.f, 0.f, 1.f, best);
-            covered |= 1ull << ((i - 1) * (kGrid - 1) + (j - 1));
-            covered |= 1ull << ((i - 1) * (kGrid - 1) + j);
-            covered |= 1ull << (i * (kGrid - 1) + (j - 1));
-            covered |= 1ull << (i * (kGrid - 1) + j);
-        }
-    // edges: certified 1D minima of the boundary curves whose sampled bound
-    // (second-order along the edge) reaches below the best
-    for (int w = 0; w < 4; ++w) {
-        float mn = INFINITY;
+            for (int j = 0; j < kGrid; ++j) F[i][j] = bc_f(B, i * h, j * h);
+#pragma unroll
+        for (int i = 1; i < kGrid - 1; ++i)
+#pragma unroll
+            for (int j = 1; j < kGrid - 1; ++j) {
+                const float v = F[i][j];
+                bool m = v < cap;
+#pragma unroll
+                for (int a = -1; a <= 1; ++a)
+#pragma unroll
+                    for (int b = -1; b <= 1; ++b)
+                        if (a || b) m = m && !(F[i + a][j + b] < v);
+                lmin |= (uint32_t)m << ((i - 1) * (kGrid - 2) + (j - 1));
+            }
 #pragma unroll
         for (int k = 0; k < kGrid; ++k) {
-            const float v = w == 0 ? F[0][k] : (w == 1 ? F[kGrid - 1][k] : (w == 2 ? F[k][0] : F[k][kGrid - 1]));
-            mn = fminf(mn, v);
+            emn[0] = fminf(emn[0], F[0][k]);
+            emn[1] = fminf(emn[1], F[kGrid - 1][k]);
+            emn[2] = fminf(emn[2], F[k][0]);
+            emn[3] = fminf(emn[3], F[k][kGrid - 1]);
         }
-        const float g1 = (w < 2 ? Mtt : Mss) * h * h * 0.125f;
-        if (!(mn - g1 < best.f * (1.f + 8e-6f))) continue;
+#pragma unroll
+        for (int i = 0; i < kC; ++i)
+#pragma unroll
+            for (int j = 0; j < kC; ++j) {
+                const float mn = fminf(fminf(F[i][j], F[i + 1][j]), fminf(F[i][j + 1], F[i + 1][j + 1]));
+                cells |= (uint64_t)(mn - gap < cap) << (i * kC + j);
+            }
+    }
+    PatchMin best{0.f, 0.f, cap, 1.f};
+    // Phase 2: Newton from each local minimum; the four cells around such a
+    // sample count as covered
+    uint64_t covered = 0;
+    for (uint32_t m = lmin; m; m &= m - 1) {
+        const int k = __ffs(m) - 1;
+        const int i = k / (kGrid - 2) + 1, j = k % (kGrid - 2) + 1;
+        bc_newton(B, i * h, j * h, 0.f, 1.f, 0.f, 1.f, best);
+        covered |= (3ull << ((i - 1) * kC + (j - 1))) | (3ull << (i * kC + (j - 1)));
+    }
+    // Phase 3: certified 1D minima of the boundary curves whose sampled bound
+    // (second-order along the edge) reaches below the best
+    for (int w = 0; w < 4; ++w) {
+        const float e = w == 0 ? emn[0] : (w == 1 ? emn[1] : (w == 2 ? emn[2] : emn[3]));
+        if (!(e - (w < 2 ? Mtt : Mss) * h * h * 0.125f < best.f * (1.f + 8e-6f))) continue;
         Cubic<float> E;
         bc_edge(B, w, E);
         float u, d, k;
@@ -605,14 +626,17 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
         const float t = w == 2 ? 0.f : (w == 3 ? 1.f : u);
         pm_take(best, s, t, d, 1.f);
     }
-    // second-order bound of each cell: f >= min(corners) - (M_ss + M_tt) h^2 / 8
-    for (int i = 0; i < kGrid - 1; ++i)
-        for (int j = 0; j < kGrid - 1; ++j) {
-            if ((covered >> (i * (kGrid - 1) + j)) & 1ull) continue;
-            const float mn = fminf(fminf(F[i][j], F[i + 1][j]), fminf(F[i][j + 1], F[i + 1][j + 1]));
-            if (mn - gap < best.f * (1.f - 8e-6f))
-                bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
-        }
+    // Phase 4: a Newton solve in every uncovered cell whose second-order bound
+    // min(corner f) - (M_ss + M_tt) h^2 / 8 is still below the best (corners
+    // evaluated again)
+    for (uint64_t m = cells & ~covered; m; m &= m - 1) {
+        const int c = __ffsll((unsigned long long)m) - 1;
+        const int i = c / kC, j = c % kC;
+        const float mn = fminf(fminf(bc_f(B, i * h, j * h), bc_f(B, (i + 1) * h, j * h)),
+                               fminf(bc_f(B, i * h, (j + 1) * h), bc_f(B, (i + 1) * h, (j + 1) * h)));
+        if (mn - gap < best.f * (1.f - 8e-6f))
+            bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
+    }
     if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f};
     return best;
 }
@@ -774,27 +798,28 @@ struct SCand {
     int64_t patch;
 };
 
+// lexicographic (d2, u, v); bitwise operators keep it free of branches
 __device__ __forceinline__ bool s_better(const SCand& a, const SCand& b)
 {
-    return a.d2 < b.d2 || (a.d2 == b.d2 && (a.u < b.u || (a.u == b.u && a.v < b.v)));
+    return (a.d2 < b.d2) | ((a.d2 == b.d2) & ((a.u < b.u) | ((a.u == b.u) & (a.v < b.v))));
 }
 
-__device__ __forceinline__ void s_sel(bool c, const SCand& a, SCand& d)
-{
-    d.u = c ? a.u : d.u;
-    d.v = c ? a.v : d.v;
-    d.d2 = c ? a.d2 : d.d2;
-    d.kappa = c ? a.kappa : d.kappa;
-    d.patch = c ? a.patch : d.patch;
-}
-
+// (b1, b2) <- the two best of (b1, b2, x), field by field so that the
+// candidates stay in registers
 __device__ __forceinline__ void s_top2(const SCand& x, SCand& b1, SCand& b2)
 {
     const bool first = s_better(x, b1);
     const bool second = !first && s_better(x, b2);
-    s_sel(first, b1, b2);
-    s_sel(second, x, b2);
-    s_sel(first, x, b1);
+    b2.u = first ? b1.u : (second ? x.u : b2.u);
+    b2.v = first ? b1.v : (second ? x.v : b2.v);
+    b2.d2 = first ? b1.d2 : (second ? x.d2 : b2.d2);
+    b2.kappa = first ? b1.kappa : (second ? x.kappa : b2.kappa);
+    b2.patch = first ? b1.patch : (second ? x.patch : b2.patch);
+    b1.u = first ? x.u : b1.u;
+    b1.v = first ? x.v : b1.v;
+    b1.d2 = first ? x.d2 : b1.d2;
+    b1.kappa = first ? x.kappa : b1.kappa;
+    b1.patch = first ? x.patch : b1.patch;
 }
 
 __device__ __forceinline__ SCand s_empty()
@@ -824,14 +849,25 @@ struct ExactEval {
     double f, gs, gt, h11, h12, h22, g11, g12, g22;
 };
 
-__device__ ExactEval exact_eval(const double* cf, int p, int q, const double* x, double s, double t)
+// P, Q > 0: degrees fixed at compile time (loops unrolled, coefficient loads
+// issued together); P = Q = 0: the degrees p, q given at run time.
+template <int P, int Q>
+__device__ __forceinline__ ExactEval exact_eval_deg(const double* cf, int p, int q, const double* x, double s,
+                                                    double t)
 {
+    if (P > 0) {
+        p = P;
+        q = Q;
+    }
     double r[3], Ss[3], St[3], Sss[3], Sst[3], Stt[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         // Horner in s of D_a(t), D_a'(t), D_a''(t)
         double v = 0, vs = 0, vss = 0, vt = 0, vst = 0, vtt = 0;
+#pragma unroll 1
         for (int a = p; a >= 0; --a) {
             double d = 0, d1 = 0, d2 = 0;
+#pragma unroll
             for (int b = q; b >= 0; --b) {
                 const double cc = cf[3 * (a * (q + 1) + b) + c];
                 d2 = d2 * t + 2.0 * d1;
@@ -863,6 +899,14 @@ __device__ ExactEval exact_eval(const double* cf, int p, int q, const double* x,
     e.h12 = e.g12 + r[0] * Sst[0] + r[1] * Sst[1] + r[2] * Sst[2];
     e.h22 = e.g22 + r[0] * Stt[0] + r[1] * Stt[1] + r[2] * Stt[2];
     return e;
+}
+
+// the degrees of the benchmark surfaces (3 x 3 and 5 x 5) get unrolled code
+__device__ __forceinline__ ExactEval exact_eval(const double* cf, int p, int q, const double* x, double s, double t)
+{
+    if (p == 3 && q == 3) return exact_eval_deg<3, 3>(cf, p, q, x, s, t);
+    if (p == 5 && q == 5) return exact_eval_deg<5, 5>(cf, p, q, x, s, t);
+    return exact_eval_deg<0, 0>(cf, p, q, x, s, t);
 }
 
 // span index of parameter w among n spans with breakpoints b[0..n]
@@ -927,19 +971,20 @@ __device__ Polished s_polish(const DevSurf& D, const DSurf& sf, double u, double
             if (m > 0.25) { ds *= 0.25 / m; dt *= 0.25 / m; }
             double sn = fmin(fmax(s + ds, 0.0), 1.0), tn = fmin(fmax(t + dt, 0.0), 1.0);
             ExactEval en = exact_eval(cf, p, q, x, sn, tn);
-            for (int bt = 0; bt < 30 && en.f > e.f; ++bt) {
+            for (int bt = 0; bt < 12 && en.f > e.f; ++bt) {
                 ds *= 0.5;
                 dt *= 0.5;
                 sn = fmin(fmax(s + ds, 0.0), 1.0);
                 tn = fmin(fmax(t + dt, 0.0), 1.0);
                 en = exact_eval(cf, p, q, x, sn, tn);
             }
-            if (en.f > e.f) break;
+            if (en.f > e.f) break;  // no decrease above rounding: converged
             const double step = fabs(sn - s) + fabs(tn - t);
             s = sn;
             t = tn;
             e = en;
-            if (step <= 1e-15) break;
+            // the error after a Newton step is of the order of its square
+            if (step <= 1e-10) break;
         }
         u = s == 1.0 ? ub : ua + s * (ub - ua);
         v = t == 1.0 ? vb : va + t * (vb - va);
@@ -977,7 +1022,18 @@ __device__ void s_finish(const DevSurf& D, const DSurf& sf, const double* x, con
     const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
     flags |= MREP_F_POLISHED;
     Polished r = s_polish(D, sf, b1.u, b1.v, x);
-    if (tie) {
+    // A runner-up needs no polish of its own when it is the point the polish of
+    // the best already reached, or when it lies on the closed rectangle of the
+    // best's patch: that patch's minimum (the best) is then no larger, and a
+    // descent from the runner-up can only end lower by entering a patch whose
+    // minimum would have ranked above it.
+    const double* bu0 = D.brk + sf.brk_off;
+    const double* bv0 = bu0 + sf.n_su + 1;
+    const double span = fmax(bu0[sf.n_su] - bu0[0], bv0[sf.n_sv] - bv0[0]);
+    const double* r1 = D.uv + 4 * b1.patch;
+    const double eps = 1e-12 * span;
+    const bool on_best = b2.u >= r1[0] - eps && b2.u <= r1[1] + eps && b2.v >= r1[2] - eps && b2.v <= r1[3] + eps;
+    if (tie && !on_best && fabs(b2.u - r.u) + fabs(b2.v - r.v) > 1e-6 * span) {
         const Polished r2 = s_polish(D, sf, b2.u, b2.v, x);
         const bool take = r2.dist < r.dist || (r2.dist == r.dist && (r2.u < r.u || (r2.u == r.u && r2.v < r.v)));
         const double sep = fabs(r2.u - r.u) + fabs(r2.v - r.v);
@@ -1031,7 +1087,7 @@ __global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __res
     const int64_t p0 = so.pair_off[j];
     for (int i = 0; i < n_list; ++i) {
         const float4 r = res[p0 + i];
-        s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
+        if (r.z < INFINITY) s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
     }
     if (!(b1.d2 < INFINITY)) {
         // no pair reached below its cap (FP32 rounding at the threshold): full scan
