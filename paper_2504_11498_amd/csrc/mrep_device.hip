@@ -633,6 +633,7 @@ static int32_t upload_surfaces(const SurfPlan& P, void* dev_buf, int64_t bytes, 
     HIP_OK(cp(L.off_uv, P.uv.data(), sizeof(double) * P.uv.size()));
     HIP_OK(cp(L.off_pspan, P.pspan.data(), sizeof(int32_t) * P.pspan.size()));
     HIP_OK(cp(L.off_span0, P.span0.data(), sizeof(int32_t) * P.span0.size()));
+    HIP_OK(cp(L.off_csph, P.csph.data(), sizeof(float) * P.csph.size()));
     HIP_OK(cp(L.off_brk, P.brk.data(), sizeof(double) * P.brk.size()));
     HIP_OK(cp(L.off_coef, P.coef.data(), sizeof(double) * P.coef.size()));
     // the plan's host vectors are pageable: finish the copies before returning

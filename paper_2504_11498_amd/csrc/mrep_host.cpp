@@ -1016,6 +1016,50 @@ void patch_tables(const double* R, const double* o, double tol_eff, float* sph, 
     sph[3] = nextafterf((float)(r * (1.0 + 1e-6) + tol_eff * (1.0 + 1e-6)), INFINITY);
 }
 
+// Cluster = block of bs x bs exact spans of one surface, about 32 patches,
+// at most 65535 clusters per surface.
+int cluster_block(int64_t n_patch, int32_t n_su, int32_t n_sv)
+{
+    const double pps = (double)n_patch / std::max<int64_t>(1, (int64_t)n_su * n_sv);
+    int bs = (int)std::max(1L, std::min(8L, lround(sqrt(32.0 / std::max(pps, 1e-9)))));
+    while ((int64_t)((n_su + bs - 1) / bs) * ((n_sv + bs - 1) / bs) > 65535) ++bs;
+    return bs;
+}
+
+// sphere (FP32 centre in the same frame, radius rounded up) containing the
+// patch spheres sph[4k..] of the cluster's span rows: centre at the middle of
+// their centres' box
+void cluster_sphere(const float* sph, const int32_t* span0, const DSurf& d, int32_t c, float* out)
+{
+    const int bs = d.clu_bs, bu = c / d.n_cbv, bv = c % d.n_cbv;
+    const int iu0 = bu * bs, iu1 = std::min(d.n_su, iu0 + bs), iv0 = bv * bs, iv1 = std::min(d.n_sv, iv0 + bs);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t end = d.span_off + (int64_t)d.n_su * d.n_sv;  // first span of the next surface
+    auto rows = [&](auto&& f) {
+        for (int iu = iu0; iu < iu1; ++iu) {
+            const int64_t rs = d.span_off + (int64_t)iu * d.n_sv;
+            const int64_t k1 = rs + iv1 == end ? d.patch_off + d.n_patch : span0[rs + iv1];
+            for (int64_t k = span0[rs + iv0]; k < k1; ++k) f(k);
+        }
+    };
+    rows([&](int64_t k) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], (double)sph[4 * k + a]);
+            hi[a] = std::max(hi[a], (double)sph[4 * k + a]);
+        }
+    });
+    float cf[3];
+    for (int a = 0; a < 3; ++a) cf[a] = lo[a] <= hi[a] ? (float)(0.5 * (lo[a] + hi[a])) : 0.f;
+    double r = 0.0;
+    rows([&](int64_t k) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) d2 += ((double)sph[4 * k + a] - cf[a]) * ((double)sph[4 * k + a] - cf[a]);
+        r = std::max(r, sqrt(d2) + (double)sph[4 * k + 3]);
+    });
+    for (int a = 0; a < 3; ++a) out[a] = cf[a];
+    out[3] = nextafterf((float)(r * (1.0 + 1e-6)), INFINITY);
+}
+
 }  // namespace
 
 int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u, const int32_t* n_v,
@@ -1059,7 +1103,7 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
     plan.n_surf = n_surf;
     plan.tol_rel = tol_rel;
     plan.surfs.resize((size_t)n_surf);
-    int64_t npatch = 0, nspan = 0, ncoef = 0, nbrk = 0;
+    int64_t npatch = 0, nspan = 0, ncoef = 0, nbrk = 0, nclu = 0;
     for (int32_t s = 0; s < n_surf; ++s) {
         const SurfOut& o = outs[(size_t)s];
         DSurf& d = plan.surfs[(size_t)s];
@@ -1072,7 +1116,11 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
         d.n_sv = o.n_sv;
         d.deg_u = deg_u[s];
         d.deg_v = deg_v[s];
-        d.pad = 0;
+        d.clu_bs = cluster_block((int64_t)o.pieces.size(), o.n_su, o.n_sv);
+        d.n_cbv = (o.n_sv + d.clu_bs - 1) / d.clu_bs;
+        d.n_clu = ((o.n_su + d.clu_bs - 1) / d.clu_bs) * d.n_cbv;
+        d.clu_off = nclu;
+        nclu += d.n_clu;
         d.tol_eff = (deg_u[s] >= 4 || deg_v[s] >= 4) ? o.tol_abs : 1e-13 * o.diag;
         d.tol_user = tol_rel * o.diag;
         d.diag = o.diag;
@@ -1098,6 +1146,7 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
     plan.coef.resize((size_t)ncoef);
     plan.sph.resize((size_t)npatch * 4);
     plan.lcp.resize((size_t)npatch * 48);
+    plan.csph.resize((size_t)nclu * 4);
     std::atomic<int32_t> next2{0};
     auto worker2 = [&]() {
         for (;;) {
@@ -1116,8 +1165,11 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
                 plan.pspan[(size_t)g] = (int32_t)(d.span_off + pc.span);
                 patch_tables(pc.R, d.origin, d.tol_eff, &plan.sph[(size_t)g * 4], &plan.lcp[(size_t)g * 48]);
             }
-            for (int64_t j = 0; j < (int64_t)o.n_su * o.n_sv; ++j)
+            const int64_t ns_s = (int64_t)o.n_su * o.n_sv;
+            for (int64_t j = 0; j < ns_s; ++j)
                 plan.span0[(size_t)(d.span_off + j)] = (int32_t)(d.patch_off + o.span_first[(size_t)j]);
+            for (int32_t c = 0; c < d.n_clu; ++c)
+                cluster_sphere(plan.sph.data(), plan.span0.data(), d, c, &plan.csph[(size_t)(d.clu_off + c) * 4]);
             memcpy(&plan.brk[(size_t)d.brk_off], o.brk.data(), sizeof(double) * o.brk.size());
             memcpy(&plan.coef[(size_t)d.coef_off], o.coef.data(), sizeof(double) * o.coef.size());
         }
@@ -1141,6 +1193,8 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
     L.off_uv = off; off = align256(off + 8 * 4 * npatch);
     L.off_pspan = off; off = align256(off + 4 * npatch);
     L.off_span0 = off; off = align256(off + 4 * (nspan + 1));
+    L.n_clu = nclu;
+    L.off_csph = off; off = align256(off + 16 * nclu);
     L.off_brk = off; off = align256(off + 8 * nbrk);
     L.off_coef = off; off = align256(off + 8 * ncoef);
     L.total = off;

@@ -106,13 +106,15 @@ struct DSurf {
     int32_t n_patch;
     int32_t n_su, n_sv;  // exact span grid
     int32_t deg_u, deg_v;
-    int32_t pad;
+    int32_t clu_bs;      // cluster = block of clu_bs x clu_bs exact spans
     double tol_eff;      // deviation bound of the patches from the exact surface
     double tol_user;     // tol_rel * diag
     double diag;         // control-net box diagonal
     double origin[3];    // FP32-representable box centre
+    int64_t clu_off;     // first cluster (global); clusters row-major over the span blocks
+    int32_t n_clu, n_cbv;  // clusters, cluster columns (blocks along v)
 };
-static_assert(sizeof(DSurf) == 104, "DSurf layout");
+static_assert(sizeof(DSurf) == 120, "DSurf layout");
 
 struct SurfLayout {
     int64_t n_surf = 0, n_patch = 0, n_span = 0, n_coef = 0, n_brk = 0;
@@ -123,6 +125,8 @@ struct SurfLayout {
     int64_t off_uv = 0;     // double[n_patch][4]  (u_a, u_b, v_a, v_b)
     int64_t off_pspan = 0;  // int32[n_patch]      exact span patch (global)
     int64_t off_span0 = 0;  // int32[n_span + 1]   first patch of each exact span patch (global)
+    int64_t n_clu = 0;
+    int64_t off_csph = 0;   // float4[n_clu]       sphere around the spheres of each cluster's patches
     int64_t off_brk = 0;    // double[n_brk]
     int64_t off_coef = 0;   // double[n_coef]      exact span patches: power coefficients in local (s, t)
     int64_t total = 0;
@@ -135,7 +139,7 @@ struct SurfPlan {
     std::vector<DSurf> surfs;
     std::vector<double> gcp, uv, brk, coef;
     std::vector<int32_t> pspan, span0;
-    std::vector<float> sph, lcp;
+    std::vector<float> sph, lcp, csph;
     SurfLayout layout;
 };
 

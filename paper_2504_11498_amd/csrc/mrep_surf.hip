@@ -4,15 +4,19 @@
 //
 // Pipeline for n queries, each onto its own surface:
 //   1. group queries by surface (counting sort, shared with the curve path);
-//   2. sphere candidates: every patch lies in a sphere (centre, radius bound
-//      incl. its deviation from the exact surface); per query, the pieces
-//      whose lower bound |q - c| - r reaches the best upper bound |q - c| + r
-//      plus the tie margin are listed as (query, patch) pairs;
+//   2. per query (one kernel): every patch lies in a sphere (centre, radius
+//      bound incl. its deviation from the exact surface); the patches whose
+//      lower bound |q - c| - r reaches the best upper bound |q - c| + r plus
+//      the tie margin are listed, a 4 x 4 sample bound of each listed patch
+//      (second-order, min(samples) - (M_ss + M_tt) / 72) is taken, the best
+//      sample lowers the query's bound, and the patches whose sampled bound
+//      still reaches it form the query's (query, patch) pairs;
 //   3. per pair, the certified minimum of |S(s,t) - q|^2 over the patch in
-//      FP32: a 7 x 7 sample grid, box-constrained Newton on the stationarity
-//      conditions (S - q).S_s = (S - q).S_t = 0 from its local minima, the four
-//      edge curves by the curve path's certified 1D minimum, and a Newton solve
-//      in every grid cell whose second-order lower bound
+//      FP32, capped at the query's bound plus the tie margin: a 7 x 7 sample
+//      grid, box-constrained Newton on the stationarity conditions
+//      (S - q).S_s = (S - q).S_t = 0 from its local minima, the four edge
+//      curves by the curve path's certified 1D minimum, and a Newton solve in
+//      every grid cell whose second-order lower bound
 //      min(corner f) - (M_ss h^2 + M_tt h^2) / 8 still beats the best;
 //   4. per query, the two best pairs; FP64 box-constrained Newton on the EXACT
 //      span patch (power form of degree (p, q)) from the best, continuing into
@@ -21,12 +25,11 @@
 //      the tie margin; write (u, v), distance, patch index and flags.
 // Queries whose list overflows take a wave-per-query scan of all their patches.
 //
-// Seeded calls (learned seeding, an extension): step 2 also keeps each
+// Seeded calls (learned seeding, an extension): a first sweep keeps each
 // query's 4 patches with the smallest sphere lower bounds and writes their
 // network inputs; the surface network scores them; Newton from the predicted
-// (s, t) on the best-scored patch attains a first upper bound.  A pair whose
-// sphere lower bound already exceeds the best bound so far is dropped before
-// its sampled bound is computed; the rest of the pipeline is unchanged, so the
+// (s, t) on the best-scored patch attains a first bound, which replaces the
+// sphere upper bound of step 2; the rest of the pipeline is unchanged, so the
 // answer is the certified global minimum whatever the network predicts.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -46,14 +49,16 @@ namespace {
 
 constexpr int kSphSub = 8;
 constexpr int kSphThreads = kQueriesPerTile * kSphSub;
-constexpr int kSphChunk = 1024;
-constexpr int kSphCap = 256;
+constexpr int kSphCap = 256;    // listed patches per query; more: the full scan
+constexpr int kCluChunk = 2048;  // cluster spheres staged per round
+constexpr int kCluCap = 64;     // candidate clusters per query; more: the full scan
 constexpr int kXcds = 8;
 constexpr int64_t kSurfPairsPerQuery = 96;
 constexpr int kGrid = 7;  // samples per direction in a patch
 constexpr int kK = MREP_NN_K;  // candidate patches scored per query (seeded calls)
 constexpr int kFeat = MREP_NN_SURFACE_IN;
-static_assert(kSphThreads == 256, "sphere kernel: 32 queries x 8 lanes");
+static_assert(kSphThreads == 256, "sphere kernels: 32 queries x 8 lanes");
+static_assert(sizeof(float4) * kCluChunk == sizeof(float) * kQueriesPerTile * kSphCap, "list kernel LDS union");
 
 struct DevSurf {
     const DSurf* surfs;
@@ -63,6 +68,7 @@ struct DevSurf {
     const double* uv;
     const int32_t* pspan;
     const int32_t* span0;
+    const float4* csph;
     const double* brk;
     const double* coef;
     int32_t n_surf;
@@ -79,6 +85,7 @@ DevSurf surf_view(const SurfGeom& g)
     d.uv = reinterpret_cast<const double*>(g.base + g.L.off_uv);
     d.pspan = reinterpret_cast<const int32_t*>(g.base + g.L.off_pspan);
     d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
+    d.csph = reinterpret_cast<const float4*>(g.base + g.L.off_csph);
     d.brk = reinterpret_cast<const double*>(g.base + g.L.off_brk);
     d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
     d.n_surf = (int32_t)g.L.n_surf;
@@ -94,8 +101,7 @@ __device__ __forceinline__ float s_margin(float d, const DSurf& sf, float tie_re
 // ---------------------------------------------------------------------------
 // 2. sphere candidate lists
 // ---------------------------------------------------------------------------
-// Seeded calls also keep, per query, the kK patches with the smallest lower
-// bounds (ties to the lower index) and write their network inputs.
+// Seeded calls: candidate patches and their network inputs
 struct SphTop {
     int32_t* cand;  // [n][kK] global patch index (-1: fewer patches)
     uint16_t* xb;   // [n][kK][64] BF16 network inputs (null: not written)
@@ -151,16 +157,146 @@ __device__ __forceinline__ void patch_features(const DevSurf& D, const DSurf& sf
     for (int a = 0; a < 3; ++a) x[48 + a] = (ql[a] - m[a]) * inv;
 }
 
-template <bool kTop>
-__global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* __restrict__ tile_off,
-                                                      const int32_t* __restrict__ q_off,
-                                                      const int32_t* __restrict__ perm,
-                                                      const double* __restrict__ qxyz, float tie_rel, ScreenOut so,
-                                                      SphTop top)
+// ---------------------------------------------------------------------------
+// Two-level sphere sweeps.  The exact spans of a surface are grouped into
+// clusters (blocks of clu_bs x clu_bs spans, about 32 patches), each with a
+// sphere around its patches' spheres, so for a query q and any patch p of
+// cluster C
+//     |q - c_p| - r_p >= |q - c_C| - r_C    and    |q - c_p| + r_p <= |q - c_C| + r_C.
+// A query's 8 lanes test the surface's cluster spheres (staged in LDS) and then
+// only the patches of the clusters whose lower bound reaches the threshold
+// (read from global memory; one row of a cluster's spans holds contiguous
+// patches).
+// ---------------------------------------------------------------------------
+// one staging round of cluster spheres; all threads of the block call it
+__device__ __forceinline__ void stage_clusters(const DevSurf& D, const DSurf& sf, int c0, int cn, float4* st)
 {
-    __shared__ float4 s_sph[kSphChunk];
-    __shared__ int32_t s_list[kQueriesPerTile][kSphCap];
-    __shared__ int32_t s_base[kQueriesPerTile];
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += kSphThreads) st[i] = D.csph[sf.clu_off + c0 + i];
+    __syncthreads();
+}
+
+// span rows of cluster c: rows iu in [iu0, iu1), each the patches
+// [span0[r + iv0], span0[r + iv1]) with r = span_off + iu * n_sv
+struct CluRows {
+    int iu0, iu1, iv0, iv1;
+};
+__device__ __forceinline__ CluRows clu_rows(const DSurf& sf, int c)
+{
+    const int bs = sf.clu_bs, bu = c / sf.n_cbv, bv = c % sf.n_cbv;
+    return CluRows{bu * bs, min(sf.n_su, bu * bs + bs), bv * bs, min(sf.n_sv, bv * bs + bs)};
+}
+
+// min over the patches of cluster c of |q - c_p| + r_p + eps (per lane)
+__device__ __forceinline__ float clu_patch_ub(const DevSurf& D, const DSurf& sf, int c, const float* ql, float eps,
+                                              int sub, float ub)
+{
+    const CluRows R = clu_rows(sf, c);
+    for (int iu = R.iu0; iu < R.iu1; ++iu) {
+        const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
+        const int k1 = D.span0[rs + R.iv1];
+        for (int k = D.span0[rs + R.iv0] + sub; k < k1; k += kSphSub) {
+            const float4 p = D.sph[k];
+            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+            ub = fminf(ub, sqrtf(dx * dx + dy * dy + dz * dz) + p.w + eps);
+        }
+    }
+    return ub;
+}
+
+// A first bound on the distance: min over clusters of |q - c_C| + r_C + eps,
+// and over the patches of the kK clusters with the smallest lower bounds
+// |q - c_C| - r_C of |q - c_p| + r_p + eps (same value in the query's 8 lanes).
+__device__ float first_ub(const DevSurf& D, const DSurf& sf, float4* st, const float* ql, float eps, bool active,
+                          int sub)
+{
+    float ub = INFINITY;
+    uint64_t key[kK];  // (ordered lower bound, local cluster), sorted
+#pragma unroll
+    for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+    for (int c0 = 0; c0 < sf.n_clu; c0 += kCluChunk) {
+        const int cn = min(kCluChunk, sf.n_clu - c0);
+        stage_clusters(D, sf, c0, cn, st);
+        if (!active) continue;
+        for (int i = sub; i < cn; i += kSphSub) {
+            const float4 p = st[i];
+            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+            const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+            ub = fminf(ub, d + p.w + eps);
+            uint64_t x = ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i);
+            if (x < key[kK - 1]) {
+#pragma unroll
+                for (int k = 0; k < kK; ++k) cswap(key[k], x);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kSphSub; off <<= 1) {
+        uint64_t o[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
+#pragma unroll
+        for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
+        cswap(key[0], key[2]);
+        cswap(key[1], key[3]);
+        cswap(key[0], key[1]);
+        cswap(key[2], key[3]);
+    }
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < kK; ++m)
+            if (key[m] != ~0ull) ub = clu_patch_ub(D, sf, (int)(uint32_t)key[m], ql, eps, sub, ub);
+    }
+#pragma unroll
+    for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
+    return ub;
+}
+
+// clusters whose lower bound |q - c_C| - r_C - eps reaches thr, in index
+// order, into list[0..kCluCap) as local indices; returns their count (more
+// than kCluCap: overflow)
+__device__ int clu_list(const DevSurf& D, const DSurf& sf, float4* st, const float* ql, float eps, float thr,
+                        bool active, int lane, int sub, int32_t* list)
+{
+    int cnt = 0;
+    for (int c0 = 0; c0 < sf.n_clu; c0 += kCluChunk) {
+        const int cn = min(kCluChunk, sf.n_clu - c0);
+        stage_clusters(D, sf, c0, cn, st);
+        if (!active) continue;
+        // the 8 lanes of a query run the same trip count: the ballot sees all of them
+        for (int i0 = 0; i0 < cn; i0 += kSphSub) {
+            const int i = i0 + sub;
+            bool hit = false;
+            if (i < cn) {
+                const float4 p = st[i];
+                const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                const float tt = thr + p.w + eps;
+                hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+            }
+            const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+            const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+            if (hit && pos < kCluCap) list[pos] = c0 + i;
+            cnt += __popc(grp);
+        }
+    }
+    return cnt;
+}
+
+// Candidates of the seeded calls: per query, the kK patches with the smallest
+// sphere lower bounds (ties to the lower index) among the clusters whose bound
+// reaches the first bound plus the tie margin, their network inputs (BF16
+// rows of 64, when top.xb is set) and the best patch sphere upper bound
+// so.ub.  One workgroup per tile of kQueriesPerTile queries of one surface, 8
+// lanes per query.  A query with more than kCluCap such clusters gets so.ub =
+// +inf and candidates from the first kCluCap only.
+__global__ __launch_bounds__(kSphThreads) void k_scand(DevSurf D, const int32_t* __restrict__ tile_off,
+                                                       const int32_t* __restrict__ q_off,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ qxyz, float tie_rel, ScreenOut so,
+                                                       SphTop top)
+{
+    __shared__ float4 s_st[kCluChunk];
+    __shared__ int32_t s_clu[kQueriesPerTile][kCluCap];
     const int n_tiles = tile_off[D.n_surf];
     const int per = (n_tiles + kXcds - 1) / kXcds;
     const int slot = (int)(blockIdx.x / kXcds);
@@ -183,111 +319,51 @@ __global__ __launch_bounds__(kSphThreads) void k_ssph(DevSurf D, const int32_t* 
         for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - sf.origin[k]);
     }
     const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
-    float ub = INFINITY, thr = 0.f;
-    int cnt = 0;
+    const float ubs = first_ub(D, sf, s_st, ql, eps, active, sub);
+    const float thr0 = ubs + s_margin(ubs, sf, tie_rel);
+    const int ns = clu_list(D, sf, s_st, ql, eps, thr0, active, lane, sub, s_clu[qs]);
+    float ub = INFINITY;
     uint64_t key[kK];
 #pragma unroll
     for (int k = 0; k < kK; ++k) key[k] = ~0ull;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int c0 = 0; c0 < sf.n_patch; c0 += kSphChunk) {
-            const int cn = min(kSphChunk, sf.n_patch - c0);
-            __syncthreads();
-            for (int i = threadIdx.x; i < cn; i += kSphThreads) s_sph[i] = D.sph[sf.patch_off + c0 + i];
-            __syncthreads();
-            if (!active) continue;
-            if (pass == 0 && !kTop) {
-                for (int i = sub; i < cn; i += kSphSub) {
-                    const float4 p = s_sph[i];
+    if (active) {
+        for (int m = 0; m < min(ns, kCluCap); ++m) {
+            const CluRows R = clu_rows(sf, s_clu[qs][m]);
+            for (int iu = R.iu0; iu < R.iu1; ++iu) {
+                const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
+                const int k1 = D.span0[rs + R.iv1];
+                for (int k = D.span0[rs + R.iv0] + sub; k < k1; k += kSphSub) {
+                    const float4 p = D.sph[k];
                     const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                    const float tu = ub - p.w - eps;
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    if (!(tu > 0.f) || d2 < tu * tu) ub = fminf(ub, sqrtf(d2) + p.w + eps);
-                }
-            } else if (pass == 0) {
-                for (int i = sub; i < cn; i += kSphSub) {
-                    const float4 p = s_sph[i];
-                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
                     const float re = p.w + eps;
-                    const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
-                    const float tu = ub - re;
-                    const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
-                    const bool cu = !(tu > 0.f) || d2 < tu * tu;
-                    if (c4 || cu) {
-                        const float d = sqrtf(d2);
-                        ub = fminf(ub, d + re);
-                        uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
+                    ub = fminf(ub, d + re);
+                    uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(k - sf.patch_off);
+                    if (x < key[kK - 1]) {
 #pragma unroll
-                        for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
+                        for (int t = 0; t < kK; ++t) cswap(key[t], x);  // insertion into the sorted list
                     }
-                }
-            } else {
-                for (int i0 = 0; i0 < cn; i0 += kSphSub) {
-                    const int i = i0 + sub;
-                    bool hit = false;
-                    if (i < cn) {
-                        const float4 p = s_sph[i];
-                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                        const float tt = thr + p.w + eps;
-                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
-                    }
-                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
-                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-                    if (hit && pos < kSphCap) s_list[qs][pos] = c0 + i;
-                    cnt += __popc(grp);
                 }
             }
         }
-        if (pass == 0) {
-#pragma unroll
-            for (int off = 1; off < kSphSub; off <<= 1) {
-                ub = fminf(ub, __shfl_xor(ub, off, 64));
-                if (kTop) {
-                    // merge the lanes' sorted lists: exchange, keep the smaller half (bitonic)
-                    uint64_t o[kK];
-#pragma unroll
-                    for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
-#pragma unroll
-                    for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
-                    cswap(key[0], key[2]);
-                    cswap(key[1], key[3]);
-                    cswap(key[0], key[1]);
-                    cswap(key[2], key[3]);
-                }
-            }
-            thr = ub + s_margin(ub, sf, tie_rel);
-        }
     }
-    const bool listed = active && cnt <= kSphCap;
-    if (sub == 0) s_base[qs] = listed ? cnt : 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int k = 0; k < kQueriesPerTile; ++k) {
-            const int v = s_base[k];
-            s_base[k] = tot;
-            tot += v;
-        }
-        const int base = tot > 0 ? atomicAdd(so.pair_count, tot) : 0;
-        for (int k = 0; k < kQueriesPerTile; ++k) s_base[k] += base;
+    // merge the lanes' sorted lists: exchange, keep the smaller half (bitonic)
+#pragma unroll
+    for (int off = 1; off < kSphSub; off <<= 1) {
+        ub = fminf(ub, __shfl_xor(ub, off, 64));
+        uint64_t o[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
+#pragma unroll
+        for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
+        cswap(key[0], key[2]);
+        cswap(key[1], key[3]);
+        cswap(key[0], key[1]);
+        cswap(key[2], key[3]);
     }
-    __syncthreads();
     if (!active) return;
-    const int64_t b = s_base[qs];
-    const bool fits = listed && b + cnt <= so.pair_cap;
-    if (sub == 0) {
-        so.cand_n[j] = fits ? cnt : -1;
-        so.pair_off[j] = (int32_t)b;
-        so.ub[j] = ub;
-    }
-    if (listed) {
-        for (int k = sub; k < cnt; k += kSphSub) {
-            if (b + k >= so.pair_cap) break;
-            so.pair_seg[b + k] = fits ? (int32_t)(sf.patch_off + s_list[qs][k]) : 0;
-            so.pair_j[b + k] = fits ? (int32_t)j : -1;
-        }
-    }
-    if (kTop && sub < kK) {
+    if (sub == 0) so.ub[j] = ns <= kCluCap ? ub : INFINITY;
+    if (sub < kK) {
         const uint64_t kk = sub == 0 ? key[0] : (sub == 1 ? key[1] : (sub == 2 ? key[2] : key[3]));
         const int64_t g = kk == ~0ull ? -1 : sf.patch_off + (int64_t)(uint32_t)kk;
         top.cand[j * kK + sub] = (int32_t)g;
@@ -641,97 +717,184 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
     return best;
 }
 
-// Per pair: a 4 x 4 sample bound of the patch.  lb = min(samples) - (M_ss +
-// M_tt) h^2 / 8 with h = 1/3 (second-order bound of f = |S - q|^2) and the
-// best sample value, atomically minimised per query (non-negative float bits
-// order like integers).
-__global__ __launch_bounds__(256) void k_sbound(DevSurf D, const int32_t* __restrict__ sid,
+// ---------------------------------------------------------------------------
+// 2 + 3a. per query, the patches that can hold its minimum
+// ---------------------------------------------------------------------------
+// One workgroup per tile of kQueriesPerTile queries of one surface, 8 lanes per
+// query:
+//   a. threshold: a first bound from the cluster spheres and the patches of
+//      the nearest clusters, then the best patch sphere upper bound over the
+//      clusters that reach it (plain calls), or the seed's value (seeded
+//      calls, in fub); plus the tie margin;
+//   b. list the patches of those clusters whose sphere lower bound reaches the
+//      threshold (at most kSphCap, and at most kCluCap clusters; more: the
+//      query takes the full scan);
+//   c. a 4 x 4 sample bound of every listed patch: lb = min(samples) -
+//      (M_ss + M_tt) h^2 / 8 with h = 1/3 (second-order bound of f = |S - q|^2),
+//      and the best sample value lowers the query's bound;
+//   d. keep the patches whose lb reaches the final threshold, compacted into
+//      the query's pair list (one atomic per workgroup); fub = final bound.
+template <bool kSeeded>
+__global__ __launch_bounds__(kSphThreads) void k_slist(DevSurf D, const int32_t* __restrict__ tile_off,
+                                                       const int32_t* __restrict__ q_off,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ qxyz, float tie_rel, ScreenOut so,
+                                                       uint32_t* __restrict__ fub)
+{
+    // the sampled bounds reuse the cluster staging area once the sweeps are done
+    __shared__ union {
+        float4 st[kCluChunk];
+        float lb[kQueriesPerTile][kSphCap];
+    } s_u;
+    __shared__ int32_t s_list[kQueriesPerTile][kSphCap];
+    __shared__ int32_t s_clu[kQueriesPerTile][kCluCap];
+    __shared__ int32_t s_base[kQueriesPerTile];
+    const int n_tiles = tile_off[D.n_surf];
+    const int per = (n_tiles + kXcds - 1) / kXcds;
+    const int slot = (int)(blockIdx.x / kXcds);
+    const int tile = (int)(blockIdx.x % kXcds) * per + slot;
+    if (slot >= per || tile >= n_tiles) return;
+    int lo_c = 0, hi_c = D.n_surf;
+    while (hi_c - lo_c > 1) {
+        const int mid = (lo_c + hi_c) >> 1;
+        if (tile_off[mid] <= tile) lo_c = mid; else hi_c = mid;
+    }
+    const DSurf sf = D.surfs[lo_c];
+    const int lane = threadIdx.x & 63;
+    const int qs = threadIdx.x / kSphSub, sub = threadIdx.x % kSphSub;
+    const int64_t j = (int64_t)q_off[lo_c] + (int64_t)(tile - tile_off[lo_c]) * kQueriesPerTile + qs;
+    const bool active = j < q_off[lo_c + 1];
+    double q[3] = {0.0, 0.0, 0.0};
+    if (active) {
+        const int32_t qi = perm[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] = qxyz[3 * (int64_t)qi + k];
+    }
+    const float ql[3] = {(float)(q[0] - sf.origin[0]), (float)(q[1] - sf.origin[1]), (float)(q[2] - sf.origin[2])};
+    const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
+    // a. threshold and candidate clusters
+    float ub = INFINITY, fq = INFINITY;
+    int ns;
+    if (kSeeded) {
+        if (active) fq = __uint_as_float(fub[j]);
+        ub = sqrtf(fq);
+        ns = clu_list(D, sf, s_u.st, ql, eps, ub + s_margin(ub, sf, tie_rel), active, lane, sub, s_clu[qs]);
+    } else {
+        const float ubs = first_ub(D, sf, s_u.st, ql, eps, active, sub);
+        ns = clu_list(D, sf, s_u.st, ql, eps, ubs + s_margin(ubs, sf, tie_rel), active, lane, sub, s_clu[qs]);
+        // the best patch sphere upper bound over the candidate clusters
+        if (active && ns <= kCluCap)
+            for (int m = 0; m < ns; ++m) ub = clu_patch_ub(D, sf, s_clu[qs][m], ql, eps, sub, ub);
+#pragma unroll
+        for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
+    }
+    const float thr = ub + s_margin(ub, sf, tie_rel);
+    // b. list the patches of the candidate clusters whose sphere bound reaches thr
+    int cnt = 0;  // same value in the query's 8 lanes
+    if (active && ns <= kCluCap) {
+        for (int m = 0; m < ns; ++m) {
+            const CluRows R = clu_rows(sf, s_clu[qs][m]);
+            for (int iu = R.iu0; iu < R.iu1; ++iu) {
+                const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
+                const int k0 = D.span0[rs + R.iv0], k1 = D.span0[rs + R.iv1];
+                for (int i0 = k0; i0 < k1; i0 += kSphSub) {
+                    const int k = i0 + sub;
+                    bool hit = false;
+                    if (k < k1) {
+                        const float4 p = D.sph[k];
+                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                        const float tt = thr + p.w + eps;
+                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                    }
+                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                    if (hit && pos < kSphCap) s_list[qs][pos] = k - (int)sf.patch_off;
+                    cnt += __popc(grp);
+                }
+            }
+        }
+    } else if (active) {
+        cnt = kSphCap + 1;  // too many clusters: the full scan
+    }
+    const bool listed = active && cnt <= kSphCap;
+    __syncthreads();  // every wave is done with the staged spheres
+    // c. sampled bounds
+    if (listed) {
+        for (int k = sub; k < cnt; k += kSphSub) {
+            Bicubic B;
+            load_bicubic(D, sf, sf.patch_off + s_list[qs][k], q, B);
+            float mn = INFINITY;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) mn = fminf(mn, bc_f(B, a * (1.f / 3.f), b * (1.f / 3.f)));
+            const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
+            s_u.lb[qs][k] = mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f;
+            fq = fminf(fq, mn * (1.f + 4e-6f));
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kSphSub; off <<= 1) fq = fminf(fq, __shfl_xor(fq, off, 64));
+    __syncthreads();
+    // d. gate: compaction in place (a kept entry moves to a position at most its own)
+    int live = 0;
+    if (listed) {
+        const float u = sqrtf(fq);
+        const float t = u + s_margin(u, sf, tie_rel);
+        const float t2 = t * t;
+        for (int i0 = 0; i0 < cnt; i0 += kSphSub) {
+            const int k = i0 + sub;
+            const bool keep = k < cnt && s_u.lb[qs][k] <= t2;
+            const int32_t v = keep ? s_list[qs][k] : 0;
+            const uint32_t grp = (uint32_t)(__ballot(keep) >> (lane & 56)) & 0xffu;
+            const int pos = live + __popc(grp & ((1u << sub) - 1u));
+            if (keep) s_list[qs][pos] = v;
+            live += __popc(grp);
+        }
+    }
+    // reserve the workgroup's pairs with one atomic
+    if (sub == 0) s_base[qs] = listed ? live : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) {
+            const int v = s_base[k];
+            s_base[k] = tot;
+            tot += v;
+        }
+        const int base = tot > 0 ? atomicAdd(so.pair_count, tot) : 0;
+        for (int k = 0; k < kQueriesPerTile; ++k) s_base[k] += base;
+    }
+    __syncthreads();
+    if (!active) return;
+    const int64_t b = s_base[qs];
+    const bool fits = listed && b + live <= so.pair_cap;
+    if (sub == 0) {
+        so.cand_n[j] = fits ? live : -1;
+        so.pair_off[j] = (int32_t)b;
+        so.ub[j] = ub;
+        fub[j] = __float_as_uint(fq);
+    }
+    if (listed) {
+        for (int k = sub; k < live; k += kSphSub) {
+            if (b + k >= so.pair_cap) break;
+            so.pair_seg[b + k] = fits ? (int32_t)(sf.patch_off + s_list[qs][k]) : 0;
+            so.pair_j[b + k] = fits ? (int32_t)j : -1;  // a slot past the capacity stays unused
+        }
+    }
+}
+
+// 3b. One thread per listed pair: the certified patch minimum below the
+// query's threshold.
+__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
-                                                ScreenOut so, float tie_rel, float* __restrict__ lb,
-                                                uint32_t* __restrict__ fub)
+                                                ScreenOut so, const uint32_t* __restrict__ fub, float tie_rel,
+                                                float4* __restrict__ res)
 {
     const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t jj = so.pair_j[p];
         if (jj < 0) continue;
-        const int64_t k = so.pair_seg[p];
-        if (k < 0 || k >= D.n_patch) continue;
-        const int32_t qi = perm[jj];
-        const DSurf sf = D.surfs[sid[qi]];
-        const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
-        {
-            // sphere bound against the query's best value so far (any value
-            // fub has held is attained, so the test only drops patches that
-            // cannot hold the minimum)
-            const float4 c = D.sph[k];
-            const float dx = (float)(q[0] - sf.origin[0]) - c.x, dy = (float)(q[1] - sf.origin[1]) - c.y,
-                        dz = (float)(q[2] - sf.origin[2]) - c.z;
-            const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-            const float eps = 1e-6f * (d + sqrtf(c.x * c.x + c.y * c.y + c.z * c.z) + (float)sf.diag);
-            const float ub = sqrtf(__uint_as_float(fub[jj]));
-            if (d - c.w - eps > ub + s_margin(ub, sf, tie_rel)) {
-                lb[p] = INFINITY;
-                continue;
-            }
-        }
-        Bicubic B;
-        load_bicubic(D, sf, k, q, B);
-        float mn = INFINITY;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) mn = fminf(mn, bc_f(B, i * (1.f / 3.f), j * (1.f / 3.f)));
-        const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
-        lb[p] = mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f;
-        atomicMin(&fub[jj], __float_as_uint(mn * (1.f + 4e-6f)));
-    }
-}
-
-// Pairs whose lower bound reaches the query's best sample plus the tie margin
-// go to a dense list (one atomic per wave); the others get +inf.
-__global__ __launch_bounds__(256) void k_sgate(DevSurf D, const int32_t* __restrict__ sid,
-                                               const int32_t* __restrict__ perm, ScreenOut so,
-                                               const float* __restrict__ lb, const uint32_t* __restrict__ fub,
-                                               float tie_rel, int32_t* __restrict__ live, int32_t* __restrict__ n_live,
-                                               float4* __restrict__ res)
-{
-    const int64_t total = min((int64_t)*so.pair_count, so.pair_cap);
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-        const int64_t p = base + threadIdx.x;
-        bool keep = false;
-        if (p < total) {
-            const int32_t jj = so.pair_j[p];
-            const int64_t k = so.pair_seg[p];
-            if (jj >= 0 && k >= 0 && k < D.n_patch) {
-                const DSurf& sf = D.surfs[sid[perm[jj]]];
-                const float ub = sqrtf(__uint_as_float(fub[jj]));
-                const float thr = ub + s_margin(ub, sf, tie_rel);
-                keep = lb[p] <= thr * thr;
-                if (!keep) res[p] = make_float4(0.f, 0.f, INFINITY, 1.f);
-            }
-        }
-        const uint64_t m = __ballot(keep);
-        int32_t first = 0;
-        if (lane == 0 && m) first = atomicAdd(n_live, (int32_t)__popcll(m));
-        first = __shfl(first, 0, 64);
-        if (keep) live[first + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)p;
-    }
-}
-
-// One thread per live pair: the certified patch minimum.
-__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
-                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
-                                                ScreenOut so, const int32_t* __restrict__ live,
-                                                const int32_t* __restrict__ n_live,
-                                                const uint32_t* __restrict__ fub, float tie_rel,
-                                                float4* __restrict__ res)
-{
-    const int64_t total = *n_live;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = live[i];
-        const int32_t jj = so.pair_j[p];
         const int64_t k = so.pair_seg[p];
         const int32_t qi = perm[jj];
         const DSurf sf = D.surfs[sid[qi]];
@@ -747,12 +910,13 @@ __global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __rest
 
 // Seeded calls, one thread per query: Newton from the network's (s, t) on the
 // best-scored candidate patch; the attained value (with the same rounding
-// allowance as a sample) is the query's first upper bound.
+// allowance as a sample), or the square of the best sphere upper bound when
+// that is smaller, is the query's first bound.
 __global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restrict__ sid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ cand,
-                                               const float4* __restrict__ score, uint32_t* __restrict__ fub,
-                                               int32_t* __restrict__ seed_patch)
+                                               const float4* __restrict__ score, const float* __restrict__ ub,
+                                               uint32_t* __restrict__ fub, int32_t* __restrict__ seed_patch)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q_off[D.n_surf]) return;
@@ -763,8 +927,9 @@ __global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restr
         const float zk = score[j * kK + k].z;
         if (cand[j * kK + k] >= 0 && (best < 0 || zk > z)) { best = k; z = zk; }
     }
+    const float u2 = ub[j] * ub[j];
     if (best < 0) {
-        fub[j] = 0x7f800000u;
+        fub[j] = __float_as_uint(u2);
         seed_patch[j] = -1;
         return;
     }
@@ -780,14 +945,9 @@ __global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restr
     const float t0 = sc.y == sc.y ? fminf(fmaxf(sc.y, 0.f), 1.f) : 0.5f;
     PatchMin m{0.f, 0.f, INFINITY, 1.f};
     bc_newton(B, s0, t0, 0.f, 1.f, 0.f, 1.f, m);
-    fub[j] = __float_as_uint(m.f * (1.f + 4e-6f));
+    const float f = m.f * (1.f + 4e-6f);
+    fub[j] = __float_as_uint(f < u2 ? f : u2);
     seed_patch[j] = (int32_t)k;
-}
-
-__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1099,8 +1259,48 @@ __global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __res
     s_finish(D, sf, x, b1, b2, missed ? (uint32_t)MREP_F_NN_FALLBACK : 0u, tie_rel, invert, qi, o);
 }
 
-// Overflowed lists: one wave per query over all its patches (sphere bound
-// against the wave's best sphere upper bound, then the patch minimum).
+// Overflowed lists: one wave per query, three traversals of the clusters whose
+// sphere reaches the current threshold (the lanes test 64 clusters at a time,
+// then stride over the patches of each hit whose own sphere reaches it):
+//   A. the best patch sphere upper bound;
+//   B. the 4 x 4 sample bounds, whose best sample lowers the bound;
+//   C. the capped patch minimum of every patch whose sampled bound reaches it.
+template <typename F>
+__device__ void wave_patches(const DevSurf& D, const DSurf& sf, const float* ql, float eps, float thr, int lane,
+                             F&& f)
+{
+    for (int c0 = 0; c0 < sf.n_clu; c0 += 64) {
+        const int c = c0 + lane;
+        bool hit = false;
+        if (c < sf.n_clu) {
+            const float4 p = D.csph[sf.clu_off + c];
+            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+            const float tt = thr + p.w + eps;
+            hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+        }
+        for (uint64_t m = __ballot(hit); m; m &= m - 1) {
+            const CluRows R = clu_rows(sf, c0 + __ffsll((unsigned long long)m) - 1);
+            for (int iu = R.iu0; iu < R.iu1; ++iu) {
+                const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
+                const int k1 = D.span0[rs + R.iv1];
+                for (int k = D.span0[rs + R.iv0] + lane; k < k1; k += 64) {
+                    const float4 p = D.sph[k];
+                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+                    if (d - p.w - eps <= thr) f(k, d + p.w + eps);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restrict__ sid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ list, const int32_t* __restrict__ count,
@@ -1110,6 +1310,7 @@ __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restr
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t total = *count;
+    const float tr = (float)tie_rel;
     for (int64_t item = wave; item < total; item += nwaves) {
         const int32_t qi = perm[list[item]];
         const DSurf sf = D.surfs[sid[qi]];
@@ -1117,24 +1318,47 @@ __global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restr
         const float ql[3] = {(float)(x[0] - sf.origin[0]), (float)(x[1] - sf.origin[1]), (float)(x[2] - sf.origin[2])};
         const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)sf.diag);
         float ub = INFINITY;
-        for (int64_t k = lane; k < sf.n_patch; k += 64) {
-            const float4 c = D.sph[sf.patch_off + k];
-            const float dx = ql[0] - c.x, dy = ql[1] - c.y, dz = ql[2] - c.z;
-            ub = fminf(ub, sqrtf(dx * dx + dy * dy + dz * dz) + c.w + eps);
+        for (int c = lane; c < sf.n_clu; c += 64) {
+            const float4 p = D.csph[sf.clu_off + c];
+            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+            ub = fminf(ub, sqrtf(dx * dx + dy * dy + dz * dz) + p.w + eps);
         }
-        for (int off = 32; off > 0; off >>= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
-        const float thr = ub + s_margin(ub, sf, (float)tie_rel);
-        SCand b1 = s_empty(), b2 = b1;
-        for (int64_t k = lane; k < sf.n_patch; k += 64) {
-            const int64_t g = sf.patch_off + k;
-            const float4 c = D.sph[g];
-            const float dx = ql[0] - c.x, dy = ql[1] - c.y, dz = ql[2] - c.z;
-            if (sqrtf(dx * dx + dy * dy + dz * dz) - c.w - eps > thr) continue;
+        ub = wave_min(ub);
+        // A
+        float ubp = ub;
+        wave_patches(D, sf, ql, eps, ub + s_margin(ub, sf, tr), lane, [&](int, float u) { ubp = fminf(ubp, u); });
+        ub = wave_min(ubp);
+        // B
+        float fq = ub * ub;
+        wave_patches(D, sf, ql, eps, ub + s_margin(ub, sf, tr), lane, [&](int k, float) {
             Bicubic B;
-            load_bicubic(D, sf, g, x, B);
-            const PatchMin m = patch_min(B, thr * thr * (1.f + 1e-5f));
-            s_top2(s_make(D, g, m.s, m.t, m.f, m.kappa), b1, b2);
-        }
+            load_bicubic(D, sf, k, x, B);
+            float mn = INFINITY;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) mn = fminf(mn, bc_f(B, a * (1.f / 3.f), b * (1.f / 3.f)));
+            fq = fminf(fq, mn * (1.f + 4e-6f));
+        });
+        fq = wave_min(fq);
+        // C
+        const float u = sqrtf(fq);
+        const float thr = u + s_margin(u, sf, tr);
+        const float thr2 = thr * thr;
+        SCand b1 = s_empty(), b2 = b1;
+        wave_patches(D, sf, ql, eps, thr, lane, [&](int k, float) {
+            Bicubic B;
+            load_bicubic(D, sf, k, x, B);
+            float mn = INFINITY;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) mn = fminf(mn, bc_f(B, a * (1.f / 3.f), b * (1.f / 3.f)));
+            const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
+            if (mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f > thr2) return;
+            const PatchMin m = patch_min(B, thr2 * (1.f + 1e-5f));
+            if (m.f < INFINITY) s_top2(s_make(D, k, m.s, m.t, m.f, m.kappa), b1, b2);
+        });
         // wave top-2
         for (int off = 32; off > 0; off >>= 1) {
             SCand o1, o2;
@@ -1210,12 +1434,9 @@ __global__ void k_sfeat_fill(int64_t n, int32_t* __restrict__ patch_out, float* 
 
 struct SWork {
     int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
-    ScreenOut so;
-    float4* res;
-    float* lb;       // [cap] sampled lower bound of each pair
-    uint32_t* fub;  // [n] best sample value of each query (float bits)
-    int32_t* live;   // [cap] pairs that need the patch minimum
-    int32_t* n_live; // their count
+    ScreenOut so;     // per query: its pairs (patches that can hold its minimum)
+    float4* res;      // [cap] patch minimum of each pair
+    uint32_t* fub;    // [n] bound on each query's squared distance (float bits)
     // seeded calls
     SphTop top;          // [n][kK] candidates, [n][kK][64] BF16 inputs
     float4* score;       // [n][kK] network outputs
@@ -1233,8 +1454,8 @@ int64_t s_layout(int64_t ns, int64_t n, bool seeded, char* base, SWork* w)
     const int64_t cap = std::min<int64_t>(kSurfPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
     const int64_t oh = take(4 * (ns + 2)), oq = take(4 * (ns + 1)), ot = take(4 * (ns + 1)), op = take(4 * n);
     const int64_t oov = take(4 * n), ocn = take(4 * n), opo = take(4 * n), oub = take(4 * n);
-    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap), olb = take(4 * cap);
-    const int64_t ofu = take(4 * n), olv = take(4 * cap), onl = take(4);
+    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap);
+    const int64_t ofu = take(4 * n);
     const int64_t m = seeded ? n : 0;
     const int64_t oca = take(4 * kK * m), oxb = take(128 * kK * m), osc = take(16 * kK * m), osp = take(4 * m);
     if (w) {
@@ -1253,10 +1474,7 @@ int64_t s_layout(int64_t ns, int64_t n, bool seeded, char* base, SWork* w)
         w->so.pair_count = w->hist + ns + 1;
         w->so.pair_cap = cap;
         w->res = (float4*)(base + ors);
-        w->lb = (float*)(base + olb);
         w->fub = (uint32_t*)(base + ofu);
-        w->live = (int32_t*)(base + olv);
-        w->n_live = (int32_t*)(base + onl);
     }
     return off;
 }
@@ -1320,34 +1538,29 @@ int32_t run_surf(const char* fn, const mrep_geom* geom, const mrep_nn* nn, const
     S_HIP(launch_grouping(ns, n, nullptr, sid, w.hist, w.q_off, w.tile_off, w.perm,
                           Outs{nullptr, nullptr, nullptr, nullptr}, st));
     const int64_t tiles = ns + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
+    const int32_t* tq[3] = {w.tile_off, w.q_off, w.perm};
     if (seeded) {
-        hipLaunchKernelGGL(k_ssph<true>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D,
-                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q, tie, w.so,
-                           w.top);
+        hipLaunchKernelGGL(k_scand, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, tq[0], tq[1], tq[2], q, tie,
+                           w.so, w.top);
         S_HIP(hipGetLastError());
         if (timed && (rc = stage_mark(++stage, st))) return rc;
         if ((rc = nn_score_surface_pairs(nn, w.q_off, (int32_t)ns, w.top.cand, w.top.xb, w.score, n * kK, st)))
             return rc;
         if (timed && (rc = stage_mark(++stage, st))) return rc;
-        hipLaunchKernelGGL(k_sseed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, sid, q,
-                           (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.top.cand,
-                           (const float4*)w.score, w.fub, w.seed_patch);
+        hipLaunchKernelGGL(k_sseed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, D, sid, q, tq[1], tq[2],
+                           (const int32_t*)w.top.cand, (const float4*)w.score, (const float*)w.so.ub, w.fub,
+                           w.seed_patch);
+        hipLaunchKernelGGL(k_slist<true>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, tq[0], tq[1], tq[2], q,
+                           tie, w.so, w.fub);
     } else {
-        hipLaunchKernelGGL(k_ssph<false>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D,
-                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q, tie, w.so,
-                           SphTop{nullptr, nullptr});
+        hipLaunchKernelGGL(k_slist<false>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, tq[0], tq[1], tq[2], q,
+                           tie, w.so, w.fub);
         S_HIP(hipGetLastError());
         if (timed && (rc = stage_mark(++stage, st))) return rc;
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.fub, n, 0x7f800000u);
     }
     const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.so.pair_cap + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)w.n_live, (int64_t)1, 0u);
-    hipLaunchKernelGGL(k_sbound, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so, tie, w.lb,
-                       w.fub);
-    hipLaunchKernelGGL(k_sgate, dim3(pb), dim3(256), 0, st, D, sid, (const int32_t*)w.perm, w.so, (const float*)w.lb,
-                       (const uint32_t*)w.fub, tie, w.live, w.n_live, w.res);
-    hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, (const int32_t*)w.perm, w.so,
-                       (const int32_t*)w.live, (const int32_t*)w.n_live, (const uint32_t*)w.fub, tie, w.res);
+    hipLaunchKernelGGL(k_spairs, dim3(pb), dim3(256), 0, st, D, sid, q, tq[2], w.so, (const uint32_t*)w.fub, tie,
+                       w.res);
     S_HIP(hipGetLastError());
     if (timed && (rc = stage_mark(++stage, st))) return rc;
     SOuts o{uv_out, dist_out, patch_out, flags_out};
@@ -1486,7 +1699,7 @@ int32_t mrep_nn_surface_features(const mrep_geom* geom, int64_t n, const int32_t
     S_HIP(launch_grouping(ns, n, nullptr, surface_id, w.hist, w.q_off, w.tile_off, w.perm,
                           Outs{nullptr, nullptr, nullptr, nullptr}, st));
     const int64_t tiles = ns + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
-    hipLaunchKernelGGL(k_ssph<true>, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, (const int32_t*)w.tile_off,
+    hipLaunchKernelGGL(k_scand, dim3((unsigned)tiles), dim3(kSphThreads), 0, st, D, (const int32_t*)w.tile_off,
                        (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, 2e-6f, w.so,
                        SphTop{w.top.cand, nullptr});
     hipLaunchKernelGGL(k_sfeat_write, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, D, surface_id, q_xyz,
