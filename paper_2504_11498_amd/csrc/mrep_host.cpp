@@ -465,8 +465,11 @@ void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* co
     aux[AUX_CY] = cf[1];
     aux[AUX_CZ] = cf[2];
     aux[AUX_CC] = (float)dot3(crel, crel);
-    aux[AUX_KA] = (float)(kScreenKappaBf16 * As * 1.01);
-    aux[AUX_KE] = (float)(kScreenKappaBf16 * Es * 1.01);
+    // with the epilogue's FP32 rounding 1e-6 (|q'|^2 + |c|^2 + |acc|), |acc| <=
+    // max|q'_i| A + E: the A, E and |c|^2 parts are folded in here (the |q'|^2
+    // part is added per query)
+    aux[AUX_KA] = (float)((kScreenKappaBf16 * 1.01 + 1.02e-6) * As);
+    aux[AUX_KE] = (float)((kScreenKappaBf16 * 1.01 + 1.02e-6) * Es + 1.02e-6 * dot3(crel, crel));
     aux[AUX_ES] = (float)((L / (2.0 * (kSamples - 1)) + tol_eff) * 1.0001);
     aux[AUX_L] = (float)L;
     for (int i = 0; i < 4; ++i)
@@ -567,7 +570,7 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
         d.n_seg = (int32_t)o.pieces.size();
         d.n_span = (int32_t)(o.span_t.size() / 2);
         d.degree = degree[c];
-        d.pad = 0;
+        d.es_max = 0.f;
         d.tol_eff = degree[c] >= 4 ? o.tol_abs : 1e-13 * o.diag;
         d.tol_user = tol_rel * o.diag;
         d.diag = o.diag;
@@ -601,8 +604,9 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
             int32_t c = next2.fetch_add(1);
             if (c >= n_curves) break;
             const CurveOut& o = outs[(size_t)c];
-            const DCurve& d = plan.curves[(size_t)c];
+            DCurve& d = plan.curves[(size_t)c];
             double tol_eff = d.tol_eff;
+            float es_max = 0.f;
             for (int32_t s = 0; s < d.n_seg; ++s) {
                 const Piece& pc = o.pieces[(size_t)s];
                 int64_t g = d.seg_off + s;
@@ -612,7 +616,9 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
                 plan.seg_span[(size_t)g] = (int32_t)(d.span_off + pc.span);
                 piece_tables(pc.R, d.origin, tol_eff, &plan.col[(size_t)g * kScreenK], &plan.aux[(size_t)g * 8],
                              &plan.lcp[(size_t)g * 12]);
+                es_max = std::max(es_max, plan.aux[(size_t)g * 8 + AUX_ES]);
             }
+            d.es_max = es_max;
             for (int32_t j = 0; j < d.n_span; ++j) {
                 plan.span_t[(size_t)(d.span_off + j) * 2] = o.span_t[(size_t)j * 2];
                 plan.span_t[(size_t)(d.span_off + j) * 2 + 1] = o.span_t[(size_t)j * 2 + 1];

@@ -32,7 +32,7 @@ struct DCurve {
     int32_t n_seg;
     int32_t n_span;
     int32_t degree;
-    int32_t pad;
+    float es_max;        // largest sample-spacing term e = L/(2(S-1)) + tol of the curve's pieces
     double tol_eff;      // same-parameter deviation bound of the pieces (rounding level for p <= 3)
     double tol_user;     // tol_rel * diag: the caller's tolerance (inversion's on-curve test)
     double diag;         // control-point box diagonal
@@ -57,8 +57,10 @@ struct GeomLayout {
 };
 
 // aux[8] per piece: cx, cy, cz (FP32 centre relative to the curve origin),
-// |c|^2, kappa A and kappa E (the screen's rounding-bound terms: A = sum |2 b_j|_1,
-// E = sum |e_m|, kappa = kScreenKappaBf16), e = L/(2(S-1)) + tol, L (speed bound in u).
+// |c|^2, kappa' A and kappa' E + 1.02e-6 |c|^2 (the screen's rounding-bound
+// terms: A = sum |2 b_j|_1, E = sum |e_m|, kappa' = 1.01 kScreenKappaBf16 +
+// 1.02e-6 for the epilogue's FP32 rounding), e = L/(2(S-1)) + tol, L (speed
+// bound in u).
 enum { AUX_CX = 0, AUX_CY, AUX_CZ, AUX_CC, AUX_KA, AUX_KE, AUX_ES, AUX_L };
 
 // BF16 screen: |computed - exact| of a sample's squared distance is at most

@@ -61,8 +61,14 @@ static_assert(kChunk * 4 % kThreads == 0 && kChunk * 2 % kThreads == 0, "full-ch
 // certified bounds, with room for the FP32 rounding of the epilogue
 constexpr float kSqrtLo = 1.0f - 0x1p-20f;
 constexpr float kSqrtHi = 1.0f + 0x1p-20f;
+// lb <= U implies D - delta <= ((U + e) / kSqrtLo)^2 <= ((U + e_max) / kSqrtLo)^2;
+// the threshold is computed with a relative margin of 2^-18 so that FP32
+// rounding can only let more pieces through
+constexpr int kShareEvery = 4;  // tiles between refreshes of a query's shared upper bound
 
-__global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
+// 3 waves per SIMD (at most 168 VGPRs): the MFMA-to-reduction latency is
+// hidden by the other waves; 2 waves per SIMD lose a fifth of the throughput
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_screen_bf16(DevGeom G, const int32_t* __restrict__ tile_off,
                                                           const int32_t* __restrict__ q_off,
                                                           const int32_t* __restrict__ perm,
                                                           const double* __restrict__ qxyz, int32_t kc,
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32
     const int kb = lane >> 4;
     bf16x8 A[kSets][8];
     // epilogue query of this lane (query lane>>4 of each set): -2 q', |q'|^2, max |q'_i|
-    float m2q[kSets][3], qq[kSets], qmax[kSets], eq[kSets];
+    float m2q[kSets][3], qq[kSets], qq6[kSets], qmax[kSets], eq[kSets];
     bool pvalid[kSets];
     for (int s = 0; s < kSets; ++s) {
         int ja = qbase + 4 * s + (arow >> 2);
@@ -141,6 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32
         }
         m2q[s][0] = -2.f * px; m2q[s][1] = -2.f * py; m2q[s][2] = -2.f * pz;
         qq[s] = px * px + py * py + pz * pz;
+        qq6[s] = 1.02e-6f * qq[s];  // the epilogue's FP32 rounding, query part
         qmax[s] = fmaxf(fabsf(px), fmaxf(fabsf(py), fabsf(pz)));
         // rounding q - o to FP32 moves the query by <= 2^-24 |q - o| per axis
         // (the origin is exact in FP32): 2.4e-7 |q'| bounds the distance change
@@ -150,13 +157,20 @@ __global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32
     // per lane and query set: running upper bound (squared), the kDepth smallest
     // lower bounds (sorted) with their pieces, the smallest discarded bound.
     // Lower bounds here leave out the per-query term eq, added at the end.
-    float ubsq[kSets], lbk[kSets][kDepth], disc[kSets];
+    // ush: the query's upper bound shared among its 16 lanes every kShareEvery
+    // tiles, in the form the final candidate test uses; a piece whose lower
+    // bound is above it can never be a candidate and skips the list update.
+    float ubsq[kSets], lbk[kSets][kDepth], disc[kSets], xth[kSets];
     int sk[kSets][kDepth];
     for (int s = 0; s < kSets; ++s) {
         ubsq[s] = INFINITY;
         disc[s] = INFINITY;
+        xth[s] = INFINITY;
         for (int k = 0; k < kDepth; ++k) { lbk[s][k] = INFINITY; sk[s][k] = -1; }
     }
+    const float tol = (float)cv.tol_eff;
+    const float es_max = cv.es_max;
+    int it = 0;
 
     const int nseg = cv.n_seg;
     for (int base = 0; base < nseg; base += kChunk) {
@@ -195,26 +209,47 @@ __global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32
             const float4 x0 = *reinterpret_cast<const float4*>(&s_aux[sl * 8]);      // c, |c|^2
             const float4 x1 = *reinterpret_cast<const float4*>(&s_aux[sl * 8 + 4]);  // kappa A, kappa E, e
             const int gseg = (int)(cv.seg_off + base + sl);
-            for (int s = 0; s < kSets; ++s) {
-                float acc = INFINITY;
+            // the sets' MFMAs are interleaved and each result is reduced one
+            // step later, so that no reduction waits on the MFMA just issued
+            float accs[kSets];
+            {
+                const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+                floatx4 prev[kSets];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    floatx4 z = {0.f, 0.f, 0.f, 0.f};
-                    floatx4 r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][i], B, z, 0, 0, 0);
-                    acc = __builtin_fminf(__builtin_fminf(acc, r[0]), r[1]);
-                    acc = __builtin_fminf(__builtin_fminf(acc, r[2]), r[3]);
+                for (int s = 0; s < kSets; ++s) {
+                    accs[s] = INFINITY;
+                    prev[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][0], B, z, 0, 0, 0);
                 }
-                // epilogue for (query lane>>4 of set s, piece sl)
-                const float qqcc = qq[s] + x0.w;
-                const float d2c = fmaf(m2q[s][0], x0.x, fmaf(m2q[s][1], x0.y, fmaf(m2q[s][2], x0.z, qqcc)));
+#pragma unroll
+                for (int i = 1; i <= 8; ++i) {
+                    floatx4 cur[kSets];
+#pragma unroll
+                    for (int s = 0; s < kSets; ++s)
+                        if (i < 8) cur[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s][i], B, z, 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < kSets; ++s) {
+                        accs[s] = __builtin_fminf(__builtin_fminf(accs[s], prev[s][0]), prev[s][1]);
+                        accs[s] = __builtin_fminf(__builtin_fminf(accs[s], prev[s][2]), prev[s][3]);
+                        if (i < 8) prev[s] = cur[s];
+                    }
+                }
+            }
+            for (int s = 0; s < kSets; ++s) {
+                const float acc = accs[s];
+                // epilogue for (query lane>>4 of set s, piece sl).  The FP32
+                // rounding term 1e-6 (|q'|^2 + |c|^2 + |acc|) is folded into the
+                // stored A and E terms and qq6 (|acc| <= max|q'_i| A + E).
+                const float d2c = fmaf(m2q[s][0], x0.x, fmaf(m2q[s][1], x0.y, fmaf(m2q[s][2], x0.z, qq[s] + x0.w)));
                 const float D = acc + d2c;
-                const float delta = fmaf(qmax[s], x1.x, x1.y) + 1e-6f * (qqcc + fabsf(acc));
+                const float delta = fmaf(qmax[s], x1.x, x1.y) + qq6[s];
                 ubsq[s] = fminf(ubsq[s], D + delta);
+                const float X = D - delta;
+                if (!(X <= xth[s])) continue;  // above the query's bound: never a candidate
                 // raw v_sqrt_f32 (<= 1 ulp): the lower bound is shrunk by 2^-20 relative
-                const float lb = fmaf(__builtin_amdgcn_sqrtf(fmaxf(D - delta, 0.f)), kSqrtLo, -x1.z);
+                const float lb = fmaf(__builtin_amdgcn_sqrtf(fmaxf(X, 0.f)), kSqrtLo, -x1.z);
                 const float l3 = lbk[s][kDepth - 1];
                 disc[s] = fminf(disc[s], fmaxf(lb, l3));  // the value that leaves the list
-                if (lb < l3) {  // rare: insert into the sorted list
+                if (lb < l3) {  // insert into the sorted list
                     float v = lb;
                     int g = gseg;
 #pragma unroll
@@ -227,6 +262,15 @@ __global__ __launch_bounds__(kThreads) void k_screen_bf16(DevGeom G, const int32
                         v = tv;
                         g = tg;
                     }
+                }
+            }
+            if (++it % kShareEvery == 0) {
+                for (int s = 0; s < kSets; ++s) {
+                    float u = ubsq[s];
+                    for (int off = 1; off < 16; off <<= 1) u = fminf(u, __shfl_xor(u, off, 64));
+                    const float w = (__builtin_amdgcn_sqrtf(u) * kSqrtHi + tol + 2.f * eq[s] + es_max) *
+                                     (1.0f / kSqrtLo);
+                    xth[s] = w * w * (1.0f + 0x1p-18f);
                 }
             }
         }
