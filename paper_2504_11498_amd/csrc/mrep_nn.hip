@@ -514,11 +514,28 @@ __device__ __forceinline__ bf16x8 pack8(const floatx4& a, const floatx4& b)
     return r;
 }
 
+// GELU for inference: erf by Abramowitz and Stegun, Handbook of Mathematical
+// Functions, formula 7.1.28 (erf a = 1 - (1 + a1 a + ... + a6 a^6)^-16 for
+// a >= 0, |error| <= 3e-7), so GELU is within 1e-6 absolute of the erf form --
+// far below the BF16 rounding of the next layer's operands.  No exp and one
+// reciprocal, against libm's erf in the training kernels.
+__device__ __forceinline__ float gelu_inf(float z)
+{
+    const float x = z * 0.70710678118654752f;
+    const float a = fabsf(x);
+    const float p = 1.f + a * (0.0705230784f + a * (0.0422820123f + a * (0.0092705272f +
+                    a * (0.0001520143f + a * (0.0002765672f + a * 0.0000430638f)))));
+    const float r = __builtin_amdgcn_rcpf(p);
+    const float r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+    const float h = 0.5f * z * (r8 * r8);  // 0.5 z erfc(a)
+    return x >= 0.f ? z - h : h;
+}
+
 __device__ __forceinline__ floatx4 gelu4(floatx4 z)
 {
     floatx4 h;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) h[i] = gelu(z[i]);
+    for (int i = 0; i < 4; ++i) h[i] = gelu_inf(z[i]);
     return h;
 }
 
@@ -565,6 +582,9 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[kb], acc, 0, 0, 0);
             }
             h[t] = gelu4(acc);
+            // keeps the scheduler from hoisting every output tile's weight loads
+            // (which took all 512 registers and left one wave per SIMD)
+            __builtin_amdgcn_sched_barrier(0);
         }
         // layer 3 (the first rows of the 16-row weight tile are the outputs)
 #pragma unroll
