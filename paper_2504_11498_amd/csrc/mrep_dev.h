@@ -23,6 +23,8 @@ struct DevGeom {
     const double* spant;
     const int32_t* span0;
     const double* coef;
+    const float4* sph;   // piece spheres
+    const float4* csph;  // cluster spheres
     int32_t n_curves;
     int64_t n_seg;
 };
@@ -40,6 +42,8 @@ inline DevGeom dev_view(const Geom& g)
     d.spant = reinterpret_cast<const double*>(g.base + g.L.off_spant);
     d.span0 = reinterpret_cast<const int32_t*>(g.base + g.L.off_span0);
     d.coef = reinterpret_cast<const double*>(g.base + g.L.off_coef);
+    d.sph = reinterpret_cast<const float4*>(g.base + g.L.off_sph);
+    d.csph = reinterpret_cast<const float4*>(g.base + g.L.off_csph);
     d.n_curves = (int32_t)g.L.n_curves;
     d.n_seg = g.L.n_seg;
     return d;

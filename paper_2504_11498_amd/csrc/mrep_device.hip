@@ -595,6 +595,8 @@ int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* s
     HIP_OK(cp(L.off_spant, P.span_t.data(), sizeof(double) * P.span_t.size()));
     HIP_OK(cp(L.off_span0, P.span0.data(), sizeof(int32_t) * P.span0.size()));
     HIP_OK(cp(L.off_coef, P.coef.data(), sizeof(double) * P.coef.size()));
+    HIP_OK(cp(L.off_sph, P.sph.data(), sizeof(float) * P.sph.size()));
+    HIP_OK(cp(L.off_csph, P.csph.data(), sizeof(float) * P.csph.size()));
     // the plan's host vectors are pageable: finish the copies before returning
     HIP_OK(hipStreamSynchronize(st));
     mrep_geom* g = new mrep_geom();

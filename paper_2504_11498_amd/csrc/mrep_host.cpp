@@ -412,6 +412,43 @@ void decompose_curve(int p, int n, const double* P, const double* U, double tol_
 
 inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// sphere of one piece: its FP32 centre (aux) and the largest control-point
+// distance from it plus the deviation bound, rounded up
+void piece_sphere(const float* aux, const float* lcp, double tol_eff, float* out)
+{
+    double r2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        const double x = lcp[3 * i], y = lcp[3 * i + 1], z = lcp[3 * i + 2];
+        r2 = std::max(r2, x * x + y * y + z * z);
+    }
+    out[0] = aux[AUX_CX];
+    out[1] = aux[AUX_CY];
+    out[2] = aux[AUX_CZ];
+    out[3] = nextafterf((float)(sqrt(r2) * (1.0 + 2e-6) + tol_eff * (1.0 + 1e-6)), INFINITY);
+}
+
+// sphere containing the m spheres sph[4k..]: centre at the middle of their
+// centres' box, radius rounded up
+void bounding_sphere(const float* sph, int64_t m, float* out)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = 0; k < m; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], (double)sph[4 * k + a]);
+            hi[a] = std::max(hi[a], (double)sph[4 * k + a]);
+        }
+    float cf[3];
+    for (int a = 0; a < 3; ++a) cf[a] = m > 0 ? (float)(0.5 * (lo[a] + hi[a])) : 0.f;
+    double r = 0.0;
+    for (int64_t k = 0; k < m; ++k) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) d2 += ((double)sph[4 * k + a] - cf[a]) * ((double)sph[4 * k + a] - cf[a]);
+        r = std::max(r, sqrt(d2) + (double)sph[4 * k + 3]);
+    }
+    for (int a = 0; a < 3; ++a) out[a] = cf[a];
+    out[3] = nextafterf((float)(r * (1.0 + 1e-6)), INFINITY);
+}
+
 // Screen and refine tables of one piece.  The centre c = o + c_rel with c_rel
 // rounded to FP32, o the curve origin, so that c is exact in FP64.
 void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* col, float* aux, float* lcp)
@@ -560,10 +597,14 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
     plan.tol_rel = tol_rel;
     plan.max_degree = 0;
     plan.curves.resize((size_t)n_curves);
-    int64_t nseg = 0, nspan = 0, ncoef = 0;
+    int64_t nseg = 0, nspan = 0, ncoef = 0, nclu = 0;
     for (int32_t c = 0; c < n_curves; ++c) {
         const CurveOut& o = outs[(size_t)c];
         DCurve& d = plan.curves[(size_t)c];
+        d.clu_off = nclu;
+        d.n_clu = (int32_t)((o.pieces.size() + kCluPieces - 1) / kCluPieces);
+        d.clu_use = 0;
+        nclu += d.n_clu;
         d.seg_off = nseg;
         d.span_off = nspan;
         d.coef_off = ncoef;
@@ -598,6 +639,8 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
     plan.col.resize((size_t)nseg * kScreenK);
     plan.aux.resize((size_t)nseg * 8);
     plan.lcp.resize((size_t)nseg * 12);
+    plan.sph.resize((size_t)nseg * 4);
+    plan.csph.resize((size_t)nclu * 4);
     std::atomic<int32_t> next2{0};
     auto worker2 = [&]() {
         for (;;) {
@@ -617,8 +660,19 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
                 piece_tables(pc.R, d.origin, tol_eff, &plan.col[(size_t)g * kScreenK], &plan.aux[(size_t)g * 8],
                              &plan.lcp[(size_t)g * 12]);
                 es_max = std::max(es_max, plan.aux[(size_t)g * 8 + AUX_ES]);
+                piece_sphere(&plan.aux[(size_t)g * 8], &plan.lcp[(size_t)g * 12], tol_eff, &plan.sph[(size_t)g * 4]);
             }
             d.es_max = es_max;
+            double rsum = 0.0;
+            for (int32_t k = 0; k < d.n_clu; ++k) {
+                const int64_t a = d.seg_off + (int64_t)k * kCluPieces;
+                const int64_t m = std::min<int64_t>(kCluPieces, d.n_seg - (int64_t)k * kCluPieces);
+                bounding_sphere(&plan.sph[(size_t)a * 4], m, &plan.csph[(size_t)(d.clu_off + k) * 4]);
+                rsum += plan.csph[(size_t)(d.clu_off + k) * 4 + 3];
+            }
+            // clusters pay off when they are small against the curve (a wandering
+            // curve), not when consecutive pieces jump across its whole box
+            d.clu_use = d.n_clu >= 4 && d.n_clu < 65536 && rsum / d.n_clu <= 0.1 * d.diag ? 1 : 0;
             for (int32_t j = 0; j < d.n_span; ++j) {
                 plan.span_t[(size_t)(d.span_off + j) * 2] = o.span_t[(size_t)j * 2];
                 plan.span_t[(size_t)(d.span_off + j) * 2 + 1] = o.span_t[(size_t)j * 2 + 1];
@@ -650,6 +704,9 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
     L.off_spant = off; off = align256(off + 8 * 2 * nspan);
     L.off_span0 = off; off = align256(off + 4 * (nspan + 1));
     L.off_coef = off; off = align256(off + 8 * ncoef);
+    L.n_clu = nclu;
+    L.off_sph = off; off = align256(off + 16 * nseg);
+    L.off_csph = off; off = align256(off + 16 * nclu);
     L.total = off;
     return MREP_OK;
 }

@@ -37,8 +37,13 @@ struct DCurve {
     double tol_user;     // tol_rel * diag: the caller's tolerance (inversion's on-curve test)
     double diag;         // control-point box diagonal
     double origin[3];    // FP32-representable box centre: screen coordinates are relative to it
+    int64_t clu_off;     // first cluster (global): kCluPieces consecutive pieces each
+    int32_t n_clu;
+    int32_t clu_use;     // 1: the clusters are compact enough for the candidate sweep to use them
 };
-static_assert(sizeof(DCurve) == 88, "DCurve layout");
+static_assert(sizeof(DCurve) == 104, "DCurve layout");
+// pieces per cluster of a curve (the last one may hold fewer)
+constexpr int kCluPieces = 32;
 
 // Offsets (bytes) of each table inside the device buffer.
 struct GeomLayout {
@@ -53,6 +58,9 @@ struct GeomLayout {
     int64_t off_spant = 0;   // double[n_span][2]               (t_q, t_q+1)
     int64_t off_span0 = 0;   // int32[n_span + 1]               first piece of each span (global)
     int64_t off_coef = 0;    // double[n_coef]                  exact span power coefficients in local u
+    int64_t n_clu = 0;
+    int64_t off_sph = 0;     // float4[n_seg]                   piece sphere: centre (as aux), radius
+    int64_t off_csph = 0;    // float4[n_clu]                   sphere around each cluster's piece spheres
     int64_t total = 0;
 };
 
@@ -86,6 +94,8 @@ struct Plan {
     std::vector<uint16_t> col;    // 32 per piece
     std::vector<float> aux;       // 8 per piece
     std::vector<float> lcp;       // 12 per piece
+    std::vector<float> sph;       // 4 per piece
+    std::vector<float> csph;      // 4 per cluster
     GeomLayout layout;
 };
 

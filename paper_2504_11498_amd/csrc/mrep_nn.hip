@@ -603,17 +603,26 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
 // Candidates by sphere bounds.  Piece s lies in the sphere of radius r_s
 // (largest control-point distance from its box centre c_s, plus the piece's
 // deviation bound tol_eff) around c_s, so for the query q
-//     |q - c_s| - r_s  <=  dist(q, piece s)  <=  |q - c_s| + r_s.
-// One workgroup per tile of kQueriesPerTile queries of one curve, 8 lanes per
-// query striding over the curve's pieces staged in LDS.  Pass 1: the K
-// smallest lower bounds (ties to the lower index) and UB = min upper bound;
-// pass 2: [lo, hi] = index range of the pieces whose lower bound is at most
-// UB + margin(UB).  Bounds carry a rounding allowance of 1e-6 (|q'| + diag).
+//     |q - c_s| - r_s  <=  dist(q, piece s)  <=  |q - c_s| + r_s,
+// and a cluster of kCluPieces consecutive pieces lies in a sphere around
+// theirs.  One workgroup per tile of kQueriesPerTile queries of one curve, 8
+// lanes per query.  Curves whose clusters are compact (clu_use):
+//   a. a first bound: the best cluster upper bound and the piece upper bounds
+//      of the kK clusters with the smallest lower bounds (clusters staged in
+//      LDS, pieces read from global memory);
+//   b. the clusters whose lower bound reaches it plus the tie margin;
+//   c. over their pieces: UB = the smallest upper bound and the K pieces with
+//      the smallest lower bounds (ties to the lower index);
+//   d. the list of every piece whose lower bound reaches UB + margin(UB).
+// Other curves: the same UB, K nearest and list from two passes over all the
+// curve's piece spheres staged in LDS.  Bounds carry a rounding allowance of 1e-6 (|q'| + diag).  More than
+// kBoxCluCap clusters or kBoxCap pieces: the query takes the full scan.
 // ---------------------------------------------------------------------------
 constexpr int kBoxSub = 8;
 constexpr int kBoxThreads = kQueriesPerTile * kBoxSub;
-constexpr int kBoxChunk = 1024;
-constexpr int kBoxCap = 64;  // listed pieces per query; more: the query goes to the full scan
+constexpr int kBoxChunk = 768;   // cluster or piece spheres staged per round (LDS for 6 workgroups per CU)
+constexpr int kBoxCluCap = 64;   // candidate clusters per query
+constexpr int kBoxCap = 64;      // listed pieces per query; more: the query goes to the full scan
 constexpr int kXcds = 8;
 static_assert(kBoxThreads == 256, "box kernel: 32 queries x 8 lanes");
 
@@ -623,7 +632,7 @@ struct BoxOut {
     ScreenOut so;   // per query: the pieces whose lower bound reaches UB + margin; so.ub = UB
 };
 
-// float -> uint32 with the same order (negative values included)
+// float -> uint32 with the same order (negative values included), and back
 __device__ __forceinline__ uint32_t ord_key(float x)
 {
     const uint32_t b = __float_as_uint(x);
@@ -639,10 +648,46 @@ __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b)
     a = lo;
     b = hi;
 }
+// merge the 8 lanes' sorted lists of kK keys: exchange, keep the smaller half (bitonic)
+__device__ __forceinline__ void merge_keys(uint64_t* key)
+{
+#pragma unroll
+    for (int off = 1; off < kBoxSub; off <<= 1) {
+        uint64_t o[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
+#pragma unroll
+        for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
+        cswap(key[0], key[2]);
+        cswap(key[1], key[3]);
+        cswap(key[0], key[1]);
+        cswap(key[2], key[3]);
+    }
+}
+__device__ __forceinline__ void insert_key(uint64_t* key, uint64_t x)
+{
+    if (x < key[kK - 1]) {
+#pragma unroll
+        for (int k = 0; k < kK; ++k) cswap(key[k], x);
+    }
+}
+__device__ __forceinline__ float min8(float v)
+{
+#pragma unroll
+    for (int off = 1; off < kBoxSub; off <<= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 __device__ __forceinline__ float tie_margin(float d, const DCurve& cv, float tie_rel)
 {
     return 2.f * (float)cv.tol_eff + 4e-6f * (d + (float)cv.diag) + tie_rel * (float)cv.diag;
+}
+
+__device__ __forceinline__ void stage_clusters(const DevGeom& G, const DCurve& cv, int c0, int cn, float4* st)
+{
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += kBoxThreads) st[i] = G.csph[cv.clu_off + c0 + i];
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* __restrict__ tile_off,
@@ -650,7 +695,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                                                      const int32_t* __restrict__ perm, const double* __restrict__ qxyz,
                                                      float tie_rel, BoxOut out)
 {
-    __shared__ float4 s_sph[kBoxChunk];
+    __shared__ float4 s_st[kBoxChunk];
+    __shared__ uint16_t s_clu[kQueriesPerTile][kBoxCluCap];  // a curve using clusters has < 65536
     __shared__ int32_t s_list[kQueriesPerTile][kBoxCap];
     __shared__ int32_t s_base[kQueriesPerTile];
     const int n_tiles = tile_off[G.n_curves];
@@ -676,80 +722,154 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - cv.origin[k]);
     }
     const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)cv.diag);
-    const float tol = (float)(cv.tol_eff * 1.000001);
+    auto dist = [&](const float4& p) {
+        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+        return sqrtf(dx * dx + dy * dy + dz * dz);
+    };
+    float ub = INFINITY;
     uint64_t key[kK];
+    int cnt = 0;  // pieces listed (same value in the query's 8 lanes)
+    if (cv.clu_use) {
+        // a. first bound
 #pragma unroll
-    for (int k = 0; k < kK; ++k) key[k] = ~0ull;
-    float ub = INFINITY, thr = 0.f;
-    int cnt = 0;  // pieces listed so far (same value in the query's 8 lanes)
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int c0 = 0; c0 < cv.n_seg; c0 += kBoxChunk) {
-            const int cn = min(kBoxChunk, cv.n_seg - c0);
-            __syncthreads();
-            for (int i = threadIdx.x; i < cn; i += kBoxThreads) {
-                const int64_t sg = cv.seg_off + c0 + i;
-                const float* lp = G.lcp + sg * 12;
-                const float* ax = G.aux + sg * 8;
-                float r2 = 0.f;
-#pragma unroll
-                for (int p = 0; p < 4; ++p)
-                    r2 = fmaxf(r2, lp[3 * p] * lp[3 * p] + lp[3 * p + 1] * lp[3 * p + 1] + lp[3 * p + 2] * lp[3 * p + 2]);
-                s_sph[i] = make_float4(ax[AUX_CX], ax[AUX_CY], ax[AUX_CZ], sqrtf(r2) * 1.000002f + tol);
-            }
-            __syncthreads();
+        for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+        for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
+            const int cn = min(kBoxChunk, cv.n_clu - c0);
+            stage_clusters(G, cv, c0, cn, s_st);
             if (!active) continue;
-            if (pass == 0) {
-                for (int i = sub; i < cn; i += kBoxSub) {
-                    const float4 p = s_sph[i];
-                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    const float re = p.w + eps;
-                    const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
-                    const float tu = ub - re;
-                    const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
-                    const bool cu = tu > 0.f && d2 < tu * tu;
-                    if (c4 || cu) {
-                        const float d = sqrtf(d2);
-                        ub = fminf(ub, d + re);
-                        uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
+            for (int i = sub; i < cn; i += kBoxSub) {
+                const float4 p = s_st[i];
+                const float d = dist(p);
+                ub = fminf(ub, d + p.w + eps);
+                insert_key(key, ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i));
+            }
+        }
+        merge_keys(key);
+        if (active) {
 #pragma unroll
-                        for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
-                    }
-                }
-            } else {
-                // the 8 lanes of a query run the same trip count: the ballot below sees all of them
-                for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
-                    const int i = i0 + sub;
-                    bool hit = false;
-                    if (i < cn) {
-                        const float4 p = s_sph[i];
-                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                        const float tt = thr + p.w + eps;
-                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
-                    }
-                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
-                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-                    if (hit && pos < kBoxCap) s_list[qs][pos] = c0 + i;
-                    cnt += __popc(grp);
+            for (int m = 0; m < kK; ++m) {
+                if (key[m] == ~0ull) continue;
+                const int k0 = (int)(uint32_t)key[m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
+                for (int k = k0 + sub; k < k1; k += kBoxSub) {
+                    const float4 p = G.sph[cv.seg_off + k];
+                    ub = fminf(ub, dist(p) + p.w + eps);
                 }
             }
         }
-        if (pass == 0) {
-            // merge the 8 lanes' sorted lists: exchange, keep the smaller half (bitonic)
-#pragma unroll
-            for (int off = 1; off < kBoxSub; off <<= 1) {
-                uint64_t o[kK];
-#pragma unroll
-                for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
-#pragma unroll
-                for (int k = 0; k < kK; ++k) key[k] = min(key[k], o[kK - 1 - k]);
-                cswap(key[0], key[2]);
-                cswap(key[1], key[3]);
-                cswap(key[0], key[1]);
-                cswap(key[2], key[3]);
-                ub = fminf(ub, __shfl_xor(ub, off, 64));
+        ub = min8(ub);
+        // b. candidate clusters
+        const float thr0 = ub + tie_margin(ub, cv, tie_rel);
+        int ncl = 0;  // same value in the query's 8 lanes
+        for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
+            const int cn = min(kBoxChunk, cv.n_clu - c0);
+            stage_clusters(G, cv, c0, cn, s_st);
+            if (!active) continue;
+            // the 8 lanes of a query run the same trip count: the ballot below sees all of them
+            for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
+                const int i = i0 + sub;
+                bool hit = false;
+                if (i < cn) {
+                    const float4 p = s_st[i];
+                    hit = dist(p) - p.w - eps <= thr0;
+                }
+                const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                const int pos = ncl + __popc(grp & ((1u << sub) - 1u));
+                if (hit && pos < kBoxCluCap) s_clu[qs][pos] = (uint16_t)(c0 + i);
+                ncl += __popc(grp);
             }
-            thr = ub + tie_margin(ub, cv, tie_rel);
+        }
+        // c. UB and the K nearest-bound pieces over the candidate clusters
+        const bool clus_ok = ncl <= kBoxCluCap;
+#pragma unroll
+        for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+        if (active && clus_ok) {
+            for (int m = 0; m < ncl; ++m) {
+                const int k0 = s_clu[qs][m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
+                for (int k = k0 + sub; k < k1; k += kBoxSub) {
+                    const float4 p = G.sph[cv.seg_off + k];
+                    const float d = dist(p), re = p.w + eps;
+                    ub = fminf(ub, d + re);
+                    insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)k);
+                }
+            }
+        }
+        ub = min8(ub);
+        merge_keys(key);
+        // d. the list
+        const float thr = ub + tie_margin(ub, cv, tie_rel);
+        if (active && clus_ok) {
+            for (int m = 0; m < ncl; ++m) {
+                const int k0 = s_clu[qs][m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
+                for (int i0 = k0; i0 < k1; i0 += kBoxSub) {
+                    const int k = i0 + sub;
+                    bool hit = false;
+                    if (k < k1) {
+                        const float4 p = G.sph[cv.seg_off + k];
+                        hit = dist(p) - p.w - eps <= thr;
+                    }
+                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                    if (hit && pos < kBoxCap) s_list[qs][pos] = k;
+                    cnt += __popc(grp);
+                }
+            }
+        } else if (active) {
+            cnt = kBoxCap + 1;  // too many clusters: the full scan
+        }
+    } else {
+        // one pass over the curve's piece spheres staged in LDS for the bound and
+        // the K nearest, a second one for the list
+#pragma unroll
+        for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+        float thr = 0.f;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c0 = 0; c0 < cv.n_seg; c0 += kBoxChunk) {
+                const int cn = min(kBoxChunk, cv.n_seg - c0);
+                __syncthreads();
+                for (int i = threadIdx.x; i < cn; i += kBoxThreads) s_st[i] = G.sph[cv.seg_off + c0 + i];
+                __syncthreads();
+                if (!active) continue;
+                if (pass == 0) {
+                    for (int i = sub; i < cn; i += kBoxSub) {
+                        const float4 p = s_st[i];
+                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                        const float d2 = dx * dx + dy * dy + dz * dz;
+                        const float re = p.w + eps;
+                        const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
+                        const float tu = ub - re;
+                        const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
+                        const bool cu = tu > 0.f && d2 < tu * tu;
+                        if (c4 || cu) {
+                            const float d = sqrtf(d2);
+                            ub = fminf(ub, d + re);
+                            uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
+#pragma unroll
+                            for (int k = 0; k < kK; ++k) cswap(key[k], x);  // insertion into the sorted list
+                        }
+                    }
+                } else {
+                    // the 8 lanes of a query run the same trip count: the ballot sees all of them
+                    for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
+                        const int i = i0 + sub;
+                        bool hit = false;
+                        if (i < cn) {
+                            const float4 p = s_st[i];
+                            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                            const float tt = thr + p.w + eps;
+                            hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                        }
+                        const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                        const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                        if (hit && pos < kBoxCap) s_list[qs][pos] = c0 + i;
+                        cnt += __popc(grp);
+                    }
+                }
+            }
+            if (pass == 0) {
+                merge_keys(key);
+                ub = min8(ub);
+                thr = ub + tie_margin(ub, cv, tie_rel);
+            }
         }
     }
     // reserve the workgroup's pairs with one atomic
