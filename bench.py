@@ -65,6 +65,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--no-surfaces", action="store_true", help="skip the batched-surfaces workload")
+    ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-strut curves workload")
+    ap.add_argument("--lattice-curves", type=int, default=4096,
+                    help="strut curves in the lattice workload (65536 = the full microstructure configuration, "
+                         "several minutes of host decomposition)")
     ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
     args = ap.parse_args()
     if args.summarize_rocprof:
@@ -171,6 +175,9 @@ def main():
         del geom, ws
         torch.cuda.empty_cache()
         result["surfaces"] = surfaces_bench(args, dev)
+    if not args.no_lattice:
+        torch.cuda.empty_cache()
+        result["lattice"] = lattice_bench(args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(curves, qs, outs, args.cpu_seconds)
     print(json.dumps(result), flush=True)
@@ -246,6 +253,88 @@ def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):
                        **stats, "epochs": 10, "batch": 4096, "lr": 1e-3, "steps": int(len(losses)),
                        "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
                        "prep_s": prep_s, "train_s": train_s}
+    return res
+
+
+def lattice_bench(args, dev):
+    """Lattice struts: random-walk curves (degree U{3..9}, 64..1024 control points, steps N(0, 0.01^2)),
+    256 queries per curve on average in proportion to each curve's cubic pieces, offset as in the batched
+    curves.  Plain (BF16 screen), NN-seeded (curve network trained on held-out struts) and sphere-pruned."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep, seeding
+
+    n_curves = int(args.lattice_curves)
+    curves = gen.curves_lattice_geometry(5, n_curves=n_curves)
+    t0 = time.perf_counter()
+    plan = mrep.decompose_curves(curves, 1e-6)
+    decompose_s = time.perf_counter() - t0
+    n_seg = np.diff(plan.export()["seg_off"])
+    qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
+    geom = plan.upload(dev)
+    cid = torch.from_numpy(qs.curve_id).to(dev)
+    q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
+    n = q.shape[0]
+    opts = mrep.default_opts("bf16", time_stages=True)
+    outs = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
+            torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    steps = max(1, min(args.steps, 5))
+    ws = torch.empty(geom.workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
+
+    def plain():
+        geom.project(q, cid, opts, workspace=ws, out=outs)
+
+    for _ in range(max(1, args.warmup)):
+        plain()
+    ms, stage = _timed(plain, steps)
+    del ws
+    res = {
+        "workload": f"lattice struts: {n_curves} random-walk B-splines (degree 3..9, 64..1024 control points), "
+                    f"{n:,} queries in proportion to cubic pieces",
+        "queries": int(n),
+        "cubic_pieces": int(plan.n_segments),
+        "decompose_s_host": decompose_s,
+        "plain": {"value": n / (ms / 1e3), "unit": "projections/s", "ms_per_step": ms,
+                  "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "refine": float(stage[2])},
+                  "fullscan_frac": float(np.mean((outs[3].cpu().numpy().view(np.uint32) & mrep.F_FULLSCAN) != 0))},
+    }
+    if args.no_seeded:
+        return res
+    # curve network trained on held-out struts
+    t0 = time.perf_counter()
+    tr_curves = gen.curves_lattice_geometry(15, n_curves=max(64, n_curves // 8))
+    tr_plan = mrep.decompose_curves(tr_curves, 1e-6)
+    tr_qs = gen.offset_queries(115, tr_curves, per_curve=256)
+    tr_geom = tr_plan.upload(dev)
+    tr_cid = torch.from_numpy(tr_qs.curve_id).to(dev)
+    tr_q = (tr_geom.eval(tr_cid, torch.from_numpy(tr_qs.t0).to(dev)) + torch.from_numpy(tr_qs.offset).to(dev)).contiguous()
+    x, u, a, stats = seeding.training_pairs(tr_plan, tr_geom, tr_q, tr_cid, seed=0)
+    net = mrep.Network(dev, seed=7)
+    losses = seeding.train(net, x, u, a, epochs=10, batch=4096, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t0
+    del x, u, a, tr_geom
+    so = tuple(torch.empty_like(o) for o in outs)
+    sws = torch.empty(geom.seeded_workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
+    diag = torch.from_numpy(curves.bbox_diag()).to(dev)[cid.long()]
+    for name, nn in (("nn", net), ("sphere_pruned", None)):
+        def step():
+            geom.project_seeded(q, cid, nn, opts, workspace=sws, out=so)
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        ms2, st2 = _timed(step, steps)
+        flags = so[3].cpu().numpy().view(np.uint32)
+        res[name] = {
+            "value": n / (ms2 / 1e3), "unit": "projections/s", "ms_per_step": ms2,
+            "speedup_vs_plain": ms / ms2,
+            "stage_ms": {"group_candidates": float(st2[0]), "network": float(st2[1]),
+                         "seed_certify": float(st2[2]), "fallback": float(st2[3])},
+            "fallback_frac": float(np.mean((flags & mrep.F_NN_FALLBACK) != 0)),
+            "vs_plain_max_dist_rel": float(((so[1] - outs[1]).abs() / diag).max().item()),
+        }
+    res["training"] = {"curves": int(tr_curves.n), **stats, "steps": int(len(losses)),
+                       "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
+                       "seconds": train_s}
     return res
 
 

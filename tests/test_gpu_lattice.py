@@ -1,0 +1,86 @@
+"""GPU parity on lattice-strut curves (random walks of degree 3..9 with 64..1024 control points, queries in
+proportion to each curve's cubic pieces): plain BF16 and FP64 projection, the seeded and sphere-pruned
+projections, against the FP64 oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_11498_amd import gen
+from parity import compare, oracle_pieces
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mrep():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_11498_amd import mrep as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def lattice(mrep):
+    curves = gen.curves_lattice_geometry(55, n_curves=256)
+    _say("[setup] lattice: decomposing 256 strut curves on the host")
+    plan = mrep.decompose_curves(curves, 1e-6)
+    n_seg = np.diff(plan.export()["seg_off"])
+    counts = gen.proportional_counts(n_seg, 256 * 256)
+    qs = gen.offset_queries(155, curves, counts=counts)
+    q = qs.materialise(lambda cid, t: oracle.eval_batch(curves, cid, t))
+    geom = plan.upload()
+    rng = np.random.default_rng(17)
+    sub = np.sort(rng.choice(qs.n, 3000, replace=False))
+    _say(f"[setup] {plan.n_segments} pieces, {qs.n} queries; oracle on a 3000-query sample")
+    ref = oracle.project(curves, qs.curve_id[sub], q[sub])
+    return curves, qs, q, geom, sub, ref, oracle_pieces(curves, 1e-6)
+
+
+def _out(t, d, s, f):
+    torch.cuda.synchronize()
+    return {"t": t.cpu().numpy(), "dist": d.cpu().numpy(), "seg": s.cpu().numpy(), "flags": f.cpu().numpy().view(np.uint32)}
+
+
+def test_lattice_plain_all_queries_sampled(mrep, lattice):
+    curves, qs, q, geom, sub, ref, dec = lattice
+    _say(f"[case] lattice plain bf16, all {qs.n} queries, 3000 sampled")
+    qt = torch.from_numpy(q).cuda()
+    ct = torch.from_numpy(qs.curve_id).cuda()
+    out = _out(*geom.project(qt, ct, mrep.default_opts("bf16")))
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["seg"] >= 0)
+    st = compare(curves, qs.curve_id[sub], q[sub], {k: v[sub] for k, v in out.items()}, ref, dec, label="lattice/bf16")
+    _say(f"[ok] {st} fullscan={np.mean((out['flags'] & mrep.F_FULLSCAN) != 0):.4f}")
+
+
+def test_lattice_fp64_subset(mrep, lattice):
+    curves, qs, q, geom, sub, ref, dec = lattice
+    _say("[case] lattice fp64, 3000-query sample")
+    qt = torch.from_numpy(np.ascontiguousarray(q[sub])).cuda()
+    ct = torch.from_numpy(np.ascontiguousarray(qs.curve_id[sub])).cuda()
+    out = _out(*geom.project(qt, ct, mrep.default_opts("fp64")))
+    st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label="lattice/fp64")
+    _say(f"[ok] {st}")
+
+
+@pytest.mark.parametrize("which", ["seeded", "pruned"])
+def test_lattice_seeded_and_pruned(mrep, lattice, which):
+    """The seeded call with an untrained network (the certificate decides, whatever the network says) and the
+    sphere-pruned call: same answers as the oracle on the sample."""
+    curves, qs, q, geom, sub, ref, dec = lattice
+    _say(f"[case] lattice {which}, 3000-query sample")
+    net = mrep.Network(seed=3) if which == "seeded" else None
+    qt = torch.from_numpy(np.ascontiguousarray(q[sub])).cuda()
+    ct = torch.from_numpy(np.ascontiguousarray(qs.curve_id[sub])).cuda()
+    out = _out(*geom.project_seeded(qt, ct, net, mrep.default_opts("bf16")))
+    st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label=f"lattice/{which}")
+    _say(f"[ok] {st} fallback={np.mean((out['flags'] & mrep.F_NN_FALLBACK) != 0):.4f}")
