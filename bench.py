@@ -169,6 +169,10 @@ def main():
             "per_unit": "64 flop per screened (query, piece, sample): one 16x16x32 BF16 MFMA output element",
         },
     }
+    # the autotuner on this batch (the timed steps above always use the screen)
+    strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
+    result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
+                                    "ms": {"screen": ms_screen, "spheres": ms_spheres}}
     if not args.no_seeded:
         result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
     if not args.no_surfaces:
@@ -298,6 +302,19 @@ def lattice_bench(args, dev):
                   "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "refine": float(stage[2])},
                   "fullscan_frac": float(np.mean((outs[3].cpu().numpy().view(np.uint32) & mrep.F_FULLSCAN) != 0))},
     }
+    # the autotuner's choice between the screen and the sphere strategy, and the tuned call's time
+    strat, ms_screen, ms_spheres, _ = geom.tune(q, cid)
+    topts = mrep.default_opts("bf16", time_stages=True, tuned=True)
+    tws = torch.empty(geom.workspace_bytes(n, topts), dtype=torch.uint8, device=dev)
+
+    def tuned():
+        geom.project(q, cid, topts, workspace=tws, out=outs)
+
+    tuned()
+    ms_t, _ = _timed(tuned, steps)
+    del tws
+    res["tuned"] = {"strategy": ["screen", "spheres"][strat], "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
+                    "value": n / (ms_t / 1e3), "unit": "projections/s", "ms_per_step": ms_t}
     if args.no_seeded:
         return res
     # curve network trained on held-out struts

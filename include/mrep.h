@@ -99,6 +99,12 @@ typedef struct {
 /* mrep_opts.flags: record HIP events around each stage of the call on its
  * stream; read them back with mrep_last_stage_times. */
 #define MREP_OPT_TIME_STAGES 0x1
+/* mrep_opts.flags: mrep_project_curves / mrep_invert_curves in BF16 mode run
+ * the strategy mrep_tune_curves last chose for the geometry (the screen until
+ * then); the workspace must then hold mrep_workspace_bytes with this flag. */
+#define MREP_OPT_TUNED 0x2
+#define MREP_STRATEGY_SCREEN 0  /* BF16 MFMA screen, certified candidates, refine */
+#define MREP_STRATEGY_SPHERES 1 /* sphere lists (span clusters where compact), refine every listed piece */
 #define MREP_N_STAGES 4 /* most stages any call records (see mrep_last_stage_times) */
 
 /* ---------------------------------------------------------------------- */
@@ -192,6 +198,19 @@ int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t
  * Out-of-range ids give NaN.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
 int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t,
                          double* xyz_out, void* stream);
+
+/* Autotuner (BF16 mode): projects the batch with each strategy (one untimed
+ * and two timed runs each, HIP events on `stream`), keeps the faster one for
+ * this geometry (used by calls with MREP_OPT_TUNED), and leaves its answers in
+ * the outputs.  Both strategies return the certified global minimum; they
+ * differ in speed, by how compact the curves are against their boxes.
+ * workspace: mrep_workspace_bytes with MREP_OPT_TUNED.  strategy_out (HOST,
+ * nullable): the choice; ms_out (HOST double[2], nullable): per-call times of
+ * the screen and sphere strategies.  Synchronous.  Errors: as
+ * mrep_project_curves. */
+int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                         const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
+                         int32_t* seg_out, uint32_t* flags_out, int32_t* strategy_out, double* ms_out, void* stream);
 
 /* Durations in milliseconds of the stages of the last call on the calling
  * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 3

@@ -131,6 +131,15 @@ struct mrep_plan {
 };
 struct mrep_geom {
     int kind = MREP_GEOM_CURVES;
+    int strategy = MREP_STRATEGY_SCREEN;  // chosen by mrep_tune_curves
     mrep::Geom g;
     mrep::SurfGeom sg;
 };
+
+namespace mrep {
+// the seeded / sphere-pruned curve projection (nn == NULL: sphere-pruned)
+int seeded_core(const char* fn, const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
+                double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream, int invert);
+int64_t seeded_ws_bytes(const mrep_geom* geom, int64_t n);
+}  // namespace mrep

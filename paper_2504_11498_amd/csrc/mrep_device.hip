@@ -697,6 +697,7 @@ int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* 
     int rc = check_opts(opts);
     if (rc) return rc;
     *bytes = work_layout(geom->g.L.n_curves, n, opts->max_candidates, nullptr, nullptr);
+    if (opts->flags & MREP_OPT_TUNED) *bytes = std::max<int64_t>(*bytes, seeded_ws_bytes(geom, n));
     return MREP_OK;
 }
 
@@ -771,7 +772,7 @@ int64_t mrep::project_ws_bytes(int64_t n_curves, int64_t n, int kc) { return wor
 
 static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
-                           int32_t* seg_out, uint32_t* flags_out, void* stream, int invert)
+                           int32_t* seg_out, uint32_t* flags_out, void* stream, int invert, int strategy = -1)
 {
     if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
         set_error("mrep_project_curves: null or surface geometry, or negative n");
@@ -779,6 +780,10 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
     }
     int rc = check_opts(opts);
     if (rc) return rc;
+    if (strategy < 0) strategy = (opts->flags & MREP_OPT_TUNED) ? geom->strategy : MREP_STRATEGY_SCREEN;
+    if (strategy == MREP_STRATEGY_SPHERES && opts->precision == MREP_PREC_BF16)
+        return seeded_core(invert ? "mrep_invert_curves" : "mrep_project_curves", geom, nullptr, opts, n, curve_id,
+                           q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out, stream, invert);
     if (n == 0) return MREP_OK;
     // the screen's pair counter is 32-bit: n * max_candidates must stay below 2^31
     if (n * (int64_t)opts->max_candidates >= (int64_t)INT32_MAX) {
@@ -828,6 +833,63 @@ int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t
 {
     return run_project(geom, opts, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
                        stream, 1);
+}
+
+int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                         const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
+                         int32_t* seg_out, uint32_t* flags_out, int32_t* strategy_out, double* ms_out, void* stream)
+{
+    if (!geom || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_tune_curves: null or surface geometry");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (opts->precision != MREP_PREC_BF16) {
+        set_error("mrep_tune_curves: the strategies differ in the BF16 mode only");
+        return MREP_E_INVALID_ARG;
+    }
+    int64_t need = 0;
+    mrep_opts o2 = *opts;
+    o2.flags = (opts->flags | MREP_OPT_TUNED) & ~MREP_OPT_TIME_STAGES;
+    if ((rc = mrep_workspace_bytes(geom, n, &o2, &need))) return rc;
+    if (ws_bytes < need) {
+        set_error("mrep_tune_curves: workspace smaller than mrep_workspace_bytes with MREP_OPT_TUNED");
+        return MREP_E_SMALL_BUFFER;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    double ms[2] = {0.0, 0.0};
+    for (int strat = 0; strat < 2 && rc == MREP_OK; ++strat) {
+        for (int it = 0; it < 3 && rc == MREP_OK; ++it) {
+            if (it == 1) rc = hipEventRecord(e0, st) == hipSuccess ? MREP_OK : MREP_E_HIP;
+            if (rc == MREP_OK)
+                rc = run_project(geom, &o2, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out,
+                                 flags_out, stream, 0, strat);
+        }
+        float t = 0.f;
+        if (rc == MREP_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&t, e0, e1) != hipSuccess)) {
+            set_error("mrep_tune_curves: event timing failed");
+            rc = MREP_E_HIP;
+        }
+        ms[strat] = 0.5 * (double)t;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    geom->strategy = ms[MREP_STRATEGY_SPHERES] < ms[MREP_STRATEGY_SCREEN] ? MREP_STRATEGY_SPHERES : MREP_STRATEGY_SCREEN;
+    // leave the chosen strategy's answers in the outputs
+    if (geom->strategy == MREP_STRATEGY_SCREEN &&
+        (rc = run_project(geom, &o2, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
+                          stream, 0, MREP_STRATEGY_SCREEN)))
+        return rc;
+    HIP_OK(hipStreamSynchronize(st));
+    if (strategy_out) *strategy_out = geom->strategy;
+    if (ms_out) { ms_out[0] = ms[0]; ms_out[1] = ms[1]; }
+    return MREP_OK;
 }
 
 int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t, double* xyz_out,

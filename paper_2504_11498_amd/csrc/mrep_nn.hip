@@ -1524,41 +1524,58 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
                                    const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
                                    double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream)
 {
+    return seeded_core("mrep_project_curves_seeded", geom, nn, opts, n, curve_id, q_xyz, workspace, ws_bytes, t_out,
+                       dist_out, seg_out, flags_out, stream, 0);
+}
+
+}  // extern "C"
+
+int64_t mrep::seeded_ws_bytes(const mrep_geom* geom, int64_t n)
+{
+    return seed_layout(geom->g.L.n_curves, n, nullptr, nullptr);
+}
+
+int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
+                      const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes,
+                      double* t_out, double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream,
+                      int invert)
+{
+    const std::string fn(fn_);
     if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
-        set_error("mrep_project_curves_seeded: null or surface geometry, or negative n");
+        set_error(fn + ": null or surface geometry, or negative n");
         return MREP_E_INVALID_ARG;
     }
     if (nn && nn->kind != MREP_NN_CURVE) {
-        set_error("mrep_project_curves_seeded: the network is not of kind MREP_NN_CURVE");
+        set_error(fn + ": the network is not of kind MREP_NN_CURVE");
         return MREP_E_INVALID_ARG;
     }
     int rc = check_opts(opts);
     if (rc) return rc;
     if (opts->precision != MREP_PREC_BF16) {
-        set_error("mrep_project_curves_seeded: the seeded path runs in the BF16 mode (FP32 refine)");
+        set_error(fn + ": the seeded path runs in the BF16 mode (FP32 refine)");
         return MREP_E_INVALID_ARG;
     }
     if (n == 0) return MREP_OK;
     if (n * (int64_t)std::max(opts->max_candidates, kK) >= (int64_t)INT32_MAX) {
-        set_error("mrep_project_curves_seeded: n * max(max_candidates, 4) must be < 2^31");
+        set_error(fn + ": n * max(max_candidates, 4) must be < 2^31");
         return MREP_E_INVALID_ARG;
     }
     if (!curve_id || !q_xyz || !workspace || !t_out || !dist_out || !seg_out || !flags_out) {
-        set_error("mrep_project_curves_seeded: null pointer");
+        set_error(fn + ": null pointer");
         return MREP_E_INVALID_ARG;
     }
     const int64_t nc = geom->g.L.n_curves;
     if (nc == 0) {
-        set_error("mrep_project_curves_seeded: geometry has no curves");
+        set_error(fn + ": geometry has no curves");
         return MREP_E_INVALID_ARG;
     }
     SeedWork w;
     if (ws_bytes < seed_layout(nc, n, (char*)workspace, &w)) {
-        set_error("mrep_project_curves_seeded: workspace smaller than mrep_seeded_workspace_bytes");
+        set_error(fn + ": workspace smaller than mrep_seeded_workspace_bytes");
         return MREP_E_SMALL_BUFFER;
     }
     if (((uintptr_t)workspace & 255) != 0) {
-        set_error("mrep_project_curves_seeded: workspace not 256-byte aligned");
+        set_error(fn + ": workspace not 256-byte aligned");
         return MREP_E_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -1583,17 +1600,15 @@ int32_t mrep_project_curves_seeded(const mrep_geom* geom, const mrep_nn* nn, con
     if (nn) {
         hipLaunchKernelGGL(k_decide, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
                            (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
-                           (int32_t)0, w.done, o);
+                           (int32_t)invert, w.done, o);
         NN_HIP(hipGetLastError());
     }
     if (timed && (rc = stage_mark(3, st))) return rc;
     NN_HIP(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.box.so, w.pair_res, nn ? w.done : nullptr,
-                         nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, 0, w.ovf_list, w.ovf_count, o, st));
+                         nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, invert, w.ovf_list, w.ovf_count, o, st));
     if (timed) {
         if ((rc = stage_mark(4, st))) return rc;
         stage_end(4);
     }
     return MREP_OK;
 }
-
-}  // extern "C"

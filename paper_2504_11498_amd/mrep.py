@@ -27,7 +27,8 @@ OK, E_INVALID_ARG, E_BAD_DEGREE, E_BAD_KNOTS, E_TOL, E_SMALL_BUFFER, E_HIP, E_NO
 F_POLISHED, F_NEAR_TIE, F_ILL_COND, F_ENDPOINT, F_OFFCURVE, F_FULLSCAN, F_BAD_ID = 1, 2, 4, 8, 16, 32, 64
 F_NN_FALLBACK = 128
 PREC_FP64, PREC_BF16 = 0, 3
-OPT_TIME_STAGES = 1
+OPT_TIME_STAGES, OPT_TUNED = 1, 2
+STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
 N_STAGES = 4
 MAX_DEGREE = 15
 NN_CURVE, NN_SURFACE = 0, 1
@@ -68,6 +69,8 @@ _ws_bytes = _sig("mrep_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POI
 _project = _sig("mrep_project_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
+_tune = _sig("mrep_tune_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+             C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp)
 _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
 _subdiv = _sig("mrep_subdivision_matrix", _i32, _i32, _dbl, _pd)
 _gram = _sig("mrep_gram_matrix", _i32, _i32, _i32, _pd)
@@ -113,7 +116,8 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_seeded_workspace_bytes", "mrep_nn_features", "mrep_project_curves_seeded",
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
-           "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded"]
+           "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
+           "mrep_tune_curves"]
 
 
 class MrepError(RuntimeError):
@@ -243,10 +247,11 @@ def decompose_surfaces(surfs, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan
 
 
 def default_opts(precision: str | int = "bf16", max_candidates: int = 16, tie_rel: float = 2e-6,
-                 time_stages: bool = False) -> Opts:
+                 time_stages: bool = False, tuned: bool = False) -> Opts:
+    """tuned: curve projections run the strategy Geometry.tune() chose (BF16 mode)."""
     o = Opts()
     _check(_opts_default(C.byref(o)), "mrep_opts_default")
-    o.flags = OPT_TIME_STAGES if time_stages else 0
+    o.flags = (OPT_TIME_STAGES if time_stages else 0) | (OPT_TUNED if tuned else 0)
     if isinstance(precision, str):
         precision = {"fp64": PREC_FP64, "bf16": PREC_BF16}[precision]
     o.precision = int(precision)
@@ -337,6 +342,29 @@ class Geometry:
                   int(ws.numel()), _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
                   _vp(stream)), "mrep_invert_curves" if invert else "mrep_project_curves")
         return t, d, s, f
+
+    def tune(self, q, curve_id, opts: Opts | None = None, out=None):
+        """Autotune the curve strategy on this batch (mrep_tune_curves): returns (strategy, ms_screen,
+        ms_spheres, (t, dist, seg, flags)); later calls with default_opts(tuned=True) use the choice."""
+        import torch
+
+        if opts is None:
+            opts = default_opts("bf16")
+        n = q.shape[0]
+        o2 = Opts.from_buffer_copy(opts)
+        o2.flags |= OPT_TUNED
+        ws = self._workspace(n, o2, None)
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float64, device=q.device), torch.empty(n, dtype=torch.float64, device=q.device),
+                   torch.empty(n, dtype=torch.int32, device=q.device), torch.empty(n, dtype=torch.int32, device=q.device))
+        t, d, s, f = out
+        strat = C.c_int32()
+        ms = (C.c_double * 2)()
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_tune(self._h, C.byref(opts), int(n), _vp(curve_id.data_ptr()), _vp(q.data_ptr()), _vp(ws.data_ptr()),
+                     int(ws.numel()), _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
+                     C.byref(strat), ms, _vp(stream)), "mrep_tune_curves")
+        return int(strat.value), float(ms[0]), float(ms[1]), out
 
     def seeded_workspace_bytes(self, n: int, opts: Opts) -> int:
         b = C.c_int64()

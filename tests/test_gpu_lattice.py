@@ -84,3 +84,33 @@ def test_lattice_seeded_and_pruned(mrep, lattice, which):
     out = _out(*geom.project_seeded(qt, ct, net, mrep.default_opts("bf16")))
     st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label=f"lattice/{which}")
     _say(f"[ok] {st} fallback={np.mean((out['flags'] & mrep.F_NN_FALLBACK) != 0):.4f}")
+
+
+def test_lattice_autotuner(mrep, lattice):
+    """mrep_tune_curves times both strategies on the batch; on these compact struts the sphere strategy is the
+    faster one.  The tuned projection and inversion then run it, with the oracle's answers on the sample."""
+    curves, qs, q, geom, sub, ref, dec = lattice
+    _say("[case] lattice autotuner")
+    qt = torch.from_numpy(q).cuda()
+    ct = torch.from_numpy(qs.curve_id).cuda()
+    strat, ms_screen, ms_spheres, outs = geom.tune(qt, ct)
+    _say(f"[info] strategy {strat}, screen {ms_screen:.3f} ms, spheres {ms_spheres:.3f} ms")
+    assert strat == mrep.STRATEGY_SPHERES and ms_spheres < ms_screen
+    tuned = _out(*outs)
+    compare(curves, qs.curve_id[sub], q[sub], {k: v[sub] for k, v in tuned.items()}, ref, dec, label="lattice/tuned")
+    again = _out(*geom.project(qt, ct, mrep.default_opts("bf16", tuned=True)))
+    for k in ("t", "dist", "seg", "flags"):
+        np.testing.assert_array_equal(again[k], tuned[k])
+    # inversion through the tuned strategy: on-curve points, and offset points reported off the curve
+    rng = np.random.default_rng(4)
+    cid = rng.integers(0, curves.n, 4000).astype(np.int32)
+    t0 = rng.uniform(0, 1, 4000)
+    pts = oracle.eval_batch(curves, cid, t0)
+    diag = curves.bbox_diag()[cid]
+    inv = _out(*geom.project(torch.from_numpy(pts).cuda(), torch.from_numpy(cid).cuda(),
+                             mrep.default_opts("bf16", tuned=True), invert=True))
+    assert np.all(inv["dist"] <= 1e-6 * diag) and not np.any(inv["flags"] & mrep.F_OFFCURVE)
+    off = pts + rng.normal(size=pts.shape) * (0.01 * diag)[:, None]
+    inv2 = _out(*geom.project(torch.from_numpy(off).cuda(), torch.from_numpy(cid).cuda(),
+                              mrep.default_opts("bf16", tuned=True), invert=True))
+    assert np.all(((inv2["flags"] & mrep.F_OFFCURVE) != 0) == (inv2["dist"] > 1e-6 * diag))

@@ -200,6 +200,8 @@ def test_seeding_network_sizes_and_host_errors():
     assert mrep._project_s_seeded(None, None, None, 10, None, None, None, 0, None, None, None, None,
                                   None) == mrep.E_INVALID_ARG
     assert mrep._nn_surf_features(None, 10, None, None, None, None, None, 0, None) == mrep.E_INVALID_ARG
+    assert mrep._tune(None, None, 10, None, None, None, 0, None, None, None, None, None, None,
+                      None) == mrep.E_INVALID_ARG
 
 
 # --------------------------------------------------------------------------- surfaces
