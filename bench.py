@@ -173,6 +173,7 @@ def main():
     strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
     result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
                                     "ms": {"screen": ms_screen, "spheres": ms_spheres}}
+    result["config"]["graph_small_batches"] = graph_small_batches(geom, q, cid)
     if not args.no_seeded:
         result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
     if not args.no_surfaces:
@@ -202,6 +203,56 @@ def _timed(fn, steps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps, stage / steps
+
+
+def graph_small_batches(geom, q, cid, batch: int = 4096, calls: int = 200):
+    """Small batches are launch-bound: per-call time of `calls` projections of `batch` queries, eager and as
+    replays of one captured HIP graph (new queries copied into its input buffer before each replay)."""
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    dev = q.device
+    opts = mrep.default_opts("bf16")
+    qb, cb = q[:batch].clone(), cid[:batch].clone()
+    ws = torch.empty(geom.workspace_bytes(batch, opts), dtype=torch.uint8, device=dev)
+    outs = (torch.empty(batch, dtype=torch.float64, device=dev), torch.empty(batch, dtype=torch.float64, device=dev),
+            torch.empty(batch, dtype=torch.int32, device=dev), torch.empty(batch, dtype=torch.int32, device=dev))
+    src = [(q[i * batch:(i + 1) * batch], cid[i * batch:(i + 1) * batch]) for i in range(8)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        geom.project(qb, cb, opts, workspace=ws, out=outs)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        geom.project(qb, cb, opts, workspace=ws, out=outs)
+
+    def eager():
+        for i in range(calls):
+            qi, ci = src[i % 8]
+            qb.copy_(qi)
+            cb.copy_(ci)
+            geom.project(qb, cb, opts, workspace=ws, out=outs)
+
+    def replay():
+        for i in range(calls):
+            qi, ci = src[i % 8]
+            qb.copy_(qi)
+            cb.copy_(ci)
+            g.replay()
+
+    res = {"batch": batch, "calls": calls}
+    for name, fn in (("eager", eager), ("graph", replay)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        res[name + "_us_per_call"] = (time.perf_counter() - t0) / calls * 1e6
+    res["graph_projections_per_s"] = batch / (res["graph_us_per_call"] / 1e6)
+    return res
 
 
 def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):

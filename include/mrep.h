@@ -212,6 +212,10 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
                          const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
                          int32_t* seg_out, uint32_t* flags_out, int32_t* strategy_out, double* ms_out, void* stream);
 
+/* Set the strategy of calls with MREP_OPT_TUNED directly (MREP_STRATEGY_*),
+ * for a caller that knows its workload.  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_set_curve_strategy(mrep_geom* geom, int32_t strategy);
+
 /* Durations in milliseconds of the stages of the last call on the calling
  * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 3
  * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine/polish/write.

@@ -892,6 +892,17 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
     return MREP_OK;
 }
 
+int32_t mrep_set_curve_strategy(mrep_geom* geom, int32_t strategy)
+{
+    if (!geom || geom->kind != MREP_GEOM_CURVES ||
+        (strategy != MREP_STRATEGY_SCREEN && strategy != MREP_STRATEGY_SPHERES)) {
+        set_error("mrep_set_curve_strategy: null or surface geometry, or unknown strategy");
+        return MREP_E_INVALID_ARG;
+    }
+    geom->strategy = strategy;
+    return MREP_OK;
+}
+
 int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t, double* xyz_out,
                          void* stream)
 {

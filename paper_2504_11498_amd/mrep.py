@@ -69,6 +69,7 @@ _ws_bytes = _sig("mrep_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POI
 _project = _sig("mrep_project_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
+_set_strategy = _sig("mrep_set_curve_strategy", _i32, _vp, _i32)
 _tune = _sig("mrep_tune_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
              C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp)
 _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
@@ -117,7 +118,7 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
-           "mrep_tune_curves"]
+           "mrep_tune_curves", "mrep_set_curve_strategy"]
 
 
 class MrepError(RuntimeError):
@@ -365,6 +366,10 @@ class Geometry:
                      int(ws.numel()), _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
                      C.byref(strat), ms, _vp(stream)), "mrep_tune_curves")
         return int(strat.value), float(ms[0]), float(ms[1]), out
+
+    def set_strategy(self, strategy: int):
+        """The strategy of calls with default_opts(tuned=True): STRATEGY_SCREEN or STRATEGY_SPHERES."""
+        _check(_set_strategy(self._h, int(strategy)), "mrep_set_curve_strategy")
 
     def seeded_workspace_bytes(self, n: int, opts: Opts) -> int:
         b = C.c_int64()

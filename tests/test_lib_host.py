@@ -202,6 +202,7 @@ def test_seeding_network_sizes_and_host_errors():
     assert mrep._nn_surf_features(None, 10, None, None, None, None, None, 0, None) == mrep.E_INVALID_ARG
     assert mrep._tune(None, None, 10, None, None, None, 0, None, None, None, None, None, None,
                       None) == mrep.E_INVALID_ARG
+    assert mrep._set_strategy(None, 0) == mrep.E_INVALID_ARG
 
 
 # --------------------------------------------------------------------------- surfaces
