@@ -66,13 +66,28 @@ def main():
     ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--no-surfaces", action="store_true", help="skip the batched-surfaces workload")
     ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-strut curves workload")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the autotuner and small-batch graph measurements on the batched curves (so that a "
+                         "kernel trace of the run holds the timed screen launches only)")
     ap.add_argument("--lattice-curves", type=int, default=4096,
                     help="strut curves in the lattice workload (65536 = the full microstructure configuration, "
                          "several minutes of host decomposition)")
     ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run three 512 MiB device-to-device copies and exit (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         summarize_rocprof(args.summarize_rocprof)
+        return
+    if args.calibrate_copy:
+        import torch
+
+        x = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copied 3 x 512 MiB", flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -169,11 +184,12 @@ def main():
             "per_unit": "64 flop per screened (query, piece, sample): one 16x16x32 BF16 MFMA output element",
         },
     }
-    # the autotuner on this batch (the timed steps above always use the screen)
-    strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
-    result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
-                                    "ms": {"screen": ms_screen, "spheres": ms_spheres}}
-    result["config"]["graph_small_batches"] = graph_small_batches(geom, q, cid)
+    if not args.no_extras:
+        # the autotuner on this batch (the timed steps above always use the screen)
+        strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
+        result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
+                                        "ms": {"screen": ms_screen, "spheres": ms_spheres}}
+        result["config"]["graph_small_batches"] = graph_small_batches(geom, q, cid)
     if not args.no_seeded:
         result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
     if not args.no_surfaces:
