@@ -91,7 +91,7 @@ typedef struct {
 typedef struct {
     int32_t struct_size;
     int32_t precision;      /* MREP_PREC_* */
-    int32_t max_candidates; /* screen candidates kept per query (1..16); overflow -> full scan */
+    int32_t max_candidates; /* screen candidates kept per query (1..48, default 32); overflow -> full scan */
     int32_t flags;          /* MREP_OPT_* bits */
     double tie_rel;         /* near-tie margin relative to the curve's box diagonal (default 2e-6) */
 } mrep_opts;

@@ -59,14 +59,23 @@ struct ScreenOut {
     int32_t* pair_j;      // [cap] sorted query position of pair p
     int32_t* pair_count;  // pairs reserved so far (zero before the screen)
     int64_t pair_cap;     // capacity of the pair arrays; beyond it a query overflows
-    float* ub;            // [n] the certified upper bound of query j (diagnostic)
+    float* ub;            // [n] a certified upper bound of query j's distance (the full scan starts from it)
 };
 
 // Launch the BF16 MFMA screen (mrep_screen.hip): one workgroup per tile of
-// kQueriesPerTile queries of one curve; grid = n_curves + ceil(n / tile).
-hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int32_t* tile_off, const int32_t* q_off,
-                              const int32_t* perm, const double* qxyz, int32_t kc, const ScreenOut& out,
-                              hipStream_t st);
+// kQueriesPerTile queries of one curve, workgroup b taking tile_map[b];
+// grid = screen_grid(n_curves, n).
+hipError_t launch_screen_bf16(const DevGeom& G, int64_t grid, const int4* tile_map, const int32_t* perm,
+                              const double* qxyz, int32_t kc, const ScreenOut& out, hipStream_t st);
+// workgroup slots of a tiled launch over n queries in n_groups groups: an upper
+// bound of the tile count plus room for the per-XCD rounding
+inline int64_t screen_grid(int64_t n_groups, int64_t n)
+{
+    return n_groups + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcdCount;
+}
+// k_tile_map: slot -> {group, first sorted query, end of the group's queries, tile}
+hipError_t launch_tile_map(const int32_t* tile_off, const int32_t* q_off, int64_t n_groups, int64_t grid,
+                           int4* map, hipStream_t st);
 
 // Output arrays of a projection call (indexed by the caller's query index).
 struct Outs {

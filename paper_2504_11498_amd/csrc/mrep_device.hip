@@ -57,6 +57,7 @@ struct Work {
     int32_t* hist;        // n_curves + 1: per-curve counts / scatter cursors, then the overflow count
     int32_t* q_off;       // n_curves + 1
     int32_t* tile_off;    // n_curves + 1
+    int4* tile_map;       // screen_grid(n_curves, n): workgroup slot -> {curve, first query, end, tile}
     int32_t* perm;        // n: sorted position -> query
     int32_t* ovf_list;    // n: sorted positions whose candidate list overflowed
     int32_t* ovf_count;   // = hist + n_curves
@@ -106,6 +107,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
     int64_t o_hist = take(4 * (n_curves + 2));
     int64_t o_qoff = take(4 * (n_curves + 1));
     int64_t o_toff = take(4 * (n_curves + 1));
+    int64_t o_tmap = take(16 * screen_grid(n_curves, n));
     int64_t o_perm = take(4 * n);
     int64_t o_ovf = take(4 * n);
     int64_t o_candn = take(4 * n);
@@ -118,6 +120,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
         w->hist = reinterpret_cast<int32_t*>(base + o_hist);
         w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
         w->tile_off = reinterpret_cast<int32_t*>(base + o_toff);
+        w->tile_map = reinterpret_cast<int4*>(base + o_tmap);
         w->perm = reinterpret_cast<int32_t*>(base + o_perm);
         w->ovf_list = reinterpret_cast<int32_t*>(base + o_ovf);
         w->ovf_count = w->hist + n_curves;
@@ -242,6 +245,41 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cid
 }
 
 
+// Workgroup slot -> tile of the grouped queries.  Tiles are dealt to the 8
+// XCDs in contiguous ranges (slot b runs on XCD b % 8 and takes tile
+// (b % 8) * per + b / 8), so the tiles of one group share an L2; each entry is
+// {group, first sorted query of the tile, end of the group's queries, tile}, or
+// group -1 for a slot without a tile.
+__global__ __launch_bounds__(256) void k_tile_map(const int32_t* __restrict__ tile_off,
+                                                  const int32_t* __restrict__ q_off, int32_t n_groups, int64_t grid,
+                                                  int4* __restrict__ map)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= grid) return;
+    const int n_tiles = tile_off[n_groups];
+    const int per = (n_tiles + kXcdCount - 1) / kXcdCount;
+    const int slot = (int)(b / kXcdCount);
+    const int tile = (int)(b % kXcdCount) * per + slot;
+    int4 r = make_int4(-1, 0, 0, 0);
+    if (slot < per && tile < n_tiles) {
+        int lo = 0, hi = n_groups;  // tile_off[lo] <= tile < tile_off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+        }
+        r = make_int4(lo, q_off[lo] + (tile - tile_off[lo]) * kQueriesPerTile, q_off[lo + 1], tile);
+    }
+    map[b] = r;
+}
+
+hipError_t mrep::launch_tile_map(const int32_t* tile_off, const int32_t* q_off, int64_t n_groups, int64_t grid,
+                                 int4* map, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tile_map, dim3((unsigned)((grid + 255) / 256)), dim3(256), 0, st, tile_off, q_off,
+                       (int32_t)n_groups, grid, map);
+    return hipGetLastError();
+}
+
 // One thread per (query, candidate piece) pair reserved by the screen: the
 // certified minimum over the piece in the refine precision.  Persistent grid.
 // done (nullable): per sorted query, nonzero when the query is already decided.
@@ -339,8 +377,8 @@ __global__ __launch_bounds__(256) void k_fullscan(DevGeom G, const int32_t* __re
                                                   const int32_t* __restrict__ q_off,
                                                   const int32_t* __restrict__ perm,
                                                   const int32_t* __restrict__ list,
-                                                  const int32_t* __restrict__ count, uint32_t flag_in,
-                                                  double tie_rel, int32_t invert, Outs o)
+                                                  const int32_t* __restrict__ count, const float* __restrict__ ub_in,
+                                                  uint32_t flag_in, double tie_rel, int32_t invert, Outs o)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -354,14 +392,40 @@ __global__ __launch_bounds__(256) void k_fullscan(DevGeom G, const int32_t* __re
         const DCurve cv = G.curves[cid[qi]];
         double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         const int64_t s_end = cv.seg_off + cv.n_seg;
-        double ub = INFINITY;
+        // distance from q to the centre of piece s's sphere (which holds the
+        // exact curve over the piece), with its radius
+        auto sph = [&](int64_t s, double& r) {
+            const float4 p = G.sph[s];
+            const double dx = q[0] - (cv.origin[0] + (double)p.x), dy = q[1] - (cv.origin[1] + (double)p.y),
+                         dz = q[2] - (cv.origin[2] + (double)p.z);
+            r = (double)p.w;
+            return sqrt(dx * dx + dy * dy + dz * dz);
+        };
+        // a piece whose sphere lies beyond ub + margin can be neither the
+        // minimum nor a runner-up within the tie margin of the finish
+        auto margin = [&](double d) { return 2.0 * cv.tol_eff + 4e-6 * (d + cv.diag) + tie_rel * cv.diag; };
+        // upper bound: the caller's (a certified bound from the screen or the
+        // sphere listing), then the spheres', then the sampled minima
+        double ub = ub_in ? (double)ub_in[j] : INFINITY;
         for (int64_t s = cv.seg_off + lane; s < s_end; s += 64) {
+            double r;
+            const double d = sph(s, r);
+            ub = fmin(ub, (d + r) * (1.0 + 1e-12));
+        }
+        for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off, 64));
+        double lim = ub + margin(ub);
+        for (int64_t s = cv.seg_off + lane; s < s_end; s += 64) {
+            double r;
+            if (sph(s, r) - r > lim) continue;
             double m = (double)piece_sample_min<T>(G, cv, s, q);
             ub = fmin(ub, sqrt(m * (1.0 + rel)) + cv.tol_eff);
         }
         for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off, 64));
+        lim = ub + margin(ub);
         Cand b1 = empty_cand(cv), b2 = b1;
         for (int64_t s = cv.seg_off + lane; s < s_end; s += 64) {
+            double r;
+            if (sph(s, r) - r > lim) continue;
             double m = (double)piece_sample_min<T>(G, cv, s, q);
             double lb = sqrt(fmax(m * (1.0 - rel), 0.0)) - (double)G.aux[s * 8 + AUX_ES] * 1.001;
             if (lb <= ub) consider<T>(G, cv, s, q, b1, b2);
@@ -657,7 +721,7 @@ int32_t mrep_opts_default(mrep_opts* o)
     }
     o->struct_size = (int32_t)sizeof(mrep_opts);
     o->precision = MREP_PREC_BF16;
-    o->max_candidates = 16;
+    o->max_candidates = 32;
     o->flags = 0;
     o->tie_rel = 2e-6;
     return MREP_OK;
@@ -676,7 +740,7 @@ int mrep::check_opts(const mrep_opts* o)
         return MREP_E_INVALID_ARG;
     }
     if (o->max_candidates < 1 || o->max_candidates > kMaxCand) {
-        set_error("mrep_opts: max_candidates out of range 1..16");
+        set_error("mrep_opts: max_candidates out of range 1..48");
         return MREP_E_INVALID_ARG;
     }
     if (!(o->tie_rel >= 0.0)) {
@@ -730,9 +794,9 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     HIP_OK(launch_grouping(nc, n, n_dev, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
     if (timed && (rc = stage_mark(stage0 + 1, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
-        // upper bound of the tile count, plus room for the per-XCD rounding
-        const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + 8;
-        HIP_OK(launch_screen_bf16(G, tiles, w.tile_off, w.q_off, w.perm, q_xyz, (int32_t)kc, w.so, st));
+        const int64_t grid = screen_grid(nc, n);
+        HIP_OK(launch_tile_map(w.tile_off, w.q_off, nc, grid, w.tile_map, st));
+        HIP_OK(launch_screen_bf16(G, grid, w.tile_map, w.perm, q_xyz, (int32_t)kc, w.so, st));
     }
     if (timed && (rc = stage_mark(stage0 + 2, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
@@ -741,7 +805,7 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     } else {
         const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
         hipLaunchKernelGGL(k_fullscan<double>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
-                           (const int32_t*)nullptr, (const int32_t*)nullptr, 0u, opts->tie_rel, invert, o);
+                           (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr, 0u, opts->tie_rel, invert, o);
     }
     HIP_OK(hipGetLastError());
     if (timed && (rc = stage_mark(stage0 + 3, st))) return rc;
@@ -763,8 +827,8 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
                        q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list, ovf_count,
                        o);
     hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off, perm,
-                       (const int32_t*)ovf_list, (const int32_t*)ovf_count, (uint32_t)MREP_F_FULLSCAN | flag_in,
-                       tie_rel, invert, o);
+                       (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,
+                       (uint32_t)MREP_F_FULLSCAN | flag_in, tie_rel, invert, o);
     return hipGetLastError();
 }
 

@@ -37,6 +37,14 @@ namespace {
 constexpr int kMaxP = MREP_MAX_DEGREE;
 constexpr int kErrSamples = 129;  // u_i = i / 128
 
+float bf16_to_f32(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
 double binom(int n, int k)
 {
     if (k < 0 || k > n) return 0.0;
@@ -489,10 +497,52 @@ void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* co
     for (int j = 0; j < 4; ++j)
         for (int c = 0; c < 3; ++c) colv[3 * j + c] = -2.0 * b[j][c];
     for (int m = 0; m < 7; ++m) colv[12 + m] = e[m];
-    double As = 0.0, Es = 0.0;
+    double As = 0.0, Es = 0.0, Cs = 0.0;
     for (int i = 0; i < 12; ++i) As += fabs(colv[i]);
     for (int m = 0; m < 7; ++m) Es += fabs(e[m]);
     for (int i = 0; i < kScreenK; ++i) col[i] = f32_to_bf16_rne((float)colv[i]);
+    // entries 19..31: the piece's part of |q' - c|^2.  c_i = ch_i + cl_i (+ a
+    // rest of <= 2^-16 |c_i|), both BF16; rows carry qh_i, qh_i, ql_i, Qh, Ql,
+    // 1, 1 (see the screen kernel), so that the row . column sum adds
+    // -2 (qh.ch + qh.cl + ql.ch) + (Qh + Ql) + (Ph + Pl) ~ |q' - c|^2 - beta - gamma.
+    const double ccf = (double)cf[0] * cf[0] + (double)cf[1] * cf[1] + (double)cf[2] * cf[2];
+    for (int c = 0; c < 3; ++c) {
+        const uint16_t h = f32_to_bf16_rne(cf[c]);
+        const float hf = bf16_to_f32(h);
+        const uint16_t l = f32_to_bf16_rne(cf[c] - hf);  // cf - hf is exact in FP32
+        col[19 + c] = f32_to_bf16_rne(-2.0f * hf);
+        col[22 + c] = f32_to_bf16_rne(-2.0f * bf16_to_f32(l));
+        col[25 + c] = col[19 + c];
+        Cs += fabs((double)cf[c]);
+    }
+    col[28] = col[29] = f32_to_bf16_rne(1.0f);
+    // Error of the screen's sum against D - beta_eff - gamma_eff (D the exact
+    // squared sample distance), per (query, piece):
+    //   qmax alpha + beta_req + gamma_req,
+    //   alpha = kappa' A + 1.02e-4 sum|c_i|     (BF16 rounding of the first 19
+    //           entries; the split cross term 6.03 * 2^-16 |q'_i||c_i|; the
+    //           FP32 accumulation 62 * 2^-24 of |products| <= 2.05 qmax sum|c_i|)
+    //   beta_req  = kappa' E + 4e-6 |c|^2       (accumulation of |Ph + Pl|)
+    //   gamma_req = 4e-6 |q'|^2                 (per query, in the kernel)
+    // The constant entry P = |c|^2 - beta_t is split into Ph + Pl, and
+    // beta_eff = |c|^2 - (Ph + Pl) (exact in FP64 here) is checked to be at
+    // least beta_req, so that the sum minus qmax alpha is a lower bound of D.
+    const double kap = kScreenKappaBf16 * 1.01 + 1e-6;
+    const double alpha = kap * As + 1.02e-4 * Cs;
+    const double beta_req = kap * Es + 4e-6 * ccf + 1e-30;
+    double beta_t = beta_req + 0x1p-15 * (ccf + beta_req);
+    double beta_eff = 0.0;
+    for (int tries = 0; tries < 4; ++tries) {
+        const double P = ccf - beta_t;
+        const uint16_t h = f32_to_bf16_rne((float)P);
+        const double hd = (double)bf16_to_f32(h);
+        const uint16_t l = f32_to_bf16_rne((float)(P - hd));
+        col[30] = h;
+        col[31] = l;
+        beta_eff = ccf - (hd + (double)bf16_to_f32(l));
+        if (beta_eff >= beta_req) break;
+        beta_t += 2.0 * (beta_req - beta_eff);
+    }
     double L = 0.0;
     for (int i = 0; i < 3; ++i) {
         double d[3] = {R[3 * (i + 1)] - R[3 * i], R[3 * (i + 1) + 1] - R[3 * i + 1], R[3 * (i + 1) + 2] - R[3 * i + 2]};
@@ -502,11 +552,9 @@ void piece_tables(const double* R, const double* o, double tol_eff, uint16_t* co
     aux[AUX_CY] = cf[1];
     aux[AUX_CZ] = cf[2];
     aux[AUX_CC] = (float)dot3(crel, crel);
-    // with the epilogue's FP32 rounding 1e-6 (|q'|^2 + |c|^2 + |acc|), |acc| <=
-    // max|q'_i| A + E: the A, E and |c|^2 parts are folded in here (the |q'|^2
-    // part is added per query)
-    aux[AUX_KA] = (float)((kScreenKappaBf16 * 1.01 + 1.02e-6) * As);
-    aux[AUX_KE] = (float)((kScreenKappaBf16 * 1.01 + 1.02e-6) * Es + 1.02e-6 * dot3(crel, crel));
+    // rounded up from FP64 by a relative 1e-5
+    aux[AUX_KA] = (float)(alpha * 1.00001);
+    aux[AUX_KE] = (float)((beta_req + beta_eff * (1.0 + 1e-12) + 1e-30) * 1.00001);
     aux[AUX_ES] = (float)((L / (2.0 * (kSamples - 1)) + tol_eff) * 1.0001);
     aux[AUX_L] = (float)L;
     for (int i = 0; i < 4; ++i)

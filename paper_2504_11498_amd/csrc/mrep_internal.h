@@ -18,11 +18,15 @@ constexpr int kSamples = 32;
 #define MREP_TILE_QUERIES 32
 #endif
 constexpr int kQueriesPerTile = MREP_TILE_QUERIES;
+// accelerator complex dies of an MI355X, each with its own L2: tiled launches
+// deal contiguous tile ranges to the dies
+constexpr int kXcdCount = 8;
 // Segments staged in LDS per chunk by the screen.
 constexpr int kChunk = 256;
 // Length of a screen row / column (MFMA K dimension, 19 entries used).
 constexpr int kScreenK = 32;
-constexpr int kMaxCand = 16;
+// candidates a query may keep from the screen (16 lanes x 3 per lane at most)
+constexpr int kMaxCand = 48;
 
 // Per-curve record in device memory.
 struct DCurve {
@@ -65,10 +69,11 @@ struct GeomLayout {
 };
 
 // aux[8] per piece: cx, cy, cz (FP32 centre relative to the curve origin),
-// |c|^2, kappa' A and kappa' E + 1.02e-6 |c|^2 (the screen's rounding-bound
-// terms: A = sum |2 b_j|_1, E = sum |e_m|, kappa' = 1.01 kScreenKappaBf16 +
-// 1.02e-6 for the epilogue's FP32 rounding), e = L/(2(S-1)) + tol, L (speed
-// bound in u).
+// |c|^2, then the screen's bound terms alpha (AUX_KA: the coefficient of
+// max|q'_i| in the error of a screened squared distance) and K_B (AUX_KE: the
+// piece's part of the upper bound's offset, beta_req + beta_eff), e = L/(2(S-1))
+// + tol (sample spacing term), L (speed bound in u).  The screen reads the
+// last four as one 16-byte record.
 enum { AUX_CX = 0, AUX_CY, AUX_CZ, AUX_CC, AUX_KA, AUX_KE, AUX_ES, AUX_L };
 
 // BF16 screen: |computed - exact| of a sample's squared distance is at most

@@ -247,7 +247,7 @@ def decompose_surfaces(surfs, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan
     return Plan(h.value)
 
 
-def default_opts(precision: str | int = "bf16", max_candidates: int = 16, tie_rel: float = 2e-6,
+def default_opts(precision: str | int = "bf16", max_candidates: int = 32, tie_rel: float = 2e-6,
                  time_stages: bool = False, tuned: bool = False) -> Opts:
     """tuned: curve projections run the strategy Geometry.tune() chose (BF16 mode)."""
     o = Opts()

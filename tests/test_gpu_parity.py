@@ -27,9 +27,9 @@ def mrep():
     return m
 
 
-def _run(geom, q, cid, precision, invert=False, max_candidates=16):
+def _run(geom, q, cid, precision, invert=False, max_candidates=None):
     m = sys.modules["paper_2504_11498_amd.mrep"]
-    opts = m.default_opts(precision, max_candidates=max_candidates)
+    opts = m.default_opts(precision) if max_candidates is None else m.default_opts(precision, max_candidates=max_candidates)
     qt = torch.from_numpy(np.ascontiguousarray(q)).cuda()
     ct = torch.from_numpy(np.ascontiguousarray(cid, dtype=np.int32)).cuda()
     t, d, s, f = geom.project(qt, ct, opts, invert=invert)
@@ -114,6 +114,14 @@ def test_candidate_overflow_falls_back_correctly(batched):
     assert np.mean((out["flags"] & 0x20) != 0) > 0.05
     r = {k: v[:3000] for k, v in ref.items()}
     compare(curves, qs.curve_id[small], q[small], out, r, dec, label="overflow")
+    # the largest list the screen can keep (16 lanes x 3), and one past it
+    _say("[case] max_candidates=48, bf16")
+    out = _run(geom, q[small], qs.curve_id[small], "bf16", max_candidates=48)
+    compare(curves, qs.curve_id[small], q[small], out, r, dec, label="max candidates")
+    m = sys.modules["paper_2504_11498_amd.mrep"]
+    with pytest.raises(m.MrepError) as ei:
+        _run(geom, q[small], qs.curve_id[small], "bf16", max_candidates=49)
+    assert ei.value.code == m.E_INVALID_ARG
 
 
 def test_inversion_of_on_curve_points(batched):

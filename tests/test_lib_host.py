@@ -155,6 +155,10 @@ def test_error_codes():
     assert ei.value.code == mrep.E_BAD_KNOTS
     # null pointers and bad option structs at the C level
     assert mrep._decompose(1, None, None, None, None, None, 1e-6, 0, None) == mrep.E_INVALID_ARG
+    o = mrep.Opts()
+    assert mrep._opts_default(C.byref(o)) == mrep.OK and o.max_candidates == 32 and o.precision == mrep.PREC_BF16
+    assert mrep.default_opts().max_candidates == 32
+    assert mrep._opts_default(None) == mrep.E_INVALID_ARG
     o = mrep.default_opts()
     o.struct_size = 3
     b = C.c_int64()
