@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrep_oracle.c")
 _SRC_MLP = os.path.join(_HERE, "mlp_oracle.c")
 _SRC_SURF = os.path.join(_HERE, "surf_oracle.c")
+_SRC_CLIP = os.path.join(_HERE, "clip_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +30,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
-               "-shared", "-o", tmp, _SRC, _SRC_MLP, _SRC_SURF, "-lm"]
+               "-shared", "-o", tmp, _SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -39,7 +40,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC_MLP, _SRC_SURF)):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP)):
         build(force=True)
     lib = C.CDLL(_LIB)
     dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -74,6 +75,21 @@ def _load():
     lib.orc_surf_patches.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, dp]
     lib.orc_surf_patch_deviation.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_int]
     lib.orc_surf_patch_deviation.restype = C.c_double
+    lib.orc_clip_e_poly.argtypes = [dp, dp, dp]
+    lib.orc_clip_e_poly.restype = None
+    lib.orc_ferrari.argtypes = [dp, dp]
+    lib.orc_rebase.argtypes = [C.c_int, dp, dp]
+    lib.orc_rebase.restype = None
+    lib.orc_sub_left.argtypes = [C.c_int, C.c_double, dp]
+    lib.orc_sub_left.restype = None
+    lib.orc_sub_right.argtypes = [C.c_int, C.c_double, dp]
+    lib.orc_sub_right.restype = None
+    lib.orc_hull_axis.argtypes = [C.c_int, dp, dp, dp]
+    lib.orc_clip_apply.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp]
+    lib.orc_clip_apply.restype = None
+    lib.orc_clip_piece.argtypes = [dp, dp, C.c_int, dp, dp, dp]
+    lib.orc_clip_pairs.argtypes = [C.c_int64, dp, dp, C.c_int, C.c_int, C.c_double, dp, dp, dp]
+    lib.orc_clip_pairs.restype = None
     _lib = lib
     return lib
 
@@ -315,3 +331,84 @@ def surf_project(S, sid, q, nthreads: int = 0):
     if rc != 0:
         raise ValueError("orc_surf_project_batch failed")
     return {"uv": uv, "dist": dist, "runner": runner, "kappa": kappa}
+
+
+# ---------------------------------------------------------------------------
+# The paper's refinement path for one cubic piece (clip_oracle.c): monotonic
+# decomposition (Sec. 5.2.3), elimination (Sec. 5.3, Properties 1-2),
+# rebasement (Sec. 5.3, matrix T) and Bezier clipping (Sec. 5.4.1).
+# ---------------------------------------------------------------------------
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def clip_e_poly(Q, q) -> np.ndarray:
+    """Power coefficients a[0..5] of E(t) = 2 (C(t) - q) . C'(t) (eq. Et) for a cubic Bezier Q[4,3]."""
+    Q, q = _d(Q), _d(q)
+    a = np.zeros(6)
+    _load().orc_clip_e_poly(_dp(Q), _dp(q), _dp(a))
+    return a
+
+
+def ferrari(c) -> np.ndarray:
+    """Sorted real roots of c[0] + c[1] x + ... + c[4] x^4 by Ferrari's method (Sec. 5.2.3)."""
+    c = _d(c)
+    r = np.zeros(4)
+    n = _load().orc_ferrari(_dp(c), _dp(r))
+    return r[:n].copy()
+
+
+def rebase(a) -> np.ndarray:
+    """Bernstein coefficients b = T a of a power-form polynomial (Sec. 5.3)."""
+    a = _d(a)
+    b = np.zeros_like(a)
+    _load().orc_rebase(a.shape[0] - 1, _dp(a), _dp(b))
+    return b
+
+
+def sub_matrices(n: int, z: float):
+    """(S_L(z), S_R(z)) of a degree-n Bezier (Sec. 5.2.2)."""
+    L, R = np.zeros((n + 1, n + 1)), np.zeros((n + 1, n + 1))
+    lib = _load()
+    lib.orc_sub_left(n, float(z), _dp(L))
+    lib.orc_sub_right(n, float(z), _dp(R))
+    return L, R
+
+
+def hull_axis(b):
+    """[z1, z2] = the convex hull of (i/n, b_i) intersected with the t axis, or None (Sec. 5.4.1)."""
+    b = _d(b)
+    z1, z2 = C.c_double(), C.c_double()
+    ok = _load().orc_hull_axis(b.shape[0] - 1, _dp(b), C.byref(z1), C.byref(z2))
+    return (z1.value, z2.value) if ok else None
+
+
+def clip_apply(b, z1: float, z2: float) -> np.ndarray:
+    """S_[z1,z2] b = S_L((z2 - z1)/(1 - z1)) S_R(z1) b (eq. subdivisionmatrix)."""
+    b = _d(b)
+    out = np.zeros_like(b)
+    _load().orc_clip_apply(b.shape[0] - 1, _dp(b), float(z1), float(z2), _dp(out))
+    return out
+
+
+def clip_piece(Q, q, iters: int = 3):
+    """The paper's refinement of one (query, cubic piece) pair; returns (t, d2, info) with info = (monotonic
+    intervals, kept intervals, largest remaining clip width, roots of E' in (0, 1))."""
+    Q, q = _d(Q), _d(q)
+    t, d2 = C.c_double(), C.c_double()
+    info = np.zeros(4)
+    _load().orc_clip_piece(_dp(Q), _dp(q), int(iters), C.byref(t), C.byref(d2), _dp(info))
+    return t.value, d2.value, info
+
+
+def clip_pairs(Q, q, iters: int = 3, safeguard: bool = False, tol_t: float = 0.0):
+    """clip_piece over pairs Q[n,4,3], q[n,3] (OpenMP); returns (t[n], d2[n], info[n,4]).  With safeguard, a
+    clipping that keeps more than half of the interval is followed by a halving on the sign of E, and clipping
+    stops once the interval is below tol_t (or after iters)."""
+    Q = _d(Q).reshape(-1, 12)
+    q = _d(q).reshape(-1, 3)
+    n = Q.shape[0]
+    t, d2, info = np.zeros(n), np.zeros(n), np.zeros((n, 4))
+    _load().orc_clip_pairs(n, _dp(Q), _dp(q), int(iters), int(bool(safeguard)), float(tol_t), _dp(t), _dp(d2),
+                           _dp(info))
+    return t, d2, info

@@ -1,0 +1,199 @@
+"""Pins of the oracle of the paper's refinement path (monotonic decomposition, elimination, rebasement, Bezier
+clipping; Sec. 5.2.3-5.4.1) against what the paper and the mathematics fix: the printed matrices T (Sec. 5.3) and
+S(z) (Sec. 5.2.2), numerical derivatives, polynomial identities, a library root finder, brute force."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_11498_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _bern(b, s):
+    n = len(b) - 1
+    from math import comb
+
+    return sum(b[i] * comb(n, i) * s**i * (1 - s) ** (n - i) for i in range(n + 1))
+
+
+def _bez_d2(Q, q, t):
+    s = 1 - t
+    C = s**3 * Q[0] + 3 * s * s * t * Q[1] + 3 * s * t * t * Q[2] + t**3 * Q[3]
+    return float(np.sum((C - q) ** 2))
+
+
+def test_e_poly_is_the_derivative_of_d():
+    """E(t) (eq. Et) equals a central difference of D(t) = |C(t) - q|^2 evaluated independently."""
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        Q = rng.uniform(-1, 1, (4, 3))
+        q = rng.uniform(-1, 1, 3)
+        a = oracle.clip_e_poly(Q, q)
+        for t in rng.uniform(0.05, 0.95, 5):
+            h = 1e-5
+            fd = (_bez_d2(Q, q, t + h) - _bez_d2(Q, q, t - h)) / (2 * h)
+            assert abs(np.polyval(a[::-1], t) - fd) <= 1e-7 * (1 + abs(fd))
+
+
+def test_ferrari_recovers_known_roots():
+    """Quartics built from their roots (library product of linear factors): Ferrari returns them."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        r = np.sort(rng.uniform(-2, 2, 4))
+        if np.min(np.diff(r)) < 1e-2:
+            continue
+        lead = rng.uniform(0.5, 3) * rng.choice([-1, 1])
+        c = np.polynomial.polynomial.polyfromroots(r) * lead
+        got = oracle.ferrari(c)
+        assert got.shape[0] == 4
+        np.testing.assert_allclose(got, r, atol=1e-8)
+
+
+def test_ferrari_matches_numpy_roots_on_random_quartics():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        c = rng.normal(size=5)
+        ref = np.roots(c[::-1])
+        real = np.sort(ref[np.abs(ref.imag) < 1e-9].real)
+        got = oracle.ferrari(c)
+        # well-separated real roots only (near-double roots are ill-conditioned for both methods)
+        if real.size > 1 and np.min(np.diff(real)) < 1e-3:
+            continue
+        if np.min(np.abs(ref.imag[np.abs(ref.imag) > 0]), initial=1.0) < 1e-3:
+            continue
+        assert got.shape == real.shape, (c, got, real)
+        np.testing.assert_allclose(got, real, rtol=1e-7, atol=1e-7)
+
+
+def test_ferrari_special_cases():
+    np.testing.assert_allclose(oracle.ferrari([4, 0, -5, 0, 1]), [-2, -1, 1, 2], atol=1e-12)  # biquadratic
+    assert oracle.ferrari([1, 0, 0, 0, 1]).size == 0  # x^4 + 1: no real root
+    np.testing.assert_allclose(oracle.ferrari([-6, 11, -6, 1, 0]), [1, 2, 3], atol=1e-10)  # degree drop to a cubic
+    np.testing.assert_allclose(oracle.ferrari([2, -3, 1, 0, 0]), [1, 2], atol=1e-12)  # quadratic
+    np.testing.assert_allclose(oracle.ferrari([-1, 2, 0, 0, 0]), [0.5], atol=1e-15)  # linear
+
+
+def test_rebasement_matrix_is_the_printed_t5():
+    """Columns of T (b = T a applied to unit vectors) equal the matrix printed in Sec. 5.3."""
+    rows = [list(map(float, ln.split())) for ln in open(os.path.join(GOLDEN, "power_to_bernstein_deg5.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    T = np.array(rows)
+    got = np.stack([oracle.rebase(np.eye(6)[j]) for j in range(6)], axis=1)
+    np.testing.assert_allclose(got, T, atol=1e-15)
+
+
+def test_rebasement_preserves_the_polynomial():
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        a = rng.normal(size=6)
+        b = oracle.rebase(a)
+        for s in rng.uniform(0, 1, 7):
+            assert abs(_bern(b, s) - np.polyval(a[::-1], s)) <= 1e-12 * (1 + np.abs(a).sum())
+
+
+def test_subdivision_matrices_match_the_printed_cubic_sz():
+    rows = [ln for ln in open(os.path.join(GOLDEN, "subdivision_matrix_Sz.txt")) if ln.strip() and not ln.startswith("#")]
+    for z in (0.2, 0.5, 0.77):
+        S = np.array([[eval(e, {"z": z}) for e in ln.split(";")] for ln in rows])
+        L, R = oracle.sub_matrices(3, z)
+        np.testing.assert_allclose(np.vstack([L, R]), S, atol=1e-15)
+
+
+def test_degree5_subdivision_and_clip_reparameterise():
+    """S_L(z) b on [0,1] equals b at z s; S_[z1,z2] b at s equals b at z1 + (z2 - z1) s (eq. subdivisionmatrix)."""
+    rng = np.random.default_rng(5)
+    for _ in range(30):
+        b = rng.normal(size=6)
+        z = rng.uniform(0.1, 0.9)
+        L, R = oracle.sub_matrices(5, z)
+        z1, z2 = np.sort(rng.uniform(0, 1, 2))
+        cb = oracle.clip_apply(b, z1, z2)
+        for s in rng.uniform(0, 1, 5):
+            assert abs(_bern(L @ b, s) - _bern(b, z * s)) < 1e-12
+            assert abs(_bern(R @ b, s) - _bern(b, z + (1 - z) * s)) < 1e-12
+            assert abs(_bern(cb, s) - _bern(b, z1 + (z2 - z1) * s)) < 1e-11
+
+
+def test_hull_interval_contains_the_root_and_clipping_keeps_it():
+    """For a monotonic polynomial with a root in (0,1) the hull interval holds the root (found by bisection)."""
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        # increasing Bernstein coefficients give an increasing polynomial
+        b = np.cumsum(rng.uniform(0.01, 1, 6))
+        b -= rng.uniform(b[0] + 1e-3, b[-1] - 1e-3)
+        lo, hi = 0.0, 1.0
+        for _ in range(80):
+            m = 0.5 * (lo + hi)
+            if _bern(b, m) < 0:
+                lo = m
+            else:
+                hi = m
+        root = 0.5 * (lo + hi)
+        z1, z2 = oracle.hull_axis(b)
+        assert z1 - 1e-12 <= root <= z2 + 1e-12
+    assert oracle.hull_axis(np.ones(6)) is None
+
+
+def test_elimination_and_monotonic_split_against_a_grid():
+    """Kept intervals are exactly the monotonic intervals where E goes from negative to non-negative: compared with
+    the sign pattern of E on a fine grid (brute force) for random pieces and queries."""
+    rng = np.random.default_rng(7)
+    grid = np.linspace(0, 1, 20001)
+    for _ in range(100):
+        Q = rng.uniform(0, 1, (4, 3))
+        q = rng.uniform(-0.2, 1.2, 3)
+        a = oracle.clip_e_poly(Q, q)
+        E = np.polyval(a[::-1], grid)
+        # interior local minima of D = sign changes of E from - to +
+        up = int(np.sum((E[:-1] < 0) & (E[1:] >= 0)))
+        _, _, info = oracle.clip_piece(Q, q, 3)
+        assert int(info[1]) == up
+
+
+def test_clip_piece_minimum_matches_dense_search():
+    """The piece minimum of the refinement path equals a dense FP64 search refined by golden sections."""
+    rng = np.random.default_rng(8)
+    grid = np.linspace(0, 1, 4001)
+    for _ in range(200):
+        Q = rng.uniform(0, 1, (4, 3))
+        q = rng.uniform(-0.2, 1.2, 3)
+        t, d2, _ = oracle.clip_pairs(Q[None], q[None], 12, True, 1e-13)
+        s = 1 - grid
+        C = (s**3)[:, None] * Q[0] + (3 * s * s * grid)[:, None] * Q[1] + (3 * s * grid * grid)[:, None] * Q[2] + \
+            (grid**3)[:, None] * Q[3]
+        D = np.sum((C - q) ** 2, axis=1)
+        k = int(np.argmin(D))
+        lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, grid.size - 1)]
+        for _ in range(100):
+            m1, m2 = lo + (hi - lo) * 0.382, lo + (hi - lo) * 0.618
+            if _bez_d2(Q, q, m1) < _bez_d2(Q, q, m2):
+                hi = m2
+            else:
+                lo = m1
+        dref = min(_bez_d2(Q, q, 0.5 * (lo + hi)), D[0], D[-1])
+        assert abs(d2[0] - dref) <= 1e-12 * (1 + dref)
+
+
+def test_clipping_convergence_claim():
+    """Sec. 5.4.1: parameters converge to about 1e-6 after three clippings.  On pairs of the batched-curve workload
+    (each query against every piece of its curve), the median kept interval is below 1e-6 after three plain
+    clippings, but not every interval is; with the halving safeguard every one is below 1e-9 after ten."""
+    curves, qs = gen.curves_batched(2, n_curves=16, per_curve=16)
+    q = qs.materialise(lambda cid, t: oracle.eval_batch(curves, cid, t))
+    dec = oracle.decompose(curves, 1e-6 * curves.bbox_diag())
+    off = np.concatenate([[0], np.cumsum(dec["counts"])])
+    Qs, qq = [], []
+    for i in range(qs.n):
+        c = qs.curve_id[i]
+        Qs.append(dec["R"][off[c] : off[c + 1]])
+        qq.append(np.repeat(q[i][None], off[c + 1] - off[c], axis=0))
+    Qs, qq = np.concatenate(Qs), np.concatenate(qq)
+    _, _, info = oracle.clip_pairs(Qs, qq, 3)
+    w = info[info[:, 1] > 0, 2]
+    assert np.median(w) < 1e-6
+    assert np.quantile(w, 0.99) > 1e-6  # the tail does not converge in three plain clippings
+    _, _, info = oracle.clip_pairs(Qs, qq, 10, True, 0.0)
+    assert info[info[:, 1] > 0, 2].max() < 1e-9
