@@ -78,6 +78,7 @@ def _load():
     lib.orc_clip_e_poly.argtypes = [dp, dp, dp]
     lib.orc_clip_e_poly.restype = None
     lib.orc_ferrari.argtypes = [dp, dp]
+    lib.orc_ferrari_01.argtypes = [dp, dp]
     lib.orc_rebase.argtypes = [C.c_int, dp, dp]
     lib.orc_rebase.restype = None
     lib.orc_sub_left.argtypes = [C.c_int, C.c_double, dp]

@@ -19,6 +19,12 @@
  *     [z1, z2] = the hull of the crossings of all point pairs;
  *   - after the last clipping the root is the midpoint of the remaining
  *     interval;
+ *   - Ferrari's method is applied to E' at the degree its coefficients show: a
+ *     leading coefficient below 1e-6 of the largest lower one is dropped (it
+ *     only adds roots far outside [0, 1]; normalising by it leaves no
+ *     accurate root in [0, 1], as for the E' of a degree-elevated quadratic,
+ *     whose cubic and quartic coefficients are rounding noise), and the roots
+ *     in [-0.5, 1.5] are polished by three Newton steps on the full E';
  *   - optional safeguard (off for the paper's three clippings): when a clipping
  *     keeps more than half of the interval, the half holding the sign change
  *     of E (E is monotonic there, so exactly one half) replaces it, and the
@@ -107,9 +113,17 @@ int orc_ferrari(const double* c, double* roots)
     for (int i = 0; i < 5; ++i) mx = fmax(mx, fabs(c[i]));
     int n = 0;
     if (mx == 0.0) return 0;
-    if (fabs(c[4]) <= 1e-14 * mx) {
+    /* the degree: a leading coefficient below 1e-6 of the largest lower one only
+     * adds roots far outside [0, 1] and is dropped (the kept roots are then
+     * polished on the full polynomial by orc_ferrari_01) */
+    double lower[5];
+    lower[0] = 0.0;
+    for (int k = 1; k < 5; ++k) lower[k] = fmax(lower[k - 1], fabs(c[k - 1]));
+    int deg = 4;
+    while (deg > 0 && !(fabs(c[deg]) > 1e-6 * lower[deg])) --deg;
+    if (deg < 4) {
         /* degree <= 3 */
-        if (fabs(c[3]) > 1e-14 * mx) {
+        if (deg == 3) {
             const double A = c[2] / c[3], B = c[1] / c[3], C = c[0] / c[3];
             const double P = B - A * A / 3.0;
             const double Qc = 2.0 * A * A * A / 27.0 - A * B / 3.0 + C;
@@ -127,9 +141,9 @@ int orc_ferrari(const double* c, double* roots)
                 const double phi = acos(cphi);
                 for (int k = 0; k < 3; ++k) roots[n++] = 2.0 * r * cos((phi - 2.0 * M_PI * k) / 3.0) - A / 3.0;
             }
-        } else if (fabs(c[2]) > 1e-14 * mx) {
+        } else if (deg == 2) {
             quad_roots(c[1] / c[2], c[0] / c[2], roots, &n);
-        } else if (fabs(c[1]) > 1e-14 * mx) {
+        } else if (deg == 1) {
             roots[n++] = -c[0] / c[1];
         }
     } else {
@@ -164,6 +178,34 @@ int orc_ferrari(const double* c, double* roots)
         for (int i = 0; i < ny; ++i) roots[n++] = y[i] - b / 4.0;
     }
     /* sort */
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && roots[j] < roots[j - 1]; --j) {
+            const double t = roots[j];
+            roots[j] = roots[j - 1];
+            roots[j - 1] = t;
+        }
+    return n;
+}
+
+/* Roots of E' used as split points: the roots by Ferrari's method within
+ * [-0.5, 1.5], each polished by three Newton steps on the full quartic (a
+ * dropped leading term shifts them by a little; the polish removes it). */
+int orc_ferrari_01(const double* c, double* roots)
+{
+    double r[4];
+    const int nr = orc_ferrari(c, r);
+    int n = 0;
+    for (int i = 0; i < nr; ++i) {
+        double x = r[i];
+        if (!(x > -0.5 && x < 1.5)) continue;
+        for (int it = 0; it < 3; ++it) {
+            const double f = (((c[4] * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0];
+            const double fp = ((4.0 * c[4] * x + 3.0 * c[3]) * x + 2.0 * c[2]) * x + c[1];
+            if (fp == 0.0) break;
+            x -= f / fp;
+        }
+        roots[n++] = x;
+    }
     for (int i = 1; i < n; ++i)
         for (int j = i; j > 0 && roots[j] < roots[j - 1]; --j) {
             const double t = roots[j];
@@ -281,7 +323,7 @@ int orc_clip_piece_ex(const double* Q, const double* q, int iters, int safeguard
     double a[6], ep[5], r[4];
     orc_clip_e_poly(Q, q, a);
     for (int m = 0; m < 5; ++m) ep[m] = (double)(m + 1) * a[m + 1];
-    const int nr = orc_ferrari(ep, r);
+    const int nr = orc_ferrari_01(ep, r);
     double br[6];
     int nb = 0;
     br[nb++] = 0.0;

@@ -177,6 +177,24 @@ def test_clip_piece_minimum_matches_dense_search():
         assert abs(d2[0] - dref) <= 1e-12 * (1 + dref)
 
 
+def test_clip_piece_on_nearly_quadratic_pieces():
+    """Degree-elevated quadratics perturbed by eps (E' then has cubic and quartic coefficients from rounding level up
+    to eps): the piece minimum still equals a dense search at every scale of eps."""
+    rng = np.random.default_rng(9)
+    grid = np.linspace(0, 1, 20001)
+    for eps in (0.0, 1e-12, 1e-10, 1e-9, 1e-8, 1e-6):
+        for _ in range(60):
+            P = rng.uniform(0, 1, (3, 3))
+            Q = np.stack([P[0], (P[0] + 2 * P[1]) / 3, (2 * P[1] + P[2]) / 3, P[2]]) + eps * rng.normal(size=(4, 3))
+            q = rng.uniform(-0.2, 1.2, 3)
+            _, d2, _ = oracle.clip_pairs(Q[None], q[None], 24, True, 1e-13)
+            s = 1 - grid
+            C = (s**3)[:, None] * Q[0] + (3 * s * s * grid)[:, None] * Q[1] + (3 * s * grid * grid)[:, None] * Q[2] + \
+                (grid**3)[:, None] * Q[3]
+            D = np.sum((C - q) ** 2, axis=1)
+            assert d2[0] <= D.min() * (1 + 1e-9) + 1e-15, eps
+
+
 def test_clipping_convergence_claim():
     """Sec. 5.4.1: parameters converge to about 1e-6 after three clippings.  On pairs of the batched-curve workload
     (each query against every piece of its curve), the median kept interval is below 1e-6 after three plain
