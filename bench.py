@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--no-surfaces", action="store_true", help="skip the batched-surfaces workload")
     ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-strut curves workload")
+    ap.add_argument("--no-clip", action="store_true",
+                    help="skip the batched curves with the paper's refinement path (MREP_OPT_CLIP)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the autotuner and small-batch graph measurements on the batched curves (so that a "
                          "kernel trace of the run holds the timed screen launches only)")
@@ -190,6 +192,8 @@ def main():
         result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
                                         "ms": {"screen": ms_screen, "spheres": ms_spheres}}
         result["config"]["graph_small_batches"] = graph_small_batches(geom, q, cid)
+    if not args.no_clip:
+        result["clip_refiner"] = clip_refiner(geom, q, cid, outs, curves, value, stage_ms, ws, args)
     if not args.no_seeded:
         result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
     if not args.no_surfaces:
@@ -269,6 +273,38 @@ def graph_small_batches(geom, q, cid, batch: int = 4096, calls: int = 200):
         res[name + "_us_per_call"] = (time.perf_counter() - t0) / calls * 1e6
     res["graph_projections_per_s"] = batch / (res["graph_us_per_call"] / 1e6)
     return res
+
+
+def clip_refiner(geom, q, cid, plain_outs, curves, plain_value, plain_stage, ws, args):
+    """The same batch with the paper's refinement path on every candidate pair (Ferrari split of E', elimination,
+    rebasement, Bezier clipping; MREP_OPT_CLIP) in place of the sampled minimum + Newton; compared with the plain
+    method's answers."""
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    n = q.shape[0]
+    opts = mrep.default_opts("bf16", time_stages=True, clip=True)
+    outs = tuple(torch.empty_like(o) for o in plain_outs)
+
+    def step():
+        geom.project(q, cid, opts, workspace=ws, out=outs)
+
+    for _ in range(args.warmup):
+        step()
+    ms, stage = _timed(step, args.steps)
+    diag = torch.from_numpy(curves.bbox_diag()).to(q.device)[cid.long()]
+    dd = ((outs[1] - plain_outs[1]).abs() / diag).max().item()
+    dt = (outs[0] - plain_outs[0]).abs()
+    return {
+        "value": n / (ms / 1e3),
+        "ms_per_step": ms,
+        "vs_plain_value": (n / (ms / 1e3)) / plain_value,
+        "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "refine": float(stage[2])},
+        "plain_refine_ms": float(plain_stage[2]),
+        "vs_plain_max_dist_rel": dd,
+        "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
+    }
 
 
 def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):

@@ -103,6 +103,15 @@ typedef struct {
  * the strategy mrep_tune_curves last chose for the geometry (the screen until
  * then); the workspace must then hold mrep_workspace_bytes with this flag. */
 #define MREP_OPT_TUNED 0x2
+/* mrep_opts.flags: BF16 mode refines each candidate (query, piece) pair with
+ * the paper's path instead of the sampled minimum + Newton: Ferrari roots of
+ * E' split the piece into monotonic intervals (Sec. 5.2.3), the elimination
+ * criterion keeps intervals where E goes from negative to non-negative (Sec.
+ * 5.3, Properties 1-2; both piece ends are always candidates), E is rebased to
+ * Bernstein form (Sec. 5.3, b = T a) and Bezier clipping locates its root
+ * (Sec. 5.4.1, eq. subdivisionmatrix), in FP64.  The finish (FP64 polish on the
+ * exact span) and the full-scan fallback are unchanged. */
+#define MREP_OPT_CLIP 0x4
 #define MREP_STRATEGY_SCREEN 0  /* BF16 MFMA screen, certified candidates, refine */
 #define MREP_STRATEGY_SPHERES 1 /* sphere lists (span clusters where compact), refine every listed piece */
 #define MREP_N_STAGES 4 /* most stages any call records (see mrep_last_stage_times) */

@@ -42,8 +42,10 @@ def build(verbose: bool = False) -> str:
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_nn.hip"), "-o", nn_o])
     surf_o = os.path.join(BUILD, "mrep_surf.o")
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_surf.hip"), "-o", surf_o])
+    clip_o = os.path.join(BUILD, "mrep_clip.o")
+    _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_clip.hip"), "-o", clip_o])
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, nn_o, surf_o, host_o, "-o", tmp,
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, nn_o, surf_o, clip_o, host_o, "-o", tmp,
           "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:

@@ -801,7 +801,7 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     if (timed && (rc = stage_mark(stage0 + 2, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
         HIP_OK(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.so, w.pair_res, nullptr, 0u, opts->tie_rel,
-                             invert, w.ovf_list, w.ovf_count, o, st));
+                             invert, w.ovf_list, w.ovf_count, o, st, (opts->flags & MREP_OPT_CLIP) != 0));
     } else {
         const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
         hipLaunchKernelGGL(k_fullscan<double>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
@@ -815,14 +815,19 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
 hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
                                const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
                                const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
-                               int32_t* ovf_count, const Outs& o, hipStream_t st)
+                               int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip)
 {
     const int RT = 128;
     const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
     const unsigned pr_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((so.pair_cap + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, perm,
-                       (const int32_t*)so.pair_seg, (const int32_t*)so.pair_j, (const int32_t*)so.pair_count,
-                       so.pair_cap, done, pair_res);
+    if (clip) {
+        const hipError_t e = launch_pairs_clip(G, curve_id, q_xyz, perm, so, done, pair_res, st);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, perm,
+                           (const int32_t*)so.pair_seg, (const int32_t*)so.pair_j, (const int32_t*)so.pair_count,
+                           so.pair_cap, done, pair_res);
+    }
     hipLaunchKernelGGL(k_finish<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
                        q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list, ovf_count,
                        o);

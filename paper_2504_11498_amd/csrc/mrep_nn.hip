@@ -1605,7 +1605,8 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
     }
     if (timed && (rc = stage_mark(3, st))) return rc;
     NN_HIP(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.box.so, w.pair_res, nn ? w.done : nullptr,
-                         nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, invert, w.ovf_list, w.ovf_count, o, st));
+                         nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, invert, w.ovf_list, w.ovf_count, o, st,
+                         (opts->flags & MREP_OPT_CLIP) != 0));
     if (timed) {
         if ((rc = stage_mark(4, st))) return rc;
         stage_end(4);

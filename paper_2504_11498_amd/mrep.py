@@ -27,7 +27,7 @@ OK, E_INVALID_ARG, E_BAD_DEGREE, E_BAD_KNOTS, E_TOL, E_SMALL_BUFFER, E_HIP, E_NO
 F_POLISHED, F_NEAR_TIE, F_ILL_COND, F_ENDPOINT, F_OFFCURVE, F_FULLSCAN, F_BAD_ID = 1, 2, 4, 8, 16, 32, 64
 F_NN_FALLBACK = 128
 PREC_FP64, PREC_BF16 = 0, 3
-OPT_TIME_STAGES, OPT_TUNED = 1, 2
+OPT_TIME_STAGES, OPT_TUNED, OPT_CLIP = 1, 2, 4
 STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
 N_STAGES = 4
 MAX_DEGREE = 15
@@ -248,11 +248,12 @@ def decompose_surfaces(surfs, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan
 
 
 def default_opts(precision: str | int = "bf16", max_candidates: int = 32, tie_rel: float = 2e-6,
-                 time_stages: bool = False, tuned: bool = False) -> Opts:
-    """tuned: curve projections run the strategy Geometry.tune() chose (BF16 mode)."""
+                 time_stages: bool = False, tuned: bool = False, clip: bool = False) -> Opts:
+    """tuned: curve projections run the strategy Geometry.tune() chose (BF16 mode).  clip: candidate pieces are
+    refined by the paper's monotonic split, elimination, rebasement and Bezier clipping (MREP_OPT_CLIP)."""
     o = Opts()
     _check(_opts_default(C.byref(o)), "mrep_opts_default")
-    o.flags = (OPT_TIME_STAGES if time_stages else 0) | (OPT_TUNED if tuned else 0)
+    o.flags = (OPT_TIME_STAGES if time_stages else 0) | (OPT_TUNED if tuned else 0) | (OPT_CLIP if clip else 0)
     if isinstance(precision, str):
         precision = {"fp64": PREC_FP64, "bf16": PREC_BF16}[precision]
     o.precision = int(precision)
