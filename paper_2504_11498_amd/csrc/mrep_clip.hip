@@ -35,7 +35,8 @@ namespace mrep {
 namespace {
 
 constexpr int kClipIters = 24;      // clippings per interval at most
-constexpr double kClipTol = 1e-10;  // interval width in the piece parameter that ends the clipping
+constexpr double kClipTol = 1e-8;   // interval width in the piece parameter that ends the clipping (the
+                                    // pair result keeps u in FP32; the finish polishes in FP64)
 
 // real roots of y^2 + b y + c, appended to r
 __device__ __forceinline__ void quad_real(double b, double c, double* r, int& n)
@@ -185,7 +186,8 @@ __device__ __forceinline__ double bern_at(const double* b, double z)
     return w[0];
 }
 
-// Convex hull of (i/5, b_i) against the axis: [z1, z2], false when they do not meet.
+// Convex hull of (i/5, b_i) against the axis: [z1, z2], false when they do not
+// meet (only the pairs of opposite signs cross; a few per clipping).
 __device__ __forceinline__ bool hull_axis(const double* b, double& z1, double& z2)
 {
     double lo = INFINITY, hi = -INFINITY;
