@@ -22,7 +22,10 @@ constexpr int kQueriesPerTile = MREP_TILE_QUERIES;
 // deal contiguous tile ranges to the dies
 constexpr int kXcdCount = 8;
 // Segments staged in LDS per chunk by the screen.
-constexpr int kChunk = 256;
+#ifndef MREP_SCREEN_CHUNK
+#define MREP_SCREEN_CHUNK 256
+#endif
+constexpr int kChunk = MREP_SCREEN_CHUNK;
 // Length of a screen row / column (MFMA K dimension, 19 entries used).
 constexpr int kScreenK = 32;
 // candidates a query may keep from the screen (16 lanes x 3 per lane at most)

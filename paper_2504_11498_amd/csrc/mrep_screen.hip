@@ -123,7 +123,13 @@ constexpr float kSqrtHi = 1.0f + 0x1p-20f;
 // lb <= U implies D - delta <= ((U + e) / kSqrtLo)^2 <= ((U + e_max) / kSqrtLo)^2;
 // the threshold is computed with a relative margin of 2^-18 so that FP32
 // rounding can only let more pieces through
-constexpr int kShareEvery = 4;  // tiles between refreshes of a query's shared upper bound
+#ifndef MREP_CHUNK_AHEAD
+#define MREP_CHUNK_AHEAD 0  // 1: the next chunk's loads are issued before the current chunk is screened
+#endif
+#ifndef MREP_SHARE_EVERY
+#define MREP_SHARE_EVERY 8
+#endif
+constexpr int kShareEvery = MREP_SHARE_EVERY;  // tiles between refreshes of a query's shared upper bound
 
 // Staging of one chunk of kChunk pieces as 80-byte LDS records: the column
 // (64 B) and the bound terms (16 B) of each piece.  Each thread loads
@@ -131,8 +137,9 @@ constexpr int kShareEvery = 4;  // tiles between refreshes of a query's shared u
 // the curve's end get columns whose constant entry is +inf (every sum is +inf:
 // never a candidate, never an upper bound).
 constexpr int kColLoads = kChunk * 4 / kThreads;
-static_assert(kChunk == kThreads, "one bound record per thread");
-__device__ __forceinline__ void load_chunk(const DevGeom& G, const DCurve& cv, int base, uint4* cr, uint4& ar)
+constexpr int kAuxLoads = kChunk / kThreads;
+static_assert(kChunk % kThreads == 0, "whole bound records per thread");
+__device__ __forceinline__ void load_chunk(const DevGeom& G, const DCurve& cv, int base, uint4* cr, uint4* ar)
 {
     const int cn = min(kChunk, cv.n_seg - base);
     const uint4* gc = reinterpret_cast<const uint4*>(G.col + (cv.seg_off + base) * kScreenK);
@@ -142,12 +149,22 @@ __device__ __forceinline__ void load_chunk(const DevGeom& G, const DCurve& cv, i
         const int i = threadIdx.x + k * kThreads;
         cr[k] = (i < cn * 4) ? gc[i] : ((i & 3) == 3 ? make_uint4(0, 0, 0, kBf16Inf) : make_uint4(0, 0, 0, 0));
     }
-    ar = ((int)threadIdx.x < cn) ? ga[2 * threadIdx.x + 1] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < kAuxLoads; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        ar[k] = (i < cn) ? ga[2 * i + 1] : make_uint4(0, 0, 0, 0);
+    }
 }
 
-// 3 waves per SIMD (at most 168 VGPRs): the MFMA-to-reduction latency is
-// hidden by the other waves; 2 waves per SIMD lose a fifth of the throughput
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_screen_bf16(
+// 4 waves per SIMD (at most 128 VGPRs; one value spills, stored in the
+// prologue and read back in the candidate output): the MFMA-to-reduction
+// latency and the per-tile row building and staging are hidden by the other
+// waves.  Measured on the batched curves: 3 waves (with the next chunk's loads
+// issued ahead, 163 VGPRs) 1.03 ms, 4 waves 0.96 ms; 2 waves lose a fifth.
+#ifndef MREP_SCREEN_MIN_WAVES
+#define MREP_SCREEN_MIN_WAVES 4
+#endif
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MREP_SCREEN_MIN_WAVES, 8))) void k_screen_bf16(
     DevGeom G, const int4* __restrict__ tile_map, const int32_t* __restrict__ perm, const double* __restrict__ qxyz,
     int32_t kc, ScreenOut out)
 {
@@ -168,8 +185,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))
 
     // the first chunk's loads are in flight while the rows are built
     const int nseg = cv.n_seg;
-    uint4 cr[kColLoads], ar;
-    load_chunk(G, cv, 0, cr, ar);
+    uint4 cr[kColLoads], ar[kAuxLoads];
+    if (MREP_CHUNK_AHEAD) load_chunk(G, cv, 0, cr, ar);
 
     // A fragments (rows), built once per query set: entry k of lane l is
     // kRowM[i][l][k] (the sample's power) times the query factor w[k].
@@ -261,15 +278,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))
         const int cn = min(kChunk, nseg - base);
         const int cn16 = (cn + 15) & ~15;
         __syncthreads();  // every wave is done with the previous chunk
+        if (!MREP_CHUNK_AHEAD) load_chunk(G, cv, base, cr, ar);
 #pragma unroll
         for (int k = 0; k < kColLoads; ++k) {
             const int i = threadIdx.x + k * kThreads;
             s_rec[(i >> 2) * 5 + (i & 3)] = cr[k];
         }
-        s_rec[threadIdx.x * 5 + 4] = ar;
+#pragma unroll
+        for (int k = 0; k < kAuxLoads; ++k) s_rec[(threadIdx.x + k * kThreads) * 5 + 4] = ar[k];
         __syncthreads();
         // the next chunk's loads are in flight while this one is screened
-        if (base + kChunk < nseg) load_chunk(G, cv, base + kChunk, cr, ar);
+        if (MREP_CHUNK_AHEAD && base + kChunk < nseg) load_chunk(G, cv, base + kChunk, cr, ar);
         for (int tb = 0; tb < cn16; tb += 16) {
             const int sl = tb + (lane & 15);
             const bf16x8 B = __builtin_bit_cast(bf16x8, s_rec[sl * 5 + kb]);
