@@ -295,7 +295,12 @@ __device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_
     }
 }
 
-__global__ __launch_bounds__(256) void k_pairs_clip(DevGeom G, const int32_t* __restrict__ cid,
+// 3 waves per SIMD (168 VGPRs, some FP64 temporaries spill): refine 1.03 ms
+// on the batched curves against 1.16 ms with 2 waves (211 VGPRs, no spill)
+#ifndef MREP_CLIP_MIN_WAVES
+#define MREP_CLIP_MIN_WAVES 3
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_CLIP_MIN_WAVES, 8))) void k_pairs_clip(DevGeom G, const int32_t* __restrict__ cid,
                                                     const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ pair_seg,
                                                     const int32_t* __restrict__ pair_j,
