@@ -49,8 +49,15 @@ namespace {
 
 constexpr int kSphSub = 8;
 constexpr int kSphThreads = kQueriesPerTile * kSphSub;
-constexpr int kSphCap = 256;    // listed patches per query; more: the full scan
-constexpr int kCluChunk = 2048;  // cluster spheres staged per round
+// 192 listed patches per query keep the list kernel at 53 KB of LDS, 3
+// workgroups per CU: on the batched surfaces the list stage takes 43 ms
+// against 63 ms with 256 (2 workgroups), for 1.8% instead of 1.3% of the
+// queries sent to the full scan; 160 sends 2.5% and is slower overall.
+#ifndef MREP_SPH_CAP
+#define MREP_SPH_CAP 192
+#endif
+constexpr int kSphCap = MREP_SPH_CAP;    // listed patches per query; more: the full scan
+constexpr int kCluChunk = 8 * kSphCap;  // cluster spheres staged per round (shares LDS with the lists' bounds)
 constexpr int kCluCap = 64;     // candidate clusters per query; more: the full scan
 constexpr int kXcds = 8;
 constexpr int64_t kSurfPairsPerQuery = 96;
@@ -256,7 +263,7 @@ __device__ float first_ub(const DevSurf& D, const DSurf& sf, float4* st, const f
 // order, into list[0..kCluCap) as local indices; returns their count (more
 // than kCluCap: overflow)
 __device__ int clu_list(const DevSurf& D, const DSurf& sf, float4* st, const float* ql, float eps, float thr,
-                        bool active, int lane, int sub, int32_t* list)
+                        bool active, int lane, int sub, uint16_t* list)
 {
     int cnt = 0;
     for (int c0 = 0; c0 < sf.n_clu; c0 += kCluChunk) {
@@ -275,7 +282,7 @@ __device__ int clu_list(const DevSurf& D, const DSurf& sf, float4* st, const flo
             }
             const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
             const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-            if (hit && pos < kCluCap) list[pos] = c0 + i;
+            if (hit && pos < kCluCap) list[pos] = (uint16_t)(c0 + i);  // a surface has < 65536 clusters
             cnt += __popc(grp);
         }
     }
@@ -296,7 +303,7 @@ __global__ __launch_bounds__(kSphThreads) void k_scand(DevSurf D, const int32_t*
                                                        SphTop top)
 {
     __shared__ float4 s_st[kCluChunk];
-    __shared__ int32_t s_clu[kQueriesPerTile][kCluCap];
+    __shared__ uint16_t s_clu[kQueriesPerTile][kCluCap];
     const int n_tiles = tile_off[D.n_surf];
     const int per = (n_tiles + kXcds - 1) / kXcds;
     const int slot = (int)(blockIdx.x / kXcds);
@@ -747,7 +754,7 @@ __global__ __launch_bounds__(kSphThreads) void k_slist(DevSurf D, const int32_t*
         float lb[kQueriesPerTile][kSphCap];
     } s_u;
     __shared__ int32_t s_list[kQueriesPerTile][kSphCap];
-    __shared__ int32_t s_clu[kQueriesPerTile][kCluCap];
+    __shared__ uint16_t s_clu[kQueriesPerTile][kCluCap];
     __shared__ int32_t s_base[kQueriesPerTile];
     const int n_tiles = tile_off[D.n_surf];
     const int per = (n_tiles + kXcds - 1) / kXcds;
@@ -886,7 +893,20 @@ __global__ __launch_bounds__(kSphThreads) void k_slist(DevSurf D, const int32_t*
 
 // 3b. One thread per listed pair: the certified patch minimum below the
 // query's threshold.
-__global__ __launch_bounds__(256) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
+// Occupancy of the patch kernels (waves per SIMD; the register limit makes the
+// compiler spill some temporaries): measured on the batched surfaces,
+// patch minima 40.9 -> 31.2 ms with k_spairs at 4 (256 VGPRs -> 128), polish
+// and write 26.8 -> 23.5 ms with k_sfinish at 3 and k_sfull at 2.
+#ifndef MREP_SPAIRS_MIN_WAVES
+#define MREP_SPAIRS_MIN_WAVES 4
+#endif
+#ifndef MREP_SFINISH_MIN_WAVES
+#define MREP_SFINISH_MIN_WAVES 3
+#endif
+#ifndef MREP_SFULL_MIN_WAVES
+#define MREP_SFULL_MIN_WAVES 2
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SPAIRS_MIN_WAVES, 8))) void k_spairs(DevSurf D, const int32_t* __restrict__ sid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                 ScreenOut so, const uint32_t* __restrict__ fub, float tie_rel,
                                                 float4* __restrict__ res)
@@ -1226,7 +1246,7 @@ __device__ void s_finish(const DevSurf& D, const DSurf& sf, const double* x, con
     o.f[qi] = flags;
 }
 
-__global__ __launch_bounds__(128) void k_sfinish(DevSurf D, const int32_t* __restrict__ sid,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_SFINISH_MIN_WAVES, 8))) void k_sfinish(DevSurf D, const int32_t* __restrict__ sid,
                                                  const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                  const int32_t* __restrict__ perm, ScreenOut so,
                                                  const float4* __restrict__ res, double tie_rel, int32_t invert,
@@ -1301,7 +1321,7 @@ __device__ __forceinline__ float wave_min(float v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_sfull(DevSurf D, const int32_t* __restrict__ sid,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SFULL_MIN_WAVES, 8))) void k_sfull(DevSurf D, const int32_t* __restrict__ sid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ list, const int32_t* __restrict__ count,
                                                double tie_rel, int32_t invert, uint32_t extra, SOuts o)
