@@ -283,8 +283,20 @@ hipError_t mrep::launch_tile_map(const int32_t* tile_off, const int32_t* q_off, 
 // One thread per (query, candidate piece) pair reserved by the screen: the
 // certified minimum over the piece in the refine precision.  Persistent grid.
 // done (nullable): per sorted query, nonzero when the query is already decided.
+// occupancy hints (waves per SIMD): k_pairs 6 (80 VGPRs, no spill) and
+// k_finish 6 trim the refine stage by about 3% on the batched curves; the full
+// scan keeps its registers (its FP64 instance would spill heavily)
+#ifndef MREP_PAIRS_MIN_WAVES
+#define MREP_PAIRS_MIN_WAVES 6
+#endif
+#ifndef MREP_FINISH_MIN_WAVES
+#define MREP_FINISH_MIN_WAVES 6
+#endif
+#ifndef MREP_FULLSCAN_MIN_WAVES
+#define MREP_FULLSCAN_MIN_WAVES 1
+#endif
 template <typename T>
-__global__ __launch_bounds__(256) void k_pairs(DevGeom G, const int32_t* __restrict__ cid,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_MIN_WAVES, 8))) void k_pairs(DevGeom G, const int32_t* __restrict__ cid,
                                                const double* __restrict__ qxyz, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ pair_seg,
                                                const int32_t* __restrict__ pair_j,
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(256) void k_pairs(DevGeom G, const int32_t* __restr
 // One thread per query: the two best of its pairs, then finish.  Queries whose
 // list overflowed are appended to ovf_list for k_fullscan.
 template <typename T>
-__global__ __launch_bounds__(128) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH_MIN_WAVES, 8))) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, ScreenOut so,
                                                 const float4* __restrict__ pair_res, const uint8_t* __restrict__ done,
@@ -372,7 +384,7 @@ __device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
 // query in the FP64 mode (list == nullptr) and for the screen's overflows.
 // Persistent: wave w takes items w, w + waves, ... until the count is reached.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fullscan(DevGeom G, const int32_t* __restrict__ cid,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_FULLSCAN_MIN_WAVES, 8))) void k_fullscan(DevGeom G, const int32_t* __restrict__ cid,
                                                   const double* __restrict__ qxyz,
                                                   const int32_t* __restrict__ q_off,
                                                   const int32_t* __restrict__ perm,
