@@ -296,7 +296,25 @@ def clip_refiner(geom, q, cid, plain_outs, curves, plain_value, plain_stage, ws,
     diag = torch.from_numpy(curves.bbox_diag()).to(q.device)[cid.long()]
     dd = ((outs[1] - plain_outs[1]).abs() / diag).max().item()
     dt = (outs[0] - plain_outs[0]).abs()
+    # the monotonic split alone (roots of E'), Ferrari against Newton's iteration, on every query paired with the
+    # piece holding its projection (the paper's comparison of the analytic and the numerical root finders)
+    piece = plain_outs[2]
+    split = {}
+    for name, method in (("ferrari", mrep.ROOTS_FERRARI), ("newton", mrep.ROOTS_NEWTON)):
+        for _ in range(args.warmup):
+            geom.monotonic_split(cid, piece, q, method)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            roots, count = geom.monotonic_split(cid, piece, q, method)
+        e1.record()
+        torch.cuda.synchronize()
+        split[name] = {"us_per_call": e0.elapsed_time(e1) * 1e3 / args.steps,
+                       "mean_roots": float(count.float().mean().item())}
+    split["pairs"] = int(n)
+    split["newton_over_ferrari"] = split["newton"]["us_per_call"] / split["ferrari"]["us_per_call"]
     return {
+        "monotonic_split": split,
         "value": n / (ms / 1e3),
         "ms_per_step": ms,
         "vs_plain_value": (n / (ms / 1e3)) / plain_value,

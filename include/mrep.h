@@ -202,6 +202,27 @@ int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t
                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
                            double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
 
+/* Monotonic decomposition (Sec. 5.2.3): for each (query, piece) pair, the
+ * roots in (0, 1) of E'(u) (eq. E't), the second derivative of the squared
+ * distance D(u) = |C(u) - q|^2 on the cubic piece in its local parameter u;
+ * between consecutive roots E = D' is monotonic.  method MREP_ROOTS_FERRARI:
+ * Ferrari's method on the quartic (at the degree its coefficients show, each
+ * root polished by three Newton steps); MREP_ROOTS_NEWTON: Newton's iteration
+ * from 8 uniform starts (at most 20 steps each, converged roots in (0, 1)
+ * kept once), the numerical method the paper compares against (Table
+ * tab:analytical).  FP64, one thread per pair.
+ *   curve_id[n]  DEVICE int32   curve of pair i
+ *   piece[n]     DEVICE int32   0-based piece index within that curve (mrep_plan_export)
+ *   q_xyz[3n]    DEVICE double  query of pair i
+ *   roots_out[4n] DEVICE double roots of pair i, ascending, in roots_out[4i..4i+count)
+ *   count_out[n] DEVICE int32   number of roots (0..4); -1 for an out-of-range curve or piece
+ * Errors: MREP_E_INVALID_ARG (null pointers with n > 0, n < 0, unknown method), MREP_E_HIP. */
+#define MREP_ROOTS_FERRARI 0
+#define MREP_ROOTS_NEWTON 1
+int32_t mrep_monotonic_split(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const int32_t* piece,
+                             const double* q_xyz, int32_t method, double* roots_out, int32_t* count_out,
+                             void* stream);
+
 /* Evaluate C_{curve_id[i]}(t[i]) on the exact curve (FP64).  t outside the
  * domain is clamped to it.  curve_id[n], t[n], xyz_out[3n]: DEVICE.
  * Out-of-range ids give NaN.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */

@@ -359,6 +359,15 @@ def ferrari(c) -> np.ndarray:
     return r[:n].copy()
 
 
+def ferrari_01(c) -> np.ndarray:
+    """The split points of the refinement path: Ferrari's roots within [-0.5, 1.5], each polished by three Newton
+    steps on the full quartic (the reading for leading coefficients at rounding level), sorted."""
+    c = _d(c)
+    r = np.zeros(4)
+    n = _load().orc_ferrari_01(_dp(c), _dp(r))
+    return r[:n].copy()
+
+
 def rebase(a) -> np.ndarray:
     """Bernstein coefficients b = T a of a power-form polynomial (Sec. 5.3)."""
     a = _d(a)

@@ -328,6 +328,69 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_CLIP_M
     }
 }
 
+// Monotonic split of one (query, piece) pair: the roots of E' in (0, 1),
+// ascending.  kNewton: Newton's iteration from 8 uniform starts instead of
+// Ferrari's method.
+template <bool kNewton>
+__global__ __launch_bounds__(256) void k_split(DevGeom G, int64_t n, const int32_t* __restrict__ cid,
+                                               const int32_t* __restrict__ piece, const double* __restrict__ qxyz,
+                                               double* __restrict__ roots, int32_t* __restrict__ count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = cid[i];
+    if (c < 0 || c >= G.n_curves) { count[i] = -1; return; }
+    const DCurve cv = G.curves[c];
+    const int32_t k = piece[i];
+    if (k < 0 || k >= cv.n_seg) { count[i] = -1; return; }
+    const double q[3] = {qxyz[3 * i], qxyz[3 * i + 1], qxyz[3 * i + 2]};
+    Cubic<double> C;
+    load_cubic(G, cv, cv.seg_off + k, q, C);
+    const V3<double> a[4] = {C.a0, C.a1, C.a2, C.a3};
+    double E[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 1; m < 4; ++m) E[j + m - 1] += 2.0 * (double)m * dot(a[j], a[m]);
+    double ep[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ep[m] = (double)(m + 1) * E[m + 1];
+    double r[8];
+    int nr = 0;
+    if (!kNewton) {
+        double x[4];
+        const int nx = quartic_real(ep, x);
+        for (int j = 0; j < nx; ++j)
+            if (x[j] > 0.0 && x[j] < 1.0) r[nr++] = x[j];
+    } else {
+        const double scale = fabs(ep[0]) + fabs(ep[1]) + fabs(ep[2]) + fabs(ep[3]) + fabs(ep[4]);
+        for (int s = 0; s < 8; ++s) {
+            double u = (s + 0.5) / 8.0;
+            bool conv = false;
+            for (int it = 0; it < 20; ++it) {
+                const double f = fma(fma(fma(fma(ep[4], u, ep[3]), u, ep[2]), u, ep[1]), u, ep[0]);
+                const double fp = fma(fma(fma(4.0 * ep[4], u, 3.0 * ep[3]), u, 2.0 * ep[2]), u, ep[1]);
+                if (fp == 0.0) break;
+                const double du = f / fp;
+                u -= du;
+                if (fabs(du) <= 1e-14 * (1.0 + fabs(u))) { conv = fabs(f) <= 1e-10 * scale; break; }
+            }
+            if (!conv || !(u > 0.0 && u < 1.0)) continue;
+            bool dup = false;
+            for (int j = 0; j < nr; ++j) dup |= fabs(r[j] - u) <= 1e-9;
+            if (!dup && nr < 4) r[nr++] = u;
+        }
+    }
+    for (int j = 1; j < nr; ++j)
+        for (int m = j; m > 0 && r[m] < r[m - 1]; --m) {
+            const double t = r[m];
+            r[m] = r[m - 1];
+            r[m - 1] = t;
+        }
+    for (int j = 0; j < 4; ++j) roots[4 * i + j] = j < nr ? r[j] : 0.0;
+    count[i] = nr;
+}
+
 }  // namespace
 
 hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const double* q_xyz, const int32_t* perm,
@@ -341,3 +404,30 @@ hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const do
 }
 
 }  // namespace mrep
+
+extern "C" int32_t mrep_monotonic_split(const mrep_geom* geom, int64_t n, const int32_t* curve_id,
+                                        const int32_t* piece, const double* q_xyz, int32_t method,
+                                        double* roots_out, int32_t* count_out, void* stream)
+{
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES ||
+        (n > 0 && (!curve_id || !piece || !q_xyz || !roots_out || !count_out)) ||
+        (method != MREP_ROOTS_FERRARI && method != MREP_ROOTS_NEWTON)) {
+        mrep::set_error("mrep_monotonic_split: null pointer, surface geometry, negative n or unknown method");
+        return MREP_E_INVALID_ARG;
+    }
+    if (n == 0) return MREP_OK;
+    const mrep::DevGeom G = mrep::dev_view(geom->g);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (method == MREP_ROOTS_FERRARI)
+        hipLaunchKernelGGL(mrep::k_split<false>, grid, block, 0, (hipStream_t)stream, G, n, curve_id, piece, q_xyz,
+                           roots_out, count_out);
+    else
+        hipLaunchKernelGGL(mrep::k_split<true>, grid, block, 0, (hipStream_t)stream, G, n, curve_id, piece, q_xyz,
+                           roots_out, count_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        mrep::set_error(std::string("mrep_monotonic_split: ") + hipGetErrorString(e));
+        return MREP_E_HIP;
+    }
+    return MREP_OK;
+}

@@ -29,6 +29,7 @@ F_NN_FALLBACK = 128
 PREC_FP64, PREC_BF16 = 0, 3
 OPT_TIME_STAGES, OPT_TUNED, OPT_CLIP = 1, 2, 4
 STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
+ROOTS_FERRARI, ROOTS_NEWTON = 0, 1
 N_STAGES = 4
 MAX_DEGREE = 15
 NN_CURVE, NN_SURFACE = 0, 1
@@ -70,6 +71,7 @@ _project = _sig("mrep_project_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _v
 _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
 _set_strategy = _sig("mrep_set_curve_strategy", _i32, _vp, _i32)
+_split = _sig("mrep_monotonic_split", _i32, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp)
 _tune = _sig("mrep_tune_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
              C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp)
 _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
@@ -118,7 +120,7 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
-           "mrep_tune_curves", "mrep_set_curve_strategy"]
+           "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split"]
 
 
 class MrepError(RuntimeError):
@@ -541,6 +543,19 @@ class Geometry:
         _check(_eval(self._h, int(n), _vp(curve_id.data_ptr()), _vp(t.data_ptr()), _vp(xyz.data_ptr()),
                      _vp(stream)), "mrep_eval_curves")
         return xyz
+
+    def monotonic_split(self, curve_id, piece, q, method: int = ROOTS_FERRARI):
+        """Roots in (0, 1) of E' for each (query, piece) pair (Sec. 5.2.3): (roots[n, 4] ascending, count[n]);
+        count -1 for an out-of-range curve or piece.  method ROOTS_FERRARI or ROOTS_NEWTON."""
+        import torch
+
+        n = q.shape[0]
+        roots = torch.empty((n, 4), dtype=torch.float64, device=q.device)
+        count = torch.empty(n, dtype=torch.int32, device=q.device)
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_split(self._h, int(n), _vp(curve_id.data_ptr()), _vp(piece.data_ptr()), _vp(q.data_ptr()),
+                      int(method), _vp(roots.data_ptr()), _vp(count.data_ptr()), _vp(stream)), "mrep_monotonic_split")
+        return roots, count
 
     def close(self):
         if self._h:

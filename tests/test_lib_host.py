@@ -207,6 +207,7 @@ def test_seeding_network_sizes_and_host_errors():
     assert mrep._tune(None, None, 10, None, None, None, 0, None, None, None, None, None, None,
                       None) == mrep.E_INVALID_ARG
     assert mrep._set_strategy(None, 0) == mrep.E_INVALID_ARG
+    assert mrep._split(None, 1, None, None, None, mrep.ROOTS_FERRARI, None, None, None) == mrep.E_INVALID_ARG
 
 
 # --------------------------------------------------------------------------- surfaces
