@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 4
+#define MREP_ABI_VERSION 5
 
 /* status codes */
 #define MREP_OK 0
