@@ -389,11 +389,17 @@ def lattice_bench(args, dev):
 
     from paper_2504_11498_amd import gen, mrep, seeding
 
+    def say(msg):
+        print(f"[lattice {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
     n_curves = int(args.lattice_curves)
+    say(f"generating {n_curves} struts")
     curves = gen.curves_lattice_geometry(5, n_curves=n_curves)
     t0 = time.perf_counter()
+    say("decomposing on the host")
     plan = mrep.decompose_curves(curves, 1e-6)
     decompose_s = time.perf_counter() - t0
+    say(f"{plan.n_segments} pieces in {decompose_s:.1f} s; uploading")
     n_seg = np.diff(plan.export()["seg_off"])
     qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
     geom = plan.upload(dev)
@@ -409,10 +415,12 @@ def lattice_bench(args, dev):
     def plain():
         geom.project(q, cid, opts, workspace=ws, out=outs)
 
+    say(f"{n} queries; plain projection")
     for _ in range(max(1, args.warmup)):
         plain()
     ms, stage = _timed(plain, steps)
     del ws
+    say(f"plain {ms:.2f} ms per call; autotuner")
     res = {
         "workload": f"lattice struts: {n_curves} random-walk B-splines (degree 3..9, 64..1024 control points), "
                     f"{n:,} queries in proportion to cubic pieces",
@@ -434,6 +442,7 @@ def lattice_bench(args, dev):
     tuned()
     ms_t, _ = _timed(tuned, steps)
     del tws
+    say(f"tuned ({['screen', 'spheres'][strat]}) {ms_t:.2f} ms per call")
     res["tuned"] = {"strategy": ["screen", "spheres"][strat], "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
                     "value": n / (ms_t / 1e3), "unit": "projections/s", "ms_per_step": ms_t}
     if args.no_seeded:
