@@ -23,6 +23,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "point projections/s (err≤1e-6·bbox), plain vs NN-seeded, curves+surfaces"
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 FLOPS_PER_SAMPLE = 2 * 32  # one 16x16x32 MFMA output element per (query, piece, sample)
 
 
@@ -66,6 +67,7 @@ def main():
     ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--no-surfaces", action="store_true", help="skip the batched-surfaces workload")
     ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-strut curves workload")
+    ap.add_argument("--no-spans", action="store_true", help="skip the device span decomposition block")
     ap.add_argument("--no-clip", action="store_true",
                     help="skip the batched curves with the paper's refinement path (MREP_OPT_CLIP)")
     ap.add_argument("--no-extras", action="store_true",
@@ -203,6 +205,9 @@ def main():
     if not args.no_lattice:
         torch.cuda.empty_cache()
         result["lattice"] = lattice_bench(args, dev)
+    if not args.no_spans:
+        torch.cuda.empty_cache()
+        result["span_decomposition"] = span_decomposition(curves, args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(curves, qs, outs, args.cpu_seconds)
     print(json.dumps(result), flush=True)
@@ -323,6 +328,42 @@ def clip_refiner(geom, q, cid, plain_outs, curves, plain_value, plain_stage, ws,
         "vs_plain_max_dist_rel": dd,
         "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
     }
+
+
+def span_decomposition(curves, args, dev):
+    """The exact Bezier form of every knot interval on the device (mrep_span_bezier_curves), for the batched curves
+    and for 65,536 lattice struts.  Algorithmic bytes per launch: every control point, knot and per-curve offset
+    read once, every Bezier point and interval end written once."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep
+
+    out = {}
+    for name, make in (("batched_curves", lambda: curves),
+                       ("lattice_struts_65536", lambda: gen.curves_lattice_geometry(5, n_curves=65_536))):
+        cv = make()
+        dc = mrep.DeviceCurves(cv, dev)
+        bz, t = dc.span_bezier()
+        for _ in range(args.warmup):
+            dc.span_bezier(bz, t)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dc.span_bezier(bz, t)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / args.steps
+        n_c = cv.n
+        alg = (cv.cp.size * 8 + cv.knots.size * 8 + n_c * 4 + 4 * (n_c + 1) * 8 +
+               dc.n_points * 24 + dc.n_intervals * 16)
+        out[name] = {"curves": int(n_c), "intervals": dc.n_intervals, "bezier_points": dc.n_points,
+                     "us_per_launch": us, "intervals_per_s": dc.n_intervals / (us * 1e-6),
+                     "algorithmic_bytes": int(alg), "achieved_GBps": alg / (us * 1e-6) / 1e9,
+                     "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+        print(f"[bench] span decomposition {name}: {us:.1f} us", file=sys.stderr, flush=True)
+        del dc, bz, t
+        torch.cuda.empty_cache()
+    return out
 
 
 def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):

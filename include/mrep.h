@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 5
+#define MREP_ABI_VERSION 6
 
 /* status codes */
 #define MREP_OK 0
@@ -228,6 +228,40 @@ int32_t mrep_monotonic_split(const mrep_geom* geom, int64_t n, const int32_t* cu
  * Out-of-range ids give NaN.  Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
 int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* t,
                          double* xyz_out, void* stream);
+
+/* Span decomposition on the device (Sec. 5.2.1, eqs. `decomposition` and
+ * `decomfinal`): the exact degree-p Bezier form of every knot interval of a
+ * batch of clamped B-spline curves, one thread per interval, FP64.  Curve c
+ * has n_c = cp_off[c+1] - cp_off[c] control points and n_c - p_c knot
+ * intervals [U_q, U_{q+1}], q = p_c .. n_c - 1; the Bezier points of each are
+ * the blossom values P(U_q^(p-j), U_{q+1}^(j)), j = 0..p, the same points as
+ * B_p^{-1} M A P.
+ *
+ * mrep_span_layout (HOST only): iv_off[n_curves+1] and pt_off[n_curves+1]
+ * receive the offsets of each curve's intervals and of its Bezier points:
+ * iv_off[c+1] = iv_off[c] + n_c - p_c, pt_off[c+1] = pt_off[c] + (n_c - p_c)(p_c + 1).
+ *   Errors: MREP_E_INVALID_ARG, MREP_E_BAD_DEGREE (degree out of range or
+ *   fewer than p + 1 points), MREP_E_BAD_KNOTS (knot count not n_c + p_c + 1).
+ *
+ * mrep_span_bezier_curves: every pointer DEVICE.  max_degree (1..MREP_MAX_DEGREE):
+ * at least the largest degree in the batch; it picks the kernel instance, and
+ * an interval of a curve of higher degree writes NaN to t_out only.  degree, cp_off, knot_off,
+ * cp_xyz, knots: the arrays of mrep_decompose_curves; iv_off, pt_off: the
+ * output of mrep_span_layout for the same curves, and n_intervals =
+ * iv_off[n_curves].  Interval k of curve c writes its p_c + 1 points (xyz
+ * interleaved) to bz_out[3 (pt_off[c] + k (p_c + 1)) ..] and [U_q, U_{q+1}] to
+ * t_out[2 (iv_off[c] + k) ..].  A zero-length interval (repeated knot) writes
+ * NaN points; an interval whose curve's counts disagree with iv_off / pt_off
+ * writes NaN to t_out only.  Knots must be non-decreasing; they are not
+ * checked.  Enqueued on stream; nothing is allocated.
+ *   Errors: MREP_E_INVALID_ARG (null pointers with n_intervals > 0, negative
+ *   counts, max_degree out of range), MREP_E_HIP. */
+int32_t mrep_span_layout(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const int64_t* knot_off,
+                         int64_t* iv_off, int64_t* pt_off);
+int32_t mrep_span_bezier_curves(int32_t n_curves, int64_t n_intervals, int32_t max_degree, const int32_t* degree,
+                                const int64_t* cp_off, const int64_t* knot_off, const int64_t* iv_off, const int64_t* pt_off,
+                                const double* cp_xyz, const double* knots, double* bz_out, double* t_out,
+                                void* stream);
 
 /* Autotuner (BF16 mode): projects the batch with each strategy (one untimed
  * and two timed runs each, HIP events on `stream`), keeps the faster one for

@@ -72,6 +72,8 @@ _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp,
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
 _set_strategy = _sig("mrep_set_curve_strategy", _i32, _vp, _i32)
 _split = _sig("mrep_monotonic_split", _i32, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp)
+_span_layout = _sig("mrep_span_layout", _i32, _i32, _pi32, _pi64, _pi64, _pi64, _pi64)
+_span_bezier = _sig("mrep_span_bezier_curves", _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _tune = _sig("mrep_tune_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
              C.POINTER(C.c_int32), C.POINTER(C.c_double), _vp)
 _bern = _sig("mrep_bernstein_matrix", _i32, _i32, _i32, _pd)
@@ -120,7 +122,8 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
-           "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split"]
+           "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split", "mrep_span_layout",
+           "mrep_span_bezier_curves"]
 
 
 class MrepError(RuntimeError):
@@ -232,6 +235,59 @@ def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:
                       _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel), int(n_threads), C.byref(h)),
            "mrep_decompose_curves")
     return Plan(h.value)
+
+
+def span_layout(curves):
+    """mrep_span_layout: (iv_off, pt_off), the offsets of each curve's knot intervals and of their Bezier points."""
+    deg = _host(curves.degree, np.int32)
+    cp_off = _host(curves.cp_off, np.int64)
+    k_off = _host(curves.knot_off, np.int64)
+    n = int(deg.shape[0])
+    iv_off = np.zeros(n + 1, np.int64)
+    pt_off = np.zeros(n + 1, np.int64)
+    _check(_span_layout(n, _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(k_off, C.c_int64), _p(iv_off, C.c_int64),
+                        _p(pt_off, C.c_int64)), "mrep_span_layout")
+    return iv_off, pt_off
+
+
+class DeviceCurves:
+    """A CSR batch of curves resident on the device, with its span layout, for mrep_span_bezier_curves."""
+
+    def __init__(self, curves, device=None):
+        import torch
+
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.iv_off, self.pt_off = span_layout(curves)
+        self.n_curves = int(np.asarray(curves.degree).shape[0])
+        self.n_intervals = int(self.iv_off[-1])
+        self.n_points = int(self.pt_off[-1])
+        self.max_degree = int(np.max(curves.degree)) if self.n_curves else 1
+        up = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+        self.degree = up(curves.degree, np.int32)
+        self.cp_off = up(curves.cp_off, np.int64)
+        self.knot_off = up(curves.knot_off, np.int64)
+        self.iv = up(self.iv_off, np.int64)
+        self.pt = up(self.pt_off, np.int64)
+        self.cp = up(curves.cp, np.float64)
+        self.knots = up(curves.knots, np.float64)
+        self.device = dev
+
+    def span_bezier(self, bz=None, t=None):
+        """mrep_span_bezier_curves: (bz [n_points, 3], t [n_intervals, 2]) device tensors (FP64)."""
+        import torch
+
+        if bz is None:
+            bz = torch.empty((self.n_points, 3), dtype=torch.float64, device=self.device)
+        if t is None:
+            t = torch.empty((self.n_intervals, 2), dtype=torch.float64, device=self.device)
+        if bz.numel() < 3 * self.n_points or t.numel() < 2 * self.n_intervals:
+            raise ValueError("output tensors too small")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(_span_bezier(self.n_curves, self.n_intervals, self.max_degree, _vp(self.degree.data_ptr()), _vp(self.cp_off.data_ptr()),
+                            _vp(self.knot_off.data_ptr()), _vp(self.iv.data_ptr()), _vp(self.pt.data_ptr()),
+                            _vp(self.cp.data_ptr()), _vp(self.knots.data_ptr()), _vp(bz.data_ptr()),
+                            _vp(t.data_ptr()), _vp(stream)), "mrep_span_bezier_curves")
+        return bz, t
 
 
 def decompose_surfaces(surfs, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:

@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 5
+    assert mrep.abi_version() == 6
 
 
 def test_rebasement_matrix_matches_printed_T5():
@@ -165,6 +165,36 @@ def test_error_codes():
     assert mrep._ws_bytes(None, 10, C.byref(o), C.byref(b)) == mrep.E_INVALID_ARG
     assert mrep._project(None, C.byref(o), 10, None, None, None, 0, None, None, None, None, None) == mrep.E_INVALID_ARG
     assert mrep._upload(None, None, 0, None, None) == mrep.E_INVALID_ARG
+
+
+def test_span_layout_offsets_and_errors():
+    """mrep_span_layout: one interval per q = p .. n - 1 and p + 1 points per interval; bad counts are rejected; the
+    device call rejects null pointers before it launches anything."""
+    curves = gen.curves_batched_geometry(2, n_curves=64)
+    iv, pt = mrep.span_layout(curves)
+    n_cp = np.diff(curves.cp_off)
+    np.testing.assert_array_equal(np.diff(iv), n_cp - curves.degree)
+    np.testing.assert_array_equal(np.diff(pt), (n_cp - curves.degree) * (curves.degree + 1))
+    assert iv[0] == 0 and pt[0] == 0
+    P = np.random.default_rng(0).uniform(0, 1, (6, 3))
+    U = np.array([0, 0, 0, 0, 0.4, 0.6, 1, 1, 1, 1.0])
+    cases = [
+        (_curveset(0, P, U[2:-2]), mrep.E_BAD_DEGREE),
+        (_curveset(16, np.zeros((20, 3)), np.linspace(0, 1, 37)), mrep.E_BAD_DEGREE),
+        (_curveset(3, P[:3], np.array([0, 0, 0, 0, 1, 1, 1.0])), mrep.E_BAD_DEGREE),
+        (_curveset(3, P, U[:-1]), mrep.E_BAD_KNOTS),
+    ]
+    for cv, code in cases:
+        with pytest.raises(mrep.MrepError) as ei:
+            mrep.span_layout(cv)
+        assert ei.value.code == code, (ei.value, code)
+    assert mrep._span_layout(-1, None, None, None, None, None) == mrep.E_INVALID_ARG
+    nul = (None,) * 10
+    assert mrep._span_bezier(1, 5, 3, *nul) == mrep.E_INVALID_ARG
+    assert mrep._span_bezier(0, -1, 3, *nul) == mrep.E_INVALID_ARG
+    assert mrep._span_bezier(0, 0, 0, *nul) == mrep.E_INVALID_ARG
+    assert mrep._span_bezier(0, 0, 16, *nul) == mrep.E_INVALID_ARG
+    assert mrep._span_bezier(0, 0, 15, *nul) == mrep.OK
 
 
 def test_piece_cap_is_reported():
