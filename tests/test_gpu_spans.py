@@ -141,3 +141,34 @@ def test_spans_minimal_curves_and_empty_batch(mrep):
     b0, t0 = d0.span_bezier()
     torch.cuda.synchronize()
     assert b0.numel() == 0 and t0.numel() == 0
+
+
+def test_spans_full_size_lattice_sampled(mrep):
+    """All 65,536 lattice struts (35.2M intervals, the size the benchmark times): every interval end checked against the
+    knots, and 60 sampled curves' Bezier points against the oracle, gathered on the device."""
+    _say("[case] device spans, 65,536 lattice struts, 60 sampled curves")
+    curves = gen.curves_lattice_geometry(5, n_curves=65_536)
+    dc = mrep.DeviceCurves(curves)
+    bz, t = dc.span_bezier()
+    torch.cuda.synchronize()
+    assert dc.n_intervals == int(np.sum(np.diff(curves.cp_off) - curves.degree))
+    # interval ends: [U_q, U_q+1] for q = p .. n - 1 of every curve (built on the host from the knots)
+    q0 = np.concatenate([curves.knot_off[c] + curves.degree[c] + np.arange(curves.cp_off[c + 1] - curves.cp_off[c]
+                                                                            - curves.degree[c])
+                         for c in range(0, curves.n, 97)])
+    ivs = np.concatenate([dc.iv_off[c] + np.arange(dc.iv_off[c + 1] - dc.iv_off[c]) for c in range(0, curves.n, 97)])
+    tt = t[torch.from_numpy(ivs).cuda()].cpu().numpy()
+    np.testing.assert_array_equal(tt[:, 0], curves.knots[q0])
+    np.testing.assert_array_equal(tt[:, 1], curves.knots[q0 + 1])
+    pick = np.sort(np.random.default_rng(23).choice(curves.n, 60, replace=False))
+    for c in pick:
+        p, P, U = curves.curve(c)
+        ref_bz, _ = oracle.bezier_spans(p, P, U)
+        rows = torch.arange(int(dc.pt_off[c]), int(dc.pt_off[c + 1]), device=bz.device)
+        got = bz[rows].cpu().numpy().reshape(-1, p + 1, 3)
+        tc = t[int(dc.iv_off[c]) : int(dc.iv_off[c + 1])].cpu().numpy()
+        live = tc[:, 0] < tc[:, 1]
+        assert int(live.sum()) == ref_bz.shape[0]
+        err = np.max(np.abs(got[live] - ref_bz)) / np.max(np.abs(P))
+        assert err <= 1e-13 * p, (c, p, err)
+    _say(f"[ok] full-size lattice: {dc.n_intervals} intervals, {dc.n_points} Bezier points, 60 curves sampled")
