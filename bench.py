@@ -44,6 +44,19 @@ def _traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def _span_traffic():
+    """HBM bytes per span-decomposition launch, per workload, from committed rocprofv3 counter runs, if still current."""
+    path = os.path.join(ROOT, "profiles", "span_bezier_curves_traffic.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "paper_2504_11498_amd", "csrc", "mrep_spans.hip"), "rb") as f:
+        if rec.get("kernel_source_sha256_16") != hashlib.sha256(f.read()).hexdigest()[:16]:
+            return {}
+    return {k: v.get("hbm_bytes_per_launch") for k, v in rec.get("workloads", {}).items()}
+
+
 def summarize_rocprof(path):
     """Per-kernel duration summary (calls, mean/min/max microseconds, total ms) of a rocprofv3 SQLite result."""
     import sqlite3
@@ -339,6 +352,7 @@ def span_decomposition(curves, args, dev):
     from paper_2504_11498_amd import gen, mrep
 
     out = {}
+    traffic = _span_traffic()
     for name, make in (("batched_curves", lambda: curves),
                        ("lattice_struts_65536", lambda: gen.curves_lattice_geometry(5, n_curves=65_536))):
         cv = make()
@@ -359,7 +373,7 @@ def span_decomposition(curves, args, dev):
         out[name] = {"curves": int(n_c), "intervals": dc.n_intervals, "bezier_points": dc.n_points,
                      "us_per_launch": us, "intervals_per_s": dc.n_intervals / (us * 1e-6),
                      "algorithmic_bytes": int(alg), "achieved_GBps": alg / (us * 1e-6) / 1e9,
-                     "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+                     "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS, "traffic": traffic.get(name)}
         print(f"[bench] span decomposition {name}: {us:.1f} us", file=sys.stderr, flush=True)
         del dc, bz, t
         torch.cuda.empty_cache()
