@@ -6,8 +6,10 @@ non-uniform knots with 10% doubled), decomposed to cubic Bezier pieces at
 offsets of 0.05 * diagonal from parameter-uniform curve points).  One step is
 one projection of all queries: BF16 MFMA screen, FP32 Newton, FP64 polish.
 
-Prints one JSON line (see the design doc for every field).  ``--gpus`` above 1 is
-refused: this build runs on one GPU.
+Prints one JSON line: the headline throughput with its roofline and the CPU
+oracle baseline, plus blocks for the surface, lattice, seeded, clip-refiner and
+span-decomposition workloads.  ``--gpus`` above 1 is refused: the library runs
+on one GPU per process.
 """
 from __future__ import annotations
 
@@ -107,7 +109,7 @@ def main():
         print("copied 3 x 512 MiB", flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
