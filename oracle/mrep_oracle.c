@@ -210,6 +210,30 @@ static void or_curve_eval(const or_curve *c, double t, double *X, double *D1, do
     }
 }
 
+/* de Boor on the polynomial piece of knot span k (U[k] <= t < U[k+1]), also
+ * at the span's right end: the one-sided limit from the left at a knot. */
+static void or_deboor_k(int p, const double *P, const double *U, int k, double t, double *out)
+{
+    double d[OR_MAXP + 1][3];
+    for (int j = 0; j <= p; ++j)
+        for (int c = 0; c < 3; ++c) d[j][c] = P[3 * (j + k - p) + c];
+    for (int r = 1; r <= p; ++r)
+        for (int j = p; j >= r; --j) {
+            double den = U[j + 1 + k - r] - U[j + k - p];
+            double a = den != 0.0 ? (t - U[j + k - p]) / den : 0.0;
+            for (int c = 0; c < 3; ++c) d[j][c] = (1.0 - a) * d[j - 1][c] + a * d[j][c];
+        }
+    out[0] = d[p][0]; out[1] = d[p][1]; out[2] = d[p][2];
+}
+
+/* C and C' from the piece of span k (the derivative curve's span is k - 1). */
+static void or_curve_eval_k(const or_curve *c, int k, double t, double *X, double *D1)
+{
+    or_deboor_k(c->p, c->P, c->U, k, t, X);
+    if (c->p >= 1) or_deboor_k(c->p - 1, c->P1, c->U + 1, k - 1, t, D1);
+    else D1[0] = D1[1] = D1[2] = 0.0;
+}
+
 int orc_eval(int p, int n, const double *P, const double *U, int64_t m, const double *t,
              double *X, double *D1, double *D2)
 {
@@ -632,6 +656,10 @@ void orc_dec_free(void *hv)
 /* ------------------------------------------------------------------------ */
 
 #define OR_NS 64      /* samples per span, ends included */
+/* Local minima within this distance of the best one (relative to the box
+ * diagonal) are searched for with the same certified branch and bound, so that
+ * the runner-up is exact whenever it matters to the uniqueness test (2e-6). */
+#define OR_RUNNER_MARGIN 4e-6
 #define OR_MAXMIN 256 /* recorded local minima per query */
 
 typedef struct {
@@ -644,6 +672,7 @@ typedef struct {
     const double *q;
     double best_d, best_t;
     int best_span;
+    double margin; /* intervals whose bound is within this of the best are searched too (runner-up) */
     or_min mins[OR_MAXMIN];
     int nmin;
 } or_query;
@@ -722,7 +751,12 @@ static void or_local_min(or_query *Q, int span, double a, double b, double t0)
     }
     double f, fp, d;
     or_orth(c, q, t, &f, &fp, &d);
-    or_record(Q, t, d, (t > a && t < b), span);
+    /* interior only when the end point is a stationary minimum within rounding */
+    double X[3], D1[3];
+    or_curve_eval(c, t, X, D1, NULL);
+    double sp = sqrt(D1[0] * D1[0] + D1[1] * D1[1] + D1[2] * D1[2]);
+    int stat = fabs(f) <= 1e-9 * sp * (d + c->diag) && fp > 0.0;
+    or_record(Q, t, d, (t > a && t < b) && stat, span);
 }
 
 static int or_contains_min(const or_query *Q, double a, double b)
@@ -744,7 +778,7 @@ static void or_bb(or_query *Q, int span, double L1, double L2, double a, double 
 {
     double w = b - a;
     double lb = 0.5 * (da + db) - 0.5 * L1 * w;
-    if (lb >= Q->best_d) return;
+    if (lb >= Q->best_d + Q->margin) return;
     if (or_contains_min(Q, a, b)) return;
     double fa, fpa, fb, fpb, dd;
     or_orth(Q->c, Q->q, a, &fa, &fpa, &dd);
@@ -771,6 +805,7 @@ static void or_project_one(const or_curve *c, const double *q, double *t_out, do
 {
     or_query Q;
     Q.c = c; Q.q = q; Q.best_d = INFINITY; Q.best_t = 0.0; Q.best_span = 0; Q.nmin = 0;
+    Q.margin = OR_RUNNER_MARGIN * c->diag;
     double ts[OR_NS], ds[OR_NS];
     double *allt = (double *)malloc(sizeof(double) * (size_t)c->nspan * OR_NS);
     double *alld = (double *)malloc(sizeof(double) * (size_t)c->nspan * OR_NS);
@@ -810,6 +845,23 @@ static void or_project_one(const or_curve *c, const double *q, double *t_out, do
         if (fabs(Q.mins[i].t - Q.best_t) <= 1e-6) continue;
         /* distinct local minima: interior stationary points */
         if (Q.mins[i].d < runner && Q.mins[i].interior) runner = Q.mins[i].d;
+    }
+    /* ... the interior knots where the curve is only C0 and the distance falls
+     * on the left of the joint and rises on its right (a corner minimum, with
+     * no stationary point: both one-sided derivatives of |C - q|^2 are used) */
+    for (int s = 1; s < c->nspan; ++s) {
+        const int kl = c->span_k[s - 1], kr = c->span_k[s];
+        const double tj = c->U[kr];
+        double XL[3], DL[3], XR[3], DR[3];
+        or_curve_eval_k(c, kl, tj, XL, DL);
+        or_curve_eval_k(c, kr, tj, XR, DR);
+        const double fl = (XL[0] - q[0]) * DL[0] + (XL[1] - q[1]) * DL[1] + (XL[2] - q[2]) * DL[2];
+        const double fr = (XR[0] - q[0]) * DR[0] + (XR[1] - q[1]) * DR[1] + (XR[2] - q[2]) * DR[2];
+        if (fl < 0.0 && fr > 0.0 && fabs(tj - Q.best_t) > 1e-6) {
+            const double dj = sqrt((XR[0] - q[0]) * (XR[0] - q[0]) + (XR[1] - q[1]) * (XR[1] - q[1]) +
+                                   (XR[2] - q[2]) * (XR[2] - q[2]));
+            if (dj < runner) runner = dj;
+        }
     }
     /* ... and the domain ends when the distance grows into the domain there */
     {

@@ -145,6 +145,7 @@ typedef struct {
     double rect[4];
     double lo[3], hi[3];               /* control-net box */
     double Lu, Lv, Luu, Lvv;           /* bounds of |S_u|, |S_v|, |S_uu|, |S_vv| from the hodograph nets */
+    int dom;                           /* sides on the domain boundary: 1 s=0, 2 s=1, 4 t=0, 8 t=1 */
 } os_patch;
 
 /* derivative nets of one patch, built when the patch is searched */
@@ -264,6 +265,9 @@ static double os_f(const os_patch *pt, const double *x, double s, double t)
 #define OS_MAXCAND 256
 typedef struct {
     double u, v, f;  /* global parameters, squared distance */
+    int out;         /* sides (as os_patch.dom) inside the domain where the point is held with the
+                        gradient pointing across: a minimum of the patch, not of the surface */
+    const os_patch *pt;
 } os_cand;
 
 typedef struct {
@@ -282,7 +286,7 @@ static void os_update_thresh(os_query *Q)
     Q->thresh_f = d * d;
 }
 
-static void os_record(os_query *Q, const os_patch *pt, double s, double t, double f, double kappa)
+static void os_record(os_query *Q, const os_patch *pt, double s, double t, double f, double kappa, int out)
 {
     const double u = pt->rect[0] + s * (pt->rect[1] - pt->rect[0]);
     const double v = pt->rect[2] + t * (pt->rect[3] - pt->rect[2]);
@@ -293,18 +297,28 @@ static void os_record(os_query *Q, const os_patch *pt, double s, double t, doubl
         Q->best_kappa = kappa;
         os_update_thresh(Q);
     }
+    /* the same point of the same patch, reached again from another start,
+     * is one candidate: duplicates of the best must not evict the runner-up */
+    for (int i = 0; i < Q->ncand; ++i)
+        if (Q->cand[i].pt == pt && fabs(Q->cand[i].u - u) <= 1e-9 && fabs(Q->cand[i].v - v) <= 1e-9) {
+            if (f < Q->cand[i].f) { Q->cand[i].f = f; Q->cand[i].out = out; }
+            return;
+        }
+    int w = Q->ncand;
     if (Q->ncand < OS_MAXCAND) {
-        Q->cand[Q->ncand].u = u;
-        Q->cand[Q->ncand].v = v;
-        Q->cand[Q->ncand].f = f;
         Q->ncand++;
     } else {
         /* keep the candidates with the smallest f */
-        int w = 0;
+        w = 0;
         for (int i = 1; i < OS_MAXCAND; ++i)
             if (Q->cand[i].f > Q->cand[w].f) w = i;
-        if (f < Q->cand[w].f) { Q->cand[w].u = u; Q->cand[w].v = v; Q->cand[w].f = f; }
+        if (!(f < Q->cand[w].f)) return;
     }
+    Q->cand[w].u = u;
+    Q->cand[w].v = v;
+    Q->cand[w].f = f;
+    Q->cand[w].out = out;
+    Q->cand[w].pt = pt;
 }
 
 /* Conditioning of a minimiser: smallest generalised eigenvalue of
@@ -405,7 +419,13 @@ static void os_newton(os_query *Q, const os_pwork *w, double s, double t)
     const int ok_t = fabs(gt) <= tol_t || (t == 0.0 && gt > 0.0) || (t == 1.0 && gt < 0.0);
     if (ok_s && ok_t) {
         const int interior = s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0;
-        os_record(Q, pt, s, t, f, interior ? os_kappa(S, Su, Sv, Suu, Suv, Svv, x) : 1.0);
+        int out = 0;
+        if (s == 0.0 && gs > tol_s) out |= 1;
+        if (s == 1.0 && gs < -tol_s) out |= 2;
+        if (t == 0.0 && gt > tol_t) out |= 4;
+        if (t == 1.0 && gt < -tol_t) out |= 8;
+        out &= ~pt->dom;
+        os_record(Q, pt, s, t, f, interior ? os_kappa(S, Su, Sv, Suu, Suv, Svv, x) : 1.0, out);
     }
 }
 
@@ -537,8 +557,20 @@ static int os_surf_build(os_surf *S, int p, int q, int nu, int nv, const double 
     if (np < 0) { free(nets); free(rects); return -1; }
     S->np = np;
     S->pts = (os_patch *)malloc(sizeof(os_patch) * (size_t)(np > 0 ? np : 1));
-    for (int k = 0; k < np; ++k)
-        os_patch_init(&S->pts[k], p, q, nets + 3 * (size_t)k * (p + 1) * (q + 1), rects + 4 * (size_t)k);
+    double dom[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int k = 0; k < np; ++k) {
+        const double *r = rects + 4 * (size_t)k;
+        if (r[0] < dom[0]) dom[0] = r[0];
+        if (r[1] > dom[1]) dom[1] = r[1];
+        if (r[2] < dom[2]) dom[2] = r[2];
+        if (r[3] > dom[3]) dom[3] = r[3];
+    }
+    for (int k = 0; k < np; ++k) {
+        const double *r = rects + 4 * (size_t)k;
+        os_patch_init(&S->pts[k], p, q, nets + 3 * (size_t)k * (p + 1) * (q + 1), r);
+        S->pts[k].dom = (r[0] == dom[0] ? 1 : 0) | (r[1] == dom[1] ? 2 : 0) | (r[2] == dom[2] ? 4 : 0) |
+                        (r[3] == dom[3] ? 8 : 0);
+    }
     S->nets = nets;
     free(rects);
     return 0;
@@ -583,10 +615,20 @@ static void os_project_one(const os_surf *S, const double *x, double margin, dou
     double rn = INFINITY;
     for (int i = 0; i < Q.ncand; ++i) {
         const double du = Q.cand[i].u - Q.best_u, dv = Q.cand[i].v - Q.best_v;
-        if (sqrt(du * du + dv * dv) > 1e-6) {
-            const double d = sqrt(Q.cand[i].f);
-            if (d < rn) rn = d;
+        if (!(sqrt(du * du + dv * dv) > 1e-6)) continue;
+        /* a point held on a side inside the domain with the gradient pointing
+         * across is the minimum of its patch only: the surface goes on falling
+         * in the neighbour, unless the neighbour's search stopped at the same
+         * point against the same side (a crease where the surface is only C0) */
+        if (Q.cand[i].out) {
+            int crease = 0;
+            for (int j = 0; j < Q.ncand && !crease; ++j)
+                crease = j != i && Q.cand[j].pt != Q.cand[i].pt && Q.cand[j].out &&
+                         fabs(Q.cand[j].u - Q.cand[i].u) <= 1e-8 && fabs(Q.cand[j].v - Q.cand[i].v) <= 1e-8;
+            if (!crease) continue;
         }
+        const double d = sqrt(Q.cand[i].f);
+        if (d < rn) rn = d;
     }
     *runner = rn;
 }
