@@ -195,6 +195,25 @@ int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_
                             const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
                             double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
 
+/* Allocation-free projection, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs, options and answers as
+ * mrep_project_curves, without the workspace: the kernels use a fixed scratch
+ * array of MREP_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on each
+ * GPU it runs on until the process ends.  The call itself allocates nothing
+ * (no hipMalloc, no library allocation).  The scratch is found once per device
+ * with that device current (the first call on it).  Every call on a GPU shares
+ * that GPU's scratch and each call clears what it needs, so calls that may
+ * overlap on one GPU (two streams, two host threads) race: order them.
+ * Errors: MREP_E_SMALL_BUFFER when mrep_workspace_bytes(geom, n, opts) exceeds
+ * the scratch (about 500k queries at the default options: split the batch),
+ * MREP_E_INVALID_ARG (as mrep_project_curves, and MREP_OPT_TIME_STAGES, whose
+ * events would be created), MREP_E_HIP. */
+#define MREP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int32_t mrep_project_curves_noalloc(const mrep_geom* geom, const mrep_opts* opts, int64_t n,
+                                    const int32_t* curve_id, const double* q_xyz, double* t_out,
+                                    double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
+
 /* Inversion (Sec. 4, eq. inversion): as mrep_project_curves, and additionally
  * sets MREP_F_OFFCURVE where the distance exceeds the curve's tolerance
  * tol_rel * diag (the point is then not on the curve). */

@@ -29,6 +29,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/mrep.h"
@@ -851,6 +852,41 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
 
 int64_t mrep::project_ws_bytes(int64_t n_curves, int64_t n, int kc) { return work_layout(n_curves, n, kc, nullptr, nullptr); }
 
+// Scratch of the allocation-free entry point: one fixed array per GPU, held
+// until the process ends.  Host code must never pass `scratch` itself to a
+// kernel (in host code it names a host-side stand-in); it uses the device
+// address hipGetSymbolAddress returns, looked up once per device with that
+// device current.  Every call on a GPU shares that GPU's array, so calls that
+// may overlap on one GPU race; each call clears what it needs cleared with its
+// own fill kernels, like a call on caller-owned workspace.
+constexpr int64_t kNoAllocScratchBytes = MREP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+constexpr int kNoAllocMaxDevices = 64;
+static char* g_scratch_dev[kNoAllocMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static int noalloc_scratch(char** out)
+{
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("mrep_project_curves_noalloc: device ordinal beyond the scratch table");
+        return MREP_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255) != 0) {
+            set_error("mrep_project_curves_noalloc: scratch symbol address missing or misaligned");
+            return MREP_E_HIP;
+        }
+        g_scratch_dev[dev] = (char*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return MREP_OK;
+}
+
 static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
                            const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
                            int32_t* seg_out, uint32_t* flags_out, void* stream, int invert, int strategy = -1)
@@ -914,6 +950,36 @@ int32_t mrep_invert_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t
 {
     return run_project(geom, opts, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
                        stream, 1);
+}
+
+int32_t mrep_project_curves_noalloc(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
+                                    const double* q_xyz, double* t_out, double* dist_out, int32_t* seg_out,
+                                    uint32_t* flags_out, void* stream)
+{
+    const char* fn = "mrep_project_curves_noalloc";
+    if (!geom || n < 0 || geom->kind != MREP_GEOM_CURVES) {
+        set_error(std::string(fn) + ": null or surface geometry, or negative n");
+        return MREP_E_INVALID_ARG;
+    }
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (opts->flags & MREP_OPT_TIME_STAGES) {
+        set_error(std::string(fn) + ": MREP_OPT_TIME_STAGES creates events; use mrep_project_curves to time stages");
+        return MREP_E_INVALID_ARG;
+    }
+    int64_t need = 0;
+    if ((rc = mrep_workspace_bytes(geom, n, opts, &need))) return rc;
+    if (need > kNoAllocScratchBytes) {
+        set_error(std::string(fn) + ": " + std::to_string(n) + " queries need " + std::to_string(need) +
+                  " bytes of scratch, more than the library's fixed " + std::to_string(kNoAllocScratchBytes) +
+                  " (MREP_NOALLOC_SCRATCH_BYTES); split the batch or use mrep_project_curves");
+        return MREP_E_SMALL_BUFFER;
+    }
+    if (n == 0) return MREP_OK;
+    char* ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
+    return run_project(geom, opts, n, curve_id, q_xyz, ws, kNoAllocScratchBytes, t_out, dist_out, seg_out, flags_out,
+                       stream, 0);
 }
 
 int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,

@@ -68,6 +68,9 @@ _geom_release = _sig("mrep_geom_release", None, _vp)
 _opts_default = _sig("mrep_opts_default", _i32, C.POINTER(Opts))
 _ws_bytes = _sig("mrep_workspace_bytes", _i32, _vp, _i64, C.POINTER(Opts), C.POINTER(C.c_int64))
 _project = _sig("mrep_project_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
+_project_noalloc = _sig("mrep_project_curves_noalloc", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                        _vp)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
 _set_strategy = _sig("mrep_set_curve_strategy", _i32, _vp, _i32)
@@ -123,7 +126,7 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
            "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split", "mrep_span_layout",
-           "mrep_span_bezier_curves"]
+           "mrep_span_bezier_curves", "mrep_project_curves_noalloc"]
 
 
 class MrepError(RuntimeError):
@@ -401,6 +404,26 @@ class Geometry:
         _check(fn(self._h, C.byref(opts), int(n), _vp(curve_id.data_ptr()), _vp(q.data_ptr()), _vp(ws.data_ptr()),
                   int(ws.numel()), _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
                   _vp(stream)), "mrep_invert_curves" if invert else "mrep_project_curves")
+        return t, d, s, f
+
+    def project_noalloc(self, q, curve_id, opts: Opts | None = None, out=None):
+        """As project(), through mrep_project_curves_noalloc: no workspace, the library's fixed per-GPU scratch."""
+        import torch
+
+        if opts is None:
+            opts = default_opts()
+        assert q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and q.dim() == 2 and q.shape[1] == 3
+        assert curve_id.is_cuda and curve_id.dtype == torch.int32 and curve_id.is_contiguous()
+        n = q.shape[0]
+        assert curve_id.shape[0] == n
+        if out is None:
+            out = (torch.empty(n, dtype=torch.float64, device=q.device), torch.empty(n, dtype=torch.float64, device=q.device),
+                   torch.empty(n, dtype=torch.int32, device=q.device), torch.empty(n, dtype=torch.int32, device=q.device))
+        t, d, s, f = out
+        stream = torch.cuda.current_stream(q.device).cuda_stream
+        _check(_project_noalloc(self._h, C.byref(opts), int(n), _vp(curve_id.data_ptr()), _vp(q.data_ptr()),
+                                _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
+                                _vp(stream)), "mrep_project_curves_noalloc")
         return t, d, s, f
 
     def tune(self, q, curve_id, opts: Opts | None = None, out=None):
