@@ -1,15 +1,18 @@
 """Throughput of batched point projection onto B-spline curves on one MI355X.
 
-Workload: 4,096 clamped B-spline curves (degree U{2..7}, 8-256 control points,
-non-uniform knots with 10% doubled), decomposed to cubic Bezier pieces at
-1e-6 of each curve's box diagonal; 1,048,576 queries (256 per curve, Gaussian
-offsets of 0.05 * diagonal from parameter-uniform curve points).  One step is
-one projection of all queries: BF16 MFMA screen, FP32 Newton, FP64 polish.
+Headline workload: lattice struts at full size -- 65,536 clamped random-walk
+B-splines (degree U{3..9}, 64..1024 control points, non-uniform knots),
+decomposed to cubic Bezier pieces at 1e-6 of each curve's box diagonal;
+16,777,216 queries split across the curves in proportion to their cubic pieces,
+each a Gaussian offset (0.05 * diagonal) from a parameter-uniform curve point.
+One step is one projection call on all queries with the plain method in the
+strategy the autotuner picks for this batch; the plain MFMA screen, the
+NN-seeded call and the sphere-pruned call are timed beside it.
 
-Prints one JSON line: the headline throughput with its roofline and the CPU
-oracle baseline, plus blocks for the surface, lattice, seeded, clip-refiner and
-span-decomposition workloads.  ``--gpus`` above 1 is refused: the library runs
-on one GPU per process.
+Prints one JSON line: the headline with its roofline and the CPU oracle
+baseline, plus blocks for the batched curves, a single cubic (latency),
+surfaces and the device span decomposition.  ``--gpus`` above 1 is refused:
+the library runs on one GPU per process.
 """
 from __future__ import annotations
 
@@ -26,7 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "point projections/s (err≤1e-6·bbox), plain vs NN-seeded, curves+surfaces"
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
-FLOPS_PER_SAMPLE = 2 * 32  # one 16x16x32 MFMA output element per (query, piece, sample)
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+FLOPS_PER_SAMPLE_METHOD = 2 * 19  # the monomial-form distance of one (query, piece, sample): 19 multiply-adds
+FLOPS_PER_SAMPLE_PADDED = 2 * 32  # one 16x16x32 MFMA output element per (query, piece, sample)
+FLOPS_PER_PAIR = 32 * 2 * 12  # refine of one (query, piece) pair: 32 sampled distances of 12 FP32 FMA
+MLP_CURVE_FLOPS = 2 * (15 * 128 + 128 * 128 + 128 * 2)  # curve network forward per row
 
 
 def _kernel_source_hash():
@@ -81,16 +88,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seeded", action="store_true", help="skip the learned-seeding and sphere-pruned variants")
     ap.add_argument("--no-surfaces", action="store_true", help="skip the batched-surfaces workload")
-    ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-strut curves workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-curves workload block")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-cubic latency block")
     ap.add_argument("--no-spans", action="store_true", help="skip the device span decomposition block")
     ap.add_argument("--no-clip", action="store_true",
                     help="skip the batched curves with the paper's refinement path (MREP_OPT_CLIP)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the autotuner and small-batch graph measurements on the batched curves (so that a "
-                         "kernel trace of the run holds the timed screen launches only)")
-    ap.add_argument("--lattice-curves", type=int, default=4096,
-                    help="strut curves in the lattice workload (65536 = the full microstructure configuration, "
-                         "several minutes of host decomposition)")
+                    help="skip the autotuner and small-batch graph measurements on the batched curves")
+    ap.add_argument("--lattice-curves", type=int, default=65_536,
+                    help="strut curves of the headline lattice workload (65536 = the full microstructure "
+                         "configuration; queries = 256 per curve)")
     ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies and exit (scales the HBM byte counters)")
@@ -114,24 +121,315 @@ def main():
 
     import torch
 
-    from paper_2504_11498_amd import gen, mrep
-
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
-    curves, qs = gen.curves_batched(2)
+    result = lattice_headline(args, dev)
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        result["batched_curves"] = batched_curves_block(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_single:
+        result["single_cubic"] = single_cubic_block(args, dev)
+    if not args.no_surfaces:
+        torch.cuda.empty_cache()
+        result["surfaces"] = surfaces_bench(args, dev)
+    if not args.no_spans:
+        torch.cuda.empty_cache()
+        from paper_2504_11498_amd import gen
+
+        result["span_decomposition"] = span_decomposition(gen.curves_batched_geometry(2), args, dev)
+    print(json.dumps(result), flush=True)
+
+
+def _say(tag, msg):
+    print(f"[{tag} {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def lattice_headline(args, dev):
+    """The headline: lattice struts at full size -- 65,536 random-walk B-splines (degree U{3..9}, 64..1024 control
+    points, steps N(0, 0.01^2)), 16,777,216 queries in proportion to each curve's cubic pieces, offset by
+    N(0, (0.05 diag)^2) from parameter-uniform curve points.  A step = one projection call on all queries with the
+    plain method in the strategy the autotuner picks on this batch (MFMA screen or sphere lists); beside it the
+    plain screen, the NN-seeded call (curve network trained on held-out struts) and the sphere-pruned call."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep, seeding
+
+    n_curves = int(args.lattice_curves)
+    _say("lattice", f"generating {n_curves} struts")
+    curves = gen.curves_lattice_geometry(5, n_curves=n_curves)
     t0 = time.perf_counter()
     plan = mrep.decompose_curves(curves, 1e-6)
     decompose_s = time.perf_counter() - t0
+    n_seg = np.diff(plan.seg_off())
+    _say("lattice", f"{plan.n_segments} pieces in {decompose_s:.1f} s (host); uploading")
     t0 = time.perf_counter()
     geom = plan.upload(dev)
     torch.cuda.synchronize()
     upload_s = time.perf_counter() - t0
-    seg_counts = np.diff(plan.export()["seg_off"])
+    qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
+    cid = torch.from_numpy(qs.curve_id).to(dev)
+    q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
+    n = q.shape[0]
+    # work units of the screen: every (query, piece of its curve, sample)
+    samples = 32 * int(np.sum(n_seg[qs.curve_id].astype(np.int64)))
 
+    def outs_like():
+        return (torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
+                torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+
+    # the plain method: the autotuner's strategy on this batch
+    strat, ms_screen, ms_spheres, _ = geom.tune(q, cid)
+    _say("lattice", f"{n} queries; tuner: screen {ms_screen:.2f} ms, spheres {ms_spheres:.2f} ms")
+    topts = mrep.default_opts("bf16", time_stages=True, tuned=True)
+    tws = torch.empty(geom.workspace_bytes(n, topts), dtype=torch.uint8, device=dev)
+    outs = outs_like()
+
+    def tuned():
+        geom.project(q, cid, topts, workspace=tws, out=outs)
+
+    for _ in range(max(1, args.warmup)):
+        tuned()
+        mrep.last_stage_times()
+    torch.cuda.synchronize()
+    stage = np.zeros(mrep.N_STAGES)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        tuned()
+        st = mrep.last_stage_times()
+        stage[:len(st)] += st
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1) / args.steps
+    stage /= args.steps
+    ovf, pairs = geom.workspace_counts(tws)
+    del tws
+    value = n / (ms / 1e3)
+    _say("lattice", f"plain ({['screen', 'spheres'][strat]}) {ms:.2f} ms per call")
+    strategy = ["screen", "spheres"][strat]
+    if strat == mrep.STRATEGY_SPHERES:
+        stage_ms = {"group_candidates": float(stage[0]), "pair_refine": float(stage[3]), "finish": float(stage[4])}
+    else:
+        stage_ms = {"group": float(stage[0]), "screen": float(stage[1]), "pair_refine": float(stage[2]),
+                    "finish": float(stage[3])}
+    flags = outs[3].cpu().numpy().view(np.uint32)
+
+    # the plain MFMA screen on the same batch (its roofline on this workload)
+    sopts = mrep.default_opts("bf16", time_stages=True)
+    sws = torch.empty(geom.workspace_bytes(n, sopts), dtype=torch.uint8, device=dev)
+    souts = outs_like()
+
+    def screen():
+        geom.project(q, cid, sopts, workspace=sws, out=souts)
+
+    screen()
+    ms_s, st_s = _timed(screen, max(1, min(args.steps, 5)))
+    del sws
+    screen_block = {
+        "value": n / (ms_s / 1e3), "unit": "projections/s", "ms_per_step": ms_s,
+        "stage_ms": {"group": float(st_s[0]), "screen": float(st_s[1]), "pair_refine": float(st_s[2]),
+                     "finish": float(st_s[3])},
+        "screened_samples_per_step": samples,
+        "roofline": screen_roofline(samples, float(st_s[1]), ms_s),
+    }
+    _say("lattice", f"screen {ms_s:.2f} ms per call")
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"lattice struts: {n_curves} random-walk B-splines (degree U{{3..9}}, 64..1024 control "
+                        f"points), {n:,} offset queries in proportion to cubic pieces; plain method (autotuned "
+                        f"strategy: {strategy}; FP32 refine, FP64 polish)",
+            "n_curves": n_curves,
+            "queries": int(n),
+            "cubic_pieces": int(plan.n_segments),
+            "tol_rel": 1e-6,
+            "strategy": strategy,
+            "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
+            "decompose_s_host": decompose_s,
+            "upload_s": upload_s,
+            "stage_ms": stage_ms,
+            "candidate_pairs": pairs,
+            "fullscan_queries": ovf,
+            "wall_s_timed": wall,
+            "polished_frac": float(np.mean((flags & mrep.F_POLISHED) != 0)),
+            "near_tie_frac": float(np.mean((flags & mrep.F_NEAR_TIE) != 0)),
+        },
+        "roofline": pairs_roofline(pairs, stage_ms["pair_refine"]),
+        "screen": screen_block,
+    }
+    if strat != mrep.STRATEGY_SPHERES:
+        result["roofline"] = screen_block["roofline"]
+
+    # NN-seeded (curve network trained on held-out struts) and sphere-pruned, same queries
+    seeded_outs = None
+    if not args.no_seeded:
+        t0 = time.perf_counter()
+        tr_curves = gen.curves_lattice_geometry(15, n_curves=max(64, n_curves // 8))
+        tr_plan = mrep.decompose_curves(tr_curves, 1e-6)
+        tr_qs = gen.offset_queries(115, tr_curves, per_curve=256)
+        tr_geom = tr_plan.upload(dev)
+        tr_cid = torch.from_numpy(tr_qs.curve_id).to(dev)
+        tr_q = (tr_geom.eval(tr_cid, torch.from_numpy(tr_qs.t0).to(dev)) +
+                torch.from_numpy(tr_qs.offset).to(dev)).contiguous()
+        x, u, a, tstats = seeding.training_pairs(tr_plan, tr_geom, tr_q, tr_cid, seed=0)
+        net = mrep.Network(dev, seed=7)
+        t1 = time.perf_counter()
+        losses = seeding.train(net, x, u, a, epochs=10, batch=4096, lr=1e-3, seed=0)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t1
+        prep_s = t1 - t0
+        del x, u, a, tr_geom, tr_plan
+        untrained = mrep.Network(dev, seed=7)
+        eopts = mrep.default_opts("bf16", time_stages=True)
+        ews = torch.empty(geom.seeded_workspace_bytes(n, eopts), dtype=torch.uint8, device=dev)
+        diag = torch.from_numpy(curves.bbox_diag()).to(dev)[cid.long()]
+        res = {}
+        for name, nn in (("nn", net), ("nn_untrained", untrained), ("sphere_pruned", None)):
+            so = outs_like()
+
+            def step():
+                geom.project_seeded(q, cid, nn, eopts, workspace=ews, out=so)
+
+            for _ in range(max(1, args.warmup)):
+                step()
+            ms2, st2 = _timed(step, max(1, min(args.steps, 10)))
+            f2 = so[3].cpu().numpy().view(np.uint32)
+            res[name] = {
+                "value": n / (ms2 / 1e3), "unit": "projections/s", "ms_per_step": ms2,
+                "vs_plain_value": ms / ms2,
+                "stage_ms": {"group_candidates": float(st2[0]), "network": float(st2[1]),
+                             "seed_certify": float(st2[2]), "pair_refine": float(st2[3]), "finish": float(st2[4])},
+                "fallback_frac": float(np.mean((f2 & mrep.F_NN_FALLBACK) != 0)),
+                "vs_plain_max_dist_rel": float(((so[1] - outs[1]).abs() / diag).max().item()),
+            }
+            if name == "nn":
+                seeded_outs = so
+                res[name]["roofline_mlp"] = mlp_roofline(4 * n, float(st2[1]))
+            _say("lattice", f"seeded {name}: {ms2:.2f} ms per call, fallback {res[name]['fallback_frac']:.3f}")
+        del ews
+        res["training"] = {"curves": int(tr_curves.n), **tstats, "epochs": 10, "batch": 4096,
+                           "steps": int(len(losses)), "loss_first": float(losses[:50].mean()),
+                           "loss_last": float(losses[-50:].mean()), "prep_s": prep_s, "train_s": train_s,
+                           "ms_per_train_step": 1e3 * train_s / max(1, len(losses))}
+        res["nn_speedup_vs_plain"] = res["nn"]["vs_plain_value"]
+        res["nn_speedup_vs_sphere_pruned"] = res["sphere_pruned"]["ms_per_step"] / res["nn"]["ms_per_step"]
+        result["seeded"] = res
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"], result["parity_on_sample"] = lattice_cpu_baseline(
+            curves, qs, q, outs, seeded_outs, souts, args.cpu_seconds)
+    return result
+
+
+def screen_roofline(samples, screen_ms, call_ms):
+    """k_screen_bf16 against the dense BF16 MFMA peak.  Method work: one distance per (query, piece, sample) in
+    the monomial form, 19 multiply-adds (38 flop); beside it the padded-K figure (one 16x16x32 MFMA output
+    element, 64 flop, what the matrix cores execute) and the whole-call fraction."""
+    method = samples * FLOPS_PER_SAMPLE_METHOD / (screen_ms / 1e3) / 1e12
+    padded = samples * FLOPS_PER_SAMPLE_PADDED / (screen_ms / 1e3) / 1e12
+    whole = samples * FLOPS_PER_SAMPLE_METHOD / (call_ms / 1e3) / 1e12
+    return {"bound": "mfma", "kernel": "k_screen_bf16", "achieved": method, "peak": BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": method / BF16_PEAK_TFLOPS,
+            "per_unit": "38 flop (19 MAC, the monomial-form distance) per screened (query, piece, sample)",
+            "frac_padded_k": padded / BF16_PEAK_TFLOPS,
+            "per_unit_padded_k": "64 flop per screened sample: one 16x16x32 BF16 MFMA output element (K padded to 32)",
+            "frac_whole_call": whole / BF16_PEAK_TFLOPS}
+
+
+def pairs_roofline(pairs, pair_ms):
+    """k_pairs<float> (the refine of every listed (query, piece) pair) against the FP32 vector peak: per pair the
+    certified piece minimum, 32 sampled distances of 12 FP32 multiply-adds each (cubic in Horner form per
+    coordinate, squared norm), 768 flop; the Newton steps that follow are not counted."""
+    achieved = pairs * FLOPS_PER_PAIR / (pair_ms / 1e3) / 1e12 if pair_ms > 0 else None
+    return {"bound": "alu", "kernel": "k_pairs<float>", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS if achieved else None,
+            "traffic": None, "units": int(pairs),
+            "per_unit": "768 flop per listed (query, piece) pair: 32 samples x 12 FP32 FMA"}
+
+
+def mlp_roofline(rows, ms):
+    """k_mlp against the dense BF16 MFMA peak: 2 x (15x128 + 128x128 + 128x2) = 37,120 flop per curve row."""
+    if not ms > 0:
+        return None
+    a = rows * MLP_CURVE_FLOPS / (ms / 1e3) / 1e12
+    return {"bound": "mfma", "kernel": "k_mlp", "achieved": a, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": a / BF16_PEAK_TFLOPS, "rows": int(rows), "per_unit": "37,120 flop per (query, candidate) row"}
+
+
+def lattice_cpu_baseline(curves, qs, q_dev, outs, seeded_outs, screen_outs, seconds):
+    """The FP64 oracle on a bounded random sample of the headline queries (its throughput on this host), and
+    the parity of the benchmarked outputs (plain, seeded, screen) on that sample."""
+    sys.path.insert(0, ROOT)
+    import oracle
+
+    oracle.build(force=False)
+    rng = np.random.default_rng(7)
+    n = qs.n
+    q_all = q_dev.cpu().numpy()
+    order = rng.permutation(n)
+    pilot = np.sort(order[:256])
+    t0 = time.perf_counter()
+    oracle.project(curves, qs.curve_id[pilot], q_all[pilot])
+    rate = 256 / max(time.perf_counter() - t0, 1e-6)
+    m = int(min(max(rate * seconds, 1024), 100_000))
+    idx = np.sort(order[:m])
+    t0 = time.perf_counter()
+    r = oracle.project(curves, qs.curve_id[idx], q_all[idx])
+    dt = time.perf_counter() - t0
+    diag = curves.bbox_diag()[qs.curve_id[idx]]
+    unique = (r["runner"] - r["dist"]) > 2e-6 * diag
+    wc = unique & (r["kappa"] >= 1e-3)
+
+    def parity(o):
+        d = o[1].cpu().numpy()[idx]
+        t = o[0].cpu().numpy()[idx]
+        err = np.abs(d - r["dist"]) / diag
+        terr = np.abs(t - r["t"])[wc]
+        return {"max_dist_err_rel_bbox": float(err.max()), "max_t_err_unique_wellcond": float(terr.max()) if wc.any() else None,
+                "pass": bool(err.max() <= 1e-6 and (not wc.any() or terr.max() <= 1e-7))}
+
+    par = {"queries": int(m), "unique_wellcond_frac": float(wc.mean()), "plain": parity(outs),
+           "screen": parity(screen_outs)}
+    if seeded_outs is not None:
+        par["nn_seeded"] = parity(seeded_outs)
+    cpu = {"value": m / dt, "unit": "projections/s", "cores": oracle.max_threads(), "kind": "oracle",
+           "sample": f"{m} of the {n} headline queries (uniform random, seed 7): certified FP64 projection on the "
+                     f"original B-splines, {dt:.1f} s"}
+    return cpu, par
+
+
+def batched_curves_block(args, dev):
+    """Batched curves: 4,096 clamped B-splines (degree U{2..7}, 8..256 control points, 10% doubled knots), 1,048,576
+    offset queries (256 per curve).  One call = BF16 MFMA screen, FP32 Newton, FP64 polish."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep
+
+    curves, qs = gen.curves_batched(2)
+    t0 = time.perf_counter()
+    plan = mrep.decompose_curves(curves, 1e-6)
+    decompose_s = time.perf_counter() - t0
+    geom = plan.upload(dev)
+    seg_counts = np.diff(plan.seg_off())
     cid = torch.from_numpy(qs.curve_id).to(dev)
     q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
     n = qs.n
@@ -140,92 +438,72 @@ def main():
             torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
     ws = torch.empty(geom.workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
 
-    for _ in range(args.warmup):
+    def step():
         geom.project(q, cid, opts, workspace=ws, out=outs)
-        mrep.last_stage_times()
-    torch.cuda.synchronize()
-    stage_ms = np.zeros(3)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        geom.project(q, cid, opts, workspace=ws, out=outs)
-        stage_ms += mrep.last_stage_times()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = gpu_ms / args.steps
-    value = n * args.steps / (gpu_ms / 1e3)
-    stage_ms /= args.steps
 
+    for _ in range(args.warmup):
+        step()
+    ms, stage = _timed(step, args.steps)
     samples = 32 * int(np.sum(seg_counts[qs.curve_id].astype(np.int64)))
-    screen_ms = float(stage_ms[1])
-    achieved = samples * FLOPS_PER_SAMPLE / (screen_ms / 1e3) / 1e12
     flags = outs[3].cpu().numpy().view(np.uint32)
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "projections/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16",
-        "data": "synthetic",
-        "config": {
-            "workload": "batched curves: 4096 clamped B-splines, degree U{2..7}, 8-256 control points, "
-                        "1,048,576 offset queries; plain method (BF16 MFMA screen, FP32 Newton, FP64 polish)",
-            "n_curves": int(curves.n),
-            "queries": int(n),
-            "cubic_pieces": int(plan.n_segments),
-            "tol_rel": 1e-6,
-            "samples_per_piece": 32,
-            "screened_samples_per_step": samples,
-            "decompose_s_host": decompose_s,
-            "upload_s": upload_s,
-            "stage_ms": {"group": float(stage_ms[0]), "screen": float(stage_ms[1]), "refine": float(stage_ms[2])},
-            "wall_s_timed": wall,
-            "fullscan_frac": float(np.mean((flags & mrep.F_FULLSCAN) != 0)),
-            "polished_frac": float(np.mean((flags & mrep.F_POLISHED) != 0)),
-        },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "k_screen_bf16",
-            "achieved": achieved,
-            "peak": BF16_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / BF16_PEAK_TFLOPS,
-            "traffic": _traffic(),
-            "per_unit": "64 flop per screened (query, piece, sample): one 16x16x32 BF16 MFMA output element",
-        },
+    ovf, pairs = geom.workspace_counts(ws)
+    roof = screen_roofline(samples, float(stage[1]), ms)
+    roof["traffic"] = _traffic()
+    res = {
+        "workload": "batched curves: 4096 clamped B-splines, degree U{2..7}, 8-256 control points, 1,048,576 "
+                    "offset queries; plain method (BF16 MFMA screen, FP32 Newton, FP64 polish)",
+        "value": n / (ms / 1e3), "unit": "projections/s", "ms_per_step": ms, "queries": int(n),
+        "cubic_pieces": int(plan.n_segments), "decompose_s_host": decompose_s,
+        "screened_samples_per_step": samples, "candidate_pairs": pairs, "fullscan_queries": ovf,
+        "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "pair_refine": float(stage[2]),
+                     "finish": float(stage[3])},
+        "polished_frac": float(np.mean((flags & mrep.F_POLISHED) != 0)),
+        "roofline": roof,
+        "roofline_pairs": pairs_roofline(pairs, float(stage[2])),
     }
+    _say("batched", f"{ms:.3f} ms per call")
     if not args.no_extras:
-        # the autotuner on this batch (the timed steps above always use the screen)
         strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
-        result["config"]["autotune"] = {"strategy": ["screen", "spheres"][strat],
-                                        "ms": {"screen": ms_screen, "spheres": ms_spheres}}
-        result["config"]["graph_small_batches"] = graph_small_batches(geom, q, cid)
+        res["autotune"] = {"strategy": ["screen", "spheres"][strat], "ms": {"screen": ms_screen, "spheres": ms_spheres}}
+        res["graph_small_batches"] = graph_small_batches(geom, q, cid)
     if not args.no_clip:
-        result["clip_refiner"] = clip_refiner(geom, q, cid, outs, curves, value, stage_ms, ws, args)
+        res["clip_refiner"] = clip_refiner(geom, q, cid, outs, curves, res["value"], stage, ws, args)
     if not args.no_seeded:
-        result["seeded"] = seeded_variants(geom, q, cid, outs, curves, value, args)
-    if not args.no_surfaces:
-        del geom, ws
-        torch.cuda.empty_cache()
-        result["surfaces"] = surfaces_bench(args, dev)
-    if not args.no_lattice:
-        torch.cuda.empty_cache()
-        result["lattice"] = lattice_bench(args, dev)
-    if not args.no_spans:
-        torch.cuda.empty_cache()
-        result["span_decomposition"] = span_decomposition(curves, args, dev)
+        res["seeded"] = seeded_variants(geom, q, cid, outs, curves, res["value"], args)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(curves, qs, outs, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
+        res["cpu_baseline"] = cpu_baseline(curves, qs, outs, min(args.cpu_seconds, 8.0))
+    return res
+
+
+def single_cubic_block(args, dev):
+    """One cubic curve (16 control points, 13 spans), 10,000 queries uniform in its box x1.1: far too small to
+    fill the GPU, so its absolute latency per call (median of 10 after 3 warm-ups), FP64 and BF16 modes."""
+    import torch
+
+    from paper_2504_11498_amd import gen, mrep
+
+    curves, qs = gen.curve_single(1)
+    geom = mrep.decompose_curves(curves, 1e-6).upload(dev)
+    q = torch.from_numpy(qs.point).to(dev)
+    cid = torch.from_numpy(qs.curve_id).to(dev)
+    res = {"workload": "single cubic: 16 control points, 13 spans, 10,000 box queries", "queries": int(qs.n)}
+    for prec in ("fp64", "bf16"):
+        opts = mrep.default_opts(prec)
+        outs = (torch.empty(qs.n, dtype=torch.float64, device=dev), torch.empty(qs.n, dtype=torch.float64, device=dev),
+                torch.empty(qs.n, dtype=torch.int32, device=dev), torch.empty(qs.n, dtype=torch.int32, device=dev))
+        ws = torch.empty(geom.workspace_bytes(qs.n, opts), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            geom.project(q, cid, opts, workspace=ws, out=outs)
+        times = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            geom.project(q, cid, opts, workspace=ws, out=outs)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        res[prec] = {"latency_ms_median": float(np.median(times)), "latency_ms_min": float(np.min(times))}
+    return res
 
 
 def _timed(fn, steps):
@@ -338,8 +616,9 @@ def clip_refiner(geom, q, cid, plain_outs, curves, plain_value, plain_stage, ws,
         "value": n / (ms / 1e3),
         "ms_per_step": ms,
         "vs_plain_value": (n / (ms / 1e3)) / plain_value,
-        "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "refine": float(stage[2])},
-        "plain_refine_ms": float(plain_stage[2]),
+        "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "pair_refine": float(stage[2]),
+                     "finish": float(stage[3])},
+        "plain_pair_refine_ms": float(plain_stage[2]),
         "vs_plain_max_dist_rel": dd,
         "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
     }
@@ -426,7 +705,7 @@ def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):
             "ms_per_step": ms,
             "speedup_vs_plain": (n / (ms / 1e3)) / plain_value,
             "stage_ms": {"group_candidates": float(stage[0]), "network": float(stage[1]),
-                         "seed_certify": float(stage[2]), "fallback": float(stage[3])},
+                         "seed_certify": float(stage[2]), "pair_refine": float(stage[3]), "finish": float(stage[4])},
             "fallback_frac": float(np.mean((flags & mrep.F_NN_FALLBACK) != 0)),
             "vs_plain_max_dist_rel": dd,
             "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
@@ -435,110 +714,6 @@ def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):
                        **stats, "epochs": 10, "batch": 4096, "lr": 1e-3, "steps": int(len(losses)),
                        "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
                        "prep_s": prep_s, "train_s": train_s}
-    return res
-
-
-def lattice_bench(args, dev):
-    """Lattice struts: random-walk curves (degree U{3..9}, 64..1024 control points, steps N(0, 0.01^2)),
-    256 queries per curve on average in proportion to each curve's cubic pieces, offset as in the batched
-    curves.  Plain (BF16 screen), NN-seeded (curve network trained on held-out struts) and sphere-pruned."""
-    import torch
-
-    from paper_2504_11498_amd import gen, mrep, seeding
-
-    def say(msg):
-        print(f"[lattice {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
-
-    n_curves = int(args.lattice_curves)
-    say(f"generating {n_curves} struts")
-    curves = gen.curves_lattice_geometry(5, n_curves=n_curves)
-    t0 = time.perf_counter()
-    say("decomposing on the host")
-    plan = mrep.decompose_curves(curves, 1e-6)
-    decompose_s = time.perf_counter() - t0
-    say(f"{plan.n_segments} pieces in {decompose_s:.1f} s; uploading")
-    n_seg = np.diff(plan.export()["seg_off"])
-    qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
-    geom = plan.upload(dev)
-    cid = torch.from_numpy(qs.curve_id).to(dev)
-    q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
-    n = q.shape[0]
-    opts = mrep.default_opts("bf16", time_stages=True)
-    outs = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
-            torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
-    steps = max(1, min(args.steps, 5))
-    ws = torch.empty(geom.workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
-
-    def plain():
-        geom.project(q, cid, opts, workspace=ws, out=outs)
-
-    say(f"{n} queries; plain projection")
-    for _ in range(max(1, args.warmup)):
-        plain()
-    ms, stage = _timed(plain, steps)
-    del ws
-    say(f"plain {ms:.2f} ms per call; autotuner")
-    res = {
-        "workload": f"lattice struts: {n_curves} random-walk B-splines (degree 3..9, 64..1024 control points), "
-                    f"{n:,} queries in proportion to cubic pieces",
-        "queries": int(n),
-        "cubic_pieces": int(plan.n_segments),
-        "decompose_s_host": decompose_s,
-        "plain": {"value": n / (ms / 1e3), "unit": "projections/s", "ms_per_step": ms,
-                  "stage_ms": {"group": float(stage[0]), "screen": float(stage[1]), "refine": float(stage[2])},
-                  "fullscan_frac": float(np.mean((outs[3].cpu().numpy().view(np.uint32) & mrep.F_FULLSCAN) != 0))},
-    }
-    # the autotuner's choice between the screen and the sphere strategy, and the tuned call's time
-    strat, ms_screen, ms_spheres, _ = geom.tune(q, cid)
-    topts = mrep.default_opts("bf16", time_stages=True, tuned=True)
-    tws = torch.empty(geom.workspace_bytes(n, topts), dtype=torch.uint8, device=dev)
-
-    def tuned():
-        geom.project(q, cid, topts, workspace=tws, out=outs)
-
-    tuned()
-    ms_t, _ = _timed(tuned, steps)
-    del tws
-    say(f"tuned ({['screen', 'spheres'][strat]}) {ms_t:.2f} ms per call")
-    res["tuned"] = {"strategy": ["screen", "spheres"][strat], "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
-                    "value": n / (ms_t / 1e3), "unit": "projections/s", "ms_per_step": ms_t}
-    if args.no_seeded:
-        return res
-    # curve network trained on held-out struts
-    t0 = time.perf_counter()
-    tr_curves = gen.curves_lattice_geometry(15, n_curves=max(64, n_curves // 8))
-    tr_plan = mrep.decompose_curves(tr_curves, 1e-6)
-    tr_qs = gen.offset_queries(115, tr_curves, per_curve=256)
-    tr_geom = tr_plan.upload(dev)
-    tr_cid = torch.from_numpy(tr_qs.curve_id).to(dev)
-    tr_q = (tr_geom.eval(tr_cid, torch.from_numpy(tr_qs.t0).to(dev)) + torch.from_numpy(tr_qs.offset).to(dev)).contiguous()
-    x, u, a, stats = seeding.training_pairs(tr_plan, tr_geom, tr_q, tr_cid, seed=0)
-    net = mrep.Network(dev, seed=7)
-    losses = seeding.train(net, x, u, a, epochs=10, batch=4096, lr=1e-3, seed=0)
-    train_s = time.perf_counter() - t0
-    del x, u, a, tr_geom
-    so = tuple(torch.empty_like(o) for o in outs)
-    sws = torch.empty(geom.seeded_workspace_bytes(n, opts), dtype=torch.uint8, device=dev)
-    diag = torch.from_numpy(curves.bbox_diag()).to(dev)[cid.long()]
-    for name, nn in (("nn", net), ("sphere_pruned", None)):
-        def step():
-            geom.project_seeded(q, cid, nn, opts, workspace=sws, out=so)
-
-        for _ in range(max(1, args.warmup)):
-            step()
-        ms2, st2 = _timed(step, steps)
-        flags = so[3].cpu().numpy().view(np.uint32)
-        res[name] = {
-            "value": n / (ms2 / 1e3), "unit": "projections/s", "ms_per_step": ms2,
-            "speedup_vs_plain": ms / ms2,
-            "stage_ms": {"group_candidates": float(st2[0]), "network": float(st2[1]),
-                         "seed_certify": float(st2[2]), "fallback": float(st2[3])},
-            "fallback_frac": float(np.mean((flags & mrep.F_NN_FALLBACK) != 0)),
-            "vs_plain_max_dist_rel": float(((so[1] - outs[1]).abs() / diag).max().item()),
-        }
-    res["training"] = {"curves": int(tr_curves.n), **stats, "steps": int(len(losses)),
-                       "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
-                       "seconds": train_s}
     return res
 
 

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 6
+#define MREP_ABI_VERSION 7
 
 /* status codes */
 #define MREP_OK 0
@@ -55,7 +55,17 @@ extern "C" {
 #define MREP_E_HIP (-6)         /* a HIP runtime call failed (message in mrep_last_error) */
 #define MREP_E_NO_DEVICE (-7)   /* no gfx950 device available to the calling thread */
 
-#define MREP_MAX_DEGREE 15
+/* Curves: degrees 1..MREP_MAX_DEGREE.  Up to MREP_POWER_MAX_DEGREE a span's
+ * exact form is kept in power form (Horner in the FP64 polish); above it the
+ * power basis has no digits left (its coefficients grow like 3^p), so the span
+ * is kept as Bezier points and evaluated by de Casteljau.  The paper's GPU
+ * design caps the degree at 31 (one 1024-thread block per basis matrix, Sec. 6
+ * discussion and limitations); this library has no block-size cap. */
+#define MREP_MAX_DEGREE 32
+#define MREP_POWER_MAX_DEGREE 15
+/* Surfaces (both directions) and the device span kernel (mrep_span_bezier_curves). */
+#define MREP_MAX_SURFACE_DEGREE 15
+#define MREP_SPAN_MAX_DEGREE 15
 #define MREP_MAX_PIECES_PER_SPAN 4096
 
 /* per-query flag bits */
@@ -114,7 +124,7 @@ typedef struct {
 #define MREP_OPT_CLIP 0x4
 #define MREP_STRATEGY_SCREEN 0  /* BF16 MFMA screen, certified candidates, refine */
 #define MREP_STRATEGY_SPHERES 1 /* sphere lists (span clusters where compact), refine every listed piece */
-#define MREP_N_STAGES 4 /* most stages any call records (see mrep_last_stage_times) */
+#define MREP_N_STAGES 5 /* most stages any call records (see mrep_last_stage_times) */
 
 /* ---------------------------------------------------------------------- */
 /* Decomposition (host, FP64)                                              */
@@ -133,14 +143,40 @@ typedef struct {
  *                              tol_rel * diag (Sec. 5.2.2, tolerance alpha)
  *   n_threads                  host threads to use (<= 0: all available)
  *   out                        receives a new plan; free with mrep_plan_free.
- * Each span's exact Bezier form is Q = B_p^{-1} M A P (Sec. 5.2.1); p = 3 keeps
- * it, p <= 2 elevates it, p >= 4 reduces it with the G1 conditions and the
- * L2-optimal (delta0, delta1) of Sec. 5.2.2 and splits it at the sample of
- * largest deviation until the tolerance holds.
+ * Each span's exact Bezier form is Q = B_p^{-1} M A P (Sec. 5.2.1; above
+ * MREP_POWER_MAX_DEGREE the same points come from the blossom values
+ * P(a^{p-j}, b^j) of the span [a, b], since the power basis in between has no
+ * digits left there); p = 3 keeps it, p <= 2 elevates it, p >= 4 reduces it
+ * with the G1 conditions and the L2-optimal (delta0, delta1) of Sec. 5.2.2 and
+ * splits it at the sample of largest deviation until the tolerance holds.
  * Errors: MREP_E_INVALID_ARG, MREP_E_BAD_DEGREE, MREP_E_BAD_KNOTS, MREP_E_TOL. */
 int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
                               const double* cp_xyz, const int64_t* knot_off, const double* knots,
                               double tol_rel, int32_t n_threads, mrep_plan** out);
+
+/* Decompose n_curves clamped RATIONAL B-spline (NURBS) curves,
+ * C(t) = sum_i N_i,p(t) w_i P_i / sum_i N_i,p(t) w_i.  The paper's method is
+ * stated for non-rational curves (Sec. 6, discussion and limitations; Sec. 7
+ * names NURBS as future work); this call carries it over:
+ *   - each non-degenerate span's exact form is its homogeneous Bezier points
+ *     (w x, w y, w z, w), the blossom of the homogeneous control points; the
+ *     FP64 polish evaluates them by de Casteljau and the quotient rule;
+ *   - the screen and the refine run on POLYNOMIAL cubic pieces: per span, the
+ *     cubic through the span's end points with its end derivatives (the G1
+ *     conditions of Sec. 5.2.2 with delta0 = delta1 = 1), split at the sample
+ *     of largest deviation until a certified bound of the deviation from the
+ *     rational curve (sampled maximum plus a derivative bound of the
+ *     homogeneous numerator X - W R) is at most tol_rel * diag.
+ * Arguments as mrep_decompose_curves, and
+ *   weights[cp_off[n]]  HOST  weight of each control point, positive and finite
+ * The returned plan uploads, projects, inverts and evaluates exactly as a
+ * non-rational one (mrep_upload, mrep_project_curves, ...); the sphere, NN and
+ * clip paths see the polynomial pieces.
+ * Errors: as mrep_decompose_curves; MREP_E_INVALID_ARG for null or
+ * non-positive weights. */
+int32_t mrep_decompose_curves_rational(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
+                                       const double* cp_xyz, const double* weights, const int64_t* knot_off,
+                                       const double* knots, double tol_rel, int32_t n_threads, mrep_plan** out);
 
 /* Summary of a plan.  Errors: MREP_E_INVALID_ARG. */
 int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info);
@@ -194,6 +230,15 @@ int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* 
 int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
                             const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,
                             double* dist_out, int32_t* seg_out, uint32_t* flags_out, void* stream);
+
+/* Counters a curve projection call leaves in its workspace: counts_out[0] =
+ * queries whose candidate list overflowed to the full scan, counts_out[1] =
+ * candidate (query, piece) pairs reserved for the refine.  workspace is the
+ * one the call used (mrep_project_curves, mrep_invert_curves,
+ * mrep_project_curves_seeded, also with MREP_OPT_TUNED), geom its geometry;
+ * the read is ordered after the call on stream and waits for it.
+ * Errors: MREP_E_INVALID_ARG, MREP_E_HIP. */
+int32_t mrep_workspace_counts(const mrep_geom* geom, const void* workspace, int64_t* counts_out, void* stream);
 
 /* Allocation-free projection, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -262,7 +307,7 @@ int32_t mrep_eval_curves(const mrep_geom* geom, int64_t n, const int32_t* curve_
  *   Errors: MREP_E_INVALID_ARG, MREP_E_BAD_DEGREE (degree out of range or
  *   fewer than p + 1 points), MREP_E_BAD_KNOTS (knot count not n_c + p_c + 1).
  *
- * mrep_span_bezier_curves: every pointer DEVICE.  max_degree (1..MREP_MAX_DEGREE):
+ * mrep_span_bezier_curves: every pointer DEVICE.  max_degree (1..MREP_SPAN_MAX_DEGREE):
  * at least the largest degree in the batch; it picks the kernel instance, and
  * an interval of a curve of higher degree writes NaN to t_out only.  degree, cp_off, knot_off,
  * cp_xyz, knots: the arrays of mrep_decompose_curves; iv_off, pt_off: the
@@ -300,11 +345,14 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
 int32_t mrep_set_curve_strategy(mrep_geom* geom, int32_t strategy);
 
 /* Durations in milliseconds of the stages of the last call on the calling
- * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 3
- * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine/polish/write.
- * mrep_project_curves_seeded: 4 stages, [0] grouping + sphere candidates,
- * [1] network scoring (0 without a network), [2] seed + certificate (or the
- * sphere-pruned refine), [3] fallback through the screened pipeline.
+ * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 4
+ * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine of the
+ * candidate (query, piece) pairs (0 in FP64 mode), [3] top-2 + FP64 polish +
+ * write, with the full scan of overflowed queries (every query in FP64 mode).
+ * mrep_project_curves_seeded: 5 stages, [0] grouping + sphere candidates,
+ * [1] network scoring (0 without a network), [2] seed + certificate (0
+ * without a network), [3] refine of the listed pairs of the undecided queries,
+ * [4] their top-2 + FP64 polish + write and the full scan of overflows.
  * mrep_project_surfaces / invert: 3 stages, [0] grouping + sphere lists,
  * [1] sampled bounds + gate + patch minima, [2] top-2 + FP64 polish + write.
  * mrep_project_surfaces_seeded: 4 stages, [0] grouping + sphere lists +
@@ -323,7 +371,7 @@ int32_t mrep_last_stage_times(double* ms_out, int32_t n);
 
 /* Decompose n_surf clamped tensor-product B-spline surfaces into bicubic
  * Bezier patches.  Per surface s:
- *   deg_u[s], deg_v[s]          HOST  degrees (1..MREP_MAX_DEGREE)
+ *   deg_u[s], deg_v[s]          HOST  degrees (1..MREP_MAX_SURFACE_DEGREE)
  *   n_u[s], n_v[s]              HOST  control-net size
  *   cp_off[n_surf+1]            HOST  CSR offsets (in points) into cp_xyz; net u-major: P[i * n_v + j]
  *   cp_xyz                      HOST  double xyz
@@ -441,6 +489,15 @@ int32_t mrep_nn_init(mrep_nn* nn, uint64_t seed, void* stream);
 int32_t mrep_nn_set_params(mrep_nn* nn, const float* host, int64_t n, void* stream);
 /* parameters -> host[n] (HOST).  Synchronous on `stream`. */
 int32_t mrep_nn_get_params(const mrep_nn* nn, float* host, int64_t n, void* stream);
+
+/* Products of mrep_nn_forward and mrep_nn_train_step: MREP_NN_COMPUTE_BF16
+ * (default; BF16 MFMA, FP32 accumulation) or MREP_NN_COMPUTE_FP32 (a debug
+ * mode: plain FP32 multiply-adds, no BF16 rounding, for checking gradients
+ * against an FP64 reference to ~1e-5).  mrep_nn_infer and the seeded
+ * projections always run BF16.  Errors: MREP_E_INVALID_ARG. */
+#define MREP_NN_COMPUTE_BF16 0
+#define MREP_NN_COMPUTE_FP32 1
+int32_t mrep_nn_set_compute(mrep_nn* nn, int32_t compute);
 
 /* Outputs y[n][out] for inputs x[n][in] (both DEVICE, FP32; in, out of the
  * network's kind).  mrep_nn_forward: the training kernels (layer by layer

@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "mrep_oracle.c")
 _SRC_MLP = os.path.join(_HERE, "mlp_oracle.c")
 _SRC_SURF = os.path.join(_HERE, "surf_oracle.c")
 _SRC_CLIP = os.path.join(_HERE, "clip_oracle.c")
+_SRC_NURBS = os.path.join(_HERE, "nurbs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
-               "-shared", "-o", tmp, _SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP, "-lm"]
+               "-shared", "-o", tmp, _SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP, _SRC_NURBS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -40,7 +41,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP)):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC_MLP, _SRC_SURF, _SRC_CLIP, _SRC_NURBS)):
         build(force=True)
     lib = C.CDLL(_LIB)
     dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -91,6 +92,11 @@ def _load():
     lib.orc_clip_piece.argtypes = [dp, dp, C.c_int, dp, dp, dp]
     lib.orc_clip_pairs.argtypes = [C.c_int64, dp, dp, C.c_int, C.c_int, C.c_double, dp, dp, dp]
     lib.orc_clip_pairs.restype = None
+    lib.onc_eval.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int64, dp, dp, dp, dp]
+    lib.onc_eval_batch.argtypes = [C.c_int, ip, lp, dp, dp, lp, dp, C.c_int64, ip, dp, dp]
+    lib.onc_project_batch.argtypes = [C.c_int, ip, lp, dp, dp, lp, dp, C.c_int64, ip, dp, dp, dp, dp, dp, C.c_int]
+    lib.onc_piece_deviation.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_double, dp, C.c_int]
+    lib.onc_piece_deviation.restype = C.c_double
     _lib = lib
     return lib
 
@@ -422,3 +428,59 @@ def clip_pairs(Q, q, iters: int = 3, safeguard: bool = False, tol_t: float = 0.0
     _load().orc_clip_pairs(n, _dp(Q), _dp(q), int(iters), int(bool(safeguard)), float(tol_t), _dp(t), _dp(d2),
                            _dp(info))
     return t, d2, info
+
+
+# ---------------------------------------------------------------------------
+# Rational B-spline (NURBS) curves (nurbs_oracle.c): the paper's method is
+# stated for non-rational curves (Sec. 6, discussion and limitations; Sec. 7);
+# these compute the plain definitions on C = sum N w P / sum N w.
+# ---------------------------------------------------------------------------
+def nurbs_eval_curve(p: int, P, w, U, t, derivs: bool = False):
+    """C(t) (and C', C'') of one rational curve: de Boor on the homogeneous points, then the quotient rule."""
+    P, w, U, t = _d(P), _d(w), _d(U), np.atleast_1d(_d(t))
+    m = t.shape[0]
+    X, D1, D2 = np.zeros((m, 3)), np.zeros((m, 3)), np.zeros((m, 3))
+    rc = _load().onc_eval(p, P.shape[0], _ptr(P, C.c_double), _ptr(w, C.c_double), _ptr(U, C.c_double), m,
+                          _ptr(t, C.c_double), _ptr(X, C.c_double), _ptr(D1, C.c_double), _ptr(D2, C.c_double))
+    if rc != 0:
+        raise ValueError("bad rational curve")
+    return (X, D1, D2) if derivs else X
+
+
+def nurbs_eval_batch(curves, weights, cid, t) -> np.ndarray:
+    """X[i] = C_{cid[i]}(t[i]) over a CSR set of rational curves (weights per control point)."""
+    cid = np.ascontiguousarray(cid, dtype=np.int32)
+    t, w = _d(t), _d(weights)
+    X = np.zeros((t.shape[0], 3))
+    rc = _load().onc_eval_batch(curves.n, _ptr(curves.degree, C.c_int32), _ptr(curves.cp_off, C.c_int64),
+                                _ptr(_d(curves.cp), C.c_double), _ptr(w, C.c_double), _ptr(curves.knot_off, C.c_int64),
+                                _ptr(_d(curves.knots), C.c_double), t.shape[0], _ptr(cid, C.c_int32),
+                                _ptr(t, C.c_double), _ptr(X, C.c_double))
+    if rc != 0:
+        raise ValueError("bad rational curve or id")
+    return X
+
+
+def nurbs_project(curves, weights, cid, q, nthreads: int = 0):
+    """Global minimiser of |q - C(t)| over each query's own rational curve (Sec. 4, eq. projections).
+
+    Returns dict(t, dist, kappa, runner) with the meanings of project()."""
+    cid = np.ascontiguousarray(cid, dtype=np.int32)
+    q, w = _d(q).reshape(-1, 3), _d(weights)
+    m = q.shape[0]
+    t, d, kap, run = np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)
+    rc = _load().onc_project_batch(curves.n, _ptr(curves.degree, C.c_int32), _ptr(curves.cp_off, C.c_int64),
+                                   _ptr(_d(curves.cp), C.c_double), _ptr(w, C.c_double),
+                                   _ptr(curves.knot_off, C.c_int64), _ptr(_d(curves.knots), C.c_double), m,
+                                   _ptr(cid, C.c_int32), _ptr(q, C.c_double), _ptr(t, C.c_double),
+                                   _ptr(d, C.c_double), _ptr(kap, C.c_double), _ptr(run, C.c_double), int(nthreads))
+    if rc != 0:
+        raise ValueError("bad rational curve or id")
+    return {"t": t, "dist": d, "kappa": kap, "runner": run}
+
+
+def nurbs_piece_deviation(p: int, P, w, U, ta: float, tb: float, R, ns: int = 2049) -> float:
+    """Largest sampled |C(t) - R(u)|, t = ta + u (tb - ta), of a cubic Bezier piece R against the rational curve."""
+    P, w, U, R = _d(P), _d(w), _d(U), _d(R).reshape(4, 3)
+    return float(_load().onc_piece_deviation(p, P.shape[0], _ptr(P, C.c_double), _ptr(w, C.c_double),
+                                             _ptr(U, C.c_double), float(ta), float(tb), _ptr(R, C.c_double), int(ns)))

@@ -52,7 +52,7 @@
 #include <omp.h>
 #endif
 
-#define OR_MAXP 24
+#define OR_MAXP 32
 
 /* ------------------------------------------------------------------------ */
 /* Knot spans and basis (Sec. 4, eq. bsplinebasis)                          */
@@ -373,14 +373,17 @@ static void or_bez_elevate(int p, const double *Q, double *Qe)
 /* G1-continuous, L2-optimal reduction to cubic (Sec. 5.2.2)                */
 /* ------------------------------------------------------------------------ */
 
-/* 16-point Gauss-Legendre nodes on [0,1], computed once by Newton on P_16. */
-static double or_gl_x[16], or_gl_w[16];
+/* OR_GL-point Gauss-Legendre nodes on [0,1], computed once by Newton on
+ * P_OR_GL: exact for the Gram integrands B_i,3 B_k,p of degree p + 3 <= 2 OR_GL - 1
+ * (eq. gram) at every degree up to OR_MAXP. */
+#define OR_GL 24
+static double or_gl_x[OR_GL], or_gl_w[OR_GL];
 static int or_gl_ready = 0;
 
 static void or_gl_init(void)
 {
     if (or_gl_ready) return;
-    const int N = 16;
+    const int N = OR_GL;
     for (int i = 0; i < N; ++i) {
         double x = cos(M_PI * (i + 0.75) / (N + 0.5));
         for (int it = 0; it < 100; ++it) {
@@ -441,7 +444,7 @@ int orc_g1_reduce(int p, const double *Q, double *R, double *delta)
     /* residual with d0 = d1 = 0:  r0(u) = Q(u) - [B0 Q0 + B1 Q0 + B2 Qp + B3 Qp]
      * full residual: r = r0 - d0 B1 a + d1 B2 b. */
     double m11 = 0, m12 = 0, m22 = 0, r1 = 0, r2 = 0;
-    for (int g = 0; g < 16; ++g) {
+    for (int g = 0; g < OR_GL; ++g) {
         double u = or_gl_x[g], w = or_gl_w[g];
         double q[3];
         or_bez_eval(p, Q, u, q);

@@ -213,7 +213,8 @@ __device__ __forceinline__ bool hull_axis(const double* b, double& z1, double& z
 // The refinement of one pair: the best of the piece ends and the roots of E
 // found by clipping on the kept monotonic intervals.  u, squared distance,
 // kappa = (|C'|^2 + r.C'')/|C'|^2 at u (1 at an end), the width left in u.
-__device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_out, double& k_out, double& w_out)
+__device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_out, double& k_out, double& w_out,
+                               double& u2_out, double& d2_out)
 {
     // E = 2 r.C' with r = C - q = a0 + a1 u + a2 u^2 + a3 u^3, C' = a1 + 2 a2 u + 3 a3 u^2
     const V3<double> a[4] = {C.a0, C.a1, C.a2, C.a3};
@@ -251,9 +252,12 @@ __device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_
     d_out = C.dist2(0.0);
     k_out = 1.0;
     w_out = 0.0;
+    u2_out = 0.0;
+    d2_out = INFINITY;
     {
         const double d1 = C.dist2(1.0);
-        if (d1 < d_out) { d_out = d1; u_out = 1.0; }
+        if (d1 < d_out) { u2_out = 0.0; d2_out = d_out; d_out = d1; u_out = 1.0; }
+        else { u2_out = 1.0; d2_out = d1; }
     }
     double ta = 0.0, ea = E[0];
     for (int k = 0; k <= nb; ++k) {
@@ -282,12 +286,16 @@ __device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_
             const double d = C.dist2(u);
             w_out = fmax(w_out, h * (hi - lo));
             if (d < d_out) {
+                if (fabs(u - u_out) > (double)kDistinctU) { u2_out = u_out; d2_out = d_out; }
                 d_out = d;
                 u_out = u;
                 V3<double> r, d1, d2;
                 C.eval(u, r, d1, d2);
                 const double sp = dot(d1, d1);
                 k_out = sp > 0.0 ? (sp + dot(r, d2)) / sp : 1.0;
+            } else if (d < d2_out && fabs(u - u_out) > (double)kDistinctU) {
+                u2_out = u;
+                d2_out = d;
             }
         }
         ta = tb;
@@ -320,11 +328,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_CLIP_M
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         Cubic<double> C;
         load_cubic(G, cv, s, q, C);
-        double u, d, k, w;
-        clip_piece_min(C, u, d, k, w);
+        double u, d, k, w, u2, d2;
+        clip_piece_min(C, u, d, k, w, u2, d2);
         // parameter error: the clipping's remaining half-width, plus rounding
         const double err = (0.5 * w + 1e-15) * (G.segt[2 * s + 1] - G.segt[2 * s]);
-        pair_res[p] = make_float4((float)u, (float)d, (float)k, (float)err);
+        pair_res[2 * p] = make_float4((float)u, (float)d, (float)k, (float)err);
+        pair_res[2 * p + 1] = make_float4((float)u2, (float)d2, 1.f, 0.f);
     }
 }
 

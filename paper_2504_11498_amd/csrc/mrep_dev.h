@@ -27,6 +27,7 @@ struct DevGeom {
     const float4* csph;  // cluster spheres
     int32_t n_curves;
     int64_t n_seg;
+    int32_t general;  // spans beyond the power form present (degree > MREP_POWER_MAX_DEGREE or rational)
 };
 
 inline DevGeom dev_view(const Geom& g)
@@ -46,6 +47,7 @@ inline DevGeom dev_view(const Geom& g)
     d.csph = reinterpret_cast<const float4*>(g.base + g.L.off_csph);
     d.n_curves = (int32_t)g.L.n_curves;
     d.n_seg = g.L.n_seg;
+    d.general = g.L.general;
     return d;
 }
 
@@ -103,13 +105,15 @@ hipError_t launch_grouping(int64_t n_curves, int64_t n, const int32_t* n_dev, co
                            hipStream_t st);
 
 // Refine, finish and full-scan fallback over candidate pairs in ScreenOut form
-// (k_pairs, k_finish, k_fullscan in FP32).  n bounds the sorted query count;
+// (k_pairs, k_finish, k_fullscan in FP32); pairs_mark >= 0 records that stage
+// event after the pair refine.  n bounds the sorted query count;
 // done (nullable) skips decided queries; flag_in is ORed into every flag word
 // written; the overflow counter *ovf_count must be zero on entry.
 hipError_t launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
                          const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
                          const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
-                         int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip = false);
+                         int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip = false,
+                         int pairs_mark = -1);
 // k_pairs_clip (mrep_clip.hip): the paper's refinement path on every candidate pair
 hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const double* q_xyz, const int32_t* perm,
                              const ScreenOut& so, const uint8_t* done, float4* pair_res, hipStream_t st);
@@ -117,8 +121,8 @@ hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const do
 // The screened projection pipeline (grouping, screen, refine, finish) on a
 // workspace of project_ws_bytes(n_curves, n, kc) bytes.  n bounds the query
 // count; n_dev (nullable) holds the actual count on the device.  With timed,
-// stage marks stage0 + 1 .. stage0 + 3 are recorded after grouping, screen and
-// refine.
+// stage marks stage0 + 1 .. stage0 + 4 are recorded after grouping, screen,
+// pair refine and finish.
 int64_t project_ws_bytes(int64_t n_curves, int64_t n, int kc);
 int project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const int32_t* n_dev, const int32_t* curve_id,
                  const double* q_xyz, void* workspace, const Outs& o, hipStream_t st, int invert, bool timed,

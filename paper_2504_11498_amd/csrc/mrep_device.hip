@@ -64,7 +64,8 @@ struct Work {
     int32_t* ovf_count;   // = hist + n_curves
     int32_t* pair_count;  // = hist + n_curves + 1
     ScreenOut so;         // candidate lists as (query, piece) pairs
-    float4* pair_res;     // [cap] u, squared distance, kappa, parameter error bound of each pair
+    float4* pair_res;     // [2 cap] per pair: u, squared distance, kappa, parameter error bound of the
+                          // piece minimum; then u, squared distance of its second distinct local minimum
 };
 
 // pairs reserved per query on average before queries overflow to the full scan
@@ -116,7 +117,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
     int64_t o_ub = take(4 * n);
     int64_t o_pseg = take(4 * cap);
     int64_t o_pj = take(4 * cap);
-    int64_t o_pres = take(16 * cap);
+    int64_t o_pres = take(32 * cap);
     if (w) {
         w->hist = reinterpret_cast<int32_t*>(base + o_hist);
         w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
@@ -317,16 +318,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         Cubic<T> C;
         load_cubic(G, cv, s, q, C);
-        T u, d, k;
-        piece_min(C, u, d, k);
+        T u, d, k, u2, d2;
+        piece_min(C, u, d, k, u2, d2);
         const double err = param_error(C, u, k, G.segt[2 * s], G.segt[2 * s + 1]);
-        pair_res[p] = make_float4((float)u, (float)d, (float)k, (float)err);
+        pair_res[2 * p] = make_float4((float)u, (float)d, (float)k, (float)err);
+        pair_res[2 * p + 1] = make_float4((float)u2, (float)d2, 1.f, 0.f);
     }
 }
 
 // One thread per query: the two best of its pairs, then finish.  Queries whose
 // list overflowed are appended to ovf_list for k_fullscan.
-template <typename T>
+template <typename T, bool kGen>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH_MIN_WAVES, 8))) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, ScreenOut so,
@@ -349,10 +351,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH
     Cand b1 = empty_cand(cv), b2 = b1;
     const int64_t p0 = so.pair_off[j];
     for (int i = 0; i < n_list; ++i) {
-        const float4 r = pair_res[p0 + i];
-        top2(make_cand(G, so.pair_seg[p0 + i], (double)r.x, (double)r.y, (double)r.z, (double)r.w), b1, b2);
+        const float4 r = pair_res[2 * (p0 + i)], r2 = pair_res[2 * (p0 + i) + 1];
+        const int32_t s = so.pair_seg[p0 + i];
+        top2(make_cand_q(G, cv, s, (double)r.x, (double)r.y, (double)r.z, (double)r.w, q), b1, b2);
+        if (r2.y < INFINITY) top2(make_cand_q(G, cv, s, (double)r2.x, (double)r2.y, 1.0, 0.0, q), b1, b2);
     }
-    finish<T>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
+    finish<T, kGen>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
 }
 
 // Lexicographic (d2, t, lane) minimum over the wave; every lane gets the winner lane.
@@ -376,6 +380,7 @@ __device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
     r.kappa = __shfl(c.kappa, src, 64);
     r.t_err = __shfl(c.t_err, src, 64);
     r.seg = __shfl(c.seg, src, 64);
+    r.across = __shfl(c.across, src, 64);
     return r;
 }
 
@@ -384,7 +389,7 @@ __device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
 // bound reaches it, (3) wave top-2, (4) finish on lane 0.  Used for every
 // query in the FP64 mode (list == nullptr) and for the screen's overflows.
 // Persistent: wave w takes items w, w + waves, ... until the count is reached.
-template <typename T>
+template <typename T, bool kGen>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_FULLSCAN_MIN_WAVES, 8))) void k_fullscan(DevGeom G, const int32_t* __restrict__ cid,
                                                   const double* __restrict__ qxyz,
                                                   const int32_t* __restrict__ q_off,
@@ -441,14 +446,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_FULLSC
             if (sph(s, r) - r > lim) continue;
             double m = (double)piece_sample_min<T>(G, cv, s, q);
             double lb = sqrt(fmax(m * (1.0 - rel), 0.0)) - (double)G.aux[s * 8 + AUX_ES] * 1.001;
-            if (lb <= ub) consider<T>(G, cv, s, q, b1, b2);
+            // lim, not ub: a runner-up within the tie margin is refined too
+            if (lb <= lim) consider<T>(G, cv, s, q, b1, b2);
         }
         const int w = wave_argmin(b1.d2, b1.t);
         const Cand best = cand_from_lane(b1, w);
-        const Cand other = (lane == w) ? b2 : b1;
+        // runner-up: the winner lane's second, every other lane's first unless that
+        // one is a piece end the distance falls across (then its second)
+        const Cand other = (lane == w || b1.across) ? b2 : b1;
         const int r = wave_argmin(other.d2, other.t);
         const Cand runner = cand_from_lane(other, r);
-        if (lane == 0) finish<T>(G, cv, q, best, runner, flag_in, tie_rel, invert, qi, o);
+        if (lane == 0) finish<T, kGen>(G, cv, q, best, runner, flag_in, tie_rel, invert, qi, o);
     }
 }
 
@@ -473,10 +481,10 @@ __global__ void k_eval(DevGeom G, int64_t n, const int32_t* __restrict__ cid, co
     const int64_t sp = cv.span_off + lo;
     const double tq = G.spant[2 * sp], tq1 = G.spant[2 * sp + 1];
     const double v = (tt - tq) / (tq1 - tq);
-    const double* cf = G.coef + cv.coef_off + (int64_t)lo * 3 * (cv.degree + 1);
+    const double* cf = span_coef(G, cv, sp);
     const double z[3] = {0, 0, 0};
     double r[3], d1[3], d2[3];
-    span_eval(cf, cv.degree, v, z, r, d1, d2);
+    span_eval_cv<true>(cv, cf, v, z, r, d1, d2);
     xyz[3 * i] = r[0];
     xyz[3 * i + 1] = r[1];
     xyz[3 * i + 2] = r[2];
@@ -510,29 +518,49 @@ int32_t mrep_abi_version(void) { return MREP_ABI_VERSION; }
 
 const char* mrep_last_error(void) { return t_err.c_str(); }
 
-int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
-                              const int64_t* knot_off, const double* knots, double tol_rel, int32_t n_threads,
-                              mrep_plan** out)
+static int32_t decompose_curves(const char* fn, int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
+                                const double* cp_xyz, const double* weights, const int64_t* knot_off,
+                                const double* knots, double tol_rel, int32_t n_threads, mrep_plan** out)
 {
     if (!out || n_curves < 0 || (n_curves > 0 && (!degree || !cp_off || !cp_xyz || !knot_off || !knots))) {
-        set_error("mrep_decompose_curves: null pointer or negative count");
+        set_error(std::string(fn) + ": null pointer or negative count");
         return MREP_E_INVALID_ARG;
     }
     *out = nullptr;
     if (!(tol_rel > 0.0) || !std::isfinite(tol_rel)) {
-        set_error("mrep_decompose_curves: tol_rel must be positive");
+        set_error(std::string(fn) + ": tol_rel must be positive");
         return MREP_E_TOL;
     }
     mrep_plan* p = new mrep_plan();
     std::string err;
-    int rc = build_plan(n_curves, degree, cp_off, cp_xyz, knot_off, knots, tol_rel, n_threads, p->p, err);
+    int rc = build_plan(n_curves, degree, cp_off, cp_xyz, weights, knot_off, knots, tol_rel, n_threads, p->p, err);
     if (rc != MREP_OK) {
         delete p;
-        set_error("mrep_decompose_curves: " + err);
+        set_error(std::string(fn) + ": " + err);
         return rc;
     }
     *out = p;
     return MREP_OK;
+}
+
+int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
+                              const int64_t* knot_off, const double* knots, double tol_rel, int32_t n_threads,
+                              mrep_plan** out)
+{
+    return decompose_curves("mrep_decompose_curves", n_curves, degree, cp_off, cp_xyz, nullptr, knot_off, knots,
+                            tol_rel, n_threads, out);
+}
+
+int32_t mrep_decompose_curves_rational(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
+                                       const double* cp_xyz, const double* weights, const int64_t* knot_off,
+                                       const double* knots, double tol_rel, int32_t n_threads, mrep_plan** out)
+{
+    if (n_curves > 0 && !weights) {
+        set_error("mrep_decompose_curves_rational: null weights");
+        return MREP_E_INVALID_ARG;
+    }
+    return decompose_curves("mrep_decompose_curves_rational", n_curves, degree, cp_off, cp_xyz, weights, knot_off,
+                            knots, tol_rel, n_threads, out);
 }
 
 int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info)
@@ -780,6 +808,23 @@ int32_t mrep_workspace_bytes(const mrep_geom* geom, int64_t n, const mrep_opts* 
 
 }  // extern "C"
 
+extern "C" int32_t mrep_workspace_counts(const mrep_geom* geom, const void* workspace, int64_t* counts_out,
+                                         void* stream)
+{
+    if (!geom || !workspace || !counts_out || geom->kind != MREP_GEOM_CURVES) {
+        set_error("mrep_workspace_counts: null pointer or surface geometry");
+        return MREP_E_INVALID_ARG;
+    }
+    // both workspace layouts start with the per-curve histogram, then the overflow and pair counters
+    int32_t c[2] = {0, 0};
+    const char* at = (const char*)workspace + 4 * geom->g.L.n_curves;
+    HIP_OK(hipMemcpyAsync(c, at, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    counts_out[0] = c[0];
+    counts_out[1] = c[1];
+    return MREP_OK;
+}
+
 hipError_t mrep::launch_grouping(int64_t nc, int64_t n, const int32_t* n_dev, const int32_t* curve_id,
                                  int32_t* hist, int32_t* q_off, int32_t* tile_off, int32_t* perm, const Outs& o,
                                  hipStream_t st)
@@ -814,21 +859,29 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     if (timed && (rc = stage_mark(stage0 + 2, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
         HIP_OK(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.so, w.pair_res, nullptr, 0u, opts->tie_rel,
-                             invert, w.ovf_list, w.ovf_count, o, st, (opts->flags & MREP_OPT_CLIP) != 0));
+                             invert, w.ovf_list, w.ovf_count, o, st, (opts->flags & MREP_OPT_CLIP) != 0,
+                             timed ? stage0 + 3 : -1));
     } else {
+        if (timed && (rc = stage_mark(stage0 + 3, st))) return rc;
         const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
-        hipLaunchKernelGGL(k_fullscan<double>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, w.q_off, w.perm,
-                           (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr, 0u, opts->tie_rel, invert, o);
+        if (G.general)
+            hipLaunchKernelGGL((k_fullscan<double, true>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz,
+                               w.q_off, w.perm, (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr,
+                               0u, opts->tie_rel, invert, o);
+        else
+            hipLaunchKernelGGL((k_fullscan<double, false>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz,
+                               w.q_off, w.perm, (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr,
+                               0u, opts->tie_rel, invert, o);
     }
     HIP_OK(hipGetLastError());
-    if (timed && (rc = stage_mark(stage0 + 3, st))) return rc;
+    if (timed && (rc = stage_mark(stage0 + 4, st))) return rc;
     return MREP_OK;
 }
 
 hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
                                const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
                                const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
-                               int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip)
+                               int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip, int pairs_mark)
 {
     const int RT = 128;
     const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
@@ -841,12 +894,23 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
                            (const int32_t*)so.pair_seg, (const int32_t*)so.pair_j, (const int32_t*)so.pair_count,
                            so.pair_cap, done, pair_res);
     }
-    hipLaunchKernelGGL(k_finish<float>, dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id, q_xyz,
-                       q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list, ovf_count,
-                       o);
-    hipLaunchKernelGGL(k_fullscan<float>, dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off, perm,
-                       (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,
-                       (uint32_t)MREP_F_FULLSCAN | flag_in, tie_rel, invert, o);
+    if (pairs_mark >= 0 && stage_mark(pairs_mark, st) != MREP_OK) return hipErrorUnknown;
+    // the general instances evaluate Bezier and rational spans as well (geometries that hold them)
+    if (G.general) {
+        hipLaunchKernelGGL((k_finish<float, true>), dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
+                           q_xyz, q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
+                           ovf_count, o);
+        hipLaunchKernelGGL((k_fullscan<float, true>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off,
+                           perm, (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,
+                           (uint32_t)MREP_F_FULLSCAN | flag_in, tie_rel, invert, o);
+    } else {
+        hipLaunchKernelGGL((k_finish<float, false>), dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
+                           q_xyz, q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
+                           ovf_count, o);
+        hipLaunchKernelGGL((k_fullscan<float, false>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off,
+                           perm, (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,
+                           (uint32_t)MREP_F_FULLSCAN | flag_in, tie_rel, invert, o);
+    }
     return hipGetLastError();
 }
 
@@ -930,7 +994,7 @@ static int32_t run_project(const mrep_geom* geom, const mrep_opts* opts, int64_t
     Outs o{t_out, dist_out, seg_out, flags_out};
     rc = project_core(geom->g, opts, n, nullptr, curve_id, q_xyz, workspace, o, st, invert, timed, 0);
     if (rc) return rc;
-    if (timed) stage_end(3);
+    if (timed) stage_end(4);
     return MREP_OK;
 }
 

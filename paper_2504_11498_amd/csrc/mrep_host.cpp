@@ -321,6 +321,169 @@ bool reduce_span(int p, const DegreeTables& T, const double* Q, double ta, doubl
     return true;
 }
 
+// Bezier points of span [a, b] = [U_q, U_q+1] of degree p as blossom values
+// b_j = P(a^{p-j}, b^j): de Boor's triangle whose level k takes the argument a
+// for k <= p - j and b after (every weight in [0, 1]: a chain of convex
+// combinations, stable at any degree).  Q[3j + c].
+void span_blossom(int p, const double* P, const double* U, int q, double* Q)
+{
+    const double a = U[q], b = U[q + 1];
+    double d[(kMaxP + 1) * 3];
+    for (int j = 0; j <= p; ++j) {
+        for (int r = 0; r <= p; ++r)
+            for (int c = 0; c < 3; ++c) d[3 * r + c] = P[3 * (q - p + r) + c];
+        for (int k = 1; k <= p; ++k) {
+            const double x = (k <= p - j) ? a : b;
+            for (int r = p; r >= k; --r) {
+                const int i = q - p + r;
+                const double al = (x - U[i]) / (U[i + p - k + 1] - U[i]);
+                for (int c = 0; c < 3; ++c) d[3 * r + c] = (1.0 - al) * d[3 * (r - 1) + c] + al * d[3 * r + c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) Q[3 * j + c] = d[3 * p + c];
+    }
+}
+
+// Homogeneous Bezier points (w x, w y, w z, w) of span q of a rational curve:
+// the blossom of the homogeneous control points, as span_blossom.
+void span_blossom4(int p, const double* H, const double* U, int q, double* Q)
+{
+    const double a = U[q], b = U[q + 1];
+    double d[(kMaxP + 1) * 4];
+    for (int j = 0; j <= p; ++j) {
+        for (int r = 0; r <= p; ++r)
+            for (int c = 0; c < 4; ++c) d[4 * r + c] = H[4 * (q - p + r) + c];
+        for (int k = 1; k <= p; ++k) {
+            const double x = (k <= p - j) ? a : b;
+            for (int r = p; r >= k; --r) {
+                const int i = q - p + r;
+                const double al = (x - U[i]) / (U[i + p - k + 1] - U[i]);
+                for (int c = 0; c < 4; ++c) d[4 * r + c] = (1.0 - al) * d[4 * (r - 1) + c] + al * d[4 * r + c];
+            }
+        }
+        for (int c = 0; c < 4; ++c) Q[4 * j + c] = d[4 * p + c];
+    }
+}
+
+// de Casteljau split at z of a degree-p homogeneous Bezier piece (exact
+// subdivision of the rational piece)
+void split_piece4(int p, const double* G, double z, double* L, double* R)
+{
+    double w[(kMaxP + 1) * 4];
+    memcpy(w, G, sizeof(double) * 4 * (size_t)(p + 1));
+    for (int c = 0; c < 4; ++c) { L[c] = w[c]; R[4 * p + c] = w[4 * p + c]; }
+    for (int r = 1; r <= p; ++r) {
+        for (int j = 0; j <= p - r; ++j)
+            for (int c = 0; c < 4; ++c) w[4 * j + c] = (1.0 - z) * w[4 * j + c] + z * w[4 * (j + 1) + c];
+        for (int c = 0; c < 4; ++c) { L[4 * r + c] = w[c]; R[4 * (p - r) + c] = w[4 * (p - r) + c]; }
+    }
+}
+
+// Cubic Hermite piece of a rational piece G (degree p, homogeneous): the end
+// points and end derivatives of the rational curve, C'(0) = p (w1/w0)(P1 - P0)
+// and C'(1) = p (w_{p-1}/w_p)(P_p - P_{p-1}) -- the G1 conditions of Sec. 5.2.2
+// with delta0 = delta1 = 1 (the L2 optimum has no closed form for a rational
+// piece).  Returns its deviation bound: the largest deviation on the error
+// samples plus (1/256) times a bound on |(C - R)'|.  With N = X - W R (the
+// numerator of C - R, degree p + 3, Bernstein coefficients by the product
+// rule) and W >= w_min:  |(N/W)'| <= ((p+3) max|dN| + max|N| p max|dw| / w_min) / w_min.
+double rational_cubic(int p, const DegreeTables& T, const double* G, double* R, int* imax)
+{
+    double P0[3], P1[3], Pq[3], Pq1[3];
+    for (int c = 0; c < 3; ++c) {
+        P0[c] = G[c] / G[3];
+        P1[c] = G[4 + c] / G[7];
+        Pq[c] = G[4 * p + c] / G[4 * p + 3];
+        Pq1[c] = G[4 * (p - 1) + c] / G[4 * (p - 1) + 3];
+    }
+    const double s0 = (double)p * G[7] / G[3] / 3.0, s1 = (double)p * G[4 * (p - 1) + 3] / G[4 * p + 3] / 3.0;
+    for (int c = 0; c < 3; ++c) {
+        R[c] = P0[c];
+        R[3 + c] = P0[c] + s0 * (P1[c] - P0[c]);
+        R[6 + c] = Pq[c] - s1 * (Pq[c] - Pq1[c]);
+        R[9 + c] = Pq[c];
+    }
+    double best = -1.0, ev[kErrSamples];
+    for (int i = 0; i < kErrSamples; ++i) {
+        double x[4] = {0, 0, 0, 0}, y[3] = {0, 0, 0};
+        for (int k = 0; k <= p; ++k)
+            for (int c = 0; c < 4; ++c) x[c] += T.Bq[i * (p + 1) + k] * G[4 * k + c];
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) y[c] += T.B3[i * 4 + k] * R[3 * k + c];
+        double e2 = 0.0;
+        for (int c = 0; c < 3; ++c) e2 += (x[c] / x[3] - y[c]) * (x[c] / x[3] - y[c]);
+        ev[i] = sqrt(e2);
+        best = std::max(best, ev[i]);
+    }
+    int bi = 64;
+    for (int i = 0; i < kErrSamples; ++i)
+        if (ev[i] >= best * (1.0 - 1e-6)) { bi = i; break; }
+    *imax = bi;
+    double N[(kMaxP + 4) * 3];
+    for (int k = 0; k <= p + 3; ++k)
+        for (int c = 0; c < 3; ++c) N[3 * k + c] = 0.0;
+    for (int i = 0; i <= p; ++i)
+        for (int j = 0; j <= 3; ++j) {
+            const double f = binom(p, i) * binom(3, j) / binom(p + 3, i + j);
+            for (int c = 0; c < 3; ++c) N[3 * (i + j) + c] += f * (G[4 * i + c] - G[4 * i + 3] * R[3 * j + c]);
+        }
+    double nmax = 0.0, dn = 0.0, wmin = INFINITY, dw = 0.0;
+    for (int k = 0; k <= p + 3; ++k) {
+        nmax = std::max(nmax, sqrt(N[3 * k] * N[3 * k] + N[3 * k + 1] * N[3 * k + 1] + N[3 * k + 2] * N[3 * k + 2]));
+        if (k < p + 3) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) d2 += (N[3 * (k + 1) + c] - N[3 * k + c]) * (N[3 * (k + 1) + c] - N[3 * k + c]);
+            dn = std::max(dn, sqrt(d2));
+        }
+    }
+    for (int k = 0; k <= p; ++k) {
+        wmin = std::min(wmin, G[4 * k + 3]);
+        if (k < p) dw = std::max(dw, fabs(G[4 * (k + 1) + 3] - G[4 * k + 3]));
+    }
+    const double lip = ((double)(p + 3) * dn + nmax * (double)p * dw / wmin) / wmin;
+    return best + lip / 256.0;
+}
+
+// Polynomial cubic pieces within tol of the rational span G on [ta, tb]:
+// split at the sample of largest deviation (clamped to [1/8, 7/8]) of the
+// rational piece itself until every piece's bound holds, as reduce_span.
+bool approx_rational_span(int p, const DegreeTables& T, const double* G, double ta, double tb, double tol,
+                          int32_t span, std::vector<Piece>& out, double& worst)
+{
+    struct Item { double G[4 * (kMaxP + 1)]; double ta, tb; };
+    std::vector<Item> stack;
+    stack.reserve(64);
+    Item first;
+    memcpy(first.G, G, sizeof(double) * 4 * (size_t)(p + 1));
+    first.ta = ta; first.tb = tb;
+    stack.push_back(first);
+    int splits = 0;
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        Piece pc;
+        int imax = 64;
+        const double e = rational_cubic(p, T, it.G, pc.R, &imax);
+        if (e <= tol) {
+            pc.ta = it.ta; pc.tb = it.tb; pc.span = span;
+            out.push_back(pc);
+            worst = std::max(worst, e);
+            continue;
+        }
+        if (++splits >= MREP_MAX_PIECES_PER_SPAN) return false;
+        const int iz = std::min(std::max(imax, 16), 112);
+        const double z = (double)iz / 128.0;
+        Item l, r;
+        split_piece4(p, it.G, z, l.G, r.G);
+        const double tm = it.ta + z * (it.tb - it.ta);
+        l.ta = it.ta; l.tb = tm;
+        r.ta = tm; r.tb = it.tb;
+        stack.push_back(r);
+        stack.push_back(l);
+    }
+    return true;
+}
+
 bool validate_curve(int p, int n, const double* P, const double* U, std::string& err, int& code)
 {
     if (p < 1 || p > kMaxP) { code = MREP_E_BAD_DEGREE; err = "degree out of range"; return false; }
@@ -351,11 +514,59 @@ bool validate_curve(int p, int n, const double* P, const double* U, std::string&
     return true;
 }
 
-void decompose_curve(int p, int n, const double* P, const double* U, double tol_rel, CurveOut& out)
+// A rational curve: each non-degenerate span's homogeneous Bezier points are
+// kept as its exact form, and polynomial cubic pieces within tol_rel * diag of
+// the rational curve feed the screen and the refine (the pieces' deviation
+// bound is the curve's tol_eff).
+void decompose_curve_rational(int p, int n, const double* P, const double* w, const double* U, double tol_rel,
+                              CurveOut& out)
+{
+    const DegreeTables& T = g_tab[p];
+    double lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], P[3 * i + c]); hi[c] = std::max(hi[c], P[3 * i + c]); }
+    out.diag = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) + (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    const double tol = tol_rel * out.diag;
+    std::vector<double> H((size_t)4 * n);
+    for (int i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) H[(size_t)4 * i + c] = w[i] * P[3 * i + c];
+        H[(size_t)4 * i + 3] = w[i];
+    }
+    double G[(kMaxP + 1) * 4];
+    double worst = 0.0;
+    int32_t span_local = 0;
+    for (int q = p; q <= n - 1; ++q) {
+        if (!(U[q] < U[q + 1])) continue;
+        span_blossom4(p, H.data(), U, q, G);
+        out.span_t.push_back(U[q]);
+        out.span_t.push_back(U[q + 1]);
+        out.coef.insert(out.coef.end(), G, G + 4 * (p + 1));
+        out.span_first.push_back((int32_t)out.pieces.size());
+        if (!approx_rational_span(p, T, G, U[q], U[q + 1], tol, span_local, out.pieces, worst)) {
+            out.rc = MREP_E_TOL;
+            out.err = "a span needed more than MREP_MAX_PIECES_PER_SPAN pieces";
+            return;
+        }
+        span_local++;
+    }
+    out.tol_abs = worst;
+}
+
+void decompose_curve(int p, int n, const double* P, const double* w, const double* U, double tol_rel, CurveOut& out)
 {
     std::string err;
     int code = 0;
     if (!validate_curve(p, n, P, U, err, code)) { out.rc = code; out.err = err; return; }
+    if (w) {
+        for (int i = 0; i < n; ++i)
+            if (!(w[i] > 0.0) || !std::isfinite(w[i])) {
+                out.rc = MREP_E_INVALID_ARG;
+                out.err = "weights must be positive and finite";
+                return;
+            }
+        decompose_curve_rational(p, n, P, w, U, tol_rel, out);
+        return;
+    }
     const DegreeTables& T = g_tab[p];
     double lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
     for (int i = 0; i < n; ++i)
@@ -366,25 +577,31 @@ void decompose_curve(int p, int n, const double* P, const double* U, double tol_
     int32_t span_local = 0;
     for (int q = p; q <= n - 1; ++q) {
         if (!(U[q] < U[q + 1])) continue;
-        double h = U[q + 1] - U[q];
-        span_basis_poly(p, U, q, A);
-        // D = diag(h^j) A P_{q-p..q}: power coefficients of the span in local u
-        double hj = 1.0;
-        for (int j = 0; j <= p; ++j) {
-            for (int c = 0; c < 3; ++c) {
-                double s = 0.0;
-                for (int r = 0; r <= p; ++r) s += A[j * (p + 1) + r] * P[3 * (q - p + r) + c];
-                D[3 * j + c] = hj * s;
+        if (p <= MREP_POWER_MAX_DEGREE) {
+            double h = U[q + 1] - U[q];
+            span_basis_poly(p, U, q, A);
+            // D = diag(h^j) A P_{q-p..q}: power coefficients of the span in local u
+            double hj = 1.0;
+            for (int j = 0; j <= p; ++j) {
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int r = 0; r <= p; ++r) s += A[j * (p + 1) + r] * P[3 * (q - p + r) + c];
+                    D[3 * j + c] = hj * s;
+                }
+                hj *= h;
             }
-            hj *= h;
+            // Q = B_p^{-1} D
+            for (int i = 0; i <= p; ++i)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int j = 0; j <= i; ++j) s += T.Bi[i * (p + 1) + j] * D[3 * j + c];
+                    Q[3 * i + c] = s;
+                }
+        } else {
+            // the exact span is kept as its Bezier points (the polish evaluates them by de Casteljau)
+            span_blossom(p, P, U, q, Q);
+            memcpy(D, Q, sizeof(double) * 3 * (size_t)(p + 1));
         }
-        // Q = B_p^{-1} D
-        for (int i = 0; i <= p; ++i)
-            for (int c = 0; c < 3; ++c) {
-                double s = 0.0;
-                for (int j = 0; j <= i; ++j) s += T.Bi[i * (p + 1) + j] * D[3 * j + c];
-                Q[3 * i + c] = s;
-            }
         out.span_t.push_back(U[q]);
         out.span_t.push_back(U[q + 1]);
         out.coef.insert(out.coef.end(), D, D + 3 * (p + 1));
@@ -607,8 +824,8 @@ void gram_matrix(int m, int n, double* G)
 }
 
 int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
-               const int64_t* knot_off, const double* knots, double tol_rel, int n_threads, Plan& plan,
-               std::string& err)
+               const double* weights, const int64_t* knot_off, const double* knots, double tol_rel, int n_threads,
+               Plan& plan, std::string& err)
 {
     init_tables();
     std::vector<CurveOut> outs((size_t)n_curves);
@@ -627,8 +844,8 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
         for (;;) {
             int32_t c = next.fetch_add(1);
             if (c >= n_curves) break;
-            decompose_curve(degree[c], (int)(cp_off[c + 1] - cp_off[c]), cp_xyz + 3 * cp_off[c], knots + knot_off[c],
-                            tol_rel, outs[(size_t)c]);
+            decompose_curve(degree[c], (int)(cp_off[c + 1] - cp_off[c]), cp_xyz + 3 * cp_off[c],
+                            weights ? weights + cp_off[c] : nullptr, knots + knot_off[c], tol_rel, outs[(size_t)c]);
         }
     };
     std::vector<std::thread> th;
@@ -660,7 +877,9 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
         d.n_span = (int32_t)(o.span_t.size() / 2);
         d.degree = degree[c];
         d.es_max = 0.f;
-        d.tol_eff = degree[c] >= 4 ? o.tol_abs : 1e-13 * o.diag;
+        d.rational = weights ? 1 : 0;
+        d.pad_ = 0;
+        d.tol_eff = (degree[c] >= 4 || weights) ? std::max(o.tol_abs, 1e-13 * o.diag) : 1e-13 * o.diag;
         d.tol_user = tol_rel * o.diag;
         d.diag = o.diag;
         {
@@ -756,6 +975,7 @@ int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, c
     L.off_sph = off; off = align256(off + 16 * nseg);
     L.off_csph = off; off = align256(off + 16 * nclu);
     L.total = off;
+    L.general = (weights != nullptr || plan.max_degree > MREP_POWER_MAX_DEGREE) ? 1 : 0;
     return MREP_OK;
 }
 
@@ -1181,7 +1401,7 @@ int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, 
     init_tables();
     for (int32_t s = 0; s < n_surf; ++s) {
         const std::string who = "surface " + std::to_string(s) + ": ";
-        if (deg_u[s] < 1 || deg_u[s] > kMaxP || deg_v[s] < 1 || deg_v[s] > kMaxP) { err = who + "degree out of range"; return MREP_E_BAD_DEGREE; }
+        if (deg_u[s] < 1 || deg_u[s] > MREP_MAX_SURFACE_DEGREE || deg_v[s] < 1 || deg_v[s] > MREP_MAX_SURFACE_DEGREE) { err = who + "degree out of range"; return MREP_E_BAD_DEGREE; }
         if (n_u[s] < deg_u[s] + 1 || n_v[s] < deg_v[s] + 1) { err = who + "too few control points"; return MREP_E_BAD_DEGREE; }
         if (cp_off[s + 1] - cp_off[s] != (int64_t)n_u[s] * n_v[s]) { err = who + "net size != n_u * n_v"; return MREP_E_INVALID_ARG; }
         if (ku_off[s + 1] - ku_off[s] != n_u[s] + deg_u[s] + 1 || kv_off[s + 1] - kv_off[s] != n_v[s] + deg_v[s] + 1) {

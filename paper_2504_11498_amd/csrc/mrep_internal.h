@@ -35,7 +35,8 @@ constexpr int kMaxCand = 48;
 struct DCurve {
     int64_t seg_off;     // first piece (global index)
     int64_t span_off;    // first span (global index)
-    int64_t coef_off;    // first double of this curve's exact-span power coefficients
+    int64_t coef_off;    // first double of this curve's exact spans (power coefficients, or Bezier points:
+                         // 3 per point, 4 homogeneous ones for a rational curve)
     int32_t n_seg;
     int32_t n_span;
     int32_t degree;
@@ -47,8 +48,10 @@ struct DCurve {
     int64_t clu_off;     // first cluster (global): kCluPieces consecutive pieces each
     int32_t n_clu;
     int32_t clu_use;     // 1: the clusters are compact enough for the candidate sweep to use them
+    int32_t rational;    // 1: a rational curve; its exact spans are homogeneous Bezier points (4 per point)
+    int32_t pad_;
 };
-static_assert(sizeof(DCurve) == 104, "DCurve layout");
+static_assert(sizeof(DCurve) == 112, "DCurve layout");
 // pieces per cluster of a curve (the last one may hold fewer)
 constexpr int kCluPieces = 32;
 
@@ -69,6 +72,7 @@ struct GeomLayout {
     int64_t off_sph = 0;     // float4[n_seg]                   piece sphere: centre (as aux), radius
     int64_t off_csph = 0;    // float4[n_clu]                   sphere around each cluster's piece spheres
     int64_t total = 0;
+    int32_t general = 0;     // 1: some span is kept as (homogeneous) Bezier points, not in power form
 };
 
 // aux[8] per piece: cx, cy, cz (FP32 centre relative to the curve origin),
@@ -170,9 +174,10 @@ struct SurfGeom {
 };
 
 // host decomposition (mrep_host.cpp)
+// weights (nullable): per control point, > 0: rational curves
 int build_plan(int32_t n_curves, const int32_t* degree, const int64_t* cp_off, const double* cp_xyz,
-               const int64_t* knot_off, const double* knots, double tol_rel, int n_threads, Plan& plan,
-               std::string& err);
+               const double* weights, const int64_t* knot_off, const double* knots, double tol_rel, int n_threads,
+               Plan& plan, std::string& err);
 int build_surf_plan(int32_t n_surf, const int32_t* deg_u, const int32_t* deg_v, const int32_t* n_u,
                     const int32_t* n_v, const int64_t* cp_off, const double* cp_xyz, const int64_t* ku_off,
                     const double* ku, const int64_t* kv_off, const double* kv, double tol_rel, int n_threads,

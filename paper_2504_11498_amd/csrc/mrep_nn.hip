@@ -134,7 +134,10 @@ unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>
 // ---------------------------------------------------------------------------
 // C[M x N] = sum_k A(m, k) B(k, n) with A, B FP32 in memory (any strides),
 // rounded to BF16 in registers; v_mfma_f32_16x16x32_bf16, FP32 accumulation.
-// One wave per 16x16 tile of C; out-of-range rows, columns and k read as zero.
+// One wave per 16x16 tile of C and K range; out-of-range rows, columns and k
+// read as zero.  Split K (the weight gradients, K = batch rows): blockIdx.y
+// takes rows [y kc, (y+1) kc) and writes a dense M x N partial to parts + y M N,
+// which k_sum_parts adds in a fixed order (deterministic).
 struct GemmArgs {
     int M, N, K;
     const float* A;
@@ -145,7 +148,7 @@ struct GemmArgs {
     int64_t scm, scn;
 };
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int kc, float* __restrict__ parts)
 {
     const int lane = threadIdx.x & 63;
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -155,31 +158,80 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
     const int m0 = (int)(tile / tiles_n) * 16, n0 = (int)(tile % tiles_n) * 16;
     const int r = lane & 15, kb = lane >> 4;
     const int am = m0 + r, bn = n0 + r;
+    const int kbeg = (int)blockIdx.y * kc, kend = min(g.K, kbeg + kc);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
         bf16x8 a, b;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = k0 + kb * 8 + j;
-            const bool kin = k < g.K;
+            const bool kin = k < kend;
             a[j] = (__bf16)((kin && am < g.M) ? g.A[am * g.sam + k * g.sak] : 0.f);
             b[j] = (__bf16)((kin && bn < g.N) ? g.B[k * g.sbk + bn * g.sbn] : 0.f);
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
     const int cn = n0 + r;
+    float* part = parts ? parts + (int64_t)blockIdx.y * g.M * g.N : nullptr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int cm = m0 + 4 * kb + i;
-        if (cm < g.M && cn < g.N) g.C[cm * g.scm + cn * g.scn] = acc[i];
+        if (cm < g.M && cn < g.N) {
+            if (part) part[(int64_t)cm * g.N + cn] = acc[i];
+            else g.C[cm * g.scm + cn * g.scn] = acc[i];
+        }
     }
 }
 
-hipError_t gemm(const GemmArgs& a, hipStream_t st)
+// C = sum over the splits of the dense M x N partials, in split order
+__global__ void k_sum_parts(int M, int N, int splits, const float* __restrict__ parts, float* __restrict__ C,
+                            int64_t scm, int64_t scn)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    float acc = 0.f;
+    for (int s = 0; s < splits; ++s) acc += parts[(int64_t)s * M * N + i];
+    C[(i / N) * scm + (i % N) * scn] = acc;
+}
+
+// FP32-compute debug form of the same product: one thread per element of C,
+// FP32 fused multiply-adds in k order, no BF16 rounding.
+__global__ void k_gemm_f32(GemmArgs g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)g.M * g.N) return;
+    const int m = (int)(i / g.N), n = (int)(i % g.N);
+    float acc = 0.f;
+    for (int k = 0; k < g.K; ++k) acc = fmaf(g.A[m * g.sam + k * g.sak], g.B[k * g.sbk + n * g.sbn], acc);
+    g.C[m * g.scm + n * g.scn] = acc;
+}
+
+// splits of a long K and the dense partials they need (parts holds kMaxSplits x M x N floats)
+constexpr int kMaxSplits = 32;
+constexpr int kSplitRows = 256;  // K rows per split
+
+// the training kernels' products in FP32 instead of BF16 MFMA (mrep_nn_set_compute; debug)
+static thread_local bool t_gemm_fp32 = false;
+
+hipError_t gemm(const GemmArgs& a, hipStream_t st, float* parts = nullptr)
 {
     const int64_t tiles = (int64_t)((a.M + 15) / 16) * ((a.N + 15) / 16);
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+    if (t_gemm_fp32) {
+        hipLaunchKernelGGL(k_gemm_f32, dim3(blocks_for((int64_t)a.M * a.N)), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    int splits = 1, kc = a.K;
+    if (parts && a.K > 2 * kSplitRows) {
+        splits = std::min(kMaxSplits, (a.K + kSplitRows - 1) / kSplitRows);
+        kc = ((a.K + splits - 1) / splits + 31) / 32 * 32;
+        splits = (a.K + kc - 1) / kc;
+    }
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4), (unsigned)splits), dim3(256), 0, st, a, kc,
+                       splits > 1 ? parts : (float*)nullptr);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for((int64_t)a.M * a.N)), dim3(256), 0, st, a.M, a.N, splits,
+                           (const float*)parts, a.C, a.scm, a.scn);
     return hipGetLastError();
 }
 
@@ -320,6 +372,7 @@ __global__ void k_pack(NetDims d, const float* __restrict__ P, uint8_t* __restri
 
 struct TrainWork {
     float *Xb, *Tb, *Ab, *Z1, *H1, *Z2, *H2, *Y, *dY, *dH, *dZ, *rowl;
+    float* parts;  // split-K partials of the weight gradients: kMaxSplits x kH x kH
 };
 
 int64_t train_layout(const NetDims& d, int64_t B, char* base, TrainWork* w)
@@ -334,7 +387,9 @@ int64_t train_layout(const NetDims& d, int64_t B, char* base, TrainWork* w)
     int64_t oZ1 = take(4 * B * kH), oH1 = take(4 * B * kH), oZ2 = take(4 * B * kH), oH2 = take(4 * B * kH);
     int64_t oY = take(4 * B * d.out), odY = take(4 * B * d.out), odH = take(4 * B * kH), odZ = take(4 * B * kH);
     int64_t orl = take(4 * B);
+    int64_t opt = take(4 * (int64_t)kMaxSplits * kH * std::max(kH, d.k1));
     if (w) {
+        w->parts = (float*)(base + opt);
         w->Xb = (float*)(base + oXb); w->Tb = (float*)(base + oT); w->Ab = (float*)(base + oA);
         w->Z1 = (float*)(base + oZ1); w->H1 = (float*)(base + oH1); w->Z2 = (float*)(base + oZ2);
         w->H2 = (float*)(base + oH2); w->Y = (float*)(base + oY); w->dY = (float*)(base + odY);
@@ -362,17 +417,17 @@ int backward(const NetDims& d, const float* P, int64_t B, const float* X, const 
     hipLaunchKernelGGL(k_loss_grad, dim3(blocks_for(B)), dim3(256), 0, st, B, d.out, w.Y, T, acc, w.dY, w.rowl);
     if (loss_out) hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, B, w.rowl, loss_out);
     // layer 3: dW3 = dY^T H2, db3 = colsum dY, dH2 = dY W3
-    NN_HIP(gemm(GemmArgs{d.out, kH, (int)B, w.dY, 1, d.out, w.H2, kH, 1, G + d.oW3, kH, 1}, st));
+    NN_HIP(gemm(GemmArgs{d.out, kH, (int)B, w.dY, 1, d.out, w.H2, kH, 1, G + d.oW3, kH, 1}, st, w.parts));
     hipLaunchKernelGGL(k_colsum, dim3(d.out), dim3(256), 0, st, B, d.out, w.dY, G + d.oB3);
     NN_HIP(gemm(GemmArgs{(int)B, kH, d.out, w.dY, d.out, 1, P + d.oW3, kH, 1, w.dH, kH, 1}, st));
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z2, w.dZ);
     // layer 2: dW2 = dZ2^T H1, db2, dH1 = dZ2 W2
-    NN_HIP(gemm(GemmArgs{kH, kH, (int)B, w.dZ, 1, kH, w.H1, kH, 1, G + d.oW2, kH, 1}, st));
+    NN_HIP(gemm(GemmArgs{kH, kH, (int)B, w.dZ, 1, kH, w.H1, kH, 1, G + d.oW2, kH, 1}, st, w.parts));
     hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + d.oB2);
     NN_HIP(gemm(GemmArgs{(int)B, kH, kH, w.dZ, kH, 1, P + d.oW2, kH, 1, w.dH, kH, 1}, st));
     hipLaunchKernelGGL(k_gelu_back, dim3(blocks_for(B * kH)), dim3(256), 0, st, B * kH, w.dH, w.Z1, w.dZ);
     // layer 1: dW1 = dZ1^T X, db1
-    NN_HIP(gemm(GemmArgs{kH, d.in, (int)B, w.dZ, 1, kH, X, d.in, 1, G + d.oW1, d.in, 1}, st));
+    NN_HIP(gemm(GemmArgs{kH, d.in, (int)B, w.dZ, 1, kH, X, d.in, 1, G + d.oW1, d.in, 1}, st, w.parts));
     hipLaunchKernelGGL(k_colsum, dim3(kH), dim3(256), 0, st, B, kH, w.dZ, G + d.oB1);
     NN_HIP(hipGetLastError());
     return MREP_OK;
@@ -1040,6 +1095,7 @@ __device__ __forceinline__ float end_dist(const BezQ& b, int i) { return norm3f(
 #ifndef MREP_DECIDE_MIN_WAVES
 #define MREP_DECIDE_MIN_WAVES 4
 #endif
+template <bool kGen>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_DECIDE_MIN_WAVES, 8))) void k_decide(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, BoxOut box,
@@ -1069,6 +1125,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_DECIDE
     }
     bool ok = s >= 0, certified = false;
     float u = 0.f, d2 = INFINITY, kap = 1.f;
+    float u_sec = 0.f, d_sec = INFINITY;  // a second distinct local minimum of the chosen piece
     Cubic<float> C;
     Cand b2 = empty_cand(cv);
     // at most 3 attempts: a failed certificate that found a strictly closer piece restarts there
@@ -1093,6 +1150,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_DECIDE
         if (!ok) break;
         load_cubic(G, cv, s, q, C);
         kap = 1.f;
+        d_sec = INFINITY;
         if (cls == 1) { u = 0.f; d2 = C.dist2(0.f); }
         else if (cls == -1) { u = 1.f; d2 = C.dist2(1.f); }
         else {
@@ -1106,7 +1164,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_DECIDE
                                   (fabsf(dot(r, d1)) <= 1e-4f * rn * sp || rn <= 1e-7f * (float)cv.diag);
                 if (!conv) cls = 0;
             }
-            if (cls == 0) piece_min(C, u, d2, kap);
+            if (cls == 0) piece_min(C, u, d2, kap, u_sec, d_sec);
         }
         const float ds = sqrtf(d2);
         // 3. certificate over the listed pieces (an unlisted piece's sphere lower bound
@@ -1159,7 +1217,11 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_DECIDE
     done[j] = 1;
     const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
     const Cand b1 = make_cand(G, s, (double)u, (double)d2, (double)kap, param_error(C, u, kap, ta, tb));
-    finish<float>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
+    if (d_sec < INFINITY) {  // two minima on the chosen piece: the second is the tie test's runner-up
+        const Cand c2 = make_cand_q(G, cv, s, (double)u_sec, (double)d_sec, 1.0, 0.0, q);
+        if (!c2.across && c2.d2 < b2.d2) b2 = c2;
+    }
+    finish<float, kGen>(G, cv, q, b1, b2, 0u, (double)tie_rel, invert, qi, o);
 }
 
 // Training-data export: candidates and features in the caller's query order.
@@ -1213,7 +1275,7 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
     const int64_t oh = take(4 * (nc + 2)), oq = take(4 * (nc + 1)), ot = take(4 * (nc + 1)), op = take(4 * n);
     const int64_t oov = take(4 * n), oc = take(4 * n * kK), oxb = take(32 * n * kK), ocn = take(4 * n);
     const int64_t opo = take(4 * n), oub = take(4 * n), ops = take(4 * cap), opj = take(4 * cap);
-    const int64_t opr = take(16 * cap), osc = take(8 * n * kK), odn = take(n);
+    const int64_t opr = take(32 * cap), osc = take(8 * n * kK), odn = take(n);
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
@@ -1240,6 +1302,7 @@ struct mrep_nn {
     uint8_t* base = nullptr;  // device: params | m | v | grad | image
     int64_t step = 0;
     int kind = MREP_NN_CURVE;
+    int compute = MREP_NN_COMPUTE_BF16;  // products of mrep_nn_forward / mrep_nn_train_step
     NetDims d;
     float* params() const { return (float*)base; }
     float* m() const { return (float*)(base + d.param_bytes); }
@@ -1406,9 +1469,21 @@ int32_t mrep_nn_forward(const mrep_nn* nn, int64_t n, const float* x, float* y, 
         return MREP_E_SMALL_BUFFER;
     }
     hipStream_t st = (hipStream_t)stream;
+    t_gemm_fp32 = nn->compute == MREP_NN_COMPUTE_FP32;
     int rc = forward(nn->d, nn->params(), n, x, w, st);
+    t_gemm_fp32 = false;
     if (rc) return rc;
     NN_HIP(hipMemcpyAsync(y, w.Y, 4 * n * nn->d.out, hipMemcpyDeviceToDevice, st));
+    return MREP_OK;
+}
+
+int32_t mrep_nn_set_compute(mrep_nn* nn, int32_t compute)
+{
+    if (!nn || (compute != MREP_NN_COMPUTE_BF16 && compute != MREP_NN_COMPUTE_FP32)) {
+        set_error("mrep_nn_set_compute: null network or unknown compute mode");
+        return MREP_E_INVALID_ARG;
+    }
+    nn->compute = compute;
     return MREP_OK;
 }
 
@@ -1459,9 +1534,10 @@ int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const fl
                            x, target, accept, w.Xb, w.Tb, w.Ab);
         X = w.Xb; T = w.Tb; A = w.Ab;
     }
+    t_gemm_fp32 = nn->compute == MREP_NN_COMPUTE_FP32;
     int rc = forward(d, nn->params(), batch, X, w, st);
-    if (rc) return rc;
-    rc = backward(d, nn->params(), batch, X, T, A, w, nn->grad(), loss_out, st);
+    if (rc == MREP_OK) rc = backward(d, nn->params(), batch, X, T, A, w, nn->grad(), loss_out, st);
+    t_gemm_fp32 = false;
     if (rc) return rc;
     if (grad_out) NN_HIP(hipMemcpyAsync(grad_out, nn->grad(), 4 * d.n, hipMemcpyDeviceToDevice, st));
     if (lr > 0.f) {
@@ -1603,18 +1679,23 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
     }
     if (timed && (rc = stage_mark(2, st))) return rc;
     if (nn) {
-        hipLaunchKernelGGL(k_decide, dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
-                           (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
-                           (int32_t)invert, w.done, o);
+        if (G.general)
+            hipLaunchKernelGGL((k_decide<true>), dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
+                               (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
+                               (int32_t)invert, w.done, o);
+        else
+            hipLaunchKernelGGL((k_decide<false>), dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
+                               (const int32_t*)w.q_off, (const int32_t*)w.perm, w.box, (const float2*)w.scores, tie,
+                               (int32_t)invert, w.done, o);
         NN_HIP(hipGetLastError());
     }
     if (timed && (rc = stage_mark(3, st))) return rc;
     NN_HIP(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.box.so, w.pair_res, nn ? w.done : nullptr,
                          nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, invert, w.ovf_list, w.ovf_count, o, st,
-                         (opts->flags & MREP_OPT_CLIP) != 0));
+                         (opts->flags & MREP_OPT_CLIP) != 0, timed ? 4 : -1));
     if (timed) {
-        if ((rc = stage_mark(4, st))) return rc;
-        stage_end(4);
+        if ((rc = stage_mark(5, st))) return rc;
+        stage_end(5);
     }
     return MREP_OK;
 }

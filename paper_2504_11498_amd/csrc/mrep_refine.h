@@ -143,16 +143,34 @@ __device__ __forceinline__ T sample_u(int k)
 template <typename T>
 __device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
 
+// parameters of a piece closer than this are one minimum, not two
+constexpr float kDistinctU = 1e-4f;
+
+// Keep the best and the second best of the piece's local minima; a candidate
+// within kDistinctU of the best is the same minimum.
+template <typename T>
+__device__ __forceinline__ void keep2(T u, T d, T k, T& u1, T& d1, T& k1, T& u2, T& d2)
+{
+    if (d < d1) {
+        if (fabs(u - u1) > (T)kDistinctU) { u2 = u1; d2 = d1; }
+        u1 = u; d1 = d; k1 = k;
+    } else if (d < d2 && fabs(u - u1) > (T)kDistinctU) {
+        u2 = u; d2 = d;
+    }
+}
+
 // Minimum of one piece.  Rescan S samples; Newton from every local minimum of
 // the samples; then every sample interval not covered by those brackets whose
 // second-order lower bound  min(D_k, D_k+1) - M h^2 / 8  still reaches below
 // the best value gets a Newton solve of its own (M >= |D''| = 2(|C'|^2 +
 // r.C'') from the hodograph control polygons), so the minimum over the piece
-// is certified, not only the sampled one.  Returns squared distance, u, kappa.
-// One unrolled pass produces bit masks; the Newton solves run in compact loops
-// over the set bits, which keeps the kernels small.
+// is certified, not only the sampled one.  Returns squared distance, u, kappa,
+// and the second best distinct local minimum found (u2, d2; d2 = inf when
+// none), which a tie between two minima of one piece needs.  One unrolled
+// pass produces bit masks; the Newton solves run in compact loops over the
+// set bits, which keeps the kernels small.
 template <typename T>
-__device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
+__device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2_out, T& d2_out)
 {
     // C' has Bezier control points a1, a1 + a2, a1 + 2 a2 + 3 a3; C'' has 2 a2, 2 a2 + 6 a3
     const V3<T> h1 = {C.a1.x + C.a2.x, C.a1.y + C.a2.y, C.a1.z + C.a2.z};
@@ -182,13 +200,14 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
         if (k < kSamples - 1) chk |= (uint32_t)(fmin(D[k], D[k + 1]) - gap < dmin) << k;
     }
     u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
+    u2_out = (T)0; d2_out = (T)INFINITY;
     uint32_t covered = 0;  // bit k: interval (k, k+1) lies inside a refined bracket
     for (uint32_t bits = lm; bits; bits &= bits - 1) {
         const int k = __builtin_ctz(bits);
         const int a = k > 0 ? k - 1 : 0, b = k < kSamples - 1 ? k + 1 : kSamples - 1;
         T ub, db, kb;
         newton_min(C, sample_u<T>(a), sample_u<T>(b), sample_u<T>(k), ub, db, kb);
-        if (db < d_out) { d_out = db; u_out = ub; k_out = kb; }
+        keep2(ub, db, kb, u_out, d_out, k_out, u2_out, d2_out);
         covered |= ((1u << b) - 1u) & ~((1u << a) - 1u);
     }
     const T best = d_out * ((T)1 - (T)(sizeof(T) == 4 ? 8e-6 : 2e-14));
@@ -198,14 +217,99 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
         if (fmin(C.dist2(ua), C.dist2(ub_)) - gap < best) {
             T ub, db, kb;
             newton_min(C, ua, ub_, (T)0.5 * (ua + ub_), ub, db, kb);
-            if (db < d_out) { d_out = db; u_out = ub; k_out = kb; }
+            keep2(ub, db, kb, u_out, d_out, k_out, u2_out, d2_out);
         }
+    }
+}
+template <typename T>
+__device__ __forceinline__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out)
+{
+    T u2, d2;
+    piece_min(C, u_out, d_out, k_out, u2, d2);
+}
+
+// Bernstein sums without a local array: sum_{i=0..m} C(m,i) v^i (1-v)^{m-i} c_i
+// with c_i = get(i), by Horner in r = v/(1-v) for v <= 1/2 and in (1-v)/v
+// above, scaled by (1-v)^m or v^m.  The ratio stays in [0, 1], and the large
+// binomial terms of the intermediate sum are scaled back by that power, so the
+// rounding stays of the order of the largest |c_i|.  Binomials are exact
+// integers updated in place (m <= 32).
+template <typename F>
+__device__ __forceinline__ double bern_sum(int m, double v, F get)
+{
+    if (m == 0) return get(0);
+    const double s = 1.0 - v;
+    double acc, bin = 1.0, pw = 1.0;
+    if (v <= 0.5) {
+        const double r = v / s;
+        acc = get(m);
+        for (int i = m - 1; i >= 0; --i) {
+            bin = bin * (double)(i + 1) / (double)(m - i);
+            acc = acc * r + bin * get(i);
+        }
+        for (int i = 0; i < m; ++i) pw *= s;
+    } else {
+        const double r = s / v;
+        acc = get(0);
+        for (int i = 1; i <= m; ++i) {
+            bin = bin * (double)(m - i + 1) / (double)i;
+            acc = acc * r + bin * get(i);
+        }
+        for (int i = 0; i < m; ++i) pw *= v;
+    }
+    return acc * pw;
+}
+
+// X, X', X'' at v of component c of a degree-p Bezier span stored with `stride`
+// doubles per point (3: Bezier points, 4: homogeneous points of a rational span).
+__device__ __forceinline__ void bern_eval(const double* cf, int stride, int c, int p, double v, double& x, double& x1,
+                                          double& x2)
+{
+    x = bern_sum(p, v, [&](int i) { return cf[stride * i + c]; });
+    x1 = p >= 1 ? (double)p * bern_sum(p - 1, v, [&](int i) { return cf[stride * (i + 1) + c] - cf[stride * i + c]; })
+                : 0.0;
+    x2 = p >= 2 ? (double)(p * (p - 1)) * bern_sum(p - 2, v, [&](int i) {
+             return (cf[stride * (i + 2) + c] - cf[stride * (i + 1) + c]) - (cf[stride * (i + 1) + c] - cf[stride * i + c]);
+         })
+                : 0.0;
+}
+
+// Exact degree-p span as Bezier points (p > MREP_POWER_MAX_DEGREE): C, C', C''.
+__device__ __forceinline__ void span_eval_bezier(const double* cf, int p, double v, const double* q, double* r,
+                                                 double* d1, double* d2)
+{
+    for (int c = 0; c < 3; ++c) {
+        double x, x1, x2;
+        bern_eval(cf, 3, c, p, v, x, x1, x2);
+        r[c] = x - q[c];
+        d1[c] = x1;
+        d2[c] = x2;
+    }
+}
+
+// Exact rational span as homogeneous Bezier points (w x, w y, w z, w): X, X',
+// X'' and W, W', W'' at v, then the quotient rule  C = X/W,  C' = (X' - C W')/W,
+// C'' = (X'' - 2 C' W' - C W'')/W.
+__device__ __forceinline__ void span_eval_rational(const double* cf, int p, double v, const double* q, double* r,
+                                                   double* d1, double* d2)
+{
+    double W, W1, W2;
+    bern_eval(cf, 4, 3, p, v, W, W1, W2);
+    for (int c = 0; c < 3; ++c) {
+        double x, x1, x2;
+        bern_eval(cf, 4, c, p, v, x, x1, x2);
+        const double C = x / W;
+        const double C1 = (x1 - C * W1) / W;
+        r[c] = C - q[c];
+        d1[c] = C1;
+        d2[c] = (x2 - 2.0 * C1 * W1 - C * W2) / W;
     }
 }
 
 // Exact degree-p span in local power form: C(v) = sum_j c_j v^j, v in [0,1].
 __device__ __forceinline__ void span_eval(const double* cf, int p, double v, const double* q, double* r, double* d1, double* d2)
 {
+
     double x[3], y[3], z[3];
     for (int c = 0; c < 3; ++c) { x[c] = cf[3 * p + c]; y[c] = 0.0; z[c] = 0.0; }
     for (int j = p - 1; j >= 0; --j)
@@ -217,36 +321,91 @@ __device__ __forceinline__ void span_eval(const double* cf, int p, double v, con
     for (int c = 0; c < 3; ++c) { r[c] = x[c] - q[c]; d1[c] = y[c]; d2[c] = z[c]; }
 }
 
-// FP64 Newton on the exact span from global parameter t0; returns (t, dist, kappa).
-__device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q, double& t_out,
-                       double& d_out, double& k_out)
+// The exact form of one span of curve cv, and its evaluation (power form,
+// Bezier points, or homogeneous Bezier points of a rational curve).
+__device__ __forceinline__ const double* span_coef(const DevGeom& G, const DCurve& cv, int64_t span)
 {
-    const int p = cv.degree;
-    const double tq = G.spant[2 * span], tq1 = G.spant[2 * span + 1];
-    const double h = tq1 - tq;
-    const double* cf = G.coef + cv.coef_off + (int64_t)(span - cv.span_off) * 3 * (p + 1);
-    double v = (t0 - tq) / h;
-    v = fmin(fmax(v, 0.0), 1.0);
-    double r[3], d1[3], d2[3];
-    span_eval(cf, p, v, q, r, d1, d2);
-    double best_v = v, best_d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    for (int it = 0; it < 12; ++it) {
-        double f = r[0] * d1[0] + r[1] * d1[1] + r[2] * d1[2];
-        double fp = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2] + r[0] * d2[0] + r[1] * d2[1] + r[2] * d2[2];
-        if (!(fp > 0.0)) break;
-        double vn = fmin(fmax(v - f / fp, 0.0), 1.0);
-        double dv = vn - v;
-        v = vn;
-        span_eval(cf, p, v, q, r, d1, d2);
-        double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        if (d <= best_d) { best_d = d; best_v = v; }
-        if (fabs(dv) <= 1e-15) break;
+    return G.coef + cv.coef_off + (span - cv.span_off) * (int64_t)(cv.rational ? 4 : 3) * (cv.degree + 1);
+}
+// kGen: the geometry has spans beyond the power form (degree above
+// MREP_POWER_MAX_DEGREE or rational curves); kernels are instantiated both
+// ways so that the common geometry does not carry the Bernstein and rational
+// evaluations in its registers.
+template <bool kGen>
+__device__ __forceinline__ void span_eval_cv(const DCurve& cv, const double* cf, double v, const double* q, double* r,
+                                             double* d1, double* d2)
+{
+    if constexpr (kGen) {
+        if (cv.rational) {
+            span_eval_rational(cf, cv.degree, v, q, r, d1, d2);
+            return;
+        }
+        if (cv.degree > MREP_POWER_MAX_DEGREE) {
+            span_eval_bezier(cf, cv.degree, v, q, r, d1, d2);
+            return;
+        }
     }
-    span_eval(cf, p, best_v, q, r, d1, d2);
-    double sp = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
-    double fp = sp + r[0] * d2[0] + r[1] * d2[1] + r[2] * d2[2];
-    k_out = sp > 0.0 ? fp / sp : 1.0;
-    t_out = (best_v == 1.0) ? tq1 : tq + best_v * h;
+    span_eval(cf, cv.degree, v, q, r, d1, d2);
+}
+
+// FP64 Newton on the exact span from global parameter t0; returns (t, dist,
+// kappa).  Newton on a span keeps its best iterate; when that lies on an end of
+// the span that is an interior joint of the curve, the polish continues on the
+// neighbouring span from the joint (at most 3 hops) and keeps the result only
+// if it goes lower: the result is then a local minimum of the exact curve, not
+// of one span.  One loop with one evaluation site keeps the kernels that inline
+// this small (the evaluation may be Bernstein or rational).
+template <bool kGen>
+__device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q,
+                                       double& t_out, double& d_out, double& k_out)
+{
+    const int32_t sp0 = (int32_t)cv.span_off, sp1 = (int32_t)(cv.span_off + cv.n_span - 1);
+    double v = (t0 - G.spant[2 * span]) / (G.spant[2 * span + 1] - G.spant[2 * span]);
+    v = fmin(fmax(v, 0.0), 1.0);
+    // best over all spans visited, and best of the current span
+    double best_v = v, best_d = INFINITY, best_k = 1.0;
+    int32_t best_span = span;
+    double cur_v = v, cur_d = INFINITY, cur_k = 1.0;
+    int hop = 0, it = 0;
+    for (int guard = 0; guard < 64; ++guard) {
+        double r[3], d1[3], d2[3];
+        span_eval_cv<kGen>(cv, span_coef(G, cv, span), v, q, r, d1, d2);
+        const double d = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double f = r[0] * d1[0] + r[1] * d1[1] + r[2] * d1[2];
+        const double sp = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+        const double fp = sp + r[0] * d2[0] + r[1] * d2[1] + r[2] * d2[2];
+        if (d <= cur_d) {
+            cur_d = d;
+            cur_v = v;
+            // conditioning of a stationary minimiser; a minimum held at an end or
+            // a corner without a stationary point is conditioned by the end: 1
+            const bool stationary = fabs(f) <= 1e-9 * sqrt(sp) * (sqrt(d) + cv.diag);
+            cur_k = (sp > 0.0 && stationary) ? fp / sp : 1.0;
+        }
+        bool done_span = !(fp > 0.0) || it >= 12;
+        if (!done_span) {
+            const double vn = fmin(fmax(v - f / fp, 0.0), 1.0);
+            done_span = fabs(vn - v) <= 1e-15;
+            v = vn;
+            ++it;
+            if (!done_span) continue;
+            // converged: the last step's point is evaluated once more only when it moved
+            if (vn != cur_v) continue;
+        }
+        // this span is done: keep it if it went lower (always for the first span)
+        if (hop > 0 && !(cur_d < best_d)) break;
+        best_v = cur_v; best_d = cur_d; best_k = cur_k; best_span = span;
+        if (hop >= 3) break;
+        if (best_v == 0.0 && span > sp0) { --span; v = 1.0; }
+        else if (best_v == 1.0 && span < sp1) { ++span; v = 0.0; }
+        else break;
+        ++hop;
+        it = 0;
+        cur_d = INFINITY;
+    }
+    const double ta = G.spant[2 * best_span], tb = G.spant[2 * best_span + 1];
+    k_out = best_k;
+    t_out = (best_v == 1.0) ? tb : ta + best_v * (tb - ta);
     d_out = sqrt(best_d);
 }
 
@@ -255,6 +414,7 @@ struct Cand {
     double kappa;
     double t_err;   // bound on the parameter error left by the refine precision
     int32_t seg;
+    int32_t across; // a piece end at an interior joint where the distance falls into the neighbour
 };
 
 template <typename T>
@@ -290,17 +450,46 @@ __device__ __forceinline__ void cand_select(bool c, const Cand& a, Cand& dst)
     dst.kappa = c ? a.kappa : dst.kappa;
     dst.t_err = c ? a.t_err : dst.t_err;
     dst.seg = c ? a.seg : dst.seg;
+    dst.across = c ? a.across : dst.across;
 }
 
 // Keep the two best candidates (squared distance, then parameter); field-wise
-// selects keep the candidates in registers.
+// selects keep the candidates in registers.  A candidate whose distance falls
+// into the neighbouring piece (across) is no local minimum of the curve: it
+// may hold the first place until a lower candidate comes, but it never becomes
+// the runner-up of the tie test, where it would stand in for the real one.
 __device__ __forceinline__ void top2(const Cand& x, Cand& b1, Cand& b2)
 {
     const bool first = x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t);
-    const bool second = !first && x.d2 < b2.d2;
-    cand_select(first, b1, b2);
+    const bool demote = first && !b1.across;
+    const bool second = !first && !x.across && x.d2 < b2.d2;
+    cand_select(demote, b1, b2);
     cand_select(second, x, b2);
     cand_select(first, x, b1);
+}
+
+// Piece s's candidate at its end u (0 or 1) when that end is an interior joint
+// of the curve: true when the squared distance keeps falling into the
+// neighbouring piece (its (C - q).C' at the joint, from the FP64 control points,
+// points back across), so the end is not a local minimum of the curve.
+__device__ __forceinline__ bool end_falls_across(const DevGeom& G, const DCurve& cv, int64_t s, double u, const double* q)
+{
+    double r[3], d[3];
+    bool left;
+    if (u == 0.0 && s > cv.seg_off) {
+        const double* P = G.gcp + (s - 1) * 12;  // previous piece: joint P3, tangent along P3 - P2
+        for (int c = 0; c < 3; ++c) { r[c] = P[9 + c] - q[c]; d[c] = P[9 + c] - P[6 + c]; }
+        left = true;
+    } else if (u == 1.0 && s < cv.seg_off + cv.n_seg - 1) {
+        const double* P = G.gcp + (s + 1) * 12;  // next piece: joint P0, tangent along P1 - P0
+        for (int c = 0; c < 3; ++c) { r[c] = P[c] - q[c]; d[c] = P[3 + c] - P[c]; }
+        left = false;
+    } else {
+        return false;
+    }
+    const double f = r[0] * d[0] + r[1] * d[1] + r[2] * d[2];
+    const double scale = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    return left ? f > 1e-12 * scale : f < -1e-12 * scale;
 }
 
 __device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u, double d2, double kappa, double t_err)
@@ -312,6 +501,16 @@ __device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u,
     x.kappa = kappa;
     x.t_err = t_err;
     x.seg = (int32_t)s;
+    x.across = 0;
+    return x;
+}
+
+// make_cand, classifying a piece-end candidate at an interior joint
+__device__ __forceinline__ Cand make_cand_q(const DevGeom& G, const DCurve& cv, int64_t s, double u, double d2,
+                                            double kappa, double t_err, const double* q)
+{
+    Cand x = make_cand(G, s, u, d2, kappa, t_err);
+    x.across = (u == 0.0 || u == 1.0) ? (int32_t)end_falls_across(G, cv, s, u, q) : 0;
     return x;
 }
 
@@ -320,10 +519,13 @@ __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const do
 {
     Cubic<T> C;
     load_cubic(G, cv, s, q, C);
-    T u, d, k;
-    piece_min(C, u, d, k);
+    T u, d, k, u2, d2;
+    piece_min(C, u, d, k, u2, d2);
     const double ta = G.segt[2 * s], tb = G.segt[2 * s + 1];
-    top2(make_cand(G, s, (double)u, (double)d, (double)k, param_error(C, u, k, ta, tb)), b1, b2);
+    top2(make_cand_q(G, cv, s, (double)u, (double)d, (double)k, param_error(C, u, k, ta, tb), q), b1, b2);
+    // a second minimum of the same piece: a runner-up candidate (its parameter
+    // error does not matter: only its distance and t enter the tie test)
+    if (d2 < (T)INFINITY) top2(make_cand_q(G, cv, s, (double)u2, (double)d2, 1.0, 0.0, q), b1, b2);
 }
 
 // Minimum sampled squared distance of a piece (the full-scan prune).
@@ -341,26 +543,36 @@ __device__ T piece_sample_min(const DevGeom& G, const DCurve& cv, int64_t s, con
 // where the cubic is an approximation (p >= 4), the minimiser is near-tangent,
 // the refine precision cannot certify the parameter to 1e-8, or the runner-up
 // is within the tie margin; then write t, distance, piece and flags.
-template <typename T>
+template <typename T, bool kGen>
 __device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const double* q, const Cand& b1, const Cand& b2,
                        uint32_t flags, double tie_rel, int invert, int32_t qi, const Outs& o)
 {
     const double d1 = sqrt(b1.d2), d2 = sqrt(b2.d2);
     const double margin = 2.0 * cv.tol_eff + (sizeof(T) == 4 ? 2e-6 : 1e-12) * (d1 + cv.diag) + tie_rel * cv.diag;
     const bool tie = b2.d2 < INFINITY && (d2 - d1) <= margin;
-    const bool approx = cv.degree >= 4;
+    const bool approx = cv.degree >= 4 || cv.rational;
     const bool illc = b1.kappa < 1e-2;
     const bool coarse = b1.t_err > 1e-8;
     double t, dist, kap = b1.kappa;
     int32_t seg = b1.seg;
     if (approx || tie || illc || coarse) {
         flags |= MREP_F_POLISHED;
-        polish(G, cv, G.segspan[b1.seg], b1.t, q, t, dist, kap);
-        if (tie) {
+        // the best, then (near tie) the runner-up, through one polish site
+        dist = INFINITY;
+        t = b1.t;
+        for (int k = 0; k < (tie ? 2 : 1); ++k) {
+            const int32_t ks = k ? b2.seg : b1.seg;
             double tt, dd, kk;
-            polish(G, cv, G.segspan[b2.seg], b2.t, q, tt, dd, kk);
-            if (dd < dist || (dd == dist && tt < t)) { t = tt; dist = dd; kap = kk; seg = b2.seg; }
+            polish<kGen>(G, cv, G.segspan[ks], k ? b2.t : b1.t, q, tt, dd, kk);
+            if (k == 0) {
+                t = tt; dist = dd; kap = kk;
+                continue;
+            }
+            // both polished points are local minima of the exact curve (the polish
+            // follows the distance across span joints): a second one within the
+            // margin and apart in t is a near tie, whichever of the two wins
             if (fabs(dd - dist) <= tie_rel * cv.diag && fabs(tt - t) > 1e-6) flags |= MREP_F_NEAR_TIE;
+            if (dd < dist || (dd == dist && tt < t)) { t = tt; dist = dd; kap = kk; seg = ks; }
         }
     } else {
         // exact cubic (p <= 3): FP64 distance at the refined parameter
@@ -393,7 +605,7 @@ __device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const
 __device__ __forceinline__ Cand empty_cand(const DCurve& cv)
 {
     Cand b;
-    b.d2 = INFINITY; b.t = 0.0; b.seg = (int32_t)cv.seg_off; b.kappa = 1.0; b.t_err = 0.0;
+    b.d2 = INFINITY; b.t = 0.0; b.seg = (int32_t)cv.seg_off; b.kappa = 1.0; b.t_err = 0.0; b.across = 0;
     return b;
 }
 

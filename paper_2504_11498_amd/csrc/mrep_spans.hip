@@ -167,8 +167,8 @@ extern "C" int32_t mrep_span_layout(int32_t n_curves, const int32_t* degree, con
     for (int32_t c = 0; c < n_curves; ++c) {
         const int p = degree[c];
         const int64_t n = cp_off[c + 1] - cp_off[c];
-        if (p < 1 || p > MREP_MAX_DEGREE) {
-            mrep::set_error("mrep_span_layout: curve " + std::to_string(c) + ": degree out of range");
+        if (p < 1 || p > MREP_SPAN_MAX_DEGREE) {
+            mrep::set_error("mrep_span_layout: curve " + std::to_string(c) + ": degree out of range 1..15");
             return MREP_E_BAD_DEGREE;
         }
         if (n < p + 1) {
@@ -191,7 +191,7 @@ extern "C" int32_t mrep_span_bezier_curves(int32_t n_curves, int64_t n_intervals
                                            const int64_t* pt_off, const double* cp_xyz, const double* knots,
                                            double* bz_out, double* t_out, void* stream)
 {
-    if (n_curves < 0 || n_intervals < 0 || max_degree < 1 || max_degree > MREP_MAX_DEGREE ||
+    if (n_curves < 0 || n_intervals < 0 || max_degree < 1 || max_degree > MREP_SPAN_MAX_DEGREE ||
         (n_intervals > 0 && (n_curves == 0 || !degree || !cp_off || !knot_off || !iv_off || !pt_off || !cp_xyz ||
                              !knots || !bz_out || !t_out))) {
         mrep::set_error("mrep_span_bezier_curves: null pointer, negative count or max_degree outside 1..15");

@@ -547,13 +547,24 @@ __device__ __forceinline__ T rel_curv(T h11, T h12, T h22, T g11, T g12, T g22)
     return (T)0.5 * (tr - sqrt(disc > (T)0 ? disc : (T)0));
 }
 
+// The patch minimum and the second best distinct local minimum found (s2, t2,
+// f2: a tie between two minima of one patch needs it).
 struct PatchMin {
     float s, t, f, kappa;
+    float s2, t2, f2;
 };
+// patch parameters closer than this (|ds| + |dt|) are one minimum, not two
+constexpr float kDistinctST = 1e-4f;
 
 __device__ __forceinline__ void pm_take(PatchMin& best, float s, float t, float f, float k)
 {
-    if (f < best.f) { best.s = s; best.t = t; best.f = f; best.kappa = k; }
+    const bool apart = fabsf(s - best.s) + fabsf(t - best.t) > kDistinctST;
+    if (f < best.f) {
+        if (apart) { best.s2 = best.s; best.t2 = best.t; best.f2 = best.f; }
+        best.s = s; best.t = t; best.f = f; best.kappa = k;
+    } else if (f < best.f2 && apart) {
+        best.s2 = s; best.t2 = t; best.f2 = f;
+    }
 }
 
 // Box-constrained Newton on [lo_s, hi_s] x [lo_t, hi_t] from (s, t): a
@@ -686,7 +697,7 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
                 cells |= (uint64_t)(mn - gap < cap) << (i * kC + j);
             }
     }
-    PatchMin best{0.f, 0.f, cap, 1.f};
+    PatchMin best{0.f, 0.f, cap, 1.f, 0.f, 0.f, cap};
     // Phase 2: Newton from each local minimum; the four cells around such a
     // sample count as covered
     uint64_t covered = 0;
@@ -720,7 +731,8 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
         if (mn - gap < best.f * (1.f - 8e-6f))
             bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
     }
-    if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f};
+    if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f, 0.f, 0.f, INFINITY};
+    if (!(best.f2 < cap)) best.f2 = INFINITY;
     return best;
 }
 
@@ -924,7 +936,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SPAIRS
         const float ub = sqrtf(__uint_as_float(fub[jj]));
         const float thr = ub + s_margin(ub, sf, tie_rel);
         const PatchMin m = patch_min(B, thr * thr * (1.f + 1e-5f));
-        res[p] = make_float4(m.s, m.t, m.f, m.kappa);
+        res[2 * p] = make_float4(m.s, m.t, m.f, m.kappa);
+        res[2 * p + 1] = make_float4(m.s2, m.t2, m.f2, 1.f);
     }
 }
 
@@ -963,7 +976,7 @@ __global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restr
     // a prediction that is not a number starts from the patch centre
     const float s0 = sc.x == sc.x ? fminf(fmaxf(sc.x, 0.f), 1.f) : 0.5f;
     const float t0 = sc.y == sc.y ? fminf(fmaxf(sc.y, 0.f), 1.f) : 0.5f;
-    PatchMin m{0.f, 0.f, INFINITY, 1.f};
+    PatchMin m{0.f, 0.f, INFINITY, 1.f, 0.f, 0.f, INFINITY};
     bc_newton(B, s0, t0, 0.f, 1.f, 0.f, 1.f, m);
     const float f = m.f * (1.f + 4e-6f);
     fub[j] = __float_as_uint(f < u2 ? f : u2);
@@ -1212,7 +1225,9 @@ __device__ void s_finish(const DevSurf& D, const DSurf& sf, const double* x, con
     const double span = fmax(bu0[sf.n_su] - bu0[0], bv0[sf.n_sv] - bv0[0]);
     const double* r1 = D.uv + 4 * b1.patch;
     const double eps = 1e-12 * span;
-    const bool on_best = b2.u >= r1[0] - eps && b2.u <= r1[1] + eps && b2.v >= r1[2] - eps && b2.v <= r1[3] + eps;
+    // (a second minimum of the best's own patch is a distinct local minimum: it is polished)
+    const bool on_best = b2.patch != b1.patch && b2.u >= r1[0] - eps && b2.u <= r1[1] + eps && b2.v >= r1[2] - eps &&
+                         b2.v <= r1[3] + eps;
     if (tie && !on_best && fabs(b2.u - r.u) + fabs(b2.v - r.v) > 1e-6 * span) {
         const Polished r2 = s_polish(D, sf, b2.u, b2.v, x);
         const bool take = r2.dist < r.dist || (r2.dist == r.dist && (r2.u < r.u || (r2.u == r.u && r2.v < r.v)));
@@ -1266,8 +1281,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_SFINIS
     SCand b1 = s_empty(), b2 = b1;
     const int64_t p0 = so.pair_off[j];
     for (int i = 0; i < n_list; ++i) {
-        const float4 r = res[p0 + i];
+        const float4 r = res[2 * (p0 + i)], r2 = res[2 * (p0 + i) + 1];
         if (r.z < INFINITY) s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
+        if (r2.z < INFINITY) s_top2(s_make(D, so.pair_seg[p0 + i], r2.x, r2.y, r2.z, r2.w), b1, b2);
     }
     if (!(b1.d2 < INFINITY)) {
         // no pair reached below its cap (FP32 rounding at the threshold): full scan
@@ -1378,6 +1394,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SFULL_
             if (mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f > thr2) return;
             const PatchMin m = patch_min(B, thr2 * (1.f + 1e-5f));
             if (m.f < INFINITY) s_top2(s_make(D, k, m.s, m.t, m.f, m.kappa), b1, b2);
+            if (m.f2 < INFINITY) s_top2(s_make(D, k, m.s2, m.t2, m.f2, 1.f), b1, b2);
         });
         // wave top-2
         for (int off = 32; off > 0; off >>= 1) {
@@ -1455,7 +1472,7 @@ __global__ void k_sfeat_fill(int64_t n, int32_t* __restrict__ patch_out, float* 
 struct SWork {
     int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
     ScreenOut so;     // per query: its pairs (patches that can hold its minimum)
-    float4* res;      // [cap] patch minimum of each pair
+    float4* res;      // [2 cap] per pair: (s, t, f, kappa) of the patch minimum, then (s, t, f) of a second one
     uint32_t* fub;    // [n] bound on each query's squared distance (float bits)
     // seeded calls
     SphTop top;          // [n][kK] candidates, [n][kK][64] BF16 inputs
@@ -1474,7 +1491,7 @@ int64_t s_layout(int64_t ns, int64_t n, bool seeded, char* base, SWork* w)
     const int64_t cap = std::min<int64_t>(kSurfPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
     const int64_t oh = take(4 * (ns + 2)), oq = take(4 * (ns + 1)), ot = take(4 * (ns + 1)), op = take(4 * n);
     const int64_t oov = take(4 * n), ocn = take(4 * n), opo = take(4 * n), oub = take(4 * n);
-    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(16 * cap);
+    const int64_t ops = take(4 * cap), opj = take(4 * cap), ors = take(32 * cap);
     const int64_t ofu = take(4 * n);
     const int64_t m = seeded ? n : 0;
     const int64_t oca = take(4 * kK * m), oxb = take(128 * kK * m), osc = take(16 * kK * m), osp = take(4 * m);

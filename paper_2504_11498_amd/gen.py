@@ -44,6 +44,7 @@ class CurveSet:
     cp: np.ndarray  # float64 [cp_off[-1], 3]
     knot_off: np.ndarray  # int64 [n+1]
     knots: np.ndarray  # float64 [knot_off[-1]]
+    weights: np.ndarray | None = None  # float64 [cp_off[-1]]: rational curves (NURBS), else None
 
     @property
     def n(self) -> int:
@@ -72,7 +73,10 @@ class CurveSet:
         cp_off[1:] = np.cumsum([len(c) for c in cps])
         k_off = np.zeros(len(ids) + 1, np.int64)
         k_off[1:] = np.cumsum([len(k) for k in kts])
-        return CurveSet(deg, cp_off, np.concatenate(cps).reshape(-1, 3), k_off, np.concatenate(kts))
+        w = None
+        if self.weights is not None:
+            w = np.concatenate([self.weights[self.cp_off[i] : self.cp_off[i + 1]] for i in ids])
+        return CurveSet(deg, cp_off, np.concatenate(cps).reshape(-1, 3), k_off, np.concatenate(kts), w)
 
 
 @dataclass
@@ -286,3 +290,242 @@ def surfaces(seed: int = 3, n_surf: int = 256, net: int = 32, per_surface: int =
     off = rng.standard_normal((m, 3)) * (0.05 * diag[sid])[:, None]
     off[on] = 0.0
     return surf, {"surface_id": sid, "uv0": uv0, "offset": off, "on_surface": on}
+
+
+# ---------------------------------------------------------------------------
+# Adversarial workloads: several correct answers, corners, poor conditioning
+# ---------------------------------------------------------------------------
+def _mirror_x(P: np.ndarray) -> np.ndarray:
+    """Mirror points in the plane x = 1/2."""
+    M = P.copy()
+    M[:, 0] = 1.0 - M[:, 0]
+    return M
+
+
+def _mirror_net(half: np.ndarray, mid: np.ndarray | None) -> np.ndarray:
+    """Control polygon symmetric about x = 1/2: half, the optional middle point, the mirrored half reversed."""
+    parts = [half] + ([mid[None, :]] if mid is not None else []) + [_mirror_x(half)[::-1]]
+    return np.concatenate(parts)
+
+
+def _mirror_knots(rng: np.random.Generator, n_int: int, double: bool = False) -> np.ndarray:
+    """n_int interior knot slots symmetric about 1/2 (each value twice when double)."""
+    per = 2 if double else 1
+    k = n_int // per
+    h = _exp_interior(rng, k // 2) * 0.5 * (1.0 - 0.1 * rng.uniform())  # strictly inside (0, 1/2)
+    vals = np.concatenate([h, [0.5] if k % 2 else [], 1.0 - h[::-1]])
+    return np.repeat(vals, per)
+
+
+def curves_adversarial(seed: int = 9):
+    """Curves and query recipes where the projection has several correct answers or a poorly
+    conditioned one (the global-minimiser definition with ties, Sec. 4 eq. projections; corner and
+    end candidates, Sec. 5.3 Properties 1-2).  Families (curve ids in ``fam``):
+
+    * ``mirror``  -- 48 curves symmetric about the plane x = 1/2 (degree 2, 3, 4, 5 or 7, 8..40
+      control points, symmetric non-uniform knots); 24 queries each uniform on that plane within the
+      control box scaled by 1.1: the distance is even about t = 1/2, so the minimum is either at
+      t = 1/2 or one of a mirror pair (an exact tie);
+    * ``corner``  -- 24 mirror-symmetric quadratics with every interior knot doubled (only C0 at
+      each joint); 16 queries each: a joint parameter plus an N(0, (0.03 diag)^2) offset, so many
+      minima sit on a corner with no stationary point;
+    * ``hairpin`` -- 8 cubic hairpins (two legs 0.4 apart joined by a bend, symmetric about
+      x = 1/2); 32 queries each on the mirror plane between the legs: equidistant from both legs;
+    * ``centre``  -- near centres of curvature, q = C(t0) + s R N (R the radius of curvature, N the
+      principal normal): on 32 mirror curves at t0 = 1/2 (two queries with s ~ U[0.9985, 0.9995], six
+      with s ~ U[0.97, 0.999]) and on 32 random cubic curves at random t0 (s ~ U[0.9, 1.0]); 8 queries
+      each.  The caller places q with its own evaluator (``centre_cid``, ``centre_t0``, ``centre_s``).
+
+    Returns (CurveSet, dict): ``point``/``point_cid`` for the absolute queries (mirror, hairpin),
+    ``corner_cid``/``corner_t0``/``corner_offset`` and the ``centre_*`` recipes, and ``fam``."""
+    rng = np.random.default_rng(seed)
+    degs, cps, kts, fam = [], [], [], {"mirror": [], "corner": [], "hairpin": [], "centre_sym": [], "centre": []}
+
+    def add(name, p, P, U):
+        fam[name].append(len(degs))
+        degs.append(p)
+        cps.append(P)
+        kts.append(U)
+
+    def mirror_curve(p, n):
+        half = rng.uniform(0.0, 1.0, (n // 2, 3))
+        half[:, 0] = rng.uniform(0.0, 0.45, n // 2)
+        mid = np.array([0.5, rng.uniform(), rng.uniform()]) if n % 2 else None
+        P = _mirror_net(half, mid)
+        U = _clamped(_mirror_knots(rng, n - p - 1), p)
+        return P, U
+
+    for i in range(48):
+        p = [2, 3, 4, 5, 7][i % 5]
+        n = int(rng.integers(max(p + 1, 8), 41))
+        add("mirror", p, *mirror_curve(p, n))
+    for i in range(24):
+        k = int(rng.integers(3, 10))  # distinct interior knots, each doubled
+        n = 3 + 2 * k
+        half = rng.uniform(0.0, 1.0, (n // 2, 3))
+        half[:, 0] = rng.uniform(0.0, 0.45, n // 2)
+        mid = np.array([0.5, rng.uniform(), rng.uniform()])
+        add("corner", 2, _mirror_net(half, mid), _clamped(_mirror_knots(rng, n - 3, double=True), 2))
+    for i in range(8):
+        ys = np.array([0.0, 0.2, 0.4, 0.6, 0.8, 0.95])
+        half = np.stack([0.3 + np.array([0, 0, 0, 0, 0, 0.06]), ys, np.full(6, 0.5)], 1)
+        half[:, 1:] += rng.normal(0.0, 0.01, (6, 2))
+        half[-1, 0] += rng.uniform(0.0, 0.04)
+        P = _mirror_net(half, None)
+        add("hairpin", 3, P, _clamped(np.arange(1, 9) / 9.0, 3))
+    for i in range(32):
+        p = [3, 4, 5][i % 3]
+        add("centre_sym", p, *mirror_curve(p, int(rng.integers(9, 30))))
+    for i in range(32):
+        n = int(rng.integers(8, 24))
+        add("centre", 3, rng.uniform(0.0, 1.0, (n, 3)), _clamped(_exp_interior(rng, n - 4), 3))
+
+    curves = _pack(degs, cps, kts)
+    diag = curves.bbox_diag()
+    out = {"fam": {k: np.array(v, np.int32) for k, v in fam.items()}}
+    pts, pcid = [], []
+    for c in fam["mirror"]:
+        P = cps[c]
+        lo, hi = P.min(0), P.max(0)
+        ctr, half = 0.5 * (lo + hi), 0.55 * (hi - lo)
+        q = rng.uniform(ctr - half, ctr + half, (24, 3))
+        q[:, 0] = 0.5
+        pts.append(q)
+        pcid.append(np.full(24, c, np.int32))
+    for c in fam["hairpin"]:
+        q = np.stack([np.full(32, 0.5), rng.uniform(0.05, 0.75, 32), 0.5 + rng.uniform(-0.05, 0.05, 32)], 1)
+        pts.append(q)
+        pcid.append(np.full(32, c, np.int32))
+    out["point"] = np.concatenate(pts)
+    out["point_cid"] = np.concatenate(pcid)
+    ccid, ct0, coff = [], [], []
+    for c in fam["corner"]:
+        U = kts[c]
+        joints = np.unique(U[3:-3])
+        ccid.append(np.full(16, c, np.int32))
+        ct0.append(rng.choice(joints, 16))
+        coff.append(rng.normal(0.0, 0.03 * diag[c], (16, 3)))
+    out["corner_cid"], out["corner_t0"], out["corner_offset"] = np.concatenate(ccid), np.concatenate(ct0), np.concatenate(coff)
+    zcid, zt0, zs = [], [], []
+    for c in fam["centre_sym"]:
+        zcid.append(np.full(8, c, np.int32))
+        zt0.append(np.full(8, 0.5))
+        zs.append(np.concatenate([rng.uniform(0.9985, 0.9995, 2), rng.uniform(0.97, 0.999, 6)]))
+    for c in fam["centre"]:
+        zcid.append(np.full(8, c, np.int32))
+        zt0.append(rng.uniform(0.1, 0.9, 8))
+        zs.append(rng.uniform(0.9, 1.0, 8))
+    out["centre_cid"], out["centre_t0"], out["centre_s"] = np.concatenate(zcid), np.concatenate(zt0), np.concatenate(zs)
+    return curves, out
+
+
+def surfaces_mirror(seed: int = 10, n_surf: int = 8, net: int = 32, per_surface: int = 160):
+    """Height fields symmetric about the plane x = 1/2 (z(x, y) = g(x, y) + g(1 - x, y) with g four random
+    sinusoids; knots in u symmetric about 1/2, in v from Exp(1) increments; degree 3x3 and 5x5 alternating)
+    and queries on that plane: (1/2, y, z) with y ~ U[0, 1] and z uniform over the net's z range widened by
+    half of it on each side.  The distance is even about u = 1/2, so the minimum is on the mirror or one of a
+    mirror pair (an exact tie).  Returns (SurfaceSet, sid, q)."""
+    rng = np.random.default_rng(seed)
+    du, dv, nu, nv, cps, kus, kvs = [], [], [], [], [], [], []
+    x = np.arange(net) / (net - 1)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    qs, sids = [], []
+    for s in range(n_surf):
+        p = 3 if s % 2 == 0 else 5
+        a = rng.uniform(0.05, 0.2, 4)
+        f = rng.uniform(0.5, 2.5, (4, 2))
+        ph = rng.uniform(0.0, 2 * np.pi, 4)
+
+        def g(Xa, Ya):
+            return sum(a[k] * np.sin(2 * np.pi * (f[k, 0] * Xa + f[k, 1] * Ya) + ph[k]) for k in range(4))
+
+        Z = g(X, Y) + g(X[::-1, :], Y)  # X[::-1] holds 1 - x exactly on this grid
+        P = np.stack([X, Y, Z], -1).reshape(-1, 3)
+        du.append(p)
+        dv.append(p)
+        nu.append(net)
+        nv.append(net)
+        cps.append(P)
+        kus.append(_clamped(_mirror_knots(rng, net - p - 1), p))
+        kvs.append(_clamped(_exp_interior(rng, net - p - 1), p))
+        zlo, zhi = Z.min(), Z.max()
+        w = zhi - zlo
+        q = np.stack([np.full(per_surface, 0.5), rng.uniform(0.0, 1.0, per_surface),
+                      rng.uniform(zlo - 0.5 * w, zhi + 0.5 * w, per_surface)], 1)
+        qs.append(q)
+        sids.append(np.full(per_surface, s, np.int32))
+    n = n_surf
+    cp_off = np.zeros(n + 1, np.int64)
+    cp_off[1:] = np.cumsum([len(c) for c in cps])
+    ku_off = np.zeros(n + 1, np.int64)
+    ku_off[1:] = np.cumsum([len(k) for k in kus])
+    kv_off = np.zeros(n + 1, np.int64)
+    kv_off[1:] = np.cumsum([len(k) for k in kvs])
+    surf = SurfaceSet(np.array(du, np.int32), np.array(dv, np.int32), np.array(nu, np.int32),
+                      np.array(nv, np.int32), cp_off, np.concatenate(cps), ku_off, np.concatenate(kus),
+                      kv_off, np.concatenate(kvs))
+    return surf, np.concatenate(sids), np.concatenate(qs)
+
+
+def curves_high_degree(seed: int = 11, degrees=(16, 20, 24, 28, 32), per_degree: int = 4, cp_extra=(1, 24),
+                       per_curve: int = 128):
+    """Curves of degree 16..32 (beyond the power form's reach): per degree, ``per_degree`` curves with
+    p + 1 + U{cp_extra} control points uniform in [0,1]^3 and Exp(1) knots (the first curve of each degree a
+    single Bezier span), and ``per_curve`` offset queries each (sigma = 0.05 * diag, a quarter on the curve)."""
+    rng = np.random.default_rng(seed)
+    degs, cps, kts = [], [], []
+    for p in degrees:
+        for k in range(per_degree):
+            n_cp = p + 1 + (0 if k == 0 else int(rng.integers(cp_extra[0], cp_extra[1] + 1)))
+            degs.append(int(p))
+            cps.append(rng.uniform(0.0, 1.0, (n_cp, 3)))
+            kts.append(_clamped(_exp_interior(rng, n_cp - p - 1), int(p)))
+    curves = _pack(degs, cps, kts)
+    return curves, offset_queries(seed + 100, curves, per_curve=per_curve, on_curve_frac=0.25)
+
+
+# ---------------------------------------------------------------------------
+# Rational curves (NURBS)
+# ---------------------------------------------------------------------------
+def _circle_net(rng: np.random.Generator):
+    """Full circle as a quadratic NURBS: 9 control points on a square around the centre, weights 1 and
+    sqrt(1/2) alternating, knots {0^3, 1/4^2, 1/2^2, 3/4^2, 1^3}; random centre, radius and plane."""
+    sq = np.array([[1, 0], [1, 1], [0, 1], [-1, 1], [-1, 0], [-1, -1], [0, -1], [1, -1], [1, 0]], float)
+    w = np.array([1.0, np.sqrt(0.5)] * 4 + [1.0])
+    A = np.linalg.qr(rng.standard_normal((3, 3)))[0]  # random orthonormal frame
+    r = rng.uniform(0.2, 0.5)
+    c = rng.uniform(0.3, 0.7, 3)
+    P = c + r * (sq[:, :1] * A[:, 0] + sq[:, 1:] * A[:, 1])
+    U = np.array([0, 0, 0, 0.25, 0.25, 0.5, 0.5, 0.75, 0.75, 1, 1, 1.0])
+    return P, w, U, c, r, A[:, 2]
+
+
+def curves_rational(seed: int = 13, n_random: int = 56, n_circles: int = 8, per_curve: int = 128):
+    """Rational B-spline curves: ``n_circles`` exact full circles (quadratic NURBS) and ``n_random`` curves of
+    degree U{2..5} with U{8..40} control points uniform in [0,1]^3, weights log-uniform in [1/4, 4] and Exp(1)
+    knots with 10% doubled.  Queries as the batched curves: ``per_curve`` offsets of N(0, (0.05 diag)^2) from
+    parameter-uniform curve points, a quarter of them on the curve.  Returns (CurveSet with weights, queries,
+    circles) where circles = list of (centre, radius, normal) of the first ``n_circles`` curves."""
+    rng = np.random.default_rng(seed)
+    degs, cps, kts, ws, circles = [], [], [], [], []
+    for _ in range(n_circles):
+        P, w, U, c, r, nrm = _circle_net(rng)
+        degs.append(2)
+        cps.append(P)
+        ws.append(w)
+        kts.append(U)
+        circles.append((c, r, nrm))
+    for _ in range(n_random):
+        p = int(rng.integers(2, 6))
+        n_cp = int(rng.integers(max(8, p + 1), 41))
+        n_int = n_cp - p - 1
+        n_dup = min(int(round(0.1 * n_int)), n_int // 2)
+        base = _exp_interior(rng, n_int - n_dup)
+        interior = np.concatenate([base, base[rng.choice(n_int - n_dup, n_dup, replace=False)]]) if n_dup else base
+        degs.append(p)
+        cps.append(rng.uniform(0.0, 1.0, (n_cp, 3)))
+        ws.append(np.exp(rng.uniform(np.log(0.25), np.log(4.0), n_cp)))
+        kts.append(_clamped(interior, p))
+    curves = _pack(degs, cps, kts)
+    curves.weights = np.concatenate(ws)
+    return curves, offset_queries(seed + 100, curves, per_curve=per_curve, on_curve_frac=0.25), circles

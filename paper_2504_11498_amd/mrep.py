@@ -30,8 +30,11 @@ PREC_FP64, PREC_BF16 = 0, 3
 OPT_TIME_STAGES, OPT_TUNED, OPT_CLIP = 1, 2, 4
 STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
 ROOTS_FERRARI, ROOTS_NEWTON = 0, 1
-N_STAGES = 4
-MAX_DEGREE = 15
+N_STAGES = 5
+MAX_DEGREE = 32  # curves
+POWER_MAX_DEGREE = 15  # spans kept in power form up to here, as Bezier points above
+MAX_SURFACE_DEGREE = 15
+SPAN_MAX_DEGREE = 15  # mrep_span_bezier_curves
 NN_CURVE, NN_SURFACE = 0, 1
 NN_HIDDEN, NN_K = 128, 4
 NN_DIMS = {NN_CURVE: (15, 2), NN_SURFACE: (51, 3)}  # kind -> (inputs, outputs)
@@ -60,6 +63,8 @@ def _sig(name, res, *args):
 
 
 _decompose = _sig("mrep_decompose_curves", _i32, _i32, _pi32, _pi64, _pd, _pi64, _pd, _dbl, _i32, C.POINTER(_vp))
+_decompose_rational = _sig("mrep_decompose_curves_rational", _i32, _i32, _pi32, _pi64, _pd, _pd, _pi64, _pd, _dbl,
+                          _i32, C.POINTER(_vp))
 _plan_info = _sig("mrep_plan_info", _i32, _vp, C.POINTER(PlanInfo))
 _plan_export = _sig("mrep_plan_export", _i32, _vp, _pi64, _pd, _pd, _pi32)
 _plan_free = _sig("mrep_plan_free", None, _vp)
@@ -111,6 +116,9 @@ _surf_seed_ws = _sig("mrep_surface_seeded_workspace_bytes", _i32, _vp, _i64, C.P
 _nn_surf_features = _sig("mrep_nn_surface_features", _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp)
 _project_s_seeded = _sig("mrep_project_surfaces_seeded", _i32, _vp, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64,
                          _vp, _vp, _vp, _vp, _vp)
+_ws_counts = _sig("mrep_workspace_counts", _i32, _vp, _vp, _pi64, _vp)
+_nn_set_compute = _sig("mrep_nn_set_compute", _i32, _vp, _i32)
+NN_COMPUTE_BF16, NN_COMPUTE_FP32 = 0, 1
 _last_error = _sig("mrep_last_error", C.c_char_p)
 _abi = _sig("mrep_abi_version", _i32)
 
@@ -126,7 +134,8 @@ EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
            "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split", "mrep_span_layout",
-           "mrep_span_bezier_curves", "mrep_project_curves_noalloc"]
+           "mrep_span_bezier_curves", "mrep_project_curves_noalloc", "mrep_decompose_curves_rational",
+           "mrep_workspace_counts", "mrep_nn_set_compute"]
 
 
 class MrepError(RuntimeError):
@@ -189,6 +198,12 @@ class Plan:
                             _p(seg_span, C.c_int32)), "mrep_plan_export")
         return {"seg_off": seg_off, "seg_t": seg_t, "seg_cp": seg_cp, "seg_span": seg_span}
 
+    def seg_off(self):
+        """Per-curve offsets of the cubic pieces (n_curves + 1), without copying the piece tables."""
+        seg_off = np.zeros(self.n_curves + 1, np.int64)
+        _check(_plan_export(self._h, _p(seg_off, C.c_int64), None, None, None), "mrep_plan_export")
+        return seg_off
+
     @property
     def is_surfaces(self):
         return int(self.info.reserved) == 1
@@ -226,17 +241,26 @@ class Plan:
             pass
 
 
-def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0) -> Plan:
-    """mrep_decompose_curves on a CurveSet-like object (degree, cp_off, cp, knot_off, knots)."""
+def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0, weights=None) -> Plan:
+    """mrep_decompose_curves on a CurveSet-like object (degree, cp_off, cp, knot_off, knots); with weights (one
+    per control point, or a ``weights`` attribute of the curve set) mrep_decompose_curves_rational."""
     deg = _host(curves.degree, np.int32)
     cp_off = _host(curves.cp_off, np.int64)
     cp = _host(curves.cp, np.float64)
     k_off = _host(curves.knot_off, np.int64)
     kn = _host(curves.knots, np.float64)
+    if weights is None:
+        weights = getattr(curves, "weights", None)
     h = _vp()
-    _check(_decompose(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(cp, C.c_double),
-                      _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel), int(n_threads), C.byref(h)),
-           "mrep_decompose_curves")
+    if weights is None:
+        _check(_decompose(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(cp, C.c_double),
+                          _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel), int(n_threads), C.byref(h)),
+               "mrep_decompose_curves")
+    else:
+        w = _host(weights, np.float64)
+        _check(_decompose_rational(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(cp, C.c_double),
+                                   _p(w, C.c_double), _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel),
+                                   int(n_threads), C.byref(h)), "mrep_decompose_curves_rational")
     return Plan(h.value)
 
 
@@ -326,8 +350,8 @@ def default_opts(precision: str | int = "bf16", max_candidates: int = 32, tie_re
 def last_stage_times():
     """Stage milliseconds of the last call made with time_stages=True on this thread.
 
-    mrep_project_curves: [grouping, screen, refine]; seeded call: [grouping + sphere candidates, network,
-    seed + certificate, fallback]."""
+    mrep_project_curves: [grouping, screen, pair refine, finish]; seeded call: [grouping + sphere candidates,
+    network, seed + certificate, pair refine, finish]."""
     out = np.zeros(N_STAGES)
     rc = _stage_times(_p(out, C.c_double), N_STAGES)
     if rc <= 0:
@@ -405,6 +429,15 @@ class Geometry:
                   int(ws.numel()), _vp(t.data_ptr()), _vp(d.data_ptr()), _vp(s.data_ptr()), _vp(f.data_ptr()),
                   _vp(stream)), "mrep_invert_curves" if invert else "mrep_project_curves")
         return t, d, s, f
+
+    def workspace_counts(self, workspace):
+        """(queries overflowed to the full scan, candidate pairs reserved) left by the last call on workspace."""
+        import torch
+
+        c = np.zeros(2, np.int64)
+        stream = torch.cuda.current_stream(workspace.device).cuda_stream
+        _check(_ws_counts(self._h, _vp(workspace.data_ptr()), _p(c, C.c_int64), _vp(stream)), "mrep_workspace_counts")
+        return int(c[0]), int(c[1])
 
     def project_noalloc(self, q, curve_id, opts: Opts | None = None, out=None):
         """As project(), through mrep_project_curves_noalloc: no workspace, the library's fixed per-GPU scratch."""
@@ -681,6 +714,10 @@ class Network:
 
     def init(self, seed: int):
         _check(_nn_init(self._h, C.c_uint64(int(seed)), self._stream()), "mrep_nn_init")
+
+    def set_compute(self, compute: int):
+        """NN_COMPUTE_BF16 (default) or NN_COMPUTE_FP32 (debug) for forward() and train_step()."""
+        _check(_nn_set_compute(self._h, int(compute)), "mrep_nn_set_compute")
 
     def set_params(self, p):
         p = _host(p, np.float32)

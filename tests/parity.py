@@ -40,9 +40,58 @@ def oracle_seg_index(ref, off, cid, t):
     return seg, near
 
 
-def compare(curves, cid, q, gpu, ref_proj, ref_dec=None, tol_rel=1e-6, label=""):
-    """gpu: dict of numpy t, dist, seg, flags.  Returns a dict of stats; asserts the bar."""
+# the reported distance must be realised by the reported parameter: |C(t) - q|
+# (the oracle's de Boor evaluation) within this of dist, relative to the diagonal
+REAL_REL = 1e-12
+# flag bands (the oracle's runner-up gap and kappa; between the bands either answer is right)
+TIE_SET, TIE_CLEAR = 1e-6, 4e-6
+ILL_SET, ILL_CLEAR = 3e-3, 3e-2
+F_NEAR_TIE, F_ILL_COND = 0x2, 0x4
+
+
+def check_flags(gpu, ref_proj, diag, label=""):
+    """NEAR_TIE set where the oracle's runner-up is within TIE_SET * diag of the minimum and clear where it
+    is beyond TIE_CLEAR * diag; where unique, ILL_COND set where the oracle's kappa < ILL_SET and clear where
+    kappa > ILL_CLEAR (interior stationary minima: the oracle reports kappa = 1 at ends and corners)."""
+    gap = (ref_proj["runner"] - ref_proj["dist"]) / diag
+    tie_flag = (gpu["flags"] & F_NEAR_TIE) != 0
+    ill_flag = (gpu["flags"] & F_ILL_COND) != 0
+    must_tie, must_not = gap <= TIE_SET, gap > TIE_CLEAR
+    bad = np.nonzero((must_tie & ~tie_flag) | (must_not & tie_flag))[0]
+    st = {"ties": int(must_tie.sum()), "unique": int(must_not.sum()), "near_tie_set": int(tie_flag.sum())}
+    tkey = "t" if "t" in gpu else "uv"
+    for i in bad[:6]:
+        print(f"  q{i} gpu {tkey}={gpu[tkey][i]} d={gpu['dist'][i]:.15g} flags={int(gpu['flags'][i]):#x} | oracle "
+              f"{tkey}={ref_proj[tkey][i]} d={ref_proj['dist'][i]:.15g} runner={ref_proj['runner'][i]:.15g} "
+              f"kappa={ref_proj['kappa'][i]:.4g}", flush=True)
+    assert bad.size == 0, (f"{label}: NEAR_TIE disagrees with the oracle on {bad.size} queries, e.g. {bad[:5]} "
+                           f"gap {gap[bad[:5]]} flag {tie_flag[bad[:5]]}")
+    kap = ref_proj["kappa"]
+    ill, well = must_not & (kap < ILL_SET), must_not & (kap > ILL_CLEAR)
+    bad = np.nonzero((ill & ~ill_flag) | (well & ill_flag))[0]
+    st["ill"] = int(ill.sum())
+    assert bad.size == 0, (f"{label}: ILL_COND disagrees with the oracle on {bad.size} queries, e.g. {bad[:5]} "
+                           f"kappa {kap[bad[:5]]} flag {ill_flag[bad[:5]]}")
+    return st
+
+
+def compare(curves, cid, q, gpu, ref_proj, ref_dec=None, tol_rel=1e-6, label="", flags=False):
+    """gpu: dict of numpy t, dist, seg, flags.  Returns a dict of stats; asserts the bar.
+
+    Every query: distance parity; the distance realised by the returned parameter on the exact curve
+    (oracle evaluation, rational when the curve set has weights); the returned piece holds the returned
+    parameter (with ref_dec: (dict with "tab", offsets) -- the oracle's decomposition, or the library's exported
+    pieces for rational curves, whose pieces the oracle validates instead of reproducing).  flags: the
+    NEAR_TIE / ILL_COND bits against the oracle's runner-up and kappa (check_flags)."""
     diag = curves.bbox_diag()[cid]
+    if getattr(curves, "weights", None) is not None:
+        X = oracle.nurbs_eval_batch(curves, curves.weights, cid, gpu["t"])
+    else:
+        X = oracle.eval_batch(curves, cid, gpu["t"])
+    real = np.abs(np.linalg.norm(X - q, axis=1) - gpu["dist"]) / diag
+    bad_r = np.nonzero(~(real <= REAL_REL))[0]
+    assert bad_r.size == 0, (f"{label}: {bad_r.size} distances not realised by their parameter, worst "
+                             f"{np.nanmax(real):.3e} at {bad_r[:5]}")
     d_ref, t_ref = ref_proj["dist"], ref_proj["t"]
     err_d = np.abs(gpu["dist"] - d_ref) / diag
     below = (d_ref - gpu["dist"]) / diag
@@ -56,8 +105,19 @@ def compare(curves, cid, q, gpu, ref_proj, ref_dec=None, tol_rel=1e-6, label="")
     assert below.max() <= 1e-12, f"{label}: GPU distance below the global minimum by {below.max():.3e}"
     bad_t = np.nonzero(wc & (err_t > T_ABS))[0]
     assert bad_t.size == 0, f"{label}: {bad_t.size} parameters off, worst {err_t[wc].max():.3e} at {bad_t[:5]}"
+    stats["max_realised_rel"] = float(real.max()) if real.size else 0.0
+    if flags:
+        stats.update(check_flags(gpu, ref_proj, diag, label))
     if ref_dec is not None:
         ref, off = ref_dec
+        # the returned piece holds the returned parameter (the oracle's pieces have the library's breakpoints)
+        g = off[cid] + gpu["seg"]
+        inside = (gpu["seg"] >= 0) & (off[cid] + gpu["seg"] < off[cid + 1])
+        g = np.where(inside, g, 0)
+        slack = 1e-12
+        holds = inside & (ref["tab"][g, 0] - slack <= gpu["t"]) & (gpu["t"] <= ref["tab"][g, 1] + slack)
+        bad_h = np.nonzero(~holds)[0]
+        assert bad_h.size == 0, f"{label}: {bad_h.size} returned pieces do not hold the returned t, e.g. {bad_h[:5]}"
         seg_ref, near = oracle_seg_index(ref, off, cid, t_ref)
         chk = unique & ~near
         bad_s = np.nonzero(chk & (gpu["seg"] != seg_ref))[0]
@@ -72,18 +132,25 @@ def surf_diag(S):
                      for k in range(S.n)])
 
 
-def compare_surf(S, sid, q, out, ref, ex=None, label=""):
+def compare_surf(S, sid, q, out, ref, ex=None, label="", flags=False):
     """Parity bar: distance within 1e-6 * diag and never below the oracle; (u, v) within 1e-7 where the
     oracle's minimum is unique and well conditioned; the patch index equals the exported patch holding the
     oracle's (u, v) where unique and not within 1e-7 of a patch side."""
     diag = surf_diag(S)[sid]
+    X = oracle.surf_eval(S, sid, out["uv"])
+    real = np.abs(np.linalg.norm(X - q, axis=1) - out["dist"]) / diag
+    bad = np.nonzero(~(real <= REAL_REL))[0]
+    assert bad.size == 0, (f"{label}: {bad.size} distances not realised by their (u, v), worst {np.nanmax(real):.3e} "
+                           f"at {bad[:5]}")
     err = np.abs(out["dist"] - ref["dist"]) / diag
     below = (ref["dist"] - out["dist"]) / diag
     unique = (ref["runner"] - ref["dist"]) > UNIQUE_REL * diag
     wc = unique & (ref["kappa"] >= KAPPA_MIN)
     duv = np.abs(out["uv"] - ref["uv"]).max(1)
     st = {"n": int(len(sid)), "max_dist_rel": float(err.max()), "max_uv_err_wc": float(duv[wc].max()) if wc.any() else 0.0,
-          "wc_frac": float(wc.mean())}
+          "wc_frac": float(wc.mean()), "max_realised_rel": float(real.max())}
+    if flags:
+        st.update(check_flags(out, ref, diag, label))
     bad = np.nonzero(err > DIST_REL)[0]
     assert bad.size == 0, f"{label}: {bad.size} distances off, worst {err.max():.3e} at {bad[:5]}"
     assert below.max() <= 1e-12, f"{label}: below the oracle by {below.max():.3e}"

@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 6
+    assert mrep.abi_version() == 7
 
 
 def test_rebasement_matrix_matches_printed_T5():
@@ -100,8 +100,14 @@ def test_decomposition_low_degree_matches_boehm():
     assert np.abs(ex["seg_cp"] - ref["R"]).max() <= 1e-12
 
 
-def test_decomposition_high_degree_matches_oracle_breakpoints():
-    curves = gen.curves_batched_geometry(seed=9, n_curves=48, deg_lo=4, deg_hi=7, cp_lo=8, cp_hi=120)
+@pytest.mark.parametrize("which", ["deg4-7", "deg16-32"])
+def test_decomposition_high_degree_matches_oracle_breakpoints(which):
+    """Degrees 4..7, and 16..32 where the library takes each span's Bezier points from blossoms instead of the
+    power form (the oracle always from Boehm's knot insertion)."""
+    if which == "deg4-7":
+        curves = gen.curves_batched_geometry(seed=9, n_curves=48, deg_lo=4, deg_hi=7, cp_lo=8, cp_hi=120)
+    else:
+        curves, _ = gen.curves_high_degree(per_degree=2, cp_extra=(1, 12))
     plan, ex, ref, counts, mismatch, diag = _compare_with_oracle(curves, 1e-6)
     assert mismatch.size == 0, mismatch
     np.testing.assert_allclose(ex["seg_t"], ref["tab"], atol=1e-14)
@@ -134,7 +140,7 @@ def test_error_codes():
     mrep.decompose_curves(_curveset(3, P, U), 1e-6)  # valid
     cases = [
         (_curveset(0, P, np.concatenate([[0], U[3:7], [1, 1]])), 1e-6, mrep.E_BAD_DEGREE),
-        (_curveset(16, np.zeros((20, 3)), np.linspace(0, 1, 37)), 1e-6, mrep.E_BAD_DEGREE),
+        (_curveset(33, np.zeros((40, 3)), np.linspace(0, 1, 74)), 1e-6, mrep.E_BAD_DEGREE),
         (_curveset(3, P, U[::-1]), 1e-6, mrep.E_BAD_KNOTS),
         (_curveset(3, P, np.array([0, 0, 0, 0.1, 0.4, 0.6, 1, 1, 1, 1.0])), 1e-6, mrep.E_BAD_KNOTS),
         (_curveset(3, P, np.array([0, 0, 0, 0, 0.5, 0.5, 0.5, 0.5, 1, 1, 1, 1.0])[:10]), 1e-6, mrep.E_BAD_KNOTS),
@@ -333,3 +339,29 @@ def test_surface_decomposition_errors():
     assert plan.is_surfaces and plan.n_segments == 9
     with pytest.raises(mrep.MrepError):
         plan.export()
+
+
+def test_rational_decomposition_pieces_within_tolerance():
+    """NURBS: every exported polynomial cubic piece lies within tol of the rational curve (the rational oracle's
+    dense check), pieces tile each curve's domain in order, and bad weights are refused."""
+    curves, _, circles = gen.curves_rational(13, n_random=24, n_circles=4, per_curve=1)
+    plan = mrep.decompose_curves(curves, 1e-6)
+    ex = plan.export()
+    diag = curves.bbox_diag()
+    worst = 0.0
+    for k in range(curves.n):
+        p, P, U = curves.curve(k)
+        w = curves.weights[curves.cp_off[k]:curves.cp_off[k + 1]]
+        tab = ex["seg_t"][ex["seg_off"][k]:ex["seg_off"][k + 1]]
+        assert tab[0, 0] == U[p] and tab[-1, 1] == U[-p - 1]
+        np.testing.assert_array_equal(tab[1:, 0], tab[:-1, 1])
+        for s in range(ex["seg_off"][k], ex["seg_off"][k + 1]):
+            ta, tb = ex["seg_t"][s]
+            worst = max(worst, oracle.nurbs_piece_deviation(p, P, w, U, ta, tb, ex["seg_cp"][s], 513) / (1e-6 * diag[k]))
+    assert worst <= 1.0
+    bad = gen.CurveSet(curves.degree, curves.cp_off, curves.cp, curves.knot_off, curves.knots, curves.weights.copy())
+    bad.weights[3] = -1.0
+    with pytest.raises(mrep.MrepError) as e:
+        mrep.decompose_curves(bad, 1e-6)
+    assert e.value.code == mrep.E_INVALID_ARG
+    assert mrep._decompose_rational(1, None, None, None, None, None, None, 1e-6, 0, None) == mrep.E_INVALID_ARG
