@@ -234,6 +234,14 @@ static void or_curve_eval_k(const or_curve *c, int k, double t, double *X, doubl
     else D1[0] = D1[1] = D1[2] = 0.0;
 }
 
+/* ... and C'' (the second derivative curve's span is k - 2). */
+static void or_curve_eval_k2(const or_curve *c, int k, double t, double *X, double *D1, double *D2)
+{
+    or_curve_eval_k(c, k, t, X, D1);
+    if (c->p >= 2) or_deboor_k(c->p - 2, c->P2, c->U + 2, k - 2, t, D2);
+    else D2[0] = D2[1] = D2[2] = 0.0;
+}
+
 int orc_eval(int p, int n, const double *P, const double *U, int64_t m, const double *t,
              double *X, double *D1, double *D2)
 {
@@ -688,11 +696,14 @@ static double or_dist(const or_curve *c, const double *q, double t)
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-/* f(t) = (C - q).C' and f'(t) = |C'|^2 + (C - q).C''  (eqs. Et and E't, halved). */
-static void or_orth(const or_curve *c, const double *q, double t, double *f, double *fp, double *dist)
+/* f(t) = (C - q).C' and f'(t) = |C'|^2 + (C - q).C''  (eqs. Et and E't, halved)
+ * on the polynomial piece of span s (index into span_k), ends included: at a
+ * knot where the curve is only C0 (or C1), f jumps, and each span's search
+ * needs its own one-sided values there (Sec. 5.3, Properties 1-2). */
+static void or_orth(const or_curve *c, int s, const double *q, double t, double *f, double *fp, double *dist)
 {
     double X[3], D1[3], D2[3];
-    or_curve_eval(c, t, X, D1, D2);
+    or_curve_eval_k2(c, c->span_k[s], t, X, D1, D2);
     double r[3] = {X[0] - q[0], X[1] - q[1], X[2] - q[2]};
     *f = r[0] * D1[0] + r[1] * D1[1] + r[2] * D1[2];
     *fp = D1[0] * D1[0] + D1[1] * D1[1] + D1[2] * D1[2] + r[0] * D2[0] + r[1] * D2[1] + r[2] * D2[2];
@@ -720,8 +731,8 @@ static void or_local_min(or_query *Q, int span, double a, double b, double t0)
     const or_curve *c = Q->c;
     const double *q = Q->q;
     double fa, fpa, da, fb, fpb, db;
-    or_orth(c, q, a, &fa, &fpa, &da);
-    or_orth(c, q, b, &fb, &fpb, &db);
+    or_orth(c, span, q, a, &fa, &fpa, &da);
+    or_orth(c, span, q, b, &fb, &fpb, &db);
     or_record(Q, a, da, 0, span);
     or_record(Q, b, db, 0, span);
     if (fa < 0.0 && fb > 0.0) {
@@ -729,14 +740,14 @@ static void or_local_min(or_query *Q, int span, double a, double b, double t0)
         if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
         double f, fp, d;
         for (int it = 0; it < 100; ++it) {
-            or_orth(c, q, t, &f, &fp, &d);
+            or_orth(c, span, q, t, &f, &fp, &d);
             if (f < 0.0) lo = t; else if (f > 0.0) hi = t; else break;
             double tn = (fp > 0.0) ? t - f / fp : 0.5 * (lo + hi);
             if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
             if (fabs(tn - t) <= 1e-15 * (fabs(t) + 1e-300) || hi - lo <= 4e-16 * (fabs(t) + 1e-300)) { t = tn; break; }
             t = tn;
         }
-        or_orth(c, q, t, &f, &fp, &d);
+        or_orth(c, span, q, t, &f, &fp, &d);
         or_record(Q, t, d, 1, span);
         return;
     }
@@ -744,7 +755,7 @@ static void or_local_min(or_query *Q, int span, double a, double b, double t0)
     double t = t0 < a ? a : (t0 > b ? b : t0);
     for (int it = 0; it < 60; ++it) {
         double f, fp, d;
-        or_orth(c, q, t, &f, &fp, &d);
+        or_orth(c, span, q, t, &f, &fp, &d);
         if (!(fp > 0.0)) break;
         double tn = t - f / fp;
         if (tn < a) tn = a;
@@ -753,10 +764,10 @@ static void or_local_min(or_query *Q, int span, double a, double b, double t0)
         t = tn;
     }
     double f, fp, d;
-    or_orth(c, q, t, &f, &fp, &d);
+    or_orth(c, span, q, t, &f, &fp, &d);
     /* interior only when the end point is a stationary minimum within rounding */
     double X[3], D1[3];
-    or_curve_eval(c, t, X, D1, NULL);
+    or_curve_eval_k(c, c->span_k[span], t, X, D1);
     double sp = sqrt(D1[0] * D1[0] + D1[1] * D1[1] + D1[2] * D1[2]);
     int stat = fabs(f) <= 1e-9 * sp * (d + c->diag) && fp > 0.0;
     or_record(Q, t, d, (t > a && t < b) && stat, span);
@@ -784,8 +795,8 @@ static void or_bb(or_query *Q, int span, double L1, double L2, double a, double 
     if (lb >= Q->best_d + Q->margin) return;
     if (or_contains_min(Q, a, b)) return;
     double fa, fpa, fb, fpb, dd;
-    or_orth(Q->c, Q->q, a, &fa, &fpa, &dd);
-    or_orth(Q->c, Q->q, b, &fb, &fpb, &dd);
+    or_orth(Q->c, span, Q->q, a, &fa, &fpa, &dd);
+    or_orth(Q->c, span, Q->q, b, &fb, &fpb, &dd);
     double F = L1 * L1 + ((da > db ? da : db) + L1 * w) * L2;
     if (fa > F * w || fb < -F * w) return;
     if (depth >= 14) { or_local_min(Q, span, a, b, 0.5 * (a + b)); return; }
@@ -794,7 +805,7 @@ static void or_bb(or_query *Q, int span, double L1, double L2, double a, double 
     for (int i = 1; i < 4; ++i) {
         double fp;
         t[i] = a + w * (double)i / 4.0;
-        or_orth(Q->c, Q->q, t[i], &f[i], &fp, &d[i]);
+        or_orth(Q->c, span, Q->q, t[i], &f[i], &fp, &d[i]);
     }
     for (int i = 1; i < 4; ++i)
         if (d[i] <= d[i - 1] && d[i] <= d[i + 1]) or_local_min(Q, span, t[i - 1], t[i + 1], t[i]);
@@ -837,8 +848,8 @@ static void or_project_one(const or_curve *c, const double *q, double *t_out, do
     free(allt); free(alld);
     /* conditioning at the minimiser and the best distinct local minimum */
     double f, fp, d, X[3], D1[3], D2[3];
-    or_orth(c, q, Q.best_t, &f, &fp, &d);
-    or_curve_eval(c, Q.best_t, X, D1, D2);
+    or_orth(c, Q.best_span, q, Q.best_t, &f, &fp, &d);
+    or_curve_eval_k2(c, c->span_k[Q.best_span], Q.best_t, X, D1, D2);
     double sp2 = D1[0] * D1[0] + D1[1] * D1[1] + D1[2] * D1[2];
     double kappa = 1.0;
     double tol_f = 1e-9 * (sqrt(sp2) * (d + c->diag) + 1e-300);
@@ -870,8 +881,8 @@ static void or_project_one(const or_curve *c, const double *q, double *t_out, do
     {
         double t0 = c->U[c->p], t1 = c->U[c->n];
         double f0, fp0, d0, f1, fp1, d1;
-        or_orth(c, q, t0, &f0, &fp0, &d0);
-        or_orth(c, q, t1, &f1, &fp1, &d1);
+        or_orth(c, 0, q, t0, &f0, &fp0, &d0);
+        or_orth(c, c->nspan - 1, q, t1, &f1, &fp1, &d1);
         if (f0 >= 0.0 && fabs(t0 - Q.best_t) > 1e-6 && d0 < runner) runner = d0;
         if (f1 <= 0.0 && fabs(t1 - Q.best_t) > 1e-6 && d1 < runner) runner = d1;
     }

@@ -215,3 +215,76 @@ def test_surface_crease_minima():
             assert abs(r["runner"][0] - max(dl, dr)) <= 1e-12
         else:
             assert np.isinf(r["runner"][0]) or abs(r["runner"][0] - max(dl, dr)) <= 1e-12
+
+
+# --------------------------------------------------------------------------- C0 quadratics, every minimum by roots
+def _quadratic_minima(P, U, q):
+    """Every local minimum of |C(t) - q| on a quadratic B-spline, from closed forms per span.
+
+    On a span the curve is C(x) = A x^2 + B x + D (x in [0, 1], taken exactly through three points
+    of scipy's evaluation), so f(x) = (C - q).C' = 2|A|^2 x^3 + 3 A.B x^2 + (|B|^2 + 2 A.(D - q)) x
+    + B.(D - q) is a cubic whose real roots (numpy.roots) with f' > 0 are the stationary minima.
+    A C0 joint is a minimum when the left span's f at its end is negative and the right span's f at
+    its start positive; a domain end when f points into the domain.  Returns [(t, dist)]."""
+    from scipy.interpolate import BSpline
+
+    bs = BSpline(np.asarray(U, float), np.asarray(P, float), 2)
+    ks = [k for k in range(2, len(U) - 3) if U[k] < U[k + 1]]
+    mins, ends = [], []
+    for k in ks:
+        a, b = U[k], U[k + 1]
+        x = np.array([a, 0.5 * (a + b), b])
+        X = np.stack([bs(t) for t in x])
+        # the span's own polynomial through C(a), C(mid), C(b) (continuous at the ends)
+        P0, Pm, P2 = X[0], X[1], X[2]
+        P1 = 2.0 * Pm - 0.5 * (P0 + P2)
+        A, B, D = P0 - 2 * P1 + P2, 2 * (P1 - P0), P0
+        r = D - q
+        coef = [2 * (A @ A), 3 * (A @ B), B @ B + 2 * (A @ r), B @ r]
+        f = lambda s: np.polyval(coef, s)  # noqa: E731
+        fp = lambda s: 6 * (A @ A) * s * s + 6 * (A @ B) * s + B @ B + 2 * (A @ r)  # noqa: E731
+        for z in np.roots(coef):
+            if abs(z.imag) < 1e-9 and 0.0 < z.real < 1.0 and fp(z.real) > 0:
+                s = z.real
+                mins.append((a + s * (b - a), np.linalg.norm(A * s * s + B * s + r)))
+        ends.append((a, b, f(0.0), f(1.0), np.linalg.norm(r), np.linalg.norm(A + B + r)))
+    for (a0, b0, f00, f01, d00, d01), (a1, b1, f10, f11, d10, d11) in zip(ends[:-1], ends[1:]):
+        if f01 < 0.0 and f10 > 0.0:
+            mins.append((b0, d01))
+    if ends[0][2] >= 0.0:
+        mins.append((ends[0][0], ends[0][4]))
+    if ends[-1][3] <= 0.0:
+        mins.append((ends[-1][1], ends[-1][5]))
+    return mins
+
+
+def test_c0_quadratic_runner_from_cubic_roots():
+    """The corner family of the adversarial workload (C0 quadratics, queries next to the joints):
+    the oracle's distance and runner-up equal the best and the best distinct (|t - t*| > 1e-6) of all
+    closed-form local minima.  This includes minima inside a span a few 1e-6 from a C0 joint, where
+    the one-sided derivatives of the two spans differ."""
+    from scipy.interpolate import BSpline
+
+    curves, o = gen.curves_adversarial()
+    cids = np.asarray(o["corner_cid"])
+    q = np.empty((len(cids), 3))
+    for i, (c, t0, off) in enumerate(zip(cids, o["corner_t0"], o["corner_offset"])):
+        p, P, U = curves.curve(c)
+        q[i] = BSpline(np.asarray(U, float), np.asarray(P, float), p)(t0) + off
+    r = oracle.project(curves, cids.astype(np.int32), q)
+    checked_close = 0
+    for i, c in enumerate(cids):
+        p, P, U = curves.curve(c)
+        assert p == 2
+        mins = _quadratic_minima(P, U, q[i])
+        t_best, d_best = min(mins, key=lambda m: m[1])
+        others = [d for t, d in mins if abs(t - t_best) > 1e-6]
+        runner = min(others) if others else np.inf
+        diag = curves.bbox_diag()[c]
+        assert abs(r["dist"][i] - d_best) <= 1e-12 * diag, i
+        if np.isfinite(runner):
+            assert abs(r["runner"][i] - runner) <= 1e-11 * diag, (i, r["runner"][i], runner)
+            checked_close += runner - d_best <= 4e-6 * diag
+        else:
+            assert np.isinf(r["runner"][i])
+    assert checked_close >= 1  # at least one runner-up within the tie margin (next to a joint)
