@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 7
+#define MREP_ABI_VERSION 8
 
 /* status codes */
 #define MREP_OK 0
@@ -177,6 +177,42 @@ int32_t mrep_decompose_curves(int32_t n_curves, const int32_t* degree, const int
 int32_t mrep_decompose_curves_rational(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
                                        const double* cp_xyz, const double* weights, const int64_t* knot_off,
                                        const double* knots, double tol_rel, int32_t n_threads, mrep_plan** out);
+
+/* Decompose n_curves clamped polynomial B-spline curves ON THE DEVICE: the
+ * same pieces, breakpoints and tables as mrep_decompose_curves followed by
+ * mrep_upload, bit for bit (the host and the device run the same arithmetic,
+ * compiled without contraction).  Steps, each a set of kernels on `stream`:
+ * per curve the validation of mrep_decompose_curves and the box; per knot
+ * interval the exact Bezier form Q = B_p^{-1} M A P (Sec. 5.2.1, eqs.
+ * decomposition / decomfinal) and a prefix sum that numbers the non-empty
+ * spans; then level by level (Sec. 5.2.2, the subdivision figure) the G1 cubic
+ * with the L2-optimal (delta0, delta1) from the preloaded Gram matrices (eqs.
+ * gram, G1-condition, epsl) and its certified deviation bound for every piece
+ * of the level, prefix sums that compact the finished pieces and the pieces
+ * to split, and the split of each of those at its sample of largest deviation
+ * (eqs. submatrix, subLandR) into the next level; finally one small sort per
+ * span puts its pieces in parameter order.  mrep_upload builds the screen
+ * tables of the returned plan with kernels, device to device.
+ *   n_curves                     > 0
+ *   degree[n_curves]       HOST  1 .. MREP_SPAN_MAX_DEGREE (higher degrees and
+ *                                rational curves: mrep_decompose_curves*)
+ *   cp_off[n_curves+1]     HOST  CSR offsets into cp_xyz (points)
+ *   cp_xyz[3*cp_off[n]]    DEVICE control points, xyz interleaved, FP64
+ *   knot_off[n_curves+1]   HOST  CSR offsets into knots
+ *   knots[knot_off[n]]     DEVICE clamped knot vectors, FP64
+ *   tol_rel                as mrep_decompose_curves
+ *   stream                 HIP stream (NULL: the default stream)
+ *   out                    receives a plan holding device arrays; mrep_plan_info,
+ *                          mrep_plan_export (copies to the host), mrep_upload and
+ *                          mrep_plan_free work on it as on a host plan.
+ * The call allocates its device temporaries and the plan's arrays with
+ * hipMalloc (freed on return and by mrep_plan_free) and synchronises the
+ * stream between levels (each level's counts size the next).
+ * Errors: as mrep_decompose_curves (a curve's validation error names it), and
+ * MREP_E_HIP (an allocation or a launch failed), MREP_E_NO_DEVICE. */
+int32_t mrep_decompose_curves_device(int32_t n_curves, const int32_t* degree, const int64_t* cp_off,
+                                     const double* cp_xyz, const int64_t* knot_off, const double* knots,
+                                     double tol_rel, void* stream, mrep_plan** out);
 
 /* Summary of a plan.  Errors: MREP_E_INVALID_ARG. */
 int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info);

@@ -46,8 +46,12 @@ def build(verbose: bool = False) -> str:
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_clip.hip"), "-o", clip_o])
     spans_o = os.path.join(BUILD, "mrep_spans.o")
     _run(["hipcc", *HIP_FLAGS, "-I", INC, "-c", os.path.join(CSRC, "mrep_spans.hip"), "-o", spans_o])
+    # the device decomposition repeats the host's arithmetic bit for bit: no contraction
+    ddec_o = os.path.join(BUILD, "mrep_ddecomp.o")
+    _run(["hipcc", *HIP_FLAGS, "-ffp-contract=off", "-I", INC, "-c", os.path.join(CSRC, "mrep_ddecomp.hip"), "-o",
+          ddec_o])
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, nn_o, surf_o, clip_o, spans_o, host_o, "-o", tmp,
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_o, scr_o, nn_o, surf_o, clip_o, spans_o, ddec_o, host_o, "-o", tmp,
           "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:

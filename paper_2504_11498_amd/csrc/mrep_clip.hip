@@ -248,16 +248,29 @@ __device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_
                           E[0] + 0.6 * E[1] + 0.3 * E[2] + 0.1 * E[3],
                           E[0] + 0.8 * E[1] + 0.6 * E[2] + 0.4 * E[3] + 0.2 * E[4],
                           E[0] + E[1] + E[2] + E[3] + E[4] + E[5]};
+    V3<double> er, e1, e2;
+    C.eval(0.0, er, e1, e2);
+    const double k0 = end_kappa(er, e1, e2);
+    C.eval(1.0, er, e1, e2);
+    const double k1 = end_kappa(er, e1, e2);
     u_out = 0.0;
     d_out = C.dist2(0.0);
-    k_out = 1.0;
+    k_out = k0;
     w_out = 0.0;
     u2_out = 0.0;
     d2_out = INFINITY;
+    // an end is a local minimum of the piece only where the distance grows into
+    // the piece; only local minima become the second minimum
+    bool l_out = E[0] >= 0.0;
     {
         const double d1 = C.dist2(1.0);
-        if (d1 < d_out) { u2_out = 0.0; d2_out = d_out; d_out = d1; u_out = 1.0; }
-        else { u2_out = 1.0; d2_out = d1; }
+        const bool l1 = bf[5] <= 0.0;
+        if (d1 < d_out) {
+            if (l_out) { u2_out = 0.0; d2_out = d_out; }
+            d_out = d1; u_out = 1.0; l_out = l1; k_out = k1;
+        } else if (l1) {
+            u2_out = 1.0; d2_out = d1;
+        }
     }
     double ta = 0.0, ea = E[0];
     for (int k = 0; k <= nb; ++k) {
@@ -285,21 +298,39 @@ __device__ void clip_piece_min(const Cubic<double>& C, double& u_out, double& d_
             const double u = ta + h * 0.5 * (lo + hi);
             const double d = C.dist2(u);
             w_out = fmax(w_out, h * (hi - lo));
+            // two minima only with a barrier between them (as in piece_min)
+            const bool apart = fabs(u - u_out) > (double)kDistinctU &&
+                               C.dist2(0.5 * (u + u_out)) > fmax(d, d_out) * (1.0 + 1e-13);
             if (d < d_out) {
-                if (fabs(u - u_out) > (double)kDistinctU) { u2_out = u_out; d2_out = d_out; }
+                if (l_out && apart) { u2_out = u_out; d2_out = d_out; }
                 d_out = d;
                 u_out = u;
+                l_out = true;
                 V3<double> r, d1, d2;
                 C.eval(u, r, d1, d2);
                 const double sp = dot(d1, d1);
                 k_out = sp > 0.0 ? (sp + dot(r, d2)) / sp : 1.0;
-            } else if (d < d2_out && fabs(u - u_out) > (double)kDistinctU) {
+            } else if (d < d2_out && apart) {
                 u2_out = u;
                 d2_out = d;
             }
         }
         ta = tb;
         ea = eb;
+    }
+    // A minimum that the clipping left within its resolution of an end whose
+    // distance is no higher (up to rounding) is that end: where the distance
+    // keeps falling into the neighbouring piece, E at the end is a rounding
+    // level either way.  The candidate selection knows a joint by u = 0 or 1.
+    for (int e = 0; e < 2; ++e) {
+        const double ue = (double)e;
+        if (u_out != ue && fabs(u_out - ue) <= kClipTol) {
+            const double de = C.dist2(ue);
+            if (de <= d_out * (1.0 + 1e-12)) {
+                u_out = ue;
+                d_out = de;
+            }
+        }
     }
 }
 

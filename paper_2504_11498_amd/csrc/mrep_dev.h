@@ -137,13 +137,28 @@ int nn_score_surface_pairs(const mrep_nn* nn, const int32_t* q_off, int32_t n_su
 
 }  // namespace mrep
 
-// Handles of the C ABI.  A plan (host) and a geometry (non-owning device view
-// of the caller's buffer) hold either curves or surfaces.
+namespace mrep {
+// Result of the device decomposition (mrep_ddecomp.hip): device arrays owned by
+// its plan; the geometry tables are built from them by mrep_upload.
+struct DevPlan;
+void devplan_free(DevPlan* d);
+int devplan_upload(const DevPlan& d, char* buf, hipStream_t st);
+int devplan_export(const DevPlan& d, int64_t* seg_off, double* seg_t, double* seg_cp, int32_t* seg_span);
+const GeomLayout& devplan_layout(const DevPlan& d);
+int32_t devplan_max_degree(const DevPlan& d);
+double devplan_tol_rel(const DevPlan& d);
+}  // namespace mrep
+
+// Handles of the C ABI.  A plan (host tables, or device arrays for a device
+// decomposition) and a geometry (non-owning device view of the caller's
+// buffer) hold either curves or surfaces.
 enum { MREP_GEOM_CURVES = 0, MREP_GEOM_SURFACES = 1 };
 struct mrep_plan {
     int kind = MREP_GEOM_CURVES;
     mrep::Plan p;
     mrep::SurfPlan sp;
+    mrep::DevPlan* dev = nullptr;  // set by mrep_decompose_curves_device
+    ~mrep_plan() { mrep::devplan_free(dev); }
 };
 struct mrep_geom {
     int kind = MREP_GEOM_CURVES;

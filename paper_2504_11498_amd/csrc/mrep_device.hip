@@ -350,26 +350,18 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH
     const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
     Cand b1 = empty_cand(cv), b2 = b1;
     const int64_t p0 = so.pair_off[j];
-    for (int i = 0; i < n_list; ++i) {
-        const float4 r = pair_res[2 * (p0 + i)], r2 = pair_res[2 * (p0 + i) + 1];
-        const int32_t s = so.pair_seg[p0 + i];
-        top2(make_cand_q(G, cv, s, (double)r.x, (double)r.y, (double)r.z, (double)r.w, q), b1, b2);
-        if (r2.y < INFINITY) top2(make_cand_q(G, cv, s, (double)r2.x, (double)r2.y, 1.0, 0.0, q), b1, b2);
+    // each pair's minimum, then its second local minimum (kappa 1, no parameter
+    // error: only its distance and t enter the tie test), through one call site
+    for (int i = 0; i < 2 * n_list; ++i) {
+        const float4 r = pair_res[2 * p0 + i];
+        if (!(r.y < INFINITY)) continue;
+        const bool sec = (i & 1) != 0;
+        Cand x = make_cand_q(G, cv, so.pair_seg[p0 + (i >> 1)], (double)r.x, (double)r.y, sec ? 1.0 : (double)r.z,
+                             sec ? 0.0 : (double)r.w, q);
+        x.end |= sec ? kSecond : 0;
+        top2(x, b1, b2);
     }
     finish<T, kGen>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
-}
-
-// Lexicographic (d2, t, lane) minimum over the wave; every lane gets the winner lane.
-__device__ __forceinline__ int wave_argmin(double d2, double t)
-{
-    int lane = threadIdx.x & 63, bl = lane;
-    double bd = d2, bt = t;
-    for (int off = 32; off > 0; off >>= 1) {
-        double od = __shfl_xor(bd, off, 64), ot = __shfl_xor(bt, off, 64);
-        int ol = __shfl_xor(bl, off, 64);
-        if (od < bd || (od == bd && (ot < bt || (ot == bt && ol < bl)))) { bd = od; bt = ot; bl = ol; }
-    }
-    return bl;
 }
 
 __device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
@@ -381,6 +373,7 @@ __device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
     r.t_err = __shfl(c.t_err, src, 64);
     r.seg = __shfl(c.seg, src, 64);
     r.across = __shfl(c.across, src, 64);
+    r.end = __shfl(c.end, src, 64);
     return r;
 }
 
@@ -449,14 +442,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_FULLSC
             // lim, not ub: a runner-up within the tie margin is refined too
             if (lb <= lim) consider<T>(G, cv, s, q, b1, b2);
         }
-        const int w = wave_argmin(b1.d2, b1.t);
-        const Cand best = cand_from_lane(b1, w);
-        // runner-up: the winner lane's second, every other lane's first unless that
-        // one is a piece end the distance falls across (then its second)
-        const Cand other = (lane == w || b1.across) ? b2 : b1;
-        const int r = wave_argmin(other.d2, other.t);
-        const Cand runner = cand_from_lane(other, r);
-        if (lane == 0) finish<T, kGen>(G, cv, q, best, runner, flag_in, tie_rel, invert, qi, o);
+        // wave top-2 by the same rules as one lane's: a tree onto lane 0, in a fixed order
+        for (int off = 32; off > 0; off >>= 1) {
+            const Cand o1 = cand_from_lane(b1, lane + off), o2 = cand_from_lane(b2, lane + off);
+            if (lane + off < 64) {
+                top2(o1, b1, b2);
+                top2(o2, b1, b2);
+            }
+        }
+        if (lane == 0) finish<T, kGen>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
     }
 }
 
@@ -580,6 +574,17 @@ int32_t mrep_plan_info(const mrep_plan* plan, mrep_plan_info_t* info)
         info->tol_rel = S.tol_rel;
         return MREP_OK;
     }
+    if (plan->dev) {
+        const GeomLayout& L = devplan_layout(*plan->dev);
+        info->n_curves = L.n_curves;
+        info->n_spans = L.n_span;
+        info->n_segments = L.n_seg;
+        info->device_bytes = L.total;
+        info->max_degree = devplan_max_degree(*plan->dev);
+        info->reserved = 0;
+        info->tol_rel = devplan_tol_rel(*plan->dev);
+        return MREP_OK;
+    }
     info->n_curves = plan->p.n_curves;
     info->n_spans = plan->p.layout.n_span;
     info->n_segments = plan->p.layout.n_seg;
@@ -649,6 +654,7 @@ int32_t mrep_plan_export(const mrep_plan* plan, int64_t* seg_off, double* seg_t,
         set_error("mrep_plan_export: null plan or a surface plan");
         return MREP_E_INVALID_ARG;
     }
+    if (plan->dev) return devplan_export(*plan->dev, seg_off, seg_t, seg_cp, seg_span);
     const Plan& P = plan->p;
     if (seg_off) {
         for (int64_t c = 0; c < P.n_curves; ++c) seg_off[c] = P.curves[(size_t)c].seg_off;
@@ -672,6 +678,27 @@ int32_t mrep_upload(const mrep_plan* plan, void* dev_buf, int64_t bytes, void* s
     }
     *out = nullptr;
     if (plan->kind == MREP_GEOM_SURFACES) return upload_surfaces(plan->sp, dev_buf, bytes, stream, out);
+    if (plan->dev) {
+        const GeomLayout& L = devplan_layout(*plan->dev);
+        if (bytes < L.total) {
+            set_error("mrep_upload: buffer smaller than device_bytes");
+            return MREP_E_SMALL_BUFFER;
+        }
+        if (((uintptr_t)dev_buf & 255) != 0) {
+            set_error("mrep_upload: buffer not 256-byte aligned");
+            return MREP_E_INVALID_ARG;
+        }
+        int rc = check_device();
+        if (rc) return rc;
+        rc = devplan_upload(*plan->dev, (char*)dev_buf, (hipStream_t)stream);
+        if (rc) return rc;
+        mrep_geom* g = new mrep_geom();
+        g->g.L = L;
+        g->g.base = (char*)dev_buf;
+        HIP_OK(hipGetDevice(&g->g.device));
+        *out = g;
+        return MREP_OK;
+    }
     const Plan& P = plan->p;
     if (bytes < P.layout.total) {
         set_error("mrep_upload: buffer smaller than device_bytes");

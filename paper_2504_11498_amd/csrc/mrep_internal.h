@@ -188,6 +188,8 @@ void subdivision_matrix(int p, double z, double* S);
 void gram_matrix(int m, int n, double* G);
 uint16_t f32_to_bf16_rne(float x);
 
+// Byte offsets of a curve geometry with these counts (general = 0).
+void curve_layout(GeomLayout& L, int64_t n_curves, int64_t n_seg, int64_t n_span, int64_t n_coef, int64_t n_clu);
 void set_error(const std::string& msg);
 
 }  // namespace mrep

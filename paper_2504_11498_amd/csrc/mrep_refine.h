@@ -82,23 +82,43 @@ template <typename T>
 struct Newt {
     static constexpr int iters = 8;
     static constexpr T eps = (T)1e-6;
+    static constexpr T stat = (T)1e-5;  // |r.C'| <= stat |r||C'|: stationary to rounding
 };
 template <>
 struct Newt<double> {
     static constexpr int iters = 40;
     static constexpr double eps = 1e-15;
+    static constexpr double stat = 1e-12;
 };
+
+// kappa = f'/|C'|^2 at a bracket end where f = r.C' vanishes to rounding (a
+// stationary minimiser that lies on the end, e.g. on a piece joint); 1 at an
+// end the distance leaves with a slope (the end conditions the minimum)
+template <typename T>
+__device__ __forceinline__ T end_kappa(const V3<T>& r, const V3<T>& d1, const V3<T>& d2)
+{
+    const T sp = dot(d1, d1), f = dot(r, d1);
+    return (sp > (T)0 && fabs(f) <= Newt<T>::stat * sqrt(dot(r, r) * sp)) ? (sp + dot(r, d2)) / sp : (T)1;
+}
 
 // Minimum of |C(u) - q|^2 on [lo, hi] near the sample u0: safeguarded Newton on
 // f = r.C' when f changes sign on the bracket; otherwise the better bracket end.
+// loc (nullable) tells whether the result stands for a local minimum of the
+// piece: a bracket over which f changes sign holds one (the result may be a
+// bracket end where rounding made it lower than the stationary point), as does
+// a piece end (u = 0 or 1) where the distance grows into the piece; an
+// interior bracket end without a sign change of f does not.
 template <typename T>
-__device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_best, T& kappa)
+__device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, T& u_best, T& d_best, T& kappa,
+                                           bool* loc = nullptr)
 {
     V3<T> r, d1, d2;
     C.eval(lo, r, d1, d2);
     T flo = dot(r, d1), dlo = dot(r, r);
+    const T klo = end_kappa(r, d1, d2);
     C.eval(hi, r, d1, d2);
     T fhi = dot(r, d1), dhi = dot(r, r);
+    const T khi = end_kappa(r, d1, d2);
     T u = u0;
     kappa = (T)1;
     if (flo < (T)0 && fhi > (T)0) {
@@ -123,14 +143,17 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
         T d = dot(r, r);
         u_best = u;
         d_best = d;
-        if (dlo < d_best) { u_best = lo; d_best = dlo; kappa = (T)1; }
-        if (dhi < d_best) { u_best = hi; d_best = dhi; kappa = (T)1; }
+        if (dlo < d_best) { u_best = lo; d_best = dlo; kappa = klo; }
+        if (dhi < d_best) { u_best = hi; d_best = dhi; kappa = khi; }
+        if (loc) *loc = true;
         return;
     }
     u_best = dlo <= dhi ? lo : hi;
     d_best = dlo <= dhi ? dlo : dhi;
+    kappa = dlo <= dhi ? klo : khi;
     T d0 = C.dist2(u0);
-    if (d0 < d_best) { u_best = u0; d_best = d0; }
+    if (d0 < d_best) { u_best = u0; d_best = d0; kappa = (T)1; }
+    if (loc) *loc = (u_best == (T)0 && flo >= (T)0) || (u_best == (T)1 && fhi <= (T)0);
 }
 
 // Sample k of a piece's local parameter: k / (S-1), the last one exactly 1.
@@ -146,15 +169,23 @@ __device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
 // parameters of a piece closer than this are one minimum, not two
 constexpr float kDistinctU = 1e-4f;
 
-// Keep the best and the second best of the piece's local minima; a candidate
-// within kDistinctU of the best is the same minimum.
+// Keep the best and the second best of the piece's local minima.  Two points
+// are two minima only when they are kDistinctU apart with a barrier between
+// them (the distance at the midpoint above both, beyond rounding): solves that
+// stop at different points of one shallow minimum are one minimum.  Only a
+// local minimum of the piece (loc; l1 for the current best) can become the
+// second: a bracket end that the certification pass reached is a bound.
 template <typename T>
-__device__ __forceinline__ void keep2(T u, T d, T k, T& u1, T& d1, T& k1, T& u2, T& d2)
+__device__ __forceinline__ void keep2(const Cubic<T>& C, T u, T d, T k, bool loc, T& u1, T& d1, T& k1, bool& l1, T& u2,
+                                      T& d2)
 {
+    bool apart = fabs(u - u1) > (T)kDistinctU;
+    if (apart && d1 < (T)INFINITY)
+        apart = C.dist2((T)0.5 * (u + u1)) > fmax(d, d1) * ((T)1 + (T)(sizeof(T) == 4 ? 4e-6 : 1e-13));
     if (d < d1) {
-        if (fabs(u - u1) > (T)kDistinctU) { u2 = u1; d2 = d1; }
-        u1 = u; d1 = d; k1 = k;
-    } else if (d < d2 && fabs(u - u1) > (T)kDistinctU) {
+        if (l1 && apart) { u2 = u1; d2 = d1; }
+        u1 = u; d1 = d; k1 = k; l1 = loc;
+    } else if (loc && d < d2 && apart) {
         u2 = u; d2 = d;
     }
 }
@@ -201,13 +232,15 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2
     }
     u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
     u2_out = (T)0; d2_out = (T)INFINITY;
+    bool l1 = false;
     uint32_t covered = 0;  // bit k: interval (k, k+1) lies inside a refined bracket
     for (uint32_t bits = lm; bits; bits &= bits - 1) {
         const int k = __builtin_ctz(bits);
         const int a = k > 0 ? k - 1 : 0, b = k < kSamples - 1 ? k + 1 : kSamples - 1;
         T ub, db, kb;
         newton_min(C, sample_u<T>(a), sample_u<T>(b), sample_u<T>(k), ub, db, kb);
-        keep2(ub, db, kb, u_out, d_out, k_out, u2_out, d2_out);
+        // a local minimum of the samples: the bracket holds a local minimum of the piece
+        keep2(C, ub, db, kb, true, u_out, d_out, k_out, l1, u2_out, d2_out);
         covered |= ((1u << b) - 1u) & ~((1u << a) - 1u);
     }
     const T best = d_out * ((T)1 - (T)(sizeof(T) == 4 ? 8e-6 : 2e-14));
@@ -216,8 +249,9 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2
         const T ua = sample_u<T>(k), ub_ = sample_u<T>(k + 1);
         if (fmin(C.dist2(ua), C.dist2(ub_)) - gap < best) {
             T ub, db, kb;
-            newton_min(C, ua, ub_, (T)0.5 * (ua + ub_), ub, db, kb);
-            keep2(ub, db, kb, u_out, d_out, k_out, u2_out, d2_out);
+            bool loc;
+            newton_min(C, ua, ub_, (T)0.5 * (ua + ub_), ub, db, kb, &loc);
+            keep2(C, ub, db, kb, loc, u_out, d_out, k_out, l1, u2_out, d2_out);
         }
     }
 }
@@ -357,15 +391,18 @@ __device__ __forceinline__ void span_eval_cv(const DCurve& cv, const double* cf,
 // this small (the evaluation may be Bernstein or rational).
 template <bool kGen>
 __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32_t span, double t0, const double* q,
-                                       double& t_out, double& d_out, double& k_out)
+                                       double& t_out, double& d_out, double& k_out, double* sp_out = nullptr,
+                                       bool* conv_out = nullptr)
 {
     const int32_t sp0 = (int32_t)cv.span_off, sp1 = (int32_t)(cv.span_off + cv.n_span - 1);
     double v = (t0 - G.spant[2 * span]) / (G.spant[2 * span + 1] - G.spant[2 * span]);
     v = fmin(fmax(v, 0.0), 1.0);
     // best over all spans visited, and best of the current span
-    double best_v = v, best_d = INFINITY, best_k = 1.0;
+    double best_v = v, best_d = INFINITY, best_k = 1.0, best_sp = 0.0;
     int32_t best_span = span;
-    double cur_v = v, cur_d = INFINITY, cur_k = 1.0;
+    bool best_c = false;
+    double cur_v = v, cur_d = INFINITY, cur_k = 1.0, cur_sp = 0.0;
+    bool cur_c = false;
     int hop = 0, it = 0;
     for (int guard = 0; guard < 64; ++guard) {
         double r[3], d1[3], d2[3];
@@ -377,10 +414,15 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
         if (d <= cur_d) {
             cur_d = d;
             cur_v = v;
-            // conditioning of a stationary minimiser; a minimum held at an end or
-            // a corner without a stationary point is conditioned by the end: 1
-            const bool stationary = fabs(f) <= 1e-9 * sqrt(sp) * (sqrt(d) + cv.diag);
+            // conditioning of a stationary minimiser (inside the span, or where f
+            // vanishes); a minimum held at an end or a corner without a
+            // stationary point is conditioned by the end: 1.  Near a centre of
+            // curvature Newton converges only linearly, so an interior iterate
+            // counts as stationary without a residual test.
+            cur_c = fabs(f) <= 1e-9 * sqrt(sp) * (sqrt(d) + cv.diag);
+            const bool stationary = (v > 0.0 && v < 1.0) || cur_c;
             cur_k = (sp > 0.0 && stationary) ? fp / sp : 1.0;
+            cur_sp = sp;
         }
         bool done_span = !(fp > 0.0) || it >= 12;
         if (!done_span) {
@@ -394,7 +436,7 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
         }
         // this span is done: keep it if it went lower (always for the first span)
         if (hop > 0 && !(cur_d < best_d)) break;
-        best_v = cur_v; best_d = cur_d; best_k = cur_k; best_span = span;
+        best_v = cur_v; best_d = cur_d; best_k = cur_k; best_span = span; best_sp = cur_sp; best_c = cur_c;
         if (hop >= 3) break;
         if (best_v == 0.0 && span > sp0) { --span; v = 1.0; }
         else if (best_v == 1.0 && span < sp1) { ++span; v = 0.0; }
@@ -407,15 +449,20 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
     k_out = best_k;
     t_out = (best_v == 1.0) ? tb : ta + best_v * (tb - ta);
     d_out = sqrt(best_d);
+    if (sp_out) *sp_out = best_sp / ((tb - ta) * (tb - ta));  // |C'|^2 in the curve's parameter
+    if (conv_out) *conv_out = best_c;
 }
 
 struct Cand {
     double t, d2;   // FP64 global parameter, squared distance (refine precision)
-    double kappa;
-    double t_err;   // bound on the parameter error left by the refine precision
+    float kappa;    // conditioning at the candidate (only compared with 1e-2)
+    float t_err;    // bound on the parameter error left by the refine precision (compared with 1e-8)
     int32_t seg;
     int32_t across; // a piece end at an interior joint where the distance falls into the neighbour
+    int32_t end;    // bits 0-1: 1 at the piece's start (u = 0), 2 at its end (u = 1), else 0;
+                    // bit 2 (kSecond): the piece's second local minimum, not its minimum
 };
+constexpr int32_t kSecond = 4;
 
 template <typename T>
 struct Eps;
@@ -451,18 +498,38 @@ __device__ __forceinline__ void cand_select(bool c, const Cand& a, Cand& dst)
     dst.t_err = c ? a.t_err : dst.t_err;
     dst.seg = c ? a.seg : dst.seg;
     dst.across = c ? a.across : dst.across;
+    dst.end = c ? a.end : dst.end;
+}
+
+// x is the joint it shares with candidate y's piece, and y is that piece's
+// minimum (false when y is empty or a second minimum)
+__device__ __forceinline__ bool on_piece(const Cand& x, const Cand& y)
+{
+    const int32_t e = x.end & 3;
+    return y.d2 < INFINITY && !(y.end & kSecond) && ((e == 1 && x.seg == y.seg + 1) || (e == 2 && x.seg == y.seg - 1));
 }
 
 // Keep the two best candidates (squared distance, then parameter); field-wise
-// selects keep the candidates in registers.  A candidate whose distance falls
-// into the neighbouring piece (across) is no local minimum of the curve: it
-// may hold the first place until a lower candidate comes, but it never becomes
-// the runner-up of the tie test, where it would stand in for the real one.
+// selects keep the candidates in registers.  A candidate at the joint it shares
+// with the piece whose minimum is the best is no lower than that minimum and is
+// no other local minimum of the curve: it is dropped, and when the best itself
+// sits on the piece whose minimum the new candidate is, the new one replaces it
+// without becoming the runner-up (a piece's second local minimum has no such
+// bound, and takes its place by distance alone).  Without this, the two pieces' copies of one minimum (or a
+// joint next to it) would hold both places and push a genuine second minimum
+// out of the tie test.  A candidate whose distance falls into the neighbouring
+// piece (across) is no local minimum of the curve either: it may hold the first
+// place until a lower candidate comes, but it never becomes the runner-up.
 __device__ __forceinline__ void top2(const Cand& x, Cand& b1, Cand& b2)
 {
-    const bool first = x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t);
-    const bool demote = first && !b1.across;
-    const bool second = !first && !x.across && x.d2 < b2.d2;
+    const bool live = x.d2 < INFINITY && !on_piece(x, b1);
+    const bool repl = live && on_piece(b1, x);
+    const bool first = live && (repl || x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t));
+    const bool demote = first && !repl && !b1.across;
+    const bool second = live && !first && !x.across && !on_piece(x, b2) &&
+                        (x.d2 < b2.d2 || (x.d2 == b2.d2 && x.t < b2.t));
+    // a runner-up on the new best's piece goes too
+    if (repl && on_piece(b2, x)) b2.d2 = INFINITY;
     cand_select(demote, b1, b2);
     cand_select(second, x, b2);
     cand_select(first, x, b1);
@@ -498,10 +565,19 @@ __device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u,
     Cand x;
     x.t = (u == 1.0) ? tb : ta + u * (tb - ta);
     x.d2 = d2;
-    x.kappa = kappa;
-    x.t_err = t_err;
+    x.kappa = (float)kappa;
+    x.t_err = (float)t_err;
     x.seg = (int32_t)s;
     x.across = 0;
+    x.end = u == 0.0 ? 1 : (u == 1.0 ? 2 : 0);
+    return x;
+}
+
+// a piece's second local minimum as a candidate (kappa 1, no parameter error:
+// only its distance and t enter the tie test)
+__device__ __forceinline__ Cand second_cand(Cand x)
+{
+    x.end |= kSecond;
     return x;
 }
 
@@ -525,7 +601,7 @@ __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const do
     top2(make_cand_q(G, cv, s, (double)u, (double)d, (double)k, param_error(C, u, k, ta, tb), q), b1, b2);
     // a second minimum of the same piece: a runner-up candidate (its parameter
     // error does not matter: only its distance and t enter the tie test)
-    if (d2 < (T)INFINITY) top2(make_cand_q(G, cv, s, (double)u2, (double)d2, 1.0, 0.0, q), b1, b2);
+    if (d2 < (T)INFINITY) top2(second_cand(make_cand_q(G, cv, s, (double)u2, (double)d2, 1.0, 0.0, q)), b1, b2);
 }
 
 // Minimum sampled squared distance of a piece (the full-scan prune).
@@ -557,21 +633,43 @@ __device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const
     int32_t seg = b1.seg;
     if (approx || tie || illc || coarse) {
         flags |= MREP_F_POLISHED;
-        // the best, then (near tie) the runner-up, through one polish site
+        // the best, then (near tie) the runner-up, then (an ill-conditioned
+        // best) two probes of its valley, through one polish site
         dist = INFINITY;
         t = b1.t;
-        for (int k = 0; k < (tie ? 2 : 1); ++k) {
-            const int32_t ks = k ? b2.seg : b1.seg;
-            double tt, dd, kk;
-            polish<kGen>(G, cv, G.segspan[ks], k ? b2.t : b1.t, q, tt, dd, kk);
+        int nk = tie ? 2 : 1;
+        bool conv = false;
+        double h = 0.0;
+        for (int k = 0; k < nk; ++k) {
+            const bool probe = k >= (tie ? 2 : 1);
+            const int32_t ks = probe ? seg : (k ? b2.seg : b1.seg);
+            int32_t span = G.segspan[ks];
+            double t0 = k == 0 ? b1.t : b2.t;
+            if (probe) {
+                const double ta = G.spant[2 * span], tb = G.spant[2 * span + 1];
+                t0 = fmin(fmax(t + ((k & 1) ? -h : h), ta), tb);
+            }
+            double tt, dd, kk, sp;
+            bool cv_ok;
+            polish<kGen>(G, cv, span, t0, q, tt, dd, kk, &sp, &cv_ok);
             if (k == 0) {
-                t = tt; dist = dd; kap = kk;
+                t = tt; dist = dd; kap = kk; conv = cv_ok;
+                // An ill-conditioned minimum lies in a flat valley that the refine
+                // precision cannot resolve into one or two minima: probe it in FP64
+                // from both sides, h = the parameter offset at which the distance
+                // rises by the tie margin (f = d^2/2 grows by d m, f'' = kappa |C'|^2).
+                if (kk < 1e-2 && kk > 0.0 && sp > 0.0 && conv) {
+                    h = sqrt(2.0 * dd * tie_rel * cv.diag / (kk * sp));
+                    nk += 2;
+                }
                 continue;
             }
             // both polished points are local minima of the exact curve (the polish
             // follows the distance across span joints): a second one within the
-            // margin and apart in t is a near tie, whichever of the two wins
-            if (fabs(dd - dist) <= tie_rel * cv.diag && fabs(tt - t) > 1e-6) flags |= MREP_F_NEAR_TIE;
+            // margin and apart in t is a near tie, whichever of the two wins (a
+            // probe counts only where its Newton converged)
+            if (fabs(dd - dist) <= tie_rel * cv.diag && fabs(tt - t) > 1e-6 && (!probe || cv_ok))
+                flags |= MREP_F_NEAR_TIE;
             if (dd < dist || (dd == dist && tt < t)) { t = tt; dist = dd; kap = kk; seg = ks; }
         }
     } else {
@@ -605,7 +703,7 @@ __device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const
 __device__ __forceinline__ Cand empty_cand(const DCurve& cv)
 {
     Cand b;
-    b.d2 = INFINITY; b.t = 0.0; b.seg = (int32_t)cv.seg_off; b.kappa = 1.0; b.t_err = 0.0; b.across = 0;
+    b.d2 = INFINITY; b.t = 0.0; b.seg = (int32_t)cv.seg_off; b.kappa = 1.f; b.t_err = 0.f; b.across = 0; b.end = 0;
     return b;
 }
 

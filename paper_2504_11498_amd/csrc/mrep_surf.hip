@@ -552,17 +552,26 @@ __device__ __forceinline__ T rel_curv(T h11, T h12, T h22, T g11, T g12, T g22)
 struct PatchMin {
     float s, t, f, kappa;
     float s2, t2, f2;
+    int loc;  // the best is a local minimum of the patch (not an edge point the distance leaves inward)
 };
 // patch parameters closer than this (|ds| + |dt|) are one minimum, not two
 constexpr float kDistinctST = 1e-4f;
 
-__device__ __forceinline__ void pm_take(PatchMin& best, float s, float t, float f, float k)
+// Only a local minimum of the patch (loc) can become the second: the minimum
+// of an edge where the distance falls into the patch is a bound, not a minimum.
+// Two points are two minima only with a barrier between them (the distance at
+// their midpoint above both): FP32 Newton solves that stop at different points
+// of one shallow minimum are one minimum.
+__device__ __forceinline__ void pm_take(const Bicubic& B, PatchMin& best, float s, float t, float f, float k,
+                                        bool loc = true)
 {
-    const bool apart = fabsf(s - best.s) + fabsf(t - best.t) > kDistinctST;
+    bool apart = fabsf(s - best.s) + fabsf(t - best.t) > kDistinctST;
+    if (apart && best.f < INFINITY)
+        apart = bc_f(B, 0.5f * (s + best.s), 0.5f * (t + best.t)) > fmaxf(f, best.f) * (1.f + 4e-6f);
     if (f < best.f) {
-        if (apart) { best.s2 = best.s; best.t2 = best.t; best.f2 = best.f; }
-        best.s = s; best.t = t; best.f = f; best.kappa = k;
-    } else if (f < best.f2 && apart) {
+        if (apart && best.loc) { best.s2 = best.s; best.t2 = best.t; best.f2 = best.f; }
+        best.s = s; best.t = t; best.f = f; best.kappa = k; best.loc = loc;
+    } else if (loc && f < best.f2 && apart) {
         best.s2 = s; best.t2 = t; best.f2 = f;
     }
 }
@@ -621,7 +630,7 @@ __device__ void bc_newton(const Bicubic& B, float s, float t, float lo_s, float 
         if (step <= 1e-7f) break;
     }
     const bool interior = s > 0.f && s < 1.f && t > 0.f && t < 1.f;
-    pm_take(best, s, t, e.f, interior ? rel_curv(e.h11, e.h12, e.h22, e.g11, e.g12, e.g22) : 1.f);
+    pm_take(B, best, s, t, e.f, interior ? rel_curv(e.h11, e.h12, e.h22, e.g11, e.g12, e.g22) : 1.f);
 }
 
 // one edge of the patch as a cubic curve relative to the query
@@ -697,7 +706,7 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
                 cells |= (uint64_t)(mn - gap < cap) << (i * kC + j);
             }
     }
-    PatchMin best{0.f, 0.f, cap, 1.f, 0.f, 0.f, cap};
+    PatchMin best{0.f, 0.f, cap, 1.f, 0.f, 0.f, cap, 0};
     // Phase 2: Newton from each local minimum; the four cells around such a
     // sample count as covered
     uint64_t covered = 0;
@@ -718,7 +727,12 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
         piece_min(E, u, d, k);
         const float s = w == 0 ? 0.f : (w == 1 ? 1.f : u);
         const float t = w == 2 ? 0.f : (w == 3 ? 1.f : u);
-        pm_take(best, s, t, d, 1.f);
+        // a local minimum of the patch only where the distance does not fall
+        // into the patch across this edge (up to rounding)
+        const BcEval ev = bc_eval(B, s, t);
+        const float g = w < 2 ? ev.gs : ev.gt, tol = 1e-5f * sqrtf(ev.f * (w < 2 ? ev.g11 : ev.g22));
+        const bool loc = (w == 0 || w == 2) ? g >= -tol : g <= tol;
+        pm_take(B, best, s, t, d, 1.f, loc);
     }
     // Phase 4: a Newton solve in every uncovered cell whose second-order bound
     // min(corner f) - (M_ss + M_tt) h^2 / 8 is still below the best (corners
@@ -731,7 +745,7 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
         if (mn - gap < best.f * (1.f - 8e-6f))
             bc_newton(B, (i + 0.5f) * h, (j + 0.5f) * h, i * h, (i + 1) * h, j * h, (j + 1) * h, best);
     }
-    if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f, 0.f, 0.f, INFINITY};
+    if (!(best.f < cap)) best = PatchMin{0.f, 0.f, INFINITY, 1.f, 0.f, 0.f, INFINITY, 0};
     if (!(best.f2 < cap)) best.f2 = INFINITY;
     return best;
 }
@@ -989,6 +1003,8 @@ __global__ __launch_bounds__(256) void k_sseed(DevSurf D, const int32_t* __restr
 struct SCand {
     double u, v, d2, kappa;
     int64_t patch;
+    int32_t edge;  // bit 0: on the boundary of its patch's rectangle; bit 1: the patch's second
+                   // local minimum, not its minimum
 };
 
 // lexicographic (d2, u, v); bitwise operators keep it free of branches
@@ -997,22 +1013,44 @@ __device__ __forceinline__ bool s_better(const SCand& a, const SCand& b)
     return (a.d2 < b.d2) | ((a.d2 == b.d2) & ((a.u < b.u) | ((a.u == b.u) & (a.v < b.v))));
 }
 
-// (b1, b2) <- the two best of (b1, b2, x), field by field so that the
-// candidates stay in registers
-__device__ __forceinline__ void s_top2(const SCand& x, SCand& b1, SCand& b2)
+// x sits on the boundary of the closed rectangle of another patch whose
+// minimum is y (false when y is empty or a second minimum)
+__device__ __forceinline__ bool s_on(const DevSurf& D, const SCand& x, const SCand& y)
 {
-    const bool first = s_better(x, b1);
-    const bool second = !first && s_better(x, b2);
-    b2.u = first ? b1.u : (second ? x.u : b2.u);
-    b2.v = first ? b1.v : (second ? x.v : b2.v);
-    b2.d2 = first ? b1.d2 : (second ? x.d2 : b2.d2);
-    b2.kappa = first ? b1.kappa : (second ? x.kappa : b2.kappa);
-    b2.patch = first ? b1.patch : (second ? x.patch : b2.patch);
-    b1.u = first ? x.u : b1.u;
-    b1.v = first ? x.v : b1.v;
-    b1.d2 = first ? x.d2 : b1.d2;
-    b1.kappa = first ? x.kappa : b1.kappa;
-    b1.patch = first ? x.patch : b1.patch;
+    if (!(x.edge & 1) || (y.edge & 2) || !(y.d2 < INFINITY) || x.patch == y.patch) return false;
+    const double* r = D.uv + 4 * y.patch;
+    const double eps = 1e-12 * (fabs(r[0]) + fabs(r[1]) + fabs(r[2]) + fabs(r[3]) + 1e-300);
+    return x.u >= r[0] - eps && x.u <= r[1] + eps && x.v >= r[2] - eps && x.v <= r[3] + eps;
+}
+
+__device__ __forceinline__ void s_select(bool c, const SCand& a, SCand& dst)
+{
+    dst.u = c ? a.u : dst.u;
+    dst.v = c ? a.v : dst.v;
+    dst.d2 = c ? a.d2 : dst.d2;
+    dst.kappa = c ? a.kappa : dst.kappa;
+    dst.patch = c ? a.patch : dst.patch;
+    dst.edge = c ? a.edge : dst.edge;
+}
+
+// (b1, b2) <- the two best of (b1, b2, x), field by field so that the
+// candidates stay in registers.  A candidate on the boundary of the patch whose
+// minimum is the best is no lower than that minimum and no other local minimum
+// of the surface (a genuine one there is that patch's second minimum): it is
+// dropped, and when the best lies on the patch whose minimum the new candidate
+// is, the new one replaces it without becoming the runner-up.  Otherwise the
+// copies of one minimum held by the patches around it would fill both places
+// and push a genuine second minimum out of the tie test.
+__device__ __forceinline__ void s_top2(const DevSurf& D, const SCand& x, SCand& b1, SCand& b2)
+{
+    const bool live = x.d2 < INFINITY && !s_on(D, x, b1);
+    const bool repl = live && s_on(D, b1, x);
+    const bool first = live && (repl || s_better(x, b1));
+    const bool second = live && !first && !s_on(D, x, b2) && s_better(x, b2);
+    if (repl && s_on(D, b2, x)) b2.d2 = INFINITY;
+    s_select(first && !repl, b1, b2);
+    s_select(second, x, b2);
+    s_select(first, x, b1);
 }
 
 __device__ __forceinline__ SCand s_empty()
@@ -1022,6 +1060,7 @@ __device__ __forceinline__ SCand s_empty()
     c.d2 = INFINITY;
     c.kappa = 1.0;
     c.patch = -1;
+    c.edge = 0;
     return c;
 }
 
@@ -1034,6 +1073,7 @@ __device__ __forceinline__ SCand s_make(const DevSurf& D, int64_t k, float s, fl
     c.d2 = (double)f;
     c.kappa = (double)kap;
     c.patch = k;
+    c.edge = s == 0.f || s == 1.f || t == 0.f || t == 1.f;
     return c;
 }
 
@@ -1282,8 +1322,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_SFINIS
     const int64_t p0 = so.pair_off[j];
     for (int i = 0; i < n_list; ++i) {
         const float4 r = res[2 * (p0 + i)], r2 = res[2 * (p0 + i) + 1];
-        if (r.z < INFINITY) s_top2(s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
-        if (r2.z < INFINITY) s_top2(s_make(D, so.pair_seg[p0 + i], r2.x, r2.y, r2.z, r2.w), b1, b2);
+        if (r.z < INFINITY) s_top2(D, s_make(D, so.pair_seg[p0 + i], r.x, r.y, r.z, r.w), b1, b2);
+        if (r2.z < INFINITY) {
+            SCand c2 = s_make(D, so.pair_seg[p0 + i], r2.x, r2.y, r2.z, r2.w);
+            c2.edge |= 2;  // the patch's second local minimum
+            s_top2(D, c2, b1, b2);
+        }
     }
     if (!(b1.d2 < INFINITY)) {
         // no pair reached below its cap (FP32 rounding at the threshold): full scan
@@ -1393,8 +1437,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SFULL_
             const float Mss = 2.f * (B.Ls * B.Ls + B.far * B.Lss), Mtt = 2.f * (B.Lt * B.Lt + B.far * B.Ltt);
             if (mn * (1.f - 4e-6f) - (Mss + Mtt) * (1.f / 72.f) * 1.0001f > thr2) return;
             const PatchMin m = patch_min(B, thr2 * (1.f + 1e-5f));
-            if (m.f < INFINITY) s_top2(s_make(D, k, m.s, m.t, m.f, m.kappa), b1, b2);
-            if (m.f2 < INFINITY) s_top2(s_make(D, k, m.s2, m.t2, m.f2, 1.f), b1, b2);
+            if (m.f < INFINITY) s_top2(D, s_make(D, k, m.s, m.t, m.f, m.kappa), b1, b2);
+            if (m.f2 < INFINITY) {
+                SCand c2 = s_make(D, k, m.s2, m.t2, m.f2, 1.f);
+                c2.edge |= 2;
+                s_top2(D, c2, b1, b2);
+            }
         });
         // wave top-2
         for (int off = 32; off > 0; off >>= 1) {
@@ -1403,8 +1451,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_SFULL_
             o1.kappa = __shfl_xor(b1.kappa, off, 64); o1.patch = __shfl_xor(b1.patch, off, 64);
             o2.u = __shfl_xor(b2.u, off, 64); o2.v = __shfl_xor(b2.v, off, 64); o2.d2 = __shfl_xor(b2.d2, off, 64);
             o2.kappa = __shfl_xor(b2.kappa, off, 64); o2.patch = __shfl_xor(b2.patch, off, 64);
-            s_top2(o1, b1, b2);
-            s_top2(o2, b1, b2);
+            o1.edge = __shfl_xor(b1.edge, off, 64); o2.edge = __shfl_xor(b2.edge, off, 64);
+            s_top2(D, o1, b1, b2);
+            s_top2(D, o2, b1, b2);
         }
         if (lane == 0) s_finish(D, sf, x, b1, b2, (uint32_t)MREP_F_FULLSCAN | extra, tie_rel, invert, qi, o);
     }

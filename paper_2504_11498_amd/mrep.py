@@ -65,6 +65,8 @@ def _sig(name, res, *args):
 _decompose = _sig("mrep_decompose_curves", _i32, _i32, _pi32, _pi64, _pd, _pi64, _pd, _dbl, _i32, C.POINTER(_vp))
 _decompose_rational = _sig("mrep_decompose_curves_rational", _i32, _i32, _pi32, _pi64, _pd, _pd, _pi64, _pd, _dbl,
                           _i32, C.POINTER(_vp))
+_decompose_device = _sig("mrep_decompose_curves_device", _i32, _i32, _pi32, _pi64, _vp, _pi64, _vp, _dbl, _vp,
+                         C.POINTER(_vp))
 _plan_info = _sig("mrep_plan_info", _i32, _vp, C.POINTER(PlanInfo))
 _plan_export = _sig("mrep_plan_export", _i32, _vp, _pi64, _pd, _pd, _pi32)
 _plan_free = _sig("mrep_plan_free", None, _vp)
@@ -123,7 +125,7 @@ _last_error = _sig("mrep_last_error", C.c_char_p)
 _abi = _sig("mrep_abi_version", _i32)
 
 # every symbol the header declares (checked by the CPU test-suite)
-EXPORTS = ["mrep_decompose_curves", "mrep_plan_info", "mrep_plan_export", "mrep_plan_free", "mrep_upload",
+EXPORTS = ["mrep_decompose_curves", "mrep_decompose_curves_device", "mrep_plan_info", "mrep_plan_export", "mrep_plan_free", "mrep_upload",
            "mrep_geom_release", "mrep_opts_default", "mrep_workspace_bytes", "mrep_project_curves",
            "mrep_invert_curves", "mrep_eval_curves", "mrep_bernstein_matrix", "mrep_subdivision_matrix",
            "mrep_gram_matrix", "mrep_last_stage_times", "mrep_last_error", "mrep_abi_version",
@@ -218,12 +220,14 @@ class Plan:
                               _p(patch_span, C.c_int32)), "mrep_plan_export_surfaces")
         return {"patch_off": patch_off, "patch_uv": patch_uv, "patch_cp": patch_cp, "patch_span": patch_span}
 
-    def upload(self, device=None):
-        """Copy the tables to a new device buffer (a torch tensor) and return a Geometry."""
+    def upload(self, device=None, zero: bool = False):
+        """Copy the tables to a new device buffer (a torch tensor) and return a Geometry.  zero: clear the buffer
+        first, so that the alignment gaps between tables compare equal too."""
         import torch
 
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        buf = torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=dev)
+        alloc = torch.zeros if zero else torch.empty
+        buf = alloc(max(self.device_bytes, 256), dtype=torch.uint8, device=dev)
         stream = torch.cuda.current_stream(dev).cuda_stream
         g = _vp()
         _check(_upload(self._h, _vp(buf.data_ptr()), buf.numel(), _vp(stream), C.byref(g)), "mrep_upload")
@@ -261,6 +265,26 @@ def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0, weights=
         _check(_decompose_rational(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _p(cp, C.c_double),
                                    _p(w, C.c_double), _p(k_off, C.c_int64), _p(kn, C.c_double), float(tol_rel),
                                    int(n_threads), C.byref(h)), "mrep_decompose_curves_rational")
+    return Plan(h.value)
+
+
+def decompose_curves_device(curves, tol_rel: float = 1e-6, device=None) -> Plan:
+    """mrep_decompose_curves_device: the decomposition run by kernels on the GPU (degrees 1..15, polynomial).
+    The control points and knots are copied to the device first (torch tensors held until the call returns);
+    the plan holds device arrays and uploads, exports and frees like a host plan."""
+    import torch
+
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    deg = _host(curves.degree, np.int32)
+    cp_off = _host(curves.cp_off, np.int64)
+    k_off = _host(curves.knot_off, np.int64)
+    cp = torch.as_tensor(_host(curves.cp, np.float64)).to(dev)
+    kn = torch.as_tensor(_host(curves.knots, np.float64)).to(dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    h = _vp()
+    _check(_decompose_device(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _vp(cp.data_ptr()),
+                             _p(k_off, C.c_int64), _vp(kn.data_ptr()), float(tol_rel), _vp(stream), C.byref(h)),
+           "mrep_decompose_curves_device")
     return Plan(h.value)
 
 
