@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-curves workload block")
     ap.add_argument("--no-single", action="store_true", help="skip the single-cubic latency block")
     ap.add_argument("--no-spans", action="store_true", help="skip the device span decomposition block")
+    ap.add_argument("--no-host-decompose", action="store_true",
+                    help="lattice: skip the host decomposition that the device decomposition is timed and compared "
+                         "against (profiling runs)")
     ap.add_argument("--no-clip", action="store_true",
                     help="skip the batched curves with the paper's refinement path (MREP_OPT_CLIP)")
     ap.add_argument("--no-extras", action="store_true",
@@ -149,6 +152,55 @@ def _say(tag, msg):
     print(f"[{tag} {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def device_decomposition(args, dev, curves):
+    """Decompose the batch on the device (Sec. 5.2.1-5.2.2 by kernels) and, unless --no-host-decompose, on the
+    host too: the host time, the device time (decomposition, then the table build of mrep_upload; inputs already
+    resident), and whether the two geometry buffers are byte-equal.  Returns the device geometry."""
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    out = {}
+    geom_h = None
+    if not args.no_host_decompose:
+        t0 = time.perf_counter()
+        plan_h = mrep.decompose_curves(curves, 1e-6)
+        out["host_s"] = time.perf_counter() - t0
+        _say("decompose", f"host: {plan_h.n_segments} pieces in {out['host_s']:.1f} s; uploading")
+        t0 = time.perf_counter()
+        geom_h = plan_h.upload(dev, zero=True)
+        torch.cuda.synchronize()
+        out["host_upload_s"] = time.perf_counter() - t0  # PCIe copy of the host tables
+        del plan_h
+    cp = torch.from_numpy(np.ascontiguousarray(curves.cp, dtype=np.float64)).to(dev)
+    kn = torch.from_numpy(np.ascontiguousarray(curves.knots, dtype=np.float64)).to(dev)
+    mrep.decompose_curves_device(curves, 1e-6, dev, cp_dev=cp, knots_dev=kn).close()  # first launch of each kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = mrep.decompose_curves_device(curves, 1e-6, dev, cp_dev=cp, knots_dev=kn)
+    torch.cuda.synchronize()
+    out["device_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    geom = plan.upload(dev, zero=True)
+    torch.cuda.synchronize()
+    out["device_tables_s"] = time.perf_counter() - t0
+    out["pieces"] = int(plan.n_segments)
+    out["spans"] = int(plan.info.n_spans)
+    out["geometry_bytes"] = int(plan.device_bytes)
+    if geom_h is not None:
+        out["device_equals_host"] = bool(geom_h.buf.numel() == geom.buf.numel() and torch.equal(geom_h.buf, geom.buf))
+        out["speedup_vs_host"] = out["host_s"] / (out["device_s"] + out["device_tables_s"])
+        del geom_h
+    _say("decompose", f"device: {plan.n_segments} pieces in {out['device_s']:.3f} s + tables "
+                      f"{out['device_tables_s']:.3f} s; equal to host: {out.get('device_equals_host')}")
+    n_seg = np.diff(plan.seg_off())
+    n_pieces = int(plan.n_segments)
+    plan.close()
+    torch.cuda.empty_cache()
+    out.update(geom=geom, n_seg=n_seg, n_pieces=n_pieces)
+    return out
+
+
 def lattice_headline(args, dev):
     """The headline: lattice struts at full size -- 65,536 random-walk B-splines (degree U{3..9}, 64..1024 control
     points, steps N(0, 0.01^2)), 16,777,216 queries in proportion to each curve's cubic pieces, offset by
@@ -162,15 +214,8 @@ def lattice_headline(args, dev):
     n_curves = int(args.lattice_curves)
     _say("lattice", f"generating {n_curves} struts")
     curves = gen.curves_lattice_geometry(5, n_curves=n_curves)
-    t0 = time.perf_counter()
-    plan = mrep.decompose_curves(curves, 1e-6)
-    decompose_s = time.perf_counter() - t0
-    n_seg = np.diff(plan.seg_off())
-    _say("lattice", f"{plan.n_segments} pieces in {decompose_s:.1f} s (host); uploading")
-    t0 = time.perf_counter()
-    geom = plan.upload(dev)
-    torch.cuda.synchronize()
-    upload_s = time.perf_counter() - t0
+    dec = device_decomposition(args, dev, curves)
+    geom, n_seg, n_pieces = dec.pop("geom"), dec.pop("n_seg"), dec.pop("n_pieces")
     qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
     cid = torch.from_numpy(qs.curve_id).to(dev)
     q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
@@ -260,12 +305,11 @@ def lattice_headline(args, dev):
                         f"strategy: {strategy}; FP32 refine, FP64 polish)",
             "n_curves": n_curves,
             "queries": int(n),
-            "cubic_pieces": int(plan.n_segments),
+            "cubic_pieces": n_pieces,
             "tol_rel": 1e-6,
             "strategy": strategy,
             "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
-            "decompose_s_host": decompose_s,
-            "upload_s": upload_s,
+            "decomposition": dec,
             "stage_ms": stage_ms,
             "candidate_pairs": pairs,
             "fullscan_queries": ovf,

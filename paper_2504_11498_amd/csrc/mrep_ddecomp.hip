@@ -343,6 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_dd_spans(int32_t n_curves, int64_t n
 
 // 4. one level: the cubic of every piece, and leaf (deviation bound within the
 //    curve's tolerance, or an exact cubic) or split at the worst sample.
+template <int MP>
 __global__ __launch_bounds__(kBlock) void k_dd_level(int64_t n_items, const int32_t* __restrict__ deg,
                                                      const int32_t* __restrict__ span_curve,
                                                      const double* __restrict__ tol_abs,
@@ -365,9 +366,20 @@ __global__ __launch_bounds__(kBlock) void k_dd_level(int64_t n_items, const int3
     if (p <= 3) {
         dm::elevate_to_cubic(p, Q, R);
     } else {
-        dm::g1_reduce(p, tab[p], Q, R);
         int imax = 64;
-        const double e = dm::deviation_bound(p, tab[p], Q, R, &imax);
+        double e;
+        // The pieces of one curve share its degree, so a wave is nearly always of one
+        // degree: then the degree is wave-uniform and every table entry the reduction
+        // and the deviation bound read is one scalar load for the whole wave.
+        const int p0 = __builtin_amdgcn_readfirstlane(p);
+        if (__all(p == p0)) {
+            const dm::DegreeTables& T0 = tab[p0];
+            dm::g1_reduce(p0, T0, Q, R);
+            e = dm::deviation_bound(p0, T0, Q, R, &imax);
+        } else {
+            dm::g1_reduce(p, tab[p], Q, R);
+            e = dm::deviation_bound(p, tab[p], Q, R, &imax);
+        }
         if (!(e <= tol_abs[c])) {
             leaf = false;
             iz = dm::mn(dm::mx(imax, 16), 112);
@@ -793,8 +805,13 @@ int device_decompose(int32_t n_curves, const int32_t* degree, const int64_t* cp_
     int64_t n_leaves = 0;
     while (n_items > 0) {
         const unsigned g = blocks_of(n_items);
-        hipLaunchKernelGGL(k_dd_level, dim3(g), dim3(kBlock), 0, st, n_items, D->deg, D->span_curve, T.tol_abs, T.tab,
-                           cur.span, cur.Q, stride, cur.R, cur.z, cur.leaf, cur.split, T.splits, T.cnt + 3);
+#define DD_LEVEL(MPV)                                                                                              \
+    hipLaunchKernelGGL(k_dd_level<MPV>, dim3(g), dim3(kBlock), 0, st, n_items, D->deg, D->span_curve, T.tol_abs, T.tab, \
+                       cur.span, cur.Q, stride, cur.R, cur.z, cur.leaf, cur.split, T.splits, T.cnt + 3)
+        if (mp == 5) DD_LEVEL(5);
+        else if (mp == 9) DD_LEVEL(9);
+        else DD_LEVEL(15);
+#undef DD_LEVEL
         DD_HIP(hipGetLastError());
         DD_HIP(sc.run(cur.leaf, n_items, cur.lpos, T.cnt + 1, st));
         DD_HIP(sc.run(cur.split, n_items, cur.cpos, T.cnt + 2, st));

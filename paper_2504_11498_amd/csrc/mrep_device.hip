@@ -292,7 +292,7 @@ hipError_t mrep::launch_tile_map(const int32_t* tile_off, const int32_t* q_off, 
 #define MREP_PAIRS_MIN_WAVES 6
 #endif
 #ifndef MREP_FINISH_MIN_WAVES
-#define MREP_FINISH_MIN_WAVES 6
+#define MREP_FINISH_MIN_WAVES 4
 #endif
 #ifndef MREP_FULLSCAN_MIN_WAVES
 #define MREP_FULLSCAN_MIN_WAVES 1

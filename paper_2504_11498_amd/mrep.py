@@ -268,18 +268,21 @@ def decompose_curves(curves, tol_rel: float = 1e-6, n_threads: int = 0, weights=
     return Plan(h.value)
 
 
-def decompose_curves_device(curves, tol_rel: float = 1e-6, device=None) -> Plan:
+def decompose_curves_device(curves, tol_rel: float = 1e-6, device=None, cp_dev=None, knots_dev=None) -> Plan:
     """mrep_decompose_curves_device: the decomposition run by kernels on the GPU (degrees 1..15, polynomial).
-    The control points and knots are copied to the device first (torch tensors held until the call returns);
-    the plan holds device arrays and uploads, exports and frees like a host plan."""
+    The control points and knots are copied to the device first unless given as device tensors (cp_dev [n, 3]
+    and knots_dev, FP64, the curve set's arrays); the plan holds device arrays and uploads, exports and frees
+    like a host plan."""
     import torch
 
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     deg = _host(curves.degree, np.int32)
     cp_off = _host(curves.cp_off, np.int64)
     k_off = _host(curves.knot_off, np.int64)
-    cp = torch.as_tensor(_host(curves.cp, np.float64)).to(dev)
-    kn = torch.as_tensor(_host(curves.knots, np.float64)).to(dev)
+    cp = cp_dev if cp_dev is not None else torch.as_tensor(_host(curves.cp, np.float64)).to(dev)
+    kn = knots_dev if knots_dev is not None else torch.as_tensor(_host(curves.knots, np.float64)).to(dev)
+    if cp.dtype != torch.float64 or kn.dtype != torch.float64 or not cp.is_contiguous() or not kn.is_contiguous():
+        raise ValueError("cp_dev and knots_dev must be contiguous float64 device tensors")
     stream = torch.cuda.current_stream(dev).cuda_stream
     h = _vp()
     _check(_decompose_device(int(deg.shape[0]), _p(deg, C.c_int32), _p(cp_off, C.c_int64), _vp(cp.data_ptr()),
