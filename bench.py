@@ -33,6 +33,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 FLOPS_PER_SAMPLE_METHOD = 2 * 19  # the monomial-form distance of one (query, piece, sample): 19 multiply-adds
 FLOPS_PER_SAMPLE_PADDED = 2 * 32  # one 16x16x32 MFMA output element per (query, piece, sample)
 FLOPS_PER_PAIR = 32 * 2 * 12  # refine of one (query, piece) pair: 32 sampled distances of 12 FP32 FMA
+FLOPS_PER_SPHERE_TEST = 10  # |q - c| - r against a bound: 3 sub, 3 mul, 2 add, sqrt, sub
 MLP_CURVE_FLOPS = 2 * (15 * 128 + 128 * 128 + 128 * 2)  # curve network forward per row
 
 
@@ -180,8 +181,10 @@ def device_decomposition(args, dev, curves):
     plan = mrep.decompose_curves_device(curves, 1e-6, dev, cp_dev=cp, knots_dev=kn)
     torch.cuda.synchronize()
     out["device_s"] = time.perf_counter() - t0
+    buf = torch.zeros(max(plan.device_bytes, 256), dtype=torch.uint8, device=dev)  # allocation not timed
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    geom = plan.upload(dev, zero=True)
+    geom = plan.upload(dev, buf=buf)
     torch.cuda.synchronize()
     out["device_tables_s"] = time.perf_counter() - t0
     out["pieces"] = int(plan.n_segments)
@@ -254,7 +257,7 @@ def lattice_headline(args, dev):
     wall = time.perf_counter() - wall0
     ms = e0.elapsed_time(e1) / args.steps
     stage /= args.steps
-    ovf, pairs = geom.workspace_counts(tws)
+    ovf, pairs, tests = geom.workspace_counts(tws, tests=True)
     del tws
     value = n / (ms / 1e3)
     _say("lattice", f"plain ({['screen', 'spheres'][strat]}) {ms:.2f} ms per call")
@@ -317,11 +320,25 @@ def lattice_headline(args, dev):
             "polished_frac": float(np.mean((flags & mrep.F_POLISHED) != 0)),
             "near_tie_frac": float(np.mean((flags & mrep.F_NEAR_TIE) != 0)),
         },
-        "roofline": pairs_roofline(pairs, stage_ms["pair_refine"]),
         "screen": screen_block,
     }
-    if strat != mrep.STRATEGY_SPHERES:
-        result["roofline"] = screen_block["roofline"]
+    # the roofline of the call's dominant kernel (largest stage), the others beside it
+    coef_bytes = int(np.sum(24 * (np.asarray(curves.degree, np.int64)[qs.curve_id] + 1)))
+    roofs = {"k_pairs": pairs_roofline(pairs, stage_ms["pair_refine"]),
+             "k_finish": finish_roofline(n, pairs, coef_bytes, stage_ms["finish"])}
+    if strat == mrep.STRATEGY_SPHERES:
+        # the box kernel: the grouping-and-candidates stage minus the grouping stage of the screen call on the
+        # same queries (the same grouping kernels)
+        box_ms = stage_ms["group_candidates"] - float(st_s[0])
+        roofs["k_box"] = box_roofline(tests, box_ms)
+        stage_ms["candidates_k_box"] = box_ms
+        result["config"]["sphere_tests"] = tests
+    else:
+        roofs["k_screen_bf16"] = screen_block["roofline"]
+    kernel_ms = {k: (r or {}).get("time_ms", 0.0) for k, r in roofs.items()}
+    dominant = max(kernel_ms, key=kernel_ms.get)
+    result["roofline"] = roofs.pop(dominant)
+    result["rooflines_other_kernels"] = roofs
 
     # NN-seeded (curve network trained on held-out struts) and sphere-pruned, same queries
     seeded_outs = None
@@ -396,7 +413,7 @@ def screen_roofline(samples, screen_ms, call_ms):
             "per_unit": "38 flop (19 MAC, the monomial-form distance) per screened (query, piece, sample)",
             "frac_padded_k": padded / BF16_PEAK_TFLOPS,
             "per_unit_padded_k": "64 flop per screened sample: one 16x16x32 BF16 MFMA output element (K padded to 32)",
-            "frac_whole_call": whole / BF16_PEAK_TFLOPS}
+            "frac_whole_call": whole / BF16_PEAK_TFLOPS, "time_ms": screen_ms}
 
 
 def pairs_roofline(pairs, pair_ms):
@@ -406,8 +423,30 @@ def pairs_roofline(pairs, pair_ms):
     achieved = pairs * FLOPS_PER_PAIR / (pair_ms / 1e3) / 1e12 if pair_ms > 0 else None
     return {"bound": "alu", "kernel": "k_pairs<float>", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS if achieved else None,
-            "traffic": None, "units": int(pairs),
+            "traffic": None, "units": int(pairs), "time_ms": pair_ms,
             "per_unit": "768 flop per listed (query, piece) pair: 32 samples x 12 FP32 FMA"}
+
+
+def box_roofline(tests, box_ms):
+    """k_box (sphere lists) against the FP32 vector peak: per sphere test |q - c| - r against a bound, 10 flop
+    (3 sub, 3 mul, 2 add, sqrt, sub); the tests are counted by the kernel (mrep_workspace_counts)."""
+    achieved = tests * FLOPS_PER_SPHERE_TEST / (box_ms / 1e3) / 1e12 if box_ms > 0 else None
+    return {"bound": "alu", "kernel": "k_box", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS if achieved else None,
+            "traffic": None, "units": int(tests), "time_ms": box_ms,
+            "per_unit": "10 flop per sphere test |q - c| - r against a bound (cluster and piece spheres)"}
+
+
+def finish_roofline(n, pairs, coef_bytes, finish_ms):
+    """k_finish (top-2 of each query's pair records, FP64 polish on the exact span, write) against HBM: per
+    query 4 index words, the query, the polished span's (p+1) x 3 FP64 coefficients, its interval and piece
+    bounds, and the 24-byte result; per pair its 48-byte record and 4-byte piece index."""
+    byts = n * (16 + 24 + 16 + 4 + 16 + 24) + pairs * 52 + coef_bytes
+    achieved = byts / (finish_ms / 1e3) / 1e9 if finish_ms > 0 else None
+    return {"bound": "hbm", "kernel": "k_finish", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None, "units": int(n),
+            "algorithmic_bytes": int(byts), "time_ms": finish_ms,
+            "per_unit": "100 B per query + 52 B per pair + 24 (p+1) B of span coefficients per query"}
 
 
 def mlp_roofline(rows, ms):

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 8
+#define MREP_ABI_VERSION 9
 
 /* status codes */
 #define MREP_OK 0
@@ -269,7 +269,10 @@ int32_t mrep_project_curves(const mrep_geom* geom, const mrep_opts* opts, int64_
 
 /* Counters a curve projection call leaves in its workspace: counts_out[0] =
  * queries whose candidate list overflowed to the full scan, counts_out[1] =
- * candidate (query, piece) pairs reserved for the refine.  workspace is the
+ * candidate (query, piece) pairs reserved for the refine, counts_out[2] =
+ * sphere tests |q - c| - r of the sphere-list strategy (cluster and piece
+ * spheres; 0 after a call in the screen strategy).  counts_out holds 3
+ * entries.  workspace is the
  * one the call used (mrep_project_curves, mrep_invert_curves,
  * mrep_project_curves_seeded, also with MREP_OPT_TUNED), geom its geometry;
  * the read is ordered after the call on stream and waits for it.

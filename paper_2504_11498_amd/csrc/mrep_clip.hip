@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_CLIP_M
                                                     const int32_t* __restrict__ pair_seg,
                                                     const int32_t* __restrict__ pair_j,
                                                     const int32_t* __restrict__ pair_count, int64_t pair_cap,
-                                                    const uint8_t* __restrict__ done, float4* __restrict__ pair_res)
+                                                    const uint8_t* __restrict__ done, PairRes* __restrict__ pair_res)
 {
     const int64_t total = min((int64_t)*pair_count, pair_cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
@@ -363,8 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_CLIP_M
         clip_piece_min(C, u, d, k, w, u2, d2);
         // parameter error: the clipping's remaining half-width, plus rounding
         const double err = (0.5 * w + 1e-15) * (G.segt[2 * s + 1] - G.segt[2 * s]);
-        pair_res[2 * p] = make_float4((float)u, (float)d, (float)k, (float)err);
-        pair_res[2 * p + 1] = make_float4((float)u2, (float)d2, 1.f, 0.f);
+        pair_res[p] = pair_result(G, cv, s, q, u, d, k, err, u2, d2);
     }
 }
 
@@ -434,7 +433,7 @@ __global__ __launch_bounds__(256) void k_split(DevGeom G, int64_t n, const int32
 }  // namespace
 
 hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const double* q_xyz, const int32_t* perm,
-                             const ScreenOut& so, const uint8_t* done, float4* pair_res, hipStream_t st)
+                             const ScreenOut& so, const uint8_t* done, PairRes* pair_res, hipStream_t st)
 {
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((so.pair_cap + 255) / 256, 8192));
     hipLaunchKernelGGL(k_pairs_clip, dim3(blocks), dim3(256), 0, st, G, curve_id, q_xyz, perm,

@@ -304,6 +304,51 @@ __global__ void k_dd_curve_spans(int32_t n_curves, int64_t n_iv, const int32_t* 
     coef_n[c] = (b - a) * 3 * (deg[c] + 1);
 }
 
+// Span forms and splits with the degree a compile-time constant (the shared
+// functions inlined with p = P: unrolled loops, arrays in registers).  A wave
+// holds the intervals or pieces of one or two curves, so its degree is nearly
+// always uniform; a mixed wave takes the generic path.
+template <int P>
+__device__ __forceinline__ void span_forms_fixed(const dm::DegreeTables& T, const double* U, int q, const double* P_,
+                                                 double* cf, double* o)
+{
+    double D[(P + 1) * 3], Q[(P + 1) * 3];
+    dm::span_power_bezier<P>(P, T, U, q, P_, D, Q);
+    for (int i = 0; i < 3 * (P + 1); ++i) cf[i] = D[i];
+    for (int i = 0; i < 3 * (P + 1); ++i) o[i] = Q[i];
+}
+
+template <int MP, int P = 1>
+__device__ __forceinline__ void span_forms_degree(int p, const dm::DegreeTables* tab, const double* U, int q,
+                                                  const double* P_, double* cf, double* o)
+{
+    if constexpr (P < MP) {
+        if (p != P) return span_forms_degree<MP, P + 1>(p, tab, U, q, P_, cf, o);
+    }
+    span_forms_fixed<P>(tab[P], U, q, P_, cf, o);
+}
+
+template <int P>
+__device__ __forceinline__ void split_fixed(const double* Q, double z, double* Ql, double* Qr)
+{
+    double Lq[(P + 1) * 3], Rq[(P + 1) * 3], Qv[(P + 1) * 3];
+    for (int k = 0; k < 3 * (P + 1); ++k) Qv[k] = Q[k];
+    dm::split_piece(P, Qv, z, Lq, Rq);
+    for (int k = 0; k < 3 * (P + 1); ++k) {
+        Ql[k] = Lq[k];
+        Qr[k] = Rq[k];
+    }
+}
+
+template <int MP, int P = 4>
+__device__ __forceinline__ void split_degree(int p, const double* Q, double z, double* Ql, double* Qr)
+{
+    if constexpr (P < MP) {
+        if (p != P) return split_degree<MP, P + 1>(p, Q, z, Ql, Qr);
+    }
+    split_fixed<P>(Q, z, Ql, Qr);
+}
+
 // 3. exact span forms and the first level of pieces: one thread per interval.
 //    MP bounds the batch's degree (array sizes only).
 template <int MP>
@@ -327,18 +372,45 @@ __global__ __launch_bounds__(kBlock) void k_dd_spans(int32_t n_curves, int64_t n
     const int q = (int)(g - iv_off[c]) + p;
     const double* U = knots + knot_off[c];
     const int64_t s = sidx[g];
-    double D[(MP + 1) * 3], Q[(MP + 1) * 3];
-    dm::span_power_bezier<MP>(p, tab[p], U, q, cp + 3 * cp_off[c], D, Q);
     span_curve[s] = c;
     span_t[2 * s] = U[q];
     span_t[2 * s + 1] = U[q + 1];
     double* cf = coef + coef_off[c] + (s - span_off[c]) * 3 * (p + 1);
-    for (int i = 0; i < 3 * (p + 1); ++i) cf[i] = D[i];
     it_span[s] = (int32_t)s;
     it_t[2 * s] = U[q];
     it_t[2 * s + 1] = U[q + 1];
     double* o = it_Q + s * (int64_t)q_stride;
-    for (int i = 0; i < 3 * (p + 1); ++i) o[i] = Q[i];
+    const double* P_ = cp + 3 * cp_off[c];
+    const int p0 = __builtin_amdgcn_readfirstlane(p);
+    if (__all(p == p0)) {
+        span_forms_degree<MP>(p0, tab, U, q, P_, cf, o);
+    } else {
+        double D[(MP + 1) * 3], Q[(MP + 1) * 3];
+        dm::span_power_bezier<MP>(p, tab[p], U, q, P_, D, Q);
+        for (int i = 0; i < 3 * (p + 1); ++i) cf[i] = D[i];
+        for (int i = 0; i < 3 * (p + 1); ++i) o[i] = Q[i];
+    }
+}
+
+// The reduction and the deviation bound of one piece with the degree a
+// compile-time constant: the shared (host) functions, inlined with p = P, so
+// that the loops over the control points unroll and the piece's points are
+// loaded once into registers instead of once per error sample.
+template <int P>
+__device__ __forceinline__ double reduce_fixed(const dm::DegreeTables& T, const double* Q, double* R, int* imax)
+{
+    dm::g1_reduce(P, T, Q, R);
+    return dm::deviation_bound(P, T, Q, R, imax);
+}
+
+template <int MP, int P = 4>
+__device__ __forceinline__ double reduce_degree(int p, const dm::DegreeTables* tab, const double* Q, double* R,
+                                                int* imax)
+{
+    if constexpr (P < MP) {
+        if (p != P) return reduce_degree<MP, P + 1>(p, tab, Q, R, imax);
+    }
+    return reduce_fixed<P>(tab[P], Q, R, imax);
 }
 
 // 4. one level: the cubic of every piece, and leaf (deviation bound within the
@@ -373,9 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_dd_level(int64_t n_items, const int3
         // and the deviation bound read is one scalar load for the whole wave.
         const int p0 = __builtin_amdgcn_readfirstlane(p);
         if (__all(p == p0)) {
-            const dm::DegreeTables& T0 = tab[p0];
-            dm::g1_reduce(p0, T0, Q, R);
-            e = dm::deviation_bound(p0, T0, Q, R, &imax);
+            e = reduce_degree<MP>(p0, tab, Q, R, &imax);
         } else {
             dm::g1_reduce(p, tab[p], Q, R);
             e = dm::deviation_bound(p, tab[p], Q, R, &imax);
@@ -426,11 +496,16 @@ __global__ __launch_bounds__(kBlock) void k_dd_emit(int64_t n_items, const int32
     const int64_t j = 2 * (int64_t)cpos[i];
     double* Ql = nx_Q + j * q_stride;
     double* Qr = Ql + q_stride;
-    double Lq[(MP + 1) * 3], Rq[(MP + 1) * 3];
-    dm::split_piece(p, it_Q + i * (int64_t)q_stride, z, Lq, Rq);
-    for (int k = 0; k < 3 * (p + 1); ++k) {
-        Ql[k] = Lq[k];
-        Qr[k] = Rq[k];
+    const int p0 = __builtin_amdgcn_readfirstlane(p);
+    if (__all(p == p0)) {
+        split_degree<MP>(p0, it_Q + i * (int64_t)q_stride, z, Ql, Qr);
+    } else {
+        double Lq[(MP + 1) * 3], Rq[(MP + 1) * 3];
+        dm::split_piece(p, it_Q + i * (int64_t)q_stride, z, Lq, Rq);
+        for (int k = 0; k < 3 * (p + 1); ++k) {
+            Ql[k] = Lq[k];
+            Qr[k] = Rq[k];
+        }
     }
     nx_span[j] = s;
     nx_span[j + 1] = s;
@@ -646,7 +721,9 @@ struct DdTemps {
     }
 };
 
-// Items of one level.
+// Items of one level.  The two level buffers are reused from level to level
+// and only grow (by half again), so a decomposition makes a handful of
+// allocations instead of a set per level.
 struct Level {
     int32_t* span = nullptr;
     double* t = nullptr;
@@ -657,14 +734,23 @@ struct Level {
     int32_t* split = nullptr;
     int32_t* lpos = nullptr;
     int32_t* cpos = nullptr;
+    int64_t cap = 0;
     ~Level() { release(); }
     void release()
     {
         dfree(span); dfree(t); dfree(Q); dfree(R); dfree(z); dfree(leaf); dfree(split); dfree(lpos); dfree(cpos);
+        cap = 0;
+    }
+    hipError_t ensure(int64_t n, int32_t stride)
+    {
+        if (n <= cap) return hipSuccess;
+        release();
+        return alloc(std::max<int64_t>(n, cap + cap / 2), stride);
     }
     hipError_t alloc(int64_t n, int32_t stride)
     {
         hipError_t e;
+        cap = n;
         if ((e = dmalloc(&span, n)) != hipSuccess) return e;
         if ((e = dmalloc(&t, 2 * n)) != hipSuccess) return e;
         if ((e = dmalloc(&Q, n * stride)) != hipSuccess) return e;
@@ -782,7 +868,7 @@ int device_decompose(int32_t n_curves, const int32_t* degree, const int64_t* cp_
     // 3. exact span forms; level 0 = every span
     Level cur, nxt;
     int64_t n_items = n_span;
-    DD_HIP(cur.alloc(n_items, stride));
+    DD_HIP(cur.ensure(n_items, stride));
     if (n_iv > 0) {
         const unsigned g = blocks_of(n_iv);
         if (mp == 5)
@@ -828,8 +914,8 @@ int device_decompose(int32_t n_curves, const int32_t* degree, const int64_t* cp_
             return MREP_E_INVALID_ARG;
         }
         if (n_leaves + nl > T.lf_cap) {
-            // grow the leaf arrays (geometric), keeping what is there
-            const int64_t cap = std::max<int64_t>(n_leaves + nl, 2 * T.lf_cap);
+            // grow the leaf arrays (geometric, from four pieces per span), keeping what is there
+            const int64_t cap = std::max<int64_t>(std::max<int64_t>(n_leaves + nl, 2 * T.lf_cap), 4 * (int64_t)n_span);
             double *R2 = nullptr, *t2 = nullptr;
             int32_t* s2 = nullptr;
             DD_HIP(dmalloc(&R2, 12 * cap));
@@ -845,8 +931,7 @@ int device_decompose(int32_t n_curves, const int32_t* degree, const int64_t* cp_
             T.lf_R = R2; T.lf_t = t2; T.lf_span = s2;
             T.lf_cap = cap;
         }
-        nxt.release();
-        DD_HIP(nxt.alloc(2 * ns, stride));
+        DD_HIP(nxt.ensure(2 * ns, stride));
         if (mp == 5)
             launch_emit<5>(g, st, n_items, D->deg, D->span_curve, cur.span, cur.t, cur.Q, stride, cur.R, cur.z, cur.leaf,
                            cur.lpos, cur.cpos, n_leaves, T.lf_R, T.lf_t, T.lf_span, T.span_nleaf, nxt.span, nxt.t, nxt.Q);
@@ -863,7 +948,7 @@ int device_decompose(int32_t n_curves, const int32_t* degree, const int64_t* cp_
         n_items = 2 * ns;
         std::swap(cur.span, nxt.span); std::swap(cur.t, nxt.t); std::swap(cur.Q, nxt.Q); std::swap(cur.R, nxt.R);
         std::swap(cur.z, nxt.z); std::swap(cur.leaf, nxt.leaf); std::swap(cur.split, nxt.split);
-        std::swap(cur.lpos, nxt.lpos); std::swap(cur.cpos, nxt.cpos);
+        std::swap(cur.lpos, nxt.lpos); std::swap(cur.cpos, nxt.cpos); std::swap(cur.cap, nxt.cap);
     }
     cur.release();
     nxt.release();

@@ -9,6 +9,8 @@
 
 namespace mrep {
 
+struct PairRes;  // one (query, piece) refine result (mrep_refine.h)
+
 // ---------------------------------------------------------------------------
 // device views
 // ---------------------------------------------------------------------------
@@ -110,13 +112,13 @@ hipError_t launch_grouping(int64_t n_curves, int64_t n, const int32_t* n_dev, co
 // done (nullable) skips decided queries; flag_in is ORed into every flag word
 // written; the overflow counter *ovf_count must be zero on entry.
 hipError_t launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
-                         const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
+                         const int32_t* q_off, const int32_t* perm, const ScreenOut& so, PairRes* pair_res,
                          const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
                          int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip = false,
                          int pairs_mark = -1);
 // k_pairs_clip (mrep_clip.hip): the paper's refinement path on every candidate pair
 hipError_t launch_pairs_clip(const DevGeom& G, const int32_t* curve_id, const double* q_xyz, const int32_t* perm,
-                             const ScreenOut& so, const uint8_t* done, float4* pair_res, hipStream_t st);
+                             const ScreenOut& so, const uint8_t* done, PairRes* pair_res, hipStream_t st);
 
 // The screened projection pipeline (grouping, screen, refine, finish) on a
 // workspace of project_ws_bytes(n_curves, n, kc) bytes.  n bounds the query

@@ -64,8 +64,7 @@ struct Work {
     int32_t* ovf_count;   // = hist + n_curves
     int32_t* pair_count;  // = hist + n_curves + 1
     ScreenOut so;         // candidate lists as (query, piece) pairs
-    float4* pair_res;     // [2 cap] per pair: u, squared distance, kappa, parameter error bound of the
-                          // piece minimum; then u, squared distance of its second distinct local minimum
+    PairRes* pair_res;    // [cap] per pair: the piece's minimum and second local minimum (mrep_refine.h)
 };
 
 // pairs reserved per query on average before queries overflow to the full scan
@@ -107,6 +106,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
     };
     const int64_t cap = std::min<int64_t>(kPairsPerQuery * n + 1024, (int64_t)INT32_MAX);
     int64_t o_hist = take(4 * (n_curves + 2));
+    (void)take(8 * kWsCounters);  // the sphere-test counters (written by the sphere strategy only)
     int64_t o_qoff = take(4 * (n_curves + 1));
     int64_t o_toff = take(4 * (n_curves + 1));
     int64_t o_tmap = take(16 * screen_grid(n_curves, n));
@@ -117,7 +117,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
     int64_t o_ub = take(4 * n);
     int64_t o_pseg = take(4 * cap);
     int64_t o_pj = take(4 * cap);
-    int64_t o_pres = take(32 * cap);
+    int64_t o_pres = take((int64_t)sizeof(PairRes) * cap);
     if (w) {
         w->hist = reinterpret_cast<int32_t*>(base + o_hist);
         w->q_off = reinterpret_cast<int32_t*>(base + o_qoff);
@@ -134,7 +134,7 @@ static int64_t work_layout(int64_t n_curves, int64_t n, int kc, char* base, Work
         w->so.pair_count = w->pair_count;
         w->so.pair_cap = cap;
         w->so.ub = reinterpret_cast<float*>(base + o_ub);
-        w->pair_res = reinterpret_cast<float4*>(base + o_pres);
+        w->pair_res = reinterpret_cast<PairRes*>(base + o_pres);
     }
     return off;
 }
@@ -289,7 +289,7 @@ hipError_t mrep::launch_tile_map(const int32_t* tile_off, const int32_t* q_off, 
 // k_finish 6 trim the refine stage by about 3% on the batched curves; the full
 // scan keeps its registers (its FP64 instance would spill heavily)
 #ifndef MREP_PAIRS_MIN_WAVES
-#define MREP_PAIRS_MIN_WAVES 6
+#define MREP_PAIRS_MIN_WAVES 5
 #endif
 #ifndef MREP_FINISH_MIN_WAVES
 #define MREP_FINISH_MIN_WAVES 4
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_
                                                const int32_t* __restrict__ pair_seg,
                                                const int32_t* __restrict__ pair_j,
                                                const int32_t* __restrict__ pair_count, int64_t pair_cap,
-                                               const uint8_t* __restrict__ done, float4* __restrict__ pair_res)
+                                               const uint8_t* __restrict__ done, PairRes* __restrict__ pair_res)
 {
     const int64_t total = min((int64_t)*pair_count, pair_cap);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
@@ -321,18 +321,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_
         T u, d, k, u2, d2;
         piece_min(C, u, d, k, u2, d2);
         const double err = param_error(C, u, k, G.segt[2 * s], G.segt[2 * s + 1]);
-        pair_res[2 * p] = make_float4((float)u, (float)d, (float)k, (float)err);
-        pair_res[2 * p + 1] = make_float4((float)u2, (float)d2, 1.f, 0.f);
+        pair_res[p] = pair_result(G, cv, s, q, (double)u, (double)d, (double)k, err, (double)u2, (double)d2);
     }
 }
 
+__device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
+{
+    Cand r;
+    r.d2 = __shfl(c.d2, src, 64);
+    r.t = __shfl(c.t, src, 64);
+    r.kappa = __shfl(c.kappa, src, 64);
+    r.t_err = __shfl(c.t_err, src, 64);
+    r.seg = __shfl(c.seg, src, 64);
+    r.across = __shfl(c.across, src, 64);
+    r.end = __shfl(c.end, src, 64);
+    return r;
+}
+
 // One thread per query: the two best of its pairs, then finish.  Queries whose
-// list overflowed are appended to ovf_list for k_fullscan.
+// list overflowed are appended to ovf_list for k_fullscan.  (A split into a
+// coalesced selection kernel, eight lanes per query, and a polish kernel was
+// measured slower on the lattice struts: 27.6 ms against 16.8 ms.)
 template <typename T, bool kGen>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH_MIN_WAVES, 8))) void k_finish(DevGeom G, const int32_t* __restrict__ cid,
                                                 const double* __restrict__ qxyz, const int32_t* __restrict__ q_off,
                                                 const int32_t* __restrict__ perm, ScreenOut so,
-                                                const float4* __restrict__ pair_res, const uint8_t* __restrict__ done,
+                                                const PairRes* __restrict__ pair_res, const uint8_t* __restrict__ done,
                                                 uint32_t flag_in, double tie_rel, int32_t invert,
                                                 int32_t* __restrict__ ovf_list, int32_t* __restrict__ ovf_count,
                                                 Outs o)
@@ -350,32 +364,18 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(MREP_FINISH
     const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
     Cand b1 = empty_cand(cv), b2 = b1;
     const int64_t p0 = so.pair_off[j];
-    // each pair's minimum, then its second local minimum (kappa 1, no parameter
-    // error: only its distance and t enter the tie test), through one call site
-    for (int i = 0; i < 2 * n_list; ++i) {
-        const float4 r = pair_res[2 * p0 + i];
-        if (!(r.y < INFINITY)) continue;
-        const bool sec = (i & 1) != 0;
-        Cand x = make_cand_q(G, cv, so.pair_seg[p0 + (i >> 1)], (double)r.x, (double)r.y, sec ? 1.0 : (double)r.z,
-                             sec ? 0.0 : (double)r.w, q);
-        x.end |= sec ? kSecond : 0;
-        top2(x, b1, b2);
+    // each pair record is loaded once; its minimum, then its second local minimum
+    for (int i = 0; i < n_list; ++i) {
+        const PairRes r = pair_res[p0 + i];
+        const int32_t sg = so.pair_seg[p0 + i];
+        const Cand x0 = pair_cand(r, sg, false);
+        top2(x0, b1, b2);
+        if (r.d2b < INFINITY) top2(pair_cand(r, sg, true), b1, b2);
     }
     finish<T, kGen>(G, cv, q, b1, b2, flag_in, tie_rel, invert, qi, o);
 }
 
-__device__ __forceinline__ Cand cand_from_lane(const Cand& c, int src)
-{
-    Cand r;
-    r.d2 = __shfl(c.d2, src, 64);
-    r.t = __shfl(c.t, src, 64);
-    r.kappa = __shfl(c.kappa, src, 64);
-    r.t_err = __shfl(c.t_err, src, 64);
-    r.seg = __shfl(c.seg, src, 64);
-    r.across = __shfl(c.across, src, 64);
-    r.end = __shfl(c.end, src, 64);
-    return r;
-}
+
 
 // One wave per query, lanes striding over the query's pieces: (1) the best
 // upper bound from every piece's samples, (2) refine every piece whose lower
@@ -842,13 +842,21 @@ extern "C" int32_t mrep_workspace_counts(const mrep_geom* geom, const void* work
         set_error("mrep_workspace_counts: null pointer or surface geometry");
         return MREP_E_INVALID_ARG;
     }
-    // both workspace layouts start with the per-curve histogram, then the overflow and pair counters
+    // both workspace layouts start with the per-curve histogram, then the overflow
+    // and pair counters, then (256-byte aligned) the sphere-test counters
     int32_t c[2] = {0, 0};
-    const char* at = (const char*)workspace + 4 * geom->g.L.n_curves;
+    const int64_t nc = geom->g.L.n_curves;
+    const char* at = (const char*)workspace + 4 * nc;
+    std::vector<unsigned long long> tests(kWsCounters);
     HIP_OK(hipMemcpyAsync(c, at, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_OK(hipMemcpyAsync(tests.data(), (const char*)workspace + ((4 * (nc + 2) + 255) & ~(int64_t)255),
+                          sizeof(unsigned long long) * kWsCounters, hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     counts_out[0] = c[0];
     counts_out[1] = c[1];
+    unsigned long long t = 0;
+    for (unsigned long long v : tests) t += v;
+    counts_out[2] = (int64_t)t;
     return MREP_OK;
 }
 
@@ -877,6 +885,9 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     DevGeom G = dev_view(geom);
     int rc;
     HIP_OK(launch_grouping(nc, n, n_dev, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
+    // the sphere-test counters after the histogram: none in this strategy
+    hipLaunchKernelGGL(k_fill_i32, dim3(2 * kWsCounters / 256), dim3(256), 0, st,
+                       (int32_t*)((char*)workspace + a256(4 * (nc + 2))), (int64_t)(2 * kWsCounters), 0);
     if (timed && (rc = stage_mark(stage0 + 1, st))) return rc;
     if (opts->precision == MREP_PREC_BF16) {
         const int64_t grid = screen_grid(nc, n);
@@ -906,7 +917,7 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
 }
 
 hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve_id, const double* q_xyz,
-                               const int32_t* q_off, const int32_t* perm, const ScreenOut& so, float4* pair_res,
+                               const int32_t* q_off, const int32_t* perm, const ScreenOut& so, PairRes* pair_res,
                                const uint8_t* done, uint32_t flag_in, double tie_rel, int invert, int32_t* ovf_list,
                                int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip, int pairs_mark)
 {
@@ -925,14 +936,14 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
     // the general instances evaluate Bezier and rational spans as well (geometries that hold them)
     if (G.general) {
         hipLaunchKernelGGL((k_finish<float, true>), dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
-                           q_xyz, q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
+                           q_xyz, q_off, perm, so, (const PairRes*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
                            ovf_count, o);
         hipLaunchKernelGGL((k_fullscan<float, true>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off,
                            perm, (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,
                            (uint32_t)MREP_F_FULLSCAN | flag_in, tie_rel, invert, o);
     } else {
         hipLaunchKernelGGL((k_finish<float, false>), dim3((unsigned)((n + RT - 1) / RT)), dim3(RT), 0, st, G, curve_id,
-                           q_xyz, q_off, perm, so, (const float4*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
+                           q_xyz, q_off, perm, so, (const PairRes*)pair_res, done, flag_in, tie_rel, invert, ovf_list,
                            ovf_count, o);
         hipLaunchKernelGGL((k_fullscan<float, false>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz, q_off,
                            perm, (const int32_t*)ovf_list, (const int32_t*)ovf_count, (const float*)so.ub,

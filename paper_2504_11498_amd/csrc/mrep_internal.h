@@ -52,6 +52,10 @@ struct DCurve {
     int32_t pad_;
 };
 static_assert(sizeof(DCurve) == 112, "DCurve layout");
+// 64-bit counters that follow the per-curve histogram at the start of a curve
+// projection workspace (the sphere lists count their sphere tests there; one
+// counter per workgroup slot modulo this, summed by mrep_workspace_counts)
+constexpr int kWsCounters = 1024;
 // pieces per cluster of a curve (the last one may hold fewer)
 constexpr int kCluPieces = 32;
 

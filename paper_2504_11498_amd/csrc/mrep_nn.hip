@@ -685,6 +685,7 @@ struct BoxOut {
     int32_t* cand;  // [n][kK] global piece index (-1: fewer pieces)
     uint16_t* xb;   // [n][kK][16] BF16 network inputs of the candidates (null: not written)
     ScreenOut so;   // per query: the pieces whose lower bound reaches UB + margin; so.ub = UB
+    unsigned long long* tests;  // [kWsCounters] sphere tests, per workgroup slot modulo kWsCounters (zeroed)
 };
 
 // float -> uint32 with the same order (negative values included), and back
@@ -784,6 +785,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
     float ub = INFINITY;
     uint64_t key[kK];
     int cnt = 0;  // pieces listed (same value in the query's 8 lanes)
+    uint32_t nt = 0;  // sphere tests of this lane (the algorithmic work the bench reports)
     if (cv.clu_use) {
         // a. first bound
 #pragma unroll
@@ -797,6 +799,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                 const float d = dist(p);
                 ub = fminf(ub, d + p.w + eps);
                 insert_key(key, ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i));
+                ++nt;
             }
         }
         merge_keys(key);
@@ -808,6 +811,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                 for (int k = k0 + sub; k < k1; k += kBoxSub) {
                     const float4 p = G.sph[cv.seg_off + k];
                     ub = fminf(ub, dist(p) + p.w + eps);
+                    ++nt;
                 }
             }
         }
@@ -826,6 +830,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                 if (i < cn) {
                     const float4 p = s_st[i];
                     hit = dist(p) - p.w - eps <= thr0;
+                    ++nt;
                 }
                 const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
                 const int pos = ncl + __popc(grp & ((1u << sub) - 1u));
@@ -845,6 +850,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                     const float d = dist(p), re = p.w + eps;
                     ub = fminf(ub, d + re);
                     insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)k);
+                    ++nt;
                 }
             }
         }
@@ -861,6 +867,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                     if (k < k1) {
                         const float4 p = G.sph[cv.seg_off + k];
                         hit = dist(p) - p.w - eps <= thr;
+                        ++nt;
                     }
                     const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
                     const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
@@ -890,6 +897,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                         const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
                         const float d2 = dx * dx + dy * dy + dz * dz;
                         const float re = p.w + eps;
+                        ++nt;
                         const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
                         const float tu = ub - re;
                         const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
@@ -912,6 +920,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                             const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
                             const float tt = thr + p.w + eps;
                             hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                            ++nt;
                         }
                         const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
                         const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
@@ -926,6 +935,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                 thr = ub + tie_margin(ub, cv, tie_rel);
             }
         }
+    }
+    // the workgroup's sphere tests: one atomic per wave into a counter chosen by the slot
+    {
+        unsigned long long w = nt;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        if (lane == 0 && out.tests) atomicAdd(&out.tests[blockIdx.x % kWsCounters], w);
     }
     // reserve the workgroup's pairs with one atomic
     const bool listed = active && cnt <= kBoxCap;
@@ -1258,7 +1274,7 @@ constexpr int64_t kSpherePairsPerQuery = 24;  // average listed pieces per query
 struct SeedWork {
     int32_t *hist, *q_off, *tile_off, *perm, *ovf_list, *ovf_count;
     BoxOut box;
-    float4* pair_res;
+    PairRes* pair_res;
     float2* scores;
     uint8_t* done;
 };
@@ -1272,15 +1288,17 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
         return o;
     };
     const int64_t cap = std::min<int64_t>(kSpherePairsPerQuery * n + 1024, (int64_t)INT32_MAX);
-    const int64_t oh = take(4 * (nc + 2)), oq = take(4 * (nc + 1)), ot = take(4 * (nc + 1)), op = take(4 * n);
+    const int64_t oh = take(4 * (nc + 2)), otc = take(8 * kWsCounters), oq = take(4 * (nc + 1)),
+                  ot = take(4 * (nc + 1)), op = take(4 * n);
     const int64_t oov = take(4 * n), oc = take(4 * n * kK), oxb = take(32 * n * kK), ocn = take(4 * n);
     const int64_t opo = take(4 * n), oub = take(4 * n), ops = take(4 * cap), opj = take(4 * cap);
-    const int64_t opr = take(32 * cap), osc = take(8 * n * kK), odn = take(n);
+    const int64_t opr = take((int64_t)sizeof(PairRes) * cap), osc = take(8 * n * kK), odn = take(n);
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
         w->ovf_count = w->hist + nc;  // zeroed by the grouping, like the pair counter after it
         w->box.cand = (int32_t*)(base + oc);
+        w->box.tests = (unsigned long long*)(base + otc);
         w->box.xb = (uint16_t*)(base + oxb);
         w->box.so.cand_n = (int32_t*)(base + ocn);
         w->box.so.pair_off = (int32_t*)(base + opo);
@@ -1289,7 +1307,7 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
         w->box.so.pair_j = (int32_t*)(base + opj);
         w->box.so.pair_count = w->hist + nc + 1;
         w->box.so.pair_cap = cap;
-        w->pair_res = (float4*)(base + opr);
+        w->pair_res = (PairRes*)(base + opr);
         w->scores = (float2*)(base + osc);
         w->done = (uint8_t*)(base + odn);
     }
@@ -1322,11 +1340,18 @@ static int pack_image(const mrep_nn* nn, hipStream_t st)
 }
 
 // grouping + sphere candidates shared by the seeded call and the feature export
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz, float tie_rel,
                       SeedWork& w, const Outs& o, hipStream_t st)
 {
     const int64_t nc = geom->g.L.n_curves;
     NN_HIP(launch_grouping(nc, n, nullptr, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
+    hipLaunchKernelGGL(k_zero_u64, dim3(kWsCounters / 256), dim3(256), 0, st, w.box.tests, (int64_t)kWsCounters);
     const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
     hipLaunchKernelGGL(k_box, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
                        (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,

@@ -490,17 +490,6 @@ __device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
     return (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
 }
 
-__device__ __forceinline__ void cand_select(bool c, const Cand& a, Cand& dst)
-{
-    dst.t = c ? a.t : dst.t;
-    dst.d2 = c ? a.d2 : dst.d2;
-    dst.kappa = c ? a.kappa : dst.kappa;
-    dst.t_err = c ? a.t_err : dst.t_err;
-    dst.seg = c ? a.seg : dst.seg;
-    dst.across = c ? a.across : dst.across;
-    dst.end = c ? a.end : dst.end;
-}
-
 // x is the joint it shares with candidate y's piece, and y is that piece's
 // minimum (false when y is empty or a second minimum)
 __device__ __forceinline__ bool on_piece(const Cand& x, const Cand& y)
@@ -522,17 +511,34 @@ __device__ __forceinline__ bool on_piece(const Cand& x, const Cand& y)
 // place until a lower candidate comes, but it never becomes the runner-up.
 __device__ __forceinline__ void top2(const Cand& x, Cand& b1, Cand& b2)
 {
+    // decisions first, then every field of both places written unconditionally
+    // from selects: branches that store into b1 or b2 get merged by the compiler
+    // into one store through a pointer chosen at run time, which keeps both
+    // candidates in scratch memory
     const bool live = x.d2 < INFINITY && !on_piece(x, b1);
     const bool repl = live && on_piece(b1, x);
     const bool first = live && (repl || x.d2 < b1.d2 || (x.d2 == b1.d2 && x.t < b1.t));
     const bool demote = first && !repl && !b1.across;
     const bool second = live && !first && !x.across && !on_piece(x, b2) &&
                         (x.d2 < b2.d2 || (x.d2 == b2.d2 && x.t < b2.t));
-    // a runner-up on the new best's piece goes too
-    if (repl && on_piece(b2, x)) b2.d2 = INFINITY;
-    cand_select(demote, b1, b2);
-    cand_select(second, x, b2);
-    cand_select(first, x, b1);
+    const bool clear2 = repl && on_piece(b2, x);  // a runner-up on the new best's piece goes too
+    Cand n1, n2;
+    n2.t = demote ? b1.t : (second ? x.t : b2.t);
+    n2.d2 = clear2 ? (double)INFINITY : (demote ? b1.d2 : (second ? x.d2 : b2.d2));
+    n2.kappa = demote ? b1.kappa : (second ? x.kappa : b2.kappa);
+    n2.t_err = demote ? b1.t_err : (second ? x.t_err : b2.t_err);
+    n2.seg = demote ? b1.seg : (second ? x.seg : b2.seg);
+    n2.across = demote ? b1.across : (second ? x.across : b2.across);
+    n2.end = demote ? b1.end : (second ? x.end : b2.end);
+    n1.t = first ? x.t : b1.t;
+    n1.d2 = first ? x.d2 : b1.d2;
+    n1.kappa = first ? x.kappa : b1.kappa;
+    n1.t_err = first ? x.t_err : b1.t_err;
+    n1.seg = first ? x.seg : b1.seg;
+    n1.across = first ? x.across : b1.across;
+    n1.end = first ? x.end : b1.end;
+    b1 = n1;
+    b2 = n2;
 }
 
 // Piece s's candidate at its end u (0 or 1) when that end is an interior joint
@@ -590,6 +596,60 @@ __device__ __forceinline__ Cand make_cand_q(const DevGeom& G, const DCurve& cv, 
     return x;
 }
 
+// Result of the refine for one (query, piece) pair, already in the curve's
+// parameter and classified (piece end, distance falling across the joint), so
+// that the finish reads one contiguous record per pair and no piece table.
+struct alignas(16) PairRes {
+    double t;       // the piece's minimum (global parameter)
+    double t2;      // its second local minimum (when d2b < inf)
+    float d2;       // squared distance at t (refine precision)
+    float kappa;
+    float t_err;    // bound on the parameter error left by the refine precision
+    float d2b;      // squared distance at t2; +inf when the piece has no second minimum
+    uint32_t tag;   // bits 0-1: t at the piece's start (1) or end (2); bit 2: across; bits 4-6: the same for t2
+    uint32_t pad_[3];
+};
+static_assert(sizeof(PairRes) == 48, "PairRes layout");
+
+__device__ __forceinline__ PairRes pair_result(const DevGeom& G, const DCurve& cv, int64_t s, const double* q,
+                                               double u, double d, double k, double err, double u2, double d2)
+{
+    const Cand c1 = make_cand_q(G, cv, s, u, d, k, err, q);
+    PairRes r;
+    r.t = c1.t;
+    r.d2 = (float)d;
+    r.kappa = (float)k;
+    r.t_err = (float)err;
+    uint32_t tag = (uint32_t)c1.end | ((uint32_t)c1.across << 2);
+    if (d2 < INFINITY) {
+        const Cand c2 = make_cand_q(G, cv, s, u2, d2, 1.0, 0.0, q);
+        r.t2 = c2.t;
+        r.d2b = (float)d2;
+        tag |= ((uint32_t)c2.end | ((uint32_t)c2.across << 2)) << 4;
+    } else {
+        r.t2 = 0.0;
+        r.d2b = INFINITY;
+    }
+    r.tag = tag;
+    r.pad_[0] = r.pad_[1] = r.pad_[2] = 0u;
+    return r;
+}
+
+// candidate i of a pair record: its minimum (i = 0) or its second minimum (1)
+__device__ __forceinline__ Cand pair_cand(const PairRes& r, int32_t seg, bool sec)
+{
+    Cand x;
+    x.t = sec ? r.t2 : r.t;
+    x.d2 = (double)(sec ? r.d2b : r.d2);
+    x.kappa = sec ? 1.f : r.kappa;
+    x.t_err = sec ? 0.f : r.t_err;
+    x.seg = seg;
+    const uint32_t tg = sec ? (r.tag >> 4) : r.tag;
+    x.end = (int32_t)(tg & 3u) | (sec ? kSecond : 0);
+    x.across = (int32_t)((tg >> 2) & 1u);
+    return x;
+}
+
 template <typename T>
 __device__ void consider(const DevGeom& G, const DCurve& cv, int64_t s, const double* q, Cand& b1, Cand& b2)
 {
@@ -640,11 +700,15 @@ __device__ __forceinline__ void finish(const DevGeom& G, const DCurve& cv, const
         int nk = tie ? 2 : 1;
         bool conv = false;
         double h = 0.0;
+        // the start points as scalars: selecting fields of b1 / b2 by the loop
+        // index would make the compiler keep both candidates in scratch memory
+        const double t1s = b1.t, t2s = b2.t;
+        const int32_t s1s = b1.seg, s2s = b2.seg;
         for (int k = 0; k < nk; ++k) {
             const bool probe = k >= (tie ? 2 : 1);
-            const int32_t ks = probe ? seg : (k ? b2.seg : b1.seg);
+            const int32_t ks = probe ? seg : (k ? s2s : s1s);
             int32_t span = G.segspan[ks];
-            double t0 = k == 0 ? b1.t : b2.t;
+            double t0 = k == 0 ? t1s : t2s;
             if (probe) {
                 const double ta = G.spant[2 * span], tb = G.spant[2 * span + 1];
                 t0 = fmin(fmax(t + ((k & 1) ? -h : h), ta), tb);

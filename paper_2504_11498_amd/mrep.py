@@ -220,14 +220,19 @@ class Plan:
                               _p(patch_span, C.c_int32)), "mrep_plan_export_surfaces")
         return {"patch_off": patch_off, "patch_uv": patch_uv, "patch_cp": patch_cp, "patch_span": patch_span}
 
-    def upload(self, device=None, zero: bool = False):
+    def upload(self, device=None, zero: bool = False, buf=None):
         """Copy the tables to a new device buffer (a torch tensor) and return a Geometry.  zero: clear the buffer
-        first, so that the alignment gaps between tables compare equal too."""
+        first, so that the alignment gaps between tables compare equal too.  buf: a uint8 device tensor of at least
+        device_bytes to use instead of a new one."""
         import torch
 
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        alloc = torch.zeros if zero else torch.empty
-        buf = alloc(max(self.device_bytes, 256), dtype=torch.uint8, device=dev)
+        if buf is None:
+            alloc = torch.zeros if zero else torch.empty
+            buf = alloc(max(self.device_bytes, 256), dtype=torch.uint8, device=dev)
+        elif buf.dtype != torch.uint8 or buf.numel() < self.device_bytes:
+            raise ValueError("buf must be a uint8 device tensor of at least device_bytes")
+        dev = buf.device
         stream = torch.cuda.current_stream(dev).cuda_stream
         g = _vp()
         _check(_upload(self._h, _vp(buf.data_ptr()), buf.numel(), _vp(stream), C.byref(g)), "mrep_upload")
@@ -457,14 +462,15 @@ class Geometry:
                   _vp(stream)), "mrep_invert_curves" if invert else "mrep_project_curves")
         return t, d, s, f
 
-    def workspace_counts(self, workspace):
-        """(queries overflowed to the full scan, candidate pairs reserved) left by the last call on workspace."""
+    def workspace_counts(self, workspace, tests: bool = False):
+        """(queries overflowed to the full scan, candidate pairs reserved) left by the last call on workspace; with
+        tests, also the sphere tests of the sphere-list strategy."""
         import torch
 
-        c = np.zeros(2, np.int64)
+        c = np.zeros(3, np.int64)
         stream = torch.cuda.current_stream(workspace.device).cuda_stream
         _check(_ws_counts(self._h, _vp(workspace.data_ptr()), _p(c, C.c_int64), _vp(stream)), "mrep_workspace_counts")
-        return int(c[0]), int(c[1])
+        return (int(c[0]), int(c[1]), int(c[2])) if tests else (int(c[0]), int(c[1]))
 
     def project_noalloc(self, q, curve_id, opts: Opts | None = None, out=None):
         """As project(), through mrep_project_curves_noalloc: no workspace, the library's fixed per-GPU scratch."""
