@@ -746,6 +746,9 @@ __device__ __forceinline__ void stage_clusters(const DevGeom& G, const DCurve& c
     __syncthreads();
 }
 
+// kKeys: also find the K pieces with the smallest lower bounds (the network's
+// candidates); the sphere-pruned call needs only the bound and the list.
+template <bool kKeys>
 __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* __restrict__ tile_off,
                                                      const int32_t* __restrict__ q_off,
                                                      const int32_t* __restrict__ perm, const double* __restrict__ qxyz,
@@ -849,13 +852,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                     const float4 p = G.sph[cv.seg_off + k];
                     const float d = dist(p), re = p.w + eps;
                     ub = fminf(ub, d + re);
-                    insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)k);
+                    if constexpr (kKeys) insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)k);
                     ++nt;
                 }
             }
         }
         ub = min8(ub);
-        merge_keys(key);
+        if constexpr (kKeys) merge_keys(key);
         // d. the list
         const float thr = ub + tie_margin(ub, cv, tie_rel);
         if (active && clus_ok) {
@@ -900,7 +903,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                         ++nt;
                         const float t4 = ord_val((uint32_t)(key[kK - 1] >> 32)) + re;
                         const float tu = ub - re;
-                        const bool c4 = key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4);
+                        const bool c4 = kKeys && (key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4));
                         const bool cu = tu > 0.f && d2 < tu * tu;
                         if (c4 || cu) {
                             const float d = sqrtf(d2);
@@ -965,9 +968,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         out.so.cand_n[j] = fits ? cnt : -1;
         out.so.pair_off[j] = (int32_t)b;
         out.so.ub[j] = ub;
+        if constexpr (kKeys) {
 #pragma unroll
-        for (int k = 0; k < kK; ++k)
-            out.cand[j * kK + k] = key[k] == ~0ull ? -1 : (int32_t)(cv.seg_off + (uint32_t)key[k]);
+            for (int k = 0; k < kK; ++k)
+                out.cand[j * kK + k] = key[k] == ~0ull ? -1 : (int32_t)(cv.seg_off + (uint32_t)key[k]);
+        }
     }
     if (listed) {
         for (int k = sub; k < cnt; k += kBoxSub) {
@@ -976,7 +981,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
             out.so.pair_j[b + k] = fits ? (int32_t)j : -1;  // a slot past the capacity stays unused
         }
     }
-    if (out.xb && sub < kK) {
+    if (kKeys && out.xb && sub < kK) {
         const uint64_t kk = sub == 0 ? key[0] : (sub == 1 ? key[1] : (sub == 2 ? key[2] : key[3]));
         float f[kCurveIn];
 #pragma unroll
@@ -1347,15 +1352,20 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n)
 }
 
 static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz, float tie_rel,
-                      SeedWork& w, const Outs& o, hipStream_t st)
+                      SeedWork& w, const Outs& o, hipStream_t st, bool keys)
 {
     const int64_t nc = geom->g.L.n_curves;
     NN_HIP(launch_grouping(nc, n, nullptr, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
     hipLaunchKernelGGL(k_zero_u64, dim3(kWsCounters / 256), dim3(256), 0, st, w.box.tests, (int64_t)kWsCounters);
     const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
-    hipLaunchKernelGGL(k_box, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
-                       (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
-                       w.box);
+    if (keys)
+        hipLaunchKernelGGL(k_box<true>, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
+                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
+                           w.box);
+    else
+        hipLaunchKernelGGL(k_box<false>, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
+                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
+                           w.box);
     NN_HIP(hipGetLastError());
     return MREP_OK;
 }
@@ -1618,7 +1628,7 @@ int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_
     // grouping writes nothing for invalid ids when the outputs are null
     const Outs none{nullptr, nullptr, nullptr, nullptr};
     w.box.xb = nullptr;
-    int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st);
+    int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st, true);
     if (rc) return rc;
     hipLaunchKernelGGL(k_feat_write, dim3(blocks_for(n, 128)), dim3(128), 0, st, dev_view(geom->g), curve_id, q_xyz,
                        (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.box.cand, seg_out, x_out);
@@ -1691,7 +1701,7 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
     const DevGeom G = dev_view(geom->g);
     const float tie = (float)opts->tie_rel;
     if (!nn) w.box.xb = nullptr;
-    rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st);
+    rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st, nn != nullptr);
     if (rc) return rc;
     if (timed && (rc = stage_mark(1, st))) return rc;
     if (nn) {
