@@ -67,6 +67,36 @@ def _span_traffic():
     return {k: v.get("hbm_bytes_per_launch") for k, v in rec.get("workloads", {}).items()}
 
 
+# the sources each headline kernel is built from (its file and the headers it includes)
+KERNEL_SOURCES = {
+    "k_box": ["mrep_nn.hip", "mrep_refine.h", "mrep_dev.h", "mrep_internal.h", "mrep.h"],
+    "k_pairs": ["mrep_device.hip", "mrep_refine.h", "mrep_dev.h", "mrep_internal.h", "mrep.h"],
+    "k_finish": ["mrep_device.hip", "mrep_refine.h", "mrep_dev.h", "mrep_internal.h", "mrep.h"],
+}
+
+
+def sources_hash(names):
+    h = hashlib.sha256()
+    for name in names:
+        d = "include" if name == "mrep.h" else os.path.join("paper_2504_11498_amd", "csrc")
+        h.update(name.encode())
+        with open(os.path.join(ROOT, d, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _lattice_traffic():
+    """HBM bytes per launch of the lattice headline's kernels (k_box, k_pairs, k_finish of the sphere-strategy
+    call) from committed rocprofv3 counter runs, for each kernel whose sources have not changed since."""
+    path = os.path.join(ROOT, "profiles", "lattice_struts_traffic.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    return {k: v.get("hbm_bytes_per_launch") for k, v in rec.get("kernels", {}).items()
+            if k in KERNEL_SOURCES and v.get("sources_sha256_16") == sources_hash(KERNEL_SOURCES[k])}
+
+
 def summarize_rocprof(path):
     """Per-kernel duration summary (calls, mean/min/max microseconds, total ms) of a rocprofv3 SQLite result."""
     import sqlite3
@@ -153,6 +183,39 @@ def _say(tag, msg):
     print(f"[{tag} {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def host_points(curves, qs):
+    """The query points C(t0) + offset on the host, evaluated by scipy's B-spline routine (neither the oracle nor
+    the library under test), so that the GPU and the oracle's sample see the same inputs."""
+    from scipy.interpolate import BSpline
+
+    cid = np.asarray(qs.curve_id)
+    order = np.argsort(cid, kind="stable")
+    bounds = np.searchsorted(cid[order], np.arange(curves.n + 1))
+    out = np.empty((cid.shape[0], 3))
+    for c in np.nonzero(np.diff(bounds))[0]:
+        idx = order[bounds[c]:bounds[c + 1]]
+        p, P, U = curves.curve(int(c))
+        out[idx] = BSpline(U, P, p)(qs.t0[idx])
+    return np.ascontiguousarray(out + qs.offset)
+
+
+def host_surface_points(S, Q):
+    """Surface query points S(u0, v0) + offset on the host, by scipy's tensor-product B-spline routine."""
+    from scipy.interpolate import NdBSpline
+
+    sid = np.asarray(Q["surface_id"])
+    out = np.empty((sid.shape[0], 3))
+    for k in range(S.n):
+        idx = np.nonzero(sid == k)[0]
+        if idx.size == 0:
+            continue
+        P = S.cp[S.cp_off[k]:S.cp_off[k + 1]].reshape(int(S.n_u[k]), int(S.n_v[k]), 3)
+        ku = S.ku[S.ku_off[k]:S.ku_off[k + 1]]
+        kv = S.kv[S.kv_off[k]:S.kv_off[k + 1]]
+        out[idx] = NdBSpline((ku, kv), P, (int(S.deg_u[k]), int(S.deg_v[k])))(Q["uv0"][idx])
+    return np.ascontiguousarray(out + Q["offset"])
+
+
 def device_decomposition(args, dev, curves):
     """Decompose the batch on the device (Sec. 5.2.1-5.2.2 by kernels) and, unless --no-host-decompose, on the
     host too: the host time, the device time (decomposition, then the table build of mrep_upload; inputs already
@@ -221,7 +284,8 @@ def lattice_headline(args, dev):
     geom, n_seg, n_pieces = dec.pop("geom"), dec.pop("n_seg"), dec.pop("n_pieces")
     qs = gen.offset_queries(105, curves, counts=gen.proportional_counts(n_seg, 256 * n_curves))
     cid = torch.from_numpy(qs.curve_id).to(dev)
-    q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
+    q_host = host_points(curves, qs)
+    q = torch.from_numpy(q_host).to(dev)
     n = q.shape[0]
     # work units of the screen: every (query, piece of its curve, sample)
     samples = 32 * int(np.sum(n_seg[qs.curve_id].astype(np.int64)))
@@ -232,7 +296,9 @@ def lattice_headline(args, dev):
 
     # the plain method: the autotuner's strategy on this batch
     strat, ms_screen, ms_spheres, _ = geom.tune(q, cid)
-    _say("lattice", f"{n} queries; tuner: screen {ms_screen:.2f} ms, spheres {ms_spheres:.2f} ms")
+    lanes, persistent, sched_ms = geom.schedule()
+    _say("lattice", f"{n} queries; tuner: screen {ms_screen:.2f} ms, spheres {ms_spheres:.2f} ms (box kernel "
+                    f"{lanes} lanes per query, {'persistent' if persistent else 'tile map'})")
     topts = mrep.default_opts("bf16", time_stages=True, tuned=True)
     tws = torch.empty(geom.workspace_bytes(n, topts), dtype=torch.uint8, device=dev)
     outs = outs_like()
@@ -263,7 +329,8 @@ def lattice_headline(args, dev):
     _say("lattice", f"plain ({['screen', 'spheres'][strat]}) {ms:.2f} ms per call")
     strategy = ["screen", "spheres"][strat]
     if strat == mrep.STRATEGY_SPHERES:
-        stage_ms = {"group_candidates": float(stage[0]), "pair_refine": float(stage[3]), "finish": float(stage[4])}
+        stage_ms = {"group": float(stage[0]), "candidates_k_box": float(stage[1]), "pair_refine": float(stage[4]),
+                    "finish": float(stage[5])}
     else:
         stage_ms = {"group": float(stage[0]), "screen": float(stage[1]), "pair_refine": float(stage[2]),
                     "finish": float(stage[3])}
@@ -312,6 +379,9 @@ def lattice_headline(args, dev):
             "tol_rel": 1e-6,
             "strategy": strategy,
             "tune_ms": {"screen": ms_screen, "spheres": ms_spheres},
+            "box_schedule": {"lanes_per_query": lanes, "persistent": bool(persistent),
+                             "tune_ms": {f"{4 << (k % 3)} lanes, {'persistent' if k >= 3 else 'tile map'}": m
+                                         for k, m in enumerate(sched_ms)}},
             "decomposition": dec,
             "stage_ms": stage_ms,
             "candidate_pairs": pairs,
@@ -327,14 +397,14 @@ def lattice_headline(args, dev):
     roofs = {"k_pairs": pairs_roofline(pairs, stage_ms["pair_refine"]),
              "k_finish": finish_roofline(n, pairs, coef_bytes, stage_ms["finish"])}
     if strat == mrep.STRATEGY_SPHERES:
-        # the box kernel: the grouping-and-candidates stage minus the grouping stage of the screen call on the
-        # same queries (the same grouping kernels)
-        box_ms = stage_ms["group_candidates"] - float(st_s[0])
-        roofs["k_box"] = box_roofline(tests, box_ms)
-        stage_ms["candidates_k_box"] = box_ms
+        roofs["k_box"] = box_roofline(tests, stage_ms["candidates_k_box"])
         result["config"]["sphere_tests"] = tests
     else:
         roofs["k_screen_bf16"] = screen_block["roofline"]
+    traffic = _lattice_traffic() if strat == mrep.STRATEGY_SPHERES else {}
+    for k, r in roofs.items():
+        if k in traffic and r is not None:
+            r["traffic"] = traffic[k]
     kernel_ms = {k: (r or {}).get("time_ms", 0.0) for k, r in roofs.items()}
     dominant = max(kernel_ms, key=kernel_ms.get)
     result["roofline"] = roofs.pop(dominant)
@@ -377,14 +447,14 @@ def lattice_headline(args, dev):
             res[name] = {
                 "value": n / (ms2 / 1e3), "unit": "projections/s", "ms_per_step": ms2,
                 "vs_plain_value": ms / ms2,
-                "stage_ms": {"group_candidates": float(st2[0]), "network": float(st2[1]),
-                             "seed_certify": float(st2[2]), "pair_refine": float(st2[3]), "finish": float(st2[4])},
+                "stage_ms": {"group": float(st2[0]), "candidates": float(st2[1]), "network": float(st2[2]),
+                             "seed_certify": float(st2[3]), "pair_refine": float(st2[4]), "finish": float(st2[5])},
                 "fallback_frac": float(np.mean((f2 & mrep.F_NN_FALLBACK) != 0)),
                 "vs_plain_max_dist_rel": float(((so[1] - outs[1]).abs() / diag).max().item()),
             }
             if name == "nn":
                 seeded_outs = so
-                res[name]["roofline_mlp"] = mlp_roofline(4 * n, float(st2[1]))
+                res[name]["roofline_mlp"] = mlp_roofline(4 * n, float(st2[2]))
             _say("lattice", f"seeded {name}: {ms2:.2f} ms per call, fallback {res[name]['fallback_frac']:.3f}")
         del ews
         res["training"] = {"curves": int(tr_curves.n), **tstats, "epochs": 10, "batch": 4096,
@@ -397,7 +467,7 @@ def lattice_headline(args, dev):
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"], result["parity_on_sample"] = lattice_cpu_baseline(
-            curves, qs, q, outs, seeded_outs, souts, args.cpu_seconds)
+            curves, qs, q_host, outs, seeded_outs, souts, args.cpu_seconds)
     return result
 
 
@@ -458,7 +528,7 @@ def mlp_roofline(rows, ms):
             "frac": a / BF16_PEAK_TFLOPS, "rows": int(rows), "per_unit": "37,120 flop per (query, candidate) row"}
 
 
-def lattice_cpu_baseline(curves, qs, q_dev, outs, seeded_outs, screen_outs, seconds):
+def lattice_cpu_baseline(curves, qs, q_all, outs, seeded_outs, screen_outs, seconds):
     """The FP64 oracle on a bounded random sample of the headline queries (its throughput on this host), and
     the parity of the benchmarked outputs (plain, seeded, screen) on that sample."""
     sys.path.insert(0, ROOT)
@@ -467,7 +537,6 @@ def lattice_cpu_baseline(curves, qs, q_dev, outs, seeded_outs, screen_outs, seco
     oracle.build(force=False)
     rng = np.random.default_rng(7)
     n = qs.n
-    q_all = q_dev.cpu().numpy()
     order = rng.permutation(n)
     pilot = np.sort(order[:256])
     t0 = time.perf_counter()
@@ -514,7 +583,8 @@ def batched_curves_block(args, dev):
     geom = plan.upload(dev)
     seg_counts = np.diff(plan.seg_off())
     cid = torch.from_numpy(qs.curve_id).to(dev)
-    q = (geom.eval(cid, torch.from_numpy(qs.t0).to(dev)) + torch.from_numpy(qs.offset).to(dev)).contiguous()
+    q_host = host_points(curves, qs)
+    q = torch.from_numpy(q_host).to(dev)
     n = qs.n
     opts = mrep.default_opts("bf16", time_stages=True)
     outs = (torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
@@ -554,7 +624,7 @@ def batched_curves_block(args, dev):
     if not args.no_seeded:
         res["seeded"] = seeded_variants(geom, q, cid, outs, curves, res["value"], args)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(curves, qs, outs, min(args.cpu_seconds, 8.0))
+        res["cpu_baseline"] = cpu_baseline(curves, qs, q_host, outs, min(args.cpu_seconds, 8.0))
     return res
 
 
@@ -787,8 +857,8 @@ def seeded_variants(geom, q, cid, plain_outs, curves, plain_value, args):
             "value": n / (ms / 1e3),
             "ms_per_step": ms,
             "speedup_vs_plain": (n / (ms / 1e3)) / plain_value,
-            "stage_ms": {"group_candidates": float(stage[0]), "network": float(stage[1]),
-                         "seed_certify": float(stage[2]), "pair_refine": float(stage[3]), "finish": float(stage[4])},
+            "stage_ms": {"group": float(stage[0]), "candidates": float(stage[1]), "network": float(stage[2]),
+                         "seed_certify": float(stage[3]), "pair_refine": float(stage[4]), "finish": float(stage[5])},
             "fallback_frac": float(np.mean((flags & mrep.F_NN_FALLBACK) != 0)),
             "vs_plain_max_dist_rel": dd,
             "vs_plain_t_over_1e-7": int((dt > 1e-7).sum().item()),
@@ -814,7 +884,8 @@ def surfaces_bench(args, dev):
     decompose_s = time.perf_counter() - t0
     geom = plan.upload(dev)
     sid = torch.from_numpy(Q["surface_id"]).to(dev)
-    q = (geom.eval_surfaces(sid, torch.from_numpy(Q["uv0"]).to(dev)) + torch.from_numpy(Q["offset"]).to(dev)).contiguous()
+    q_host = host_surface_points(S, Q)
+    q = torch.from_numpy(q_host).to(dev)
     n = q.shape[0]
     opts = mrep.default_opts(time_stages=True)
     outs = (torch.empty((n, 2), dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
@@ -889,7 +960,7 @@ def surfaces_bench(args, dev):
         oracle.build(force=False)
         rng = np.random.default_rng(8)
         pick = np.sort(rng.choice(n, 2000, replace=False))
-        qs = q.cpu().numpy()[pick]
+        qs = q_host[pick]
         t0 = time.perf_counter()
         r = oracle.surf_project(S, Q["surface_id"][pick], qs)
         dt = time.perf_counter() - t0
@@ -912,7 +983,7 @@ def surfaces_bench(args, dev):
     return res
 
 
-def cpu_baseline(curves, qs, outs, seconds):
+def cpu_baseline(curves, qs, q_all, outs, seconds):
     """The FP64 oracle timed on this host on a bounded random sample of the same queries."""
     sys.path.insert(0, ROOT)
     import oracle
@@ -920,13 +991,10 @@ def cpu_baseline(curves, qs, outs, seconds):
     oracle.build(force=False)
     rng = np.random.default_rng(7)
     order = rng.permutation(qs.n)
-    q_all = None
 
     def run(idx):
-        nonlocal q_all
-        pts = oracle.eval_batch(curves, qs.curve_id[idx], qs.t0[idx]) + qs.offset[idx]
         t0 = time.perf_counter()
-        r = oracle.project(curves, qs.curve_id[idx], pts)
+        r = oracle.project(curves, qs.curve_id[idx], q_all[idx])
         return r, time.perf_counter() - t0
 
     pilot = np.sort(order[:1024])

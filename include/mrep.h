@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MREP_ABI_VERSION 9
+#define MREP_ABI_VERSION 10
 
 /* status codes */
 #define MREP_OK 0
@@ -124,7 +124,8 @@ typedef struct {
 #define MREP_OPT_CLIP 0x4
 #define MREP_STRATEGY_SCREEN 0  /* BF16 MFMA screen, certified candidates, refine */
 #define MREP_STRATEGY_SPHERES 1 /* sphere lists (span clusters where compact), refine every listed piece */
-#define MREP_N_STAGES 5 /* most stages any call records (see mrep_last_stage_times) */
+#define MREP_N_BOX_SCHEDULES 6  /* schedules of the sphere-list kernel: s = 3 * persistent + log2(lanes / 4) */
+#define MREP_N_STAGES 6 /* most stages any call records (see mrep_last_stage_times) */
 
 /* ---------------------------------------------------------------------- */
 /* Decomposition (host, FP64)                                              */
@@ -370,11 +371,16 @@ int32_t mrep_span_bezier_curves(int32_t n_curves, int64_t n_intervals, int32_t m
  * and two timed runs each, HIP events on `stream`), keeps the faster one for
  * this geometry (used by calls with MREP_OPT_TUNED), and leaves its answers in
  * the outputs.  Both strategies return the certified global minimum; they
- * differ in speed, by how compact the curves are against their boxes.
- * workspace: mrep_workspace_bytes with MREP_OPT_TUNED.  strategy_out (HOST,
- * nullable): the choice; ms_out (HOST double[2], nullable): per-call times of
- * the screen and sphere strategies.  Synchronous.  Errors: as
- * mrep_project_curves. */
+ * differ in speed, by how compact the curves are against their boxes.  The
+ * sphere strategy is timed in each of the MREP_N_BOX_SCHEDULES schedules of
+ * its sphere-list kernel (4, 8 or 16 lanes per query; one workgroup per tile
+ * of 32 queries in XCD-aware order, or a persistent grid that takes tiles
+ * from one queue per XCD and then from the others'), and the fastest schedule
+ * is kept for the geometry too (mrep_curve_schedule); the schedules give
+ * identical answers.  workspace: mrep_workspace_bytes with MREP_OPT_TUNED.
+ * strategy_out (HOST, nullable): the choice; ms_out (HOST double[2],
+ * nullable): per-call times of the screen strategy and of the sphere strategy
+ * in its best schedule.  Synchronous.  Errors: as mrep_project_curves. */
 int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, const int32_t* curve_id,
                          const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out, double* dist_out,
                          int32_t* seg_out, uint32_t* flags_out, int32_t* strategy_out, double* ms_out, void* stream);
@@ -383,15 +389,30 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
  * for a caller that knows its workload.  Errors: MREP_E_INVALID_ARG. */
 int32_t mrep_set_curve_strategy(mrep_geom* geom, int32_t strategy);
 
+/* The schedule of the sphere-list kernel for this geometry (used by the sphere
+ * strategy and the seeded calls): lanes_out (HOST) 4, 8 or 16 lanes per
+ * query, persistent_out (HOST) 1 for the persistent grid over per-XCD tile
+ * queues, 0 for one workgroup per tile; ms_out (HOST double
+ * [MREP_N_BOX_SCHEDULES], nullable): the per-call times of the sphere
+ * strategy in each schedule at the last mrep_tune_curves (index 3 * persistent
+ * + log2(lanes / 4); zeros before any tune).  The default is 8 lanes, tile
+ * map.  Errors: MREP_E_INVALID_ARG (null or surface geometry, null outputs). */
+int32_t mrep_curve_schedule(const mrep_geom* geom, int32_t* lanes_out, int32_t* persistent_out, double* ms_out);
+
+/* Set that schedule directly.  lanes: 4, 8 or 16; persistent: 0 or 1.  The
+ * answers do not depend on it.  Errors: MREP_E_INVALID_ARG. */
+int32_t mrep_set_curve_schedule(mrep_geom* geom, int32_t lanes, int32_t persistent);
+
 /* Durations in milliseconds of the stages of the last call on the calling
  * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 4
  * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine of the
  * candidate (query, piece) pairs (0 in FP64 mode), [3] top-2 + FP64 polish +
  * write, with the full scan of overflowed queries (every query in FP64 mode).
- * mrep_project_curves_seeded: 5 stages, [0] grouping + sphere candidates,
- * [1] network scoring (0 without a network), [2] seed + certificate (0
- * without a network), [3] refine of the listed pairs of the undecided queries,
- * [4] their top-2 + FP64 polish + write and the full scan of overflows.
+ * mrep_project_curves_seeded (and mrep_project_curves in the sphere
+ * strategy): 6 stages, [0] grouping, [1] sphere candidates (the box kernel),
+ * [2] network scoring (0 without a network), [3] seed + certificate (0
+ * without a network), [4] refine of the listed pairs of the undecided queries,
+ * [5] their top-2 + FP64 polish + write and the full scan of overflows.
  * mrep_project_surfaces / invert: 3 stages, [0] grouping + sphere lists,
  * [1] sampled bounds + gate + patch minima, [2] top-2 + FP64 polish + write.
  * mrep_project_surfaces_seeded: 4 stages, [0] grouping + sphere lists +

@@ -165,11 +165,20 @@ struct mrep_plan {
 struct mrep_geom {
     int kind = MREP_GEOM_CURVES;
     int strategy = MREP_STRATEGY_SCREEN;  // chosen by mrep_tune_curves
+    int box_lanes = 8;                    // schedule of the sphere-list kernel: lanes per query (4, 8, 16)
+    int box_persist = 0;                  // 1: persistent grid over per-XCD tile queues, 0: tile map
+    double box_ms[MREP_N_BOX_SCHEDULES] = {};  // the last tune's time of each schedule (ms)
     mrep::Geom g;
     mrep::SurfGeom sg;
 };
 
 namespace mrep {
+// schedule s of the sphere-list kernel: 4 << (s % 3) lanes per query, persistent grid when s >= 3
+inline void box_schedule(int s, int* lanes, int* persist)
+{
+    *lanes = 4 << (s % 3);
+    *persist = s / 3;
+}
 // the seeded / sphere-pruned curve projection (nn == NULL: sphere-pruned)
 int seeded_core(const char* fn, const mrep_geom* geom, const mrep_nn* nn, const mrep_opts* opts, int64_t n,
                 const int32_t* curve_id, const double* q_xyz, void* workspace, int64_t ws_bytes, double* t_out,

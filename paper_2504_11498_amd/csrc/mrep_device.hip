@@ -1110,8 +1110,11 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    double ms[2] = {0.0, 0.0};
-    for (int strat = 0; strat < 2 && rc == MREP_OK; ++strat) {
+    // runs 0..MREP_N_BOX_SCHEDULES-1: the sphere strategy in each schedule; the last: the screen
+    double tms[MREP_N_BOX_SCHEDULES + 1] = {};
+    for (int run = 0; run <= MREP_N_BOX_SCHEDULES && rc == MREP_OK; ++run) {
+        const int strat = run < MREP_N_BOX_SCHEDULES ? MREP_STRATEGY_SPHERES : MREP_STRATEGY_SCREEN;
+        if (strat == MREP_STRATEGY_SPHERES) box_schedule(run, &geom->box_lanes, &geom->box_persist);
         for (int it = 0; it < 3 && rc == MREP_OK; ++it) {
             if (it == 1) rc = hipEventRecord(e0, st) == hipSuccess ? MREP_OK : MREP_E_HIP;
             if (rc == MREP_OK)
@@ -1124,16 +1127,23 @@ int32_t mrep_tune_curves(mrep_geom* geom, const mrep_opts* opts, int64_t n, cons
             set_error("mrep_tune_curves: event timing failed");
             rc = MREP_E_HIP;
         }
-        ms[strat] = 0.5 * (double)t;
+        tms[run] = 0.5 * (double)t;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
+    int best = 0;
+    for (int s = 0; s < MREP_N_BOX_SCHEDULES; ++s) {
+        geom->box_ms[s] = tms[s];
+        if (tms[s] < tms[best]) best = s;
+    }
+    box_schedule(best, &geom->box_lanes, &geom->box_persist);
+    const double ms[2] = {tms[MREP_N_BOX_SCHEDULES], tms[best]};
     geom->strategy = ms[MREP_STRATEGY_SPHERES] < ms[MREP_STRATEGY_SCREEN] ? MREP_STRATEGY_SPHERES : MREP_STRATEGY_SCREEN;
-    // leave the chosen strategy's answers in the outputs
-    if (geom->strategy == MREP_STRATEGY_SCREEN &&
+    // leave the chosen strategy's answers in the outputs (the screen ran last)
+    if (geom->strategy == MREP_STRATEGY_SPHERES &&
         (rc = run_project(geom, &o2, n, curve_id, q_xyz, workspace, ws_bytes, t_out, dist_out, seg_out, flags_out,
-                          stream, 0, MREP_STRATEGY_SCREEN)))
+                          stream, 0, MREP_STRATEGY_SPHERES)))
         return rc;
     HIP_OK(hipStreamSynchronize(st));
     if (strategy_out) *strategy_out = geom->strategy;
@@ -1149,6 +1159,31 @@ int32_t mrep_set_curve_strategy(mrep_geom* geom, int32_t strategy)
         return MREP_E_INVALID_ARG;
     }
     geom->strategy = strategy;
+    return MREP_OK;
+}
+
+int32_t mrep_curve_schedule(const mrep_geom* geom, int32_t* lanes_out, int32_t* persistent_out, double* ms_out)
+{
+    if (!geom || geom->kind != MREP_GEOM_CURVES || !lanes_out || !persistent_out) {
+        set_error("mrep_curve_schedule: null or surface geometry, or null outputs");
+        return MREP_E_INVALID_ARG;
+    }
+    *lanes_out = geom->box_lanes;
+    *persistent_out = geom->box_persist;
+    if (ms_out)
+        for (int s = 0; s < MREP_N_BOX_SCHEDULES; ++s) ms_out[s] = geom->box_ms[s];
+    return MREP_OK;
+}
+
+int32_t mrep_set_curve_schedule(mrep_geom* geom, int32_t lanes, int32_t persistent)
+{
+    if (!geom || geom->kind != MREP_GEOM_CURVES || (lanes != 4 && lanes != 8 && lanes != 16) ||
+        (persistent != 0 && persistent != 1)) {
+        set_error("mrep_set_curve_schedule: null or surface geometry, lanes not 4, 8 or 16, or persistent not 0/1");
+        return MREP_E_INVALID_ARG;
+    }
+    geom->box_lanes = lanes;
+    geom->box_persist = persistent;
     return MREP_OK;
 }
 

@@ -45,6 +45,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -667,25 +668,33 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
 //      LDS, pieces read from global memory);
 //   b. the clusters whose lower bound reaches it plus the tie margin;
 //   c. over their pieces: UB = the smallest upper bound and the K pieces with
-//      the smallest lower bounds (ties to the lower index);
-//   d. the list of every piece whose lower bound reaches UB + margin(UB).
-// Other curves: the same UB, K nearest and list from two passes over all the
+//      the smallest lower bounds (ties to the lower index), and every piece
+//      whose lower bound reaches the running UB + margin (a superset of the
+//      list, since UB only falls);
+//   d. the list: those of them whose lower bound reaches UB + margin(UB) (a
+//      second pass over the clusters' pieces when the superset overflows).
+// The lanes of a query load all of their pieces of a cluster at once, so the
+// loads' latencies overlap.  Other curves: the same UB, K nearest and list from two passes over all the
 // curve's piece spheres staged in LDS.  Bounds carry a rounding allowance of 1e-6 (|q'| + diag).  More than
 // kBoxCluCap clusters or kBoxCap pieces: the query takes the full scan.
+//
+// Schedules (chosen per geometry by the autotuner): L = 4, 8 or 16 lanes per
+// query (workgroups of 32 L threads), and either one workgroup per tile in
+// XCD-aware order (tile map) or a persistent grid that takes tiles from one
+// queue per XCD and, once its own is empty, from the others.  Every schedule
+// gives the same bounds, keys and lists in the same order.
 // ---------------------------------------------------------------------------
-constexpr int kBoxSub = 8;
-constexpr int kBoxThreads = kQueriesPerTile * kBoxSub;
 constexpr int kBoxChunk = 768;   // cluster or piece spheres staged per round (LDS for 6 workgroups per CU)
 constexpr int kBoxCluCap = 64;   // candidate clusters per query
 constexpr int kBoxCap = 64;      // listed pieces per query; more: the query goes to the full scan
 constexpr int kXcds = 8;
-static_assert(kBoxThreads == 256, "box kernel: 32 queries x 8 lanes");
 
 struct BoxOut {
     int32_t* cand;  // [n][kK] global piece index (-1: fewer pieces)
     uint16_t* xb;   // [n][kK][16] BF16 network inputs of the candidates (null: not written)
     ScreenOut so;   // per query: the pieces whose lower bound reaches UB + margin; so.ub = UB
     unsigned long long* tests;  // [kWsCounters] sphere tests, per workgroup slot modulo kWsCounters (zeroed)
+    int32_t* queue;             // [kXcds] next tile of each XCD's range (persistent schedules; zeroed)
 };
 
 // float -> uint32 with the same order (negative values included), and back
@@ -704,11 +713,12 @@ __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b)
     a = lo;
     b = hi;
 }
-// merge the 8 lanes' sorted lists of kK keys: exchange, keep the smaller half (bitonic)
+// merge the L lanes' sorted lists of kK keys: exchange, keep the smaller half (bitonic)
+template <int L>
 __device__ __forceinline__ void merge_keys(uint64_t* key)
 {
 #pragma unroll
-    for (int off = 1; off < kBoxSub; off <<= 1) {
+    for (int off = 1; off < L; off <<= 1) {
         uint64_t o[kK];
 #pragma unroll
         for (int k = 0; k < kK; ++k) o[k] = __shfl_xor(key[k], off, 64);
@@ -727,11 +737,18 @@ __device__ __forceinline__ void insert_key(uint64_t* key, uint64_t x)
         for (int k = 0; k < kK; ++k) cswap(key[k], x);
     }
 }
-__device__ __forceinline__ float min8(float v)
+template <int L>
+__device__ __forceinline__ float min_lanes(float v)
 {
 #pragma unroll
-    for (int off = 1; off < kBoxSub; off <<= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    for (int off = 1; off < L; off <<= 1) v = fminf(v, __shfl_xor(v, off, 64));
     return v;
+}
+// the hits of the L lanes of this lane's query, bit i = lane i of the query
+template <int L>
+__device__ __forceinline__ uint32_t group_hits(bool hit, int lane)
+{
+    return (uint32_t)(__ballot(hit) >> (lane & (64 - L))) & (uint32_t)((1ull << L) - 1ull);
 }
 
 __device__ __forceinline__ float tie_margin(float d, const DCurve& cv, float tie_rel)
@@ -739,30 +756,50 @@ __device__ __forceinline__ float tie_margin(float d, const DCurve& cv, float tie
     return 2.f * (float)cv.tol_eff + 4e-6f * (d + (float)cv.diag) + tie_rel * (float)cv.diag;
 }
 
+template <int T>
 __device__ __forceinline__ void stage_clusters(const DevGeom& G, const DCurve& cv, int c0, int cn, float4* st)
 {
     __syncthreads();
-    for (int i = threadIdx.x; i < cn; i += kBoxThreads) st[i] = G.csph[cv.clu_off + c0 + i];
+    for (int i = threadIdx.x; i < cn; i += T) st[i] = G.csph[cv.clu_off + c0 + i];
     __syncthreads();
 }
 
-// kKeys: also find the K pieces with the smallest lower bounds (the network's
-// candidates); the sphere-pruned call needs only the bound and the list.
-template <bool kKeys>
-__global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* __restrict__ tile_off,
-                                                     const int32_t* __restrict__ q_off,
-                                                     const int32_t* __restrict__ perm, const double* __restrict__ qxyz,
-                                                     float tie_rel, BoxOut out)
+// The pieces of cluster cl that lane `sub` of a query visits (k = cl*kCluPieces
+// + sub + r*L), loaded together so that their latencies overlap; ok[r] marks
+// the ones inside the curve.
+template <int L>
+__device__ __forceinline__ void load_cluster(const DevGeom& G, const DCurve& cv, int cl, int sub, float4* p, bool* ok)
 {
-    __shared__ float4 s_st[kBoxChunk];
-    __shared__ uint16_t s_clu[kQueriesPerTile][kBoxCluCap];  // a curve using clusters has < 65536
-    __shared__ int32_t s_list[kQueriesPerTile][kBoxCap];
-    __shared__ int32_t s_base[kQueriesPerTile];
-    const int n_tiles = tile_off[G.n_curves];
-    const int per = (n_tiles + kXcds - 1) / kXcds;
-    const int slot = (int)(blockIdx.x / kXcds);
-    const int tile = (int)(blockIdx.x % kXcds) * per + slot;
-    if (slot >= per || tile >= n_tiles) return;
+    static_assert(kCluPieces % L == 0, "whole pieces per lane and cluster");
+#pragma unroll
+    for (int r = 0; r < kCluPieces / L; ++r) {
+        const int k = cl * kCluPieces + sub + r * L;
+        ok[r] = cl >= 0 && k < cv.n_seg;
+        p[r] = ok[r] ? G.sph[cv.seg_off + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+struct BoxShared {
+    float4 st[kBoxChunk];
+    uint16_t clu[kQueriesPerTile][kBoxCluCap];  // a curve using clusters has < 65536
+    int32_t list[kQueriesPerTile][kBoxCap];
+    int32_t base[kQueriesPerTile];
+    int32_t next;
+};
+
+// One tile of kQueriesPerTile queries of one curve, L lanes per query.  kKeys:
+// also find the K pieces with the smallest lower bounds (the network's
+// candidates); the sphere-pruned call needs only the bound and the list.
+template <bool kKeys, int L>
+__device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32_t* __restrict__ tile_off,
+                                         const int32_t* __restrict__ q_off, const int32_t* __restrict__ perm,
+                                         const double* __restrict__ qxyz, float tie_rel, const BoxOut& out,
+                                         BoxShared& sh)
+{
+    constexpr int T = kQueriesPerTile * L;  // threads
+    constexpr int kPer = kCluPieces / L;    // pieces of a cluster per lane
+    static_assert(L >= kK && L <= 16 && (L & (L - 1)) == 0, "4, 8 or 16 lanes per query");
+    float4* const s_st = sh.st;
     int lo_c = 0, hi_c = G.n_curves;  // tile_off[lo_c] <= tile < tile_off[hi_c]
     while (hi_c - lo_c > 1) {
         const int mid = (lo_c + hi_c) >> 1;
@@ -771,7 +808,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
     const int c = lo_c;
     const DCurve cv = G.curves[c];
     const int lane = threadIdx.x & 63;
-    const int qs = threadIdx.x / kBoxSub, sub = threadIdx.x % kBoxSub;
+    const int qs = threadIdx.x / L, sub = threadIdx.x % L;
     const int64_t j = (int64_t)q_off[c] + (int64_t)(tile - tile_off[c]) * kQueriesPerTile + qs;
     const bool active = j < q_off[c + 1];
     const int32_t qi = active ? perm[j] : 0;
@@ -781,9 +818,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         for (int k = 0; k < 3; ++k) ql[k] = (float)(qxyz[3 * (int64_t)qi + k] - cv.origin[k]);
     }
     const float eps = 1e-6f * (sqrtf(ql[0] * ql[0] + ql[1] * ql[1] + ql[2] * ql[2]) + (float)cv.diag);
+    // the raw hardware square root (<= 1 ulp) is inside the allowance eps
     auto dist = [&](const float4& p) {
         const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-        return sqrtf(dx * dx + dy * dy + dz * dz);
+        return __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
     };
     float ub = INFINITY;
     uint64_t key[kK];
@@ -795,9 +833,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         for (int k = 0; k < kK; ++k) key[k] = ~0ull;
         for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
             const int cn = min(kBoxChunk, cv.n_clu - c0);
-            stage_clusters(G, cv, c0, cn, s_st);
+            stage_clusters<T>(G, cv, c0, cn, s_st);
             if (!active) continue;
-            for (int i = sub; i < cn; i += kBoxSub) {
+            for (int i = sub; i < cn; i += L) {
                 const float4 p = s_st[i];
                 const float d = dist(p);
                 ub = fminf(ub, d + p.w + eps);
@@ -805,29 +843,38 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                 ++nt;
             }
         }
-        merge_keys(key);
+        merge_keys<L>(key);
         if (active) {
+            // at most 16 loads in flight per lane
+            constexpr int kA = kPer * kK <= 16 ? kK : 16 / kPer;
+            static_assert(kK % kA == 0, "whole batches of clusters");
 #pragma unroll
-            for (int m = 0; m < kK; ++m) {
-                if (key[m] == ~0ull) continue;
-                const int k0 = (int)(uint32_t)key[m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
-                for (int k = k0 + sub; k < k1; k += kBoxSub) {
-                    const float4 p = G.sph[cv.seg_off + k];
-                    ub = fminf(ub, dist(p) + p.w + eps);
-                    ++nt;
-                }
+            for (int m0 = 0; m0 < kK; m0 += kA) {
+                float4 p[kA][kPer];
+                bool ok[kA][kPer];
+#pragma unroll
+                for (int m = 0; m < kA; ++m)
+                    load_cluster<L>(G, cv, key[m0 + m] == ~0ull ? -1 : (int)(uint32_t)key[m0 + m], sub, p[m], ok[m]);
+#pragma unroll
+                for (int m = 0; m < kA; ++m)
+#pragma unroll
+                    for (int r = 0; r < kPer; ++r)
+                        if (ok[m][r]) {
+                            ub = fminf(ub, dist(p[m][r]) + p[m][r].w + eps);
+                            ++nt;
+                        }
             }
         }
-        ub = min8(ub);
+        ub = min_lanes<L>(ub);
         // b. candidate clusters
         const float thr0 = ub + tie_margin(ub, cv, tie_rel);
         int ncl = 0;  // same value in the query's 8 lanes
         for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
             const int cn = min(kBoxChunk, cv.n_clu - c0);
-            stage_clusters(G, cv, c0, cn, s_st);
+            stage_clusters<T>(G, cv, c0, cn, s_st);
             if (!active) continue;
-            // the 8 lanes of a query run the same trip count: the ballot below sees all of them
-            for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
+            // the L lanes of a query run the same trip count: the ballot below sees all of them
+            for (int i0 = 0; i0 < cn; i0 += L) {
                 const int i = i0 + sub;
                 bool hit = false;
                 if (i < cn) {
@@ -835,46 +882,86 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                     hit = dist(p) - p.w - eps <= thr0;
                     ++nt;
                 }
-                const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                const uint32_t grp = group_hits<L>(hit, lane);
                 const int pos = ncl + __popc(grp & ((1u << sub) - 1u));
-                if (hit && pos < kBoxCluCap) s_clu[qs][pos] = (uint16_t)(c0 + i);
+                if (hit && pos < kBoxCluCap) sh.clu[qs][pos] = (uint16_t)(c0 + i);
                 ncl += __popc(grp);
             }
         }
-        // c. UB and the K nearest-bound pieces over the candidate clusters
+        // c. UB and the K nearest-bound pieces over the candidate clusters, and
+        // every piece whose lower bound reaches the running UB + margin (UB
+        // only falls, so this holds the final list)
         const bool clus_ok = ncl <= kBoxCluCap;
 #pragma unroll
         for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+        int pre = 0;  // pieces kept so far (same value in the query's 8 lanes)
         if (active && clus_ok) {
             for (int m = 0; m < ncl; ++m) {
-                const int k0 = s_clu[qs][m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
-                for (int k = k0 + sub; k < k1; k += kBoxSub) {
-                    const float4 p = G.sph[cv.seg_off + k];
-                    const float d = dist(p), re = p.w + eps;
-                    ub = fminf(ub, d + re);
-                    if constexpr (kKeys) insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)k);
-                    ++nt;
+                const int cl = sh.clu[qs][m];
+                float4 p[kPer];
+                bool ok[kPer];
+                load_cluster<L>(G, cv, cl, sub, p, ok);
+                float lbv[kPer];
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const float d = dist(p[r]), re = p[r].w + eps;
+                    lbv[r] = d - p[r].w - eps;
+                    if (ok[r]) {
+                        ub = fminf(ub, d + re);
+                        if constexpr (kKeys)
+                            insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(cl * kCluPieces + sub + r * L));
+                        ++nt;
+                    }
+                }
+                ub = min_lanes<L>(ub);
+                const float thr_run = ub + tie_margin(ub, cv, tie_rel);
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const bool hit = ok[r] && lbv[r] <= thr_run;
+                    const uint32_t grp = group_hits<L>(hit, lane);
+                    const int pos = pre + __popc(grp & ((1u << sub) - 1u));
+                    if (hit && pos < kBoxCap) sh.list[qs][pos] = cl * kCluPieces + sub + r * L;
+                    pre += __popc(grp);
                 }
             }
         }
-        ub = min8(ub);
-        if constexpr (kKeys) merge_keys(key);
-        // d. the list
+        ub = min_lanes<L>(ub);
+        if constexpr (kKeys) merge_keys<L>(key);
+        // d. the list: the kept pieces whose lower bound reaches the final UB +
+        // margin, in visiting order; if more than kBoxCap were kept, a second
+        // pass over the candidate clusters
         const float thr = ub + tie_margin(ub, cv, tie_rel);
-        if (active && clus_ok) {
+        if (active && clus_ok && pre <= kBoxCap) {
+            for (int i0 = 0; i0 < pre; i0 += L) {
+                const int i = i0 + sub;
+                bool hit = false;
+                int k = 0;
+                if (i < pre) {
+                    k = sh.list[qs][i];
+                    const float4 p = G.sph[cv.seg_off + k];
+                    hit = dist(p) - p.w - eps <= thr;
+                    ++nt;
+                }
+                // every lane has read its entry before any is overwritten: the
+                // write position is below i0 + L
+                const uint32_t grp = group_hits<L>(hit, lane);
+                const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                if (hit) sh.list[qs][pos] = k;
+                cnt += __popc(grp);
+            }
+        } else if (active && clus_ok) {
             for (int m = 0; m < ncl; ++m) {
-                const int k0 = s_clu[qs][m] * kCluPieces, k1 = min(cv.n_seg, k0 + kCluPieces);
-                for (int i0 = k0; i0 < k1; i0 += kBoxSub) {
-                    const int k = i0 + sub;
-                    bool hit = false;
-                    if (k < k1) {
-                        const float4 p = G.sph[cv.seg_off + k];
-                        hit = dist(p) - p.w - eps <= thr;
-                        ++nt;
-                    }
-                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                const int cl = sh.clu[qs][m];
+                float4 p[kPer];
+                bool ok[kPer];
+                load_cluster<L>(G, cv, cl, sub, p, ok);
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const bool hit = ok[r] && dist(p[r]) - p[r].w - eps <= thr;
+                    nt += ok[r];
+                    const uint32_t grp = group_hits<L>(hit, lane);
                     const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-                    if (hit && pos < kBoxCap) s_list[qs][pos] = k;
+                    if (hit && pos < kBoxCap) sh.list[qs][pos] = cl * kCluPieces + sub + r * L;
                     cnt += __popc(grp);
                 }
             }
@@ -891,11 +978,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
             for (int c0 = 0; c0 < cv.n_seg; c0 += kBoxChunk) {
                 const int cn = min(kBoxChunk, cv.n_seg - c0);
                 __syncthreads();
-                for (int i = threadIdx.x; i < cn; i += kBoxThreads) s_st[i] = G.sph[cv.seg_off + c0 + i];
+                for (int i = threadIdx.x; i < cn; i += T) s_st[i] = G.sph[cv.seg_off + c0 + i];
                 __syncthreads();
                 if (!active) continue;
                 if (pass == 0) {
-                    for (int i = sub; i < cn; i += kBoxSub) {
+                    for (int i = sub; i < cn; i += L) {
                         const float4 p = s_st[i];
                         const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
                         const float d2 = dx * dx + dy * dy + dz * dz;
@@ -906,7 +993,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                         const bool c4 = kKeys && (key[kK - 1] == ~0ull || (t4 > 0.f && d2 < t4 * t4));
                         const bool cu = tu > 0.f && d2 < tu * tu;
                         if (c4 || cu) {
-                            const float d = sqrtf(d2);
+                            const float d = __builtin_amdgcn_sqrtf(d2);
                             ub = fminf(ub, d + re);
                             uint64_t x = ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(c0 + i);
 #pragma unroll
@@ -914,8 +1001,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                         }
                     }
                 } else {
-                    // the 8 lanes of a query run the same trip count: the ballot sees all of them
-                    for (int i0 = 0; i0 < cn; i0 += kBoxSub) {
+                    // the L lanes of a query run the same trip count: the ballot sees all of them
+                    for (int i0 = 0; i0 < cn; i0 += L) {
                         const int i = i0 + sub;
                         bool hit = false;
                         if (i < cn) {
@@ -925,16 +1012,16 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
                             hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
                             ++nt;
                         }
-                        const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                        const uint32_t grp = group_hits<L>(hit, lane);
                         const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-                        if (hit && pos < kBoxCap) s_list[qs][pos] = c0 + i;
+                        if (hit && pos < kBoxCap) sh.list[qs][pos] = c0 + i;
                         cnt += __popc(grp);
                     }
                 }
             }
             if (pass == 0) {
-                merge_keys(key);
-                ub = min8(ub);
+                merge_keys<L>(key);
+                ub = min_lanes<L>(ub);
                 thr = ub + tie_margin(ub, cv, tie_rel);
             }
         }
@@ -948,21 +1035,21 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
     }
     // reserve the workgroup's pairs with one atomic
     const bool listed = active && cnt <= kBoxCap;
-    if (sub == 0) s_base[qs] = listed ? cnt : 0;
+    if (sub == 0) sh.base[qs] = listed ? cnt : 0;
     __syncthreads();
     if (threadIdx.x == 0) {
         int tot = 0;
         for (int k = 0; k < kQueriesPerTile; ++k) {
-            const int v = s_base[k];
-            s_base[k] = tot;
+            const int v = sh.base[k];
+            sh.base[k] = tot;
             tot += v;
         }
         const int base = tot > 0 ? atomicAdd(out.so.pair_count, tot) : 0;
-        for (int k = 0; k < kQueriesPerTile; ++k) s_base[k] += base;
+        for (int k = 0; k < kQueriesPerTile; ++k) sh.base[k] += base;
     }
     __syncthreads();
     if (!active) return;
-    const int64_t b = s_base[qs];
+    const int64_t b = sh.base[qs];
     const bool fits = listed && b + cnt <= out.so.pair_cap;
     if (sub == 0) {
         out.so.cand_n[j] = fits ? cnt : -1;
@@ -975,9 +1062,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         }
     }
     if (listed) {
-        for (int k = sub; k < cnt; k += kBoxSub) {
+        for (int k = sub; k < cnt; k += L) {
             if (b + k >= out.so.pair_cap) break;
-            out.so.pair_seg[b + k] = fits ? (int32_t)(cv.seg_off + s_list[qs][k]) : 0;
+            out.so.pair_seg[b + k] = fits ? (int32_t)(cv.seg_off + sh.list[qs][k]) : 0;
             out.so.pair_j[b + k] = fits ? (int32_t)j : -1;  // a slot past the capacity stays unused
         }
     }
@@ -1000,6 +1087,41 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(DevGeom G, const int32_t* _
         uint4* dst = reinterpret_cast<uint4*>(out.xb + (j * kK + sub) * 16);
         dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
         dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+}
+
+template <bool kKeys, int L, bool kPersist>
+__global__ __launch_bounds__(kQueriesPerTile * L) void k_box(DevGeom G, const int32_t* __restrict__ tile_off,
+                                                             const int32_t* __restrict__ q_off,
+                                                             const int32_t* __restrict__ perm,
+                                                             const double* __restrict__ qxyz, float tie_rel, BoxOut out)
+{
+    __shared__ BoxShared sh;
+    const int n_tiles = tile_off[G.n_curves];
+    const int per = (n_tiles + kXcds - 1) / kXcds;  // tiles of each XCD's contiguous range
+    if constexpr (!kPersist) {
+        // workgroups are dispatched to the XCDs in turn: workgroup b runs on XCD b % kXcds
+        const int slot = (int)(blockIdx.x / kXcds);
+        const int tile = (int)(blockIdx.x % kXcds) * per + slot;
+        if (slot >= per || tile >= n_tiles) return;
+        box_tile<kKeys, L>(G, tile, tile_off, q_off, perm, qxyz, tie_rel, out, sh);
+    } else {
+        // the next tile of this XCD's range, then of the others in turn; every
+        // workgroup leaves once all kXcds queues are past their ranges
+        int x = (int)(blockIdx.x % kXcds);
+        for (int hop = 0; hop < kXcds;) {
+            __syncthreads();  // the previous tile is done with sh
+            if (threadIdx.x == 0) sh.next = atomicAdd(&out.queue[x], 1);
+            __syncthreads();
+            const int t = sh.next;
+            const int tile = x * per + t;
+            if (t >= per || tile >= n_tiles) {
+                ++hop;
+                x = (x + 1) % kXcds;
+                continue;
+            }
+            box_tile<kKeys, L>(G, tile, tile_off, q_off, perm, qxyz, tie_rel, out, sh);
+        }
     }
 }
 
@@ -1298,12 +1420,14 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
     const int64_t oov = take(4 * n), oc = take(4 * n * kK), oxb = take(32 * n * kK), ocn = take(4 * n);
     const int64_t opo = take(4 * n), oub = take(4 * n), ops = take(4 * cap), opj = take(4 * cap);
     const int64_t opr = take((int64_t)sizeof(PairRes) * cap), osc = take(8 * n * kK), odn = take(n);
+    const int64_t oqu = take(4 * kXcds);
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
         w->ovf_count = w->hist + nc;  // zeroed by the grouping, like the pair counter after it
         w->box.cand = (int32_t*)(base + oc);
         w->box.tests = (unsigned long long*)(base + otc);
+        w->box.queue = (int32_t*)(base + oqu);
         w->box.xb = (uint16_t*)(base + oxb);
         w->box.so.cand_n = (int32_t*)(base + ocn);
         w->box.so.pair_off = (int32_t*)(base + opo);
@@ -1345,28 +1469,76 @@ static int pack_image(const mrep_nn* nn, hipStream_t st)
 }
 
 // grouping + sphere candidates shared by the seeded call and the feature export
-__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n)
+__global__ void k_zero_counters(unsigned long long* __restrict__ p, int64_t n, int32_t* __restrict__ queue)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+    if (i < kXcds) queue[i] = 0;
+}
+
+constexpr int kMaxDevices = 64;
+
+// one schedule of the box kernel; a persistent grid holds as many workgroups
+// as the device keeps resident at once (the occupancy is queried once per
+// device and schedule)
+template <bool kKeys, int L, bool kPersist>
+static hipError_t launch_box_t(const mrep_geom* geom, int64_t tiles, const SeedWork& w, const double* q_xyz,
+                               float tie_rel, hipStream_t st)
+{
+    constexpr int T = kQueriesPerTile * L;
+    int64_t grid = tiles;
+    if (kPersist) {
+        static std::atomic<int> cap[kMaxDevices];  // resident workgroups of the device (0: not queried yet)
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        int c = cap[dev].load(std::memory_order_relaxed);
+        if (c == 0) {
+            int cus = 0, per_cu = 0;
+            if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_box<kKeys, L, kPersist>, T, 0)) !=
+                hipSuccess)
+                return e;
+            c = std::max(1, cus) * std::max(1, per_cu);
+            cap[dev].store(c, std::memory_order_relaxed);
+        }
+        grid = std::min<int64_t>(tiles, c);
+    }
+    hipLaunchKernelGGL((k_box<kKeys, L, kPersist>), dim3((unsigned)grid), dim3(T), 0, st, dev_view(geom->g),
+                       (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
+                       w.box);
+    return hipGetLastError();
+}
+
+template <bool kKeys>
+static hipError_t launch_box(const mrep_geom* geom, int64_t tiles, const SeedWork& w, const double* q_xyz,
+                             float tie_rel, hipStream_t st)
+{
+    const bool p = geom->box_persist != 0;
+    switch (geom->box_lanes) {
+    case 4: return p ? launch_box_t<kKeys, 4, true>(geom, tiles, w, q_xyz, tie_rel, st)
+                     : launch_box_t<kKeys, 4, false>(geom, tiles, w, q_xyz, tie_rel, st);
+    case 16: return p ? launch_box_t<kKeys, 16, true>(geom, tiles, w, q_xyz, tie_rel, st)
+                      : launch_box_t<kKeys, 16, false>(geom, tiles, w, q_xyz, tie_rel, st);
+    default: return p ? launch_box_t<kKeys, 8, true>(geom, tiles, w, q_xyz, tie_rel, st)
+                      : launch_box_t<kKeys, 8, false>(geom, tiles, w, q_xyz, tie_rel, st);
+    }
 }
 
 static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id, const double* q_xyz, float tie_rel,
-                      SeedWork& w, const Outs& o, hipStream_t st, bool keys)
+                      SeedWork& w, const Outs& o, hipStream_t st, bool keys, bool timed)
 {
     const int64_t nc = geom->g.L.n_curves;
     NN_HIP(launch_grouping(nc, n, nullptr, curve_id, w.hist, w.q_off, w.tile_off, w.perm, o, st));
-    hipLaunchKernelGGL(k_zero_u64, dim3(kWsCounters / 256), dim3(256), 0, st, w.box.tests, (int64_t)kWsCounters);
+    int rc;
+    if (timed && (rc = stage_mark(1, st))) return rc;
+    hipLaunchKernelGGL(k_zero_counters, dim3(kWsCounters / 256), dim3(256), 0, st, w.box.tests, (int64_t)kWsCounters,
+                       w.box.queue);
+    // an upper bound of the tile count (tiles of a curve: ceil(its queries / kQueriesPerTile)), plus one per XCD
     const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
-    if (keys)
-        hipLaunchKernelGGL(k_box<true>, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
-                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
-                           w.box);
-    else
-        hipLaunchKernelGGL(k_box<false>, dim3((unsigned)tiles), dim3(kBoxThreads), 0, st, dev_view(geom->g),
-                           (const int32_t*)w.tile_off, (const int32_t*)w.q_off, (const int32_t*)w.perm, q_xyz, tie_rel,
-                           w.box);
-    NN_HIP(hipGetLastError());
+    NN_HIP(keys ? launch_box<true>(geom, tiles, w, q_xyz, tie_rel, st)
+                : launch_box<false>(geom, tiles, w, q_xyz, tie_rel, st));
     return MREP_OK;
 }
 
@@ -1628,7 +1800,7 @@ int32_t mrep_nn_features(const mrep_geom* geom, int64_t n, const int32_t* curve_
     // grouping writes nothing for invalid ids when the outputs are null
     const Outs none{nullptr, nullptr, nullptr, nullptr};
     w.box.xb = nullptr;
-    int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st, true);
+    int rc = candidates(geom, n, curve_id, q_xyz, 2e-6f, w, none, st, true, false);
     if (rc) return rc;
     hipLaunchKernelGGL(k_feat_write, dim3(blocks_for(n, 128)), dim3(128), 0, st, dev_view(geom->g), curve_id, q_xyz,
                        (const int32_t*)w.q_off, (const int32_t*)w.perm, (const int32_t*)w.box.cand, seg_out, x_out);
@@ -1701,9 +1873,9 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
     const DevGeom G = dev_view(geom->g);
     const float tie = (float)opts->tie_rel;
     if (!nn) w.box.xb = nullptr;
-    rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st, nn != nullptr);
+    rc = candidates(geom, n, curve_id, q_xyz, tie, w, o, st, nn != nullptr, timed);
     if (rc) return rc;
-    if (timed && (rc = stage_mark(1, st))) return rc;
+    if (timed && (rc = stage_mark(2, st))) return rc;
     if (nn) {
         rc = pack_image(nn, st);
         if (rc) return rc;
@@ -1712,7 +1884,7 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
         hipLaunchKernelGGL(k_mlp<RowsFromCandidates>, dim3(nb), dim3(256), 0, st, rows, (const uint8_t*)nn->img());
         NN_HIP(hipGetLastError());
     }
-    if (timed && (rc = stage_mark(2, st))) return rc;
+    if (timed && (rc = stage_mark(3, st))) return rc;
     if (nn) {
         if (G.general)
             hipLaunchKernelGGL((k_decide<true>), dim3(blocks_for(n, 128)), dim3(128), 0, st, G, curve_id, q_xyz,
@@ -1724,13 +1896,13 @@ int mrep::seeded_core(const char* fn_, const mrep_geom* geom, const mrep_nn* nn,
                                (int32_t)invert, w.done, o);
         NN_HIP(hipGetLastError());
     }
-    if (timed && (rc = stage_mark(3, st))) return rc;
+    if (timed && (rc = stage_mark(4, st))) return rc;
     NN_HIP(launch_refine(G, n, curve_id, q_xyz, w.q_off, w.perm, w.box.so, w.pair_res, nn ? w.done : nullptr,
                          nn ? (uint32_t)MREP_F_NN_FALLBACK : 0u, opts->tie_rel, invert, w.ovf_list, w.ovf_count, o, st,
-                         (opts->flags & MREP_OPT_CLIP) != 0, timed ? 4 : -1));
+                         (opts->flags & MREP_OPT_CLIP) != 0, timed ? 5 : -1));
     if (timed) {
-        if ((rc = stage_mark(5, st))) return rc;
-        stage_end(5);
+        if ((rc = stage_mark(6, st))) return rc;
+        stage_end(6);
     }
     return MREP_OK;
 }

@@ -30,7 +30,8 @@ PREC_FP64, PREC_BF16 = 0, 3
 OPT_TIME_STAGES, OPT_TUNED, OPT_CLIP = 1, 2, 4
 STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
 ROOTS_FERRARI, ROOTS_NEWTON = 0, 1
-N_STAGES = 5
+N_STAGES = 6
+N_BOX_SCHEDULES = 6  # sphere-list kernel schedules: index 3 * persistent + log2(lanes / 4)
 MAX_DEGREE = 32  # curves
 POWER_MAX_DEGREE = 15  # spans kept in power form up to here, as Bezier points above
 MAX_SURFACE_DEGREE = 15
@@ -81,6 +82,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 _invert = _sig("mrep_invert_curves", _i32, _vp, C.POINTER(Opts), _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp)
 _eval = _sig("mrep_eval_curves", _i32, _vp, _i64, _vp, _vp, _vp, _vp)
 _set_strategy = _sig("mrep_set_curve_strategy", _i32, _vp, _i32)
+_schedule = _sig("mrep_curve_schedule", _i32, _vp, _vp, _vp, _vp)
+_set_schedule = _sig("mrep_set_curve_schedule", _i32, _vp, _i32, _i32)
 _split = _sig("mrep_monotonic_split", _i32, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp)
 _span_layout = _sig("mrep_span_layout", _i32, _i32, _pi32, _pi64, _pi64, _pi64, _pi64)
 _span_bezier = _sig("mrep_span_bezier_curves", _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
@@ -135,7 +138,7 @@ EXPORTS = ["mrep_decompose_curves", "mrep_decompose_curves_device", "mrep_plan_i
            "mrep_decompose_surfaces", "mrep_plan_export_surfaces", "mrep_surface_workspace_bytes",
            "mrep_project_surfaces", "mrep_invert_surfaces", "mrep_eval_surfaces",
            "mrep_surface_seeded_workspace_bytes", "mrep_nn_surface_features", "mrep_project_surfaces_seeded",
-           "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_monotonic_split", "mrep_span_layout",
+           "mrep_tune_curves", "mrep_set_curve_strategy", "mrep_curve_schedule", "mrep_set_curve_schedule", "mrep_monotonic_split", "mrep_span_layout",
            "mrep_span_bezier_curves", "mrep_project_curves_noalloc", "mrep_decompose_curves_rational",
            "mrep_workspace_counts", "mrep_nn_set_compute"]
 
@@ -382,8 +385,8 @@ def default_opts(precision: str | int = "bf16", max_candidates: int = 32, tie_re
 def last_stage_times():
     """Stage milliseconds of the last call made with time_stages=True on this thread.
 
-    mrep_project_curves: [grouping, screen, pair refine, finish]; seeded call: [grouping + sphere candidates,
-    network, seed + certificate, pair refine, finish]."""
+    mrep_project_curves: [grouping, screen, pair refine, finish]; seeded call (and the sphere strategy): [grouping,
+    sphere candidates, network, seed + certificate, pair refine, finish]."""
     out = np.zeros(N_STAGES)
     rc = _stage_times(_p(out, C.c_double), N_STAGES)
     if rc <= 0:
@@ -518,6 +521,18 @@ class Geometry:
     def set_strategy(self, strategy: int):
         """The strategy of calls with default_opts(tuned=True): STRATEGY_SCREEN or STRATEGY_SPHERES."""
         _check(_set_strategy(self._h, int(strategy)), "mrep_set_curve_strategy")
+
+    def schedule(self):
+        """mrep_curve_schedule: (lanes per query, persistent, per-schedule ms of the last tune) of the sphere-list
+        kernel."""
+        lanes, pers = C.c_int32(), C.c_int32()
+        ms = (C.c_double * N_BOX_SCHEDULES)()
+        _check(_schedule(self._h, C.byref(lanes), C.byref(pers), ms), "mrep_curve_schedule")
+        return int(lanes.value), int(pers.value), [float(x) for x in ms]
+
+    def set_schedule(self, lanes: int, persistent: int):
+        """mrep_set_curve_schedule: 4, 8 or 16 lanes per query; persistent 0 (tile map) or 1 (per-XCD queues)."""
+        _check(_set_schedule(self._h, int(lanes), int(persistent)), "mrep_set_curve_schedule")
 
     def seeded_workspace_bytes(self, n: int, opts: Opts) -> int:
         b = C.c_int64()

@@ -86,6 +86,84 @@ def test_lattice_seeded_and_pruned(mrep, lattice, which):
     _say(f"[ok] {st} fallback={np.mean((out['flags'] & mrep.F_NN_FALLBACK) != 0):.4f}")
 
 
+@pytest.fixture(scope="module")
+def trained_struts(mrep):
+    """A curve network trained on 128 held-out struts (other seeds than the evaluation set)."""
+    from paper_2504_11498_amd import seeding
+
+    _say("[setup] training set: 128 held-out struts x 512 queries")
+    tc = gen.curves_lattice_geometry(65, n_curves=128)
+    tq = gen.offset_queries(165, tc, per_curve=512)
+    q = tq.materialise(lambda cid, t: oracle.eval_batch(tc, cid, t))
+    plan = mrep.decompose_curves(tc, 1e-6)
+    geom = plan.upload()
+    x, u, a, stats = seeding.training_pairs(plan, geom, q, tq.curve_id, seed=0)
+    _say(f"[setup] {stats}")
+    net = mrep.Network(seed=7)
+    losses = seeding.train(net, x, u, a, epochs=10, batch=1024, lr=1e-3, seed=0)
+    _say(f"[setup] loss first {losses[:20].mean():.4f} last {losses[-20:].mean():.4f} ({len(losses)} steps)")
+    return net, losses, stats
+
+
+def test_lattice_seeded_trained(mrep, lattice, trained_struts):
+    """The network trained on held-out struts: its loss falls, the seeded call gives the oracle's answers on
+    the sample, and its seeds are accepted more often than an untrained network's (what the seed gains)."""
+    curves, qs, q, geom, sub, ref, dec = lattice
+    net, losses, stats = trained_struts
+    assert stats["label_in_candidates"] > 0.5
+    assert losses[-20:].mean() < 0.8 * losses[:20].mean()
+    qt = torch.from_numpy(np.ascontiguousarray(q[sub])).cuda()
+    ct = torch.from_numpy(np.ascontiguousarray(qs.curve_id[sub])).cuda()
+    fb = {}
+    for name, nn in (("trained", net), ("untrained", mrep.Network(seed=3))):
+        _say(f"[case] lattice seeded, {name} network, 3000-query sample")
+        out = _out(*geom.project_seeded(qt, ct, nn, mrep.default_opts("bf16")))
+        st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label=f"lattice/{name}")
+        fb[name] = float(np.mean((out["flags"] & mrep.F_NN_FALLBACK) != 0))
+        _say(f"[ok] {st} fallback={fb[name]:.4f}")
+    assert fb["trained"] < fb["untrained"], fb
+
+
+def test_box_schedules_identical(mrep, lattice):
+    """The sphere-list kernel's schedules (4, 8, 16 lanes per query; tile map or persistent per-XCD queues) give
+    bit-identical answers: the sphere strategy on all queries, the seeded call (which also exports the network's
+    candidate pieces) on the sample, and the exported features."""
+    curves, qs, q, geom, sub, ref, dec = lattice
+    qt = torch.from_numpy(q).cuda()
+    ct = torch.from_numpy(qs.curve_id).cuda()
+    qs_t = torch.from_numpy(np.ascontiguousarray(q[sub])).cuda()
+    cs_t = torch.from_numpy(np.ascontiguousarray(qs.curve_id[sub])).cuda()
+    net = mrep.Network(seed=3)
+    geom.set_strategy(mrep.STRATEGY_SPHERES)
+    first = None
+    try:
+        for lanes in (4, 8, 16):
+            for pers in (0, 1):
+                _say(f"[case] box schedule lanes={lanes} persistent={pers}")
+                geom.set_schedule(lanes, pers)
+                assert geom.schedule()[:2] == (lanes, pers)
+                plain = _out(*geom.project(qt, ct, mrep.default_opts("bf16", tuned=True)))
+                seeded = _out(*geom.project_seeded(qs_t, cs_t, net, mrep.default_opts("bf16")))
+                seg, x = geom.features(qs_t, cs_t)
+                torch.cuda.synchronize()
+                got = (plain, seeded, seg.cpu().numpy(), x.cpu().numpy())
+                if first is None:
+                    first = got
+                    compare(curves, qs.curve_id[sub], q[sub], {k: v[sub] for k, v in plain.items()}, ref, dec,
+                            label="lattice/schedule")
+                    continue
+                for a, b in ((first[0], got[0]), (first[1], got[1])):
+                    for k in ("t", "dist", "seg", "flags"):
+                        np.testing.assert_array_equal(a[k], b[k], err_msg=f"lanes={lanes} persistent={pers} {k}")
+                np.testing.assert_array_equal(first[2], got[2])
+                np.testing.assert_array_equal(first[3], got[3])
+        with pytest.raises(mrep.MrepError):
+            geom.set_schedule(5, 0)
+    finally:
+        geom.set_schedule(8, 0)
+        geom.set_strategy(mrep.STRATEGY_SCREEN)
+
+
 def test_lattice_autotuner(mrep, lattice):
     """mrep_tune_curves times both strategies on the batch; on these compact struts the sphere strategy is the
     faster one.  The tuned projection and inversion then run it, with the oracle's answers on the sample."""
@@ -94,8 +172,12 @@ def test_lattice_autotuner(mrep, lattice):
     qt = torch.from_numpy(q).cuda()
     ct = torch.from_numpy(qs.curve_id).cuda()
     strat, ms_screen, ms_spheres, outs = geom.tune(qt, ct)
-    _say(f"[info] strategy {strat}, screen {ms_screen:.3f} ms, spheres {ms_spheres:.3f} ms")
+    lanes, pers, sched_ms = geom.schedule()
+    _say(f"[info] strategy {strat}, screen {ms_screen:.3f} ms, spheres {ms_spheres:.3f} ms; box schedule "
+         f"lanes={lanes} persistent={pers}, per schedule {sched_ms}")
     assert strat == mrep.STRATEGY_SPHERES and ms_spheres < ms_screen
+    assert lanes in (4, 8, 16) and pers in (0, 1) and all(m > 0 for m in sched_ms)
+    assert ms_spheres == min(sched_ms)
     tuned = _out(*outs)
     compare(curves, qs.curve_id[sub], q[sub], {k: v[sub] for k, v in tuned.items()}, ref, dec, label="lattice/tuned")
     again = _out(*geom.project(qt, ct, mrep.default_opts("bf16", tuned=True)))

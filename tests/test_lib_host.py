@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     lib = C.CDLL(mrep.LIB_PATH)
     for name in declared:
         assert hasattr(lib, name), name
-    assert mrep.abi_version() == 9
+    assert mrep.abi_version() == 10
 
 
 def test_rebasement_matrix_matches_printed_T5():
