@@ -404,6 +404,10 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
     double cur_v = v, cur_d = INFINITY, cur_k = 1.0, cur_sp = 0.0;
     bool cur_c = false;
     int hop = 0, it = 0;
+    bool last = false;  // the step just taken was below 1e-12: this evaluation ends the span
+    // the coordinates' scale: the evaluation rounds at about 1e-16 of it, so a
+    // step that moves the point by less than 1e-15 of it is rounding noise
+    const double scale = fmax(fabs(q[0]), fmax(fabs(q[1]), fabs(q[2]))) + cv.diag;
     for (int guard = 0; guard < 64; ++guard) {
         double r[3], d1[3], d2[3];
         span_eval_cv<kGen>(cv, span_coef(G, cv, span), v, q, r, d1, d2);
@@ -424,15 +428,22 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
             cur_k = (sp > 0.0 && stationary) ? fp / sp : 1.0;
             cur_sp = sp;
         }
-        bool done_span = !(fp > 0.0) || it >= 12;
+        bool done_span = !(fp > 0.0) || it >= 12 || last;
         if (!done_span) {
             const double vn = fmin(fmax(v - f / fp, 0.0), 1.0);
-            done_span = fabs(vn - v) <= 1e-15;
-            v = vn;
-            ++it;
-            if (!done_span) continue;
-            // converged: the last step's point is evaluated once more only when it moved
-            if (vn != cur_v) continue;
+            const double step = fabs(vn - v);
+            // Converged: a step that moves the point by less than the rounding
+            // noise ends the span at the evaluated point; a step below 1e-12 of
+            // the span is taken and evaluated once more (Newton's next error is
+            // about its square).  A fixed 1e-15 in v lies below the noise on short
+            // spans far from the origin, where Newton then ran to its cap.
+            done_span = step * sqrt(sp) <= 1e-15 * scale;
+            if (!done_span) {
+                last = step <= 1e-12;
+                v = vn;
+                ++it;
+                continue;
+            }
         }
         // this span is done: keep it if it went lower (always for the first span)
         if (hop > 0 && !(cur_d < best_d)) break;
@@ -443,6 +454,7 @@ __device__ __forceinline__ void polish(const DevGeom& G, const DCurve& cv, int32
         else break;
         ++hop;
         it = 0;
+        last = false;
         cur_d = INFINITY;
     }
     const double ta = G.spant[2 * best_span], tb = G.spant[2 * best_span + 1];
