@@ -38,6 +38,11 @@ struct Cubic {
         d2.y = (T)2 * a2.y + u * (T)6 * a3.y;
         d2.z = (T)2 * a2.z + u * (T)6 * a3.z;
     }
+    __device__ T size() const
+    {
+        return fabs(a0.x) + fabs(a0.y) + fabs(a0.z) + fabs(a1.x) + fabs(a1.y) + fabs(a1.z) + fabs(a2.x) + fabs(a2.y) +
+               fabs(a2.z) + fabs(a3.x) + fabs(a3.y) + fabs(a3.z);
+    }
     __device__ T dist2(T u) const
     {
         T x = a0.x + u * (a1.x + u * (a2.x + u * a3.x));
@@ -91,6 +96,21 @@ struct Newt<double> {
     static constexpr double stat = 1e-12;
 };
 
+// unit roundoff of the refine precision
+template <typename T>
+struct Eps;
+template <>
+struct Eps<float> {
+    static constexpr double v = 5.97e-8;  // 2^-24
+};
+template <>
+struct Eps<double> {
+    static constexpr double v = 1.12e-16;  // 2^-53
+};
+
+template <typename T>
+__device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
+
 // kappa = f'/|C'|^2 at a bracket end where f = r.C' vanishes to rounding (a
 // stationary minimiser that lies on the end, e.g. on a piece joint); 1 at an
 // end the distance leaves with a slope (the end conditions the minimum)
@@ -143,8 +163,17 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
         T d = dot(r, r);
         u_best = u;
         d_best = d;
-        if (dlo < d_best) { u_best = lo; d_best = dlo; kappa = klo; }
-        if (dhi < d_best) { u_best = hi; d_best = dhi; kappa = khi; }
+        // a bracket end replaces the stationary point only when it is lower by
+        // more than the rounding of the squared distances (about 8 eps S |r|,
+        // S the coefficients' size): within that, the end is only rounding
+        // lower, and taking it moved an interior minimum a few 1e-5 from a piece
+        // end onto the end (a parameter error the FP64 polish never saw).  S, the
+        // sum of the coefficients' absolute components, bounds |C - q| and each
+        // of its terms on [0, 1].
+        const T S = C.size();
+        const T nz = (T)(16.0 * Eps<T>::v) * S * (sqrt(d) + S);
+        if (dlo < d_best - nz) { u_best = lo; d_best = dlo; kappa = klo; }
+        if (dhi < d_best - nz) { u_best = hi; d_best = dhi; kappa = khi; }
         if (loc) *loc = true;
         return;
     }
@@ -162,9 +191,6 @@ __device__ __forceinline__ T sample_u(int k)
 {
     return k == kSamples - 1 ? (T)1 : (T)k / (T)(kSamples - 1);
 }
-
-template <typename T>
-__device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
 
 // parameters of a piece closer than this are one minimum, not two
 constexpr float kDistinctU = 1e-4f;
@@ -476,20 +502,9 @@ struct Cand {
 };
 constexpr int32_t kSecond = 4;
 
-template <typename T>
-struct Eps;
-template <>
-struct Eps<float> {
-    static constexpr double v = 5.97e-8;  // 2^-24
-};
-template <>
-struct Eps<double> {
-    static constexpr double v = 1.12e-16;  // 2^-53
-};
-
 // Bound on the parameter error the refine precision leaves at u: rounding of
 // the terms of f = r.C' (magnitude <= scale * |C'|) moves the root by about
-// 8 eps scale / (|C'| kappa) in u.
+// 8 eps scale / (|C'| kappa) in u; an unconverged solve adds |f| / f'.
 template <typename T>
 __device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
 {
@@ -499,7 +514,13 @@ __device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
     const double scale = sqrt((double)dot(C.a0, C.a0)) + sqrt((double)dot(C.a1, C.a1)) +
                          sqrt((double)dot(C.a2, C.a2)) + sqrt((double)dot(C.a3, C.a3));
     const double kap = fabs((double)k);
-    return (sp > 0.0 && kap > 0.0) ? 8.0 * Eps<T>::v * scale / (sp * kap) * (tb - ta) : 1.0;
+    if (!(sp > 0.0 && kap > 0.0)) return 1.0;
+    double e = 8.0 * Eps<T>::v * scale / (sp * kap);
+    // at an interior point, plus the Newton correction that is left (|f| / f'):
+    // a solve that ended on its iteration cap or after bisection steps is
+    // farther from the root than the rounding alone (a piece end is exact)
+    if (u > (T)0 && u < (T)1) e += fabs((double)dot(r, d1)) / (kap * sp * sp);
+    return e * (tb - ta);
 }
 
 // x is the joint it shares with candidate y's piece, and y is that piece's

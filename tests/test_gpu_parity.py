@@ -78,14 +78,21 @@ def test_batched_subset(batched, precision):
     _say(f"[ok] {st} fullscan={np.mean((out['flags'] & 0x20) != 0):.4f}")
 
 
+# queries of this workload whose FP32 refine once stopped short of the root
+# (an interior Newton solve that ended 2e-5 from it in the piece parameter, left
+# unpolished because the parameter-error bound counted rounding only)
+HARD_BATCHED = [685508, 1041146, 572588]
+
+
 def test_batched_full_size_sampled(batched):
-    """All 1,048,576 queries in the bench launch configuration; 2000 sampled outputs checked."""
+    """All 1,048,576 queries in the bench launch configuration; 100,000 sampled outputs checked, with the
+    queries of HARD_BATCHED among them."""
     curves, qs, q, plan, geom, sub, ref, dec = batched
     _say("[case] batched curves, full 1M queries, bf16")
     out = _run(geom, q, qs.curve_id, "bf16")
     assert np.all(np.isfinite(out["dist"])) and np.all(out["seg"] >= 0)
     rng = np.random.default_rng(11)
-    pick = np.sort(rng.choice(qs.n, 2000, replace=False))
+    pick = np.unique(np.concatenate([rng.choice(qs.n, 100_000, replace=False), HARD_BATCHED]))
     r = oracle.project(curves, qs.curve_id[pick], q[pick])
     sample = {k: v[pick] for k, v in out.items()}
     st = compare(curves, qs.curve_id[pick], q[pick], sample, r, dec, label="batched/full")
