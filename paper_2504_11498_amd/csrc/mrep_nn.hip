@@ -664,8 +664,8 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
 // theirs.  One workgroup per tile of kQueriesPerTile queries of one curve, 8
 // lanes per query.  Curves whose clusters are compact (clu_use):
 //   a. a first bound: the best cluster upper bound and the piece upper bounds
-//      of the kK clusters with the smallest lower bounds (clusters staged in
-//      LDS, pieces read from global memory);
+//      of the cluster with the smallest lower bound (clusters staged in LDS,
+//      pieces read from global memory);
 //   b. the clusters whose lower bound reaches it plus the tie margin;
 //   c. over their pieces: UB = the smallest upper bound and the K pieces with
 //      the smallest lower bounds (ties to the lower index), and every piece
@@ -828,9 +828,9 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
     int cnt = 0;  // pieces listed (same value in the query's 8 lanes)
     uint32_t nt = 0;  // sphere tests of this lane (the algorithmic work the bench reports)
     if (cv.clu_use) {
-        // a. first bound
-#pragma unroll
-        for (int k = 0; k < kK; ++k) key[k] = ~0ull;
+        // a. first bound: the best cluster upper bound, sharpened by the pieces
+        // of the cluster with the smallest lower bound
+        uint64_t near = ~0ull;  // (lower bound, cluster) of this lane's nearest-bound cluster
         for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
             const int cn = min(kBoxChunk, cv.n_clu - c0);
             stage_clusters<T>(G, cv, c0, cn, s_st);
@@ -839,31 +839,22 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 const float4 p = s_st[i];
                 const float d = dist(p);
                 ub = fminf(ub, d + p.w + eps);
-                insert_key(key, ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i));
+                near = min(near, ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i));
                 ++nt;
             }
         }
-        merge_keys<L>(key);
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) near = min(near, (uint64_t)__shfl_xor(near, off, 64));
         if (active) {
-            // at most 16 loads in flight per lane
-            constexpr int kA = kPer * kK <= 16 ? kK : 16 / kPer;
-            static_assert(kK % kA == 0, "whole batches of clusters");
+            float4 p[kPer];
+            bool ok[kPer];
+            load_cluster<L>(G, cv, near == ~0ull ? -1 : (int)(uint32_t)near, sub, p, ok);
 #pragma unroll
-            for (int m0 = 0; m0 < kK; m0 += kA) {
-                float4 p[kA][kPer];
-                bool ok[kA][kPer];
-#pragma unroll
-                for (int m = 0; m < kA; ++m)
-                    load_cluster<L>(G, cv, key[m0 + m] == ~0ull ? -1 : (int)(uint32_t)key[m0 + m], sub, p[m], ok[m]);
-#pragma unroll
-                for (int m = 0; m < kA; ++m)
-#pragma unroll
-                    for (int r = 0; r < kPer; ++r)
-                        if (ok[m][r]) {
-                            ub = fminf(ub, dist(p[m][r]) + p[m][r].w + eps);
-                            ++nt;
-                        }
-            }
+            for (int r = 0; r < kPer; ++r)
+                if (ok[r]) {
+                    ub = fminf(ub, dist(p[r]) + p[r].w + eps);
+                    ++nt;
+                }
         }
         ub = min_lanes<L>(ub);
         // b. candidate clusters
