@@ -96,6 +96,12 @@ struct Newt<double> {
     static constexpr double stat = 1e-12;
 };
 
+// Square root for bounds, scales and conditioning: in FP32 the raw hardware
+// one (<= 1 ulp; the correctly rounded one costs a dozen instructions with its
+// range scaling), in FP64 the library's.
+__device__ __forceinline__ float bsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double bsqrt(double x) { return sqrt(x); }
+
 // unit roundoff of the refine precision
 template <typename T>
 struct Eps;
@@ -109,7 +115,7 @@ struct Eps<double> {
 };
 
 template <typename T>
-__device__ __forceinline__ T norm3(const V3<T>& a) { return sqrt(dot(a, a)); }
+__device__ __forceinline__ T norm3(const V3<T>& a) { return bsqrt(dot(a, a)); }
 
 // kappa = f'/|C'|^2 at a bracket end where f = r.C' vanishes to rounding (a
 // stationary minimiser that lies on the end, e.g. on a piece joint); 1 at an
@@ -118,7 +124,7 @@ template <typename T>
 __device__ __forceinline__ T end_kappa(const V3<T>& r, const V3<T>& d1, const V3<T>& d2)
 {
     const T sp = dot(d1, d1), f = dot(r, d1);
-    return (sp > (T)0 && fabs(f) <= Newt<T>::stat * sqrt(dot(r, r) * sp)) ? (sp + dot(r, d2)) / sp : (T)1;
+    return (sp > (T)0 && fabs(f) <= Newt<T>::stat * bsqrt(dot(r, r) * sp)) ? (sp + dot(r, d2)) / sp : (T)1;
 }
 
 // Minimum of |C(u) - q|^2 on [lo, hi] near the sample u0: safeguarded Newton on
@@ -171,7 +177,7 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
         // sum of the coefficients' absolute components, bounds |C - q| and each
         // of its terms on [0, 1].
         const T S = C.size();
-        const T nz = (T)(16.0 * Eps<T>::v) * S * (sqrt(d) + S);
+        const T nz = (T)(16.0 * Eps<T>::v) * S * (bsqrt(d) + S);
         if (dlo < d_best - nz) { u_best = lo; d_best = dlo; kappa = klo; }
         if (dhi < d_best - nz) { u_best = hi; d_best = dhi; kappa = khi; }
         if (loc) *loc = true;
@@ -247,7 +253,7 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2
         dmax = fmax(dmax, D[k]);
         dmin = fmin(dmin, D[k]);
     }
-    const T rmax = sqrt(dmax) + L1 * h;
+    const T rmax = bsqrt(dmax) + L1 * h;
     const T gap = (T)2 * (L1 * L1 + rmax * L2) * h * h * (T)0.125;
     uint32_t lm = 0, chk = 0;  // local minima of the samples; intervals whose bound reaches the sampled minimum
 #pragma unroll
@@ -510,9 +516,8 @@ __device__ double param_error(const Cubic<T>& C, T u, T k, double ta, double tb)
 {
     V3<T> r, d1, d2;
     C.eval(u, r, d1, d2);
-    const double sp = sqrt((double)dot(d1, d1));
-    const double scale = sqrt((double)dot(C.a0, C.a0)) + sqrt((double)dot(C.a1, C.a1)) +
-                         sqrt((double)dot(C.a2, C.a2)) + sqrt((double)dot(C.a3, C.a3));
+    const double sp = (double)norm3(d1);
+    const double scale = (double)(norm3(C.a0) + norm3(C.a1) + norm3(C.a2) + norm3(C.a3));
     const double kap = fabs((double)k);
     if (!(sp > 0.0 && kap > 0.0)) return 1.0;
     double e = 8.0 * Eps<T>::v * scale / (sp * kap);
@@ -593,9 +598,10 @@ __device__ __forceinline__ bool end_falls_across(const DevGeom& G, const DCurve&
     } else {
         return false;
     }
+    // f beyond 1e-12 |r| |d| in the falling direction, compared squared (no square root)
     const double f = r[0] * d[0] + r[1] * d[1] + r[2] * d[2];
-    const double scale = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    return left ? f > 1e-12 * scale : f < -1e-12 * scale;
+    const double s2 = 1e-24 * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    return (left ? f > 0.0 : f < 0.0) && f * f > s2;
 }
 
 __device__ __forceinline__ Cand make_cand(const DevGeom& G, int64_t s, double u, double d2, double kappa, double t_err)
