@@ -695,6 +695,7 @@ struct BoxOut {
     ScreenOut so;   // per query: the pieces whose lower bound reaches UB + margin; so.ub = UB
     unsigned long long* tests;  // [kWsCounters] sphere tests, per workgroup slot modulo kWsCounters (zeroed)
     int32_t* queue;             // [kXcds] next tile of each XCD's range (persistent schedules; zeroed)
+    int32_t* tile_curve;        // [tiles] the curve of each tile (k_box_tiles)
 };
 
 // float -> uint32 with the same order (negative values included), and back
@@ -800,12 +801,7 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
     constexpr int kPer = kCluPieces / L;    // pieces of a cluster per lane
     static_assert(L >= kK && L <= 16 && (L & (L - 1)) == 0, "4, 8 or 16 lanes per query");
     float4* const s_st = sh.st;
-    int lo_c = 0, hi_c = G.n_curves;  // tile_off[lo_c] <= tile < tile_off[hi_c]
-    while (hi_c - lo_c > 1) {
-        const int mid = (lo_c + hi_c) >> 1;
-        if (tile_off[mid] <= tile) lo_c = mid; else hi_c = mid;
-    }
-    const int c = lo_c;
+    const int c = out.tile_curve[tile];
     const DCurve cv = G.curves[c];
     const int lane = threadIdx.x & 63;
     const int qs = threadIdx.x / L, sub = threadIdx.x % L;
@@ -830,7 +826,10 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
     if (cv.clu_use) {
         // a. first bound: the best cluster upper bound, sharpened by the pieces
         // of the cluster with the smallest lower bound
-        uint64_t near = ~0ull;  // (lower bound, cluster) of this lane's nearest-bound cluster
+        // this lane's nearest-bound cluster (ties to the lower index: the lane
+        // visits its clusters in increasing order), then the query's
+        float near_lb = INFINITY;
+        int near_c = -1;
         for (int c0 = 0; c0 < cv.n_clu; c0 += kBoxChunk) {
             const int cn = min(kBoxChunk, cv.n_clu - c0);
             stage_clusters<T>(G, cv, c0, cn, s_st);
@@ -839,16 +838,24 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 const float4 p = s_st[i];
                 const float d = dist(p);
                 ub = fminf(ub, d + p.w + eps);
-                near = min(near, ((uint64_t)ord_key(d - p.w) << 32) | (uint32_t)(c0 + i));
+                const float v = d - p.w;
+                near_c = v < near_lb ? c0 + i : near_c;
+                near_lb = fminf(near_lb, v);
                 ++nt;
             }
         }
 #pragma unroll
-        for (int off = 1; off < L; off <<= 1) near = min(near, (uint64_t)__shfl_xor(near, off, 64));
+        for (int off = 1; off < L; off <<= 1) {
+            const float ov = __shfl_xor(near_lb, off, 64);
+            const int oc = __shfl_xor(near_c, off, 64);
+            const bool take = ov < near_lb || (ov == near_lb && (unsigned)oc < (unsigned)near_c);
+            near_c = take ? oc : near_c;
+            near_lb = take ? ov : near_lb;
+        }
         if (active) {
             float4 p[kPer];
             bool ok[kPer];
-            load_cluster<L>(G, cv, near == ~0ull ? -1 : (int)(uint32_t)near, sub, p, ok);
+            load_cluster<L>(G, cv, near_c, sub, p, ok);
 #pragma unroll
             for (int r = 0; r < kPer; ++r)
                 if (ok[r]) {
@@ -906,6 +913,10 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 }
                 ub = min_lanes<L>(ub);
                 const float thr_run = ub + tie_margin(ub, cv, tie_rel);
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) any |= ok[r] && lbv[r] <= thr_run;
+                if (group_hits<L>(any, lane) == 0u) continue;  // most clusters add no piece
 #pragma unroll
                 for (int r = 0; r < kPer; ++r) {
                     const bool hit = ok[r] && lbv[r] <= thr_run;
@@ -1411,7 +1422,7 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
     const int64_t oov = take(4 * n), oc = take(4 * n * kK), oxb = take(32 * n * kK), ocn = take(4 * n);
     const int64_t opo = take(4 * n), oub = take(4 * n), ops = take(4 * cap), opj = take(4 * cap);
     const int64_t opr = take((int64_t)sizeof(PairRes) * cap), osc = take(8 * n * kK), odn = take(n);
-    const int64_t oqu = take(4 * kXcds);
+    const int64_t oqu = take(4 * kXcds), otcv = take(4 * (nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds));
     if (w) {
         w->hist = (int32_t*)(base + oh); w->q_off = (int32_t*)(base + oq); w->tile_off = (int32_t*)(base + ot);
         w->perm = (int32_t*)(base + op); w->ovf_list = (int32_t*)(base + oov);
@@ -1419,6 +1430,7 @@ int64_t seed_layout(int64_t nc, int64_t n, char* base, SeedWork* w)
         w->box.cand = (int32_t*)(base + oc);
         w->box.tests = (unsigned long long*)(base + otc);
         w->box.queue = (int32_t*)(base + oqu);
+        w->box.tile_curve = (int32_t*)(base + otcv);
         w->box.xb = (uint16_t*)(base + oxb);
         w->box.so.cand_n = (int32_t*)(base + ocn);
         w->box.so.pair_off = (int32_t*)(base + opo);
@@ -1468,6 +1480,15 @@ __global__ void k_zero_counters(unsigned long long* __restrict__ p, int64_t n, i
 }
 
 constexpr int kMaxDevices = 64;
+
+// the curve of every tile: one thread per curve writes its tiles
+__global__ __launch_bounds__(256) void k_box_tiles(const int32_t* __restrict__ tile_off, int32_t n_curves,
+                                                  int32_t* __restrict__ tile_curve)
+{
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= n_curves) return;
+    for (int t = tile_off[c]; t < tile_off[c + 1]; ++t) tile_curve[t] = c;
+}
 
 // one schedule of the box kernel; a persistent grid holds as many workgroups
 // as the device keeps resident at once (the occupancy is queried once per
@@ -1528,6 +1549,8 @@ static int candidates(const mrep_geom* geom, int64_t n, const int32_t* curve_id,
                        w.box.queue);
     // an upper bound of the tile count (tiles of a curve: ceil(its queries / kQueriesPerTile)), plus one per XCD
     const int64_t tiles = nc + (n + kQueriesPerTile - 1) / kQueriesPerTile + kXcds;
+    hipLaunchKernelGGL(k_box_tiles, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const int32_t*)w.tile_off,
+                       (int32_t)nc, w.box.tile_curve);
     NN_HIP(keys ? launch_box<true>(geom, tiles, w, q_xyz, tie_rel, st)
                 : launch_box<false>(geom, tiles, w, q_xyz, tie_rel, st));
     return MREP_OK;
