@@ -619,12 +619,47 @@ def batched_curves_block(args, dev):
         strat, ms_screen, ms_spheres, _ = geom.tune(q, cid, out=tuple(torch.empty_like(o) for o in outs))
         res["autotune"] = {"strategy": ["screen", "spheres"][strat], "ms": {"screen": ms_screen, "spheres": ms_spheres}}
         res["graph_small_batches"] = graph_small_batches(geom, q, cid)
+        res["precision_tiers"] = precision_tiers(geom, q, cid, outs, curves, qs)
     if not args.no_clip:
         res["clip_refiner"] = clip_refiner(geom, q, cid, outs, curves, res["value"], stage, ws, args)
     if not args.no_seeded:
         res["seeded"] = seeded_variants(geom, q, cid, outs, curves, res["value"], args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(curves, qs, q_host, outs, min(args.cpu_seconds, 8.0))
+    return res
+
+
+def precision_tiers(geom, q, cid, bf_outs, curves, qs):
+    """The same batch in the FP32 and FP64 tiers (every piece examined in that precision, FP64 polish): time
+    per call and the largest differences from the BF16 screen's answers."""
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    n = q.shape[0]
+    diag = torch.from_numpy(curves.bbox_diag()).to(q.device)[cid.long()]
+    res = {}
+    for name in ("fp32", "fp64"):
+        opts = mrep.default_opts(name)
+        ws = torch.empty(geom.workspace_bytes(n, opts), dtype=torch.uint8, device=q.device)
+        outs = tuple(torch.empty_like(o) for o in bf_outs)
+
+        def step():
+            geom.project(q, cid, opts, workspace=ws, out=outs)
+
+        step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        res[name] = {"ms_per_call": ms, "value": n / (ms / 1e3),
+                     "vs_bf16_max_dist_rel": float(((outs[1] - bf_outs[1]).abs() / diag).max().item()),
+                     "vs_bf16_same_piece_frac": float((outs[2] == bf_outs[2]).double().mean().item())}
+        _say("batched", f"{name} tier {ms:.2f} ms per call")
     return res
 
 

@@ -80,6 +80,8 @@ extern "C" {
 
 /* screen precisions (mrep_opts.precision) */
 #define MREP_PREC_FP64 0 /* exhaustive FP64 examination of every segment (no MFMA screen) */
+#define MREP_PREC_FP32 1 /* exhaustive FP32 examination of every segment: 32 samples, FP32 Newton and certified
+                            bounds, FP64 polish (no MFMA screen; the FP32 tier of the same path) */
 #define MREP_PREC_BF16 3 /* BF16 MFMA screen, FP32 accumulate, FP32 Newton, FP64 polish */
 
 typedef struct mrep_plan mrep_plan; /* host-side decomposition result, owned by the library */
@@ -405,9 +407,9 @@ int32_t mrep_set_curve_schedule(mrep_geom* geom, int32_t lanes, int32_t persiste
 
 /* Durations in milliseconds of the stages of the last call on the calling
  * thread that set MREP_OPT_TIME_STAGES.  mrep_project_curves / invert: 4
- * stages, [0] grouping, [1] screen (0 in FP64 mode), [2] refine of the
- * candidate (query, piece) pairs (0 in FP64 mode), [3] top-2 + FP64 polish +
- * write, with the full scan of overflowed queries (every query in FP64 mode).
+ * stages, [0] grouping, [1] screen (0 in the FP64 and FP32 modes), [2] refine of the
+ * candidate (query, piece) pairs (0 in those modes), [3] top-2 + FP64 polish +
+ * write, with the full scan of overflowed queries (every query in those modes).
  * mrep_project_curves_seeded (and mrep_project_curves in the sphere
  * strategy): 6 stages, [0] grouping, [1] sphere candidates (the box kernel),
  * [2] network scoring (0 without a network), [3] seed + certificate (0

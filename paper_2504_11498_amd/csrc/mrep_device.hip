@@ -803,7 +803,7 @@ int mrep::check_opts(const mrep_opts* o)
         set_error("mrep_opts: null or struct_size mismatch");
         return MREP_E_INVALID_ARG;
     }
-    if (o->precision != MREP_PREC_FP64 && o->precision != MREP_PREC_BF16) {
+    if (o->precision != MREP_PREC_FP64 && o->precision != MREP_PREC_FP32 && o->precision != MREP_PREC_BF16) {
         set_error("mrep_opts: unsupported precision");
         return MREP_E_INVALID_ARG;
     }
@@ -902,7 +902,17 @@ int mrep::project_core(const Geom& geom, const mrep_opts* opts, int64_t n, const
     } else {
         if (timed && (rc = stage_mark(stage0 + 3, st))) return rc;
         const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
-        if (G.general)
+        // every query examined over all its pieces, in FP64 or FP32
+        const bool f32 = opts->precision == MREP_PREC_FP32;
+        if (G.general && f32)
+            hipLaunchKernelGGL((k_fullscan<float, true>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz,
+                               w.q_off, w.perm, (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr,
+                               0u, opts->tie_rel, invert, o);
+        else if (f32)
+            hipLaunchKernelGGL((k_fullscan<float, false>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz,
+                               w.q_off, w.perm, (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr,
+                               0u, opts->tie_rel, invert, o);
+        else if (G.general)
             hipLaunchKernelGGL((k_fullscan<double, true>), dim3(fs_blocks), dim3(256), 0, st, G, curve_id, q_xyz,
                                w.q_off, w.perm, (const int32_t*)nullptr, (const int32_t*)nullptr, (const float*)nullptr,
                                0u, opts->tie_rel, invert, o);

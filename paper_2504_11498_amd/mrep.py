@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 OK, E_INVALID_ARG, E_BAD_DEGREE, E_BAD_KNOTS, E_TOL, E_SMALL_BUFFER, E_HIP, E_NO_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 F_POLISHED, F_NEAR_TIE, F_ILL_COND, F_ENDPOINT, F_OFFCURVE, F_FULLSCAN, F_BAD_ID = 1, 2, 4, 8, 16, 32, 64
 F_NN_FALLBACK = 128
-PREC_FP64, PREC_BF16 = 0, 3
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 3
 OPT_TIME_STAGES, OPT_TUNED, OPT_CLIP = 1, 2, 4
 STRATEGY_SCREEN, STRATEGY_SPHERES = 0, 1
 ROOTS_FERRARI, ROOTS_NEWTON = 0, 1
@@ -375,7 +375,7 @@ def default_opts(precision: str | int = "bf16", max_candidates: int = 32, tie_re
     _check(_opts_default(C.byref(o)), "mrep_opts_default")
     o.flags = (OPT_TIME_STAGES if time_stages else 0) | (OPT_TUNED if tuned else 0) | (OPT_CLIP if clip else 0)
     if isinstance(precision, str):
-        precision = {"fp64": PREC_FP64, "bf16": PREC_BF16}[precision]
+        precision = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}[precision]
     o.precision = int(precision)
     o.max_candidates = int(max_candidates)
     o.tie_rel = float(tie_rel)

@@ -62,13 +62,21 @@ def test_lattice_plain_all_queries_sampled(mrep, lattice):
     _say(f"[ok] {st} fullscan={np.mean((out['flags'] & mrep.F_FULLSCAN) != 0):.4f}")
 
 
-def test_lattice_fp64_subset(mrep, lattice):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lattice_exhaustive_subset(mrep, lattice, precision):
+    """Every piece examined (FP64, or the FP32 tier) on the sample; the FP32 tier also lands on the BF16
+    screen's parameter where the oracle's minimum is unique and well conditioned."""
     curves, qs, q, geom, sub, ref, dec = lattice
-    _say("[case] lattice fp64, 3000-query sample")
+    _say(f"[case] lattice {precision}, 3000-query sample")
     qt = torch.from_numpy(np.ascontiguousarray(q[sub])).cuda()
     ct = torch.from_numpy(np.ascontiguousarray(qs.curve_id[sub])).cuda()
-    out = _out(*geom.project(qt, ct, mrep.default_opts("fp64")))
-    st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label="lattice/fp64")
+    out = _out(*geom.project(qt, ct, mrep.default_opts(precision)))
+    st = compare(curves, qs.curve_id[sub], q[sub], out, ref, dec, label=f"lattice/{precision}")
+    if precision == "fp32":
+        bf = _out(*geom.project(qt, ct, mrep.default_opts("bf16")))
+        diag = curves.bbox_diag()[qs.curve_id[sub]]
+        wc = ((ref["runner"] - ref["dist"]) > 2e-6 * diag) & (ref["kappa"] >= 1e-3)
+        assert np.abs(bf["t"] - out["t"])[wc].max() <= 1e-10
     _say(f"[ok] {st}")
 
 

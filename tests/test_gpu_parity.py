@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from paper_2504_11498_amd import gen
-from parity import compare, oracle_pieces
+from parity import compare, oracle_pieces, oracle_seg_index
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def single(mrep):
     return curves, qs, geom, ref, oracle_pieces(curves, 1e-6)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_single_cubic_all_queries(single, precision):
     curves, qs, geom, ref, dec = single
     _say(f"[case] single cubic, 10000 box queries, {precision}")
@@ -69,7 +69,7 @@ def batched(mrep):
     return curves, qs, q, plan, geom, sub, ref, dec
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp64"])
+@pytest.mark.parametrize("precision", ["bf16", "fp32", "fp64"])
 def test_batched_subset(batched, precision):
     curves, qs, q, plan, geom, sub, ref, dec = batched
     _say(f"[case] batched curves, 20000-query subset, {precision}")
@@ -101,6 +101,26 @@ def test_batched_full_size_sampled(batched):
     for k in ("t", "dist", "seg"):
         np.testing.assert_array_equal(out_sub[k], out[k][sub])
     _say(f"[ok] {st}")
+
+
+def test_bf16_and_fp32_tiers_agree(batched):
+    """The BF16 screen and the FP32 tier (every piece examined in FP32) reach the same answers: on the
+    20,000-query subset the same piece wherever the oracle's minimum is unique and not within 1e-7 of a piece
+    boundary, parameters within 1e-10 where it is also well conditioned, distances within 1e-12 of the
+    diagonal everywhere."""
+    curves, qs, q, plan, geom, sub, ref, dec = batched
+    _say("[case] bf16 vs fp32 tiers, 20000-query subset")
+    a = _run(geom, q[sub], qs.curve_id[sub], "bf16")
+    b = _run(geom, q[sub], qs.curve_id[sub], "fp32")
+    diag = curves.bbox_diag()[qs.curve_id[sub]]
+    unique = (ref["runner"] - ref["dist"]) > 2e-6 * diag
+    wc = unique & (ref["kappa"] >= 1e-3)
+    _, near = oracle_seg_index(dec[0], dec[1], qs.curve_id[sub], ref["t"])
+    chk = unique & ~near
+    assert np.all(a["seg"][chk] == b["seg"][chk]), np.nonzero(chk & (a["seg"] != b["seg"]))[0][:10]
+    assert np.abs(a["t"] - b["t"])[wc].max() <= 1e-10
+    assert (np.abs(a["dist"] - b["dist"]) / diag).max() <= 1e-12
+    _say(f"[ok] same piece on {int(chk.sum())} queries, max |dt| {np.abs(a['t'] - b['t'])[wc].max():.2e}")
 
 
 def test_repeat_is_bitwise_deterministic(batched):
