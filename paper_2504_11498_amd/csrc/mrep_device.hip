@@ -932,7 +932,10 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
                                int32_t* ovf_count, const Outs& o, hipStream_t st, bool clip, int pairs_mark)
 {
     const int RT = 128;
-    const unsigned fs_blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);  // 4 waves per block, persistent
+    // the full scan of overflowed queries: a persistent grid sized for about one
+    // overflow in 256 queries (an empty launch of the wide grid cost 38 us on
+    // 4,096-query calls; a grid that is too small stays correct, only slower)
+    const unsigned fs_blocks = (unsigned)std::max<int64_t>(16, std::min<int64_t>((n + 63) / 64, 2048));
     const unsigned pr_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((so.pair_cap + 255) / 256, 8192));
     if (clip) {
         const hipError_t e = launch_pairs_clip(G, curve_id, q_xyz, perm, so, done, pair_res, st);
