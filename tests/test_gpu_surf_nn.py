@@ -155,6 +155,19 @@ def _seeded(geom, q, sid, net):
             "flags": f.cpu().numpy().view(np.uint32)}
 
 
+def test_surface_trained_network_falls_back_less(mrep, strained, sevalset):
+    """What the trained surface network gains: its seeded patch holds the minimum for at least 0.2 more of the
+    queries than an untrained network's, with the oracle's answers for both."""
+    S, Q, sid, q, plan, geom, ref = sevalset
+    fb = {}
+    for name, net in (("trained", strained[0]), ("untrained", mrep.Network(seed=99, kind=mrep.NN_SURFACE))):
+        out = _seeded(geom, q, sid, net)
+        compare_surf(S, sid, q, out, ref, plan.export_surfaces(), label=f"surf-seeded/{name}")
+        fb[name] = float(np.mean((out["flags"] & mrep.F_NN_FALLBACK) != 0))
+    _say(f"[ok] fallback trained {fb['trained']:.4f}, untrained {fb['untrained']:.4f}")
+    assert fb["trained"] <= fb["untrained"] - 0.2, fb
+
+
 @pytest.mark.parametrize("which", ["trained", "untrained"])
 def test_surface_seeded_projection_parity(mrep, strained, sevalset, which):
     S, Q, sid, q, plan, geom, ref = sevalset
