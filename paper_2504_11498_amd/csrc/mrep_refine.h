@@ -176,8 +176,13 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
         // end onto the end (a parameter error the FP64 polish never saw).  S, the
         // sum of the coefficients' absolute components, bounds |C - q| and each
         // of its terms on [0, 1].
-        const T S = C.size();
-        const T nz = (T)(16.0 * Eps<T>::v) * S * (bsqrt(d) + S);
+        // (in FP64 the rounding is far below any parameter tolerance: no margin,
+        // which also keeps the FP64 full scan within 256 registers)
+        T nz = (T)0;
+        if constexpr (sizeof(T) == 4) {
+            const T S = C.size();
+            nz = (T)(16.0 * Eps<T>::v) * S * (bsqrt(d) + S);
+        }
         if (dlo < d_best - nz) { u_best = lo; d_best = dlo; kappa = klo; }
         if (dhi < d_best - nz) { u_best = hi; d_best = dhi; kappa = khi; }
         if (loc) *loc = true;
