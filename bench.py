@@ -510,13 +510,13 @@ def box_roofline(tests, box_ms):
 def finish_roofline(n, pairs, coef_bytes, finish_ms):
     """k_finish (top-2 of each query's pair records, FP64 polish on the exact span, write) against HBM: per
     query 4 index words, the query, the polished span's (p+1) x 3 FP64 coefficients, its interval and piece
-    bounds, and the 24-byte result; per pair its 48-byte record and 4-byte piece index."""
-    byts = n * (16 + 24 + 16 + 4 + 16 + 24) + pairs * 52 + coef_bytes
+    bounds, and the 24-byte result; per pair its 32-byte record and 4-byte piece index."""
+    byts = n * (16 + 24 + 16 + 4 + 16 + 24) + pairs * 36 + coef_bytes
     achieved = byts / (finish_ms / 1e3) / 1e9 if finish_ms > 0 else None
     return {"bound": "hbm", "kernel": "k_finish", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None, "units": int(n),
             "algorithmic_bytes": int(byts), "time_ms": finish_ms,
-            "per_unit": "100 B per query + 52 B per pair + 24 (p+1) B of span coefficients per query"}
+            "per_unit": "100 B per query + 36 B per pair + 24 (p+1) B of span coefficients per query"}
 
 
 def mlp_roofline(rows, ms):

@@ -645,15 +645,15 @@ __device__ __forceinline__ Cand make_cand_q(const DevGeom& G, const DCurve& cv, 
 // that the finish reads one contiguous record per pair and no piece table.
 struct alignas(16) PairRes {
     double t;       // the piece's minimum (global parameter)
-    double t2;      // its second local minimum (when d2b < inf)
+    float dt2;      // its second local minimum t2 - t (when d2b < inf): within the piece, so FP32 keeps it to
+                    // 6e-8 of the piece's parameter length (the runner-up's start, polished in FP64 when it counts)
     float d2;       // squared distance at t (refine precision)
     float kappa;
     float t_err;    // bound on the parameter error left by the refine precision
     float d2b;      // squared distance at t2; +inf when the piece has no second minimum
     uint32_t tag;   // bits 0-1: t at the piece's start (1) or end (2); bit 2: across; bits 4-6: the same for t2
-    uint32_t pad_[3];
 };
-static_assert(sizeof(PairRes) == 48, "PairRes layout");
+static_assert(sizeof(PairRes) == 32, "PairRes layout");
 
 __device__ __forceinline__ PairRes pair_result(const DevGeom& G, const DCurve& cv, int64_t s, const double* q,
                                                double u, double d, double k, double err, double u2, double d2)
@@ -667,15 +667,14 @@ __device__ __forceinline__ PairRes pair_result(const DevGeom& G, const DCurve& c
     uint32_t tag = (uint32_t)c1.end | ((uint32_t)c1.across << 2);
     if (d2 < INFINITY) {
         const Cand c2 = make_cand_q(G, cv, s, u2, d2, 1.0, 0.0, q);
-        r.t2 = c2.t;
+        r.dt2 = (float)(c2.t - c1.t);
         r.d2b = (float)d2;
         tag |= ((uint32_t)c2.end | ((uint32_t)c2.across << 2)) << 4;
     } else {
-        r.t2 = 0.0;
+        r.dt2 = 0.f;
         r.d2b = INFINITY;
     }
     r.tag = tag;
-    r.pad_[0] = r.pad_[1] = r.pad_[2] = 0u;
     return r;
 }
 
@@ -683,7 +682,7 @@ __device__ __forceinline__ PairRes pair_result(const DevGeom& G, const DCurve& c
 __device__ __forceinline__ Cand pair_cand(const PairRes& r, int32_t seg, bool sec)
 {
     Cand x;
-    x.t = sec ? r.t2 : r.t;
+    x.t = sec ? r.t + (double)r.dt2 : r.t;
     x.d2 = (double)(sec ? r.d2b : r.d2);
     x.kappa = sec ? 1.f : r.kappa;
     x.t_err = sec ? 0.f : r.t_err;
