@@ -101,6 +101,10 @@ struct Newt<double> {
 // range scaling), in FP64 the library's.
 __device__ __forceinline__ float bsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double bsqrt(double x) { return sqrt(x); }
+// Quotient for Newton steps and conditioning: in FP32 through the hardware
+// reciprocal (<= 1 ulp; the iteration corrects its own step), in FP64 exact.
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 
 // unit roundoff of the refine precision
 template <typename T>
@@ -124,7 +128,7 @@ template <typename T>
 __device__ __forceinline__ T end_kappa(const V3<T>& r, const V3<T>& d1, const V3<T>& d2)
 {
     const T sp = dot(d1, d1), f = dot(r, d1);
-    return (sp > (T)0 && fabs(f) <= Newt<T>::stat * bsqrt(dot(r, r) * sp)) ? (sp + dot(r, d2)) / sp : (T)1;
+    return (sp > (T)0 && fabs(f) <= Newt<T>::stat * bsqrt(dot(r, r) * sp)) ? qdiv(sp + dot(r, d2), sp) : (T)1;
 }
 
 // Minimum of |C(u) - q|^2 on [lo, hi] near the sample u0: safeguarded Newton on
@@ -154,7 +158,7 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
             T f = dot(r, d1);
             T fp = dot(d1, d1) + dot(r, d2);
             if (f < (T)0) a = u; else if (f > (T)0) b = u; else break;
-            T un = fp > (T)0 ? u - f / fp : (T)0.5 * (a + b);
+            T un = fp > (T)0 ? u - qdiv(f, fp) : (T)0.5 * (a + b);
             // closed bracket: a converged step that rounds onto u (= a or b)
             // must end the iteration, not trigger a bisection
             if (!(un >= a && un <= b)) un = (T)0.5 * (a + b);
@@ -165,7 +169,7 @@ __device__ __forceinline__ void newton_min(const Cubic<T>& C, T lo, T hi, T u0, 
         C.eval(u, r, d1, d2);
         T sp = dot(d1, d1);
         T fp = sp + dot(r, d2);
-        kappa = sp > (T)0 ? fp / sp : (T)1;
+        kappa = sp > (T)0 ? qdiv(fp, sp) : (T)1;
         T d = dot(r, r);
         u_best = u;
         d_best = d;
