@@ -25,7 +25,7 @@
  *     Lipschitz branch-and-bound that re-examines every sample interval whose
  *     lower bound beats the best distance found.
  *
- * Readings of points the paper leaves open (also listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - the domain is [t_p, t_{n}] of a clamped knot vector; at the right end the
  *     last non-degenerate span is used;
  *   - "L1-error" of a cubic piece is the same-parameter deviation
