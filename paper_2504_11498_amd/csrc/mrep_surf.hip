@@ -195,6 +195,8 @@ __device__ __forceinline__ CluRows clu_rows(const DSurf& sf, int c)
 }
 
 // min over the patches of cluster c of |q - c_p| + r_p + eps (per lane)
+constexpr int kBatch = 4;  // patch spheres a lane loads at once
+
 __device__ __forceinline__ float clu_patch_ub(const DevSurf& D, const DSurf& sf, int c, const float* ql, float eps,
                                               int sub, float ub)
 {
@@ -202,10 +204,18 @@ __device__ __forceinline__ float clu_patch_ub(const DevSurf& D, const DSurf& sf,
     for (int iu = R.iu0; iu < R.iu1; ++iu) {
         const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
         const int k1 = D.span0[rs + R.iv1];
-        for (int k = D.span0[rs + R.iv0] + sub; k < k1; k += kSphSub) {
-            const float4 p = D.sph[k];
-            const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-            ub = fminf(ub, sqrtf(dx * dx + dy * dy + dz * dz) + p.w + eps);
+        // kBatch patches per lane loaded together, so that their latencies overlap
+        for (int k = D.span0[rs + R.iv0] + sub; k < k1; k += kBatch * kSphSub) {
+            float4 p[kBatch];
+#pragma unroll
+            for (int r = 0; r < kBatch; ++r)
+                p[r] = k + r * kSphSub < k1 ? D.sph[k + r * kSphSub] : make_float4(0.f, 0.f, 0.f, INFINITY);
+#pragma unroll
+            for (int r = 0; r < kBatch; ++r) {
+                const float dx = ql[0] - p[r].x, dy = ql[1] - p[r].y, dz = ql[2] - p[r].z;
+                // the raw square root (<= 1 ulp) is inside the allowance eps
+                ub = fminf(ub, __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz) + p[r].w + eps);
+            }
         }
     }
     return ub;
@@ -830,19 +840,27 @@ __global__ __launch_bounds__(kSphThreads) void k_slist(DevSurf D, const int32_t*
             for (int iu = R.iu0; iu < R.iu1; ++iu) {
                 const int64_t rs = sf.span_off + (int64_t)iu * sf.n_sv;
                 const int k0 = D.span0[rs + R.iv0], k1 = D.span0[rs + R.iv1];
-                for (int i0 = k0; i0 < k1; i0 += kSphSub) {
-                    const int k = i0 + sub;
-                    bool hit = false;
-                    if (k < k1) {
-                        const float4 p = D.sph[k];
-                        const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
-                        const float tt = thr + p.w + eps;
-                        hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                for (int i0 = k0; i0 < k1; i0 += kBatch * kSphSub) {
+                    float4 p[kBatch];
+#pragma unroll
+                    for (int r = 0; r < kBatch; ++r) {
+                        const int k = i0 + r * kSphSub + sub;
+                        p[r] = k < k1 ? D.sph[k] : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
-                    const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
-                    const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
-                    if (hit && pos < kSphCap) s_list[qs][pos] = k - (int)sf.patch_off;
-                    cnt += __popc(grp);
+#pragma unroll
+                    for (int r = 0; r < kBatch; ++r) {
+                        const int k = i0 + r * kSphSub + sub;
+                        bool hit = false;
+                        if (k < k1) {
+                            const float dx = ql[0] - p[r].x, dy = ql[1] - p[r].y, dz = ql[2] - p[r].z;
+                            const float tt = thr + p[r].w + eps;
+                            hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                        }
+                        const uint32_t grp = (uint32_t)(__ballot(hit) >> (lane & 56)) & 0xffu;
+                        const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
+                        if (hit && pos < kSphCap) s_list[qs][pos] = k - (int)sf.patch_off;
+                        cnt += __popc(grp);
+                    }
                 }
             }
         }
