@@ -303,6 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_
                                                const int32_t* __restrict__ pair_seg,
                                                const int32_t* __restrict__ pair_j,
                                                const int32_t* __restrict__ pair_count, int64_t pair_cap,
+                                               const float* __restrict__ ub, double tie_rel,
                                                const uint8_t* __restrict__ done, PairRes* __restrict__ pair_res)
 {
     const int64_t total = min((int64_t)*pair_count, pair_cap);
@@ -318,8 +319,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MREP_PAIRS_
         const double q[3] = {qxyz[3 * (int64_t)qi], qxyz[3 * (int64_t)qi + 1], qxyz[3 * (int64_t)qi + 2]};
         Cubic<T> C;
         load_cubic(G, cv, s, q, C);
+        // beyond the query's certified bound plus twice the widest tie margin of
+        // the finish, a piece cannot hold the minimum nor a runner-up that counts
+        const double ubq = (double)ub[jj];
+        const double lim = ubq + 2.0 * (2.0 * cv.tol_eff + 4e-6 * (ubq + cv.diag) + tie_rel * cv.diag);
         T u, d, k, u2, d2;
-        piece_min(C, u, d, k, u2, d2);
+        piece_min(C, u, d, k, u2, d2, (T)(lim * lim));
         const double err = param_error(C, u, k, G.segt[2 * s], G.segt[2 * s + 1]);
         pair_res[p] = pair_result(G, cv, s, q, (double)u, (double)d, (double)k, err, (double)u2, (double)d2);
     }
@@ -943,7 +948,7 @@ hipError_t mrep::launch_refine(const DevGeom& G, int64_t n, const int32_t* curve
     } else {
         hipLaunchKernelGGL(k_pairs<float>, dim3(pr_blocks), dim3(256), 0, st, G, curve_id, q_xyz, perm,
                            (const int32_t*)so.pair_seg, (const int32_t*)so.pair_j, (const int32_t*)so.pair_count,
-                           so.pair_cap, done, pair_res);
+                           so.pair_cap, (const float*)so.ub, tie_rel, done, pair_res);
     }
     if (pairs_mark >= 0 && stage_mark(pairs_mark, st) != MREP_OK) return hipErrorUnknown;
     // the general instances evaluate Bezier and rational spans as well (geometries that hold them)

@@ -242,7 +242,8 @@ __device__ __forceinline__ void keep2(const Cubic<T>& C, T u, T d, T k, bool loc
 // pass produces bit masks; the Newton solves run in compact loops over the
 // set bits, which keeps the kernels small.
 template <typename T>
-__device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2_out, T& d2_out)
+__device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2_out, T& d2_out,
+                          T lim2 = (T)INFINITY)
 {
     // C' has Bezier control points a1, a1 + a2, a1 + 2 a2 + 3 a3; C'' has 2 a2, 2 a2 + 6 a3
     const V3<T> h1 = {C.a1.x + C.a2.x, C.a1.y + C.a2.y, C.a1.z + C.a2.z};
@@ -273,6 +274,14 @@ __device__ void piece_min(const Cubic<T>& C, T& u_out, T& d_out, T& k_out, T& u2
     }
     u_out = (T)0; d_out = (T)INFINITY; k_out = (T)1;
     u2_out = (T)0; d2_out = (T)INFINITY;
+    // the piece's squared distance stays above dmin - gap: beyond the caller's
+    // limit (lim2), no point of it can be the minimum or a runner-up that
+    // counts, so it is not refined (reported as its sampled minimum, interior)
+    if ((dmin - gap) * ((T)1 - (T)(sizeof(T) == 4 ? 8e-6 : 2e-14)) > lim2) {
+        u_out = (T)0.5;
+        d_out = dmin;
+        return;
+    }
     bool l1 = false;
     uint32_t covered = 0;  // bit k: interval (k, k+1) lies inside a refined bracket
     for (uint32_t bits = lm; bits; bits &= bits - 1) {
