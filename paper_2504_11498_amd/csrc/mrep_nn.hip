@@ -852,6 +852,10 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
             near_c = take ? oc : near_c;
             near_lb = take ? ov : near_lb;
         }
+        // the piece of that cluster whose centre is nearest (ties to the lower
+        // index, so the same piece for every lane count)
+        float bd = INFINITY, bw = 0.f;
+        int bk = -1;
         if (active) {
             float4 p[kPer];
             bool ok[kPer];
@@ -859,9 +863,39 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
 #pragma unroll
             for (int r = 0; r < kPer; ++r)
                 if (ok[r]) {
-                    ub = fminf(ub, dist(p[r]) + p[r].w + eps);
+                    const float d = dist(p[r]);
+                    ub = fminf(ub, d + p[r].w + eps);
                     ++nt;
+                    if (d < bd) {
+                        bd = d;
+                        bw = p[r].w;
+                        bk = near_c * kCluPieces + sub + r * L;
+                    }
                 }
+        }
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) {
+            const float od = __shfl_xor(bd, off, 64), ow = __shfl_xor(bw, off, 64);
+            const int ok_ = __shfl_xor(bk, off, 64);
+            const bool take = od < bd || (od == bd && (unsigned)ok_ < (unsigned)bk);
+            bk = take ? ok_ : bk;
+            bw = take ? ow : bw;
+            bd = take ? od : bd;
+        }
+        // a point of that piece bounds the distance far tighter than its sphere:
+        // lanes 0..3 take B(0), B(1/3), B(2/3), B(1) of its FP32 Bezier form (the
+        // curve lies within tol_eff of it; 4e-6 w covers the FP32 control points
+        // and the evaluation)
+        if (active && bk >= 0 && sub < 4) {
+            const float4* lp = reinterpret_cast<const float4*>(G.lcp + 12 * (cv.seg_off + (int64_t)bk));
+            const float4 a = lp[0], b = lp[1], e = lp[2];
+            const float4 c = G.sph[cv.seg_off + bk];
+            const float t = (float)sub * (1.f / 3.f), s = 1.f - t;
+            const float w0 = s * s * s, w1 = 3.f * t * s * s, w2 = 3.f * t * t * s, w3 = t * t * t;
+            const float4 pt = make_float4(c.x + (w0 * a.x + w1 * a.w + w2 * b.z + w3 * e.y),
+                                          c.y + (w0 * a.y + w1 * b.x + w2 * b.w + w3 * e.z),
+                                          c.z + (w0 * a.z + w1 * b.y + w2 * e.x + w3 * e.w), 0.f);
+            ub = fminf(ub, dist(pt) + 1.0001f * (float)cv.tol_eff + 4e-6f * bw + eps);
         }
         ub = min_lanes<L>(ub);
         // b. candidate clusters
