@@ -663,16 +663,18 @@ __global__ __launch_bounds__(256) void k_mlp(Rows rows, const uint8_t* __restric
 // and a cluster of kCluPieces consecutive pieces lies in a sphere around
 // theirs.  One workgroup per tile of kQueriesPerTile queries of one curve, 8
 // lanes per query.  Curves whose clusters are compact (clu_use):
-//   a. a first bound: the best cluster upper bound and the piece upper bounds
-//      of the cluster with the smallest lower bound (clusters staged in LDS,
-//      pieces read from global memory);
+//   a. a first bound: the best cluster upper bound, the piece upper bounds of
+//      the cluster with the smallest lower bound (clusters staged in LDS,
+//      pieces read from global memory), and the distances to four points of
+//      its piece with the nearest centre;
 //   b. the clusters whose lower bound reaches it plus the tie margin;
 //   c. over their pieces: UB = the smallest upper bound and the K pieces with
 //      the smallest lower bounds (ties to the lower index), and every piece
 //      whose lower bound reaches the running UB + margin (a superset of the
 //      list, since UB only falls);
-//   d. the list: those of them whose lower bound reaches UB + margin(UB) (a
-//      second pass over the clusters' pieces when the superset overflows).
+//   d. the list: those of them whose lower bounds, the sphere's and the
+//      capsule's around the chord P0P3 (capsule_lb), both reach UB + margin(UB)
+//      (a second pass over the clusters' pieces when the superset overflows).
 // The lanes of a query load all of their pieces of a cluster at once, so the
 // loads' latencies overlap.  Other curves: the same UB, K nearest and list from two passes over all the
 // curve's piece spheres staged in LDS.  Bounds carry a rounding allowance of 1e-6 (|q'| + diag).  More than
@@ -755,6 +757,35 @@ __device__ __forceinline__ uint32_t group_hits(bool hit, int lane)
 __device__ __forceinline__ float tie_margin(float d, const DCurve& cv, float tie_rel)
 {
     return 2.f * (float)cv.tol_eff + 4e-6f * (d + (float)cv.diag) + tie_rel * (float)cv.diag;
+}
+
+// Distance from v to the segment [0, a] (inv = 1 / |a|^2, or 0 for a point).
+// An inexact inv moves the foot along the segment: the result can only grow,
+// by at most 2e-7 |a|.
+__device__ __forceinline__ float chord_dist(float vx, float vy, float vz, float ax, float ay, float az, float inv)
+{
+    const float t = fminf(fmaxf((vx * ax + vy * ay + vz * az) * inv, 0.f), 1.f);
+    const float x = vx - t * ax, y = vy - t * ay, z = vz - t * az;
+    return __builtin_amdgcn_sqrtf(x * x + y * y + z * z);
+}
+// A second lower bound of the distance from the query to piece k's span (c: the
+// piece's sphere).  The FP32 control points lie within rho of the chord P0P3,
+// so the Bezier piece (inside their convex hull) lies in the capsule of radius
+// rho around the chord, and the span within tol_eff of the piece; 8e-6 w covers
+// the FP32 control points and this arithmetic.  Far tighter than the sphere for
+// the long, nearly straight pieces beside the nearest one.
+__device__ __forceinline__ float capsule_lb(const DevGeom& G, const DCurve& cv, int k, const float4& c, const float* ql)
+{
+    const float4* lp = reinterpret_cast<const float4*>(G.lcp + 12 * (cv.seg_off + (int64_t)k));
+    const float4 a = lp[0], b = lp[1], e = lp[2];
+    // P0 = (a.x, a.y, a.z), P1 = (a.w, b.x, b.y), P2 = (b.z, b.w, e.x), P3 = (e.y, e.z, e.w)
+    const float ax = e.y - a.x, ay = e.z - a.y, az = e.w - a.z;
+    const float aa = ax * ax + ay * ay + az * az;
+    const float inv = aa > 1e-30f ? __builtin_amdgcn_rcpf(aa) : 0.f;
+    const float rho = fmaxf(chord_dist(a.w - a.x, b.x - a.y, b.y - a.z, ax, ay, az, inv),
+                            chord_dist(b.z - a.x, b.w - a.y, e.x - a.z, ax, ay, az, inv));
+    const float d = chord_dist(ql[0] - c.x - a.x, ql[1] - c.y - a.y, ql[2] - c.z - a.z, ax, ay, az, inv);
+    return d - rho - 1.0001f * (float)cv.tol_eff - 8e-6f * c.w;
 }
 
 template <int T>
@@ -976,6 +1007,7 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                     k = sh.list[qs][i];
                     const float4 p = G.sph[cv.seg_off + k];
                     hit = dist(p) - p.w - eps <= thr;
+                    if (hit) hit = capsule_lb(G, cv, k, p, ql) - eps <= thr;
                     ++nt;
                 }
                 // every lane has read its entry before any is overwritten: the
@@ -993,7 +1025,8 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 load_cluster<L>(G, cv, cl, sub, p, ok);
 #pragma unroll
                 for (int r = 0; r < kPer; ++r) {
-                    const bool hit = ok[r] && dist(p[r]) - p[r].w - eps <= thr;
+                    bool hit = ok[r] && dist(p[r]) - p[r].w - eps <= thr;
+                    if (hit) hit = capsule_lb(G, cv, cl * kCluPieces + sub + r * L, p[r], ql) - eps <= thr;
                     nt += ok[r];
                     const uint32_t grp = group_hits<L>(hit, lane);
                     const int pos = cnt + __popc(grp & ((1u << sub) - 1u));
@@ -1046,6 +1079,7 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                             const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
                             const float tt = thr + p.w + eps;
                             hit = tt >= 0.f && dx * dx + dy * dy + dz * dz <= tt * tt;
+                            if (hit) hit = capsule_lb(G, cv, c0 + i, p, ql) - eps <= thr;
                             ++nt;
                         }
                         const uint32_t grp = group_hits<L>(hit, lane);
