@@ -788,6 +788,37 @@ __device__ __forceinline__ float capsule_lb(const DevGeom& G, const DCurve& cv, 
     return d - rho - 1.0001f * (float)cv.tol_eff - 8e-6f * c.w;
 }
 
+// The piece with the nearest centre among the L lanes' candidates (bd, bw, bk:
+// centre distance, radius, index; ties to the lower index, so the same piece
+// for every lane count), and an upper bound from points of it, far tighter
+// than its sphere's: lanes 0..3 take B(0), B(1/3), B(2/3), B(1) of its FP32
+// Bezier form (the span lies within tol_eff of it; 4e-6 w covers the FP32
+// control points and the evaluation).  INFINITY in the other lanes.
+template <int L>
+__device__ __forceinline__ float point_bound(const DevGeom& G, const DCurve& cv, float bd, float bw, int bk, int sub,
+                                             bool active, const float* ql, float eps)
+{
+#pragma unroll
+    for (int off = 1; off < L; off <<= 1) {
+        const float od = __shfl_xor(bd, off, 64), ow = __shfl_xor(bw, off, 64);
+        const int ok = __shfl_xor(bk, off, 64);
+        const bool take = od < bd || (od == bd && (unsigned)ok < (unsigned)bk);
+        bk = take ? ok : bk;
+        bw = take ? ow : bw;
+        bd = take ? od : bd;
+    }
+    if (!active || bk < 0 || sub >= 4) return INFINITY;
+    const float4* lp = reinterpret_cast<const float4*>(G.lcp + 12 * (cv.seg_off + (int64_t)bk));
+    const float4 a = lp[0], b = lp[1], e = lp[2];
+    const float4 c = G.sph[cv.seg_off + bk];
+    const float t = (float)sub * (1.f / 3.f), s = 1.f - t;
+    const float w0 = s * s * s, w1 = 3.f * t * s * s, w2 = 3.f * t * t * s, w3 = t * t * t;
+    const float dx = ql[0] - (c.x + (w0 * a.x + w1 * a.w + w2 * b.z + w3 * e.y));
+    const float dy = ql[1] - (c.y + (w0 * a.y + w1 * b.x + w2 * b.w + w3 * e.z));
+    const float dz = ql[2] - (c.z + (w0 * a.z + w1 * b.y + w2 * e.x + w3 * e.w));
+    return __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz) + 1.0001f * (float)cv.tol_eff + 4e-6f * bw + eps;
+}
+
 template <int T>
 __device__ __forceinline__ void stage_clusters(const DevGeom& G, const DCurve& cv, int c0, int cn, float4* st)
 {
@@ -904,31 +935,7 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                     }
                 }
         }
-#pragma unroll
-        for (int off = 1; off < L; off <<= 1) {
-            const float od = __shfl_xor(bd, off, 64), ow = __shfl_xor(bw, off, 64);
-            const int ok_ = __shfl_xor(bk, off, 64);
-            const bool take = od < bd || (od == bd && (unsigned)ok_ < (unsigned)bk);
-            bk = take ? ok_ : bk;
-            bw = take ? ow : bw;
-            bd = take ? od : bd;
-        }
-        // a point of that piece bounds the distance far tighter than its sphere:
-        // lanes 0..3 take B(0), B(1/3), B(2/3), B(1) of its FP32 Bezier form (the
-        // curve lies within tol_eff of it; 4e-6 w covers the FP32 control points
-        // and the evaluation)
-        if (active && bk >= 0 && sub < 4) {
-            const float4* lp = reinterpret_cast<const float4*>(G.lcp + 12 * (cv.seg_off + (int64_t)bk));
-            const float4 a = lp[0], b = lp[1], e = lp[2];
-            const float4 c = G.sph[cv.seg_off + bk];
-            const float t = (float)sub * (1.f / 3.f), s = 1.f - t;
-            const float w0 = s * s * s, w1 = 3.f * t * s * s, w2 = 3.f * t * t * s, w3 = t * t * t;
-            const float4 pt = make_float4(c.x + (w0 * a.x + w1 * a.w + w2 * b.z + w3 * e.y),
-                                          c.y + (w0 * a.y + w1 * b.x + w2 * b.w + w3 * e.z),
-                                          c.z + (w0 * a.z + w1 * b.y + w2 * e.x + w3 * e.w), 0.f);
-            ub = fminf(ub, dist(pt) + 1.0001f * (float)cv.tol_eff + 4e-6f * bw + eps);
-        }
-        ub = min_lanes<L>(ub);
+        ub = min_lanes<L>(fminf(ub, point_bound<L>(G, cv, bd, bw, bk, sub, active, ql, eps)));
         // b. candidate clusters
         const float thr0 = ub + tie_margin(ub, cv, tie_rel);
         int ncl = 0;  // same value in the query's 8 lanes
@@ -958,6 +965,8 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
 #pragma unroll
         for (int k = 0; k < kK; ++k) key[k] = ~0ull;
         int pre = 0;  // pieces kept so far (same value in the query's 8 lanes)
+        bd = INFINITY;
+        bk = -1;
         if (active && clus_ok) {
             for (int m = 0; m < ncl; ++m) {
                 const int cl = sh.clu[qs][m];
@@ -971,6 +980,11 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                     lbv[r] = d - p[r].w - eps;
                     if (ok[r]) {
                         ub = fminf(ub, d + re);
+                        if (d < bd) {
+                            bd = d;
+                            bw = p[r].w;
+                            bk = cl * kCluPieces + sub + r * L;
+                        }
                         if constexpr (kKeys)
                             insert_key(key, ((uint64_t)ord_key(d - re) << 32) | (uint32_t)(cl * kCluPieces + sub + r * L));
                         ++nt;
@@ -992,7 +1006,8 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 }
             }
         }
-        ub = min_lanes<L>(ub);
+        // the same point bound for the nearest-centre piece of all candidate clusters
+        ub = min_lanes<L>(fminf(ub, point_bound<L>(G, cv, bd, bw, bk, sub, active && clus_ok, ql, eps)));
         if constexpr (kKeys) merge_keys<L>(key);
         // d. the list: the kept pieces whose lower bound reaches the final UB +
         // margin, in visiting order; if more than kBoxCap were kept, a second
