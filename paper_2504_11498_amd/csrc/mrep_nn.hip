@@ -161,14 +161,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int kc, float* __
     const int am = m0 + r, bn = n0 + r;
     const int kbeg = (int)blockIdx.y * kc, kend = min(g.K, kbeg + kc);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    // A with unit stride along k and 16-byte rows: a lane's 8 k values as two
+    // float4 loads (k is a multiple of 8, so they stay inside the row)
+    const bool a_vec = g.sak == 1 && g.sam % 4 == 0 && ((uintptr_t)g.A & 15u) == 0;
     for (int k0 = kbeg; k0 < kend; k0 += 32) {
         bf16x8 a, b;
+        const int kl = k0 + kb * 8;
+        if (a_vec && kl + 8 <= kend && am < g.M) {
+            const float4* ap = reinterpret_cast<const float4*>(g.A + (int64_t)am * g.sam + kl);
+            const float4 lo = ap[0], hi = ap[1];
+            a[0] = (__bf16)lo.x; a[1] = (__bf16)lo.y; a[2] = (__bf16)lo.z; a[3] = (__bf16)lo.w;
+            a[4] = (__bf16)hi.x; a[5] = (__bf16)hi.y; a[6] = (__bf16)hi.z; a[7] = (__bf16)hi.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = kl + j;
+                a[j] = (__bf16)((k < kend && am < g.M) ? g.A[am * g.sam + k * g.sak] : 0.f);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int k = k0 + kb * 8 + j;
-            const bool kin = k < kend;
-            a[j] = (__bf16)((kin && am < g.M) ? g.A[am * g.sam + k * g.sak] : 0.f);
-            b[j] = (__bf16)((kin && bn < g.N) ? g.B[k * g.sbk + bn * g.sbn] : 0.f);
+            const int k = kl + j;
+            b[j] = (__bf16)((k < kend && bn < g.N) ? g.B[k * g.sbk + bn * g.sbn] : 0.f);
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
@@ -190,8 +204,18 @@ __global__ void k_sum_parts(int M, int N, int splits, const float* __restrict__ 
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)M * N) return;
+    // sixteen loads in flight, added in split order
+    const int64_t mn = (int64_t)M * N;
     float acc = 0.f;
-    for (int s = 0; s < splits; ++s) acc += parts[(int64_t)s * M * N + i];
+    int s = 0;
+    for (; s + 16 <= splits; s += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = parts[(int64_t)(s + u) * mn + i];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (; s < splits; ++s) acc += parts[(int64_t)s * mn + i];
     C[(i / N) * scm + (i % N) * scn] = acc;
 }
 
@@ -208,8 +232,10 @@ __global__ void k_gemm_f32(GemmArgs g)
 }
 
 // splits of a long K and the dense partials they need (parts holds kMaxSplits x M x N floats)
-constexpr int kMaxSplits = 32;
-constexpr int kSplitRows = 256;  // K rows per split
+// (64 rows: the weight gradients have only 8 to 64 output tiles, so the splits
+// are what fills the chip)
+constexpr int kMaxSplits = 128;
+constexpr int kSplitRows = 64;  // K rows per split
 
 // the training kernels' products in FP32 instead of BF16 MFMA (mrep_nn_set_compute; debug)
 static thread_local bool t_gemm_fp32 = false;
@@ -314,13 +340,17 @@ __global__ void k_gather(int64_t B, const int32_t* __restrict__ rows, int64_t n_
                          const float* __restrict__ x, const float* __restrict__ t, const float* __restrict__ acc,
                          float* __restrict__ xb, float* __restrict__ tb, float* __restrict__ accb)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B) return;
+    // one thread per (batch row, column) of the in + nt + 1 columns
+    const int w = in + nt + 1;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * w) return;
+    const int64_t i = e / w;
+    const int k = (int)(e - i * w);
     const int64_t r = rows[i];
     const bool ok = r >= 0 && r < n_rows;
-    for (int k = 0; k < in; ++k) xb[i * in + k] = ok ? x[r * in + k] : 0.f;
-    for (int k = 0; k < nt; ++k) tb[i * nt + k] = ok ? t[r * nt + k] : 0.f;
-    accb[i] = ok ? acc[r] : 0.f;
+    if (k < in) xb[i * in + k] = ok ? x[r * in + k] : 0.f;
+    else if (k < in + nt) tb[i * nt + (k - in)] = ok ? t[r * nt + (k - in)] : 0.f;
+    else accb[i] = ok ? acc[r] : 0.f;
 }
 
 // Adam with bias correction c1 = 1 - b1^t, c2 = 1 - b2^t on FP32 master weights.
@@ -1834,7 +1864,7 @@ int32_t mrep_nn_train_step(mrep_nn* nn, int64_t n_rows, const float* x, const fl
     hipStream_t st = (hipStream_t)stream;
     const float *X = x, *T = target, *A = accept;
     if (rows) {
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(batch)), dim3(256), 0, st, batch, rows, n_rows, d.in, d.out - 1,
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(batch * (d.in + d.out))), dim3(256), 0, st, batch, rows, n_rows, d.in, d.out - 1,
                            x, target, accept, w.Xb, w.Tb, w.Ab);
         X = w.Xb; T = w.Tb; A = w.Ab;
     }
