@@ -97,6 +97,40 @@ def _lattice_traffic():
             if k in KERNEL_SOURCES and v.get("sources_sha256_16") == sources_hash(KERNEL_SOURCES[k])}
 
 
+def nn_training_block(dev, batch=4096, steps=200):
+    """One training step (gather, forward, loss, backward, Adam) of each network kind at a fixed batch on
+    synthetic rows, timed over `steps` steps; flops of the three layers' products (forward, input gradients
+    of layers 2 and 3, weight gradients) against the BF16 MFMA peak."""
+    import torch
+
+    from paper_2504_11498_amd import mrep
+
+    out = {"batch": batch, "steps": steps}
+    g = torch.Generator(device="cpu").manual_seed(0)
+    for kind, name in ((mrep.NN_CURVE, "curve"), (mrep.NN_SURFACE, "surface")):
+        n_in, n_out = mrep.NN_DIMS[kind]
+        h = 128
+        n = 16 * batch
+        x = torch.randn(n, n_in, generator=g).to(dev)
+        u = torch.rand(n * (n_out - 1), generator=g).to(dev)
+        a = (torch.rand(n, generator=g) > 0.5).float().to(dev)
+        rows = torch.randperm(n, generator=g).to(torch.int32).to(dev)
+        net = mrep.Network(dev, seed=1, kind=kind)
+        for i in range(5):
+            net.train_step(x, u, a, rows=rows[:batch], lr=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            net.train_step(x, u, a, rows=rows[(i % 16) * batch:(i % 16 + 1) * batch], lr=1e-3)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        flop = 2 * batch * ((n_in * h + h * h + h * n_out) + (h * n_out + h * h) + (n_in * h + h * h + h * n_out))
+        tf = flop / (ms * 1e-3) / 1e12
+        out[name] = {"ms_per_step": ms, "flop_per_step": flop, "achieved_tflops": tf, "frac_bf16_peak": tf / 2500.0,
+                     "layers": f"{n_in}-{h}-{h}-{n_out}"}
+    return out
+
+
 def summarize_rocprof(path):
     """Per-kernel duration summary (calls, mean/min/max microseconds, total ms) of a rocprofv3 SQLite result."""
     import sqlite3
@@ -133,6 +167,8 @@ def main():
                     help="strut curves of the headline lattice workload (65536 = the full microstructure "
                          "configuration; queries = 256 per curve)")
     ap.add_argument("--summarize-rocprof", metavar="RESULTS_DB", help="print a kernel summary of a rocprofv3 result and exit")
+    ap.add_argument("--train-step", action="store_true",
+                    help="time network training steps (batch 4096, both network kinds), print one JSON line and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies and exit (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -148,6 +184,11 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print("copied 3 x 512 MiB", flush=True)
+        return
+    if args.train_step:
+        import torch
+
+        print(json.dumps(nn_training_block(torch.device("cuda", 0))), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -168,6 +209,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_single:
         result["single_cubic"] = single_cubic_block(args, dev)
+        result["nn_training"] = nn_training_block(dev)
     if not args.no_surfaces:
         torch.cuda.empty_cache()
         result["surfaces"] = surfaces_bench(args, dev)
