@@ -979,7 +979,9 @@ __device__ __forceinline__ void box_tile(const DevGeom& G, int tile, const int32
                 bool hit = false;
                 if (i < cn) {
                     const float4 p = s_st[i];
-                    hit = dist(p) - p.w - eps <= thr0;
+                    const float dx = ql[0] - p.x, dy = ql[1] - p.y, dz = ql[2] - p.z;
+                    const float tt = thr0 + eps + p.w;  // >= 0
+                    hit = dx * dx + dy * dy + dz * dz <= tt * tt;
                     ++nt;
                 }
                 const uint32_t grp = group_hits<L>(hit, lane);
