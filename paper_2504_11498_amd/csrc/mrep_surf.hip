@@ -197,8 +197,10 @@ __device__ __forceinline__ CluRows clu_rows(const DSurf& sf, int c)
 // min over the patches of cluster c of |q - c_p| + r_p + eps (per lane)
 constexpr int kBatch = 4;  // patch spheres a lane loads at once
 
+// ... also keeping this lane's patch with the nearest centre (bd, bk: its
+// centre distance and global index; ties to the lower index)
 __device__ __forceinline__ float clu_patch_ub(const DevSurf& D, const DSurf& sf, int c, const float* ql, float eps,
-                                              int sub, float ub)
+                                              int sub, float ub, float& bd, int& bk)
 {
     const CluRows R = clu_rows(sf, c);
     for (int iu = R.iu0; iu < R.iu1; ++iu) {
@@ -214,11 +216,62 @@ __device__ __forceinline__ float clu_patch_ub(const DevSurf& D, const DSurf& sf,
             for (int r = 0; r < kBatch; ++r) {
                 const float dx = ql[0] - p[r].x, dy = ql[1] - p[r].y, dz = ql[2] - p[r].z;
                 // the raw square root (<= 1 ulp) is inside the allowance eps
-                ub = fminf(ub, __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz) + p[r].w + eps);
+                const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                ub = fminf(ub, d + p[r].w + eps);
+                const int kk = k + r * kSphSub;
+                if (kk < k1 && (d < bd || (d == bd && kk < bk))) {
+                    bd = d;
+                    bk = kk;
+                }
             }
         }
     }
     return ub;
+}
+
+// An upper bound from points of the patch with the nearest centre among the
+// query's 8 lanes' candidates (bd, bk; ties to the lower index): lanes 0..3
+// take its corner control points, which are points of its FP32 Bezier form,
+// lane 4 its centre B(1/2, 1/2); plus the patch's deviation bound tol_eff and
+// 4e-6 r for the FP32 net and the evaluation.  INFINITY in the other lanes.
+__device__ __forceinline__ float patch_point_bound(const DevSurf& D, const DSurf& sf, float bd, int bk, int sub,
+                                                   bool active, const float* ql, float eps)
+{
+#pragma unroll
+    for (int off = 1; off < kSphSub; off <<= 1) {
+        const float od = __shfl_xor(bd, off, 64);
+        const int ok = __shfl_xor(bk, off, 64);
+        const bool take = od < bd || (od == bd && (unsigned)ok < (unsigned)bk);
+        bk = take ? ok : bk;
+        bd = take ? od : bd;
+    }
+    if (!active || bk < 0 || sub > 4) return INFINITY;
+    const float4* lp = reinterpret_cast<const float4*>(D.lcp + (int64_t)bk * 48);
+    const float4 c = D.sph[bk];
+    float px, py, pz;
+    if (sub < 4) {
+        // P00 = lcp[0..2], P03 = lcp[9..11], P30 = lcp[36..38], P33 = lcp[45..47]
+        const float4 v = lp[sub == 0 ? 0 : (sub == 1 ? 2 : (sub == 2 ? 9 : 11))];
+        const bool hi = sub == 1 || sub == 3;
+        px = hi ? v.y : v.x;
+        py = hi ? v.z : v.y;
+        pz = hi ? v.w : v.z;
+    } else {
+        const float w[4] = {0.125f, 0.375f, 0.375f, 0.125f};
+        const float* l = D.lcp + (int64_t)bk * 48;
+        px = py = pz = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float wij = w[i] * w[j];
+                px += wij * l[3 * (4 * i + j)];
+                py += wij * l[3 * (4 * i + j) + 1];
+                pz += wij * l[3 * (4 * i + j) + 2];
+            }
+    }
+    const float dx = ql[0] - (c.x + px), dy = ql[1] - (c.y + py), dz = ql[2] - (c.z + pz);
+    return __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz) + 1.0001f * (float)sf.tol_eff + 4e-6f * c.w + eps;
 }
 
 // A first bound on the distance: min over clusters of |q - c_C| + r_C + eps,
@@ -259,11 +312,14 @@ __device__ float first_ub(const DevSurf& D, const DSurf& sf, float4* st, const f
         cswap(key[0], key[1]);
         cswap(key[2], key[3]);
     }
+    float bd = INFINITY;
+    int bk = -1;
     if (active) {
 #pragma unroll
         for (int m = 0; m < kK; ++m)
-            if (key[m] != ~0ull) ub = clu_patch_ub(D, sf, (int)(uint32_t)key[m], ql, eps, sub, ub);
+            if (key[m] != ~0ull) ub = clu_patch_ub(D, sf, (int)(uint32_t)key[m], ql, eps, sub, ub, bd, bk);
     }
+    ub = fminf(ub, patch_point_bound(D, sf, bd, bk, sub, active, ql, eps));
 #pragma unroll
     for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
     return ub;
@@ -767,7 +823,8 @@ __device__ PatchMin patch_min(const Bicubic& B, float cap)
 // query:
 //   a. threshold: a first bound from the cluster spheres and the patches of
 //      the nearest clusters, then the best patch sphere upper bound over the
-//      clusters that reach it (plain calls), or the seed's value (seeded
+//      clusters that reach it (plain calls), each sharpened by points of the
+//      nearest-centre patch (patch_point_bound), or the seed's value (seeded
 //      calls, in fub); plus the tie margin;
 //   b. list the patches of those clusters whose sphere lower bound reaches the
 //      threshold (at most kSphCap, and at most kCluCap clusters; more: the
@@ -826,8 +883,13 @@ __global__ __launch_bounds__(kSphThreads) void k_slist(DevSurf D, const int32_t*
         const float ubs = first_ub(D, sf, s_u.st, ql, eps, active, sub);
         ns = clu_list(D, sf, s_u.st, ql, eps, ubs + s_margin(ubs, sf, tie_rel), active, lane, sub, s_clu[qs]);
         // the best patch sphere upper bound over the candidate clusters
+        float bd = INFINITY;
+        int bk = -1;
         if (active && ns <= kCluCap)
-            for (int m = 0; m < ns; ++m) ub = clu_patch_ub(D, sf, s_clu[qs][m], ql, eps, sub, ub);
+            for (int m = 0; m < ns; ++m) ub = clu_patch_ub(D, sf, s_clu[qs][m], ql, eps, sub, ub, bd, bk);
+        // and the point bound of the nearest-centre patch over all of them (the
+        // first bound holds too)
+        ub = fminf(fminf(ub, ubs), patch_point_bound(D, sf, bd, bk, sub, active && ns <= kCluCap, ql, eps));
 #pragma unroll
         for (int off = 1; off < kSphSub; off <<= 1) ub = fminf(ub, __shfl_xor(ub, off, 64));
     }
